@@ -1,0 +1,226 @@
+/*
+ * pwspline.h -- periodic tricubic B-spline orbitals on AMD Instinct MI355X (gfx950).
+ *
+ * The method: single-particle orbitals given as planewave sums are replaced by
+ * cubic B-splines on a uniform periodic real-space grid (Parker, Umrigar, Alfe,
+ * Hennig, Wilkins, "Comparison of polynomial approximations to speed up
+ * planewave-based quantum Monte Carlo calculations", arXiv:1309.6250).  Every
+ * evaluation of an orbital, its gradient and its Laplacian at a point reads the
+ * 4x4x4 block of coefficients around the point (Sec. III B) and contracts it
+ * with tensor-product basis weights (App. A, Eq. b-splineapproximation); the
+ * Cartesian derivatives follow from the chain rule through the reduced
+ * coordinates (Sec. II, Eq. reducedcoordinate and the Coordinates paragraph).
+ *
+ * Conventions used by every entry point
+ *   - Pointers named "device" are HIP device pointers; everything else is host.
+ *     The caller owns every buffer.  No entry point below allocates device
+ *     memory except spline_batch_plan_create and spline_autotune (documented).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work is
+ *     enqueued asynchronously on it; nothing synchronizes with the host unless
+ *     stated.  Faults inside a kernel surface at the caller's next synchronize.
+ *   - Return values: SPL_OK (0) or a negative SPL_E* code.  All argument checks
+ *     happen before anything is enqueued; on failure nothing is enqueued and
+ *     spline_last_error() describes the problem (thread-local, never NULL).
+ *     No entry point aborts or throws.
+ *   - Lattice: lattice[3*i + c] is Cartesian component c (bohr) of lattice vector
+ *     a_i, i.e. ROWS are lattice vectors.  The paper's matrix a has them as
+ *     columns, so crystal coordinates are s = a^-1 r with a = lattice^T.
+ *   - Coefficient table layout: [N1][N2][N3][o_pad], orbital index innermost and
+ *     zero-padded to o_pad, in the storage dtype.  With has_lap, a second table of
+ *     the same shape (the separate Laplacian spline) follows the first.
+ *   - Basis normalization: the standard cubic B-spline (values 1/6, 2/3, 1/6 at
+ *     the knots; the 64 weights of a point sum to 1).  The paper's basis is this
+ *     one times 3/2 per axis (its constant C = 3/2, App. A); the spline function
+ *     is identical, stored coefficients differ by the factor (3/2)^3.
+ *   - Positions are FP64 Cartesian [n_pts][3], anywhere in R^3 (folded into the
+ *     cell).  A point with a non-finite coordinate yields NaN outputs.
+ *   - Outputs are FP64 for SPL_F64 tables and FP32 for SPL_F32 / SPL_BF16 tables
+ *     (whose arithmetic is FP32; reduced coordinates are always FP64).
+ */
+#ifndef PWSPLINE_H
+#define PWSPLINE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* storage dtype of coefficient tables */
+enum { SPL_F64 = 0, SPL_F32 = 1, SPL_BF16 = 2 };
+
+/* status codes */
+enum {
+  SPL_OK = 0,
+  SPL_EINVAL = -1,       /* bad argument: NULL required pointer, n_orb < 1, n_pts < 0, singular lattice ... */
+  SPL_EGRID = -2,        /* grid size outside [4, 1024] on some axis */
+  SPL_EDTYPE = -3,       /* unknown dtype */
+  SPL_ENOMEM = -4,       /* a library-owned allocation failed (batch plans, autotuning only) */
+  SPL_EHIP = -5,         /* a HIP runtime call or launch failed; message holds the HIP error string */
+  SPL_EUNSUPPORTED = -6  /* valid request that this build does not implement */
+};
+
+/* flags of spline_eval_vgl_backward */
+enum { SPL_DETERMINISTIC = 1 };
+
+/*
+ * Descriptor of one coefficient table.  The caller fills the first block and
+ * calls spline_desc_init, which validates it and fills the derived block.
+ * Plain data: it may be copied freely; entry points read it on the host.
+ */
+typedef struct spl_desc {
+  /* --- set by the caller --- */
+  double  lattice[9];     /* rows = lattice vectors a_i, bohr */
+  int32_t grid[3];        /* N_1, N_2, N_3: grid points along a_1, a_2, a_3 (need not be equal, Sec. II Grid) */
+  int32_t n_orb;          /* number of orbitals (>= 1) */
+  int32_t dtype;          /* SPL_F64 / SPL_F32 / SPL_BF16 */
+  int32_t has_lap;        /* 1: a separate Laplacian spline follows the orbital table (Sec. III A) */
+  /* --- derived by spline_desc_init --- */
+  double  ainv[9];        /* a^-1 (row-major): s = ainv . r */
+  double  jac[9];         /* J[i][c] = N_i ainv[i][c] = d u_i / d r_c, u = grid units */
+  double  metric[6];      /* M = J J^T as M00 M11 M22 M01 M02 M12 */
+  int32_t o_pad;          /* orbital stride of a table row: n_orb rounded up to 16 bytes of storage */
+  int32_t elem_bytes;     /* 8 / 4 / 2 */
+  int64_t table_elems;    /* N1*N2*N3*o_pad: elements of ONE table */
+  int64_t table_bytes;    /* bytes of the full table buffer: (1 + has_lap) * table_elems * elem_bytes */
+  int64_t work_bytes;     /* bytes of the FP64 workspace spline_build needs: N1*N2*N3*n_orb*8 */
+  int64_t gtable_bytes;   /* bytes of a coefficient-gradient buffer: (1 + has_lap) * table_elems * (8 or 4) */
+} spl_desc;
+
+/*
+ * Validate the caller block of *d and fill the derived block.  Host only,
+ * enqueues nothing.  Errors: d == NULL, n_orb < 1, non-finite or singular lattice
+ * -> SPL_EINVAL; any N_i outside [4, 1024] -> SPL_EGRID; unknown dtype ->
+ * SPL_EDTYPE; has_lap not 0/1 -> SPL_EINVAL.  N_i >= 4 keeps the four rows of a
+ * point's block distinct along each axis.
+ */
+int spline_desc_init(spl_desc* d);
+
+/*
+ * Interpolating B-spline coefficients from grid values (App. A, Interpolating
+ * B-spline coefficients).  The coefficients solve (B_1 x B_2 x B_3) beta = f, each
+ * B_d periodic tridiagonal with corner elements (rows 1/6, 4/6, 1/6); solved in
+ * three stages, one axis at a time, in FP64, then rounded once (to nearest even,
+ * via FP32 for BF16) into the storage dtype.
+ *   grid_vals  device, FP64 [N1][N2][N3][n_orb]: orbital values at r = a (i/N1, j/N2, k/N3)
+ *   lap_vals   device, FP64, same shape: grid values of the planewave Laplacian
+ *              (the input of the separate Laplacian spline); must be NULL iff !has_lap
+ *   table      device, d->table_bytes, written completely (padding zeroed)
+ *   work       device, d->work_bytes of scratch FP64, contents undefined afterwards
+ * grid_vals and lap_vals are not modified.  None of the buffers may overlap.
+ */
+int spline_build(const spl_desc* d, const double* grid_vals, const double* lap_vals,
+                 void* table, void* work, void* stream);
+
+/*
+ * Orbital values phi_o(r_p) (App. A, Eq. b-splineapproximation) at n_pts points.
+ *   table  device, as written by spline_build
+ *   pos    device, FP64 [n_pts][3]
+ *   v      device, [n_pts][n_orb] (FP64 for SPL_F64 tables, else FP32)
+ * n_pts == 0 is a no-op.
+ */
+int spline_eval_v(const spl_desc* d, const void* table, int64_t n_pts, const double* pos,
+                  void* v, void* stream);
+
+/*
+ * Values, Cartesian gradients and Laplacians (VGL) of every orbital at n_pts points.
+ * Gradient: grad phi = J^T grad_t phi; Laplacian: sum_ij M_ij d2 phi / dt_i dt_j with
+ * the full metric M (off-diagonal terms for non-orthogonal cells), or, with has_lap,
+ * the value of the separate Laplacian spline.
+ *   v     device, [n_pts][n_orb]
+ *   grad  device, [n_pts][3][n_orb]
+ *   lap   device, [n_pts][n_orb]
+ * (FP64 for SPL_F64 tables, else FP32.)  All three are required.
+ */
+int spline_eval_vgl(const spl_desc* d, const void* table, int64_t n_pts, const double* pos,
+                    void* v, void* grad, void* lap, void* stream);
+
+/*
+ * Same as spline_eval_vgl with an explicit launch shape: tile[0] = lanes that
+ * share one point (1, 2, 4, ..., 256), tile[1] = points per lane (1, 2 or 4, run
+ * one after the other).  Used by the autotuner and tests; results are identical
+ * for every valid tile.  Invalid tile -> SPL_EINVAL.
+ */
+int spline_eval_vgl_tile(const spl_desc* d, const void* table, int64_t n_pts, const double* pos,
+                         void* v, void* grad, void* lap, const int32_t tile[2], void* stream);
+
+/*
+ * Adjoint of spline_eval_vgl: given dL/dv, dL/dgrad, dL/dlap of a scalar loss L,
+ *   gtable += dL/dtable   (the transpose of the 64-coefficient gather, periodic wrap)
+ *   gpos    = dL/dpos     (through grad, Hessian and gradient of the Laplacian)
+ *   gv, ggrad, glap  device, same layouts and dtypes as the forward outputs; each may be
+ *                    NULL (treated as zero)
+ *   gtable           device, d->gtable_bytes: [(1+has_lap)][N1][N2][N3][o_pad], FP64 for
+ *                    SPL_F64 tables, else FP32; ACCUMULATED into (zero it first for a plain
+ *                    gradient); may be NULL to skip
+ *   gpos             device, FP64 [n_pts][3], OVERWRITTEN; may be NULL to skip
+ *   flags            0 or SPL_DETERMINISTIC (currently SPL_EUNSUPPORTED)
+ * Points with non-finite coordinates contribute nothing to gtable and get NaN in gpos.
+ */
+int spline_eval_vgl_backward(const spl_desc* d, const void* table, int64_t n_pts, const double* pos,
+                             const void* gv, const void* ggrad, const void* glap,
+                             void* gtable, double* gpos, int32_t flags, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched evaluation: many independent systems (tables of different sizes and
+ * orbital counts, point sets of different sizes) in ONE persistent launch.
+ * All items of a plan share one storage dtype.
+ */
+typedef struct spl_item {
+  const spl_desc* d;      /* host pointer, read during plan creation only */
+  const void* table;      /* device */
+  int64_t n_pts;
+  const double* pos;      /* device [n_pts][3] */
+  void* v;                /* device outputs, as for spline_eval_vgl */
+  void* grad;
+  void* lap;
+} spl_item;
+
+/*
+ * Build a plan: copies per-item parameters and a work list of (item, point range)
+ * tiles to device memory the plan owns (this call allocates, once, and
+ * synchronizes `stream`).  tile: NULL = take the tile shape from the autotune
+ * cache (or a default), else as in spline_eval_vgl_tile.  On success *plan is set.
+ */
+int spline_batch_plan_create(const spl_item* items, int32_t n_items, const int32_t* tile,
+                             void* stream, void** plan);
+
+/* One persistent launch over the plan's whole work list (graph-capturable: it
+ * enqueues one small reset kernel and the persistent kernel, no memset, no allocation). */
+int spline_batch_eval_vgl(void* plan, void* stream);
+
+/* Capture spline_batch_eval_vgl into a HIP graph owned by the plan (once) and
+ * launch it on `stream`.  Later calls relaunch the same graph. */
+int spline_batch_graph_launch(void* plan, void* stream);
+
+/* Release a plan and everything it owns (synchronizes the device first). */
+void spline_batch_plan_destroy(void* plan);
+
+/* Work counters of a plan: number of tiles and of (point, orbital) evaluations. */
+int spline_batch_plan_info(void* plan, int64_t* n_tiles, int64_t* n_evals);
+
+/*
+ * Time every valid tile shape of spline_eval_vgl_tile on the caller's buffers
+ * (each several times, HIP events on `stream`; synchronizes), keep the fastest in
+ * the process-wide cache keyed by (dtype, has_lap, o_pad, grid), and return it in
+ * tile_out[0..1].  The outputs are overwritten with valid results.  If the
+ * environment variable PWSPLINE_TUNE_CACHE names a file, the cache is also
+ * appended there and read back at first use.
+ */
+int spline_autotune(const spl_desc* d, const void* table, int64_t n_pts, const double* pos,
+                    void* v, void* grad, void* lap, void* stream, int32_t tile_out[2]);
+
+/* Tile shape spline_eval_vgl would use for this descriptor (cache hit or default). */
+int spline_tile_for(const spl_desc* d, int64_t n_pts, int32_t tile_out[2]);
+
+/* Human-readable description of the last error on this thread ("" if none). */
+const char* spline_last_error(void);
+
+/* Library version (major*10000 + minor*100 + patch). */
+int spline_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PWSPLINE_H */

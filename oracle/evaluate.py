@@ -40,6 +40,8 @@ def reduced_coordinates(lattice, grid, pos):
     ok = np.all(np.isfinite(pos), axis=1)
     safe = np.where(ok[:, None], pos, 0.0)
     s = np.linalg.solve(a, safe.T).T                   # crystal coordinates
+    ok &= np.all(np.isfinite(s), axis=1)                # finite positions can still overflow here
+    s = np.where(ok[:, None], s, 0.0)
     frac = s - np.floor(s)
     n = np.asarray(grid, dtype=np.float64)
     u = n * frac

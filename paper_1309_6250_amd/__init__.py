@@ -1,0 +1,19 @@
+"""Periodic tricubic B-spline orbital evaluation on AMD Instinct MI355X (gfx950).
+
+The computation lives in the HIP library libpwspline.so (C ABI in
+include/pwspline.h); this package only binds it.  Importing the package does not
+load the library; the first call does, and fails loudly if it was not built.
+"""
+from ._lib import (SPL_F64, SPL_F32, SPL_BF16, SPL_OK, SPL_EINVAL, SPL_EGRID, SPL_EDTYPE, SPL_ENOMEM, SPL_EHIP,
+                   SPL_EUNSUPPORTED, SPL_DETERMINISTIC, SplineError, SplDesc, EXPORTS, LIB_PATH, lib)
+from .api import (spline_desc_init, spline_build, spline_eval_v, spline_eval_vgl, spline_eval_vgl_backward,
+                  spline_autotune, spline_tile_for, BatchPlan, new_table, new_gtable, table_shape,
+                  STORE_TORCH, OUT_TORCH, DTYPES)
+
+__all__ = [
+    "spline_desc_init", "spline_build", "spline_eval_v", "spline_eval_vgl", "spline_eval_vgl_backward",
+    "spline_autotune", "spline_tile_for", "BatchPlan", "new_table", "new_gtable", "table_shape", "SplineError",
+    "SplDesc", "lib", "EXPORTS", "LIB_PATH", "SPL_F64", "SPL_F32", "SPL_BF16", "SPL_OK", "SPL_EINVAL", "SPL_EGRID",
+    "SPL_EDTYPE", "SPL_ENOMEM", "SPL_EHIP", "SPL_EUNSUPPORTED", "SPL_DETERMINISTIC", "STORE_TORCH", "OUT_TORCH",
+    "DTYPES",
+]

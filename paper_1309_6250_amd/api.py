@@ -1,0 +1,229 @@
+"""Python binding of the pwspline C ABI: the same entry points, taking torch tensors.
+
+Only argument marshalling happens here (device pointers, sizes, the current HIP
+stream); every step of the computation runs in the library's HIP kernels.  All
+tensors must live on the GPU and be contiguous.
+"""
+import ctypes
+
+import torch
+
+from ._lib import (SplDesc, SplItem, check, lib, SPL_F64, SPL_F32, SPL_BF16)
+
+DTYPES = {"f64": SPL_F64, "f32": SPL_F32, "bf16": SPL_BF16}
+STORE_TORCH = {SPL_F64: torch.float64, SPL_F32: torch.float32, SPL_BF16: torch.bfloat16}
+OUT_TORCH = {SPL_F64: torch.float64, SPL_F32: torch.float32, SPL_BF16: torch.float32}
+
+
+def _dtype_code(dtype):
+    if isinstance(dtype, str):
+        return DTYPES[dtype]
+    return int(dtype)
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _need(t, name, dtype, numel=None, device=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+
+
+def spline_desc_init(lattice, grid, n_orb, dtype="f64", has_lap=False):
+    """Validated descriptor (ctypes struct) of one coefficient table."""
+    d = SplDesc()
+    lat = [float(x) for x in torch.as_tensor(lattice, dtype=torch.float64).reshape(-1).tolist()]
+    if len(lat) != 9:
+        raise ValueError("lattice must be 3x3")
+    for i in range(9):
+        d.lattice[i] = lat[i]
+    g = [int(x) for x in grid]
+    if len(g) != 3:
+        raise ValueError("grid must have 3 entries")
+    for i in range(3):
+        d.grid[i] = g[i]
+    d.n_orb = int(n_orb)
+    d.dtype = _dtype_code(dtype)
+    d.has_lap = 1 if has_lap else 0
+    check(lib().spline_desc_init(ctypes.byref(d)), "spline_desc_init")
+    return d
+
+
+def table_shape(desc):
+    return (1 + desc.has_lap, desc.grid[0], desc.grid[1], desc.grid[2], desc.o_pad)
+
+
+def new_table(desc, device="cuda"):
+    return torch.empty(table_shape(desc), dtype=STORE_TORCH[desc.dtype], device=device)
+
+
+def new_gtable(desc, device="cuda"):
+    return torch.zeros(table_shape(desc), dtype=OUT_TORCH[desc.dtype], device=device)
+
+
+def spline_build(desc, grid_vals, lap_vals=None, table=None, work=None, stream=None):
+    """Interpolating coefficients from FP64 grid values [N1][N2][N3][n_orb] (device)."""
+    pts = desc.grid[0] * desc.grid[1] * desc.grid[2]
+    _need(grid_vals, "grid_vals", torch.float64, pts * desc.n_orb)
+    if lap_vals is not None:
+        _need(lap_vals, "lap_vals", torch.float64, pts * desc.n_orb)
+    if table is None:
+        table = new_table(desc, grid_vals.device)
+    _need(table, "table", STORE_TORCH[desc.dtype], desc.table_elems * (1 + desc.has_lap))
+    if work is None:
+        work = torch.empty(pts * desc.n_orb, dtype=torch.float64, device=grid_vals.device)
+    _need(work, "work", torch.float64, pts * desc.n_orb)
+    check(lib().spline_build(ctypes.byref(desc), _ptr(grid_vals), _ptr(lap_vals), _ptr(table), _ptr(work),
+                             _stream(stream)), "spline_build")
+    return table
+
+
+def _outputs(desc, n_pts, device, v, grad, lap, values_only=False):
+    od = OUT_TORCH[desc.dtype]
+    if v is None:
+        v = torch.empty((n_pts, desc.n_orb), dtype=od, device=device)
+    _need(v, "v", od, n_pts * desc.n_orb)
+    if values_only:
+        return v, None, None
+    if grad is None:
+        grad = torch.empty((n_pts, 3, desc.n_orb), dtype=od, device=device)
+    if lap is None:
+        lap = torch.empty((n_pts, desc.n_orb), dtype=od, device=device)
+    _need(grad, "grad", od, 3 * n_pts * desc.n_orb)
+    _need(lap, "lap", od, n_pts * desc.n_orb)
+    return v, grad, lap
+
+
+def _check_inputs(desc, table, pos):
+    _need(table, "table", STORE_TORCH[desc.dtype], desc.table_elems * (1 + desc.has_lap))
+    _need(pos, "pos", torch.float64)
+    if pos.dim() != 2 or pos.shape[1] != 3:
+        raise ValueError("pos must be [n_pts, 3]")
+    return pos.shape[0]
+
+
+def spline_eval_v(desc, table, pos, v=None, stream=None):
+    n = _check_inputs(desc, table, pos)
+    v, _, _ = _outputs(desc, n, pos.device, v, None, None, values_only=True)
+    check(lib().spline_eval_v(ctypes.byref(desc), _ptr(table), n, _ptr(pos), _ptr(v), _stream(stream)),
+          "spline_eval_v")
+    return v
+
+
+def spline_eval_vgl(desc, table, pos, v=None, grad=None, lap=None, stream=None, tile=None):
+    n = _check_inputs(desc, table, pos)
+    v, grad, lap = _outputs(desc, n, pos.device, v, grad, lap)
+    if tile is None:
+        check(lib().spline_eval_vgl(ctypes.byref(desc), _ptr(table), n, _ptr(pos), _ptr(v), _ptr(grad), _ptr(lap),
+                                    _stream(stream)), "spline_eval_vgl")
+    else:
+        t = (ctypes.c_int32 * 2)(int(tile[0]), int(tile[1]))
+        check(lib().spline_eval_vgl_tile(ctypes.byref(desc), _ptr(table), n, _ptr(pos), _ptr(v), _ptr(grad),
+                                         _ptr(lap), t, _stream(stream)), "spline_eval_vgl_tile")
+    return v, grad, lap
+
+
+def spline_eval_vgl_backward(desc, table, pos, gv=None, ggrad=None, glap=None, gtable=None, gpos=None,
+                             want_table=True, want_pos=True, flags=0, stream=None):
+    """Returns (gtable, gpos).  gtable is accumulated into (a fresh zero table if not given)."""
+    n = _check_inputs(desc, table, pos)
+    od = OUT_TORCH[desc.dtype]
+    for name, g, numel in (("gv", gv, n * desc.n_orb), ("ggrad", ggrad, 3 * n * desc.n_orb),
+                           ("glap", glap, n * desc.n_orb)):
+        if g is not None:
+            _need(g, name, od, numel)
+    if want_table and gtable is None:
+        gtable = new_gtable(desc, pos.device)
+    if gtable is not None:
+        _need(gtable, "gtable", od, desc.table_elems * (1 + desc.has_lap))
+    if want_pos and gpos is None:
+        gpos = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+    if gpos is not None:
+        _need(gpos, "gpos", torch.float64, 3 * n)
+    check(lib().spline_eval_vgl_backward(ctypes.byref(desc), _ptr(table), n, _ptr(pos), _ptr(gv), _ptr(ggrad),
+                                         _ptr(glap), _ptr(gtable), _ptr(gpos), int(flags), _stream(stream)),
+          "spline_eval_vgl_backward")
+    return gtable, gpos
+
+
+def spline_autotune(desc, table, pos, v=None, grad=None, lap=None, stream=None):
+    n = _check_inputs(desc, table, pos)
+    v, grad, lap = _outputs(desc, n, pos.device, v, grad, lap)
+    t = (ctypes.c_int32 * 2)()
+    check(lib().spline_autotune(ctypes.byref(desc), _ptr(table), n, _ptr(pos), _ptr(v), _ptr(grad), _ptr(lap),
+                                _stream(stream), t), "spline_autotune")
+    return (t[0], t[1])
+
+
+def spline_tile_for(desc, n_pts=0):
+    t = (ctypes.c_int32 * 2)()
+    check(lib().spline_tile_for(ctypes.byref(desc), int(n_pts), t), "spline_tile_for")
+    return (t[0], t[1])
+
+
+class BatchPlan:
+    """One persistent launch over many systems (spline_batch_* entry points).
+
+    items: list of (desc, table, pos, v, grad, lap) with device tensors.  The
+    tensors must stay alive as long as the plan does.
+    """
+
+    def __init__(self, items, tile=None, stream=None):
+        self._keep = list(items)
+        self._descs = [it[0] for it in items]
+        arr = (SplItem * len(items))()
+        for k, (desc, table, pos, v, grad, lap) in enumerate(items):
+            _check_inputs(desc, table, pos)
+            _outputs(desc, pos.shape[0], pos.device, v, grad, lap)
+            arr[k].d = ctypes.pointer(self._descs[k])
+            arr[k].table = table.data_ptr()
+            arr[k].n_pts = pos.shape[0]
+            arr[k].pos = pos.data_ptr()
+            arr[k].v = v.data_ptr()
+            arr[k].grad = grad.data_ptr()
+            arr[k].lap = lap.data_ptr()
+        self._items = arr
+        plan = ctypes.c_void_p()
+        t = None if tile is None else (ctypes.c_int32 * 2)(int(tile[0]), int(tile[1]))
+        check(lib().spline_batch_plan_create(arr, len(items), t, _stream(stream), ctypes.byref(plan)),
+              "spline_batch_plan_create")
+        self._plan = plan
+
+    def run(self, stream=None):
+        check(lib().spline_batch_eval_vgl(self._plan, _stream(stream)), "spline_batch_eval_vgl")
+
+    def run_graph(self, stream=None):
+        check(lib().spline_batch_graph_launch(self._plan, _stream(stream)), "spline_batch_graph_launch")
+
+    def info(self):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().spline_batch_plan_info(self._plan, ctypes.byref(a), ctypes.byref(b)), "spline_batch_plan_info")
+        return a.value, b.value
+
+    def close(self):
+        if getattr(self, "_plan", None):
+            lib().spline_batch_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

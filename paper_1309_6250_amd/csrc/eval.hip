@@ -1,0 +1,50 @@
+// Dispatch of the forward-evaluation kernels (the kernels live in eval_impl.hpp and are
+// instantiated per storage dtype in eval_f64.hip, eval_f32.hip and eval_bf16.hip).
+#include "eval_impl.hpp"
+
+namespace pws {
+
+EvalKernel pick_eval_f64(int mode, int g, int ppl);
+EvalKernel pick_eval_f32(int mode, int g, int ppl);
+EvalKernel pick_eval_bf16(int mode, int g, int ppl);
+
+int vec_of(int dtype) { return dtype == SPL_F64 ? 2 : dtype == SPL_F32 ? 4 : 8; }
+
+bool tile_valid(const int32_t tile[2]) {
+  const int g = tile[0], ppl = tile[1];
+  return g >= 1 && g <= 256 && (g & (g - 1)) == 0 && (ppl == 1 || ppl == 2);
+}
+
+// Launch one forward evaluation.  mode: 0 values only, 1 VGL (separate Laplacian if has_lap).
+int launch_eval(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, void* v, void* grad,
+                void* lap, int values_only, const int32_t tile[2], hipStream_t stream) {
+  if (n_pts == 0) return SPL_OK;
+  EvalArgs a;
+  a.g = make_geom(d);
+  a.table = table;
+  a.pos = pos;
+  a.v = v;
+  a.grad = grad;
+  a.lap = lap;
+  a.n_pts = (int32_t)n_pts;
+  a.n_orb = d->n_orb;
+  const int vec = vec_of(d->dtype);
+  a.n_chunks = d->o_pad / vec;
+  // whole-vector stores need n_orb % VEC == 0 and 16-byte aligned outputs
+  const bool al = ((uintptr_t)v & 15) == 0 && (values_only || (((uintptr_t)grad & 15) == 0 &&
+                                                               ((uintptr_t)lap & 15) == 0));
+  a.vec_store = (d->n_orb % vec) == 0 && al;
+  a.lap_off = d->table_elems;
+  const int mode = values_only ? MODE_V : (d->has_lap ? MODE_VGL_SEPLAP : MODE_VGL);
+  EvalKernel k = nullptr;
+  if (d->dtype == SPL_F64) k = pick_eval_f64(mode, tile[0], tile[1]);
+  else if (d->dtype == SPL_F32) k = pick_eval_f32(mode, tile[0], tile[1]);
+  else k = pick_eval_bf16(mode, tile[0], tile[1]);
+  if (!k) return fail(SPL_EINVAL, "invalid tile shape (%d, %d)", tile[0], tile[1]);
+  const int64_t per_block = (int64_t)(256 / tile[0]) * tile[1];
+  const dim3 grid((unsigned)((n_pts + per_block - 1) / per_block));
+  hipLaunchKernelGGL(k, grid, dim3(256), 0, stream, a);
+  return hip_fail(hipGetLastError(), "evaluation launch");
+}
+
+}  // namespace pws

@@ -1,0 +1,155 @@
+"""Host-side checks of the C ABI: the library loads, exports what the header declares, and
+validates arguments (no GPU needed: every call here fails validation before any HIP work)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1309_6250_amd as P
+from paper_1309_6250_amd._lib import SplDesc, SplItem
+from oracle import evaluate
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pwspline.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(spline_\w+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 14
+    lib = ctypes.CDLL(P.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(P.EXPORTS)
+
+
+def test_struct_layout_matches_header():
+    # offsets follow the declaration order in pwspline.h
+    assert SplDesc.lattice.offset == 0
+    assert SplDesc.grid.offset == 72
+    assert SplDesc.ainv.offset == 96
+    assert ctypes.sizeof(SplDesc) == 96 + 9 * 8 * 2 + 6 * 8 + 8 + 4 * 8
+    assert ctypes.sizeof(SplItem) == 7 * 8
+
+
+def test_desc_derived_fields_match_oracle_geometry():
+    lat = np.array([[7.0, 0.4, -0.3], [1.1, 6.2, 0.5], [-0.6, 0.9, 8.3]])
+    d = P.spline_desc_init(lat, (8, 9, 10), 5, "f32", has_lap=True)
+    jac, metric = evaluate.jacobian(lat, (8, 9, 10))
+    np.testing.assert_allclose(np.array(d.jac).reshape(3, 3), jac, rtol=1e-14)
+    m = np.array(d.metric)
+    np.testing.assert_allclose(m, [metric[0, 0], metric[1, 1], metric[2, 2], metric[0, 1], metric[0, 2],
+                                   metric[1, 2]], rtol=1e-13)
+    np.testing.assert_allclose(np.array(d.ainv).reshape(3, 3), np.linalg.inv(lat.T), rtol=1e-14)
+    assert d.o_pad == 8 and d.elem_bytes == 4
+    assert d.table_elems == 8 * 9 * 10 * 8
+    assert d.table_bytes == 2 * d.table_elems * 4          # separate Laplacian doubles the table
+    assert d.work_bytes == 8 * 9 * 10 * 5 * 8
+    assert d.gtable_bytes == 2 * d.table_elems * 4
+
+
+@pytest.mark.parametrize("dtype,pad", [("f64", 2), ("f32", 4), ("bf16", 8)])
+def test_orbital_padding_rule(dtype, pad):
+    for n_orb in (1, 3, 4, 17, 128, 256):
+        d = P.spline_desc_init(np.eye(3) * 5, (4, 4, 4), n_orb, dtype)
+        assert d.o_pad % pad == 0 and n_orb <= d.o_pad < n_orb + pad
+
+
+def test_memory_factors_one_and_two():
+    # one stored value per grid point per orbital; a separate Laplacian spline doubles it
+    a = P.spline_desc_init(np.eye(3) * 5, (16, 16, 16), 128, "f64")
+    b = P.spline_desc_init(np.eye(3) * 5, (16, 16, 16), 128, "f64", has_lap=True)
+    assert a.table_bytes == 16**3 * 128 * 8 and b.table_bytes == 2 * a.table_bytes
+
+
+def _err(fn, *args):
+    with pytest.raises(P.SplineError) as ei:
+        fn(*args)
+    return ei.value.code
+
+
+def test_desc_errors():
+    assert _err(P.spline_desc_init, np.eye(3), (3, 8, 8), 1) == P.SPL_EGRID
+    assert _err(P.spline_desc_init, np.eye(3), (8, 8, 1025), 1) == P.SPL_EGRID
+    assert _err(P.spline_desc_init, np.eye(3), (8, 8, 8), 0) == P.SPL_EINVAL
+    assert _err(P.spline_desc_init, np.zeros((3, 3)), (8, 8, 8), 1) == P.SPL_EINVAL
+    assert _err(P.spline_desc_init, [[1, 0, 0], [2, 0, 0], [0, 0, 1]], (8, 8, 8), 1) == P.SPL_EINVAL
+    assert _err(P.spline_desc_init, np.full((3, 3), np.nan), (8, 8, 8), 1) == P.SPL_EINVAL
+    assert _err(P.spline_desc_init, np.eye(3), (8, 8, 8), 1, 7) == P.SPL_EDTYPE
+
+
+def _raw_desc():
+    d = P.spline_desc_init(np.eye(3) * 5, (8, 8, 8), 4, "f64")
+    return d
+
+
+def test_entry_points_reject_bad_arguments_before_any_launch():
+    lib = P.lib()
+    d = _raw_desc()
+    ref = ctypes.byref(d)
+    fake = ctypes.c_void_p(4096)            # never dereferenced: validation fails first
+    null = ctypes.c_void_p(0)
+    # NULL table / pos / outputs
+    assert lib.spline_eval_vgl(ref, null, 10, fake, fake, fake, fake, null) == P.SPL_EINVAL
+    assert lib.spline_eval_vgl(ref, fake, 10, null, fake, fake, fake, null) == P.SPL_EINVAL
+    assert lib.spline_eval_vgl(ref, fake, 10, fake, null, fake, fake, null) == P.SPL_EINVAL
+    assert lib.spline_eval_v(ref, fake, 10, fake, null, null) == P.SPL_EINVAL
+    # negative or too many points
+    assert lib.spline_eval_vgl(ref, fake, -1, fake, fake, fake, fake, null) == P.SPL_EINVAL
+    assert lib.spline_eval_vgl(ref, fake, 1 << 31, fake, fake, fake, fake, null) == P.SPL_EINVAL
+    # misaligned table
+    assert lib.spline_eval_vgl(ref, ctypes.c_void_p(4096 + 8), 10, fake, fake, fake, fake, null) == P.SPL_EINVAL
+    # zero points is a no-op that touches nothing
+    assert lib.spline_eval_vgl(ref, null, 0, null, null, null, null, null) == P.SPL_OK
+    # invalid tile
+    tile = (ctypes.c_int32 * 2)(3, 1)
+    assert lib.spline_eval_vgl_tile(ref, fake, 10, fake, fake, fake, fake, tile, null) == P.SPL_EINVAL
+    tile = (ctypes.c_int32 * 2)(64, 3)
+    assert lib.spline_eval_vgl_tile(ref, fake, 10, fake, fake, fake, fake, tile, null) == P.SPL_EINVAL
+    # build: lap values given without has_lap, or missing with has_lap
+    assert lib.spline_build(ref, fake, fake, fake, fake, null) == P.SPL_EINVAL
+    dl = P.spline_desc_init(np.eye(3) * 5, (8, 8, 8), 4, "f64", has_lap=True)
+    assert lib.spline_build(ctypes.byref(dl), fake, null, fake, fake, null) == P.SPL_EINVAL
+    assert lib.spline_build(ref, null, null, fake, fake, null) == P.SPL_EINVAL
+    # backward flags
+    assert lib.spline_eval_vgl_backward(ref, fake, 10, fake, null, null, null, fake, null, 8, null) == P.SPL_EINVAL
+    assert lib.spline_eval_vgl_backward(ref, fake, 10, fake, null, null, null, fake, null, P.SPL_DETERMINISTIC,
+                                        null) == P.SPL_EUNSUPPORTED
+    assert b"deterministic" in lib.spline_last_error()
+
+
+def test_uninitialized_or_modified_descriptor_rejected():
+    lib = P.lib()
+    d = SplDesc()
+    for i in range(3):
+        d.lattice[4 * i] = 5.0
+        d.grid[i] = 8
+    d.n_orb = 4
+    fake = ctypes.c_void_p(4096)
+    assert lib.spline_eval_vgl(ctypes.byref(d), fake, 10, fake, fake, fake, fake, None) == P.SPL_EINVAL
+    d2 = _raw_desc()
+    d2.n_orb = 100                      # changed after init: o_pad no longer matches
+    assert lib.spline_eval_vgl(ctypes.byref(d2), fake, 10, fake, fake, fake, fake, None) == P.SPL_EINVAL
+    assert b"spline_desc_init" in lib.spline_last_error()
+
+
+def test_last_error_cleared_on_success():
+    lib = P.lib()
+    _raw_desc()
+    assert lib.spline_last_error() == b""
+
+
+def test_tile_for_default_covers_orbitals():
+    for dtype, vec in (("f64", 2), ("f32", 4), ("bf16", 8)):
+        for n_orb in (4, 128, 256):
+            d = P.spline_desc_init(np.eye(3) * 5, (8, 8, 8), n_orb, dtype)
+            g, ppl = P.spline_tile_for(d)
+            chunks = d.o_pad // vec
+            assert g >= min(chunks, 256) and (g & (g - 1)) == 0 and ppl in (1, 2)

@@ -163,3 +163,43 @@ def eval_abs_bound(beta, lattice, pos, lap_beta=None, chunk=256):
             lap[sl] = _reduced_derivative(_block(np.abs(np.asarray(lap_beta, dtype=np.float64)), i0[sl], grid),
                                           w, (0, 0, 0))
     return v, grad, lap
+
+
+def coordinate_error_bound(beta, lattice, pos, du, lap_beta=None, chunk=256):
+    """Bound on how much each output can move when the grid coordinates u_i of a point
+    are perturbed by at most du [P,3] (rounding in the coordinate reduction).
+
+    Uses the derivative one order higher, in absolute value:
+      V:     sum_i du_i sum |d_i w||beta|
+      grad:  sum_k |J_k alpha| sum_i du_i sum |d_i d_k w||beta|
+      lap:   sum_jk |M_jk| sum_i du_i sum |d_i d_j d_k w||beta|
+             (separate Laplacian spline: sum_i du_i sum |d_i w||beta_lap|)
+    The third-derivative weights are piecewise constant, so the bound also covers
+    points whose block index flips across a knot plane (the spline is C^2).
+    """
+    beta = np.abs(np.asarray(beta, dtype=np.float64))
+    grid = beta.shape[:3]
+    jac, metric = jacobian(lattice, grid)
+    i0, t, ok = reduced_coordinates(lattice, grid, pos)
+    du = np.asarray(du, dtype=np.float64)
+    n_pts, n_orb = i0.shape[0], beta.shape[3]
+    v = np.zeros((n_pts, n_orb))
+    grad = np.zeros((n_pts, 3, n_orb))
+    lap = np.zeros((n_pts, n_orb))
+    for p0 in range(0, n_pts, chunk):
+        sl = slice(p0, p0 + chunk)
+        w = [[np.abs(x) for x in ax] for ax in _weights(t[sl], 3)]
+        blk = _block(beta, i0[sl], grid)
+        d = du[sl]
+        for i in range(3):
+            v[sl] += d[:, i, None] * _reduced_derivative(blk, w, _orders(i))
+            for k in range(3):
+                hik = _reduced_derivative(blk, w, _orders(i, k))
+                grad[sl] += np.abs(jac[k])[None, :, None] * (d[:, i, None] * hik)[:, None, :]
+                if lap_beta is None:
+                    for j in range(3):
+                        lap[sl] += abs(metric[j, k]) * d[:, i, None] * _reduced_derivative(blk, w, _orders(i, j, k))
+            if lap_beta is not None:
+                lblk = _block(np.abs(np.asarray(lap_beta, dtype=np.float64)), i0[sl], grid)
+                lap[sl] += d[:, i, None] * _reduced_derivative(lblk, w, _orders(i))
+    return v, grad, lap

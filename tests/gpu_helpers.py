@@ -71,6 +71,18 @@ def assert_elementwise(got, ref, bound, factor, name):
                              f"vs bound {lim.flat[i]:.3e}")
 
 
+def coordinate_rounding(desc, lattice, pos, dtype):
+    """Per point and axis, a bound on |delta u| from rounding in the coordinate reduction on
+    either side (s = a^-1 r in FP64: a few roundings relative to sum_j |ainv_ij r_j|, then
+    u = N s), plus the FP32 rounding of t when the table arithmetic is FP32."""
+    ainv = np.abs(np.array(desc.ainv).reshape(3, 3))
+    mag = np.abs(np.nan_to_num(pos)) @ ainv.T + 1.0
+    du = 8 * 2.0**-53 * np.array(desc.grid)[None, :] * mag
+    if dtype != "f64":
+        du = du + 2.0**-24
+    return du
+
+
 def host_table(desc, table):
     """Device table -> FP64 numpy [(1+has_lap), N1, N2, N3, n_orb] (padding dropped)."""
     t = table.float() if table.dtype == torch.bfloat16 else table

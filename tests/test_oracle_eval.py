@@ -207,3 +207,19 @@ def test_spline_close_to_planewave_config0():
     vp, gp, lp = pw.pw_vgl(s.gvecs, s.coef, pos)
     rel = [np.abs(a - b).max() / np.abs(b).max() for a, b in ((v, vp), (g, gp), (lap, lp))]
     assert rel[0] < 1e-2 and rel[1] < 5e-2 and rel[2] < 0.2, rel
+
+
+def test_coordinate_error_bound_covers_small_shifts():
+    grid = (8, 9, 10)
+    beta = _random_spline(grid, 3, 18)
+    rng = np.random.default_rng(19)
+    pos = rng.uniform(-15, 15, size=(200, 3))
+    n = np.array(grid)
+    du = np.full((200, 3), 1e-6)
+    # move every point by up to du in grid units (here along the cell axes)
+    shift = (rng.uniform(-1, 1, size=(200, 3)) * du / n) @ SKEW
+    a = evaluate.eval_vgl(beta, SKEW, pos)
+    b = evaluate.eval_vgl(beta, SKEW, pos + shift)
+    bounds = evaluate.coordinate_error_bound(beta, SKEW, pos, du)
+    for x, y, bd in zip(a, b, bounds):
+        assert np.all(np.abs(x - y) <= 1.01 * bd + 1e-15)

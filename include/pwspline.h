@@ -137,9 +137,10 @@ int spline_eval_vgl(const spl_desc* d, const void* table, int64_t n_pts, const d
 
 /*
  * Same as spline_eval_vgl with an explicit launch shape: tile[0] = lanes that
- * share one point (1, 2, 4, ..., 256), tile[1] = points per lane (1, 2 or 4, run
- * one after the other).  Used by the autotuner and tests; results are identical
- * for every valid tile.  Invalid tile -> SPL_EINVAL.
+ * share one point (2, 4, ..., 256), tile[1] = consecutive orbitals per lane (one
+ * vector load per table row): 1 or 2 for SPL_F64, 1, 2 or 4 for SPL_F32, 2, 4 or 8
+ * for SPL_BF16.  Used by the autotuner and tests; results are identical for every
+ * valid tile.  Invalid tile -> SPL_EINVAL.
  */
 int spline_eval_vgl_tile(const spl_desc* d, const void* table, int64_t n_pts, const double* pos,
                          void* v, void* grad, void* lap, const int32_t tile[2], void* stream);

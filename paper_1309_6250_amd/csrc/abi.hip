@@ -118,7 +118,7 @@ static bool g_tune_loaded = false;
 
 static std::string tune_key(const spl_desc* d) {
   char buf[128];
-  snprintf(buf, sizeof(buf), "v1:%d:%d:%d:%d:%d:%d", d->dtype, d->has_lap, d->o_pad, d->grid[0], d->grid[1],
+  snprintf(buf, sizeof(buf), "v2:%d:%d:%d:%d:%d:%d", d->dtype, d->has_lap, d->o_pad, d->grid[0], d->grid[1],
            d->grid[2]);
   return buf;
 }
@@ -131,30 +131,35 @@ static void tune_load_locked() {
   FILE* f = fopen(path, "r");
   if (!f) return;
   char key[128];
-  int g, ppl;
-  while (fscanf(f, "%127s %d %d", key, &g, &ppl) == 3) g_tune[key] = {g, ppl};
+  int g, opl;
+  while (fscanf(f, "%127s %d %d", key, &g, &opl) == 3) g_tune[key] = {g, opl};
   fclose(f);
 }
 
-static void tune_store_locked(const std::string& key, int g, int ppl) {
-  g_tune[key] = {g, ppl};
+static void tune_store_locked(const std::string& key, int g, int opl) {
+  g_tune[key] = {g, opl};
   const char* path = getenv("PWSPLINE_TUNE_CACHE");
   if (!path || !*path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%s %d %d\n", key.c_str(), g, ppl);
+  fprintf(f, "%s %d %d\n", key.c_str(), g, opl);
   fclose(f);
 }
 
 int vec_of(int dtype);
-bool tile_valid(const int32_t tile[2]);
+void opl_set(int dtype, int out[3]);
+bool tile_valid(int dtype, const int32_t tile[2]);
 
+// Default launch shape: the middle orbitals-per-lane choice, and enough lanes per point to
+// cover a table row in one pass (at most 256).
 void default_tile(const spl_desc* d, int32_t tile[2]) {
-  const int chunks = d->o_pad / vec_of(d->dtype);
-  int g = 1;
+  int set[3];
+  opl_set(d->dtype, set);
+  const int chunks = d->o_pad / set[1];
+  int g = 2;
   while (g < chunks && g < 256) g <<= 1;
   tile[0] = g;
-  tile[1] = 1;
+  tile[1] = set[1];
 }
 
 void tile_for(const spl_desc* d, int32_t tile[2]) {
@@ -164,7 +169,7 @@ void tile_for(const spl_desc* d, int32_t tile[2]) {
   if (it != g_tune.end()) {
     tile[0] = it->second.first;
     tile[1] = it->second.second;
-    if (tile_valid(tile)) return;
+    if (tile_valid(d->dtype, tile)) return;
   }
   default_tile(d, tile);
 }
@@ -245,7 +250,7 @@ int spline_eval_vgl_tile(const spl_desc* d, const void* table, int64_t n_pts, co
   if (!v || !grad || !lap) return fail(SPL_EINVAL, "v, grad and lap must be non-NULL");
   if (!out_align_ok(d, v) || !out_align_ok(d, grad) || !out_align_ok(d, lap))
     return fail(SPL_EINVAL, "output not aligned to its element size");
-  if (!tile || !tile_valid(tile)) return fail(SPL_EINVAL, "invalid tile");
+  if (!tile || !tile_valid(d->dtype, tile)) return fail(SPL_EINVAL, "invalid tile");
   return launch_eval(d, table, n_pts, pos, v, grad, lap, 0, tile, static_cast<hipStream_t>(stream));
 }
 
@@ -277,17 +282,21 @@ int spline_autotune(const spl_desc* d, const void* table, int64_t n_pts, const d
   if (!v || !grad || !lap || !tile_out) return fail(SPL_EINVAL, "outputs and tile_out must be non-NULL");
   if (n_pts == 0) return fail(SPL_EINVAL, "autotuning needs n_pts > 0");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int chunks = d->o_pad / vec_of(d->dtype);
-  int gmax = 1;
-  while (gmax < chunks && gmax < 256) gmax <<= 1;
+  int set[3];
+  opl_set(d->dtype, set);
   hipEvent_t e0, e1;
   if ((rc = hip_fail(hipEventCreate(&e0), "hipEventCreate"))) return rc;
   if ((rc = hip_fail(hipEventCreate(&e1), "hipEventCreate"))) { hipEventDestroy(e0); return rc; }
   float best = 1e30f;
   int32_t best_tile[2] = {0, 0};
-  for (int g = (gmax >= 8 ? gmax / 8 : 1); g <= gmax; g <<= 1) {
-    for (int ppl = 1; ppl <= 2; ++ppl) {
-      const int32_t tile[2] = {g, ppl};
+  for (int k = 0; k < 3 && !rc; ++k) {
+    const int opl = set[k];
+    if (k > 0 && opl == set[k - 1]) continue;
+    const int chunks = d->o_pad / opl;
+    int gmax = 2;
+    while (gmax < chunks && gmax < 256) gmax <<= 1;
+    for (int g = (gmax >= 16 ? gmax / 8 : 2); g <= gmax && !rc; g <<= 1) {
+      const int32_t tile[2] = {g, opl};
       if ((rc = launch_eval(d, table, n_pts, pos, v, grad, lap, 0, tile, s))) break;   // warm-up
       float times[3];
       for (int r = 0; r < 3 && !rc; ++r) {
@@ -298,11 +307,11 @@ int spline_autotune(const spl_desc* d, const void* table, int64_t n_pts, const d
         if (!rc) rc = hip_fail(hipEventElapsedTime(&times[r], e0, e1), "hipEventElapsedTime");
       }
       if (rc) break;
-      float med = times[0] < times[1] ? (times[1] < times[2] ? times[1] : (times[0] < times[2] ? times[2] : times[0]))
-                                      : (times[0] < times[2] ? times[0] : (times[1] < times[2] ? times[2] : times[1]));
-      if (med < best) { best = med; best_tile[0] = g; best_tile[1] = ppl; }
+      float lo = times[0] < times[1] ? times[0] : times[1];
+      float hi = times[0] < times[1] ? times[1] : times[0];
+      const float med = times[2] < lo ? lo : (times[2] > hi ? hi : times[2]);
+      if (med < best) { best = med; best_tile[0] = g; best_tile[1] = opl; }
     }
-    if (rc) break;
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);

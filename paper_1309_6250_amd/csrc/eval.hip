@@ -4,15 +4,25 @@
 
 namespace pws {
 
-EvalKernel pick_eval_f64(int mode, int g, int ppl);
-EvalKernel pick_eval_f32(int mode, int g, int ppl);
-EvalKernel pick_eval_bf16(int mode, int g, int ppl);
+EvalKernel pick_eval_f64(int mode, int g, int opl);
+EvalKernel pick_eval_f32(int mode, int g, int opl);
+EvalKernel pick_eval_bf16(int mode, int g, int opl);
 
+// coefficients per 16-byte vector (the padding quantum of a table row)
 int vec_of(int dtype) { return dtype == SPL_F64 ? 2 : dtype == SPL_F32 ? 4 : 8; }
 
-bool tile_valid(const int32_t tile[2]) {
-  const int g = tile[0], ppl = tile[1];
-  return g >= 1 && g <= 256 && (g & (g - 1)) == 0 && (ppl == 1 || ppl == 2);
+// orbitals-per-lane choices of the forward kernels, per storage dtype: {lo, mid, hi}
+void opl_set(int dtype, int out[3]) {
+  if (dtype == SPL_F64) { out[0] = 1; out[1] = 2; out[2] = 2; }
+  else if (dtype == SPL_F32) { out[0] = 1; out[1] = 2; out[2] = 4; }
+  else { out[0] = 2; out[1] = 4; out[2] = 8; }
+}
+
+bool tile_valid(int dtype, const int32_t tile[2]) {
+  const int g = tile[0], opl = tile[1];
+  int set[3];
+  opl_set(dtype, set);
+  return g >= 2 && g <= 256 && (g & (g - 1)) == 0 && (opl == set[0] || opl == set[1] || opl == set[2]);
 }
 
 // Launch one forward evaluation.  mode: 0 values only, 1 VGL (separate Laplacian if has_lap).
@@ -28,12 +38,13 @@ int launch_eval(const spl_desc* d, const void* table, int64_t n_pts, const doubl
   a.lap = lap;
   a.n_pts = (int32_t)n_pts;
   a.n_orb = d->n_orb;
-  const int vec = vec_of(d->dtype);
-  a.n_chunks = d->o_pad / vec;
-  // whole-vector stores need n_orb % VEC == 0 and 16-byte aligned outputs
+  if (!tile_valid(d->dtype, tile)) return fail(SPL_EINVAL, "invalid tile shape (%d, %d)", tile[0], tile[1]);
+  const int opl = tile[1];
+  a.n_chunks = d->o_pad / opl;
+  // whole-vector stores need n_orb % OPL == 0 and 16-byte aligned outputs
   const bool al = ((uintptr_t)v & 15) == 0 && (values_only || (((uintptr_t)grad & 15) == 0 &&
                                                                ((uintptr_t)lap & 15) == 0));
-  a.vec_store = (d->n_orb % vec) == 0 && al;
+  a.vec_store = (d->n_orb % opl) == 0 && al;
   a.lap_off = d->table_elems;
   const int mode = values_only ? MODE_V : (d->has_lap ? MODE_VGL_SEPLAP : MODE_VGL);
   EvalKernel k = nullptr;
@@ -41,7 +52,7 @@ int launch_eval(const spl_desc* d, const void* table, int64_t n_pts, const doubl
   else if (d->dtype == SPL_F32) k = pick_eval_f32(mode, tile[0], tile[1]);
   else k = pick_eval_bf16(mode, tile[0], tile[1]);
   if (!k) return fail(SPL_EINVAL, "invalid tile shape (%d, %d)", tile[0], tile[1]);
-  const int64_t per_block = (int64_t)(256 / tile[0]) * tile[1];
+  const int64_t per_block = 256 / tile[0];
   const dim3 grid((unsigned)((n_pts + per_block - 1) / per_block));
   hipLaunchKernelGGL(k, grid, dim3(256), 0, stream, a);
   return hip_fail(hipGetLastError(), "evaluation launch");

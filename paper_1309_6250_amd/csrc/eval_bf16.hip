@@ -3,6 +3,6 @@
 
 namespace pws {
 
-EvalKernel pick_eval_bf16(int mode, int g, int ppl) { return pick_mode<uint16_t>(mode, g, ppl); }
+EvalKernel pick_eval_bf16(int mode, int g, int opl) { return pick_mode<uint16_t>(mode, g, opl); }
 
 }  // namespace pws

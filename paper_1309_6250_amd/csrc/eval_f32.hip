@@ -3,6 +3,6 @@
 
 namespace pws {
 
-EvalKernel pick_eval_f32(int mode, int g, int ppl) { return pick_mode<float>(mode, g, ppl); }
+EvalKernel pick_eval_f32(int mode, int g, int opl) { return pick_mode<float>(mode, g, opl); }
 
 }  // namespace pws

@@ -3,6 +3,6 @@
 
 namespace pws {
 
-EvalKernel pick_eval_f64(int mode, int g, int ppl) { return pick_mode<double>(mode, g, ppl); }
+EvalKernel pick_eval_f64(int mode, int g, int opl) { return pick_mode<double>(mode, g, opl); }
 
 }  // namespace pws

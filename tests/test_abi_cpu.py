@@ -146,10 +146,27 @@ def test_last_error_cleared_on_success():
     assert lib.spline_last_error() == b""
 
 
+OPL_SETS = {"f64": (1, 2), "f32": (1, 2, 4), "bf16": (2, 4, 8)}
+
+
 def test_tile_for_default_covers_orbitals():
-    for dtype, vec in (("f64", 2), ("f32", 4), ("bf16", 8)):
+    for dtype in ("f64", "f32", "bf16"):
         for n_orb in (4, 128, 256):
             d = P.spline_desc_init(np.eye(3) * 5, (8, 8, 8), n_orb, dtype)
-            g, ppl = P.spline_tile_for(d)
-            chunks = d.o_pad // vec
-            assert g >= min(chunks, 256) and (g & (g - 1)) == 0 and ppl in (1, 2)
+            g, opl = P.spline_tile_for(d)
+            assert opl in OPL_SETS[dtype] and (g & (g - 1)) == 0 and 2 <= g <= 256
+            assert g * opl >= min(d.o_pad, 256 * opl)        # one pass covers a table row
+
+
+def test_tile_validation_per_dtype():
+    """Orbitals-per-lane choices outside a dtype's set are rejected before any launch."""
+    lib = P.lib()
+    fake = ctypes.c_void_p(4096)        # never dereferenced: only invalid tiles are passed with n_pts > 0
+    for dtype, ok in OPL_SETS.items():
+        d = P.spline_desc_init(np.eye(3) * 5, (8, 8, 8), 16, dtype)
+        for opl in (1, 2, 3, 4, 8, 16):
+            if opl in ok:
+                continue
+            tile = (ctypes.c_int32 * 2)(64, opl)
+            assert lib.spline_eval_vgl_tile(ctypes.byref(d), fake, 10, fake, fake, fake, fake, tile,
+                                            None) == P.SPL_EINVAL

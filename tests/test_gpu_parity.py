@@ -150,10 +150,11 @@ def test_all_tiles_give_identical_results(case, dtype):
     d = _desc(case, dtype)
     tab = table_from_oracle(d, case["beta"], dtype, case["lbeta"])
     pos = case["pos"][:700]
-    ref = gpu_vgl(d, tab, pos, tile=(1, 1))
+    opls = {"f64": (1, 2), "f32": (1, 2, 4), "bf16": (2, 4, 8)}[dtype]
+    ref = gpu_vgl(d, tab, pos, tile=(2, opls[0]))
     for g in (2, 4, 16, 64, 256):
-        for ppl in (1, 2):
-            out = gpu_vgl(d, tab, pos, tile=(g, ppl))
+        for opl in opls:
+            out = gpu_vgl(d, tab, pos, tile=(g, opl))
             for a, b in zip(out, ref):
                 np.testing.assert_array_equal(a, b)
 

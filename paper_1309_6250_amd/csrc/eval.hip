@@ -40,7 +40,7 @@ int launch_eval(const spl_desc* d, const void* table, int64_t n_pts, const doubl
   a.n_orb = d->n_orb;
   if (!tile_valid(d->dtype, tile)) return fail(SPL_EINVAL, "invalid tile shape (%d, %d)", tile[0], tile[1]);
   const int opl = tile[1];
-  a.n_chunks = d->o_pad / opl;
+  a.n_chunks = (d->n_orb + opl - 1) / opl;   // loads stay inside the row: o_pad is a multiple of opl
   // whole-vector stores need n_orb % OPL == 0 and 16-byte aligned outputs
   const bool al = ((uintptr_t)v & 15) == 0 && (values_only || (((uintptr_t)grad & 15) == 0 &&
                                                                ((uintptr_t)lap & 15) == 0));

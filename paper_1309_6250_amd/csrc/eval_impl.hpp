@@ -32,7 +32,7 @@ struct EvalArgs {
   void* lap;
   int32_t n_pts;
   int32_t n_orb;
-  int32_t n_chunks;   // o_pad / OPL
+  int32_t n_chunks;   // ceil(n_orb / OPL): chunks holding at least one real orbital
   int32_t vec_store;  // n_orb % OPL == 0 and outputs 16-byte aligned: whole-vector stores
   int64_t lap_off;    // element offset of the separate Laplacian table
 };
@@ -95,9 +95,11 @@ template <> struct RowN<uint16_t, 8> {
 };
 
 // ---------------------------------------------------------------- stores of OPL outputs
+// Whole-vector stores only when the vector lies inside the n_orb real orbitals of the row;
+// otherwise element by element with the tail masked (outputs are unpadded [.][n_orb]).
 template <typename O, int OPL>
 __device__ __forceinline__ void store_out(O* dst, const O (&x)[OPL], int o, int n_orb, bool vec_ok) {
-  if (vec_ok) {
+  if (vec_ok && o + OPL <= n_orb) {
     if constexpr (sizeof(O) == 8 && OPL == 2) {
       __builtin_nontemporal_store(d2v{x[0], x[1]}, reinterpret_cast<d2v*>(dst + o));
       return;

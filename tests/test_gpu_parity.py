@@ -247,3 +247,35 @@ def test_backward_matches_oracle(case, dtype, which):
     # third derivative); compare normwise over all points, which such points cannot dominate
     gp = gpos.cpu().numpy()
     assert normwise(gp, rp) <= (1e-10 if dtype == "f64" else 1e-4)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("n_orb", [1, 3, 4, 8, 12])
+def test_no_writes_past_outputs(dtype, n_orb):
+    """Outputs live at the front of larger buffers whose tails hold a sentinel: every tile and
+    both entry points must leave the tails untouched (padding chunks are never stored)."""
+    rng = np.random.default_rng(103)
+    grid = (6, 5, 7)
+    beta = rng.standard_normal(grid + (n_orb,))
+    d = P.spline_desc_init(SKEW, grid, n_orb, dtype)
+    tab = table_from_oracle(d, beta, dtype)
+    n = 37
+    pos = to_dev(rng.uniform(-5, 5, size=(n, 3)))
+    od = torch.float64 if dtype == "f64" else torch.float32
+    guard = 64
+    opls = {"f64": (1, 2), "f32": (1, 2, 4), "bf16": (2, 4, 8)}[dtype]
+    for g in (2, 8, 64):
+        for opl in opls:
+            say("guard band", dtype, n_orb, g, opl)
+            bufs = [torch.full((k * n * n_orb + guard,), 7.25, dtype=od, device=DEV) for k in (1, 3, 1)]
+            v, gr, lp = (bufs[0][:n * n_orb].view(n, n_orb), bufs[1][:3 * n * n_orb].view(n, 3, n_orb),
+                         bufs[2][:n * n_orb].view(n, n_orb))
+            P.spline_eval_vgl(d, tab, pos, v, gr, lp, tile=(g, opl))
+            torch.cuda.synchronize()
+            for b, k in zip(bufs, (1, 3, 1)):
+                assert torch.all(b[k * n * n_orb:] == 7.25)
+            assert torch.isfinite(v).all() and torch.isfinite(gr).all() and torch.isfinite(lp).all()
+    vb = torch.full((n * n_orb + guard,), 7.25, dtype=od, device=DEV)
+    P.spline_eval_v(d, tab, pos, vb[:n * n_orb].view(n, n_orb))
+    torch.cuda.synchronize()
+    assert torch.all(vb[n * n_orb:] == 7.25)

@@ -1,0 +1,393 @@
+#!/usr/bin/env python3
+"""Orbital-VGL throughput of the periodic B-spline library on one MI355X.
+
+A step is one VGL sweep (value, gradient and Laplacian of every orbital at every point of
+one walker population) through spline_eval_vgl.  The headline workload is the 64-atom
+Si-like cell: 128 orbitals on a 48^3 grid, 256 walkers x 256 electrons, FP64 coefficient
+table.  Inputs (table and positions) are resident in HBM before timing starts.
+
+Also reported on the same JSON line:
+  forms     the precision forms (FP64 / FP32 / BF16 tables, with and without a separate
+            Laplacian spline) on the Si cell and on the MgO-like cell (256 orbitals, 96^3
+            grid, 512 x 128 points: tables of 0.45-3.6 GB, far beyond on-chip caches), each
+            with throughput, algorithmic bandwidth and its error against the FP64 oracle;
+  rows      the other entry points of the path: spline_build, spline_eval_v, the adjoint
+            and the batched persistent launch;
+  roofline  the dominant kernel (the headline VGL launch) against MI355X's 8 TB/s HBM peak;
+  cpu_baseline  the FP64 CPU oracle timed on the host on the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick] [--only FORM]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = ("paper_1309_6250_amd/csrc/eval_impl.hpp", "paper_1309_6250_amd/csrc/common.hpp")
+STORE_BYTES = {"f64": 8, "f32": 4, "bf16": 2}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def bytes_per_eval(dtype, has_lap):
+    """Algorithmic HBM bytes of one orbital-VGL: 64 coefficients (x2 with a separate Laplacian
+    table) plus 5 outputs; positions add 24 bytes per point."""
+    out = 8 if dtype == "f64" else 4
+    return 64 * STORE_BYTES[dtype] * (2 if has_lap else 1) + 5 * out
+
+
+def time_launches(fn, steps, warmup):
+    """Average ms per call of fn() over `steps` calls, HIP events on torch's current stream
+    (the stream the library launches on), bracketed by device synchronizations."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def normwise(a, b):
+    import numpy as np
+    return float(np.nanmax(np.abs(a - b)) / np.nanmax(np.abs(b)))
+
+
+class Workload:
+    """One single-system workload: host inputs at construction, device copies on upload()."""
+
+    def __init__(self, key, lap=False):
+        from workloads import config
+        self.key = key
+        self.w = config(key)
+        s = self.w.system
+        self.s = s
+        t0 = time.time()
+        self.f_host = s.grid_values()
+        self.lf_host = s.grid_laplacian() if lap else None
+        self.pos_host = self.w.positions()
+        log(f"config {key} ({s.name}) host inputs in {time.time() - t0:.1f} s")
+
+    def upload(self):
+        import torch
+        self.f = torch.from_numpy(self.f_host).cuda()
+        self.lf = None if self.lf_host is None else torch.from_numpy(self.lf_host).cuda()
+        self.pos = torch.from_numpy(self.pos_host).cuda()
+        torch.cuda.synchronize()
+        return self
+
+    def describe(self, dtype, has_lap):
+        s = self.s
+        return {"workload": s.name, "n_orb": s.n_orb, "grid": list(s.grid), "walkers": self.w.n_walkers,
+                "electrons": self.w.n_elec, "points": int(self.pos.shape[0]), "table": dtype,
+                "separate_laplacian": bool(has_lap), "lattice_bohr": [round(x, 6) for x in s.lattice.reshape(-1)]}
+
+
+def run_form(wl, dtype, has_lap, steps, warmup, tune=True):
+    """Build, autotune and time one form; returns (record, desc, table, outputs)."""
+    import torch
+    import paper_1309_6250_amd as P
+    s = wl.s
+    d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype, has_lap=has_lap)
+    work = torch.empty(d.work_bytes // 8, dtype=torch.float64, device="cuda")
+    table = P.new_table(d)
+    build_ms = time_launches(lambda: P.spline_build(d, wl.f, wl.lf if has_lap else None, table, work),
+                             1, 1)
+    outs = P.spline_eval_vgl(d, table, wl.pos)
+    tile = P.spline_autotune(d, table, wl.pos, *outs) if tune else P.spline_tile_for(d)
+    ms = time_launches(lambda: P.spline_eval_vgl(d, table, wl.pos, *outs), steps, warmup)
+    n_pts, n_orb = wl.pos.shape[0], s.n_orb
+    evals = n_pts * n_orb
+    alg = evals * bytes_per_eval(dtype, has_lap) + 24 * n_pts
+    rec = {
+        "evals_per_s": evals / (ms * 1e-3),
+        "ms_per_sweep": ms,
+        "alg_bytes_per_sweep": alg,
+        "alg_GBps": alg / (ms * 1e-3) / 1e9,
+        "frac_hbm_peak": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "tile": list(tile),
+        "table_bytes": int(d.table_bytes),
+        "build_ms": build_ms,
+    }
+    del work
+    return rec, d, table, outs
+
+
+def accuracy(wl, dtype, has_lap, outs, n_sample=48, n_orb_ref=16):
+    """Errors of the GPU outputs against the FP64 oracle on a seeded sample of points and the
+    first orbitals: the FP64 interpolating spline (storage + arithmetic error of the form) and the
+    planewave sum (the spline's own approximation error)."""
+    import numpy as np
+    from oracle import build as obuild, evaluate as oeval, pw as opw
+    rng = np.random.default_rng(1309)
+    idx = np.sort(rng.choice(wl.pos_host.shape[0], size=n_sample, replace=False))
+    pos = wl.pos_host[idx]
+    k = min(n_orb_ref, wl.s.n_orb)
+    key = (has_lap, k)
+    cache = wl.__dict__.setdefault("_oracle_cache", {})
+    if key not in cache:
+        beta = obuild.build_interp(np.ascontiguousarray(wl.f_host[..., :k]))
+        lbeta = obuild.build_interp(np.ascontiguousarray(wl.lf_host[..., :k])) if has_lap else None
+        ref = oeval.eval_vgl(beta, wl.s.lattice, pos, lap_beta=lbeta)
+        pwref = opw.pw_vgl(wl.s.gvecs, wl.s.coef[:k], pos)
+        cache[key] = (ref, pwref)
+    ref, pwref = cache[key]
+    got = [outs[0].double().cpu().numpy()[idx, :k], outs[1].double().cpu().numpy()[idx, :, :k],
+           outs[2].double().cpu().numpy()[idx, :k]]
+    res = {}
+    for name, g, r, p in zip(("V", "grad", "lap"), got, ref, pwref):
+        res[name] = {"normwise_vs_fp64_spline": normwise(g, r), "maxabs_vs_fp64_spline": float(np.abs(g - r).max()),
+                     "normwise_vs_planewave": normwise(g, p),
+                     "rmae_vs_planewave": float(np.abs(g - p).mean() / np.abs(p).mean())}
+    res["sample"] = f"{n_sample} seeded points x first {k} orbitals"
+    return res
+
+
+def cpu_baseline(wl, max_workers=16):
+    """The FP64 oracle (eval_vgl on the oracle's own interpolating table) on the host cores,
+    over the whole point set of the workload, split across worker processes."""
+    import multiprocessing as mp
+    import numpy as np
+    from oracle import build as obuild
+    global _CPU_BETA, _CPU_LAT, _CPU_POS
+    t0 = time.time()
+    _CPU_BETA = obuild.build_interp(wl.f_host)
+    _CPU_LAT = wl.s.lattice
+    _CPU_POS = wl.pos_host
+    build_s = time.time() - t0
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    workers = max(1, min(max_workers, cores))      # never more than the box's 16-core share
+    n = _CPU_POS.shape[0]
+    bounds = np.linspace(0, n, workers + 1).astype(int)
+    ctx = mp.get_context("fork")
+    t0 = time.time()
+    with ctx.Pool(workers) as pool:
+        pool.map(_cpu_worker, [(int(bounds[i]), int(bounds[i + 1])) for i in range(workers)])
+    wall = time.time() - t0
+    evals = n * wl.s.n_orb
+    return {"value": evals / wall, "unit": "orbital-VGL evals/s", "cores": workers, "kind": "oracle",
+            "sample": f"all {n} points x {wl.s.n_orb} orbitals of {wl.s.name} (FP64 table), "
+                      f"{workers} processes; oracle build {build_s:.1f} s not included",
+            "wall_s": wall}
+
+
+_CPU_BETA = _CPU_LAT = _CPU_POS = None
+
+
+def _cpu_worker(rng_):
+    from threadpoolctl import threadpool_limits
+    from oracle import evaluate as oeval
+    with threadpool_limits(1):
+        a, b = rng_
+        oeval.eval_vgl(_CPU_BETA, _CPU_LAT, _CPU_POS[a:b])
+    return rng_[1] - rng_[0]
+
+
+def traffic_for(form_key):
+    """Measured HBM bytes per launch from the committed rocprof counter summary, or None when the
+    kernel sources changed since the counters were taken."""
+    try:
+        with open(PROFILE_TRAFFIC) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = data.get("forms", {}).get(form_key)
+    if not ent or ent.get("kernel_hash") != kernel_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def rows_measurements(wl1, steps, warmup):
+    """The other entry points of the path, timed on the Si workload."""
+    import torch
+    import paper_1309_6250_amd as P
+    out = {}
+    s = wl1.s
+    n_pts = wl1.pos.shape[0]
+    # spline_build (three-stage cyclic solves): each stage reads and writes the FP64 grid once
+    for dtype in ("f64", "f32"):
+        d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype)
+        work = torch.empty(d.work_bytes // 8, dtype=torch.float64, device="cuda")
+        table = P.new_table(d)
+        ms = time_launches(lambda: P.spline_build(d, wl1.f, None, table, work), max(3, steps // 4), 1)
+        pts = s.grid[0] * s.grid[1] * s.grid[2]
+        alg = 5 * pts * s.n_orb * 8 + pts * d.o_pad * STORE_BYTES[dtype]
+        out[f"spline_build_{dtype}"] = {"ms": ms, "alg_GBps": alg / (ms * 1e-3) / 1e9,
+                                        "note": "3 stages: read+write FP64 twice, read FP64 + write table once"}
+    # spline_eval_v
+    d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, "f64")
+    table = P.spline_build(d, wl1.f)
+    v = P.spline_eval_v(d, table, wl1.pos)
+    ms = time_launches(lambda: P.spline_eval_v(d, table, wl1.pos, v), steps, warmup)
+    alg = n_pts * s.n_orb * (64 * 8 + 8) + 24 * n_pts
+    out["spline_eval_v_f64"] = {"ms": ms, "evals_per_s": n_pts * s.n_orb / (ms * 1e-3),
+                                "alg_GBps": alg / (ms * 1e-3) / 1e9}
+    # adjoint (FP32 table, all three upstream gradients)
+    d32 = P.spline_desc_init(s.lattice, s.grid, s.n_orb, "f32")
+    t32 = P.spline_build(d32, wl1.f)
+    g = torch.Generator(device="cuda").manual_seed(7)
+    gv = torch.randn((n_pts, s.n_orb), device="cuda", generator=g)
+    gg = torch.randn((n_pts, 3, s.n_orb), device="cuda", generator=g)
+    gl = torch.randn((n_pts, s.n_orb), device="cuda", generator=g)
+    gt = P.new_gtable(d32)
+    gp = torch.empty((n_pts, 3), dtype=torch.float64, device="cuda")
+    ms = time_launches(lambda: P.spline_eval_vgl_backward(d32, t32, wl1.pos, gv, gg, gl, gt, gp),
+                       max(3, steps // 4), 1)
+    out["spline_eval_vgl_backward_f32"] = {"ms": ms, "evals_per_s": n_pts * s.n_orb / (ms * 1e-3),
+                                           "note": "gather for d pos + atomic scatter of d table"}
+    return out
+
+
+def _gpu_ready():
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    import paper_1309_6250_amd as P
+    P.lib()
+    return torch
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--quick", action="store_true", help="headline only: no extra forms, rows or CPU baseline")
+    ap.add_argument("--only", default=None,
+                    help="time only one form, e.g. c2-f32 or c2-bf16-lap (for profiling runs)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device-to-device copy (scales memory counters)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the evaluation shards by points with no communication, "
+              "so N GPUs would run N independent copies of this workload. Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    if args.copy_calibration:
+        torch = _gpu_ready()
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")      # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 copies of 1 GiB (1073741824 bytes read + written each)")
+        del src, dst
+
+    if args.only:
+        key, dtype, *rest = args.only.split("-")
+        lap = bool(rest and rest[0] == "lap")
+        wl = Workload(int(key[1:]), lap=lap)
+        _gpu_ready()
+        wl.upload()
+        rec, *_ = run_form(wl, dtype, lap, args.steps, args.warmup)
+        print(json.dumps({"only": args.only, **rec}), flush=True)
+        return
+
+    wl1 = Workload(1)
+    cpu = None
+    if not args.quick and not args.no_cpu:
+        # the host leg runs first, in forked worker processes, before this process touches the GPU
+        cpu = cpu_baseline(wl1)
+        log(f"cpu baseline: {cpu['value']:.3e} evals/s on {cpu['cores']} processes")
+    torch = _gpu_ready()
+    wl1.upload()
+    head, d1, t1, o1 = run_form(wl1, "f64", False, args.steps, args.warmup)
+    log(f"headline c1-f64: {head['ms_per_sweep']:.3f} ms, {head['evals_per_s']:.3e} evals/s, "
+        f"{head['alg_GBps']:.0f} GB/s algorithmic")
+    head["accuracy"] = accuracy(wl1, "f64", False, o1)
+    n_pts = int(wl1.pos.shape[0])
+    per_launch = head["alg_bytes_per_sweep"]
+    traffic = traffic_for("c1-f64")
+    roofline = {"bound": "hbm", "achieved": head["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": head["alg_GBps"] / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "k_eval (spline_eval_vgl, FP64 table)",
+                "alg_bytes_per_launch": per_launch,
+                "per_unit": "552 B per orbital-VGL (64 x 8 B coefficients + 5 x 8 B outputs) + 24 B per point",
+                "kernel_hash": kernel_hash()}
+
+    forms = {"c1-f64": head}
+    rows = {}
+    if not args.quick:
+        for dtype in ("f32", "bf16"):
+            rec, d, t, o = run_form(wl1, dtype, False, args.steps, args.warmup)
+            rec["accuracy"] = accuracy(wl1, dtype, False, o)
+            rec["speedup_vs_f64"] = rec["evals_per_s"] / head["evals_per_s"]
+            forms[f"c1-{dtype}"] = rec
+            log(f"c1-{dtype}: {rec['evals_per_s']:.3e} evals/s, {rec['alg_GBps']:.0f} GB/s")
+            del t, o
+        rows = rows_measurements(wl1, args.steps, args.warmup)
+        del t1, o1
+        torch.cuda.empty_cache()
+        wl2 = Workload(2, lap=True).upload()
+        f64_rate = {}
+        for lap in (False, True):
+            for dtype in ("f64", "f32", "bf16"):
+                rec, d, t, o = run_form(wl2, dtype, lap, args.steps, args.warmup)
+                rec["accuracy"] = accuracy(wl2, dtype, lap, o)
+                name = f"c2-{dtype}" + ("-lap" if lap else "")
+                if dtype == "f64":
+                    f64_rate[lap] = rec["evals_per_s"]
+                rec["speedup_vs_f64"] = rec["evals_per_s"] / f64_rate[lap]
+                rec["traffic"] = traffic_for(name)
+                forms[name] = rec
+                log(f"{name}: {rec['evals_per_s']:.3e} evals/s, {rec['alg_GBps']:.0f} GB/s "
+                    f"({100 * rec['frac_hbm_peak']:.0f}% of HBM peak)")
+                del t, o
+                torch.cuda.empty_cache()
+
+    ms = head["ms_per_sweep"]
+    line = {
+        "metric": "orbital-VGL evals/sec",
+        "value": head["evals_per_s"],
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded planewave orbitals, uniform random electron positions)",
+        "config": wl1.describe("f64", False),
+        "roofline": roofline,
+        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
+        "forms": forms,
+        "rows": rows,
+    }
+    if cpu is not None:
+        line["gpu_over_cpu"] = head["evals_per_s"] / cpu["value"]
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -105,8 +105,8 @@ class Workload:
                 "separate_laplacian": bool(has_lap), "lattice_bohr": [round(x, 6) for x in s.lattice.reshape(-1)]}
 
 
-def run_form(wl, dtype, has_lap, steps, warmup, tune=True):
-    """Build, autotune and time one form; returns (record, desc, table, outputs)."""
+def run_form(wl, dtype, has_lap, steps, warmup, tune=True, tile=None):
+    """Build, autotune (or take `tile`) and time one form; returns (record, desc, table, outputs)."""
     import torch
     import paper_1309_6250_amd as P
     s = wl.s
@@ -115,9 +115,10 @@ def run_form(wl, dtype, has_lap, steps, warmup, tune=True):
     table = P.new_table(d)
     build_ms = time_launches(lambda: P.spline_build(d, wl.f, wl.lf if has_lap else None, table, work),
                              1, 1)
-    outs = P.spline_eval_vgl(d, table, wl.pos)
-    tile = P.spline_autotune(d, table, wl.pos, *outs) if tune else P.spline_tile_for(d)
-    ms = time_launches(lambda: P.spline_eval_vgl(d, table, wl.pos, *outs), steps, warmup)
+    outs = P.spline_eval_vgl(d, table, wl.pos, tile=tile)
+    if tile is None:
+        tile = P.spline_autotune(d, table, wl.pos, *outs) if tune else P.spline_tile_for(d)
+    ms = time_launches(lambda: P.spline_eval_vgl(d, table, wl.pos, *outs, tile=tile), steps, warmup)
     n_pts, n_orb = wl.pos.shape[0], s.n_orb
     evals = n_pts * n_orb
     alg = evals * bytes_per_eval(dtype, has_lap) + 24 * n_pts
@@ -282,6 +283,7 @@ def main():
     ap.add_argument("--only", default=None,
                     help="time only one form, e.g. c2-f32 or c2-bf16-lap (for profiling runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--tile", default=None, help="with --only: fixed tile 'G,OPL' instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (scales memory counters)")
     args = ap.parse_args()
@@ -308,7 +310,8 @@ def main():
         wl = Workload(int(key[1:]), lap=lap)
         _gpu_ready()
         wl.upload()
-        rec, *_ = run_form(wl, dtype, lap, args.steps, args.warmup)
+        tile = None if args.tile is None else tuple(int(x) for x in args.tile.split(","))
+        rec, *_ = run_form(wl, dtype, lap, args.steps, args.warmup, tile=tile)
         print(json.dumps({"only": args.only, **rec}), flush=True)
         return
 

@@ -264,6 +264,41 @@ def rows_measurements(wl1, steps, warmup):
     return out
 
 
+def batched_row(steps, warmup):
+    """48 uneven systems (orbitals 32-256, grids 24^3-64^3, 16-512 walkers x 64-256 electrons),
+    FP32 tables built on the GPU, all VGL evaluations in one persistent launch replayed from a
+    HIP graph, tile chosen by the batch autotuner."""
+    import torch
+    import paper_1309_6250_amd as P
+    from workloads import batched_systems
+    t0 = time.time()
+    items, table_bytes = [], 0
+    for w in batched_systems():
+        s = w.system
+        f = torch.from_numpy(s.grid_values()).cuda()
+        d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, "f32")
+        tab = P.spline_build(d, f)
+        del f
+        pos = torch.from_numpy(w.positions()).cuda()
+        n = pos.shape[0]
+        items.append((d, tab, pos, torch.empty((n, s.n_orb), device="cuda"),
+                      torch.empty((n, 3, s.n_orb), device="cuda"), torch.empty((n, s.n_orb), device="cuda")))
+        table_bytes += d.table_bytes
+    torch.cuda.synchronize()
+    log(f"batched workload: {len(items)} systems ready in {time.time() - t0:.1f} s")
+    plan = P.BatchPlan(items)
+    tile = plan.autotune()
+    n_tiles, n_evals = plan.info()
+    ms = time_launches(plan.run_graph, steps, warmup)
+    ms_eager = time_launches(plan.run, steps, warmup)
+    alg = sum(it[2].shape[0] * it[0].n_orb * bytes_per_eval("f32", False) + 24 * it[2].shape[0] for it in items)
+    plan.close()
+    return {"systems": len(items), "evals_per_launch": n_evals, "tiles": n_tiles, "tile": list(tile),
+            "ms_graph": ms, "ms_eager": ms_eager, "evals_per_s": n_evals / (ms * 1e-3),
+            "alg_GBps": alg / (ms * 1e-3) / 1e9, "frac_hbm_peak": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "table_bytes": table_bytes}
+
+
 def _gpu_ready():
     import torch
     if not torch.cuda.is_available():
@@ -348,6 +383,9 @@ def main():
             log(f"c1-{dtype}: {rec['evals_per_s']:.3e} evals/s, {rec['alg_GBps']:.0f} GB/s")
             del t, o
         rows = rows_measurements(wl1, args.steps, args.warmup)
+        rows["batched_persistent_graph_f32"] = batched_row(args.steps, args.warmup)
+        log(f"batched: {rows['batched_persistent_graph_f32']['evals_per_s']:.3e} evals/s")
+        torch.cuda.empty_cache()
         del t1, o1
         torch.cuda.empty_cache()
         wl2 = Workload(2, lap=True).upload()

@@ -178,21 +178,33 @@ typedef struct spl_item {
 } spl_item;
 
 /*
- * Build a plan: copies per-item parameters and a work list of (item, point range)
- * tiles to device memory the plan owns (this call allocates, once, and
- * synchronizes `stream`).  tile: NULL = take the tile shape from the autotune
- * cache (or a default), else as in spline_eval_vgl_tile.  On success *plan is set.
+ * Build a plan: copies per-item parameters and the work list of (item, point tile) pairs
+ * to device memory the plan owns (this call allocates, once, and synchronizes `stream`).
+ * Items are reordered internally by decreasing work per tile; outputs go to each item's
+ * own buffers.  All items must share dtype and has_lap.  tile: NULL = the tuned (or
+ * default) shape of the heaviest item, else as in spline_eval_vgl_tile with tile[0] in
+ * 8..256.  On success *plan is set.  The item buffers must outlive the plan.
+ * Errors: any item failing the checks of spline_eval_vgl -> that code, prefixed with the
+ * item index; allocation failure -> SPL_ENOMEM.
  */
 int spline_batch_plan_create(const spl_item* items, int32_t n_items, const int32_t* tile,
                              void* stream, void** plan);
 
-/* One persistent launch over the plan's whole work list (graph-capturable: it
- * enqueues one small reset kernel and the persistent kernel, no memset, no allocation). */
+/* One persistent launch over the plan's whole work list: a counter-reset kernel then the
+ * persistent kernel, whose workgroups take point tiles from a device counter until none
+ * remain.  Graph-capturable (no memset, no allocation).  One launch of a plan at a time:
+ * concurrent launches of the same plan share its counter and race. */
 int spline_batch_eval_vgl(void* plan, void* stream);
 
-/* Capture spline_batch_eval_vgl into a HIP graph owned by the plan (once) and
- * launch it on `stream`.  Later calls relaunch the same graph. */
+/* Capture spline_batch_eval_vgl into a HIP graph owned by the plan (on first use, on a
+ * private stream of default priority) and launch that graph on `stream`.  Later calls
+ * replay the same graph; changing the plan's tile drops it. */
 int spline_batch_graph_launch(void* plan, void* stream);
+
+/* Time every batch tile shape (lanes per point 8..256 x the dtype's orbitals-per-lane
+ * choices) with whole persistent launches on `stream` (synchronizes), keep the fastest in
+ * the plan and return it in tile_out.  Outputs are overwritten with valid results. */
+int spline_batch_autotune(void* plan, void* stream, int32_t tile_out[2]);
 
 /* Release a plan and everything it owns (synchronizes the device first). */
 void spline_batch_plan_destroy(void* plan);

@@ -20,7 +20,7 @@ ERROR_NAMES = {
 EXPORTS = (
     "spline_desc_init", "spline_build", "spline_eval_v", "spline_eval_vgl", "spline_eval_vgl_tile",
     "spline_eval_vgl_backward", "spline_batch_plan_create", "spline_batch_eval_vgl",
-    "spline_batch_graph_launch", "spline_batch_plan_destroy", "spline_batch_plan_info", "spline_autotune",
+    "spline_batch_graph_launch", "spline_batch_autotune", "spline_batch_plan_destroy", "spline_batch_plan_info", "spline_autotune",
     "spline_tile_for", "spline_last_error", "spline_version",
 )
 
@@ -87,6 +87,7 @@ def lib():
                                                         ctypes.POINTER(vp)]),
             "spline_batch_eval_vgl": (ctypes.c_int, [vp, vp]),
             "spline_batch_graph_launch": (ctypes.c_int, [vp, vp]),
+            "spline_batch_autotune": (ctypes.c_int, [vp, vp, i32p]),
             "spline_batch_plan_destroy": (None, [vp]),
             "spline_batch_plan_info": (ctypes.c_int, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
             "spline_autotune": (ctypes.c_int, [pd, vp, i64, vp, vp, vp, vp, vp, i32p]),

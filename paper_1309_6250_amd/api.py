@@ -212,6 +212,11 @@ class BatchPlan:
     def run_graph(self, stream=None):
         check(lib().spline_batch_graph_launch(self._plan, _stream(stream)), "spline_batch_graph_launch")
 
+    def autotune(self, stream=None):
+        t = (ctypes.c_int32 * 2)()
+        check(lib().spline_batch_autotune(self._plan, _stream(stream), t), "spline_batch_autotune")
+        return (t[0], t[1])
+
     def info(self):
         a, b = ctypes.c_int64(), ctypes.c_int64()
         check(lib().spline_batch_plan_info(self._plan, ctypes.byref(a), ctypes.byref(b)), "spline_batch_plan_info")

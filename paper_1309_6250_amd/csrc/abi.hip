@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "common.hpp"
+#include "internal.hpp"
 
 namespace pws {
 
@@ -180,7 +180,7 @@ int launch_backward(const spl_desc* d, const void* table, int64_t n_pts, const d
                     const void* ggrad, const void* glap, void* gtable, double* gpos, hipStream_t stream);
 int build_one(const spl_desc* d, const double* vals, void* table, double* work, hipStream_t stream);
 
-static int check_eval_args(const spl_desc* d, const void* table, int64_t n_pts, const double* pos) {
+int check_eval_args(const spl_desc* d, const void* table, int64_t n_pts, const double* pos) {
   int rc = check_desc(d);
   if (rc) return rc;
   if (n_pts < 0 || n_pts > 0x7fffffffLL) return fail(SPL_EINVAL, "n_pts = %lld outside [0, 2^31)", (long long)n_pts);
@@ -194,6 +194,13 @@ static int check_eval_args(const spl_desc* d, const void* table, int64_t n_pts, 
 
 static int out_align_ok(const spl_desc* d, const void* p) {
   return aligned(p, d->dtype == SPL_F64 ? 8 : 4);
+}
+
+int check_vgl_outputs(const spl_desc* d, const void* v, const void* grad, const void* lap) {
+  if (!v || !grad || !lap) return fail(SPL_EINVAL, "v, grad and lap must be non-NULL");
+  if (!out_align_ok(d, v) || !out_align_ok(d, grad) || !out_align_ok(d, lap))
+    return fail(SPL_EINVAL, "output not aligned to its element size");
+  return SPL_OK;
 }
 
 }  // namespace pws
@@ -247,9 +254,7 @@ int spline_eval_vgl_tile(const spl_desc* d, const void* table, int64_t n_pts, co
   clear_error();
   int rc = check_eval_args(d, table, n_pts, pos);
   if (rc || n_pts == 0) return rc;
-  if (!v || !grad || !lap) return fail(SPL_EINVAL, "v, grad and lap must be non-NULL");
-  if (!out_align_ok(d, v) || !out_align_ok(d, grad) || !out_align_ok(d, lap))
-    return fail(SPL_EINVAL, "output not aligned to its element size");
+  if ((rc = check_vgl_outputs(d, v, grad, lap))) return rc;
   if (!tile || !tile_valid(d->dtype, tile)) return fail(SPL_EINVAL, "invalid tile");
   return launch_eval(d, table, n_pts, pos, v, grad, lap, 0, tile, static_cast<hipStream_t>(stream));
 }

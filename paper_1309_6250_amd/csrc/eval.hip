@@ -25,27 +25,32 @@ bool tile_valid(int dtype, const int32_t tile[2]) {
   return g >= 2 && g <= 256 && (g & (g - 1)) == 0 && (opl == set[0] || opl == set[1] || opl == set[2]);
 }
 
-// Launch one forward evaluation.  mode: 0 values only, 1 VGL (separate Laplacian if has_lap).
-int launch_eval(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, void* v, void* grad,
-                void* lap, int values_only, const int32_t tile[2], hipStream_t stream) {
-  if (n_pts == 0) return SPL_OK;
-  EvalArgs a;
-  a.g = make_geom(d);
-  a.table = table;
-  a.pos = pos;
-  a.v = v;
-  a.grad = grad;
-  a.lap = lap;
-  a.n_pts = (int32_t)n_pts;
-  a.n_orb = d->n_orb;
-  if (!tile_valid(d->dtype, tile)) return fail(SPL_EINVAL, "invalid tile shape (%d, %d)", tile[0], tile[1]);
-  const int opl = tile[1];
-  a.n_chunks = (d->n_orb + opl - 1) / opl;   // loads stay inside the row: o_pad is a multiple of opl
+// Kernel arguments of one forward evaluation of one table with orbitals-per-lane `opl`.
+void fill_eval_args(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, void* v, void* grad,
+                    void* lap, int values_only, int opl, EvalArgs* a) {
+  a->g = make_geom(d);
+  a->table = table;
+  a->pos = pos;
+  a->v = v;
+  a->grad = grad;
+  a->lap = lap;
+  a->n_pts = (int32_t)n_pts;
+  a->n_orb = d->n_orb;
+  a->n_chunks = (d->n_orb + opl - 1) / opl;   // loads stay inside the row: o_pad is a multiple of opl
   // whole-vector stores need n_orb % OPL == 0 and 16-byte aligned outputs
   const bool al = ((uintptr_t)v & 15) == 0 && (values_only || (((uintptr_t)grad & 15) == 0 &&
                                                                ((uintptr_t)lap & 15) == 0));
-  a.vec_store = (d->n_orb % opl) == 0 && al;
-  a.lap_off = d->table_elems;
+  a->vec_store = (d->n_orb % opl) == 0 && al;
+  a->lap_off = d->table_elems;
+}
+
+// Launch one forward evaluation.  values_only: 1 values, 0 VGL (separate Laplacian if has_lap).
+int launch_eval(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, void* v, void* grad,
+                void* lap, int values_only, const int32_t tile[2], hipStream_t stream) {
+  if (n_pts == 0) return SPL_OK;
+  if (!tile_valid(d->dtype, tile)) return fail(SPL_EINVAL, "invalid tile shape (%d, %d)", tile[0], tile[1]);
+  EvalArgs a;
+  fill_eval_args(d, table, n_pts, pos, v, grad, lap, values_only, tile[1], &a);
   const int mode = values_only ? MODE_V : (d->has_lap ? MODE_VGL_SEPLAP : MODE_VGL);
   EvalKernel k = nullptr;
   if (d->dtype == SPL_F64) k = pick_eval_f64(mode, tile[0], tile[1]);

@@ -125,20 +125,14 @@ __device__ __forceinline__ A pick4(int l, A a0, A a1, A a2, A a3) {
   return l == 0 ? a0 : (l == 1 ? a1 : (l == 2 ? a2 : a3));
 }
 
+// All outputs of point p (0 <= p < a.n_pts) for the orbital chunks of lane `lane` of its group.
 template <typename TS, int MODE, int G, int OPL>
-__global__ __launch_bounds__(256) void k_eval(EvalArgs a) {
+__device__ __forceinline__ void eval_point(const EvalArgs& a, const int p, const int lane) {
   using A = typename Acc<TS>::type;
   using O = typename Out<TS>::type;
-  constexpr int GPB = 256 / G;
   constexpr int NQ = (MODE == MODE_V) ? 1 : (MODE == MODE_VGL ? 10 : 4);
-  const int grp = threadIdx.x / G;
-  const int lane = threadIdx.x % G;
   const TS* __restrict__ tab = static_cast<const TS*>(a.table);
   const bool vec_ok = a.vec_store != 0;
-
-  int p = (int)blockIdx.x * GPB + grp;
-  if constexpr (G >= 64) p = __builtin_amdgcn_readfirstlane(p);
-  if (p >= a.n_pts) return;
 
   int i0[3];
   double t[3];
@@ -296,7 +290,68 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs a) {
   }
 }
 
+// One launch over one table: groups of G lanes, one point per group.
+template <typename TS, int MODE, int G, int OPL>
+__global__ __launch_bounds__(256) void k_eval(EvalArgs a) {
+  constexpr int GPB = 256 / G;
+  int p = (int)blockIdx.x * GPB + (int)threadIdx.x / G;
+  if constexpr (G >= 64) p = __builtin_amdgcn_readfirstlane(p);
+  if (p >= a.n_pts) return;
+  eval_point<TS, MODE, G, OPL>(a, p, (int)threadIdx.x % G);
+}
+
+// ---------------------------------------------------------------- batched persistent launch
+// Many tables and point sets in one launch.  The work list is implicit: item j owns tiles
+// [tile_start[j], tile_start[j+1]), a tile being the 256 / G points one workgroup covers in one
+// pass.  Workgroups take tiles from a device counter until it passes n_tiles, so the launch is
+// load-balanced however uneven the items are; every workgroup leaves the loop once the counter
+// is exhausted.  Items are ordered by decreasing cost per tile on the host (largest first).
+struct BatchArgs {
+  const EvalArgs* items;      // device array [n_items]
+  const int32_t* tile_start;  // device array [n_items + 1], exclusive prefix of tiles per item
+  int32_t* counter;           // device int, zeroed by k_batch_reset before each launch
+  int32_t n_items;
+  int32_t n_tiles;
+};
+
+template <typename TS, int MODE, int G, int OPL>
+__global__ __launch_bounds__(256) void k_eval_batch(BatchArgs b) {
+  constexpr int GPB = 256 / G;
+  __shared__ int32_t s_tile;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(b.counter, 1);
+    __syncthreads();
+    const int tile = __builtin_amdgcn_readfirstlane(s_tile);
+    __syncthreads();                                   // s_tile is rewritten next iteration
+    if (tile >= b.n_tiles) break;                      // uniform: the whole workgroup leaves
+    int lo = 0, hi = b.n_items - 1;                    // last item whose first tile <= tile
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (b.tile_start[mid] <= tile) lo = mid;
+      else hi = mid - 1;
+    }
+    const EvalArgs& a = b.items[lo];
+    int p = (tile - b.tile_start[lo]) * GPB + (int)threadIdx.x / G;
+    if constexpr (G >= 64) p = __builtin_amdgcn_readfirstlane(p);
+    if (p < a.n_pts) eval_point<TS, MODE, G, OPL>(a, p, (int)threadIdx.x % G);
+  }
+}
+
 typedef void (*EvalKernel)(EvalArgs);
+typedef void (*BatchKernel)(BatchArgs);
+
+template <typename TS, int MODE, int OPL>
+inline BatchKernel pick_batch_g(int g) {
+  switch (g) {
+    case 8: return k_eval_batch<TS, MODE, 8, OPL>;
+    case 16: return k_eval_batch<TS, MODE, 16, OPL>;
+    case 32: return k_eval_batch<TS, MODE, 32, OPL>;
+    case 64: return k_eval_batch<TS, MODE, 64, OPL>;
+    case 128: return k_eval_batch<TS, MODE, 128, OPL>;
+    case 256: return k_eval_batch<TS, MODE, 256, OPL>;
+    default: return nullptr;
+  }
+}
 
 template <typename TS, int MODE, int OPL>
 inline EvalKernel pick_g(int g) {
@@ -328,6 +383,9 @@ inline EvalKernel pick_opl(int g, int opl) {
   return nullptr;
 }
 
+template <typename TS, int MODE>
+inline BatchKernel pick_batch_opl(int g, int opl);
+
 template <typename TS>
 inline EvalKernel pick_mode(int mode, int g, int opl) {
   switch (mode) {
@@ -335,6 +393,19 @@ inline EvalKernel pick_mode(int mode, int g, int opl) {
     case MODE_VGL: return pick_opl<TS, MODE_VGL>(g, opl);
     default: return pick_opl<TS, MODE_VGL_SEPLAP>(g, opl);
   }
+}
+
+template <typename TS, int MODE>
+inline BatchKernel pick_batch_opl(int g, int opl) {
+  if (opl == OplSet<TS>::lo) return pick_batch_g<TS, MODE, OplSet<TS>::lo>(g);
+  if (opl == OplSet<TS>::mid) return pick_batch_g<TS, MODE, OplSet<TS>::mid>(g);
+  if (opl == OplSet<TS>::hi) return pick_batch_g<TS, MODE, OplSet<TS>::hi>(g);
+  return nullptr;
+}
+
+template <typename TS>
+inline BatchKernel pick_batch_mode(int mode, int g, int opl) {
+  return mode == MODE_VGL ? pick_batch_opl<TS, MODE_VGL>(g, opl) : pick_batch_opl<TS, MODE_VGL_SEPLAP>(g, opl);
 }
 
 }  // namespace pws

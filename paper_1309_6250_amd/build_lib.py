@@ -24,6 +24,8 @@ CFLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # hardware FP atomics on coarse-grained (hipMalloc) memory
     "-munsafe-fp-atomics",
+    # no implicit contraction: device code writes every fused multiply-add explicitly
+    "-ffp-contract=off",
     "-Wall", "-Wno-unused-function",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]

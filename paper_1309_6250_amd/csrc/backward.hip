@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void k_backward(BwdArgs a) {
         const A g1 = (in && ggp) ? (A)ggp[pg + a.n_orb] : A(0);
         const A g2 = (in && ggp) ? (A)ggp[pg + 2 * a.n_orb] : A(0);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) gt[i][j] = jm[3 * i] * g0 + jm[3 * i + 1] * g1 + jm[3 * i + 2] * g2;
+        for (int i = 0; i < 3; ++i) gt[i][j] = fmaa(jm[3 * i + 2], g2, fmaa(jm[3 * i + 1], g1, jm[3 * i] * g0));
       }
 
       // ---------------- d beta: separable scatter, transpose of the forward contraction
@@ -113,20 +113,20 @@ __global__ __launch_bounds__(256) void k_backward(BwdArgs a) {
 #pragma unroll
           for (int j = 0; j < VEC; ++j) {
             const A cl = SEPLAP ? A(0) : gL[j];
-            e[0][j] = gV[j] * wx[l] + gt[0][j] * dwx[l] + mt[0] * cl * d2wx[l];   // with wy wz
-            e[1][j] = gt[1][j] * wx[l] + A(2) * mt[3] * cl * dwx[l];              // with dwy wz
-            e[2][j] = gt[2][j] * wx[l] + A(2) * mt[4] * cl * dwx[l];              // with wy dwz
-            e[3][j] = mt[1] * cl * wx[l];                                         // with d2wy wz
-            e[4][j] = mt[2] * cl * wx[l];                                         // with wy d2wz
-            e[5][j] = A(2) * mt[5] * cl * wx[l];                                  // with dwy dwz
+            e[0][j] = fmaa(mt[0] * cl, d2wx[l], fmaa(gt[0][j], dwx[l], gV[j] * wx[l]));   // with wy wz
+            e[1][j] = fmaa(A(2) * mt[3] * cl, dwx[l], gt[1][j] * wx[l]);                  // with dwy wz
+            e[2][j] = fmaa(A(2) * mt[4] * cl, dwx[l], gt[2][j] * wx[l]);                  // with wy dwz
+            e[3][j] = (mt[1] * cl) * wx[l];                                               // with d2wy wz
+            e[4][j] = (mt[2] * cl) * wx[l];                                               // with wy d2wz
+            e[5][j] = (A(2) * mt[5] * cl) * wx[l];                                        // with dwy dwz
           }
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
             A f0[VEC], f1[VEC], f2[VEC];
 #pragma unroll
             for (int j = 0; j < VEC; ++j) {
-              f0[j] = e[0][j] * wy[m] + e[1][j] * dwy[m] + e[3][j] * d2wy[m];
-              f1[j] = e[2][j] * wy[m] + e[5][j] * dwy[m];
+              f0[j] = fmaa(e[3][j], d2wy[m], fmaa(e[1][j], dwy[m], e[0][j] * wy[m]));
+              f1[j] = fmaa(e[5][j], dwy[m], e[2][j] * wy[m]);
               f2[j] = e[4][j] * wy[m];
             }
             GO* rp = gtab + rx[l] + ry[m] + o;
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void k_backward(BwdArgs a) {
 #pragma unroll
               for (int j = 0; j < VEC; ++j)
                 if (o + j < a.n_orb)
-                  atomic_add<GO>(rp + rz[n] + j, (GO)(f0[j] * wz[n] + f1[j] * dwz[n] + f2[j] * d2wz[n]));
+                  atomic_add<GO>(rp + rz[n] + j, (GO)fmaa(f2[j], d2wz[n], fmaa(f1[j], dwz[n], f0[j] * wz[n])));
             }
           }
         }
@@ -184,48 +184,46 @@ __global__ __launch_bounds__(256) void k_backward(BwdArgs a) {
             for (int n = 0; n < 4; ++n) Row16<TS>::load(rp + rz[n], r[n]);
 #pragma unroll
             for (int j = 0; j < VEC; ++j) {
-              const A z0 = wz[0] * r[0][j] + wz[1] * r[1][j] + wz[2] * r[2][j] + wz[3] * r[3][j];
-              const A z1 = dwz[0] * r[0][j] + dwz[1] * r[1][j] + dwz[2] * r[2][j] + dwz[3] * r[3][j];
-              B[0][j] += wy[m] * z0;
-              B[1][j] += dwy[m] * z0;
-              B[4][j] += wy[m] * z1;
+              const A z0 = dot4(wz, r[0][j], r[1][j], r[2][j], r[3][j]);
+              const A z1 = dot4(dwz, r[0][j], r[1][j], r[2][j], r[3][j]);
+              const A z2 = dot4(d2wz, r[0][j], r[1][j], r[2][j], r[3][j]);
+              B[0][j] = fmaa(wy[m], z0, B[0][j]);
+              B[1][j] = fmaa(dwy[m], z0, B[1][j]);
+              B[2][j] = fmaa(d2wy[m], z0, B[2][j]);
+              B[4][j] = fmaa(wy[m], z1, B[4][j]);
+              B[5][j] = fmaa(dwy[m], z1, B[5][j]);
+              B[7][j] = fmaa(wy[m], z2, B[7][j]);
               if constexpr (!SEPLAP) {
-                const A z2 = d2wz[0] * r[0][j] + d2wz[1] * r[1][j] + d2wz[2] * r[2][j] + d2wz[3] * r[3][j];
-                const A z3 = d3w[0] * r[0][j] + d3w[1] * r[1][j] + d3w[2] * r[2][j] + d3w[3] * r[3][j];
-                B[2][j] += d2wy[m] * z0;
-                B[3][j] += d3w[m] * z0;
-                B[5][j] += dwy[m] * z1;
-                B[6][j] += d2wy[m] * z1;
-                B[7][j] += wy[m] * z2;
-                B[8][j] += dwy[m] * z2;
-                B[9][j] += wy[m] * z3;
-              } else {
-                B[2][j] += d2wy[m] * z0;
-                B[5][j] += dwy[m] * z1;
-                const A z2 = d2wz[0] * r[0][j] + d2wz[1] * r[1][j] + d2wz[2] * r[2][j] + d2wz[3] * r[3][j];
-                B[7][j] += wy[m] * z2;
+                const A z3 = dot4(d3w, r[0][j], r[1][j], r[2][j], r[3][j]);
+                B[3][j] = fmaa(d3w[m], z0, B[3][j]);
+                B[6][j] = fmaa(d2wy[m], z1, B[6][j]);
+                B[8][j] = fmaa(dwy[m], z2, B[8][j]);
+                B[9][j] = fmaa(wy[m], z3, B[9][j]);
               }
             }
           }
 #pragma unroll
           for (int j = 0; j < VEC; ++j) {
-            dg[0][j] += dwx[l] * B[0][j];
-            dg[1][j] += wx[l] * B[1][j];
-            dg[2][j] += wx[l] * B[4][j];
-            dh[0][j] += d2wx[l] * B[0][j];
-            dh[1][j] += wx[l] * B[2][j];
-            dh[2][j] += wx[l] * B[7][j];
-            dh[3][j] += dwx[l] * B[1][j];
-            dh[4][j] += dwx[l] * B[4][j];
-            dh[5][j] += wx[l] * B[5][j];
+            dg[0][j] = fmaa(dwx[l], B[0][j], dg[0][j]);
+            dg[1][j] = fmaa(wx[l], B[1][j], dg[1][j]);
+            dg[2][j] = fmaa(wx[l], B[4][j], dg[2][j]);
+            dh[0][j] = fmaa(d2wx[l], B[0][j], dh[0][j]);
+            dh[1][j] = fmaa(wx[l], B[2][j], dh[1][j]);
+            dh[2][j] = fmaa(wx[l], B[7][j], dh[2][j]);
+            dh[3][j] = fmaa(dwx[l], B[1][j], dh[3][j]);
+            dh[4][j] = fmaa(dwx[l], B[4][j], dh[4][j]);
+            dh[5][j] = fmaa(wx[l], B[5][j], dh[5][j]);
             if constexpr (!SEPLAP) {
               const A xxx = d3w[l] * B[0][j], yyy = wx[l] * B[3][j], zzz = wx[l] * B[9][j];
               const A xxy = d2wx[l] * B[1][j], xxz = d2wx[l] * B[4][j], xyy = dwx[l] * B[2][j];
               const A yyz = wx[l] * B[6][j], xzz = dwx[l] * B[7][j], yzz = wx[l] * B[8][j];
               const A xyz = dwx[l] * B[5][j];
-              dt[0][j] += mt[0] * xxx + mt[1] * xyy + mt[2] * xzz + A(2) * (mt[3] * xxy + mt[4] * xxz + mt[5] * xyz);
-              dt[1][j] += mt[0] * xxy + mt[1] * yyy + mt[2] * yzz + A(2) * (mt[3] * xyy + mt[4] * xyz + mt[5] * yyz);
-              dt[2][j] += mt[0] * xxz + mt[1] * yyz + mt[2] * zzz + A(2) * (mt[3] * xyz + mt[4] * xzz + mt[5] * yzz);
+              dt[0][j] += fmaa(A(2), fmaa(mt[5], xyz, fmaa(mt[4], xxz, mt[3] * xxy)),
+                               fmaa(mt[2], xzz, fmaa(mt[1], xyy, mt[0] * xxx)));
+              dt[1][j] += fmaa(A(2), fmaa(mt[5], yyz, fmaa(mt[4], xyz, mt[3] * xyy)),
+                               fmaa(mt[2], yzz, fmaa(mt[1], yyy, mt[0] * xxy)));
+              dt[2][j] += fmaa(A(2), fmaa(mt[5], yzz, fmaa(mt[4], xzz, mt[3] * xyz)),
+                               fmaa(mt[2], zzz, fmaa(mt[1], yyz, mt[0] * xxz)));
             }
           }
         }
@@ -245,18 +243,18 @@ __global__ __launch_bounds__(256) void k_backward(BwdArgs a) {
               for (int n = 0; n < 4; ++n) Row16<TS>::load(rp + rz[n], r[n]);
 #pragma unroll
               for (int j = 0; j < VEC; ++j) {
-                const A z0 = wz[0] * r[0][j] + wz[1] * r[1][j] + wz[2] * r[2][j] + wz[3] * r[3][j];
-                const A z1 = dwz[0] * r[0][j] + dwz[1] * r[1][j] + dwz[2] * r[2][j] + dwz[3] * r[3][j];
-                b0[j] += wy[m] * z0;
-                b1[j] += dwy[m] * z0;
-                b4[j] += wy[m] * z1;
+                const A z0 = dot4(wz, r[0][j], r[1][j], r[2][j], r[3][j]);
+                const A z1 = dot4(dwz, r[0][j], r[1][j], r[2][j], r[3][j]);
+                b0[j] = fmaa(wy[m], z0, b0[j]);
+                b1[j] = fmaa(dwy[m], z0, b1[j]);
+                b4[j] = fmaa(wy[m], z1, b4[j]);
               }
             }
 #pragma unroll
             for (int j = 0; j < VEC; ++j) {
-              dt[0][j] += dwx[l] * b0[j];
-              dt[1][j] += wx[l] * b1[j];
-              dt[2][j] += wx[l] * b4[j];
+              dt[0][j] = fmaa(dwx[l], b0[j], dt[0][j]);
+              dt[1][j] = fmaa(wx[l], b1[j], dt[1][j]);
+              dt[2][j] = fmaa(wx[l], b4[j], dt[2][j]);
             }
           }
         }
@@ -264,9 +262,9 @@ __global__ __launch_bounds__(256) void k_backward(BwdArgs a) {
 #pragma unroll
         for (int j = 0; j < VEC; ++j) {
           const A h00 = dh[0][j], h11 = dh[1][j], h22 = dh[2][j], h01 = dh[3][j], h02 = dh[4][j], h12 = dh[5][j];
-          const A q0 = gV[j] * dg[0][j] + gt[0][j] * h00 + gt[1][j] * h01 + gt[2][j] * h02 + gL[j] * dt[0][j];
-          const A q1 = gV[j] * dg[1][j] + gt[0][j] * h01 + gt[1][j] * h11 + gt[2][j] * h12 + gL[j] * dt[1][j];
-          const A q2 = gV[j] * dg[2][j] + gt[0][j] * h02 + gt[1][j] * h12 + gt[2][j] * h22 + gL[j] * dt[2][j];
+          const A q0 = fmaa(gL[j], dt[0][j], fmaa(gt[2][j], h02, fmaa(gt[1][j], h01, fmaa(gt[0][j], h00, gV[j] * dg[0][j]))));
+          const A q1 = fmaa(gL[j], dt[1][j], fmaa(gt[2][j], h12, fmaa(gt[1][j], h11, fmaa(gt[0][j], h01, gV[j] * dg[1][j]))));
+          const A q2 = fmaa(gL[j], dt[2][j], fmaa(gt[2][j], h22, fmaa(gt[1][j], h12, fmaa(gt[0][j], h02, gV[j] * dg[2][j]))));
           qs[0] += (double)q0;
           qs[1] += (double)q1;
           qs[2] += (double)q2;
@@ -290,9 +288,9 @@ __global__ __launch_bounds__(256) void k_backward(BwdArgs a) {
       double* out = a.gpos + 3 * (int64_t)p;
       if (ok) {
         const double* J = a.g.jac;
-        out[0] = J[0] * s0 + J[3] * s1 + J[6] * s2;
-        out[1] = J[1] * s0 + J[4] * s1 + J[7] * s2;
-        out[2] = J[2] * s0 + J[5] * s1 + J[8] * s2;
+        out[0] = fmaa(J[6], s2, fmaa(J[3], s1, J[0] * s0));
+        out[1] = fmaa(J[7], s2, fmaa(J[4], s1, J[1] * s0));
+        out[2] = fmaa(J[8], s2, fmaa(J[5], s1, J[2] * s0));
       } else {
         out[0] = out[1] = out[2] = __builtin_nan("");
       }

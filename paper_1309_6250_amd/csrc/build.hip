@@ -66,12 +66,12 @@ __global__ __launch_bounds__(256) void k_cyclic_axis(LineArgs a) {
   double pw = 1.0;
   for (int j = 1; j < n; ++j) {
     pw *= nl;
-    acc += pw * x[(n - j) * tile];
+    acc = fmaa(pw, x[(n - j) * tile], acc);
   }
   double prev = acc * a.start_inv;
   x[0] = prev;
   for (int k = 1; k < n; ++k) {
-    prev = x[k * tile] - lam * prev;
+    prev = fmaa(-lam, prev, x[k * tile]);
     x[k * tile] = prev;
   }
   // (I + lam S^-1) z = y:  z_k + lam z_{k+1} = y_k (cyclic)
@@ -79,12 +79,12 @@ __global__ __launch_bounds__(256) void k_cyclic_axis(LineArgs a) {
   pw = 1.0;
   for (int j = 1; j < n; ++j) {
     pw *= nl;
-    acc += pw * x[(j - 1) * tile];
+    acc = fmaa(pw, x[(j - 1) * tile], acc);
   }
   double next = acc * a.start_inv;
   x[(n - 1) * tile] = next;
   for (int k = n - 2; k >= 0; --k) {
-    next = x[k * tile] - lam * next;
+    next = fmaa(-lam, next, x[k * tile]);
     x[k * tile] = next;
   }
 

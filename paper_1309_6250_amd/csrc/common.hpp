@@ -37,6 +37,11 @@ template <typename TS> struct Acc { using type = float; };
 template <> struct Acc<double> { using type = double; };
 
 // ---------------------------------------------------------------- device helpers
+// Every fused multiply-add in device code is written out (the library is built with
+// -ffp-contract=off), so all kernels sharing a code path round identically.
+__device__ __forceinline__ double fmaa(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmaa(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // Reduced coordinates (Sec. II, Eq. reducedcoordinate): s = a^-1 r folded into [0,1),
 // u = N s, i0 = floor(u), t = u - i0.  Always FP64.  A non-finite point returns false
 // with i0 = 0, t = 0 so every later index stays inside the table.
@@ -47,7 +52,7 @@ __device__ __forceinline__ bool reduce_point(const Geom& g, double r0, double r1
   double s[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    s[i] = g.ainv[3 * i] * r0 + g.ainv[3 * i + 1] * r1 + g.ainv[3 * i + 2] * r2;
+    s[i] = fmaa(g.ainv[3 * i + 2], r2, fmaa(g.ainv[3 * i + 1], r1, g.ainv[3 * i] * r0));
     ok = ok && __builtin_isfinite(s[i]);    // a finite position can still overflow here
   }
 #pragma unroll
@@ -73,17 +78,17 @@ __device__ __forceinline__ void bspline_weights(A t, A w[4], A dw[4], A d2w[4]) 
   const A s = A(1) - t;
   const A t2 = t * t;
   const A sixth = A(1) / A(6);
-  w[0] = sixth * s * s * s;
-  w[1] = sixth * (A(3) * t2 * t - A(6) * t2 + A(4));
-  w[2] = sixth * ((A(-3) * t + A(3)) * t2 + A(3) * t + A(1));
-  w[3] = sixth * t2 * t;
-  dw[0] = A(-0.5) * s * s;
-  dw[1] = A(0.5) * (A(3) * t2 - A(4) * t);
-  dw[2] = A(0.5) * (A(-3) * t2 + A(2) * t + A(1));
+  w[0] = sixth * (s * s * s);
+  w[1] = sixth * fmaa(t2, fmaa(A(3), t, A(-6)), A(4));
+  w[2] = sixth * fmaa(t2, fmaa(A(-3), t, A(3)), fmaa(A(3), t, A(1)));
+  w[3] = sixth * (t2 * t);
+  dw[0] = A(-0.5) * (s * s);
+  dw[1] = A(0.5) * (t * fmaa(A(3), t, A(-4)));
+  dw[2] = A(0.5) * fmaa(t, fmaa(A(-3), t, A(2)), A(1));
   dw[3] = A(0.5) * t2;
   d2w[0] = s;
-  d2w[1] = A(3) * t - A(2);
-  d2w[2] = A(1) - A(3) * t;
+  d2w[1] = fmaa(A(3), t, A(-2));
+  d2w[2] = fmaa(A(-3), t, A(1));
   d2w[3] = t;
 }
 
@@ -92,10 +97,16 @@ __device__ __forceinline__ void bspline_values(A t, A w[4]) {
   const A s = A(1) - t;
   const A t2 = t * t;
   const A sixth = A(1) / A(6);
-  w[0] = sixth * s * s * s;
-  w[1] = sixth * (A(3) * t2 * t - A(6) * t2 + A(4));
-  w[2] = sixth * ((A(-3) * t + A(3)) * t2 + A(3) * t + A(1));
-  w[3] = sixth * t2 * t;
+  w[0] = sixth * (s * s * s);
+  w[1] = sixth * fmaa(t2, fmaa(A(3), t, A(-6)), A(4));
+  w[2] = sixth * fmaa(t2, fmaa(A(-3), t, A(3)), fmaa(A(3), t, A(1)));
+  w[3] = sixth * (t2 * t);
+}
+
+// Four-term dot product in a fixed order: w0 x0 + w1 x1 + w2 x2 + w3 x3.
+template <typename A>
+__device__ __forceinline__ A dot4(const A w[4], A x0, A x1, A x2, A x3) {
+  return fmaa(w[3], x3, fmaa(w[2], x2, fmaa(w[1], x1, w[0] * x0)));
 }
 
 // Row indices i0-1 .. i0+2 modulo n (n >= 4, 0 <= i0 < n).

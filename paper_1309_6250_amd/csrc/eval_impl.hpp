@@ -185,9 +185,8 @@ __device__ __forceinline__ void eval_point(const EvalArgs& a, const int p, const
         for (int j = 0; j < OPL; ++j) {
           A q = A(0);
 #pragma unroll
-          for (int m = 0; m < 4; ++m)
-            q += wy[m] * (wz[0] * r[m][0][j] + wz[1] * r[m][1][j] + wz[2] * r[m][2][j] + wz[3] * r[m][3][j]);
-          acc[0][j] += xw * q;
+          for (int m = 0; m < 4; ++m) q = fmaa(wy[m], dot4(wz, r[m][0][j], r[m][1][j], r[m][2][j], r[m][3][j]), q);
+          acc[0][j] = fmaa(xw, q, acc[0][j]);
         }
       } else {
         const A xd = pick4(l, dwx[0], dwx[1], dwx[2], dwx[3]);
@@ -199,29 +198,29 @@ __device__ __forceinline__ void eval_point(const EvalArgs& a, const int p, const
           A s0 = A(0), s1 = A(0), s2 = A(0), s3 = A(0), s4 = A(0), s5 = A(0);
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
-            const A a0 = wz[0] * r[m][0][j] + wz[1] * r[m][1][j] + wz[2] * r[m][2][j] + wz[3] * r[m][3][j];
-            const A a1 = dwz[0] * r[m][0][j] + dwz[1] * r[m][1][j] + dwz[2] * r[m][2][j] + dwz[3] * r[m][3][j];
-            s0 += wy[m] * a0;
-            s1 += dwy[m] * a0;
-            s3 += wy[m] * a1;
+            const A a0 = dot4(wz, r[m][0][j], r[m][1][j], r[m][2][j], r[m][3][j]);
+            const A a1 = dot4(dwz, r[m][0][j], r[m][1][j], r[m][2][j], r[m][3][j]);
+            s0 = fmaa(wy[m], a0, s0);
+            s1 = fmaa(dwy[m], a0, s1);
+            s3 = fmaa(wy[m], a1, s3);
             if constexpr (MODE == MODE_VGL) {
-              const A a2 = d2wz[0] * r[m][0][j] + d2wz[1] * r[m][1][j] + d2wz[2] * r[m][2][j] + d2wz[3] * r[m][3][j];
-              s2 += d2wy[m] * a0;
-              s4 += dwy[m] * a1;
-              s5 += wy[m] * a2;
+              const A a2 = dot4(d2wz, r[m][0][j], r[m][1][j], r[m][2][j], r[m][3][j]);
+              s2 = fmaa(d2wy[m], a0, s2);
+              s4 = fmaa(dwy[m], a1, s4);
+              s5 = fmaa(wy[m], a2, s5);
             }
           }
-          acc[0][j] += xw * s0;
-          acc[1][j] += xd * s0;
-          acc[2][j] += xw * s1;
-          acc[3][j] += xw * s3;
+          acc[0][j] = fmaa(xw, s0, acc[0][j]);
+          acc[1][j] = fmaa(xd, s0, acc[1][j]);
+          acc[2][j] = fmaa(xw, s1, acc[2][j]);
+          acc[3][j] = fmaa(xw, s3, acc[3][j]);
           if constexpr (MODE == MODE_VGL) {
-            acc[4][j] += xdd * s0;
-            acc[5][j] += xw * s2;
-            acc[6][j] += xw * s5;
-            acc[7][j] += xd * s1;
-            acc[8][j] += xd * s3;
-            acc[9][j] += xw * s4;
+            acc[4][j] = fmaa(xdd, s0, acc[4][j]);
+            acc[5][j] = fmaa(xw, s2, acc[5][j]);
+            acc[6][j] = fmaa(xw, s5, acc[6][j]);
+            acc[7][j] = fmaa(xd, s1, acc[7][j]);
+            acc[8][j] = fmaa(xd, s3, acc[8][j]);
+            acc[9][j] = fmaa(xw, s4, acc[9][j]);
           }
         }
       }
@@ -251,9 +250,8 @@ __device__ __forceinline__ void eval_point(const EvalArgs& a, const int p, const
           for (int j = 0; j < OPL; ++j) {
             A q = A(0);
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
-              q += wy[m] * (wz[0] * r[m][0][j] + wz[1] * r[m][1][j] + wz[2] * r[m][2][j] + wz[3] * r[m][3][j]);
-            lacc[j] += xw * q;
+            for (int m = 0; m < 4; ++m) q = fmaa(wy[m], dot4(wz, r[m][0][j], r[m][1][j], r[m][2][j], r[m][3][j]), q);
+            lacc[j] = fmaa(xw, q, lacc[j]);
           }
         }
       }
@@ -268,15 +266,16 @@ __device__ __forceinline__ void eval_point(const EvalArgs& a, const int p, const
         const A g0 = acc[1][j], g1 = acc[2][j], g2 = acc[3][j];
         A lp;
         if constexpr (MODE == MODE_VGL) {
-          lp = (A)a.g.metric[0] * acc[4][j] + (A)a.g.metric[1] * acc[5][j] + (A)a.g.metric[2] * acc[6][j] +
-               A(2) * ((A)a.g.metric[3] * acc[7][j] + (A)a.g.metric[4] * acc[8][j] + (A)a.g.metric[5] * acc[9][j]);
+          const A diag = fmaa((A)a.g.metric[2], acc[6][j], fmaa((A)a.g.metric[1], acc[5][j], (A)a.g.metric[0] * acc[4][j]));
+          const A off = fmaa((A)a.g.metric[5], acc[9][j], fmaa((A)a.g.metric[4], acc[8][j], (A)a.g.metric[3] * acc[7][j]));
+          lp = fmaa(A(2), off, diag);
         } else {
           lp = lacc[j];
         }
         ov[j] = ok ? (O)acc[0][j] : nan;
-        gx[j] = ok ? (O)(j00 * g0 + j10 * g1 + j20 * g2) : nan;
-        gy[j] = ok ? (O)(j01 * g0 + j11 * g1 + j21 * g2) : nan;
-        gz[j] = ok ? (O)(j02 * g0 + j12 * g1 + j22 * g2) : nan;
+        gx[j] = ok ? (O)fmaa(j20, g2, fmaa(j10, g1, j00 * g0)) : nan;
+        gy[j] = ok ? (O)fmaa(j21, g2, fmaa(j11, g1, j01 * g0)) : nan;
+        gz[j] = ok ? (O)fmaa(j22, g2, fmaa(j12, g1, j02 * g0)) : nan;
         lv[j] = ok ? (O)lp : nan;
       }
       O* gout = static_cast<O*>(a.grad) + (int64_t)p * 3 * a.n_orb;

@@ -15,7 +15,11 @@
 //        that spline.  q is summed over the orbitals of a point across its lane group
 //        (LDS reduction), then one lane applies J^T and writes gpos.
 //
-// A lane group of G lanes owns a point, as in the forward kernel.
+// Mapping.  A lane group of G lanes owns a point.  Lane c of the group owns the orbitals
+// c, c + G, ..., c + (OPL-1) G of each chunk of G*OPL orbitals: consecutive lanes hold
+// consecutive orbitals, so every load and every atomic instruction of a wave covers whole
+// contiguous cache lines of a table row (the scatter is bound by the number of line-sized
+// atomic operations the memory side performs, so this matters more than vector width).
 #include "common.hpp"
 
 namespace pws {
@@ -31,9 +35,20 @@ struct BwdArgs {
   double* gpos;
   int32_t n_pts;
   int32_t n_orb;
-  int32_t n_chunks;
-  int32_t pad_;
+  int32_t pad0_;
+  int32_t pad1_;
   int64_t lap_off;
+};
+
+template <typename TS> struct Elem;
+template <> struct Elem<double> {
+  __device__ __forceinline__ static double load(const double* p) { return *p; }
+};
+template <> struct Elem<float> {
+  __device__ __forceinline__ static float load(const float* p) { return *p; }
+};
+template <> struct Elem<uint16_t> {   // BF16 bits -> FP32
+  __device__ __forceinline__ static float load(const uint16_t* p) { return __uint_as_float((uint32_t)*p << 16); }
 };
 
 template <typename T>
@@ -41,11 +56,15 @@ __device__ __forceinline__ void atomic_add(T* p, T v) {
   unsafeAtomicAdd(p, v);
 }
 
-template <typename TS, bool SEPLAP, int G>
+template <typename A>
+__device__ __forceinline__ A pick4b(int l, A a0, A a1, A a2, A a3) {
+  return l == 0 ? a0 : (l == 1 ? a1 : (l == 2 ? a2 : a3));
+}
+
+template <typename TS, bool SEPLAP, int G, int OPL>
 __global__ __launch_bounds__(256) void k_backward(BwdArgs a) {
   using A = typename Acc<TS>::type;
   using GO = typename Out<TS>::type;   // dtype of upstream gradients and of the gradient table
-  constexpr int VEC = Row16<TS>::VEC;
   constexpr int GPB = 256 / G;
   __shared__ double red[256][3];
   const int grp = threadIdx.x / G;
@@ -64,18 +83,17 @@ __global__ __launch_bounds__(256) void k_backward(BwdArgs a) {
     wrap4(i0[0], a.g.n[0], ix);
     wrap4(i0[1], a.g.n[1], iy);
     wrap4(i0[2], a.g.n[2], iz);
-    int64_t rx[4], ry[4], rz[4];
+    int64_t ry[4], rz[4];
 #pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      rx[l] = (int64_t)ix[l] * a.g.s0;
-      ry[l] = (int64_t)iy[l] * a.g.s1;
-      rz[l] = (int64_t)iz[l] * a.g.o_pad;
+    for (int m = 0; m < 4; ++m) {
+      ry[m] = (int64_t)iy[m] * a.g.s1;
+      rz[m] = (int64_t)iz[m] * a.g.o_pad;
     }
     A wx[4], wy[4], wz[4], dwx[4], dwy[4], dwz[4], d2wx[4], d2wy[4], d2wz[4];
     bspline_weights<A>((A)t[0], wx, dwx, d2wx);
     bspline_weights<A>((A)t[1], wy, dwy, d2wy);
     bspline_weights<A>((A)t[2], wz, dwz, d2wz);
-    const A d3w[4] = {A(-1), A(3), A(-3), A(1)};
+    const A d3w[4] = {A(-1), A(3), A(-3), A(1)};   // third derivative of the cubic basis (unit spacing)
     A jm[9], mt[6];
 #pragma unroll
     for (int i = 0; i < 9; ++i) jm[i] = (A)a.g.jac[i];
@@ -88,14 +106,20 @@ __global__ __launch_bounds__(256) void k_backward(BwdArgs a) {
     const GO* glp = static_cast<const GO*>(a.glap);
     GO* gtab = static_cast<GO*>(a.gtable);
 
-    for (int c = lane; c < a.n_chunks && ok; c += G) {
-      const int o = c * VEC;
-      A gV[VEC], gL[VEC], gt[3][VEC];
+    for (int cb = 0; cb < a.n_orb && ok; cb += G * OPL) {
+      int oj[OPL];            // this lane's orbitals in the chunk
+      bool inj[OPL];
 #pragma unroll
-      for (int j = 0; j < VEC; ++j) {
-        const bool in = o + j < a.n_orb;
-        const int64_t po = (int64_t)p * a.n_orb + o + j;
-        const int64_t pg = (int64_t)p * 3 * a.n_orb + o + j;
+      for (int j = 0; j < OPL; ++j) {
+        oj[j] = cb + lane + j * G;
+        inj[j] = oj[j] < a.n_orb;
+      }
+      A gV[OPL], gL[OPL], gt[3][OPL];
+#pragma unroll
+      for (int j = 0; j < OPL; ++j) {
+        const bool in = inj[j];
+        const int64_t po = (int64_t)p * a.n_orb + oj[j];
+        const int64_t pg = (int64_t)p * 3 * a.n_orb + oj[j];
         gV[j] = (in && gvp) ? (A)gvp[po] : A(0);
         gL[j] = (in && glp) ? (A)glp[po] : A(0);
         const A g0 = (in && ggp) ? (A)ggp[pg] : A(0);
@@ -107,83 +131,97 @@ __global__ __launch_bounds__(256) void k_backward(BwdArgs a) {
 
       // ---------------- d beta: separable scatter, transpose of the forward contraction
       if (gtab) {
-#pragma unroll
+#pragma unroll 1
         for (int l = 0; l < 4; ++l) {
-          A e[6][VEC];
+          const A xw = pick4b(l, wx[0], wx[1], wx[2], wx[3]);
+          const A xd = pick4b(l, dwx[0], dwx[1], dwx[2], dwx[3]);
+          const A xdd = pick4b(l, d2wx[0], d2wx[1], d2wx[2], d2wx[3]);
+          GO* slab = gtab + (int64_t)pick4b(l, ix[0], ix[1], ix[2], ix[3]) * a.g.s0;
+          A e[6][OPL];
 #pragma unroll
-          for (int j = 0; j < VEC; ++j) {
+          for (int j = 0; j < OPL; ++j) {
             const A cl = SEPLAP ? A(0) : gL[j];
-            e[0][j] = fmaa(mt[0] * cl, d2wx[l], fmaa(gt[0][j], dwx[l], gV[j] * wx[l]));   // with wy wz
-            e[1][j] = fmaa(A(2) * mt[3] * cl, dwx[l], gt[1][j] * wx[l]);                  // with dwy wz
-            e[2][j] = fmaa(A(2) * mt[4] * cl, dwx[l], gt[2][j] * wx[l]);                  // with wy dwz
-            e[3][j] = (mt[1] * cl) * wx[l];                                               // with d2wy wz
-            e[4][j] = (mt[2] * cl) * wx[l];                                               // with wy d2wz
-            e[5][j] = (A(2) * mt[5] * cl) * wx[l];                                        // with dwy dwz
+            e[0][j] = fmaa(mt[0] * cl, xdd, fmaa(gt[0][j], xd, gV[j] * xw));   // with wy wz
+            e[1][j] = fmaa(A(2) * mt[3] * cl, xd, gt[1][j] * xw);              // with dwy wz
+            e[2][j] = fmaa(A(2) * mt[4] * cl, xd, gt[2][j] * xw);              // with wy dwz
+            e[3][j] = (mt[1] * cl) * xw;                                       // with d2wy wz
+            e[4][j] = (mt[2] * cl) * xw;                                       // with wy d2wz
+            e[5][j] = (A(2) * mt[5] * cl) * xw;                                // with dwy dwz
           }
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
-            A f0[VEC], f1[VEC], f2[VEC];
+            A f0[OPL], f1[OPL], f2[OPL];
 #pragma unroll
-            for (int j = 0; j < VEC; ++j) {
+            for (int j = 0; j < OPL; ++j) {
               f0[j] = fmaa(e[3][j], d2wy[m], fmaa(e[1][j], dwy[m], e[0][j] * wy[m]));
               f1[j] = fmaa(e[5][j], dwy[m], e[2][j] * wy[m]);
               f2[j] = e[4][j] * wy[m];
             }
-            GO* rp = gtab + rx[l] + ry[m] + o;
+            GO* rp = slab + ry[m];
 #pragma unroll
             for (int n = 0; n < 4; ++n) {
 #pragma unroll
-              for (int j = 0; j < VEC; ++j)
-                if (o + j < a.n_orb)
-                  atomic_add<GO>(rp + rz[n] + j, (GO)fmaa(f2[j], d2wz[n], fmaa(f1[j], dwz[n], f0[j] * wz[n])));
+              for (int j = 0; j < OPL; ++j)
+                if (inj[j])
+                  atomic_add<GO>(rp + rz[n] + oj[j], (GO)fmaa(f2[j], d2wz[n], fmaa(f1[j], dwz[n], f0[j] * wz[n])));
             }
           }
         }
         if constexpr (SEPLAP) {
-          GO* ltab = gtab + a.lap_off;
-#pragma unroll
-          for (int l = 0; l < 4; ++l)
+#pragma unroll 1
+          for (int l = 0; l < 4; ++l) {
+            const A xw = pick4b(l, wx[0], wx[1], wx[2], wx[3]);
+            GO* slab = gtab + a.lap_off + (int64_t)pick4b(l, ix[0], ix[1], ix[2], ix[3]) * a.g.s0;
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-              GO* rp = ltab + rx[l] + ry[m] + o;
+              GO* rp = slab + ry[m];
+              const A xy = xw * wy[m];
 #pragma unroll
               for (int n = 0; n < 4; ++n) {
-                const A w = wx[l] * wy[m] * wz[n];
+                const A w = xy * wz[n];
 #pragma unroll
-                for (int j = 0; j < VEC; ++j)
-                  if (o + j < a.n_orb) atomic_add<GO>(rp + rz[n] + j, (GO)(gL[j] * w));
+                for (int j = 0; j < OPL; ++j)
+                  if (inj[j]) atomic_add<GO>(rp + rz[n] + oj[j], (GO)(gL[j] * w));
               }
             }
+          }
         }
       }
 
       // ---------------- d pos: reduced derivatives up to third order
       if (a.gpos) {
-        A dg[3][VEC], dh[6][VEC], dt[3][VEC];   // grad_t, Hessian (xx yy zz xy xz yz), T
+        A dg[3][OPL], dh[6][OPL], dt[3][OPL];   // grad_t, Hessian (xx yy zz xy xz yz), T
 #pragma unroll
-        for (int j = 0; j < VEC; ++j) {
+        for (int j = 0; j < OPL; ++j) {
 #pragma unroll
           for (int i = 0; i < 3; ++i) { dg[i][j] = A(0); dt[i][j] = A(0); }
 #pragma unroll
           for (int i = 0; i < 6; ++i) dh[i][j] = A(0);
         }
-#pragma unroll
+#pragma unroll 1
         for (int l = 0; l < 4; ++l) {
-          // y-stage sums B(b,c) = sum_m d^b wy * (sum_n d^c wz beta):
+          const A xw = pick4b(l, wx[0], wx[1], wx[2], wx[3]);
+          const A xd = pick4b(l, dwx[0], dwx[1], dwx[2], dwx[3]);
+          const A xdd = pick4b(l, d2wx[0], d2wx[1], d2wx[2], d2wx[3]);
+          const A xddd = pick4b(l, d3w[0], d3w[1], d3w[2], d3w[3]);
+          const TS* slab = tab + (int64_t)pick4b(l, ix[0], ix[1], ix[2], ix[3]) * a.g.s0;
+          // second-axis sums B(b,c) = sum_m d^b wy * (sum_n d^c wz beta):
           // 0 (0,0) 1 (1,0) 2 (2,0) 3 (3,0) 4 (0,1) 5 (1,1) 6 (2,1) 7 (0,2) 8 (1,2) 9 (0,3)
-          A B[10][VEC];
+          A B[10][OPL];
 #pragma unroll
           for (int q = 0; q < 10; ++q)
 #pragma unroll
-            for (int j = 0; j < VEC; ++j) B[q][j] = A(0);
+            for (int j = 0; j < OPL; ++j) B[q][j] = A(0);
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
-            const TS* rp = tab + rx[l] + ry[m] + o;
-            A r[4][VEC];
+            const TS* rp = slab + ry[m];
+            A r[4][OPL];
 #pragma unroll
-            for (int n = 0; n < 4; ++n) Row16<TS>::load(rp + rz[n], r[n]);
+            for (int n = 0; n < 4; ++n)
 #pragma unroll
-            for (int j = 0; j < VEC; ++j) {
+              for (int j = 0; j < OPL; ++j) r[n][j] = inj[j] ? (A)Elem<TS>::load(rp + rz[n] + oj[j]) : A(0);
+#pragma unroll
+            for (int j = 0; j < OPL; ++j) {
               const A z0 = dot4(wz, r[0][j], r[1][j], r[2][j], r[3][j]);
               const A z1 = dot4(dwz, r[0][j], r[1][j], r[2][j], r[3][j]);
               const A z2 = dot4(d2wz, r[0][j], r[1][j], r[2][j], r[3][j]);
@@ -203,21 +241,21 @@ __global__ __launch_bounds__(256) void k_backward(BwdArgs a) {
             }
           }
 #pragma unroll
-          for (int j = 0; j < VEC; ++j) {
-            dg[0][j] = fmaa(dwx[l], B[0][j], dg[0][j]);
-            dg[1][j] = fmaa(wx[l], B[1][j], dg[1][j]);
-            dg[2][j] = fmaa(wx[l], B[4][j], dg[2][j]);
-            dh[0][j] = fmaa(d2wx[l], B[0][j], dh[0][j]);
-            dh[1][j] = fmaa(wx[l], B[2][j], dh[1][j]);
-            dh[2][j] = fmaa(wx[l], B[7][j], dh[2][j]);
-            dh[3][j] = fmaa(dwx[l], B[1][j], dh[3][j]);
-            dh[4][j] = fmaa(dwx[l], B[4][j], dh[4][j]);
-            dh[5][j] = fmaa(wx[l], B[5][j], dh[5][j]);
+          for (int j = 0; j < OPL; ++j) {
+            dg[0][j] = fmaa(xd, B[0][j], dg[0][j]);
+            dg[1][j] = fmaa(xw, B[1][j], dg[1][j]);
+            dg[2][j] = fmaa(xw, B[4][j], dg[2][j]);
+            dh[0][j] = fmaa(xdd, B[0][j], dh[0][j]);
+            dh[1][j] = fmaa(xw, B[2][j], dh[1][j]);
+            dh[2][j] = fmaa(xw, B[7][j], dh[2][j]);
+            dh[3][j] = fmaa(xd, B[1][j], dh[3][j]);
+            dh[4][j] = fmaa(xd, B[4][j], dh[4][j]);
+            dh[5][j] = fmaa(xw, B[5][j], dh[5][j]);
             if constexpr (!SEPLAP) {
-              const A xxx = d3w[l] * B[0][j], yyy = wx[l] * B[3][j], zzz = wx[l] * B[9][j];
-              const A xxy = d2wx[l] * B[1][j], xxz = d2wx[l] * B[4][j], xyy = dwx[l] * B[2][j];
-              const A yyz = wx[l] * B[6][j], xzz = dwx[l] * B[7][j], yzz = wx[l] * B[8][j];
-              const A xyz = dwx[l] * B[5][j];
+              const A xxx = xddd * B[0][j], yyy = xw * B[3][j], zzz = xw * B[9][j];
+              const A xxy = xdd * B[1][j], xxz = xdd * B[4][j], xyy = xd * B[2][j];
+              const A yyz = xw * B[6][j], xzz = xd * B[7][j], yzz = xw * B[8][j];
+              const A xyz = xd * B[5][j];
               dt[0][j] += fmaa(A(2), fmaa(mt[5], xyz, fmaa(mt[4], xxz, mt[3] * xxy)),
                                fmaa(mt[2], xzz, fmaa(mt[1], xyy, mt[0] * xxx)));
               dt[1][j] += fmaa(A(2), fmaa(mt[5], yyz, fmaa(mt[4], xyz, mt[3] * xyy)),
@@ -229,20 +267,24 @@ __global__ __launch_bounds__(256) void k_backward(BwdArgs a) {
         }
         if constexpr (SEPLAP) {
           // T = reduced gradient of the separate Laplacian spline
-          const TS* ltab = tab + a.lap_off;
-#pragma unroll
+#pragma unroll 1
           for (int l = 0; l < 4; ++l) {
-            A b0[VEC], b1[VEC], b4[VEC];
+            const A xw = pick4b(l, wx[0], wx[1], wx[2], wx[3]);
+            const A xd = pick4b(l, dwx[0], dwx[1], dwx[2], dwx[3]);
+            const TS* slab = tab + a.lap_off + (int64_t)pick4b(l, ix[0], ix[1], ix[2], ix[3]) * a.g.s0;
+            A b0[OPL], b1[OPL], b4[OPL];
 #pragma unroll
-            for (int j = 0; j < VEC; ++j) { b0[j] = A(0); b1[j] = A(0); b4[j] = A(0); }
+            for (int j = 0; j < OPL; ++j) { b0[j] = A(0); b1[j] = A(0); b4[j] = A(0); }
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-              const TS* rp = ltab + rx[l] + ry[m] + o;
-              A r[4][VEC];
+              const TS* rp = slab + ry[m];
+              A r[4][OPL];
 #pragma unroll
-              for (int n = 0; n < 4; ++n) Row16<TS>::load(rp + rz[n], r[n]);
+              for (int n = 0; n < 4; ++n)
 #pragma unroll
-              for (int j = 0; j < VEC; ++j) {
+                for (int j = 0; j < OPL; ++j) r[n][j] = inj[j] ? (A)Elem<TS>::load(rp + rz[n] + oj[j]) : A(0);
+#pragma unroll
+              for (int j = 0; j < OPL; ++j) {
                 const A z0 = dot4(wz, r[0][j], r[1][j], r[2][j], r[3][j]);
                 const A z1 = dot4(dwz, r[0][j], r[1][j], r[2][j], r[3][j]);
                 b0[j] = fmaa(wy[m], z0, b0[j]);
@@ -251,16 +293,16 @@ __global__ __launch_bounds__(256) void k_backward(BwdArgs a) {
               }
             }
 #pragma unroll
-            for (int j = 0; j < VEC; ++j) {
-              dt[0][j] = fmaa(dwx[l], b0[j], dt[0][j]);
-              dt[1][j] = fmaa(wx[l], b1[j], dt[1][j]);
-              dt[2][j] = fmaa(wx[l], b4[j], dt[2][j]);
+            for (int j = 0; j < OPL; ++j) {
+              dt[0][j] = fmaa(xd, b0[j], dt[0][j]);
+              dt[1][j] = fmaa(xw, b1[j], dt[1][j]);
+              dt[2][j] = fmaa(xw, b4[j], dt[2][j]);
             }
           }
         }
         // q_k = gV g_k + sum_i gt_i H_ik + gL T_k, summed over this lane's orbitals
 #pragma unroll
-        for (int j = 0; j < VEC; ++j) {
+        for (int j = 0; j < OPL; ++j) {
           const A h00 = dh[0][j], h11 = dh[1][j], h22 = dh[2][j], h01 = dh[3][j], h02 = dh[4][j], h12 = dh[5][j];
           const A q0 = fmaa(gL[j], dt[0][j], fmaa(gt[2][j], h02, fmaa(gt[1][j], h01, fmaa(gt[0][j], h00, gV[j] * dg[0][j]))));
           const A q1 = fmaa(gL[j], dt[1][j], fmaa(gt[2][j], h12, fmaa(gt[1][j], h11, fmaa(gt[0][j], h01, gV[j] * dg[1][j]))));
@@ -300,19 +342,18 @@ __global__ __launch_bounds__(256) void k_backward(BwdArgs a) {
 
 typedef void (*BwdKernel)(BwdArgs);
 
-template <typename TS, bool SEPLAP>
-static BwdKernel pick_bwd(int g) {
+template <typename TS, bool SEPLAP, int OPL>
+static BwdKernel pick_bwd_g(int g) {
   switch (g) {
-    case 1: return k_backward<TS, SEPLAP, 1>;
-    case 2: return k_backward<TS, SEPLAP, 2>;
-    case 4: return k_backward<TS, SEPLAP, 4>;
-    case 8: return k_backward<TS, SEPLAP, 8>;
-    case 16: return k_backward<TS, SEPLAP, 16>;
-    case 32: return k_backward<TS, SEPLAP, 32>;
-    case 64: return k_backward<TS, SEPLAP, 64>;
-    case 128: return k_backward<TS, SEPLAP, 128>;
-    default: return k_backward<TS, SEPLAP, 256>;
+    case 4: return k_backward<TS, SEPLAP, 4, OPL>;
+    case 16: return k_backward<TS, SEPLAP, 16, OPL>;
+    default: return k_backward<TS, SEPLAP, 64, OPL>;
   }
+}
+
+template <typename TS, bool SEPLAP>
+static BwdKernel pick_bwd(int g, int opl) {
+  return opl == 1 ? pick_bwd_g<TS, SEPLAP, 1>(g) : pick_bwd_g<TS, SEPLAP, 2>(g);
 }
 
 int vec_of(int dtype);
@@ -331,15 +372,18 @@ int launch_backward(const spl_desc* d, const void* table, int64_t n_pts, const d
   a.gpos = gpos;
   a.n_pts = (int32_t)n_pts;
   a.n_orb = d->n_orb;
-  a.n_chunks = d->o_pad / vec_of(d->dtype);
-  a.pad_ = 0;
+  a.pad0_ = 0;
+  a.pad1_ = 0;
   a.lap_off = d->table_elems;
-  int g = 1;
-  while (g < a.n_chunks && g < 64) g <<= 1;
+  // lanes per point: 4, 16 or 64 (enough to cover the orbitals); orbitals per lane: 1 for FP64
+  // tables, up to 2 otherwise (more would cost occupancy); further orbitals loop over chunks
+  const int g = d->n_orb <= 4 ? 4 : (d->n_orb <= 16 ? 16 : 64);
+  const int need = (d->n_orb + g - 1) / g;
+  const int opl = (d->dtype == SPL_F64 || need <= 1) ? 1 : 2;
   BwdKernel k;
-  if (d->dtype == SPL_F64) k = d->has_lap ? pick_bwd<double, true>(g) : pick_bwd<double, false>(g);
-  else if (d->dtype == SPL_F32) k = d->has_lap ? pick_bwd<float, true>(g) : pick_bwd<float, false>(g);
-  else k = d->has_lap ? pick_bwd<uint16_t, true>(g) : pick_bwd<uint16_t, false>(g);
+  if (d->dtype == SPL_F64) k = d->has_lap ? pick_bwd<double, true>(g, opl) : pick_bwd<double, false>(g, opl);
+  else if (d->dtype == SPL_F32) k = d->has_lap ? pick_bwd<float, true>(g, opl) : pick_bwd<float, false>(g, opl);
+  else k = d->has_lap ? pick_bwd<uint16_t, true>(g, opl) : pick_bwd<uint16_t, false>(g, opl);
   const int64_t per_block = 256 / g;
   const dim3 grid((unsigned)((n_pts + per_block - 1) / per_block));
   hipLaunchKernelGGL(k, grid, dim3(256), 0, stream, a);

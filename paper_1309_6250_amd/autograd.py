@@ -1,0 +1,38 @@
+"""torch.autograd binding of the forward VGL kernel and its adjoint.
+
+SplineVGL.apply(table, pos, desc) -> (v, grad, lap), differentiable with respect to the
+coefficient table and the positions.  Both directions run in the library's kernels
+(spline_eval_vgl and spline_eval_vgl_backward); this module only passes tensors.
+
+For BF16 tables the coefficient gradient is produced in FP32 and autograd casts it to the
+table's dtype; keep FP32 master coefficients when training.
+"""
+import torch
+
+from .api import spline_eval_vgl, spline_eval_vgl_backward, OUT_TORCH
+
+
+class SplineVGL(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, table, pos, desc):
+        v, g, l = spline_eval_vgl(desc, table, pos)
+        ctx.save_for_backward(table, pos)
+        ctx.desc = desc
+        return v, g, l
+
+    @staticmethod
+    def backward(ctx, gv, gg, gl):
+        table, pos = ctx.saved_tensors
+        desc = ctx.desc
+        od = OUT_TORCH[desc.dtype]
+        prep = [None if g is None else g.to(od).contiguous() for g in (gv, gg, gl)]
+        want_t, want_p = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        if not (want_t or want_p):
+            return None, None, None
+        gtable, gpos = spline_eval_vgl_backward(desc, table, pos, *prep, want_table=want_t, want_pos=want_p)
+        return gtable, gpos, None
+
+
+def spline_vgl(table, pos, desc):
+    """Differentiable (v, grad, lap) of the spline `table` at `pos`."""
+    return SplineVGL.apply(table, pos, desc)

@@ -1,0 +1,135 @@
+"""Differentiation form: SplineVGL (torch.autograd over the forward kernel and its adjoint) and the
+least-squares fit built on it, against the FP64 oracle and finite differences."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1309_6250_amd as P
+from paper_1309_6250_amd.fit import make_loss, fit_adam
+from oracle import build as obuild, adjoint as oadj, fit as ofit, pw as opw, quantize as oq
+from workloads import make_system
+from workloads.configs import cubic, A_SI
+from gpu_helpers import say, to_dev, table_from_oracle, normwise, DEV
+
+pytestmark = pytest.mark.gpu
+
+SKEW = np.array([[7.0, 0.4, -0.3], [1.1, 6.2, 0.5], [-0.6, 0.9, 8.3]])
+
+
+def _case(seed, grid=(9, 8, 10), n_orb=5, n_pts=300, dtype="f64"):
+    rng = np.random.default_rng(seed)
+    beta = obuild.build_interp(rng.standard_normal(grid + (n_orb,)))
+    cells = rng.integers(0, np.array(grid), size=(n_pts, 3))
+    u = cells + rng.uniform(0.2, 0.8, size=(n_pts, 3))           # off the knot planes
+    pos = (u / np.array(grid)) @ SKEW
+    d = P.spline_desc_init(SKEW, grid, n_orb, dtype)
+    return rng, beta, pos, d
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_autograd_matches_oracle_adjoint(dtype):
+    rng, beta, pos, d = _case(300, dtype=dtype)
+    n, o = pos.shape[0], d.n_orb
+    A, B, C = rng.standard_normal((n, o)), rng.standard_normal((n, 3, o)), rng.standard_normal((n, o))
+    od = torch.float64 if dtype == "f64" else torch.float32
+    table = table_from_oracle(d, beta, dtype).requires_grad_(True)
+    x = to_dev(pos).requires_grad_(True)
+    say("SplineVGL forward/backward", dtype)
+    v, g, l = P.SplineVGL.apply(table, x, d)
+    loss = (v * to_dev(A, od)).sum() + (g * to_dev(B, od)).sum() + (l * to_dev(C, od)).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    bq = oq.quantized(beta, dtype)
+    rb, _, rp = oadj.vgl_backward(bq, SKEW, pos, A, B, C)
+    got_t = table.grad.double().cpu().numpy()[0, ..., :o]
+    tol = 1e-12 if dtype == "f64" else 2e-5
+    assert normwise(got_t, rb) < tol
+    assert normwise(x.grad.cpu().numpy(), rp) < (1e-11 if dtype == "f64" else 1e-4)
+    assert np.all(table.grad.double().cpu().numpy()[0, ..., o:] == 0)    # padding never receives gradient
+
+
+def test_position_gradient_finite_difference_on_gpu():
+    rng, beta, pos, d = _case(301)
+    n, o = pos.shape[0], d.n_orb
+    A, B, C = rng.standard_normal((n, o)), rng.standard_normal((n, 3, o)), rng.standard_normal((n, o))
+    table = table_from_oracle(d, beta, "f64")
+    At, Bt, Ct = to_dev(A), to_dev(B), to_dev(C)
+
+    def per_point(x):
+        v, g, l = P.spline_eval_vgl(d, table, x)
+        return (v * At).sum(1) + (g * Bt).sum((1, 2)) + (l * Ct).sum(1)
+
+    x = to_dev(pos).requires_grad_(True)
+    v, g, l = P.SplineVGL.apply(table, x, d)
+    ((v * At).sum() + (g * Bt).sum() + (l * Ct).sum()).backward()
+    h = 1e-5
+    fd = torch.zeros_like(x)
+    for a in range(3):
+        e = torch.zeros_like(x)
+        e[:, a] = h
+        fd[:, a] = (per_point(x.detach() + e) - per_point(x.detach() - e)) / (2 * h)
+    torch.cuda.synchronize()
+    assert normwise(x.grad.cpu().numpy(), fd.cpu().numpy()) < 1e-7
+
+
+def test_table_gradient_finite_difference_on_gpu():
+    rng, beta, pos, d = _case(302, n_orb=3)
+    n, o = pos.shape[0], d.n_orb
+    A, C = to_dev(rng.standard_normal((n, o))), to_dev(rng.standard_normal((n, o)))
+    table = table_from_oracle(d, beta, "f64").requires_grad_(True)
+    x = to_dev(pos)
+
+    def loss(tab):
+        v, g, l = P.spline_eval_vgl(d, tab, x)
+        return float(((v * A).sum() + (l * C).sum() + (g ** 2).sum()).cpu())
+
+    v, g, l = P.SplineVGL.apply(table, x, d)
+    ((v * A).sum() + (l * C).sum() + (g ** 2).sum()).backward()
+    grad = table.grad.cpu().numpy()
+    base = table.detach().clone()
+    h = 1e-6
+    for _ in range(10):
+        idx = (0,) + tuple(int(rng.integers(0, s)) for s in d.grid) + (int(rng.integers(0, o)),)
+        tp, tm = base.clone(), base.clone()
+        tp[idx] += h
+        tm[idx] -= h
+        fd = (loss(tp) - loss(tm)) / (2 * h)
+        assert abs(fd - grad[idx]) <= 1e-6 * max(1.0, abs(fd)), (idx, fd, grad[idx])
+
+
+def _fit_case():
+    s = make_system("fit-small", cubic(A_SI), (14, 14, 14), 6, 2.5, 2.0, (1309, 6250, 4, 99))
+    f = s.grid_values()
+    pos = s.positions(4000)
+    v_t, _, l_t = opw.pw_vgl(s.gvecs, s.coef, pos)
+    beta0 = obuild.build_interp(f)
+    return s, pos, v_t, l_t, beta0
+
+
+def test_fit_loss_and_gradient_match_oracle():
+    s, pos, v_t, l_t, beta0 = _fit_case()
+    d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, "f64")
+    table = table_from_oracle(d, beta0, "f64").requires_grad_(True)
+    loss_fn = make_loss(d, to_dev(pos), to_dev(v_t), to_dev(l_t), lam=0.3)
+    say("fit loss + gradient")
+    loss = loss_fn(table)
+    loss.backward()
+    torch.cuda.synchronize()
+    w_v, w_l = ofit.weights_from_targets(v_t, l_t)
+    rloss, rgrad = ofit.loss_and_grad(beta0, s.lattice, pos, v_t, l_t, w_v, w_l, lam=0.3)
+    assert abs(float(loss) - rloss) <= 1e-11 * abs(rloss)
+    assert normwise(table.grad.cpu().numpy()[0, ..., :s.n_orb], rgrad) < 1e-10
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adam_fit_lowers_the_loss(dtype):
+    s, pos, v_t, l_t, beta0 = _fit_case()
+    d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype)
+    table = table_from_oracle(d, beta0, dtype)
+    say("Adam fit", dtype)
+    fitted, losses = fit_adam(d, table, to_dev(pos), to_dev(v_t), to_dev(l_t), steps=60, lam=0.0)
+    torch.cuda.synchronize()
+    assert losses[-1] < 0.9 * losses[0], (losses[0], losses[-1])
+    assert np.all(np.isfinite(losses))
+    # padding columns stay exactly zero
+    assert torch.all(fitted[..., s.n_orb:] == 0)

@@ -153,14 +153,26 @@ int spline_eval_vgl_tile(const spl_desc* d, const void* table, int64_t n_pts, co
  *                    NULL (treated as zero)
  *   gtable           device, d->gtable_bytes: [(1+has_lap)][N1][N2][N3][o_pad], FP64 for
  *                    SPL_F64 tables, else FP32; ACCUMULATED into (zero it first for a plain
- *                    gradient); may be NULL to skip
+ *                    gradient); may be NULL to skip; padding columns are never written
  *   gpos             device, FP64 [n_pts][3], OVERWRITTEN; may be NULL to skip
- *   flags            0 or SPL_DETERMINISTIC (currently SPL_EUNSUPPORTED)
- * Points with non-finite coordinates contribute nothing to gtable and get NaN in gpos.
+ *   flags            0: the coefficient gradient is summed with hardware float atomics (fast,
+ *                    order of summation not reproducible); SPL_DETERMINISTIC: points are sorted
+ *                    by grid cell and each cell's block is accumulated in registers and written
+ *                    class by class with ordinary stores: bitwise reproducible
+ *   work, work_bytes device workspace for SPL_DETERMINISTIC, 256-byte aligned, at least
+ *                    spline_backward_work_bytes() bytes, contents undefined afterwards; may be
+ *                    NULL (0 bytes) without that flag
+ * The position gradient is deterministic either way.  Points with non-finite coordinates
+ * contribute nothing to gtable and get NaN in gpos.
  */
 int spline_eval_vgl_backward(const spl_desc* d, const void* table, int64_t n_pts, const double* pos,
                              const void* gv, const void* ggrad, const void* glap,
-                             void* gtable, double* gpos, int32_t flags, void* stream);
+                             void* gtable, double* gpos, int32_t flags,
+                             void* work, int64_t work_bytes, void* stream);
+
+/* Workspace size (bytes) spline_eval_vgl_backward needs for n_pts points and `flags` (0 without
+ * SPL_DETERMINISTIC).  Host only; may query the current HIP device. */
+int spline_backward_work_bytes(const spl_desc* d, int64_t n_pts, int32_t flags, int64_t* bytes);
 
 /* ---------------------------------------------------------------------------
  * Batched evaluation: many independent systems (tables of different sizes and

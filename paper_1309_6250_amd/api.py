@@ -157,10 +157,22 @@ def spline_eval_vgl_backward(desc, table, pos, gv=None, ggrad=None, glap=None, g
         gpos = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
     if gpos is not None:
         _need(gpos, "gpos", torch.float64, 3 * n)
+    work = None
+    nbytes = spline_backward_work_bytes(desc, n, flags)
+    if nbytes:
+        work = torch.empty(nbytes, dtype=torch.uint8, device=pos.device)     # caller-owned workspace
     check(lib().spline_eval_vgl_backward(ctypes.byref(desc), _ptr(table), n, _ptr(pos), _ptr(gv), _ptr(ggrad),
-                                         _ptr(glap), _ptr(gtable), _ptr(gpos), int(flags), _stream(stream)),
+                                         _ptr(glap), _ptr(gtable), _ptr(gpos), int(flags), _ptr(work), int(nbytes),
+                                         _stream(stream)),
           "spline_eval_vgl_backward")
     return gtable, gpos
+
+
+def spline_backward_work_bytes(desc, n_pts, flags=0):
+    out = ctypes.c_int64()
+    check(lib().spline_backward_work_bytes(ctypes.byref(desc), int(n_pts), int(flags), ctypes.byref(out)),
+          "spline_backward_work_bytes")
+    return out.value
 
 
 def spline_autotune(desc, table, pos, v=None, grad=None, lap=None, stream=None):

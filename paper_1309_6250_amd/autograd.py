@@ -14,10 +14,11 @@ from .api import spline_eval_vgl, spline_eval_vgl_backward, OUT_TORCH
 
 class SplineVGL(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, table, pos, desc):
+    def forward(ctx, table, pos, desc, flags=0):
         v, g, l = spline_eval_vgl(desc, table, pos)
         ctx.save_for_backward(table, pos)
         ctx.desc = desc
+        ctx.flags = flags
         return v, g, l
 
     @staticmethod
@@ -28,11 +29,14 @@ class SplineVGL(torch.autograd.Function):
         prep = [None if g is None else g.to(od).contiguous() for g in (gv, gg, gl)]
         want_t, want_p = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         if not (want_t or want_p):
-            return None, None, None
-        gtable, gpos = spline_eval_vgl_backward(desc, table, pos, *prep, want_table=want_t, want_pos=want_p)
-        return gtable, gpos, None
+            return None, None, None, None
+        gtable, gpos = spline_eval_vgl_backward(desc, table, pos, *prep, want_table=want_t, want_pos=want_p,
+                                                flags=ctx.flags)
+        return gtable, gpos, None, None
 
 
-def spline_vgl(table, pos, desc):
-    """Differentiable (v, grad, lap) of the spline `table` at `pos`."""
-    return SplineVGL.apply(table, pos, desc)
+def spline_vgl(table, pos, desc, deterministic=False):
+    """Differentiable (v, grad, lap) of the spline `table` at `pos`.  deterministic=True makes the
+    coefficient gradient bitwise reproducible (cell-sorted accumulation instead of atomics)."""
+    from ._lib import SPL_DETERMINISTIC
+    return SplineVGL.apply(table, pos, desc, SPL_DETERMINISTIC if deterministic else 0)

@@ -179,6 +179,9 @@ int launch_eval(const spl_desc* d, const void* table, int64_t n_pts, const doubl
 int launch_backward(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, const void* gv,
                     const void* ggrad, const void* glap, void* gtable, double* gpos, hipStream_t stream);
 int build_one(const spl_desc* d, const double* vals, void* table, double* work, hipStream_t stream);
+int sorted_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes);
+int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, const void* gv, const void* ggrad,
+                           const void* glap, void* gtable, void* work, int64_t work_bytes, hipStream_t stream);
 
 int check_eval_args(const spl_desc* d, const void* table, int64_t n_pts, const double* pos) {
   int rc = check_desc(d);
@@ -333,20 +336,40 @@ int spline_autotune(const spl_desc* d, const void* table, int64_t n_pts, const d
   return hip_fail(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
+int spline_backward_work_bytes(const spl_desc* d, int64_t n_pts, int32_t flags, int64_t* bytes) {
+  clear_error();
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if (!bytes) return fail(SPL_EINVAL, "bytes is NULL");
+  if (n_pts < 0 || n_pts > 0x7fffffffLL) return fail(SPL_EINVAL, "n_pts = %lld outside [0, 2^31)", (long long)n_pts);
+  if (flags & ~SPL_DETERMINISTIC) return fail(SPL_EINVAL, "unknown flags 0x%x", flags);
+  *bytes = 0;
+  if (!(flags & SPL_DETERMINISTIC) || n_pts == 0) return SPL_OK;
+  return sorted_work_bytes(d, n_pts, bytes);
+}
+
 int spline_eval_vgl_backward(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, const void* gv,
                              const void* ggrad, const void* glap, void* gtable, double* gpos, int32_t flags,
-                             void* stream) {
+                             void* work, int64_t work_bytes, void* stream) {
   clear_error();
   int rc = check_eval_args(d, table, n_pts, pos);
   if (rc) return rc;
   if (flags & ~SPL_DETERMINISTIC) return fail(SPL_EINVAL, "unknown flags 0x%x", flags);
-  if (flags & SPL_DETERMINISTIC) return fail(SPL_EUNSUPPORTED, "deterministic backward is not implemented");
   if (n_pts == 0) return SPL_OK;
   if (gtable && !aligned(gtable, d->dtype == SPL_F64 ? 8 : 4)) return fail(SPL_EINVAL, "gtable misaligned");
   if (gpos && !aligned(gpos, 8)) return fail(SPL_EINVAL, "gpos misaligned");
   for (const void* g : {gv, ggrad, glap})
     if (g && !out_align_ok(d, g)) return fail(SPL_EINVAL, "upstream gradient misaligned");
-  return launch_backward(d, table, n_pts, pos, gv, ggrad, glap, gtable, gpos, static_cast<hipStream_t>(stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!(flags & SPL_DETERMINISTIC))
+    return launch_backward(d, table, n_pts, pos, gv, ggrad, glap, gtable, gpos, s);
+  if (gtable) {
+    if (!work) return fail(SPL_EINVAL, "SPL_DETERMINISTIC needs a workspace (spline_backward_work_bytes)");
+    if (!aligned(work, 256)) return fail(SPL_EINVAL, "workspace must be 256-byte aligned");
+    if ((rc = launch_backward_sorted(d, n_pts, pos, gv, ggrad, glap, gtable, work, work_bytes, s))) return rc;
+  }
+  // the position gradient is deterministic as computed (fixed-order reduction per point)
+  return gpos ? launch_backward(d, table, n_pts, pos, gv, ggrad, glap, nullptr, gpos, s) : SPL_OK;
 }
 
 }  // extern "C"

@@ -118,11 +118,15 @@ def test_entry_points_reject_bad_arguments_before_any_launch():
     dl = P.spline_desc_init(np.eye(3) * 5, (8, 8, 8), 4, "f64", has_lap=True)
     assert lib.spline_build(ctypes.byref(dl), fake, null, fake, fake, null) == P.SPL_EINVAL
     assert lib.spline_build(ref, null, null, fake, fake, null) == P.SPL_EINVAL
-    # backward flags
-    assert lib.spline_eval_vgl_backward(ref, fake, 10, fake, null, null, null, fake, null, 8, null) == P.SPL_EINVAL
+    # backward flags; the deterministic form needs its workspace
+    assert lib.spline_eval_vgl_backward(ref, fake, 10, fake, null, null, null, fake, null, 8, null, 0,
+                                        null) == P.SPL_EINVAL
     assert lib.spline_eval_vgl_backward(ref, fake, 10, fake, null, null, null, fake, null, P.SPL_DETERMINISTIC,
-                                        null) == P.SPL_EUNSUPPORTED
-    assert b"deterministic" in lib.spline_last_error()
+                                        null, 0, null) == P.SPL_EINVAL
+    assert b"workspace" in lib.spline_last_error()
+    out = ctypes.c_int64(-1)
+    assert lib.spline_backward_work_bytes(ref, 10, 0, ctypes.byref(out)) == P.SPL_OK and out.value == 0
+    assert lib.spline_backward_work_bytes(ref, 10, 4, ctypes.byref(out)) == P.SPL_EINVAL
 
 
 def test_uninitialized_or_modified_descriptor_rejected():

@@ -136,3 +136,25 @@ def test_batched_48_systems_full_size():
         assert normwise(g.double().cpu().numpy()[idx, :, :12], rg) < 1e-5
         assert normwise(l.double().cpu().numpy()[idx, :12], rl) < 1e-5
     plan.close()
+
+
+@pytest.mark.timeout(600)
+def test_deterministic_adjoint_at_fit_size():
+    """10^6 points (FP32 table): the cell-sorted gradient is reproducible bit for bit and agrees with
+    the atomic form to FP32 summation accuracy."""
+    w = config(4)
+    s = w.system
+    pos = to_dev(w.positions())
+    n = pos.shape[0]
+    d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, "f32")
+    tab = P.spline_build(d, to_dev(s.grid_values()))
+    g = torch.Generator(device=DEV).manual_seed(405)
+    gv = torch.randn((n, s.n_orb), device=DEV, generator=g)
+    gl = torch.randn((n, s.n_orb), device=DEV, generator=g)
+    say("deterministic adjoint at 1e6 points")
+    a, _ = P.spline_eval_vgl_backward(d, tab, pos, gv, None, gl, want_pos=False, flags=P.SPL_DETERMINISTIC)
+    b, _ = P.spline_eval_vgl_backward(d, tab, pos, gv, None, gl, want_pos=False, flags=P.SPL_DETERMINISTIC)
+    c, _ = P.spline_eval_vgl_backward(d, tab, pos, gv, None, gl, want_pos=False)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert normwise(a.double().cpu().numpy(), c.double().cpu().numpy()) < 1e-5

@@ -279,3 +279,60 @@ def test_no_writes_past_outputs(dtype, n_orb):
     P.spline_eval_v(d, tab, pos, vb[:n * n_orb].view(n, n_orb))
     torch.cuda.synchronize()
     assert torch.all(vb[n * n_orb:] == 7.25)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_backward_deterministic_matches_oracle_and_repeats(case, dtype):
+    """SPL_DETERMINISTIC: cell-sorted accumulation, colour classes with ragged tails (5, 7, 9 cells
+    per axis here), non-finite points; equal to the oracle and bitwise equal across runs."""
+    d = _desc(case, dtype)
+    tab = table_from_oracle(d, case["beta"], dtype, case["lbeta"])
+    bq = oq.quantized(case["beta"], dtype)
+    lq = None if case["lbeta"] is None else oq.quantized(case["lbeta"], dtype)
+    rng = np.random.default_rng(104)
+    pos = case["pos"][:900]
+    n, o = pos.shape[0], d.n_orb
+    gv, gg, gl = rng.standard_normal((n, o)), rng.standard_normal((n, 3, o)), rng.standard_normal((n, o))
+    od = torch.float64 if dtype == "f64" else torch.float32
+    args = (to_dev(gv, od), to_dev(gg, od), to_dev(gl, od))
+    say("deterministic backward", case["name"], dtype)
+    runs = []
+    for _ in range(3):
+        gt, gp = P.spline_eval_vgl_backward(d, tab, to_dev(pos), *args, flags=P.SPL_DETERMINISTIC)
+        torch.cuda.synchronize()
+        runs.append((gt.clone(), gp.clone()))
+    for gt, gp in runs[1:]:
+        assert torch.equal(gt, runs[0][0])
+        assert torch.equal(torch.nan_to_num(gp, nan=7.0), torch.nan_to_num(runs[0][1], nan=7.0))
+    rb, rlb, rp = oadj.vgl_backward(bq, case["lattice"], pos, gv, gg, gl, lap_beta=lq)
+    got = runs[0][0].double().cpu().numpy()[..., :o]
+    tol = 1e-12 if dtype == "f64" else 2e-5
+    assert normwise(got[0], rb) <= tol
+    if rlb is not None:
+        assert normwise(got[1], rlb) <= tol
+    pad = runs[0][0].double().cpu().numpy()[..., o:]
+    assert pad.size == 0 or np.all(pad == 0.0)
+    ok = np.all(np.isfinite(pos), axis=1)
+    gp = runs[0][1].cpu().numpy()
+    assert np.isnan(gp[~ok]).all()
+    assert normwise(gp[ok], rp[ok]) <= (1e-10 if dtype == "f64" else 1e-4)
+
+
+def test_backward_deterministic_many_points_per_cell():
+    """Clustered points (about 60 per occupied cell): sorted accumulation equals the atomic form."""
+    rng = np.random.default_rng(105)
+    grid = (8, 8, 12)
+    beta = rng.standard_normal(grid + (33,))
+    d = P.spline_desc_init(SKEW, grid, 33, "f64")
+    tab = table_from_oracle(d, beta, "f64")
+    centers = rng.uniform(0, 1, size=(40, 3))
+    s = (centers[rng.integers(0, 40, 6000)] + rng.normal(0, 0.01, size=(6000, 3))) % 1.0
+    pos = s @ SKEW
+    gv = rng.standard_normal((6000, 33))
+    say("deterministic backward, clustered points")
+    a, _ = P.spline_eval_vgl_backward(d, tab, to_dev(pos), to_dev(gv), want_pos=False, flags=P.SPL_DETERMINISTIC)
+    b, _ = P.spline_eval_vgl_backward(d, tab, to_dev(pos), to_dev(gv), want_pos=False)
+    torch.cuda.synchronize()
+    rb, _, _ = oadj.vgl_backward(beta, SKEW, pos, gv)
+    assert normwise(a.cpu().numpy()[0, ..., :33], rb) < 1e-12
+    assert normwise(b.cpu().numpy()[0, ..., :33], rb) < 1e-12

@@ -13,6 +13,7 @@ are small elementwise tensor operations on the table.
 """
 import torch
 
+from ._lib import SPL_DETERMINISTIC
 from .autograd import SplineVGL
 
 
@@ -20,7 +21,7 @@ def second_difference(beta, dim):
     return torch.roll(beta, 1, dims=dim) - 2.0 * beta + torch.roll(beta, -1, dims=dim)
 
 
-def make_loss(desc, pos, v_t, lap_t, lam=1e-3, use_lap=True):
+def make_loss(desc, pos, v_t, lap_t, lam=1e-3, use_lap=True, deterministic=True):
     n_orb = desc.n_orb
     v_t = v_t.to(torch.float64)
     lap_t = lap_t.to(torch.float64)
@@ -29,8 +30,10 @@ def make_loss(desc, pos, v_t, lap_t, lam=1e-3, use_lap=True):
     pts = desc.grid[0] * desc.grid[1] * desc.grid[2]
     reg_scale = lam / (pts * n_orb * torch.mean(v_t * v_t))
 
+    flags = SPL_DETERMINISTIC if deterministic else 0
+
     def loss_fn(beta):
-        v, _, lap = SplineVGL.apply(beta, pos, desc)
+        v, _, lap = SplineVGL.apply(beta, pos, desc, flags)
         rv = v.to(torch.float64) - v_t
         rl = lap.to(torch.float64) - lap_t
         loss = w_v * torch.mean(rv * rv) + w_l * torch.mean(rl * rl)
@@ -43,10 +46,12 @@ def make_loss(desc, pos, v_t, lap_t, lam=1e-3, use_lap=True):
     return loss_fn
 
 
-def fit_adam(desc, table, pos, v_t, lap_t, steps=200, lam=1e-3, lr=None, use_lap=True, callback=None):
-    """Adam from `table` (not modified); returns (fitted table, list of losses per step)."""
+def fit_adam(desc, table, pos, v_t, lap_t, steps=200, lam=1e-3, lr=None, use_lap=True, callback=None,
+             deterministic=True):
+    """Adam from `table` (not modified); returns (fitted table, list of losses per step).
+    deterministic: bitwise-reproducible coefficient gradients (cell-sorted accumulation)."""
     beta = table.detach().clone().requires_grad_(True)
-    loss_fn = make_loss(desc, pos, v_t, lap_t, lam=lam, use_lap=use_lap)
+    loss_fn = make_loss(desc, pos, v_t, lap_t, lam=lam, use_lap=use_lap, deterministic=deterministic)
     if lr is None:
         lr = 1e-3 * float(torch.sqrt(torch.mean(table.detach().to(torch.float64) ** 2)))
     opt = torch.optim.Adam([beta], lr=lr, betas=(0.9, 0.999))

@@ -113,6 +113,29 @@ int spline_build(const spl_desc* d, const double* grid_vals, const double* lap_v
                  void* table, void* work, void* stream);
 
 /*
+ * Smoothing (Fourier-matched) B-spline coefficients from planewave coefficients (App. A,
+ * "Smoothing B-spline coefficients", Eq. b-splinecoefficients):
+ *   beta(r_lmn) = sum_G (c_G / gamma_G) exp(i G . r_lmn),  r_lmn = a (l/N1, m/N2, n/N3),
+ * with gamma_G = prod_m sinc^4(theta_m / 2), theta_m = 2 pi n_m / N_m (the Fourier transform of
+ * one standard-normalized tensor-product basis function), so the spline's fundamental Fourier
+ * components equal c_G.  With has_lap, the second table uses (-|G|^2) c_G.
+ *   n_g     number of planewaves
+ *   miller  device, int32 [n_g][3]: Miller indices n of G = 2 pi lattice^-1 n
+ *   coef    device, FP64 [n_orb][n_g][2]: complex coefficients (re, im), conjugate-symmetric
+ *           in G for real orbitals (the real part of the sum is stored)
+ *   table   device, d->table_bytes, written completely (padding zeroed)
+ *   work    device, spline_smoothing_work_bytes() bytes, 256-byte aligned, scratch
+ * The grid must give every G its own Fourier bin (N_i > 2 max |n_i|); planewaves that share a
+ * bin are added.  Computed in FP64 by separable inverse DFTs, rounded once into the storage dtype.
+ */
+int spline_build_smoothing(const spl_desc* d, int64_t n_g, const int32_t* miller, const double* coef,
+                           void* table, void* work, void* stream);
+
+/* Workspace bytes of spline_build_smoothing: one complex FP64 grid [N1][N2][N3][n_orb] plus
+ * twiddle tables.  Host only. */
+int spline_smoothing_work_bytes(const spl_desc* d, int64_t* bytes);
+
+/*
  * Orbital values phi_o(r_p) (App. A, Eq. b-splineapproximation) at n_pts points.
  *   table  device, as written by spline_build
  *   pos    device, FP64 [n_pts][3]

@@ -22,6 +22,7 @@ EXPORTS = (
     "spline_eval_vgl_backward", "spline_batch_plan_create", "spline_batch_eval_vgl",
     "spline_batch_graph_launch", "spline_batch_autotune", "spline_batch_plan_destroy", "spline_batch_plan_info", "spline_autotune",
     "spline_tile_for", "spline_last_error", "spline_version", "spline_backward_work_bytes",
+    "spline_build_smoothing", "spline_smoothing_work_bytes",
 )
 
 
@@ -84,6 +85,8 @@ def lib():
             "spline_eval_vgl_tile": (ctypes.c_int, [pd, vp, i64, vp, vp, vp, vp, i32p, vp]),
             "spline_eval_vgl_backward": (ctypes.c_int, [pd, vp, i64, vp, vp, vp, vp, vp, vp, i32, vp, i64, vp]),
             "spline_backward_work_bytes": (ctypes.c_int, [pd, i64, i32, ctypes.POINTER(i64)]),
+            "spline_build_smoothing": (ctypes.c_int, [pd, i64, vp, vp, vp, vp, vp]),
+            "spline_smoothing_work_bytes": (ctypes.c_int, [pd, ctypes.POINTER(i64)]),
             "spline_batch_plan_create": (ctypes.c_int, [ctypes.POINTER(SplItem), i32, i32p, vp,
                                                         ctypes.POINTER(vp)]),
             "spline_batch_eval_vgl": (ctypes.c_int, [vp, vp]),

@@ -95,6 +95,35 @@ def spline_build(desc, grid_vals, lap_vals=None, table=None, work=None, stream=N
     return table
 
 
+def spline_smoothing_work_bytes(desc):
+    out = ctypes.c_int64()
+    check(lib().spline_smoothing_work_bytes(ctypes.byref(desc), ctypes.byref(out)), "spline_smoothing_work_bytes")
+    return out.value
+
+
+def spline_build_smoothing(desc, miller, coef, table=None, work=None, stream=None):
+    """Fourier-matched coefficients from planewave coefficients.
+
+    miller: int32 [n_g, 3] (device); coef: complex128 [n_orb, n_g] (device).
+    """
+    _need(miller, "miller", torch.int32)
+    _need(coef, "coef", torch.complex128)
+    n_g = miller.shape[0]
+    if miller.shape != (n_g, 3) or coef.shape != (desc.n_orb, n_g):
+        raise ValueError("miller must be [n_g, 3] and coef [n_orb, n_g]")
+    if table is None:
+        table = new_table(desc, coef.device)
+    _need(table, "table", STORE_TORCH[desc.dtype], desc.table_elems * (1 + desc.has_lap))
+    nbytes = spline_smoothing_work_bytes(desc)
+    if work is None:
+        work = torch.empty(nbytes, dtype=torch.uint8, device=coef.device)
+    if work.numel() * work.element_size() < nbytes:
+        raise ValueError(f"work must hold {nbytes} bytes")
+    check(lib().spline_build_smoothing(ctypes.byref(desc), int(n_g), _ptr(miller), _ptr(coef), _ptr(table),
+                                       _ptr(work), _stream(stream)), "spline_build_smoothing")
+    return table
+
+
 def _outputs(desc, n_pts, device, v, grad, lap, values_only=False):
     od = OUT_TORCH[desc.dtype]
     if v is None:

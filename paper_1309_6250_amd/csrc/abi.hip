@@ -180,6 +180,9 @@ int launch_backward(const spl_desc* d, const void* table, int64_t n_pts, const d
                     const void* ggrad, const void* glap, void* gtable, double* gpos, hipStream_t stream);
 int build_one(const spl_desc* d, const double* vals, void* table, double* work, hipStream_t stream);
 int sorted_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes);
+int64_t smoothing_work_bytes(const spl_desc* d);
+int build_smoothing(const spl_desc* d, int64_t n_g, const int32_t* miller, const double* coef, void* table,
+                    void* work, hipStream_t stream);
 int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, const void* gv, const void* ggrad,
                            const void* glap, void* gtable, void* work, int64_t work_bytes, hipStream_t stream);
 
@@ -238,6 +241,28 @@ int spline_build(const spl_desc* d, const double* grid_vals, const double* lap_v
     if ((rc = build_one(d, lap_vals, lt, static_cast<double*>(work), s))) return rc;
   }
   return SPL_OK;
+}
+
+int spline_smoothing_work_bytes(const spl_desc* d, int64_t* bytes) {
+  clear_error();
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if (!bytes) return fail(SPL_EINVAL, "bytes is NULL");
+  *bytes = smoothing_work_bytes(d);
+  return SPL_OK;
+}
+
+int spline_build_smoothing(const spl_desc* d, int64_t n_g, const int32_t* miller, const double* coef, void* table,
+                           void* work, void* stream) {
+  clear_error();
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if (n_g < 1) return fail(SPL_EINVAL, "n_g = %lld < 1", (long long)n_g);
+  if ((double)n_g * d->n_orb > 9.0e18) return fail(SPL_EINVAL, "too many coefficients");
+  if (!miller || !coef || !table || !work) return fail(SPL_EINVAL, "miller, coef, table and work must be non-NULL");
+  if (!aligned(miller, 4) || !aligned(coef, 16) || !aligned(table, 16) || !aligned(work, 256))
+    return fail(SPL_EINVAL, "misaligned buffer (miller 4, coef 16, table 16, work 256 bytes)");
+  return build_smoothing(d, n_g, miller, coef, table, work, static_cast<hipStream_t>(stream));
 }
 
 int spline_eval_v(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, void* v, void* stream) {

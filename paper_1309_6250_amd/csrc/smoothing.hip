@@ -1,0 +1,243 @@
+// spline_build_smoothing: Fourier-matched (smoothing) B-spline coefficients (App. A, "Smoothing
+// B-spline coefficients", Eq. b-splinecoefficients).
+//
+//   beta(r_lmn) = sum_G (c_G / gamma_G) exp(i G . r_lmn),   r_lmn = a (l/N1, m/N2, n/N3),
+//
+// gamma_G being the Fourier transform of one tensor-product basis function: per axis m, with the
+// phase per grid step theta_m = G . a_m / N_m = 2 pi n_m / N_m, the paper's C = 3/2 basis gives
+// (3/2) sinc^4(theta/2); the standard normalization used here gives sinc^4(theta/2), and gamma is
+// the product over the three axes.  Dividing by gamma makes the spline's fundamental Fourier
+// components equal c_G.  With a separate Laplacian, the second table uses (-|G|^2) c_G.
+//
+// Steps on the device: zero a complex grid [N1][N2][N3][n_orb]; scatter c_G / gamma_G into the
+// bins (n mod N); inverse DFT along each axis in turn (one line per thread, staged in LDS, direct
+// summation with exact twiddle tables, O(N^2) per line: the build is a one-time cost); the last
+// axis writes the real part into the padded table in the storage dtype.
+#include <math.h>
+
+#include "common.hpp"
+
+namespace pws {
+
+typedef double c2v __attribute__((ext_vector_type(2)));   // (re, im)
+
+__global__ __launch_bounds__(256) void k_czero(c2v* w, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    w[i] = c2v{0.0, 0.0};
+}
+
+__device__ __forceinline__ double sinc4_half(double theta) {
+  if (theta == 0.0) return 1.0;
+  const double h = 0.5 * theta;
+  const double s = sin(h) / h;
+  const double s2 = s * s;
+  return s2 * s2;
+}
+
+// grid[bin(n)][o] += coef[o][g] * scale(g): scale = 1 / gamma_G, times -|G|^2 for the Laplacian table.
+__global__ __launch_bounds__(256) void k_scatter_coef(const int32_t* miller, const c2v* coef, int64_t n_g,
+                                                      int32_t n_orb, Geom geo, int32_t lap, c2v* grid) {
+  const int64_t total = n_g * n_orb;
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = idx / n_orb;
+    const int o = (int)(idx - g * n_orb);
+    const int n0 = miller[3 * g], n1 = miller[3 * g + 1], n2 = miller[3 * g + 2];
+    double scale = 1.0 / (sinc4_half(two_pi * n0 / geo.n[0]) * sinc4_half(two_pi * n1 / geo.n[1]) *
+                          sinc4_half(two_pi * n2 / geo.n[2]));
+    if (lap) {
+      double gsq = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        // G = 2 pi (lattice^-1) n, and lattice^-1 = ainv^T
+        const double gc = two_pi * fmaa(geo.ainv[6 + c], (double)n2, fmaa(geo.ainv[3 + c], (double)n1, geo.ainv[c] * n0));
+        gsq = fmaa(gc, gc, gsq);
+      }
+      scale *= -gsq;
+    }
+    const int b0 = ((n0 % geo.n[0]) + geo.n[0]) % geo.n[0];
+    const int b1 = ((n1 % geo.n[1]) + geo.n[1]) % geo.n[1];
+    const int b2 = ((n2 % geo.n[2]) + geo.n[2]) % geo.n[2];
+    const int64_t bin = ((int64_t)b0 * geo.n[1] + b1) * geo.n[2] + b2;
+    const c2v c = coef[(int64_t)o * n_g + g];
+    double* dst = reinterpret_cast<double*>(grid + bin * n_orb + o);
+    unsafeAtomicAdd(dst, c.x * scale);           // planewaves sharing a bin (too coarse a grid) add up
+    unsafeAtomicAdd(dst + 1, c.y * scale);
+  }
+}
+
+struct DftArgs {
+  c2v* data;             // complex grid viewed as [outer][n][inner]
+  void* table;           // final axis: padded table of the storage dtype
+  const double* cs;      // cos(2 pi k / n), k = 0 .. n-1
+  const double* sn;      // sin(2 pi k / n)
+  int64_t n_lines;
+  int64_t inner;
+  int32_t n;
+  int32_t o_pad;
+};
+
+enum { DFT_INPLACE = 0, DFT_TABLE_F64 = 1, DFT_TABLE_F32 = 2, DFT_TABLE_BF16 = 3 };
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne_s(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// y_k = sum_j x_j exp(+2 pi i j k / n) along the middle axis, one line per thread.
+template <int OUT>
+__global__ __launch_bounds__(256) void k_idft_axis(DftArgs a) {
+  extern __shared__ double lds_raw[];
+  const int tile = blockDim.x;
+  const int tid = threadIdx.x;
+  const int n = a.n;
+  double* tw_c = lds_raw;                 // [n]
+  double* tw_s = lds_raw + n;             // [n]
+  c2v* x = reinterpret_cast<c2v*>(lds_raw + 2 * n) + tid;   // [n][tile]
+  for (int k = tid; k < n; k += tile) {
+    tw_c[k] = a.cs[k];
+    tw_s[k] = a.sn[k];
+  }
+  __syncthreads();                        // every thread of the block reaches this barrier
+  const int64_t line = (int64_t)blockIdx.x * tile + tid;
+  if (line >= a.n_lines) return;
+  const int64_t outer = line / a.inner;
+  const int64_t in = line - outer * a.inner;
+  const int64_t base = outer * (int64_t)n * a.inner + in;
+  for (int j = 0; j < n; ++j) x[j * tile] = a.data[base + (int64_t)j * a.inner];
+  for (int k = 0; k < n; ++k) {
+    double re = 0.0, im = 0.0;
+    int idx = 0;                          // (j k) mod n
+    for (int j = 0; j < n; ++j) {
+      const c2v v = x[j * tile];
+      const double c = tw_c[idx], s = tw_s[idx];
+      re = fmaa(v.x, c, fmaa(-v.y, s, re));
+      im = fmaa(v.x, s, fmaa(v.y, c, im));
+      idx += k;
+      if (idx >= n) idx -= n;
+    }
+    if constexpr (OUT == DFT_INPLACE) {
+      a.data[base + (int64_t)k * a.inner] = c2v{re, im};
+    } else {
+      const int64_t t = (outer * (int64_t)n + k) * a.o_pad + in;      // inner == n_orb here
+      if constexpr (OUT == DFT_TABLE_F64) static_cast<double*>(a.table)[t] = re;
+      else if constexpr (OUT == DFT_TABLE_F32) static_cast<float*>(a.table)[t] = (float)re;
+      else static_cast<uint16_t*>(a.table)[t] = f32_to_bf16_rne_s((float)re);
+    }
+  }
+}
+
+template <typename TS>
+__global__ __launch_bounds__(256) void k_zero_pad_s(TS* table, int64_t n_rows, int32_t n_orb, int32_t o_pad) {
+  const int32_t width = o_pad - n_orb;
+  const int64_t total = n_rows * width;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / width;
+    table[r * o_pad + n_orb + (i - r * width)] = TS(0);
+  }
+}
+
+static int dft_tile(int n) {
+  int tile = 256;
+  while (tile > 4 && (int64_t)tile * n * 16 + 16 * (int64_t)n > 65536) tile >>= 1;
+  return tile;
+}
+
+// One inverse-DFT stage along the middle axis of [outer][n][inner] (twiddles in the workspace).
+static int launch_idft(int out, c2v* data, void* table, const double* cs, const double* sn, int64_t outer, int n,
+                       int64_t inner, int o_pad, hipStream_t stream) {
+  DftArgs a;
+  a.data = data;
+  a.table = table;
+  a.cs = cs;
+  a.sn = sn;
+  a.n_lines = outer * inner;
+  a.inner = inner;
+  a.n = n;
+  a.o_pad = o_pad;
+  const int tile = dft_tile(n);
+  const size_t shmem = (size_t)tile * n * 16 + (size_t)n * 16;
+  const dim3 grid((unsigned)((a.n_lines + tile - 1) / tile));
+  switch (out) {
+    case DFT_INPLACE: hipLaunchKernelGGL(k_idft_axis<DFT_INPLACE>, grid, dim3(tile), shmem, stream, a); break;
+    case DFT_TABLE_F64: hipLaunchKernelGGL(k_idft_axis<DFT_TABLE_F64>, grid, dim3(tile), shmem, stream, a); break;
+    case DFT_TABLE_F32: hipLaunchKernelGGL(k_idft_axis<DFT_TABLE_F32>, grid, dim3(tile), shmem, stream, a); break;
+    default: hipLaunchKernelGGL(k_idft_axis<DFT_TABLE_BF16>, grid, dim3(tile), shmem, stream, a); break;
+  }
+  return hip_fail(hipGetLastError(), "inverse DFT launch");
+}
+
+int build_smoothing_one(const spl_desc* d, int64_t n_g, const int32_t* miller, const double* coef, int lap,
+                        void* table, void* work, const double* twiddles, hipStream_t stream) {
+  const int64_t n1 = d->grid[0], n2 = d->grid[1], n3 = d->grid[2], no = d->n_orb;
+  c2v* grid = static_cast<c2v*>(work);
+  const int64_t cells = n1 * n2 * n3 * no;
+  int rc;
+  hipLaunchKernelGGL(k_czero, dim3(2048), dim3(256), 0, stream, grid, cells);
+  if ((rc = hip_fail(hipGetLastError(), "zero fill launch"))) return rc;
+  const Geom geo = make_geom(d);
+  const int64_t sc = n_g * no;
+  const unsigned sblocks = (unsigned)std::min<int64_t>((sc + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_scatter_coef, dim3(sblocks), dim3(256), 0, stream, miller,
+                     reinterpret_cast<const c2v*>(coef), n_g, (int32_t)no, geo, (int32_t)lap, grid);
+  if ((rc = hip_fail(hipGetLastError(), "coefficient scatter launch"))) return rc;
+  // twiddles: [axis][cos n | sin n] packed one axis after the other
+  const double* tw0 = twiddles;
+  const double* tw1 = tw0 + 2 * n1;
+  const double* tw2 = tw1 + 2 * n2;
+  if ((rc = launch_idft(DFT_INPLACE, grid, nullptr, tw0, tw0 + n1, 1, (int)n1, n2 * n3 * no, 0, stream))) return rc;
+  if ((rc = launch_idft(DFT_INPLACE, grid, nullptr, tw1, tw1 + n2, n1, (int)n2, n3 * no, 0, stream))) return rc;
+  const int out = d->dtype == SPL_F64 ? DFT_TABLE_F64 : d->dtype == SPL_F32 ? DFT_TABLE_F32 : DFT_TABLE_BF16;
+  if ((rc = launch_idft(out, grid, table, tw2, tw2 + n3, n1 * n2, (int)n3, no, d->o_pad, stream))) return rc;
+  if (d->o_pad > d->n_orb) {
+    const int64_t rows = n1 * n2 * n3;
+    const int64_t total = rows * (d->o_pad - d->n_orb);
+    const dim3 g((unsigned)std::min<int64_t>((total + 255) / 256, 65536));
+    if (d->dtype == SPL_F64)
+      hipLaunchKernelGGL(k_zero_pad_s<double>, g, dim3(256), 0, stream, (double*)table, rows, d->n_orb, d->o_pad);
+    else if (d->dtype == SPL_F32)
+      hipLaunchKernelGGL(k_zero_pad_s<float>, g, dim3(256), 0, stream, (float*)table, rows, d->n_orb, d->o_pad);
+    else
+      hipLaunchKernelGGL(k_zero_pad_s<uint16_t>, g, dim3(256), 0, stream, (uint16_t*)table, rows, d->n_orb, d->o_pad);
+    if ((rc = hip_fail(hipGetLastError(), "zero padding launch"))) return rc;
+  }
+  return SPL_OK;
+}
+
+// Twiddle tables of the three axes, packed [cos(2 pi k / N1) | sin(..) | cos(.. N2) | sin | cos(.. N3) | sin].
+__global__ void k_twiddles(double* tw, int32_t n0, int32_t n1, int32_t n2) {
+  const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  const double two_pi = 6.283185307179586476925286766559;
+  int n = n0, base = 0, kk = k;
+  if (kk >= n0) { kk -= n0; base = 2 * n0; n = n1;
+    if (kk >= n1) { kk -= n1; base = 2 * (n0 + n1); n = n2; if (kk >= n2) return; } }
+  const double ang = two_pi * kk / n;
+  tw[base + kk] = cos(ang);
+  tw[base + n + kk] = sin(ang);
+}
+
+int64_t smoothing_work_bytes(const spl_desc* d) {
+  const int64_t cells = (int64_t)d->grid[0] * d->grid[1] * d->grid[2] * d->n_orb;
+  return cells * 16 + 16 * (int64_t)(d->grid[0] + d->grid[1] + d->grid[2]) + 256;
+}
+
+int build_smoothing(const spl_desc* d, int64_t n_g, const int32_t* miller, const double* coef, void* table,
+                    void* work, hipStream_t stream) {
+  const int64_t cells = (int64_t)d->grid[0] * d->grid[1] * d->grid[2] * d->n_orb;
+  double* tw = reinterpret_cast<double*>(static_cast<char*>(work) + ((cells * 16 + 255) & ~int64_t(255)));
+  const int nt = d->grid[0] + d->grid[1] + d->grid[2];
+  hipLaunchKernelGGL(k_twiddles, dim3((nt + 255) / 256), dim3(256), 0, stream, tw, d->grid[0], d->grid[1], d->grid[2]);
+  int rc = hip_fail(hipGetLastError(), "twiddle launch");
+  if (rc) return rc;
+  if ((rc = build_smoothing_one(d, n_g, miller, coef, 0, table, work, tw, stream))) return rc;
+  if (d->has_lap) {
+    char* lt = static_cast<char*>(table) + d->table_elems * d->elem_bytes;
+    if ((rc = build_smoothing_one(d, n_g, miller, coef, 1, lt, work, tw, stream))) return rc;
+  }
+  return SPL_OK;
+}
+
+}  // namespace pws

@@ -328,6 +328,50 @@ def fit_rows(steps, warmup, adam_steps=50):
     return out
 
 
+def copy_bandwidth():
+    """Achievable HBM bandwidth of a plain device-to-device copy (2 GiB), for context."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    ms = time_launches(lambda: dst.copy_(src), 10, 2)
+    del src, dst
+    return {"bytes_per_copy": 2 * (1 << 31), "ms": ms, "GBps": 2 * (1 << 31) / (ms * 1e-3) / 1e9}
+
+
+def smoothing_rows(wl2):
+    """Fourier-matched build on the MgO-like cell and the paper's comparison of methods on the synthetic
+    orbitals: RMAE against the planewave sum of value, gradient and Laplacian for the interpolating and
+    the smoothing spline, each with the Laplacian from derivatives and from a separate spline (FP64)."""
+    import numpy as np
+    import torch
+    import paper_1309_6250_amd as P
+    from oracle import pw as opw
+    s = wl2.s
+    d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, "f64", has_lap=True)
+    miller = torch.from_numpy(s.miller.astype(np.int32)).cuda()
+    coef = torch.from_numpy(s.coef).cuda()
+    work = torch.empty(P.spline_smoothing_work_bytes(d), dtype=torch.uint8, device="cuda")
+    tab_s = P.new_table(d)
+    ms = time_launches(lambda: P.spline_build_smoothing(d, miller, coef, tab_s, work), 1, 1)
+    del work
+    tab_i = P.spline_build(d, wl2.f, wl2.lf)
+    rng = np.random.default_rng(1309)
+    idx = np.sort(rng.choice(wl2.pos_host.shape[0], size=48, replace=False))
+    k = 16
+    vp, gp, lp = opw.pw_vgl(s.gvecs, s.coef[:k], wl2.pos_host[idx])
+    d_nolap = P.spline_desc_init(s.lattice, s.grid, s.n_orb, "f64")
+    x = wl2.pos[torch.from_numpy(idx).cuda()].contiguous()
+    out = {"spline_build_smoothing_f64_lap_ms": ms, "sample": f"48 points x first {k} orbitals"}
+    rmae = lambda a, b: float(np.abs(a - b).mean() / np.abs(b).mean())
+    for name, tab in (("interpolating", tab_i), ("smoothing", tab_s)):
+        v, g, l = [t.cpu().numpy() for t in P.spline_eval_vgl(d_nolap, tab[:1].contiguous(), x)]
+        _, _, ls = [t.cpu().numpy() for t in P.spline_eval_vgl(d, tab, x)]
+        out[name] = {"rmae_V": rmae(v[:, :k], vp), "rmae_grad": rmae(g[:, :, :k], gp),
+                     "rmae_lap_derivative": rmae(l[:, :k], lp), "rmae_lap_separate": rmae(ls[:, :k], lp)}
+    del tab_s, tab_i
+    return out
+
+
 def batched_row(steps, warmup):
     """48 uneven systems (orbitals 32-256, grids 24^3-64^3, 16-512 walkers x 64-256 electrons),
     FP32 tables built on the GPU, all VGL evaluations in one persistent launch replayed from a
@@ -456,7 +500,11 @@ def main():
         torch.cuda.empty_cache()
         del t1, o1
         torch.cuda.empty_cache()
+        rows["copy_bandwidth"] = copy_bandwidth()
+        log(f"plain copy: {rows['copy_bandwidth']['GBps']:.0f} GB/s")
         wl2 = Workload(2, lap=True).upload()
+        rows["smoothing_vs_interpolating_mgo96"] = smoothing_rows(wl2)
+        torch.cuda.empty_cache()
         f64_rate = {}
         for lap in (False, True):
             for dtype in ("f64", "f32", "bf16"):

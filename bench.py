@@ -10,7 +10,8 @@ Also reported on the same JSON line:
   forms     the precision forms (FP64 / FP32 / BF16 tables, with and without a separate
             Laplacian spline) on the Si cell and on the MgO-like cell (256 orbitals, 96^3
             grid, 512 x 128 points: tables of 0.45-3.6 GB, far beyond on-chip caches), each
-            with throughput, algorithmic bandwidth and its error against the FP64 oracle;
+            with throughput, algorithmic bandwidth and its errors against the planewave sum
+            and against the FP64 table's outputs;
   rows      the other entry points of the path: spline_build, spline_eval_v, the adjoint
             and the batched persistent launch;
   roofline  the dominant kernel (the headline VGL launch) against MI355X's 8 TB/s HBM peak;
@@ -137,33 +138,49 @@ def run_form(wl, dtype, has_lap, steps, warmup, tune=True, tile=None):
 
 
 def accuracy(wl, dtype, has_lap, outs, n_sample=48, n_orb_ref=16):
-    """Errors of the GPU outputs against the FP64 oracle on a seeded sample of points and the
-    first orbitals: the FP64 interpolating spline (storage + arithmetic error of the form) and the
-    planewave sum (the spline's own approximation error)."""
+    """Errors of the GPU outputs on a seeded sample of points and the first orbitals: against the
+    planewave sum (the spline's own approximation error) and, for FP32/BF16 tables, against the FP64
+    table's outputs on the same workload (the storage and arithmetic error of the form).  The FP64
+    form must be measured first; its agreement with the FP64 oracle is what the parity tests check."""
     import numpy as np
-    from oracle import build as obuild, evaluate as oeval, pw as opw
+    import torch
     rng = np.random.default_rng(1309)
     idx = np.sort(rng.choice(wl.pos_host.shape[0], size=n_sample, replace=False))
-    pos = wl.pos_host[idx]
     k = min(n_orb_ref, wl.s.n_orb)
-    key = (has_lap, k)
-    cache = wl.__dict__.setdefault("_oracle_cache", {})
-    if key not in cache:
-        beta = obuild.build_interp(np.ascontiguousarray(wl.f_host[..., :k]))
-        lbeta = obuild.build_interp(np.ascontiguousarray(wl.lf_host[..., :k])) if has_lap else None
-        ref = oeval.eval_vgl(beta, wl.s.lattice, pos, lap_beta=lbeta)
-        pwref = opw.pw_vgl(wl.s.gvecs, wl.s.coef[:k], pos)
-        cache[key] = (ref, pwref)
-    ref, pwref = cache[key]
+    cache = wl.__dict__.setdefault("_accuracy_cache", {})
+    if "pw" not in cache:
+        x = wl.pos[torch.from_numpy(idx).cuda()].contiguous()
+        cache["pw"] = planewave_vgl_gpu(wl.s, x, k)
+    pwref = cache["pw"]
     got = [outs[0].double().cpu().numpy()[idx, :k], outs[1].double().cpu().numpy()[idx, :, :k],
            outs[2].double().cpu().numpy()[idx, :k]]
+    if dtype == "f64":
+        cache[("f64", has_lap)] = got
+    f64 = cache.get(("f64", has_lap))
     res = {}
-    for name, g, r, p in zip(("V", "grad", "lap"), got, ref, pwref):
-        res[name] = {"normwise_vs_fp64_spline": normwise(g, r), "maxabs_vs_fp64_spline": float(np.abs(g - r).max()),
-                     "normwise_vs_planewave": normwise(g, p),
-                     "rmae_vs_planewave": float(np.abs(g - p).mean() / np.abs(p).mean())}
+    for j, (name, g, p) in enumerate(zip(("V", "grad", "lap"), got, pwref)):
+        r = {"normwise_vs_planewave": normwise(g, p),
+             "rmae_vs_planewave": float(np.abs(g - p).mean() / np.abs(p).mean())}
+        if dtype != "f64" and f64 is not None:
+            r["normwise_vs_fp64_table"] = normwise(g, f64[j])
+            r["maxabs_vs_fp64_table"] = float(np.abs(g - f64[j]).max())
+        res[name] = r
     res["sample"] = f"{n_sample} seeded points x first {k} orbitals"
     return res
+
+
+def planewave_vgl_gpu(system, x, k):
+    """Value, gradient and Laplacian of the first k planewave orbitals (Eq. pw_orbital) at the points
+    x (device, [n][3]), by direct summation over the G vectors in complex128 on the GPU: the exact
+    function the splines approximate.  Returns numpy arrays [n][k], [n][3][k], [n][k]."""
+    import torch
+    g = torch.from_numpy(system.gvecs).cuda()                       # [N_G][3]
+    c = torch.from_numpy(system.coef[:k]).cuda()                    # [k][N_G]
+    e = torch.exp(1j * (x @ g.t()))                                  # [n][N_G]
+    v = (e @ c.t().contiguous()).real
+    grad = torch.stack([(e @ (1j * g[:, a][None, :] * c).t().contiguous()).real for a in range(3)], 1)
+    lap = (e @ (-(g * g).sum(1)[None, :] * c).t().contiguous()).real
+    return v.cpu().numpy(), grad.cpu().numpy(), lap.cpu().numpy()
 
 
 def cpu_baseline(wl, max_workers=16):
@@ -345,7 +362,6 @@ def smoothing_rows(wl2):
     import numpy as np
     import torch
     import paper_1309_6250_amd as P
-    from oracle import pw as opw
     s = wl2.s
     d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, "f64", has_lap=True)
     miller = torch.from_numpy(s.miller.astype(np.int32)).cuda()
@@ -358,9 +374,9 @@ def smoothing_rows(wl2):
     rng = np.random.default_rng(1309)
     idx = np.sort(rng.choice(wl2.pos_host.shape[0], size=48, replace=False))
     k = 16
-    vp, gp, lp = opw.pw_vgl(s.gvecs, s.coef[:k], wl2.pos_host[idx])
     d_nolap = P.spline_desc_init(s.lattice, s.grid, s.n_orb, "f64")
     x = wl2.pos[torch.from_numpy(idx).cuda()].contiguous()
+    vp, gp, lp = planewave_vgl_gpu(s, x, k)
     out = {"spline_build_smoothing_f64_lap_ms": ms, "sample": f"48 points x first {k} orbitals"}
     rmae = lambda a, b: float(np.abs(a - b).mean() / np.abs(b).mean())
     for name, tab in (("interpolating", tab_i), ("smoothing", tab_s)):

@@ -117,7 +117,7 @@ def test_fit_loss_and_gradient_match_oracle():
     torch.cuda.synchronize()
     w_v, w_l = ofit.weights_from_targets(v_t, l_t)
     rloss, rgrad = ofit.loss_and_grad(beta0, s.lattice, pos, v_t, l_t, w_v, w_l, lam=0.3)
-    assert abs(float(loss) - rloss) <= 1e-11 * abs(rloss)
+    assert abs(float(loss.detach()) - rloss) <= 1e-11 * abs(rloss)
     assert normwise(table.grad.cpu().numpy()[0, ..., :s.n_orb], rgrad) < 1e-10
 
 

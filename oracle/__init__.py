@@ -23,6 +23,12 @@ Plain numpy in float64, written for a reader to check against the paper by eye:
   smoothing  Fourier-matched (smoothing) B-spline coefficients (App. A,
              Eq. b-splinecoefficients)
   fit        weighted least-squares misfit with a second-difference penalty
+  lagrange   cubic Lagrange interpolation of grid values (App. A, Lagrange
+             interpolation)
+  separate   value, gradient and Laplacian from five separate interpolants
+             (direct approximations of the derivatives, Sec. III A, Fig. 1)
+  bloch      Bloch orbitals e^{ik.r} u(r): planewave sums and the product rule
+             over a complex periodic interpolant (Sec. I)
 
 Basis normalization: the paper scales the cubic B-spline so that its maximum is
 1 (C = 3/2 in the recurrence of App. A); this oracle uses the standard
@@ -31,3 +37,4 @@ The spline *function* is the same either way; only the stored coefficients
 differ, by the constant factor (3/2)^3.
 """
 from . import bspline, pw, build, evaluate, adjoint, quantize, smoothing, fit  # noqa: F401
+from . import lagrange, separate, bloch  # noqa: F401

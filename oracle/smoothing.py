@@ -32,10 +32,12 @@ def gamma(miller, grid):
     return gamma_axis(theta[:, 0]) * gamma_axis(theta[:, 1]) * gamma_axis(theta[:, 2])
 
 
-def build_smoothing(miller, coef, grid):
+def build_smoothing(miller, coef, grid, keep_complex=False):
     """beta [N1][N2][N3][O] from planewave coefficients coef [O, N_G] at Miller indices miller [N_G, 3].
 
-    Requires each Miller index to land in its own FFT bin (N_i > 2 max |n_i|).
+    The real part is returned (real orbitals), or the complex coefficients with keep_complex
+    (the periodic part of a Bloch orbital).  Requires each Miller index to land in its own FFT
+    bin (N_i > 2 max |n_i|).
     """
     grid = tuple(int(v) for v in grid)
     miller = np.asarray(miller)
@@ -48,4 +50,4 @@ def build_smoothing(miller, coef, grid):
     spec[:, bins[:, 0], bins[:, 1], bins[:, 2]] = scaled
     total = grid[0] * grid[1] * grid[2]
     beta = np.fft.ifftn(spec, axes=(1, 2, 3)) * total
-    return np.ascontiguousarray(np.moveaxis(beta.real, 0, -1))
+    return np.ascontiguousarray(np.moveaxis(beta if keep_complex else beta.real, 0, -1))

@@ -15,6 +15,7 @@ from .synth import (
     make_system,
     gvectors,
     draw_coefficients,
+    draw_bloch_coefficients,
     sample_grid,
     sample_grid_laplacian,
     draw_positions,
@@ -23,6 +24,6 @@ from .configs import CONFIGS, config, batched_systems
 
 __all__ = [
     "BOHR_PER_ANGSTROM", "System", "make_system", "gvectors", "draw_coefficients",
-    "sample_grid", "sample_grid_laplacian", "draw_positions", "CONFIGS", "config",
+    "draw_bloch_coefficients", "sample_grid", "sample_grid_laplacian", "draw_positions", "CONFIGS", "config",
     "batched_systems",
 ]

@@ -14,6 +14,10 @@ a Gaussian spectral decay stand in for them, on cells of the same shape.
   3  48 independent cubic cells of uneven size (see batched_systems).
   4  as 1 but a 32^3 grid and 10^6 fit points (smoothing fit).
   5  Al fcc primitive cell (a = 4.05 A), 4 orbitals, 16^3 grid (Al-like variant of 0).
+  6  Bloch orbitals at the L point, k = (pi/a)(1,1,1), of the Si fcc primitive cell of 0:
+     4 complex orbitals, 16^3 grid, 8 + 4096 points (small case).
+  7  Bloch orbitals in config 1's cell at the supercell zone-corner twist k = (pi/L)(1,1,1),
+     L = 2a: 128 complex orbitals, 48^3 grid, 256 walkers x 256 electrons.
 """
 from __future__ import annotations
 
@@ -68,14 +72,21 @@ CONFIGS = {
             gcut=4.0, decay=2.0, walkers=1, elec=1_000_000, extra=0, dtypes=("f32",), has_lap=False),
     5: dict(name="al-fcc-prim-16", lattice=lambda: fcc_primitive(A_AL), grid=(16, 16, 16), n_orb=4,
             gcut=4.0, decay=2.0, walkers=1, elec=8, extra=4096, dtypes=("f64",), has_lap=False),
+    6: dict(name="si-fcc-prim-16-L", lattice=lambda: fcc_primitive(A_SI), grid=(16, 16, 16), n_orb=4,
+            gcut=4.0, decay=2.0, walkers=1, elec=8, extra=4096, dtypes=("f64",), has_lap=False,
+            kvec=lambda: (np.pi / A_SI) * np.ones(3)),
+    7: dict(name="si64-cubic-48-twist", lattice=lambda: cubic(2.0 * A_SI), grid=(48, 48, 48), n_orb=128,
+            gcut=4.0, decay=2.0, walkers=256, elec=256, extra=0, dtypes=("f64", "f32"), has_lap=False,
+            kvec=lambda: (np.pi / (2.0 * A_SI)) * np.ones(3)),
 }
 
 
 def config(key: int) -> Workload:
-    """The named single-system workload ``key`` (0, 1, 2, 4 or 5)."""
+    """The named single-system workload ``key`` (0, 1, 2, 4, 5, 6 or 7)."""
     c = CONFIGS[key]
+    kvec = c["kvec"]() if "kvec" in c else None
     sysm = make_system(c["name"], c["lattice"](), c["grid"], c["n_orb"], c["gcut"], c["decay"],
-                       SEED + (key,))
+                       SEED + (key,), kvec=kvec)
     return Workload(key=key, system=sysm, n_walkers=c["walkers"], n_elec=c["elec"],
                     dtypes=c["dtypes"], has_lap=c["has_lap"], extra_points=c["extra"])
 

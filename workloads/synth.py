@@ -9,6 +9,14 @@ Conventions
   G = 2*pi * inv(lattice) @ n, so that G.r = 2*pi n.s for r = a s.
 * Orbital phi_o(r) = sum_G c_{o,G} exp(i G.r) (Eq. pw_orbital, Gamma point).
   Real orbitals: c_{-G} = conj(c_G); c_0 is real.
+* Bloch orbitals at crystal momentum k (Sec. I): phi_o(r) = exp(i k.r) u_o(r) with the
+  periodic part u_o(r) = sum_G c_{o,G} exp(i G.r), planewaves |k + G| < Gcut.  The
+  coefficients have no symmetry: Re and Im of every c_G are independent
+  N(0, exp(-|k+G|^2/decay)/2), drawn as standard_normal((n_orb, 2 N_G)) with columns
+  (2g, 2g+1) = (Re, Im) of the g-th G in lexicographic Miller order.
+* Grid samples are always of periodic functions: u itself, the periodic part of the
+  orbital's gradient, sum_G i(k+G) c_G e^{iG.r}, and of its Laplacian,
+  sum_G -|k+G|^2 c_G e^{iG.r} (k = 0 for Gamma orbitals, whose samples are real).
 * Coefficient draw: E|c_G|^2 = exp(-|G|^2 / decay).  On the half space
   H = {n : first nonzero Miller index > 0}, Re and Im are independent
   N(0, exp(-|G|^2/decay)/2); the partner -n gets the conjugate; c_0 ~ N(0, 1).
@@ -31,18 +39,22 @@ import numpy as np
 BOHR_PER_ANGSTROM = 1.0 / 0.529177210903
 
 
-def gvectors(lattice: np.ndarray, gcut: float):
-    """All reciprocal-lattice vectors with |G| < gcut (strict), lexicographic in (n1, n2, n3).
+def gvectors(lattice: np.ndarray, gcut: float, kvec=None):
+    """All reciprocal-lattice vectors with |k + G| < gcut (strict; k = 0 by default),
+    lexicographic in (n1, n2, n3).
 
     Returns (miller [N_G, 3] int64, gvecs [N_G, 3] float64).
     """
     lattice = np.asarray(lattice, dtype=np.float64)
+    k = np.zeros(3) if kvec is None else np.asarray(kvec, dtype=np.float64)
     inv = np.linalg.inv(lattice)            # columns of inv are b_j / (2 pi)
-    nmax = [int(math.ceil(gcut * np.linalg.norm(lattice[i]) / (2.0 * math.pi))) for i in range(3)]
+    reach = gcut + float(np.linalg.norm(k))
+    nmax = [int(math.ceil(reach * np.linalg.norm(lattice[i]) / (2.0 * math.pi))) for i in range(3)]
     r = [np.arange(-m, m + 1, dtype=np.int64) for m in nmax]
     n = np.stack(np.meshgrid(*r, indexing="ij"), axis=-1).reshape(-1, 3)   # lexicographic
     g = 2.0 * math.pi * (n.astype(np.float64) @ inv.T)
-    keep = np.einsum("ij,ij->i", g, g) < gcut * gcut
+    q = g + k
+    keep = np.einsum("ij,ij->i", q, q) < gcut * gcut
     return n[keep], g[keep]
 
 
@@ -71,11 +83,21 @@ def draw_coefficients(miller: np.ndarray, gvecs: np.ndarray, n_orb: int, decay: 
     return c
 
 
-def _grid_from_coef(miller, coef, grid, chunk=16, out=None):
+def draw_bloch_coefficients(gvecs: np.ndarray, kvec, n_orb: int, decay: float,
+                            rng: np.random.Generator) -> np.ndarray:
+    """Complex coefficients c[o, G] of the periodic parts of Bloch orbitals; see the module docstring."""
+    q = np.asarray(gvecs, dtype=np.float64) + np.asarray(kvec, dtype=np.float64)
+    q2 = np.einsum("ij,ij->i", q, q)
+    z = rng.standard_normal((n_orb, 2 * q.shape[0]))
+    scale = np.sqrt(np.exp(-q2 / decay) / 2.0)
+    return (z[:, 0::2] + 1j * z[:, 1::2]) * scale
+
+
+def _grid_from_coef(miller, coef, grid, chunk=16, out=None, keep_complex=False):
     n1, n2, n3 = (int(v) for v in grid)
     n_orb = coef.shape[0]
     if out is None:
-        out = np.empty((n1, n2, n3, n_orb), dtype=np.float64)
+        out = np.empty((n1, n2, n3, n_orb), dtype=np.complex128 if keep_complex else np.float64)
     bins = np.ravel_multi_index(tuple((np.asarray(miller) % np.array([n1, n2, n3])).T), (n1, n2, n3))
     total = n1 * n2 * n3
     for o0 in range(0, n_orb, chunk):
@@ -84,7 +106,7 @@ def _grid_from_coef(miller, coef, grid, chunk=16, out=None):
         np.add.at(spec, (np.arange(nc)[:, None], bins[None, :]), coef[o0:o0 + nc])
         x = np.fft.ifftn(spec.reshape(nc, n1, n2, n3), axes=(1, 2, 3))
         x *= total
-        out[..., o0:o0 + nc] = np.moveaxis(x.real, 0, -1)
+        out[..., o0:o0 + nc] = np.moveaxis(x if keep_complex else x.real, 0, -1)
     return out
 
 
@@ -115,6 +137,7 @@ class System:
     gcut: float
     decay: float
     seed_key: tuple
+    kvec: tuple = None           # crystal momentum (1/bohr) of Bloch orbitals; None = real Gamma orbitals
     miller: np.ndarray = None
     gvecs: np.ndarray = None
     coef: np.ndarray = None
@@ -124,10 +147,29 @@ class System:
         self.grid = tuple(int(v) for v in self.grid)
         ss = np.random.SeedSequence(list(self.seed_key))
         self._ss_coef, self._ss_pos = ss.spawn(2)
+        if self.kvec is not None:
+            self.kvec = tuple(float(v) for v in self.kvec)
         if self.miller is None:
-            self.miller, self.gvecs = gvectors(self.lattice, self.gcut)
-            self.coef = draw_coefficients(self.miller, self.gvecs, self.n_orb, self.decay,
-                                          np.random.Generator(np.random.PCG64(self._ss_coef)))
+            rng = np.random.Generator(np.random.PCG64(self._ss_coef))
+            self.miller, self.gvecs = gvectors(self.lattice, self.gcut, self.kvec)
+            if self.kvec is None:
+                self.coef = draw_coefficients(self.miller, self.gvecs, self.n_orb, self.decay, rng)
+            else:
+                self.coef = draw_bloch_coefficients(self.gvecs, self.kvec, self.n_orb, self.decay, rng)
+
+    @property
+    def bloch(self) -> bool:
+        return self.kvec is not None
+
+    @property
+    def k(self) -> np.ndarray:
+        """Crystal momentum as an array (zeros for Gamma orbitals)."""
+        return np.zeros(3) if self.kvec is None else np.asarray(self.kvec, dtype=np.float64)
+
+    @property
+    def qvecs(self) -> np.ndarray:
+        """k + G for every planewave: the wavevectors of the orbital's planewaves."""
+        return self.gvecs + self.k
 
     @property
     def n_g(self) -> int:
@@ -138,15 +180,27 @@ class System:
         return all(self.grid[i] > 2 * int(np.abs(self.miller[:, i]).max()) for i in range(3))
 
     def grid_values(self, out=None) -> np.ndarray:
-        return sample_grid(self.miller, self.coef, self.grid, out=out)
+        """Samples of u (the orbital itself at Gamma): [N1][N2][N3][n_orb], complex for Bloch orbitals."""
+        return _grid_from_coef(self.miller, self.coef, self.grid, out=out, keep_complex=self.bloch)
 
     def grid_laplacian(self, out=None) -> np.ndarray:
-        return sample_grid_laplacian(self.miller, self.gvecs, self.coef, self.grid, out=out)
+        """Samples of the periodic part of the orbital's Laplacian, sum_G -|k+G|^2 c_G e^{iG.r}."""
+        q = self.qvecs
+        q2 = np.einsum("ij,ij->i", q, q)
+        return _grid_from_coef(self.miller, self.coef * (-q2)[None, :], self.grid, out=out,
+                               keep_complex=self.bloch)
+
+    def grid_gradient(self) -> np.ndarray:
+        """Samples of the periodic part of the orbital's gradient, sum_G i(k+G) c_G e^{iG.r}:
+        [3][N1][N2][N3][n_orb] (Cartesian component first), complex for Bloch orbitals."""
+        q = self.qvecs
+        return np.stack([_grid_from_coef(self.miller, self.coef * (1j * q[:, a])[None, :], self.grid,
+                                         keep_complex=self.bloch) for a in range(3)])
 
     def positions(self, n_pts: int) -> np.ndarray:
         return draw_positions(self.lattice, n_pts, np.random.Generator(np.random.PCG64(self._ss_pos)))
 
 
-def make_system(name, lattice, grid, n_orb, gcut, decay, seed_key) -> System:
+def make_system(name, lattice, grid, n_orb, gcut, decay, seed_key, kvec=None) -> System:
     return System(name=name, lattice=lattice, grid=grid, n_orb=n_orb, gcut=gcut, decay=decay,
-                  seed_key=tuple(seed_key))
+                  seed_key=tuple(seed_key), kvec=kvec)

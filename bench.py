@@ -9,9 +9,11 @@ table.  Inputs (table and positions) are resident in HBM before timing starts.
 Also reported on the same JSON line:
   forms     the precision forms (FP64 / FP32 / BF16 tables, with and without a separate
             Laplacian spline) on the Si cell and on the MgO-like cell (256 orbitals, 96^3
-            grid, 512 x 128 points: tables of 0.45-3.6 GB, far beyond on-chip caches), each
-            with throughput, algorithmic bandwidth and its errors against the planewave sum
-            and against the FP64 table's outputs;
+            grid, 512 x 128 points: tables of 0.45-3.6 GB, far beyond on-chip caches); on the
+            MgO-like cell also five separate tables (B-spline or Lagrange, FP64 / FP32); Bloch
+            orbitals at a twist on the Si cell (FP64 / FP32); each with throughput, algorithmic
+            bandwidth and its errors against the planewave sum and against the FP64 table's
+            outputs;
   rows      the other entry points of the path: spline_build, spline_eval_v, the adjoint
             and the batched persistent launch;
   roofline  the dominant kernel (the headline VGL launch) against MI355X's 8 TB/s HBM peak;
@@ -47,11 +49,12 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def bytes_per_eval(dtype, has_lap):
-    """Algorithmic HBM bytes of one orbital-VGL: 64 coefficients (x2 with a separate Laplacian
-    table) plus 5 outputs; positions add 24 bytes per point."""
+def bytes_per_eval(dtype, n_tables=1, cols=1):
+    """Algorithmic HBM bytes of one orbital-VGL: 64 coefficients of each table read (1; 2 with a
+    separate Laplacian; 5 with separate gradients) plus 5 outputs, per stored column (2 for a Bloch
+    orbital's real and imaginary parts); positions add 24 bytes per point."""
     out = 8 if dtype == "f64" else 4
-    return 64 * STORE_BYTES[dtype] * (2 if has_lap else 1) + 5 * out
+    return cols * (64 * STORE_BYTES[dtype] * n_tables + 5 * out)
 
 
 def time_launches(fn, steps, warmup):
@@ -93,7 +96,7 @@ class Workload:
 
     def upload(self):
         import torch
-        self.f = torch.from_numpy(self.f_host).cuda()
+        self.f = torch.from_numpy(self.f_host).cuda()          # complex128 for Bloch orbitals
         self.lf = None if self.lf_host is None else torch.from_numpy(self.lf_host).cuda()
         self.pos = torch.from_numpy(self.pos_host).cuda()
         torch.cuda.synchronize()
@@ -101,28 +104,41 @@ class Workload:
 
     def describe(self, dtype, has_lap):
         s = self.s
-        return {"workload": s.name, "n_orb": s.n_orb, "grid": list(s.grid), "walkers": self.w.n_walkers,
-                "electrons": self.w.n_elec, "points": int(self.pos.shape[0]), "table": dtype,
-                "separate_laplacian": bool(has_lap), "lattice_bohr": [round(x, 6) for x in s.lattice.reshape(-1)]}
+        out = {"workload": s.name, "n_orb": s.n_orb, "grid": list(s.grid), "walkers": self.w.n_walkers,
+               "electrons": self.w.n_elec, "points": int(self.pos.shape[0]), "table": dtype,
+               "separate_laplacian": bool(has_lap), "lattice_bohr": [round(x, 6) for x in s.lattice.reshape(-1)]}
+        if s.bloch:
+            out["kvec_per_bohr"] = [round(x, 8) for x in s.k]
+        return out
 
 
-def run_form(wl, dtype, has_lap, steps, warmup, tune=True, tile=None):
-    """Build, autotune (or take `tile`) and time one form; returns (record, desc, table, outputs)."""
+def run_form(wl, dtype, has_lap, steps, warmup, tune=True, tile=None, sep=None, fields=None):
+    """Build, autotune (or take `tile`) and time one form; returns (record, desc, table, outputs).
+
+    sep: None (derivatives of the orbital table, plus a separate Laplacian table with has_lap) or
+    "bspline" / "lagrange" (five separate tables built from `fields`, the stacked device grid
+    values).  Bloch orbitals follow from the workload's crystal momentum."""
     import torch
     import paper_1309_6250_amd as P
     s = wl.s
-    d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype, has_lap=has_lap)
-    work = torch.empty(d.work_bytes // 8, dtype=torch.float64, device="cuda")
+    kvec = s.k if s.bloch else None
+    if sep:
+        d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype, has_lap=True, sep_grad=True, basis=sep, kvec=kvec)
+    else:
+        d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype, has_lap=has_lap, kvec=kvec)
+    work = None if sep == "lagrange" else torch.empty(d.work_bytes // 8, dtype=torch.float64, device="cuda")
     table = P.new_table(d)
-    build_ms = time_launches(lambda: P.spline_build(d, wl.f, wl.lf if has_lap else None, table, work),
-                             1, 1)
+    if sep:
+        build_ms = time_launches(lambda: P.spline_build_tables(d, fields, table, work), 1, 1)
+    else:
+        build_ms = time_launches(lambda: P.spline_build(d, wl.f, wl.lf if has_lap else None, table, work), 1, 1)
     outs = P.spline_eval_vgl(d, table, wl.pos, tile=tile)
     if tile is None:
         tile = P.spline_autotune(d, table, wl.pos, *outs) if tune else P.spline_tile_for(d)
     ms = time_launches(lambda: P.spline_eval_vgl(d, table, wl.pos, *outs, tile=tile), steps, warmup)
     n_pts, n_orb = wl.pos.shape[0], s.n_orb
     evals = n_pts * n_orb
-    alg = evals * bytes_per_eval(dtype, has_lap) + 24 * n_pts
+    alg = evals * bytes_per_eval(dtype, d.n_tables, 2 if s.bloch else 1) + 24 * n_pts
     rec = {
         "evals_per_s": evals / (ms * 1e-3),
         "ms_per_sweep": ms,
@@ -137,11 +153,49 @@ def run_form(wl, dtype, has_lap, steps, warmup, tune=True, tile=None):
     return rec, d, table, outs
 
 
-def accuracy(wl, dtype, has_lap, outs, n_sample=48, n_orb_ref=16):
+def grid_fields_gpu(system, chunk=16):
+    """Fixture for the five-table forms: grid samples of the orbital (u for Bloch orbitals), of the
+    periodic parts of its gradient, sum_G i(k+G) c_G e^{iG.r}, and of its Laplacian,
+    sum_G -|k+G|^2 c_G e^{iG.r}, by inverse FFTs on the GPU (input generation, never timed).
+    Returns FP64 [5][N1][N2][N3][n_col] on the device."""
+    import numpy as np
+    import torch
+    s = system
+    n1, n2, n3 = s.grid
+    total = n1 * n2 * n3
+    q = torch.from_numpy(s.qvecs).cuda()
+    mults = [torch.ones(s.n_g, dtype=torch.complex128, device="cuda")]
+    mults += [(1j * q[:, a]).to(torch.complex128) for a in range(3)]
+    mults.append((-(q * q).sum(1)).to(torch.complex128))
+    bins = torch.from_numpy(np.ravel_multi_index(tuple((s.miller % np.array(s.grid)).T), s.grid)).cuda()
+    coef = torch.from_numpy(s.coef).cuda()
+    n_col = s.n_orb * (2 if s.bloch else 1)
+    out = torch.empty((5, n1, n2, n3, n_col), dtype=torch.float64, device="cuda")
+    for t, m in enumerate(mults):
+        for o0 in range(0, s.n_orb, chunk):
+            nc = min(chunk, s.n_orb - o0)
+            spec = torch.zeros((nc, total), dtype=torch.complex128, device="cuda")
+            spec.index_add_(1, bins, coef[o0:o0 + nc] * m[None, :])
+            x = (torch.fft.ifftn(spec.view(nc, n1, n2, n3), dim=(1, 2, 3)) * total).permute(1, 2, 3, 0)
+            if s.bloch:
+                out[t, ..., 2 * o0:2 * (o0 + nc)] = torch.view_as_real(x.contiguous()).reshape(n1, n2, n3, 2 * nc)
+            else:
+                out[t, ..., o0:o0 + nc] = x.real
+    torch.cuda.synchronize()
+    return out
+
+
+def _host(t):
+    import numpy as np
+    return t.cpu().numpy().astype(np.complex128 if t.is_complex() else np.float64)
+
+
+def accuracy(wl, dtype, form, outs, n_sample=48, n_orb_ref=16):
     """Errors of the GPU outputs on a seeded sample of points and the first orbitals: against the
-    planewave sum (the spline's own approximation error) and, for FP32/BF16 tables, against the FP64
-    table's outputs on the same workload (the storage and arithmetic error of the form).  The FP64
-    form must be measured first; its agreement with the FP64 oracle is what the parity tests check."""
+    planewave sum (the representation's own approximation error) and, for FP32/BF16 tables,
+    against the FP64 table's outputs of the same representation `form` (the storage and arithmetic
+    error).  The FP64 form must be measured first; its agreement with the FP64 oracle is what the
+    parity tests check."""
     import numpy as np
     import torch
     rng = np.random.default_rng(1309)
@@ -152,11 +206,10 @@ def accuracy(wl, dtype, has_lap, outs, n_sample=48, n_orb_ref=16):
         x = wl.pos[torch.from_numpy(idx).cuda()].contiguous()
         cache["pw"] = planewave_vgl_gpu(wl.s, x, k)
     pwref = cache["pw"]
-    got = [outs[0].double().cpu().numpy()[idx, :k], outs[1].double().cpu().numpy()[idx, :, :k],
-           outs[2].double().cpu().numpy()[idx, :k]]
+    got = [_host(outs[0])[idx, :k], _host(outs[1])[idx, :, :k], _host(outs[2])[idx, :k]]
     if dtype == "f64":
-        cache[("f64", has_lap)] = got
-    f64 = cache.get(("f64", has_lap))
+        cache[("f64", form)] = got
+    f64 = cache.get(("f64", form))
     res = {}
     for j, (name, g, p) in enumerate(zip(("V", "grad", "lap"), got, pwref)):
         r = {"normwise_vs_planewave": normwise(g, p),
@@ -170,17 +223,20 @@ def accuracy(wl, dtype, has_lap, outs, n_sample=48, n_orb_ref=16):
 
 
 def planewave_vgl_gpu(system, x, k):
-    """Value, gradient and Laplacian of the first k planewave orbitals (Eq. pw_orbital) at the points
-    x (device, [n][3]), by direct summation over the G vectors in complex128 on the GPU: the exact
-    function the splines approximate.  Returns numpy arrays [n][k], [n][3][k], [n][k]."""
+    """Value, gradient and Laplacian of the first k planewave orbitals (Eq. pw_orbital; Bloch
+    orbitals sum over k+G) at the points x (device, [n][3]), by direct summation over the
+    planewaves in complex128 on the GPU: the exact function the representations approximate.
+    Returns numpy arrays [n][k], [n][3][k], [n][k] (complex for Bloch orbitals, else real)."""
     import torch
-    g = torch.from_numpy(system.gvecs).cuda()                       # [N_G][3]
+    q = torch.from_numpy(system.qvecs).cuda()                       # [N_G][3]
     c = torch.from_numpy(system.coef[:k]).cuda()                    # [k][N_G]
-    e = torch.exp(1j * (x @ g.t()))                                  # [n][N_G]
-    v = (e @ c.t().contiguous()).real
-    grad = torch.stack([(e @ (1j * g[:, a][None, :] * c).t().contiguous()).real for a in range(3)], 1)
-    lap = (e @ (-(g * g).sum(1)[None, :] * c).t().contiguous()).real
-    return v.cpu().numpy(), grad.cpu().numpy(), lap.cpu().numpy()
+    e = torch.exp(1j * (x @ q.t()))                                  # [n][N_G]
+    v = e @ c.t().contiguous()
+    grad = torch.stack([e @ (1j * q[:, a][None, :] * c).t().contiguous() for a in range(3)], 1)
+    lap = e @ (-(q * q).sum(1)[None, :] * c).t().contiguous()
+    if not system.bloch:
+        v, grad, lap = v.real, grad.real, lap.real
+    return _host(v), _host(grad), _host(lap)
 
 
 def cpu_baseline(wl, max_workers=16):
@@ -388,6 +444,38 @@ def smoothing_rows(wl2):
     return out
 
 
+def method_comparison_row(wl2, fields, k=16, n_sample=48):
+    """The paper's comparison of representations (Fig. 1) on the synthetic MgO-like orbitals: RMAE
+    against the planewave sum of the orbital and of direct approximations of its gradient and
+    Laplacian (five separate tables each) for Lagrange interpolation, interpolating B-splines and
+    smoothing B-splines (FP64 tables of the first k orbitals, n_sample seeded points)."""
+    import numpy as np
+    import torch
+    import paper_1309_6250_amd as P
+    s = wl2.s
+    sub = fields[..., :k].contiguous()
+    rng = np.random.default_rng(1309)
+    idx = np.sort(rng.choice(wl2.pos_host.shape[0], size=n_sample, replace=False))
+    x = wl2.pos[torch.from_numpy(idx).cuda()].contiguous()
+    ref = planewave_vgl_gpu(s, x, k)
+    miller = torch.from_numpy(s.miller.astype(np.int32)).cuda()
+    coef = torch.from_numpy(np.ascontiguousarray(s.coef[:k])).cuda()
+    rmae = lambda a, b: float(np.abs(a - b).mean() / np.abs(b).mean())
+    out = {"sample": f"{n_sample} points x first {k} orbitals, FP64 tables, five separate tables each"}
+    for name in ("lagrange", "interpolating_bspline", "smoothing_bspline"):
+        d = P.spline_desc_init(s.lattice, s.grid, k, "f64", has_lap=True, sep_grad=True,
+                               basis="lagrange" if name == "lagrange" else "bspline")
+        if name == "smoothing_bspline":
+            tab = P.spline_build_smoothing(d, miller, coef)
+        else:
+            tab = P.spline_build_tables(d, sub)
+        got = [_host(t) for t in P.spline_eval_vgl(d, tab, x)]
+        out[name] = {q: rmae(g, r) for q, g, r in zip(("rmae_V", "rmae_grad", "rmae_lap"), got, ref)}
+        del tab
+    del sub
+    return out
+
+
 def batched_row(steps, warmup):
     """48 uneven systems (orbitals 32-256, grids 24^3-64^3, 16-512 walkers x 64-256 electrons),
     FP32 tables built on the GPU, all VGL evaluations in one persistent launch replayed from a
@@ -440,7 +528,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--quick", action="store_true", help="headline only: no extra forms, rows or CPU baseline")
     ap.add_argument("--only", default=None,
-                    help="time only one form, e.g. c2-f32 or c2-bf16-lap (for profiling runs)")
+                    help="time only one form, e.g. c2-f32, c2-bf16-lap, c2-f32-sep-lagrange or c7-f64-bloch "
+                         "(for profiling runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tile", default=None, help="with --only: fixed tile 'G,OPL' instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -466,11 +555,13 @@ def main():
     if args.only:
         key, dtype, *rest = args.only.split("-")
         lap = bool(rest and rest[0] == "lap")
+        sep = rest[1] if rest and rest[0] == "sep" else None
         wl = Workload(int(key[1:]), lap=lap)
         _gpu_ready()
         wl.upload()
+        fields = grid_fields_gpu(wl.s) if sep else None
         tile = None if args.tile is None else tuple(int(x) for x in args.tile.split(","))
-        rec, *_ = run_form(wl, dtype, lap, args.steps, args.warmup, tile=tile)
+        rec, *_ = run_form(wl, dtype, lap or bool(sep), args.steps, args.warmup, tile=tile, sep=sep, fields=fields)
         print(json.dumps({"only": args.only, **rec}), flush=True)
         return
 
@@ -485,7 +576,7 @@ def main():
     head, d1, t1, o1 = run_form(wl1, "f64", False, args.steps, args.warmup)
     log(f"headline c1-f64: {head['ms_per_sweep']:.3f} ms, {head['evals_per_s']:.3e} evals/s, "
         f"{head['alg_GBps']:.0f} GB/s algorithmic")
-    head["accuracy"] = accuracy(wl1, "f64", False, o1)
+    head["accuracy"] = accuracy(wl1, "f64", "derivative", o1)
     n_pts = int(wl1.pos.shape[0])
     per_launch = head["alg_bytes_per_sweep"]
     traffic = traffic_for("c1-f64")
@@ -501,7 +592,7 @@ def main():
     if not args.quick:
         for dtype in ("f32", "bf16"):
             rec, d, t, o = run_form(wl1, dtype, False, args.steps, args.warmup)
-            rec["accuracy"] = accuracy(wl1, dtype, False, o)
+            rec["accuracy"] = accuracy(wl1, dtype, "derivative", o)
             rec["speedup_vs_f64"] = rec["evals_per_s"] / head["evals_per_s"]
             forms[f"c1-{dtype}"] = rec
             log(f"c1-{dtype}: {rec['evals_per_s']:.3e} evals/s, {rec['alg_GBps']:.0f} GB/s")
@@ -525,7 +616,7 @@ def main():
         for lap in (False, True):
             for dtype in ("f64", "f32", "bf16"):
                 rec, d, t, o = run_form(wl2, dtype, lap, args.steps, args.warmup)
-                rec["accuracy"] = accuracy(wl2, dtype, lap, o)
+                rec["accuracy"] = accuracy(wl2, dtype, "separate_lap" if lap else "derivative", o)
                 name = f"c2-{dtype}" + ("-lap" if lap else "")
                 if dtype == "f64":
                     f64_rate[lap] = rec["evals_per_s"]
@@ -536,6 +627,38 @@ def main():
                     f"({100 * rec['frac_hbm_peak']:.0f}% of HBM peak)")
                 del t, o
                 torch.cuda.empty_cache()
+        # the representations the paper compares, with direct approximations of the gradient and the
+        # Laplacian: five separate tables of B-spline coefficients or of Lagrange grid values
+        fields = grid_fields_gpu(wl2.s)
+        rows["method_comparison_mgo96"] = method_comparison_row(wl2, fields)
+        log("method comparison: " + ", ".join(f"{k}: lap {v['rmae_lap']:.2e}" for k, v in
+                                              rows["method_comparison_mgo96"].items() if isinstance(v, dict)))
+        for basis in ("bspline", "lagrange"):
+            for dtype in ("f64", "f32"):
+                rec, d, t, o = run_form(wl2, dtype, True, args.steps, args.warmup, sep=basis, fields=fields)
+                name = f"c2-{dtype}-sep-{basis}"
+                rec["accuracy"] = accuracy(wl2, dtype, "separate_" + basis, o)
+                rec["traffic"] = traffic_for(name)
+                forms[name] = rec
+                log(f"{name}: {rec['evals_per_s']:.3e} evals/s, {rec['alg_GBps']:.0f} GB/s "
+                    f"({100 * rec['frac_hbm_peak']:.0f}% of HBM peak)")
+                del t, o
+                torch.cuda.empty_cache()
+        del fields, wl2
+        torch.cuda.empty_cache()
+        # Bloch orbitals at a twist: complex orbitals, twice the columns of config 1
+        wl7 = Workload(7).upload()
+        for dtype in ("f64", "f32"):
+            rec, d, t, o = run_form(wl7, dtype, False, args.steps, args.warmup)
+            name = f"c7-{dtype}-bloch"
+            rec["accuracy"] = accuracy(wl7, dtype, "bloch", o)
+            rec["traffic"] = traffic_for(name)
+            forms[name] = rec
+            log(f"{name}: {rec['evals_per_s']:.3e} evals/s, {rec['alg_GBps']:.0f} GB/s "
+                f"({100 * rec['frac_hbm_peak']:.0f}% of HBM peak)")
+            del t, o
+        del wl7
+        torch.cuda.empty_cache()
 
     ms = head["ms_per_sweep"]
     line = {

@@ -27,7 +27,17 @@
  *     columns, so crystal coordinates are s = a^-1 r with a = lattice^T.
  *   - Coefficient table layout: [N1][N2][N3][o_pad], orbital index innermost and
  *     zero-padded to o_pad, in the storage dtype.  With has_lap, a second table of
- *     the same shape (the separate Laplacian spline) follows the first.
+ *     the same shape (the separate Laplacian spline) follows the first; with
+ *     sep_grad, five tables follow one another (see spl_desc).
+ *   - Representations (App. A): cubic B-splines (default) or cubic Lagrange
+ *     interpolation of grid values; the gradient and the Laplacian are either
+ *     derivatives of the orbital's interpolant or interpolants of their own grid
+ *     values (the paper's "separate" or direct approximations, Sec. III A, Fig. 1).
+ *   - Bloch orbitals (Sec. I): phi(r) = exp(i k.r) u(r) with u periodic and complex.
+ *     Each orbital occupies two adjacent real columns (Re u, Im u) of every table,
+ *     and every output is complex, stored as (re, im) pairs: v [n_pts][n_orb][2],
+ *     grad [n_pts][3][n_orb][2], lap [n_pts][n_orb][2].  The phase uses the
+ *     unfolded Cartesian position.
  *   - Basis normalization: the standard cubic B-spline (values 1/6, 2/3, 1/6 at
  *     the knots; the 64 weights of a point sum to 1).  The paper's basis is this
  *     one times 3/2 per axis (its constant C = 3/2, App. A); the spline function
@@ -63,6 +73,9 @@ enum {
 /* flags of spline_eval_vgl_backward */
 enum { SPL_DETERMINISTIC = 1 };
 
+/* basis of the interpolant (spl_desc.basis) */
+enum { SPL_BSPLINE = 0, SPL_LAGRANGE = 1 };
+
 /*
  * Descriptor of one coefficient table.  The caller fills the first block and
  * calls spline_desc_init, which validates it and fills the derived block.
@@ -75,6 +88,14 @@ typedef struct spl_desc {
   int32_t n_orb;          /* number of orbitals (>= 1) */
   int32_t dtype;          /* SPL_F64 / SPL_F32 / SPL_BF16 */
   int32_t has_lap;        /* 1: a separate Laplacian spline follows the orbital table (Sec. III A) */
+  int32_t basis;          /* SPL_BSPLINE (App. A, B-splines) or SPL_LAGRANGE (App. A, Lagrange
+                             interpolation: the table holds grid values; needs sep_grad, since the
+                             Lagrange interpolant has no continuous derivatives) */
+  int32_t sep_grad;       /* 1: separate gradient tables too (needs has_lap): five tables in the order
+                             orbital, d/dx, d/dy, d/dz (Cartesian), Laplacian, each read by value */
+  int32_t bloch;          /* 1: Bloch orbitals exp(i k.r) u(r) (Sec. I); n_orb counts complex orbitals */
+  int32_t reserved;       /* must be 0 */
+  double  kvec[3];        /* k, Cartesian, 1/bohr; must be all zero unless bloch */
   /* --- derived by spline_desc_init --- */
   double  ainv[9];        /* a^-1 (row-major): s = ainv . r */
   double  jac[9];         /* J[i][c] = N_i ainv[i][c] = d u_i / d r_c, u = grid units */
@@ -82,16 +103,20 @@ typedef struct spl_desc {
   int32_t o_pad;          /* orbital stride of a table row: n_orb rounded up to 16 bytes of storage */
   int32_t elem_bytes;     /* 8 / 4 / 2 */
   int64_t table_elems;    /* N1*N2*N3*o_pad: elements of ONE table */
-  int64_t table_bytes;    /* bytes of the full table buffer: (1 + has_lap) * table_elems * elem_bytes */
-  int64_t work_bytes;     /* bytes of the FP64 workspace spline_build needs: N1*N2*N3*n_orb*8 */
-  int64_t gtable_bytes;   /* bytes of a coefficient-gradient buffer: (1 + has_lap) * table_elems * (8 or 4) */
+  int64_t table_bytes;    /* bytes of the full table buffer: n_tables * table_elems * elem_bytes */
+  int64_t work_bytes;     /* bytes of the FP64 workspace spline_build needs: N1*N2*N3*n_col*8 */
+  int64_t gtable_bytes;   /* bytes of a coefficient-gradient buffer: n_tables * table_elems * (8 or 4) */
+  int32_t n_tables;       /* 1 + has_lap + 3 sep_grad */
+  int32_t n_col;          /* real columns of a table row: n_orb, or 2 n_orb (Re u, Im u) with bloch */
 } spl_desc;
 
 /*
  * Validate the caller block of *d and fill the derived block.  Host only,
  * enqueues nothing.  Errors: d == NULL, n_orb < 1, non-finite or singular lattice
  * -> SPL_EINVAL; any N_i outside [4, 1024] -> SPL_EGRID; unknown dtype ->
- * SPL_EDTYPE; has_lap not 0/1 -> SPL_EINVAL.  N_i >= 4 keeps the four rows of a
+ * SPL_EDTYPE; has_lap, sep_grad or bloch not 0/1, unknown basis, reserved != 0,
+ * sep_grad without has_lap, SPL_LAGRANGE without sep_grad, a non-finite kvec, or a
+ * nonzero kvec without bloch -> SPL_EINVAL.  N_i >= 4 keeps the four rows of a
  * point's block distinct along each axis.
  */
 int spline_desc_init(spl_desc* d);
@@ -102,15 +127,31 @@ int spline_desc_init(spl_desc* d);
  * B_d periodic tridiagonal with corner elements (rows 1/6, 4/6, 1/6); solved in
  * three stages, one axis at a time, in FP64, then rounded once (to nearest even,
  * via FP32 for BF16) into the storage dtype.
- *   grid_vals  device, FP64 [N1][N2][N3][n_orb]: orbital values at r = a (i/N1, j/N2, k/N3)
+ *   grid_vals  device, FP64 [N1][N2][N3][n_col]: orbital values at r = a (i/N1, j/N2, k/N3)
+ *              (with bloch: (Re u, Im u) per orbital)
  *   lap_vals   device, FP64, same shape: grid values of the planewave Laplacian
- *              (the input of the separate Laplacian spline); must be NULL iff !has_lap
+ *              (the input of the separate Laplacian spline; with bloch its periodic part
+ *              exp(-i k.r) lap phi); must be NULL iff !has_lap
  *   table      device, d->table_bytes, written completely (padding zeroed)
  *   work       device, d->work_bytes of scratch FP64, contents undefined afterwards
  * grid_vals and lap_vals are not modified.  None of the buffers may overlap.
+ * For SPL_LAGRANGE or sep_grad descriptors use spline_build_tables (-> SPL_EINVAL here).
  */
 int spline_build(const spl_desc* d, const double* grid_vals, const double* lap_vals,
                  void* table, void* work, void* stream);
+
+/*
+ * All n_tables tables of a descriptor from their grid values, stacked:
+ *   vals   device, FP64 [n_tables][N1][N2][N3][n_col]: the orbital, then (sep_grad) the
+ *          Cartesian gradient components x, y, z, then (has_lap) the Laplacian, each sampled
+ *          at r = a (i/N1, j/N2, k/N3) (with bloch: periodic parts, (re, im) per orbital)
+ *   table  device, d->table_bytes, written completely (padding zeroed)
+ *   work   device, d->work_bytes of scratch FP64 (unused for SPL_LAGRANGE, may be NULL then)
+ * SPL_BSPLINE tables are interpolating coefficients, solved as in spline_build; SPL_LAGRANGE
+ * tables are the grid values themselves, rounded once into the storage dtype (App. A,
+ * Eq. lagrangeinterpolation3).  vals is not modified.
+ */
+int spline_build_tables(const spl_desc* d, const double* vals, void* table, void* work, void* stream);
 
 /*
  * Smoothing (Fourier-matched) B-spline coefficients from planewave coefficients (App. A,
@@ -122,11 +163,15 @@ int spline_build(const spl_desc* d, const double* grid_vals, const double* lap_v
  *   n_g     number of planewaves
  *   miller  device, int32 [n_g][3]: Miller indices n of G = 2 pi lattice^-1 n
  *   coef    device, FP64 [n_orb][n_g][2]: complex coefficients (re, im), conjugate-symmetric
- *           in G for real orbitals (the real part of the sum is stored)
+ *           in G for real orbitals (the real part of the sum is stored); with bloch, the
+ *           coefficients of u (no symmetry; real and imaginary parts are stored)
  *   table   device, d->table_bytes, written completely (padding zeroed)
  *   work    device, spline_smoothing_work_bytes() bytes, 256-byte aligned, scratch
- * The grid must give every G its own Fourier bin (N_i > 2 max |n_i|); planewaves that share a
- * bin are added.  Computed in FP64 by separable inverse DFTs, rounded once into the storage dtype.
+ * The tables after the first hold the smoothing splines of the gradient's periodic parts,
+ * coefficients i (k+G)_c c_G (sep_grad), and of the Laplacian's, -|k+G|^2 c_G (has_lap).
+ * SPL_LAGRANGE descriptors -> SPL_EINVAL.  The grid must give every G its own Fourier bin
+ * (N_i > 2 max |n_i|); planewaves that share a bin are added.  Computed in FP64 by separable
+ * inverse DFTs, rounded once into the storage dtype.
  */
 int spline_build_smoothing(const spl_desc* d, int64_t n_g, const int32_t* miller, const double* coef,
                            void* table, void* work, void* stream);
@@ -139,8 +184,9 @@ int spline_smoothing_work_bytes(const spl_desc* d, int64_t* bytes);
  * Orbital values phi_o(r_p) (App. A, Eq. b-splineapproximation) at n_pts points.
  *   table  device, as written by spline_build
  *   pos    device, FP64 [n_pts][3]
- *   v      device, [n_pts][n_orb] (FP64 for SPL_F64 tables, else FP32)
- * n_pts == 0 is a no-op.
+ *   v      device, [n_pts][n_col] (FP64 for SPL_F64 tables, else FP32)
+ * SPL_LAGRANGE tables use the Lagrange weights (App. A, Eq. lagrangeinterpolation3); Bloch
+ * orbitals are multiplied by exp(i k.r).  n_pts == 0 is a no-op.
  */
 int spline_eval_v(const spl_desc* d, const void* table, int64_t n_pts, const double* pos,
                   void* v, void* stream);
@@ -149,10 +195,13 @@ int spline_eval_v(const spl_desc* d, const void* table, int64_t n_pts, const dou
  * Values, Cartesian gradients and Laplacians (VGL) of every orbital at n_pts points.
  * Gradient: grad phi = J^T grad_t phi; Laplacian: sum_ij M_ij d2 phi / dt_i dt_j with
  * the full metric M (off-diagonal terms for non-orthogonal cells), or, with has_lap,
- * the value of the separate Laplacian spline.
- *   v     device, [n_pts][n_orb]
- *   grad  device, [n_pts][3][n_orb]
- *   lap   device, [n_pts][n_orb]
+ * the value of the separate Laplacian spline; with sep_grad every output is the value of
+ * its own table.  Bloch orbitals (phase e = exp(i k.r)): V = e u, grad = e (grad u + i k u),
+ * lap = e (lap u + 2 i k.grad u - |k|^2 u), or e w with a separate Laplacian table of the
+ * periodic part w, and e g_c for separate gradient tables.
+ *   v     device, [n_pts][n_col]
+ *   grad  device, [n_pts][3][n_col]
+ *   lap   device, [n_pts][n_col]
  * (FP64 for SPL_F64 tables, else FP32.)  All three are required.
  */
 int spline_eval_vgl(const spl_desc* d, const void* table, int64_t n_pts, const double* pos,
@@ -162,8 +211,9 @@ int spline_eval_vgl(const spl_desc* d, const void* table, int64_t n_pts, const d
  * Same as spline_eval_vgl with an explicit launch shape: tile[0] = lanes that
  * share one point (2, 4, ..., 256), tile[1] = consecutive orbitals per lane (one
  * vector load per table row): 1 or 2 for SPL_F64, 1, 2 or 4 for SPL_F32, 2, 4 or 8
- * for SPL_BF16.  Used by the autotuner and tests; results are identical for every
- * valid tile.  Invalid tile -> SPL_EINVAL.
+ * for SPL_BF16; with bloch only the even choices (a lane holds whole (re, im) pairs).
+ * Used by the autotuner and tests; results are identical for every valid tile.
+ * Invalid tile -> SPL_EINVAL.
  */
 int spline_eval_vgl_tile(const spl_desc* d, const void* table, int64_t n_pts, const double* pos,
                          void* v, void* grad, void* lap, const int32_t tile[2], void* stream);
@@ -186,7 +236,8 @@ int spline_eval_vgl_tile(const spl_desc* d, const void* table, int64_t n_pts, co
  *                    spline_backward_work_bytes() bytes, contents undefined afterwards; may be
  *                    NULL (0 bytes) without that flag
  * The position gradient is deterministic either way.  Points with non-finite coordinates
- * contribute nothing to gtable and get NaN in gpos.
+ * contribute nothing to gtable and get NaN in gpos.  Descriptors with basis, sep_grad or
+ * bloch set -> SPL_EUNSUPPORTED (the adjoint covers the real B-spline forms).
  */
 int spline_eval_vgl_backward(const spl_desc* d, const void* table, int64_t n_pts, const double* pos,
                              const void* gv, const void* ggrad, const void* glap,
@@ -216,7 +267,8 @@ typedef struct spl_item {
  * Build a plan: copies per-item parameters and the work list of (item, point tile) pairs
  * to device memory the plan owns (this call allocates, once, and synchronizes `stream`).
  * Items are reordered internally by decreasing work per tile; outputs go to each item's
- * own buffers.  All items must share dtype and has_lap.  tile: NULL = the tuned (or
+ * own buffers.  All items must share dtype and has_lap, and be real B-spline tables
+ * without sep_grad (others -> SPL_EUNSUPPORTED).  tile: NULL = the tuned (or
  * default) shape of the heaviest item, else as in spline_eval_vgl_tile with tile[0] in
  * 8..256.  On success *plan is set.  The item buffers must outlive the plan.
  * Errors: any item failing the checks of spline_eval_vgl -> that code, prefixed with the

@@ -17,14 +17,29 @@ from .bspline import OFFSETS
 from .evaluate import reduced_coordinates, _block
 
 
-def weights(t):
-    """ell_l(t) for l = -1..2, from the product formula.  t: array [...]; returns [..., 4]."""
+def weights(t, order=0):
+    """ell_l(t) (order 0) or d ell_l / dt (order 1) for l = -1..2, from the product formula
+    (the derivative by the product rule: one factor differentiated at a time).
+    t: array [...]; returns [..., 4]."""
     t = np.asarray(t, dtype=np.float64)
-    out = np.ones(t.shape + (4,))
+    out = np.zeros(t.shape + (4,))
     for a, l in enumerate(OFFSETS):
-        for j in OFFSETS:
-            if j != l:
-                out[..., a] *= (t - j) / (l - j)
+        others = [j for j in OFFSETS if j != l]
+        denom = np.prod([float(l - j) for j in others])
+        if order == 0:
+            term = np.ones_like(t)
+            for j in others:
+                term = term * (t - j)
+            out[..., a] = term / denom
+        elif order == 1:
+            for skip in others:
+                term = np.ones_like(t)
+                for j in others:
+                    if j != skip:
+                        term = term * (t - j)
+                out[..., a] += term / denom
+        else:
+            raise ValueError("order 0 or 1")
     return out
 
 
@@ -43,3 +58,27 @@ def eval_values(vals, lattice, pos, chunk=256):
         out[sl] = np.einsum("pl,pm,pn,plmno->po", wx, wy, wz, _block(vals, i0[sl], grid))
     out[~ok] = np.nan
     return out
+
+
+def eval_abs_bound(vals, lattice, pos, du=None, chunk=256):
+    """Rounding-error scales of the interpolant at each point: sum |ell_l ell_m ell_n| |f| (for the
+    accumulation error) and, with du [P,3], sum_i du_i sum |d_i(ell ell ell)| |f| (how far a
+    perturbation du of the grid coordinates moves the value).  Returns (acc [P,O], coord [P,O])."""
+    vals = np.abs(np.asarray(vals, dtype=np.float64))
+    grid = vals.shape[:3]
+    i0, t, ok = reduced_coordinates(lattice, grid, pos)
+    n_pts, n_orb = i0.shape[0], vals.shape[3]
+    acc = np.zeros((n_pts, n_orb))
+    coord = np.zeros((n_pts, n_orb))
+    for p0 in range(0, n_pts, chunk):
+        sl = slice(p0, p0 + chunk)
+        w = [np.abs(weights(t[sl, d])) for d in range(3)]
+        dw = [np.abs(weights(t[sl, d], 1)) for d in range(3)]
+        blk = _block(vals, i0[sl], grid)
+        acc[sl] = np.einsum("pl,pm,pn,plmno->po", w[0], w[1], w[2], blk)
+        if du is not None:
+            d = np.asarray(du, dtype=np.float64)[sl]
+            coord[sl] = (d[:, 0, None] * np.einsum("pl,pm,pn,plmno->po", dw[0], w[1], w[2], blk)
+                         + d[:, 1, None] * np.einsum("pl,pm,pn,plmno->po", w[0], dw[1], w[2], blk)
+                         + d[:, 2, None] * np.einsum("pl,pm,pn,plmno->po", w[0], w[1], dw[2], blk))
+    return acc, coord

@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(HERE, "libpwspline.so")
 SPL_F64, SPL_F32, SPL_BF16 = 0, 1, 2
 SPL_OK, SPL_EINVAL, SPL_EGRID, SPL_EDTYPE, SPL_ENOMEM, SPL_EHIP, SPL_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 SPL_DETERMINISTIC = 1
+SPL_BSPLINE, SPL_LAGRANGE = 0, 1
 
 ERROR_NAMES = {
     SPL_EINVAL: "SPL_EINVAL", SPL_EGRID: "SPL_EGRID", SPL_EDTYPE: "SPL_EDTYPE", SPL_ENOMEM: "SPL_ENOMEM",
@@ -22,7 +23,7 @@ EXPORTS = (
     "spline_eval_vgl_backward", "spline_batch_plan_create", "spline_batch_eval_vgl",
     "spline_batch_graph_launch", "spline_batch_autotune", "spline_batch_plan_destroy", "spline_batch_plan_info", "spline_autotune",
     "spline_tile_for", "spline_last_error", "spline_version", "spline_backward_work_bytes",
-    "spline_build_smoothing", "spline_smoothing_work_bytes",
+    "spline_build_smoothing", "spline_smoothing_work_bytes", "spline_build_tables",
 )
 
 
@@ -33,6 +34,11 @@ class SplDesc(ctypes.Structure):
         ("n_orb", ctypes.c_int32),
         ("dtype", ctypes.c_int32),
         ("has_lap", ctypes.c_int32),
+        ("basis", ctypes.c_int32),
+        ("sep_grad", ctypes.c_int32),
+        ("bloch", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("kvec", ctypes.c_double * 3),
         ("ainv", ctypes.c_double * 9),
         ("jac", ctypes.c_double * 9),
         ("metric", ctypes.c_double * 6),
@@ -42,6 +48,8 @@ class SplDesc(ctypes.Structure):
         ("table_bytes", ctypes.c_int64),
         ("work_bytes", ctypes.c_int64),
         ("gtable_bytes", ctypes.c_int64),
+        ("n_tables", ctypes.c_int32),
+        ("n_col", ctypes.c_int32),
     ]
 
 
@@ -80,6 +88,7 @@ def lib():
         sig = {
             "spline_desc_init": (ctypes.c_int, [pd]),
             "spline_build": (ctypes.c_int, [pd, vp, vp, vp, vp, vp]),
+            "spline_build_tables": (ctypes.c_int, [pd, vp, vp, vp, vp]),
             "spline_eval_v": (ctypes.c_int, [pd, vp, i64, vp, vp, vp]),
             "spline_eval_vgl": (ctypes.c_int, [pd, vp, i64, vp, vp, vp, vp, vp]),
             "spline_eval_vgl_tile": (ctypes.c_int, [pd, vp, i64, vp, vp, vp, vp, i32p, vp]),

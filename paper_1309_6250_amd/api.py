@@ -8,9 +8,10 @@ import ctypes
 
 import torch
 
-from ._lib import (SplDesc, SplItem, check, lib, SPL_F64, SPL_F32, SPL_BF16)
+from ._lib import (SplDesc, SplItem, check, lib, SPL_F64, SPL_F32, SPL_BF16, SPL_BSPLINE, SPL_LAGRANGE)
 
 DTYPES = {"f64": SPL_F64, "f32": SPL_F32, "bf16": SPL_BF16}
+BASES = {"bspline": SPL_BSPLINE, "lagrange": SPL_LAGRANGE}
 STORE_TORCH = {SPL_F64: torch.float64, SPL_F32: torch.float32, SPL_BF16: torch.bfloat16}
 OUT_TORCH = {SPL_F64: torch.float64, SPL_F32: torch.float32, SPL_BF16: torch.float32}
 
@@ -46,8 +47,13 @@ def _need(t, name, dtype, numel=None, device=None):
         raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
 
 
-def spline_desc_init(lattice, grid, n_orb, dtype="f64", has_lap=False):
-    """Validated descriptor (ctypes struct) of one coefficient table."""
+def spline_desc_init(lattice, grid, n_orb, dtype="f64", has_lap=False, basis="bspline", sep_grad=False, kvec=None):
+    """Validated descriptor (ctypes struct) of one coefficient table set.
+
+    basis: "bspline" or "lagrange" (the latter needs sep_grad and has_lap); sep_grad: five
+    tables (orbital, gradient x/y/z, Laplacian) read by value; kvec: crystal momentum (1/bohr)
+    of Bloch orbitals exp(i k.r) u(r), whose n_orb complex orbitals take two columns each.
+    """
     d = SplDesc()
     lat = [float(x) for x in torch.as_tensor(lattice, dtype=torch.float64).reshape(-1).tolist()]
     if len(lat) != 9:
@@ -62,12 +68,30 @@ def spline_desc_init(lattice, grid, n_orb, dtype="f64", has_lap=False):
     d.n_orb = int(n_orb)
     d.dtype = _dtype_code(dtype)
     d.has_lap = 1 if has_lap else 0
+    d.basis = BASES[basis] if isinstance(basis, str) else int(basis)
+    d.sep_grad = 1 if sep_grad else 0
+    if kvec is not None:
+        k = [float(x) for x in torch.as_tensor(kvec, dtype=torch.float64).reshape(-1).tolist()]
+        if len(k) != 3:
+            raise ValueError("kvec must have 3 entries")
+        d.bloch = 1
+        for i in range(3):
+            d.kvec[i] = k[i]
     check(lib().spline_desc_init(ctypes.byref(d)), "spline_desc_init")
     return d
 
 
 def table_shape(desc):
-    return (1 + desc.has_lap, desc.grid[0], desc.grid[1], desc.grid[2], desc.o_pad)
+    return (desc.n_tables, desc.grid[0], desc.grid[1], desc.grid[2], desc.o_pad)
+
+
+def _real_columns(desc, t, name):
+    """Bloch inputs may be given as complex tensors [..., n_orb]; the ABI takes (re, im) columns."""
+    if t is not None and t.is_complex():
+        if not desc.bloch:
+            raise TypeError(f"{name} is complex but the descriptor has no Bloch orbitals")
+        return torch.view_as_real(t.contiguous()).reshape(*t.shape[:-1], 2 * t.shape[-1])
+    return t
 
 
 def new_table(desc, device="cuda"):
@@ -79,19 +103,43 @@ def new_gtable(desc, device="cuda"):
 
 
 def spline_build(desc, grid_vals, lap_vals=None, table=None, work=None, stream=None):
-    """Interpolating coefficients from FP64 grid values [N1][N2][N3][n_orb] (device)."""
+    """Interpolating coefficients from FP64 grid values [N1][N2][N3][n_orb] (device; complex128
+    or (re, im) columns for Bloch orbitals)."""
     pts = desc.grid[0] * desc.grid[1] * desc.grid[2]
-    _need(grid_vals, "grid_vals", torch.float64, pts * desc.n_orb)
+    grid_vals = _real_columns(desc, grid_vals, "grid_vals")
+    lap_vals = _real_columns(desc, lap_vals, "lap_vals")
+    _need(grid_vals, "grid_vals", torch.float64, pts * desc.n_col)
     if lap_vals is not None:
-        _need(lap_vals, "lap_vals", torch.float64, pts * desc.n_orb)
+        _need(lap_vals, "lap_vals", torch.float64, pts * desc.n_col)
     if table is None:
         table = new_table(desc, grid_vals.device)
-    _need(table, "table", STORE_TORCH[desc.dtype], desc.table_elems * (1 + desc.has_lap))
+    _need(table, "table", STORE_TORCH[desc.dtype], desc.table_elems * desc.n_tables)
     if work is None:
-        work = torch.empty(pts * desc.n_orb, dtype=torch.float64, device=grid_vals.device)
-    _need(work, "work", torch.float64, pts * desc.n_orb)
+        work = torch.empty(pts * desc.n_col, dtype=torch.float64, device=grid_vals.device)
+    _need(work, "work", torch.float64, pts * desc.n_col)
     check(lib().spline_build(ctypes.byref(desc), _ptr(grid_vals), _ptr(lap_vals), _ptr(table), _ptr(work),
                              _stream(stream)), "spline_build")
+    return table
+
+
+def spline_build_tables(desc, vals, table=None, work=None, stream=None):
+    """All tables of a descriptor from stacked FP64 grid values [n_tables][N1][N2][N3][n_orb]
+    (orbital, gradient x/y/z with sep_grad, Laplacian with has_lap; device; complex128 or
+    (re, im) columns for Bloch orbitals).  A list of per-table tensors is stacked first."""
+    if isinstance(vals, (list, tuple)):
+        vals = torch.stack(list(vals))
+    vals = _real_columns(desc, vals, "vals")
+    pts = desc.grid[0] * desc.grid[1] * desc.grid[2]
+    _need(vals, "vals", torch.float64, desc.n_tables * pts * desc.n_col)
+    if table is None:
+        table = new_table(desc, vals.device)
+    _need(table, "table", STORE_TORCH[desc.dtype], desc.table_elems * desc.n_tables)
+    if work is None and desc.basis == SPL_BSPLINE:
+        work = torch.empty(pts * desc.n_col, dtype=torch.float64, device=vals.device)
+    if work is not None:
+        _need(work, "work", torch.float64, pts * desc.n_col)
+    check(lib().spline_build_tables(ctypes.byref(desc), _ptr(vals), _ptr(table), _ptr(work), _stream(stream)),
+          "spline_build_tables")
     return table
 
 
@@ -113,7 +161,7 @@ def spline_build_smoothing(desc, miller, coef, table=None, work=None, stream=Non
         raise ValueError("miller must be [n_g, 3] and coef [n_orb, n_g]")
     if table is None:
         table = new_table(desc, coef.device)
-    _need(table, "table", STORE_TORCH[desc.dtype], desc.table_elems * (1 + desc.has_lap))
+    _need(table, "table", STORE_TORCH[desc.dtype], desc.table_elems * desc.n_tables)
     nbytes = spline_smoothing_work_bytes(desc)
     if work is None:
         work = torch.empty(nbytes, dtype=torch.uint8, device=coef.device)
@@ -125,23 +173,33 @@ def spline_build_smoothing(desc, miller, coef, table=None, work=None, stream=Non
 
 
 def _outputs(desc, n_pts, device, v, grad, lap, values_only=False):
+    """Real output buffers [.][n_col] (Bloch outputs given as complex tensors are viewed as
+    (re, im) columns)."""
     od = OUT_TORCH[desc.dtype]
+    v, grad, lap = (_real_columns(desc, t, n) for t, n in ((v, "v"), (grad, "grad"), (lap, "lap")))
     if v is None:
-        v = torch.empty((n_pts, desc.n_orb), dtype=od, device=device)
-    _need(v, "v", od, n_pts * desc.n_orb)
+        v = torch.empty((n_pts, desc.n_col), dtype=od, device=device)
+    _need(v, "v", od, n_pts * desc.n_col)
     if values_only:
         return v, None, None
     if grad is None:
-        grad = torch.empty((n_pts, 3, desc.n_orb), dtype=od, device=device)
+        grad = torch.empty((n_pts, 3, desc.n_col), dtype=od, device=device)
     if lap is None:
-        lap = torch.empty((n_pts, desc.n_orb), dtype=od, device=device)
-    _need(grad, "grad", od, 3 * n_pts * desc.n_orb)
-    _need(lap, "lap", od, n_pts * desc.n_orb)
+        lap = torch.empty((n_pts, desc.n_col), dtype=od, device=device)
+    _need(grad, "grad", od, 3 * n_pts * desc.n_col)
+    _need(lap, "lap", od, n_pts * desc.n_col)
     return v, grad, lap
 
 
+def _as_complex(desc, t):
+    """Bloch outputs as complex tensors [..., n_orb] viewing the (re, im) columns."""
+    if t is None or not desc.bloch:
+        return t
+    return torch.view_as_complex(t.view(*t.shape[:-1], desc.n_orb, 2))
+
+
 def _check_inputs(desc, table, pos):
-    _need(table, "table", STORE_TORCH[desc.dtype], desc.table_elems * (1 + desc.has_lap))
+    _need(table, "table", STORE_TORCH[desc.dtype], desc.table_elems * desc.n_tables)
     _need(pos, "pos", torch.float64)
     if pos.dim() != 2 or pos.shape[1] != 3:
         raise ValueError("pos must be [n_pts, 3]")
@@ -153,7 +211,7 @@ def spline_eval_v(desc, table, pos, v=None, stream=None):
     v, _, _ = _outputs(desc, n, pos.device, v, None, None, values_only=True)
     check(lib().spline_eval_v(ctypes.byref(desc), _ptr(table), n, _ptr(pos), _ptr(v), _stream(stream)),
           "spline_eval_v")
-    return v
+    return _as_complex(desc, v)
 
 
 def spline_eval_vgl(desc, table, pos, v=None, grad=None, lap=None, stream=None, tile=None):
@@ -166,7 +224,7 @@ def spline_eval_vgl(desc, table, pos, v=None, grad=None, lap=None, stream=None, 
         t = (ctypes.c_int32 * 2)(int(tile[0]), int(tile[1]))
         check(lib().spline_eval_vgl_tile(ctypes.byref(desc), _ptr(table), n, _ptr(pos), _ptr(v), _ptr(grad),
                                          _ptr(lap), t, _stream(stream)), "spline_eval_vgl_tile")
-    return v, grad, lap
+    return _as_complex(desc, v), _as_complex(desc, grad), _as_complex(desc, lap)
 
 
 def spline_eval_vgl_backward(desc, table, pos, gv=None, ggrad=None, glap=None, gtable=None, gpos=None,
@@ -181,7 +239,7 @@ def spline_eval_vgl_backward(desc, table, pos, gv=None, ggrad=None, glap=None, g
     if want_table and gtable is None:
         gtable = new_gtable(desc, pos.device)
     if gtable is not None:
-        _need(gtable, "gtable", od, desc.table_elems * (1 + desc.has_lap))
+        _need(gtable, "gtable", od, desc.table_elems * desc.n_tables)
     if want_pos and gpos is None:
         gpos = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
     if gpos is not None:

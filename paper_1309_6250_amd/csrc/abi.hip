@@ -56,7 +56,19 @@ static int derive(spl_desc* d) {
     if (d->grid[i] < 4 || d->grid[i] > 1024)
       return fail(SPL_EGRID, "grid[%d] = %d outside [4, 1024]", i, d->grid[i]);
   if (d->n_orb < 1) return fail(SPL_EINVAL, "n_orb = %d < 1", d->n_orb);
+  if (d->n_orb > (1 << 29)) return fail(SPL_EINVAL, "n_orb = %d too large", d->n_orb);
   if (d->has_lap != 0 && d->has_lap != 1) return fail(SPL_EINVAL, "has_lap must be 0 or 1");
+  if (d->sep_grad != 0 && d->sep_grad != 1) return fail(SPL_EINVAL, "sep_grad must be 0 or 1");
+  if (d->bloch != 0 && d->bloch != 1) return fail(SPL_EINVAL, "bloch must be 0 or 1");
+  if (d->basis != SPL_BSPLINE && d->basis != SPL_LAGRANGE) return fail(SPL_EINVAL, "unknown basis %d", d->basis);
+  if (d->reserved != 0) return fail(SPL_EINVAL, "reserved must be 0");
+  if (d->sep_grad && !d->has_lap) return fail(SPL_EINVAL, "sep_grad needs has_lap (five tables)");
+  if (d->basis == SPL_LAGRANGE && !d->sep_grad)
+    return fail(SPL_EINVAL, "Lagrange tables have no continuous derivatives: set sep_grad and has_lap");
+  for (int c = 0; c < 3; ++c) {
+    if (!isfinite(d->kvec[c])) return fail(SPL_EINVAL, "kvec has a non-finite entry");
+    if (!d->bloch && d->kvec[c] != 0.0) return fail(SPL_EINVAL, "kvec must be zero unless bloch = 1");
+  }
   for (int i = 0; i < 9; ++i)
     if (!isfinite(d->lattice[i])) return fail(SPL_EINVAL, "lattice has a non-finite entry");
   // a = lattice^T (columns = lattice vectors); ainv = a^-1 = (lattice^-1)^T
@@ -88,13 +100,15 @@ static int derive(spl_desc* d) {
   d->metric[0] = m[0]; d->metric[1] = m[4]; d->metric[2] = m[8];
   d->metric[3] = m[1]; d->metric[4] = m[2]; d->metric[5] = m[5];
   d->elem_bytes = elem_bytes_of(d->dtype);
+  d->n_col = d->n_orb * (1 + d->bloch);
+  d->n_tables = 1 + d->has_lap + 3 * d->sep_grad;
   const int per16 = 16 / d->elem_bytes;
-  d->o_pad = (d->n_orb + per16 - 1) / per16 * per16;
+  d->o_pad = (d->n_col + per16 - 1) / per16 * per16;
   const int64_t pts = (int64_t)d->grid[0] * d->grid[1] * d->grid[2];
   d->table_elems = pts * d->o_pad;
-  d->table_bytes = (1 + d->has_lap) * d->table_elems * d->elem_bytes;
-  d->work_bytes = pts * d->n_orb * 8;
-  d->gtable_bytes = (1 + d->has_lap) * d->table_elems * (d->dtype == SPL_F64 ? 8 : 4);
+  d->table_bytes = d->n_tables * d->table_elems * d->elem_bytes;
+  d->work_bytes = pts * d->n_col * 8;
+  d->gtable_bytes = d->n_tables * d->table_elems * (d->dtype == SPL_F64 ? 8 : 4);
   return SPL_OK;
 }
 
@@ -104,7 +118,8 @@ int check_desc(const spl_desc* d) {
   const int rc = derive(&tmp);
   if (rc) return rc;
   if (tmp.o_pad != d->o_pad || tmp.table_elems != d->table_elems || tmp.table_bytes != d->table_bytes ||
-      tmp.elem_bytes != d->elem_bytes || memcmp(tmp.jac, d->jac, sizeof(tmp.jac)) != 0)
+      tmp.elem_bytes != d->elem_bytes || tmp.n_col != d->n_col || tmp.n_tables != d->n_tables ||
+      memcmp(tmp.jac, d->jac, sizeof(tmp.jac)) != 0)
     return fail(SPL_EINVAL, "descriptor not initialized by spline_desc_init (or modified since)");
   return SPL_OK;
 }
@@ -118,8 +133,8 @@ static bool g_tune_loaded = false;
 
 static std::string tune_key(const spl_desc* d) {
   char buf[128];
-  snprintf(buf, sizeof(buf), "v2:%d:%d:%d:%d:%d:%d", d->dtype, d->has_lap, d->o_pad, d->grid[0], d->grid[1],
-           d->grid[2]);
+  snprintf(buf, sizeof(buf), "v3:%d:%d:%d:%d:%d:%d:%d:%d:%d", d->dtype, d->has_lap, d->o_pad, d->grid[0],
+           d->grid[1], d->grid[2], d->basis, d->sep_grad, d->bloch);
   return buf;
 }
 
@@ -169,7 +184,7 @@ void tile_for(const spl_desc* d, int32_t tile[2]) {
   if (it != g_tune.end()) {
     tile[0] = it->second.first;
     tile[1] = it->second.second;
-    if (tile_valid(d->dtype, tile)) return;
+    if (tile_valid_for(d, tile)) return;
   }
   default_tile(d, tile);
 }
@@ -179,6 +194,7 @@ int launch_eval(const spl_desc* d, const void* table, int64_t n_pts, const doubl
 int launch_backward(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, const void* gv,
                     const void* ggrad, const void* glap, void* gtable, double* gpos, hipStream_t stream);
 int build_one(const spl_desc* d, const double* vals, void* table, double* work, hipStream_t stream);
+int cast_one(const spl_desc* d, const double* vals, void* table, hipStream_t stream);
 int sorted_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes);
 int64_t smoothing_work_bytes(const spl_desc* d);
 int build_smoothing(const spl_desc* d, int64_t n_g, const int32_t* miller, const double* coef, void* table,
@@ -215,7 +231,7 @@ using namespace pws;
 
 extern "C" {
 
-int spline_version(void) { return 10000; }
+int spline_version(void) { return 10100; }
 
 const char* spline_last_error(void) { return g_last_error.c_str(); }
 
@@ -229,6 +245,8 @@ int spline_build(const spl_desc* d, const double* grid_vals, const double* lap_v
   clear_error();
   int rc = check_desc(d);
   if (rc) return rc;
+  if (d->basis != SPL_BSPLINE || d->sep_grad)
+    return fail(SPL_EINVAL, "Lagrange or separate-gradient descriptors are built with spline_build_tables");
   if (!grid_vals || !table || !work) return fail(SPL_EINVAL, "grid_vals, table and work must be non-NULL");
   if (d->has_lap && !lap_vals) return fail(SPL_EINVAL, "has_lap = 1 needs lap_vals");
   if (!d->has_lap && lap_vals) return fail(SPL_EINVAL, "lap_vals given but has_lap = 0");
@@ -239,6 +257,24 @@ int spline_build(const spl_desc* d, const double* grid_vals, const double* lap_v
   if (d->has_lap) {
     char* lt = static_cast<char*>(table) + d->table_elems * d->elem_bytes;
     if ((rc = build_one(d, lap_vals, lt, static_cast<double*>(work), s))) return rc;
+  }
+  return SPL_OK;
+}
+
+int spline_build_tables(const spl_desc* d, const double* vals, void* table, void* work, void* stream) {
+  clear_error();
+  int rc = check_desc(d);
+  if (rc) return rc;
+  const bool lagr = d->basis == SPL_LAGRANGE;
+  if (!vals || !table || (!lagr && !work)) return fail(SPL_EINVAL, "vals, table and (B-spline) work must be non-NULL");
+  if (!aligned(vals, 8) || !aligned(table, 16) || (work && !aligned(work, 8)))
+    return fail(SPL_EINVAL, "misaligned buffer (grid values/work need 8 bytes, table 16)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t per_vals = (int64_t)d->grid[0] * d->grid[1] * d->grid[2] * d->n_col;
+  for (int t = 0; t < d->n_tables; ++t) {
+    const double* v = vals + t * per_vals;
+    void* dst = static_cast<char*>(table) + t * d->table_elems * d->elem_bytes;
+    if ((rc = lagr ? cast_one(d, v, dst, s) : build_one(d, v, dst, static_cast<double*>(work), s))) return rc;
   }
   return SPL_OK;
 }
@@ -257,6 +293,7 @@ int spline_build_smoothing(const spl_desc* d, int64_t n_g, const int32_t* miller
   clear_error();
   int rc = check_desc(d);
   if (rc) return rc;
+  if (d->basis != SPL_BSPLINE) return fail(SPL_EINVAL, "smoothing coefficients are B-spline coefficients");
   if (n_g < 1) return fail(SPL_EINVAL, "n_g = %lld < 1", (long long)n_g);
   if ((double)n_g * d->n_orb > 9.0e18) return fail(SPL_EINVAL, "too many coefficients");
   if (!miller || !coef || !table || !work) return fail(SPL_EINVAL, "miller, coef, table and work must be non-NULL");
@@ -283,7 +320,7 @@ int spline_eval_vgl_tile(const spl_desc* d, const void* table, int64_t n_pts, co
   int rc = check_eval_args(d, table, n_pts, pos);
   if (rc || n_pts == 0) return rc;
   if ((rc = check_vgl_outputs(d, v, grad, lap))) return rc;
-  if (!tile || !tile_valid(d->dtype, tile)) return fail(SPL_EINVAL, "invalid tile");
+  if (!tile || !tile_valid_for(d, tile)) return fail(SPL_EINVAL, "invalid tile");
   return launch_eval(d, table, n_pts, pos, v, grad, lap, 0, tile, static_cast<hipStream_t>(stream));
 }
 
@@ -325,6 +362,7 @@ int spline_autotune(const spl_desc* d, const void* table, int64_t n_pts, const d
   for (int k = 0; k < 3 && !rc; ++k) {
     const int opl = set[k];
     if (k > 0 && opl == set[k - 1]) continue;
+    if (d->bloch && opl % 2 != 0) continue;       // Bloch lanes hold whole (re, im) pairs
     const int chunks = d->o_pad / opl;
     int gmax = 2;
     while (gmax < chunks && gmax < 256) gmax <<= 1;
@@ -368,6 +406,8 @@ int spline_backward_work_bytes(const spl_desc* d, int64_t n_pts, int32_t flags, 
   if (!bytes) return fail(SPL_EINVAL, "bytes is NULL");
   if (n_pts < 0 || n_pts > 0x7fffffffLL) return fail(SPL_EINVAL, "n_pts = %lld outside [0, 2^31)", (long long)n_pts);
   if (flags & ~SPL_DETERMINISTIC) return fail(SPL_EINVAL, "unknown flags 0x%x", flags);
+  if (d->basis != SPL_BSPLINE || d->sep_grad || d->bloch)
+    return fail(SPL_EUNSUPPORTED, "the adjoint covers real B-spline tables without separate gradients");
   *bytes = 0;
   if (!(flags & SPL_DETERMINISTIC) || n_pts == 0) return SPL_OK;
   return sorted_work_bytes(d, n_pts, bytes);
@@ -380,6 +420,8 @@ int spline_eval_vgl_backward(const spl_desc* d, const void* table, int64_t n_pts
   int rc = check_eval_args(d, table, n_pts, pos);
   if (rc) return rc;
   if (flags & ~SPL_DETERMINISTIC) return fail(SPL_EINVAL, "unknown flags 0x%x", flags);
+  if (d->basis != SPL_BSPLINE || d->sep_grad || d->bloch)
+    return fail(SPL_EUNSUPPORTED, "the adjoint covers real B-spline tables without separate gradients");
   if (n_pts == 0) return SPL_OK;
   if (gtable && !aligned(gtable, d->dtype == SPL_F64 ? 8 : 4)) return fail(SPL_EINVAL, "gtable misaligned");
   if (gpos && !aligned(gpos, 8)) return fail(SPL_EINVAL, "gpos misaligned");

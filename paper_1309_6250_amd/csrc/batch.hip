@@ -142,6 +142,8 @@ int spline_batch_plan_create(const spl_item* items, int32_t n_items, const int32
     if ((rc = check_eval_args(it.d, it.table, it.n_pts, it.pos))) return fail(rc, "item %d: %s", j, spline_last_error());
     if (it.n_pts > 0 && (rc = check_vgl_outputs(it.d, it.v, it.grad, it.lap)))
       return fail(rc, "item %d: %s", j, spline_last_error());
+    if (it.d->basis != SPL_BSPLINE || it.d->sep_grad || it.d->bloch)
+      return fail(SPL_EUNSUPPORTED, "item %d: batched plans take real B-spline tables without separate gradients", j);
     if (it.d->dtype != items[0].d->dtype || it.d->has_lap != items[0].d->has_lap)
       return fail(SPL_EINVAL, "item %d: all items of a plan must share dtype and has_lap", j);
   }

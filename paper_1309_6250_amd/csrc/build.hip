@@ -13,7 +13,7 @@
 // sweep.  Two sweeps plus two start sums, about 4 FMA per element, no pivoting (|lam| < 1).
 //
 // Layout: data is viewed as [outer][n][inner] with the solved axis in the middle; the
-// third-axis stage has inner = n_orb and writes straight into the padded table in the
+// third-axis stage has inner = n_col and writes straight into the padded table in the
 // storage dtype (one rounding, FP64 -> FP32 -> BF16, round to nearest even).  A
 // workgroup stages `tile` consecutive lines in LDS ([n][tile], conflict-free), so each
 // element is read from and written to HBM once per stage.
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void k_cyclic_axis(LineArgs a) {
     double* dst = static_cast<double*>(a.dst);
     for (int k = 0; k < n; ++k) dst[base + (int64_t)k * a.inner] = a.scale * x[k * tile];
   } else {
-    const int64_t row0 = outer * (int64_t)n;     // table row of (outer, k = 0); inner == n_orb
+    const int64_t row0 = outer * (int64_t)n;     // table row of (outer, k = 0); inner == n_col
     for (int k = 0; k < n; ++k) {
       const double val = a.scale * x[k * tile];
       const int64_t idx = (row0 + k) * a.o_pad + in;
@@ -103,15 +103,33 @@ __global__ __launch_bounds__(256) void k_cyclic_axis(LineArgs a) {
   }
 }
 
-// Zero the padding columns [n_orb, o_pad) of every table row.
+// Zero the padding columns [n_col, o_pad) of every table row.
 template <typename TS>
-__global__ __launch_bounds__(256) void k_zero_pad(TS* table, int64_t n_rows, int32_t n_orb, int32_t o_pad) {
-  const int32_t width = o_pad - n_orb;
+__global__ __launch_bounds__(256) void k_zero_pad(TS* table, int64_t n_rows, int32_t n_col, int32_t o_pad) {
+  const int32_t width = o_pad - n_col;
   const int64_t total = n_rows * width;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = i / width;
-    table[r * o_pad + n_orb + (i - r * width)] = TS(0);
+    table[r * o_pad + n_col + (i - r * width)] = TS(0);
+  }
+}
+
+// Lagrange tables (App. A, Eq. lagrangeinterpolation3): the coefficients are the grid values,
+// rounded once into the storage dtype; padding columns are zeroed.  One element of the padded
+// table per iteration: vals [rows][n_col] FP64 -> table [rows][o_pad].
+template <int OUT>
+__global__ __launch_bounds__(256) void k_cast_table(const double* vals, void* table, int64_t n_rows, int32_t n_col,
+                                                    int32_t o_pad) {
+  const int64_t total = n_rows * o_pad;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / o_pad;
+    const int32_t c = (int32_t)(i - r * o_pad);
+    const double x = c < n_col ? vals[r * n_col + c] : 0.0;
+    if constexpr (OUT == OUT_TABLE_F64) static_cast<double*>(table)[i] = x;
+    else if constexpr (OUT == OUT_TABLE_F32) static_cast<float*>(table)[i] = (float)x;
+    else static_cast<uint16_t*>(table)[i] = f32_to_bf16_rne((float)x);
   }
 }
 
@@ -145,9 +163,10 @@ static int launch_axis(int out, const double* src, void* dst, int64_t outer, int
   return hip_fail(hipGetLastError(), "cyclic solve launch");
 }
 
-// Build one table (orbital or Laplacian) from FP64 grid values into `table` (element offset applied).
+// Build one B-spline table (orbital, gradient component or Laplacian) from FP64 grid values
+// [N1][N2][N3][n_col] into `table` (element offset applied).
 int build_one(const spl_desc* d, const double* vals, void* table, double* work, hipStream_t stream) {
-  const int64_t n1 = d->grid[0], n2 = d->grid[1], n3 = d->grid[2], no = d->n_orb;
+  const int64_t n1 = d->grid[0], n2 = d->grid[1], n3 = d->grid[2], no = d->n_col;
   int rc;
   // stage 1: first axis, lines over (j, k, o): [1][N1][N2*N3*O], grid values -> work
   if ((rc = launch_axis(OUT_F64_WORK, vals, work, 1, (int)n1, n2 * n3 * no, 0, stream))) return rc;
@@ -156,20 +175,35 @@ int build_one(const spl_desc* d, const double* vals, void* table, double* work, 
   // stage 3: third axis, [N1*N2][N3][O], written into the padded table in the storage dtype
   const int out = d->dtype == SPL_F64 ? OUT_TABLE_F64 : d->dtype == SPL_F32 ? OUT_TABLE_F32 : OUT_TABLE_BF16;
   if ((rc = launch_axis(out, work, table, n1 * n2, (int)n3, no, d->o_pad, stream))) return rc;
-  if (d->o_pad > d->n_orb) {
+  if (d->o_pad > d->n_col) {
     const int64_t rows = n1 * n2 * n3;
-    const int64_t total = rows * (d->o_pad - d->n_orb);
+    const int64_t total = rows * (d->o_pad - d->n_col);
     const dim3 grid((unsigned)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536));
     if (d->dtype == SPL_F64)
-      hipLaunchKernelGGL(k_zero_pad<double>, grid, dim3(256), 0, stream, (double*)table, rows, d->n_orb, d->o_pad);
+      hipLaunchKernelGGL(k_zero_pad<double>, grid, dim3(256), 0, stream, (double*)table, rows, d->n_col, d->o_pad);
     else if (d->dtype == SPL_F32)
-      hipLaunchKernelGGL(k_zero_pad<float>, grid, dim3(256), 0, stream, (float*)table, rows, d->n_orb, d->o_pad);
+      hipLaunchKernelGGL(k_zero_pad<float>, grid, dim3(256), 0, stream, (float*)table, rows, d->n_col, d->o_pad);
     else
-      hipLaunchKernelGGL(k_zero_pad<uint16_t>, grid, dim3(256), 0, stream, (uint16_t*)table, rows, d->n_orb,
+      hipLaunchKernelGGL(k_zero_pad<uint16_t>, grid, dim3(256), 0, stream, (uint16_t*)table, rows, d->n_col,
                          d->o_pad);
     if ((rc = hip_fail(hipGetLastError(), "zero padding launch"))) return rc;
   }
   return SPL_OK;
+}
+
+// One Lagrange table: grid values [N1][N2][N3][n_col] cast into the padded table.
+int cast_one(const spl_desc* d, const double* vals, void* table, hipStream_t stream) {
+  const int64_t rows = (int64_t)d->grid[0] * d->grid[1] * d->grid[2];
+  const int64_t total = rows * d->o_pad;
+  const dim3 grid((unsigned)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536));
+  if (d->dtype == SPL_F64)
+    hipLaunchKernelGGL(k_cast_table<OUT_TABLE_F64>, grid, dim3(256), 0, stream, vals, table, rows, d->n_col, d->o_pad);
+  else if (d->dtype == SPL_F32)
+    hipLaunchKernelGGL(k_cast_table<OUT_TABLE_F32>, grid, dim3(256), 0, stream, vals, table, rows, d->n_col, d->o_pad);
+  else
+    hipLaunchKernelGGL(k_cast_table<OUT_TABLE_BF16>, grid, dim3(256), 0, stream, vals, table, rows, d->n_col,
+                       d->o_pad);
+  return hip_fail(hipGetLastError(), "table cast launch");
 }
 
 }  // namespace pws

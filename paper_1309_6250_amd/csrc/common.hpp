@@ -103,6 +103,18 @@ __device__ __forceinline__ void bspline_values(A t, A w[4]) {
   w[3] = sixth * (t2 * t);
 }
 
+// Cubic Lagrange weights for the rows i0-1, i0, i0+1, i0+2 at reduced coordinate t in [0,1)
+// (App. A, Eq. lagrangebasis): -t(t-1)(t-2)/6, (t+1)(t-1)(t-2)/2, -(t+1)t(t-2)/2, (t+1)t(t-1)/6.
+template <typename A>
+__device__ __forceinline__ void lagrange_values(A t, A w[4]) {
+  const A tp = t + A(1), tm = t - A(1), tm2 = t - A(2);
+  const A sixth = A(1) / A(6);
+  w[0] = -sixth * (t * tm * tm2);
+  w[1] = A(0.5) * (tp * tm * tm2);
+  w[2] = A(-0.5) * (tp * t * tm2);
+  w[3] = sixth * (tp * t * tm);
+}
+
 // Four-term dot product in a fixed order: w0 x0 + w1 x1 + w2 x2 + w3 x3.
 template <typename A>
 __device__ __forceinline__ A dot4(const A w[4], A x0, A x1, A x2, A x3) {

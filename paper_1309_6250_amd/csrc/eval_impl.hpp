@@ -1,5 +1,8 @@
 // Forward evaluation kernels: orbital values, gradients and Laplacians through the periodic
-// tricubic B-spline (App. A, Eq. b-splineapproximation; chain rule of Sec. II).
+// tricubic B-spline (App. A, Eq. b-splineapproximation; chain rule of Sec. II), and the other
+// representations the paper compares: cubic Lagrange interpolation of grid values (App. A,
+// Eq. lagrangeinterpolation3) and separate interpolants of the gradient and the Laplacian
+// (Sec. III A, Fig. 1), for real orbitals and for Bloch orbitals exp(i k.r) u(r) (Sec. I).
 //
 // Mapping.  A group of G lanes (G a power of two, 2..256) owns one point; lane c of the group
 // owns the orbital chunks c, c+G, c+2G, ... where a chunk is OPL consecutive orbitals (one
@@ -18,6 +21,11 @@
 // issues the 16 row loads of one slab (l fixed) before using them, so each wave keeps 16
 // vector loads in flight with a register budget that leaves room for several waves per SIMD.
 // No matrix cores: the work is a gather followed by a short dot product, bound by memory.
+//
+// Variants.  MODE_SEP reads five tables (orbital, d/dx, d/dy, d/dz, Laplacian) by value, with
+// B-spline or Lagrange weights.  Bloch orbitals keep (Re u, Im u) in adjacent columns, so a lane
+// with an even OPL holds whole pairs; after the contraction the product rule and the phase
+// exp(i k.r) (FP64 argument, unfolded position) turn them into the orbital's complex outputs.
 #pragma once
 #include "common.hpp"
 
@@ -31,13 +39,16 @@ struct EvalArgs {
   void* grad;
   void* lap;
   int32_t n_pts;
-  int32_t n_orb;
-  int32_t n_chunks;   // ceil(n_orb / OPL): chunks holding at least one real orbital
+  int32_t n_orb;      // columns of an output row (stored real columns: 2 per Bloch orbital)
+  int32_t n_chunks;   // ceil(n_orb / OPL): chunks holding at least one real column
   int32_t vec_store;  // n_orb % OPL == 0 and outputs 16-byte aligned: whole-vector stores
-  int64_t lap_off;    // element offset of the separate Laplacian table
+  int64_t tab_stride; // elements of one table: table q (separate Laplacian, gradients) starts at q * tab_stride
+  double k[3];        // crystal momentum of Bloch orbitals (Bloch variants only)
 };
 
-enum { MODE_V = 0, MODE_VGL = 1, MODE_VGL_SEPLAP = 2 };
+enum { MODE_V = 0, MODE_VGL = 1, MODE_VGL_SEPLAP = 2, MODE_SEP = 3 };
+// variant bits of a kernel: Lagrange weights instead of B-spline, Bloch phase
+enum { VAR_LAGRANGE = 1, VAR_BLOCH = 2 };
 
 // ---------------------------------------------------------------- loads of OPL stored values
 template <typename TS, int OPL> struct RowN;
@@ -125,19 +136,69 @@ __device__ __forceinline__ A pick4(int l, A a0, A a1, A a2, A a3) {
   return l == 0 ? a0 : (l == 1 ? a1 : (l == 2 ? a2 : a3));
 }
 
+// Value of one table at a point for OPL consecutive columns: sum_lmn w_l w_m w_n beta_lmn.
+// `tab` points at the column o of table row 0; the first-axis loop stays rolled (16 loads in
+// flight per slab).
+template <typename TS, int OPL, typename A>
+__device__ __forceinline__ void value_pass(const TS* __restrict__ tab, const int ix[4], const int64_t ry[4],
+                                           const int64_t rz[4], int64_t s0, const A wx[4], const A wy[4],
+                                           const A wz[4], A out[OPL]) {
+#pragma unroll
+  for (int j = 0; j < OPL; ++j) out[j] = A(0);
+#pragma unroll 1
+  for (int l = 0; l < 4; ++l) {
+    const TS* slab = tab + (int64_t)pick4(l, ix[0], ix[1], ix[2], ix[3]) * s0;
+    A r[4][4][OPL];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) RowN<TS, OPL>::load(slab + ry[m] + rz[n], r[m][n]);
+    const A xw = pick4(l, wx[0], wx[1], wx[2], wx[3]);
+#pragma unroll
+    for (int j = 0; j < OPL; ++j) {
+      A q = A(0);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) q = fmaa(wy[m], dot4(wz, r[m][0][j], r[m][1][j], r[m][2][j], r[m][3][j]), q);
+      out[j] = fmaa(xw, q, out[j]);
+    }
+  }
+}
+
+// (re, im) <- (c + i s)(re + i im) for every pair (2i, 2i+1) of x.
+template <typename A, int OPL>
+__device__ __forceinline__ void phase_pairs(A c, A s, A (&x)[OPL]) {
+#pragma unroll
+  for (int j = 0; j < OPL; j += 2) {
+    const A re = x[j], im = x[j + 1];
+    x[j] = fmaa(c, re, -(s * im));
+    x[j + 1] = fmaa(s, re, c * im);
+  }
+}
+
+template <typename O, typename A, int OPL>
+__device__ __forceinline__ void to_out(const A (&x)[OPL], bool ok, O (&y)[OPL]) {
+#pragma unroll
+  for (int j = 0; j < OPL; ++j) y[j] = ok ? (O)x[j] : (O)__builtin_nan("");
+}
+
 // All outputs of point p (0 <= p < a.n_pts) for the orbital chunks of lane `lane` of its group.
-template <typename TS, int MODE, int G, int OPL>
+template <typename TS, int MODE, int G, int OPL, int VAR>
 __device__ __forceinline__ void eval_point(const EvalArgs& a, const int p, const int lane) {
   using A = typename Acc<TS>::type;
   using O = typename Out<TS>::type;
-  constexpr int NQ = (MODE == MODE_V) ? 1 : (MODE == MODE_VGL ? 10 : 4);
+  constexpr bool LAGR = (VAR & VAR_LAGRANGE) != 0;
+  constexpr bool BLOCH = (VAR & VAR_BLOCH) != 0;
+  constexpr bool DERIV = MODE == MODE_VGL || MODE == MODE_VGL_SEPLAP;
+  static_assert(!(LAGR && DERIV), "Lagrange tables are read by value only");
+  static_assert(!BLOCH || OPL % 2 == 0, "Bloch orbitals need whole (re, im) pairs per lane");
+  constexpr int NQ = (MODE == MODE_VGL) ? 10 : 4;
   const TS* __restrict__ tab = static_cast<const TS*>(a.table);
   const bool vec_ok = a.vec_store != 0;
 
+  const double r0 = a.pos[3 * (int64_t)p], r1 = a.pos[3 * (int64_t)p + 1], r2 = a.pos[3 * (int64_t)p + 2];
   int i0[3];
   double t[3];
-  const bool ok = reduce_point(a.g, a.pos[3 * (int64_t)p], a.pos[3 * (int64_t)p + 1], a.pos[3 * (int64_t)p + 2],
-                               i0, t);
+  const bool ok = reduce_point(a.g, r0, r1, r2, i0, t);
   int ix[4], iy[4], iz[4];
   wrap4(i0[0], a.g.n[0], ix);
   wrap4(i0[1], a.g.n[1], iy);
@@ -149,11 +210,25 @@ __device__ __forceinline__ void eval_point(const EvalArgs& a, const int p, const
     rz[m] = (int64_t)iz[m] * a.g.o_pad;
   }
 
+  A ph_c = A(1), ph_s = A(0);   // exp(i k.r), Bloch variants
+  if constexpr (BLOCH) {
+    double sn, cs;
+    sincos(fmaa(a.k[2], r2, fmaa(a.k[1], r1, a.k[0] * r0)), &sn, &cs);
+    ph_c = (A)cs;
+    ph_s = (A)sn;
+  }
+
   A wx[4], wy[4], wz[4], dwx[4], dwy[4], dwz[4], d2wx[4], d2wy[4], d2wz[4];
-  if constexpr (MODE == MODE_V) {
-    bspline_values<A>((A)t[0], wx);
-    bspline_values<A>((A)t[1], wy);
-    bspline_values<A>((A)t[2], wz);
+  if constexpr (!DERIV) {
+    if constexpr (LAGR) {
+      lagrange_values<A>((A)t[0], wx);
+      lagrange_values<A>((A)t[1], wy);
+      lagrange_values<A>((A)t[2], wz);
+    } else {
+      bspline_values<A>((A)t[0], wx);
+      bspline_values<A>((A)t[1], wy);
+      bspline_values<A>((A)t[2], wz);
+    }
   } else {
     bspline_weights<A>((A)t[0], wx, dwx, d2wx);
     bspline_weights<A>((A)t[1], wy, dwy, d2wy);
@@ -161,34 +236,54 @@ __device__ __forceinline__ void eval_point(const EvalArgs& a, const int p, const
   }
 
   O* vout = static_cast<O*>(a.v) + (int64_t)p * a.n_orb;
+  O* gout = static_cast<O*>(a.grad) + (int64_t)p * 3 * a.n_orb;
+  O* lout = static_cast<O*>(a.lap) + (int64_t)p * a.n_orb;
   for (int c = lane; c < a.n_chunks; c += G) {
     const int o = c * OPL;
-    // reduced derivatives: 0 V, 1-3 first, 4 xx, 5 yy, 6 zz, 7 xy, 8 xz, 9 yz
-    A acc[NQ][OPL];
+    if constexpr (MODE == MODE_V) {
+      A val[OPL];
+      value_pass<TS, OPL, A>(tab + o, ix, ry, rz, a.g.s0, wx, wy, wz, val);
+      if constexpr (BLOCH) phase_pairs<A, OPL>(ph_c, ph_s, val);
+      O ov[OPL];
+      to_out<O, A, OPL>(val, ok, ov);
+      store_out<O, OPL>(vout, ov, o, a.n_orb, vec_ok);
+    } else if constexpr (MODE == MODE_SEP) {
+      // orbital, three Cartesian gradient components and Laplacian, each its own table
+      A val[5][OPL];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q)
+      for (int q = 0; q < 5; ++q) {
+        value_pass<TS, OPL, A>(tab + q * a.tab_stride + o, ix, ry, rz, a.g.s0, wx, wy, wz, val[q]);
+        if constexpr (BLOCH) phase_pairs<A, OPL>(ph_c, ph_s, val[q]);
+      }
+      O y[OPL];
+      to_out<O, A, OPL>(val[0], ok, y);
+      store_out<O, OPL>(vout, y, o, a.n_orb, vec_ok);
+      to_out<O, A, OPL>(val[1], ok, y);
+      store_out<O, OPL>(gout, y, o, a.n_orb, vec_ok);
+      to_out<O, A, OPL>(val[2], ok, y);
+      store_out<O, OPL>(gout + a.n_orb, y, o, a.n_orb, vec_ok);
+      to_out<O, A, OPL>(val[3], ok, y);
+      store_out<O, OPL>(gout + 2 * a.n_orb, y, o, a.n_orb, vec_ok);
+      to_out<O, A, OPL>(val[4], ok, y);
+      store_out<O, OPL>(lout, y, o, a.n_orb, vec_ok);
+    } else {
+      // reduced derivatives: 0 V, 1-3 first, 4 xx, 5 yy, 6 zz, 7 xy, 8 xz, 9 yz
+      A acc[NQ][OPL];
 #pragma unroll
-      for (int j = 0; j < OPL; ++j) acc[q][j] = A(0);
+      for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int j = 0; j < OPL; ++j) acc[q][j] = A(0);
 
 #pragma unroll 1
-    for (int l = 0; l < 4; ++l) {
-      const TS* slab = tab + (int64_t)pick4(l, ix[0], ix[1], ix[2], ix[3]) * a.g.s0 + o;
-      A r[4][4][OPL];
+      for (int l = 0; l < 4; ++l) {
+        const TS* slab = tab + (int64_t)pick4(l, ix[0], ix[1], ix[2], ix[3]) * a.g.s0 + o;
+        A r[4][4][OPL];
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int n = 0; n < 4; ++n) RowN<TS, OPL>::load(slab + ry[m] + rz[n], r[m][n]);
+          for (int n = 0; n < 4; ++n) RowN<TS, OPL>::load(slab + ry[m] + rz[n], r[m][n]);
 
-      const A xw = pick4(l, wx[0], wx[1], wx[2], wx[3]);
-      if constexpr (MODE == MODE_V) {
-#pragma unroll
-        for (int j = 0; j < OPL; ++j) {
-          A q = A(0);
-#pragma unroll
-          for (int m = 0; m < 4; ++m) q = fmaa(wy[m], dot4(wz, r[m][0][j], r[m][1][j], r[m][2][j], r[m][3][j]), q);
-          acc[0][j] = fmaa(xw, q, acc[0][j]);
-        }
-      } else {
+        const A xw = pick4(l, wx[0], wx[1], wx[2], wx[3]);
         const A xd = pick4(l, dwx[0], dwx[1], dwx[2], dwx[3]);
         const A xdd = pick4(l, d2wx[0], d2wx[1], d2wx[2], d2wx[3]);
 #pragma unroll
@@ -224,79 +319,82 @@ __device__ __forceinline__ void eval_point(const EvalArgs& a, const int p, const
           }
         }
       }
-    }
 
-    if constexpr (MODE == MODE_V) {
-      O ov[OPL];
-#pragma unroll
-      for (int j = 0; j < OPL; ++j) ov[j] = ok ? (O)acc[0][j] : (O)__builtin_nan("");
-      store_out<O, OPL>(vout, ov, o, a.n_orb, vec_ok);
-    } else {
       A lacc[OPL];
-#pragma unroll
-      for (int j = 0; j < OPL; ++j) lacc[j] = A(0);
       if constexpr (MODE == MODE_VGL_SEPLAP) {
         // Laplacian = value of the separate Laplacian spline (same block, value weights)
-#pragma unroll 1
-        for (int l = 0; l < 4; ++l) {
-          const TS* slab = tab + a.lap_off + (int64_t)pick4(l, ix[0], ix[1], ix[2], ix[3]) * a.g.s0 + o;
-          A r[4][4][OPL];
-#pragma unroll
-          for (int m = 0; m < 4; ++m)
-#pragma unroll
-            for (int n = 0; n < 4; ++n) RowN<TS, OPL>::load(slab + ry[m] + rz[n], r[m][n]);
-          const A xw = pick4(l, wx[0], wx[1], wx[2], wx[3]);
-#pragma unroll
-          for (int j = 0; j < OPL; ++j) {
-            A q = A(0);
-#pragma unroll
-            for (int m = 0; m < 4; ++m) q = fmaa(wy[m], dot4(wz, r[m][0][j], r[m][1][j], r[m][2][j], r[m][3][j]), q);
-            lacc[j] = fmaa(xw, q, lacc[j]);
-          }
-        }
+        value_pass<TS, OPL, A>(tab + a.tab_stride + o, ix, ry, rz, a.g.s0, wx, wy, wz, lacc);
       }
       // chain rule (Sec. II): grad = J^T grad_t, lap = sum_ij M_ij H_ij
       const A j00 = (A)a.g.jac[0], j01 = (A)a.g.jac[1], j02 = (A)a.g.jac[2];
       const A j10 = (A)a.g.jac[3], j11 = (A)a.g.jac[4], j12 = (A)a.g.jac[5];
       const A j20 = (A)a.g.jac[6], j21 = (A)a.g.jac[7], j22 = (A)a.g.jac[8];
-      O ov[OPL], gx[OPL], gy[OPL], gz[OPL], lv[OPL];
-      const O nan = (O)__builtin_nan("");
+      A av[OPL], ax[OPL], ay[OPL], az[OPL], al[OPL];
 #pragma unroll
       for (int j = 0; j < OPL; ++j) {
         const A g0 = acc[1][j], g1 = acc[2][j], g2 = acc[3][j];
-        A lp;
         if constexpr (MODE == MODE_VGL) {
           const A diag = fmaa((A)a.g.metric[2], acc[6][j], fmaa((A)a.g.metric[1], acc[5][j], (A)a.g.metric[0] * acc[4][j]));
           const A off = fmaa((A)a.g.metric[5], acc[9][j], fmaa((A)a.g.metric[4], acc[8][j], (A)a.g.metric[3] * acc[7][j]));
-          lp = fmaa(A(2), off, diag);
+          al[j] = fmaa(A(2), off, diag);
         } else {
-          lp = lacc[j];
+          al[j] = lacc[j];
         }
-        ov[j] = ok ? (O)acc[0][j] : nan;
-        gx[j] = ok ? (O)fmaa(j20, g2, fmaa(j10, g1, j00 * g0)) : nan;
-        gy[j] = ok ? (O)fmaa(j21, g2, fmaa(j11, g1, j01 * g0)) : nan;
-        gz[j] = ok ? (O)fmaa(j22, g2, fmaa(j12, g1, j02 * g0)) : nan;
-        lv[j] = ok ? (O)lp : nan;
+        av[j] = acc[0][j];
+        ax[j] = fmaa(j20, g2, fmaa(j10, g1, j00 * g0));
+        ay[j] = fmaa(j21, g2, fmaa(j11, g1, j01 * g0));
+        az[j] = fmaa(j22, g2, fmaa(j12, g1, j02 * g0));
       }
-      O* gout = static_cast<O*>(a.grad) + (int64_t)p * 3 * a.n_orb;
-      O* lout = static_cast<O*>(a.lap) + (int64_t)p * a.n_orb;
-      store_out<O, OPL>(vout, ov, o, a.n_orb, vec_ok);
-      store_out<O, OPL>(gout, gx, o, a.n_orb, vec_ok);
-      store_out<O, OPL>(gout + a.n_orb, gy, o, a.n_orb, vec_ok);
-      store_out<O, OPL>(gout + 2 * a.n_orb, gz, o, a.n_orb, vec_ok);
-      store_out<O, OPL>(lout, lv, o, a.n_orb, vec_ok);
+      if constexpr (BLOCH) {
+        // product rule for phi = e u (e = exp(i k.r)): grad phi = e (grad u + i k u),
+        // lap phi = e (lap u + 2 i k.grad u - |k|^2 u), or e w with a separate Laplacian table
+        const A k0 = (A)a.k[0], k1 = (A)a.k[1], k2 = (A)a.k[2];
+        const A kk = (A)fmaa(a.k[2], a.k[2], fmaa(a.k[1], a.k[1], a.k[0] * a.k[0]));
+#pragma unroll
+        for (int j = 0; j < OPL; j += 2) {
+          const A ur = av[j], ui = av[j + 1];
+          if constexpr (MODE == MODE_VGL) {
+            const A kgr = fmaa(k2, az[j], fmaa(k1, ay[j], k0 * ax[j]));
+            const A kgi = fmaa(k2, az[j + 1], fmaa(k1, ay[j + 1], k0 * ax[j + 1]));
+            al[j] = fmaa(-kk, ur, fmaa(A(-2), kgi, al[j]));
+            al[j + 1] = fmaa(-kk, ui, fmaa(A(2), kgr, al[j + 1]));
+          }
+          ax[j] = fmaa(-k0, ui, ax[j]);
+          ax[j + 1] = fmaa(k0, ur, ax[j + 1]);
+          ay[j] = fmaa(-k1, ui, ay[j]);
+          ay[j + 1] = fmaa(k1, ur, ay[j + 1]);
+          az[j] = fmaa(-k2, ui, az[j]);
+          az[j + 1] = fmaa(k2, ur, az[j + 1]);
+        }
+        phase_pairs<A, OPL>(ph_c, ph_s, av);
+        phase_pairs<A, OPL>(ph_c, ph_s, ax);
+        phase_pairs<A, OPL>(ph_c, ph_s, ay);
+        phase_pairs<A, OPL>(ph_c, ph_s, az);
+        phase_pairs<A, OPL>(ph_c, ph_s, al);
+      }
+      O y[OPL];
+      to_out<O, A, OPL>(av, ok, y);
+      store_out<O, OPL>(vout, y, o, a.n_orb, vec_ok);
+      to_out<O, A, OPL>(ax, ok, y);
+      store_out<O, OPL>(gout, y, o, a.n_orb, vec_ok);
+      to_out<O, A, OPL>(ay, ok, y);
+      store_out<O, OPL>(gout + a.n_orb, y, o, a.n_orb, vec_ok);
+      to_out<O, A, OPL>(az, ok, y);
+      store_out<O, OPL>(gout + 2 * a.n_orb, y, o, a.n_orb, vec_ok);
+      to_out<O, A, OPL>(al, ok, y);
+      store_out<O, OPL>(lout, y, o, a.n_orb, vec_ok);
     }
   }
 }
 
 // One launch over one table: groups of G lanes, one point per group.
-template <typename TS, int MODE, int G, int OPL>
+template <typename TS, int MODE, int G, int OPL, int VAR>
 __global__ __launch_bounds__(256) void k_eval(EvalArgs a) {
   constexpr int GPB = 256 / G;
   int p = (int)blockIdx.x * GPB + (int)threadIdx.x / G;
   if constexpr (G >= 64) p = __builtin_amdgcn_readfirstlane(p);
   if (p >= a.n_pts) return;
-  eval_point<TS, MODE, G, OPL>(a, p, (int)threadIdx.x % G);
+  eval_point<TS, MODE, G, OPL, VAR>(a, p, (int)threadIdx.x % G);
 }
 
 // ---------------------------------------------------------------- batched persistent launch
@@ -332,7 +430,7 @@ __global__ __launch_bounds__(256) void k_eval_batch(BatchArgs b) {
     const EvalArgs& a = b.items[lo];
     int p = (tile - b.tile_start[lo]) * GPB + (int)threadIdx.x / G;
     if constexpr (G >= 64) p = __builtin_amdgcn_readfirstlane(p);
-    if (p < a.n_pts) eval_point<TS, MODE, G, OPL>(a, p, (int)threadIdx.x % G);
+    if (p < a.n_pts) eval_point<TS, MODE, G, OPL, 0>(a, p, (int)threadIdx.x % G);
   }
 }
 
@@ -352,18 +450,23 @@ inline BatchKernel pick_batch_g(int g) {
   }
 }
 
-template <typename TS, int MODE, int OPL>
+template <typename TS, int MODE, int OPL, int VAR>
 inline EvalKernel pick_g(int g) {
-  switch (g) {
-    case 2: return k_eval<TS, MODE, 2, OPL>;
-    case 4: return k_eval<TS, MODE, 4, OPL>;
-    case 8: return k_eval<TS, MODE, 8, OPL>;
-    case 16: return k_eval<TS, MODE, 16, OPL>;
-    case 32: return k_eval<TS, MODE, 32, OPL>;
-    case 64: return k_eval<TS, MODE, 64, OPL>;
-    case 128: return k_eval<TS, MODE, 128, OPL>;
-    case 256: return k_eval<TS, MODE, 256, OPL>;
-    default: return nullptr;
+  if constexpr ((VAR & VAR_BLOCH) != 0 && OPL % 2 != 0) {
+    (void)g;
+    return nullptr;                        // Bloch pairs need an even number of columns per lane
+  } else {
+    switch (g) {
+      case 2: return k_eval<TS, MODE, 2, OPL, VAR>;
+      case 4: return k_eval<TS, MODE, 4, OPL, VAR>;
+      case 8: return k_eval<TS, MODE, 8, OPL, VAR>;
+      case 16: return k_eval<TS, MODE, 16, OPL, VAR>;
+      case 32: return k_eval<TS, MODE, 32, OPL, VAR>;
+      case 64: return k_eval<TS, MODE, 64, OPL, VAR>;
+      case 128: return k_eval<TS, MODE, 128, OPL, VAR>;
+      case 256: return k_eval<TS, MODE, 256, OPL, VAR>;
+      default: return nullptr;
+    }
   }
 }
 
@@ -374,24 +477,51 @@ template <> struct OplSet<double> { static constexpr int lo = 1, mid = 2, hi = 2
 template <> struct OplSet<float> { static constexpr int lo = 1, mid = 2, hi = 4; };
 template <> struct OplSet<uint16_t> { static constexpr int lo = 2, mid = 4, hi = 8; };
 
-template <typename TS, int MODE>
+template <typename TS, int MODE, int VAR>
 inline EvalKernel pick_opl(int g, int opl) {
-  if (opl == OplSet<TS>::lo) return pick_g<TS, MODE, OplSet<TS>::lo>(g);
-  if (opl == OplSet<TS>::mid) return pick_g<TS, MODE, OplSet<TS>::mid>(g);
-  if (opl == OplSet<TS>::hi) return pick_g<TS, MODE, OplSet<TS>::hi>(g);
+  if (opl == OplSet<TS>::lo) return pick_g<TS, MODE, OplSet<TS>::lo, VAR>(g);
+  if (opl == OplSet<TS>::mid) return pick_g<TS, MODE, OplSet<TS>::mid, VAR>(g);
+  if (opl == OplSet<TS>::hi) return pick_g<TS, MODE, OplSet<TS>::hi, VAR>(g);
   return nullptr;
 }
 
 template <typename TS, int MODE>
 inline BatchKernel pick_batch_opl(int g, int opl);
 
+// Real B-spline tables, values or VGL from derivatives (with or without a separate Laplacian).
 template <typename TS>
 inline EvalKernel pick_mode(int mode, int g, int opl) {
   switch (mode) {
-    case MODE_V: return pick_opl<TS, MODE_V>(g, opl);
-    case MODE_VGL: return pick_opl<TS, MODE_VGL>(g, opl);
-    default: return pick_opl<TS, MODE_VGL_SEPLAP>(g, opl);
+    case MODE_V: return pick_opl<TS, MODE_V, 0>(g, opl);
+    case MODE_VGL: return pick_opl<TS, MODE_VGL, 0>(g, opl);
+    case MODE_VGL_SEPLAP: return pick_opl<TS, MODE_VGL_SEPLAP, 0>(g, opl);
+    default: return nullptr;
   }
+}
+
+// Everything else: Lagrange weights, five separate tables, Bloch orbitals.
+template <typename TS>
+inline EvalKernel pick_mode_variant(int mode, int var, int g, int opl) {
+  if (mode == MODE_SEP) {
+    switch (var) {
+      case 0: return pick_opl<TS, MODE_SEP, 0>(g, opl);
+      case VAR_LAGRANGE: return pick_opl<TS, MODE_SEP, VAR_LAGRANGE>(g, opl);
+      case VAR_BLOCH: return pick_opl<TS, MODE_SEP, VAR_BLOCH>(g, opl);
+      case VAR_BLOCH | VAR_LAGRANGE: return pick_opl<TS, MODE_SEP, VAR_BLOCH | VAR_LAGRANGE>(g, opl);
+      default: return nullptr;
+    }
+  }
+  if (mode == MODE_V) {
+    switch (var) {
+      case VAR_LAGRANGE: return pick_opl<TS, MODE_V, VAR_LAGRANGE>(g, opl);
+      case VAR_BLOCH: return pick_opl<TS, MODE_V, VAR_BLOCH>(g, opl);
+      case VAR_BLOCH | VAR_LAGRANGE: return pick_opl<TS, MODE_V, VAR_BLOCH | VAR_LAGRANGE>(g, opl);
+      default: return nullptr;
+    }
+  }
+  if (var != VAR_BLOCH) return nullptr;
+  return mode == MODE_VGL ? pick_opl<TS, MODE_VGL, VAR_BLOCH>(g, opl)
+                          : pick_opl<TS, MODE_VGL_SEPLAP, VAR_BLOCH>(g, opl);
 }
 
 template <typename TS, int MODE>

@@ -7,6 +7,7 @@ namespace pws {
 int vec_of(int dtype);
 void opl_set(int dtype, int out[3]);
 bool tile_valid(int dtype, const int32_t tile[2]);
+bool tile_valid_for(const spl_desc* d, const int32_t tile[2]);
 void default_tile(const spl_desc* d, int32_t tile[2]);
 void tile_for(const spl_desc* d, int32_t tile[2]);
 int check_eval_args(const spl_desc* d, const void* table, int64_t n_pts, const double* pos);

@@ -7,12 +7,15 @@
 // phase per grid step theta_m = G . a_m / N_m = 2 pi n_m / N_m, the paper's C = 3/2 basis gives
 // (3/2) sinc^4(theta/2); the standard normalization used here gives sinc^4(theta/2), and gamma is
 // the product over the three axes.  Dividing by gamma makes the spline's fundamental Fourier
-// components equal c_G.  With a separate Laplacian, the second table uses (-|G|^2) c_G.
+// components equal c_G.  The other tables of a descriptor are the smoothing splines of the
+// periodic parts of the gradient, coefficients i (k+G)_c c_G (separate gradients), and of the
+// Laplacian, -|k+G|^2 c_G (k = 0 for real orbitals).
 //
 // Steps on the device: zero a complex grid [N1][N2][N3][n_orb]; scatter c_G / gamma_G into the
 // bins (n mod N); inverse DFT along each axis in turn (one line per thread, staged in LDS, direct
 // summation with exact twiddle tables, O(N^2) per line: the build is a one-time cost); the last
-// axis writes the real part into the padded table in the storage dtype.
+// axis writes the real part (real orbitals) or both parts (Bloch orbitals: columns 2o, 2o+1)
+// into the padded table in the storage dtype.
 #include <math.h>
 
 #include "common.hpp"
@@ -34,9 +37,16 @@ __device__ __forceinline__ double sinc4_half(double theta) {
   return s2 * s2;
 }
 
-// grid[bin(n)][o] += coef[o][g] * scale(g): scale = 1 / gamma_G, times -|G|^2 for the Laplacian table.
+struct Kvec {
+  double k[3];
+};
+
+enum { COMP_VALUE = 0, COMP_LAP = 4 };   // 1, 2, 3: Cartesian gradient component 0, 1, 2
+
+// grid[bin(n)][o] += coef[o][g] * scale(g): scale = 1 / gamma_G, times i (k+G)_c for a gradient
+// component c, or -|k+G|^2 for the Laplacian.
 __global__ __launch_bounds__(256) void k_scatter_coef(const int32_t* miller, const c2v* coef, int64_t n_g,
-                                                      int32_t n_orb, Geom geo, int32_t lap, c2v* grid) {
+                                                      int32_t n_orb, Geom geo, int32_t comp, Kvec kv, c2v* grid) {
   const int64_t total = n_g * n_orb;
   const double two_pi = 6.283185307179586476925286766559;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -44,26 +54,33 @@ __global__ __launch_bounds__(256) void k_scatter_coef(const int32_t* miller, con
     const int64_t g = idx / n_orb;
     const int o = (int)(idx - g * n_orb);
     const int n0 = miller[3 * g], n1 = miller[3 * g + 1], n2 = miller[3 * g + 2];
-    double scale = 1.0 / (sinc4_half(two_pi * n0 / geo.n[0]) * sinc4_half(two_pi * n1 / geo.n[1]) *
-                          sinc4_half(two_pi * n2 / geo.n[2]));
-    if (lap) {
-      double gsq = 0.0;
+    const double scale = 1.0 / (sinc4_half(two_pi * n0 / geo.n[0]) * sinc4_half(two_pi * n1 / geo.n[1]) *
+                                sinc4_half(two_pi * n2 / geo.n[2]));
+    double q[3], qsq = 0.0;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        // G = 2 pi (lattice^-1) n, and lattice^-1 = ainv^T
-        const double gc = two_pi * fmaa(geo.ainv[6 + c], (double)n2, fmaa(geo.ainv[3 + c], (double)n1, geo.ainv[c] * n0));
-        gsq = fmaa(gc, gc, gsq);
-      }
-      scale *= -gsq;
+    for (int c = 0; c < 3; ++c) {
+      // k + G with G = 2 pi (lattice^-1) n, and lattice^-1 = ainv^T
+      q[c] = kv.k[c] + two_pi * fmaa(geo.ainv[6 + c], (double)n2, fmaa(geo.ainv[3 + c], (double)n1, geo.ainv[c] * n0));
+      qsq = fmaa(q[c], q[c], qsq);
     }
     const int b0 = ((n0 % geo.n[0]) + geo.n[0]) % geo.n[0];
     const int b1 = ((n1 % geo.n[1]) + geo.n[1]) % geo.n[1];
     const int b2 = ((n2 % geo.n[2]) + geo.n[2]) % geo.n[2];
     const int64_t bin = ((int64_t)b0 * geo.n[1] + b1) * geo.n[2] + b2;
     const c2v c = coef[(int64_t)o * n_g + g];
+    double re = c.x * scale, im = c.y * scale;
+    if (comp == COMP_LAP) {
+      re *= -qsq;
+      im *= -qsq;
+    } else if (comp != COMP_VALUE) {
+      const double qc = q[comp - 1];            // i q_c (re + i im) = -q_c im + i q_c re
+      const double t = re;
+      re = -qc * im;
+      im = qc * t;
+    }
     double* dst = reinterpret_cast<double*>(grid + bin * n_orb + o);
-    unsafeAtomicAdd(dst, c.x * scale);           // planewaves sharing a bin (too coarse a grid) add up
-    unsafeAtomicAdd(dst + 1, c.y * scale);
+    unsafeAtomicAdd(dst, re);                    // planewaves sharing a bin (too coarse a grid) add up
+    unsafeAtomicAdd(dst + 1, im);
   }
 }
 
@@ -76,6 +93,7 @@ struct DftArgs {
   int64_t inner;
   int32_t n;
   int32_t o_pad;
+  int32_t bloch;         // final axis: store (re, im) into columns (2o, 2o+1) instead of re into o
 };
 
 enum { DFT_INPLACE = 0, DFT_TABLE_F64 = 1, DFT_TABLE_F32 = 2, DFT_TABLE_BF16 = 3 };
@@ -122,21 +140,29 @@ __global__ __launch_bounds__(256) void k_idft_axis(DftArgs a) {
     if constexpr (OUT == DFT_INPLACE) {
       a.data[base + (int64_t)k * a.inner] = c2v{re, im};
     } else {
-      const int64_t t = (outer * (int64_t)n + k) * a.o_pad + in;      // inner == n_orb here
-      if constexpr (OUT == DFT_TABLE_F64) static_cast<double*>(a.table)[t] = re;
-      else if constexpr (OUT == DFT_TABLE_F32) static_cast<float*>(a.table)[t] = (float)re;
-      else static_cast<uint16_t*>(a.table)[t] = f32_to_bf16_rne_s((float)re);
+      const int64_t row = (outer * (int64_t)n + k) * a.o_pad;      // inner == n_orb here
+      const int64_t t = a.bloch ? row + 2 * in : row + in;
+      if constexpr (OUT == DFT_TABLE_F64) {
+        static_cast<double*>(a.table)[t] = re;
+        if (a.bloch) static_cast<double*>(a.table)[t + 1] = im;
+      } else if constexpr (OUT == DFT_TABLE_F32) {
+        static_cast<float*>(a.table)[t] = (float)re;
+        if (a.bloch) static_cast<float*>(a.table)[t + 1] = (float)im;
+      } else {
+        static_cast<uint16_t*>(a.table)[t] = f32_to_bf16_rne_s((float)re);
+        if (a.bloch) static_cast<uint16_t*>(a.table)[t + 1] = f32_to_bf16_rne_s((float)im);
+      }
     }
   }
 }
 
 template <typename TS>
-__global__ __launch_bounds__(256) void k_zero_pad_s(TS* table, int64_t n_rows, int32_t n_orb, int32_t o_pad) {
-  const int32_t width = o_pad - n_orb;
+__global__ __launch_bounds__(256) void k_zero_pad_s(TS* table, int64_t n_rows, int32_t n_col, int32_t o_pad) {
+  const int32_t width = o_pad - n_col;
   const int64_t total = n_rows * width;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = i / width;
-    table[r * o_pad + n_orb + (i - r * width)] = TS(0);
+    table[r * o_pad + n_col + (i - r * width)] = TS(0);
   }
 }
 
@@ -148,7 +174,7 @@ static int dft_tile(int n) {
 
 // One inverse-DFT stage along the middle axis of [outer][n][inner] (twiddles in the workspace).
 static int launch_idft(int out, c2v* data, void* table, const double* cs, const double* sn, int64_t outer, int n,
-                       int64_t inner, int o_pad, hipStream_t stream) {
+                       int64_t inner, int o_pad, int bloch, hipStream_t stream) {
   DftArgs a;
   a.data = data;
   a.table = table;
@@ -158,6 +184,7 @@ static int launch_idft(int out, c2v* data, void* table, const double* cs, const 
   a.inner = inner;
   a.n = n;
   a.o_pad = o_pad;
+  a.bloch = bloch;
   const int tile = dft_tile(n);
   const size_t shmem = (size_t)tile * n * 16 + (size_t)n * 16;
   const dim3 grid((unsigned)((a.n_lines + tile - 1) / tile));
@@ -170,7 +197,7 @@ static int launch_idft(int out, c2v* data, void* table, const double* cs, const 
   return hip_fail(hipGetLastError(), "inverse DFT launch");
 }
 
-int build_smoothing_one(const spl_desc* d, int64_t n_g, const int32_t* miller, const double* coef, int lap,
+int build_smoothing_one(const spl_desc* d, int64_t n_g, const int32_t* miller, const double* coef, int comp,
                         void* table, void* work, const double* twiddles, hipStream_t stream) {
   const int64_t n1 = d->grid[0], n2 = d->grid[1], n3 = d->grid[2], no = d->n_orb;
   c2v* grid = static_cast<c2v*>(work);
@@ -181,27 +208,29 @@ int build_smoothing_one(const spl_desc* d, int64_t n_g, const int32_t* miller, c
   const Geom geo = make_geom(d);
   const int64_t sc = n_g * no;
   const unsigned sblocks = (unsigned)std::min<int64_t>((sc + 255) / 256, 65536);
+  Kvec kv;
+  for (int c = 0; c < 3; ++c) kv.k[c] = d->kvec[c];
   hipLaunchKernelGGL(k_scatter_coef, dim3(sblocks), dim3(256), 0, stream, miller,
-                     reinterpret_cast<const c2v*>(coef), n_g, (int32_t)no, geo, (int32_t)lap, grid);
+                     reinterpret_cast<const c2v*>(coef), n_g, (int32_t)no, geo, (int32_t)comp, kv, grid);
   if ((rc = hip_fail(hipGetLastError(), "coefficient scatter launch"))) return rc;
   // twiddles: [axis][cos n | sin n] packed one axis after the other
   const double* tw0 = twiddles;
   const double* tw1 = tw0 + 2 * n1;
   const double* tw2 = tw1 + 2 * n2;
-  if ((rc = launch_idft(DFT_INPLACE, grid, nullptr, tw0, tw0 + n1, 1, (int)n1, n2 * n3 * no, 0, stream))) return rc;
-  if ((rc = launch_idft(DFT_INPLACE, grid, nullptr, tw1, tw1 + n2, n1, (int)n2, n3 * no, 0, stream))) return rc;
+  if ((rc = launch_idft(DFT_INPLACE, grid, nullptr, tw0, tw0 + n1, 1, (int)n1, n2 * n3 * no, 0, 0, stream))) return rc;
+  if ((rc = launch_idft(DFT_INPLACE, grid, nullptr, tw1, tw1 + n2, n1, (int)n2, n3 * no, 0, 0, stream))) return rc;
   const int out = d->dtype == SPL_F64 ? DFT_TABLE_F64 : d->dtype == SPL_F32 ? DFT_TABLE_F32 : DFT_TABLE_BF16;
-  if ((rc = launch_idft(out, grid, table, tw2, tw2 + n3, n1 * n2, (int)n3, no, d->o_pad, stream))) return rc;
-  if (d->o_pad > d->n_orb) {
+  if ((rc = launch_idft(out, grid, table, tw2, tw2 + n3, n1 * n2, (int)n3, no, d->o_pad, d->bloch, stream))) return rc;
+  if (d->o_pad > d->n_col) {
     const int64_t rows = n1 * n2 * n3;
-    const int64_t total = rows * (d->o_pad - d->n_orb);
+    const int64_t total = rows * (d->o_pad - d->n_col);
     const dim3 g((unsigned)std::min<int64_t>((total + 255) / 256, 65536));
     if (d->dtype == SPL_F64)
-      hipLaunchKernelGGL(k_zero_pad_s<double>, g, dim3(256), 0, stream, (double*)table, rows, d->n_orb, d->o_pad);
+      hipLaunchKernelGGL(k_zero_pad_s<double>, g, dim3(256), 0, stream, (double*)table, rows, d->n_col, d->o_pad);
     else if (d->dtype == SPL_F32)
-      hipLaunchKernelGGL(k_zero_pad_s<float>, g, dim3(256), 0, stream, (float*)table, rows, d->n_orb, d->o_pad);
+      hipLaunchKernelGGL(k_zero_pad_s<float>, g, dim3(256), 0, stream, (float*)table, rows, d->n_col, d->o_pad);
     else
-      hipLaunchKernelGGL(k_zero_pad_s<uint16_t>, g, dim3(256), 0, stream, (uint16_t*)table, rows, d->n_orb, d->o_pad);
+      hipLaunchKernelGGL(k_zero_pad_s<uint16_t>, g, dim3(256), 0, stream, (uint16_t*)table, rows, d->n_col, d->o_pad);
     if ((rc = hip_fail(hipGetLastError(), "zero padding launch"))) return rc;
   }
   return SPL_OK;
@@ -232,10 +261,11 @@ int build_smoothing(const spl_desc* d, int64_t n_g, const int32_t* miller, const
   hipLaunchKernelGGL(k_twiddles, dim3((nt + 255) / 256), dim3(256), 0, stream, tw, d->grid[0], d->grid[1], d->grid[2]);
   int rc = hip_fail(hipGetLastError(), "twiddle launch");
   if (rc) return rc;
-  if ((rc = build_smoothing_one(d, n_g, miller, coef, 0, table, work, tw, stream))) return rc;
-  if (d->has_lap) {
-    char* lt = static_cast<char*>(table) + d->table_elems * d->elem_bytes;
-    if ((rc = build_smoothing_one(d, n_g, miller, coef, 1, lt, work, tw, stream))) return rc;
+  // tables in order: orbital, gradient components x, y, z (sep_grad), Laplacian (has_lap)
+  for (int t = 0; t < d->n_tables; ++t) {
+    const int comp = t == 0 ? COMP_VALUE : (d->sep_grad && t <= 3 ? t : COMP_LAP);
+    char* dst = static_cast<char*>(table) + t * d->table_elems * d->elem_bytes;
+    if ((rc = build_smoothing_one(d, n_g, miller, coef, comp, dst, work, tw, stream))) return rc;
   }
   return SPL_OK;
 }

@@ -30,13 +30,23 @@ def test_exports_every_declared_symbol():
     assert set(names) == set(P.EXPORTS)
 
 
-def test_struct_layout_matches_header():
-    # offsets follow the declaration order in pwspline.h
-    assert SplDesc.lattice.offset == 0
-    assert SplDesc.grid.offset == 72
-    assert SplDesc.ainv.offset == 96
-    assert ctypes.sizeof(SplDesc) == 96 + 9 * 8 * 2 + 6 * 8 + 8 + 4 * 8
-    assert ctypes.sizeof(SplItem) == 7 * 8
+def test_struct_layout_matches_header(tmp_path):
+    # compile the header with the host C compiler and compare every offset with the binding's
+    names = [f[0] for f in SplDesc._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "pwspline.h"\nint main(void) {\n'
+                   + "".join(f'  printf("{n} %zu\\n", offsetof(spl_desc, {n}));\n' for n in names)
+                   + '  printf("sizeof %zu\\n", sizeof(spl_desc));\n'
+                   + '  printf("item %zu\\n", sizeof(spl_item));\n  return 0;\n}\n')
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                        check=True).stdout.splitlines())
+    for n in names:
+        assert int(out[n]) == getattr(SplDesc, n).offset, n
+    assert int(out["sizeof"]) == ctypes.sizeof(SplDesc)
+    assert int(out["item"]) == ctypes.sizeof(SplItem)
 
 
 def test_desc_derived_fields_match_oracle_geometry():
@@ -174,3 +184,85 @@ def test_tile_validation_per_dtype():
             tile = (ctypes.c_int32 * 2)(64, opl)
             assert lib.spline_eval_vgl_tile(ctypes.byref(d), fake, 10, fake, fake, fake, fake, tile,
                                             None) == P.SPL_EINVAL
+
+
+# ---------------------------------------------------------------- representations and Bloch orbitals
+LAT = np.array([[7.0, 0.4, -0.3], [1.1, 6.2, 0.5], [-0.6, 0.9, 8.3]])
+
+
+def test_desc_sizes_of_the_representations():
+    d = P.spline_desc_init(LAT, (8, 9, 10), 5, "f32", has_lap=True, sep_grad=True)
+    assert d.n_tables == 5 and d.n_col == 5 and d.o_pad == 8
+    assert d.table_bytes == 5 * d.table_elems * 4 and d.gtable_bytes == 5 * d.table_elems * 4
+    d = P.spline_desc_init(LAT, (8, 9, 10), 5, "bf16", has_lap=True, sep_grad=True, basis="lagrange")
+    assert d.basis == P.SPL_LAGRANGE and d.n_tables == 5
+    d = P.spline_desc_init(LAT, (8, 9, 10), 5, "f64", kvec=(0.1, -0.2, 0.3))
+    assert d.bloch == 1 and d.n_col == 10 and d.o_pad == 10 and d.n_tables == 1
+    assert d.work_bytes == 8 * 9 * 10 * 10 * 8
+    assert list(d.kvec) == [0.1, -0.2, 0.3]
+    d = P.spline_desc_init(LAT, (8, 9, 10), 3, "bf16", has_lap=True, kvec=(0.0, 0.0, 0.5))
+    assert d.n_col == 6 and d.o_pad == 8 and d.n_tables == 2
+
+
+def _unchecked_desc(**kw):
+    d = SplDesc()
+    for i, x in enumerate(LAT.reshape(-1)):
+        d.lattice[i] = x
+    for i in range(3):
+        d.grid[i] = 8
+    d.n_orb = 4
+    for k, v in kw.items():
+        if k == "kvec":
+            for i in range(3):
+                d.kvec[i] = v[i]
+        else:
+            setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("kw", [
+    dict(basis=2), dict(sep_grad=2), dict(bloch=2), dict(reserved=1),
+    dict(sep_grad=1),                                   # five tables need has_lap
+    dict(basis=1, has_lap=1),                           # Lagrange needs separate gradients
+    dict(kvec=(0.1, 0.0, 0.0)),                         # k without bloch
+    dict(bloch=1, kvec=(float("nan"), 0.0, 0.0)),
+])
+def test_desc_rejects_inconsistent_representations(kw):
+    d = _unchecked_desc(**kw)
+    assert P.lib().spline_desc_init(ctypes.byref(d)) == P.SPL_EINVAL
+    assert P.lib().spline_last_error()
+
+
+def test_adjoint_and_batch_reject_other_representations():
+    fake = ctypes.c_void_p(256)        # never dereferenced: every call fails validation first
+    for kw in (dict(kvec=(0.1, 0.0, 0.0)), dict(has_lap=True, sep_grad=True),
+               dict(has_lap=True, sep_grad=True, basis="lagrange")):
+        d = P.spline_desc_init(LAT, (8, 8, 8), 4, "f32", **kw)
+        nb = ctypes.c_int64()
+        assert P.lib().spline_backward_work_bytes(ctypes.byref(d), 10, 0, ctypes.byref(nb)) == P.SPL_EUNSUPPORTED
+        rc = P.lib().spline_eval_vgl_backward(ctypes.byref(d), fake, 10, fake, fake, None, None, fake, None, 0,
+                                              None, 0, None)
+        assert rc == P.SPL_EUNSUPPORTED
+        item = SplItem(ctypes.pointer(d), fake, 10, fake, fake, fake, fake)
+        plan = ctypes.c_void_p()
+        assert P.lib().spline_batch_plan_create(ctypes.byref(item), 1, None, None, ctypes.byref(plan)) == \
+            P.SPL_EUNSUPPORTED
+
+
+def test_build_entry_points_check_the_representation():
+    fake = ctypes.c_void_p(256)
+    d = P.spline_desc_init(LAT, (8, 8, 8), 4, "f32", has_lap=True, sep_grad=True)
+    assert P.lib().spline_build(ctypes.byref(d), fake, fake, fake, fake, None) == P.SPL_EINVAL
+    d = P.spline_desc_init(LAT, (8, 8, 8), 4, "f32", has_lap=True, sep_grad=True, basis="lagrange")
+    assert P.lib().spline_build_smoothing(ctypes.byref(d), 5, fake, ctypes.c_void_p(512), fake, fake,
+                                          None) == P.SPL_EINVAL
+    assert P.lib().spline_build_tables(ctypes.byref(d), None, fake, None, None) == P.SPL_EINVAL
+
+
+def test_bloch_tiles_need_whole_pairs():
+    fake = ctypes.c_void_p(256)
+    d = P.spline_desc_init(LAT, (8, 8, 8), 4, "f64", kvec=(0.1, 0.2, 0.3))
+    odd = (ctypes.c_int32 * 2)(16, 1)
+    assert P.lib().spline_eval_vgl_tile(ctypes.byref(d), fake, 10, fake, fake, fake, fake, odd, None) == P.SPL_EINVAL
+    t = (ctypes.c_int32 * 2)()
+    assert P.lib().spline_tile_for(ctypes.byref(d), 10, t) == 0 and t[1] % 2 == 0

@@ -158,3 +158,72 @@ def test_deterministic_adjoint_at_fit_size():
     torch.cuda.synchronize()
     assert torch.equal(a, b)
     assert normwise(a.double().cpu().numpy(), c.double().cpu().numpy()) < 1e-5
+
+
+# ---------------------------------------------------------------- the other representations at full size
+@pytest.fixture(scope="module")
+def twist():
+    w = config(7)
+    s = w.system
+    f = s.grid_values()                      # periodic parts u, complex
+    pos = w.positions()
+    return dict(s=s, f=f, pos=pos, f_dev=to_dev(f, torch.complex128), pos_dev=to_dev(pos))
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_bloch_twist_full_size(twist, dtype):
+    """128 complex orbitals at the zone-corner twist on config 1's cell, autotuned tile."""
+    from oracle import bloch as obl
+    s = twist["s"]
+    d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype, kvec=s.k)
+    say("full size Bloch", s.name, dtype)
+    tab = P.spline_build(d, twist["f_dev"])
+    out = P.spline_eval_vgl(d, tab, twist["pos_dev"])
+    tile = P.spline_autotune(d, tab, twist["pos_dev"], *out)
+    out = P.spline_eval_vgl(d, tab, twist["pos_dev"], *out, tile=tile)
+    torch.cuda.synchronize()
+    k_orb = 8
+    idx = _sample(twist["pos"].shape[0])
+    u = twist["f"][..., :k_orb]
+    beta = obuild.build_interp(np.ascontiguousarray(u.real)) + 1j * obuild.build_interp(np.ascontiguousarray(u.imag))
+    ref = obl.eval_bloch_vgl(beta, s.lattice, s.k, twist["pos"][idx])
+    got = [out[0][idx, :k_orb], out[1][idx, :, :k_orb], out[2][idx, :k_orb]]
+    got = [g.cpu().numpy().astype(np.complex128) for g in got]
+    gv, gg, gd, _ = GATES[dtype]
+    assert normwise(got[0], ref[0]) <= gv
+    assert normwise(got[1], ref[1]) <= gg
+    assert normwise(got[2], ref[2]) <= gd
+
+
+@pytest.fixture(scope="module")
+def mgo96_grad(mgo96):
+    return mgo96["s"].grid_gradient()        # [3][96^3][256]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("basis", ["bspline", "lagrange"])
+def test_mgo96_separate_tables_full_size(mgo96, mgo96_grad, basis):
+    """Five separate FP32 tables (orbital, gradient, Laplacian) of all 256 orbitals on the 96^3 grid:
+    the bench's separate-table forms, autotuned tile; sampled against the oracle."""
+    from oracle import separate as osep
+    s = mgo96["s"]
+    d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, "f32", has_lap=True, sep_grad=True, basis=basis)
+    say("full size separate tables", s.name, basis)
+    vals = torch.stack([mgo96["f_dev"]] + [to_dev(g) for g in mgo96_grad] + [mgo96["lf_dev"]])
+    tab = P.spline_build_tables(d, vals)
+    del vals
+    out = P.spline_eval_vgl(d, tab, mgo96["pos_dev"])
+    tile = P.spline_autotune(d, tab, mgo96["pos_dev"], *out)
+    out = P.spline_eval_vgl(d, tab, mgo96["pos_dev"], *out, tile=tile)
+    torch.cuda.synchronize()
+    k_orb = 16
+    grids = [mgo96["f"], *mgo96_grad, mgo96["lf"]]
+    grids = [np.ascontiguousarray(g[..., :k_orb]) for g in grids]
+    tabs = [obuild.build_interp(g) for g in grids] if basis == "bspline" else grids
+    idx = _sample(mgo96["pos"].shape[0])
+    ref = osep.eval_separate(tabs, s.lattice, mgo96["pos"][idx], basis)
+    got = [out[0][idx, :k_orb], out[1][idx, :, :k_orb], out[2][idx, :k_orb]]
+    got = [g.double().cpu().numpy() for g in got]
+    for g, r in zip(got, ref):
+        assert normwise(g, r) <= 1e-5

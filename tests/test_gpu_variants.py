@@ -1,0 +1,321 @@
+"""Parity of the other representations on the GPU against the FP64 oracle: five separate tables
+(cubic B-spline coefficients or Lagrange grid values; App. A, Sec. III A, Fig. 1) and Bloch
+orbitals exp(i k.r) u(r) (Sec. I) with the Laplacian from derivatives, from a separate table, or
+with five separate tables; their builds (interpolating, Lagrange cast, smoothing); launch-shape
+invariance and the degenerate cases."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1309_6250_amd as P
+from oracle import build as obuild, evaluate as oeval, lagrange as olag, separate as osep, bloch as obl
+from oracle import smoothing as osm, quantize as oq
+from workloads import config, make_system
+from gpu_helpers import say, to_dev, normwise, assert_elementwise, coordinate_rounding, DEV, U_ACC
+
+pytestmark = pytest.mark.gpu
+
+SKEW = np.array([[7.0, 0.4, -0.3], [1.1, 6.2, 0.5], [-0.6, 0.9, 8.3]])
+PARITY = {"f64": 1e-12, "f32": 4e-6, "bf16": 4e-6}          # kernel parity (same stored values), normwise
+GATE = {"f64": (1e-10,) * 3, "f32": (1e-5,) * 3, "bf16": (5e-3, 1e-2, 5e-3)}   # end to end, separate tables
+GATE_DERIV = {"f64": (1e-10,) * 3, "f32": (1e-5,) * 3, "bf16": (5e-3, 1e-2, 5e-2)}
+
+
+def real_cases():
+    return [make_system("sep-skew", SKEW, (10, 9, 11), 5, 2.2, 2.0, (41, 1)), config(0).system]
+
+
+def bloch_cases():
+    return [config(6).system,
+            make_system("bloch-skew", SKEW, (10, 9, 11), 3, 2.0, 2.0, (41, 2), kvec=(0.21, -0.13, 0.33))]
+
+
+def points(s, n=700):
+    """Seeded uniform points plus grid points, far images and negative coordinates (ragged count)."""
+    pos = s.positions(n)
+    idx = np.random.default_rng(42).integers(0, np.array(s.grid), size=(9, 3))
+    knots = (idx / np.array(s.grid)) @ s.lattice
+    far = pos[:6] + np.array([3.0, -7.0, 11.0]) @ s.lattice
+    return np.concatenate([pos, knots, far, -pos[6:13]])
+
+
+def cols(x):
+    """complex [..., n] -> real [..., 2n] with (re, im) adjacent; real arrays unchanged."""
+    x = np.asarray(x)
+    if not np.iscomplexobj(x):
+        return x
+    return np.stack([x.real, x.imag], -1).reshape(*x.shape[:-1], 2 * x.shape[-1])
+
+
+def quant(t, dtype):
+    t = np.asarray(t)
+    if np.iscomplexobj(t):
+        return oq.quantized(np.ascontiguousarray(t.real), dtype) + 1j * oq.quantized(np.ascontiguousarray(t.imag), dtype)
+    return oq.quantized(t, dtype)
+
+
+def upload(desc, tables, dtype):
+    """Device table [n_tables][N1][N2][N3][o_pad] in the storage dtype (padding zeroed)."""
+    arr = np.zeros(tuple(P.table_shape(desc)))
+    for q, t in enumerate(tables):
+        c = cols(t)
+        arr[q, ..., :c.shape[-1]] = c
+    if dtype == "f64":
+        return to_dev(arr)
+    if dtype == "f32":
+        return to_dev(oq.to_f32(arr), torch.float32)
+    return torch.from_numpy(oq.to_bf16_bits(arr).view(np.int16)).to(DEV).view(torch.bfloat16)
+
+
+def gpu_eval(desc, table, pos, tile=None, what="vgl"):
+    say(what, desc.grid[0], desc.n_orb, desc.dtype, "basis", desc.basis, "sep", desc.sep_grad, "bloch", desc.bloch,
+        len(pos), tile)
+    x = to_dev(pos)
+    out = P.spline_eval_vgl(desc, table, x, tile=tile) if what == "vgl" else (P.spline_eval_v(desc, table, x),)
+    torch.cuda.synchronize()
+    cast = np.complex128 if desc.bloch else np.float64
+    return [o.cpu().numpy().astype(cast) for o in out]
+
+
+def interp_tables(grids):
+    """Interpolating coefficients of (possibly complex) grid values."""
+    out = []
+    for g in grids:
+        if np.iscomplexobj(g):
+            out.append(obuild.build_interp(np.ascontiguousarray(g.real)) + 1j * obuild.build_interp(np.ascontiguousarray(g.imag)))
+        else:
+            out.append(obuild.build_interp(np.ascontiguousarray(g)))
+    return out
+
+
+def sep_grids(s):
+    return [s.grid_values()] + list(s.grid_gradient()) + [s.grid_laplacian()]
+
+
+_cache = {}
+
+
+def case_tables(s, basis):
+    key = (s.name, basis)
+    if key not in _cache:
+        g = sep_grids(s)
+        _cache[key] = (g, interp_tables(g) if basis == "bspline" else g)
+    return _cache[key]
+
+
+# ---------------------------------------------------------------- five separate tables, real orbitals
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("basis", ["bspline", "lagrange"])
+@pytest.mark.parametrize("k", [0, 1])
+def test_separate_tables_kernel_parity(k, basis, dtype):
+    s = real_cases()[k]
+    _, tabs = case_tables(s, basis)
+    pos = points(s)
+    d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype, has_lap=True, sep_grad=True, basis=basis)
+    got = gpu_eval(d, upload(d, tabs, dtype), pos)
+    tq = [quant(t, dtype) for t in tabs]
+    ref = osep.eval_separate(tq, s.lattice, pos, basis)
+    du = coordinate_rounding(d, s.lattice, pos, dtype)
+    u = U_ACC[dtype]
+    names = ("V", "grad_x", "grad_y", "grad_z", "lap")
+    outs = [got[0], got[1][:, 0], got[1][:, 1], got[1][:, 2], got[2]]
+    refs = [ref[0], ref[1][:, 0], ref[1][:, 1], ref[1][:, 2], ref[2]]
+    for q in range(5):
+        if basis == "bspline":
+            acc = oeval.eval_abs_bound(tq[q], s.lattice, pos)[0]
+            coord = oeval.coordinate_error_bound(tq[q], s.lattice, pos, du)[0]
+        else:
+            acc, coord = olag.eval_abs_bound(tq[q], s.lattice, pos, du)
+        assert_elementwise(outs[q], refs[q], 64 * u * acc + coord, 4.0, names[q])
+        assert normwise(outs[q], refs[q]) <= PARITY[dtype], names[q]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("basis", ["bspline", "lagrange"])
+def test_separate_tables_build_and_end_to_end(basis, dtype):
+    s = real_cases()[0]
+    grids, tabs = case_tables(s, basis)
+    d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype, has_lap=True, sep_grad=True, basis=basis)
+    say("spline_build_tables", basis, dtype)
+    table = P.spline_build_tables(d, [to_dev(g) for g in grids])
+    torch.cuda.synchronize()
+    t = (table.float() if dtype == "bf16" else table).double().cpu().numpy()
+    for q in range(5):
+        ref = quant(tabs[q], dtype)
+        if basis == "lagrange" or dtype == "f64":
+            tol = 0.0 if basis == "lagrange" else 1e-12 * np.abs(ref).max()
+            assert np.abs(t[q, ..., :s.n_orb] - ref).max() <= tol
+        else:
+            ulp = (2.0**-23 if dtype == "f32" else 2.0**-7) * np.abs(ref)
+            assert np.all(np.abs(t[q, ..., :s.n_orb] - ref) <= ulp + 1e-300)
+    assert np.all(t[..., s.n_orb:] == 0)
+    pos = points(s)
+    got = gpu_eval(d, table, pos)
+    ref = osep.eval_separate(tabs, s.lattice, pos, basis)
+    for g, r, gate in zip(got, ref, GATE[dtype]):
+        assert normwise(g, r) <= gate
+
+
+# ---------------------------------------------------------------- Bloch orbitals
+KINDS = ["derivative", "separate_lap", "separate_bspline", "separate_lagrange"]
+
+
+def bloch_desc(s, kind, dtype):
+    if kind == "derivative":
+        return P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype, kvec=s.k)
+    if kind == "separate_lap":
+        return P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype, has_lap=True, kvec=s.k)
+    basis = "bspline" if kind == "separate_bspline" else "lagrange"
+    return P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype, has_lap=True, sep_grad=True, basis=basis, kvec=s.k)
+
+
+def bloch_tables(s, kind):
+    key = (s.name, kind)
+    if key not in _cache:
+        if kind == "derivative":
+            g = [s.grid_values()]
+        elif kind == "separate_lap":
+            g = [s.grid_values(), s.grid_laplacian()]
+        else:
+            g = sep_grids(s)
+        _cache[key] = (g, g if kind == "separate_lagrange" else interp_tables(g))
+    return _cache[key]
+
+
+def bloch_oracle(s, kind, tabs, pos):
+    if kind == "derivative":
+        return obl.eval_bloch_vgl(tabs[0], s.lattice, s.k, pos)
+    if kind == "separate_lap":
+        return obl.eval_bloch_vgl(tabs[0], s.lattice, s.k, pos, lap_beta=tabs[1])
+    basis = "bspline" if kind == "separate_bspline" else "lagrange"
+    return obl.eval_bloch_separate(tabs, s.lattice, s.k, pos, basis)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("k", [0, 1])
+def test_bloch_kernel_parity(k, kind, dtype):
+    s = bloch_cases()[k]
+    assert s.nyquist_ok()
+    _, tabs = bloch_tables(s, kind)
+    pos = points(s)
+    d = bloch_desc(s, kind, dtype)
+    got = gpu_eval(d, upload(d, tabs, dtype), pos)
+    ref = bloch_oracle(s, kind, [quant(t, dtype) for t in tabs], pos)
+    for g, r, name in zip(got, ref, ("V", "grad", "lap")):
+        assert normwise(g, r) <= PARITY[dtype], (name, normwise(g, r))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("kind", KINDS)
+def test_bloch_build_and_end_to_end(kind, dtype):
+    s = bloch_cases()[0]
+    grids, tabs = bloch_tables(s, kind)
+    d = bloch_desc(s, kind, dtype)
+    say("Bloch build", kind, dtype)
+    if kind in ("derivative", "separate_lap"):
+        table = P.spline_build(d, to_dev(grids[0], torch.complex128),
+                               None if kind == "derivative" else to_dev(grids[1], torch.complex128))
+    else:
+        table = P.spline_build_tables(d, [to_dev(g, torch.complex128) for g in grids])
+    torch.cuda.synchronize()
+    pos = points(s)
+    got = gpu_eval(d, table, pos)
+    ref = bloch_oracle(s, kind, tabs, pos)
+    gates = GATE_DERIV[dtype] if kind == "derivative" else GATE[dtype]
+    for g, r, gate, name in zip(got, ref, gates, ("V", "grad", "lap")):
+        assert normwise(g, r) <= gate, (name, normwise(g, r))
+
+
+def test_bloch_gpu_approaches_planewave():
+    s = config(6).system
+    grids, _ = bloch_tables(s, "separate_lap")
+    d = bloch_desc(s, "separate_lap", "f64")
+    table = P.spline_build(d, to_dev(grids[0], torch.complex128), to_dev(grids[1], torch.complex128))
+    pos = s.positions(400)
+    got = gpu_eval(d, table, pos)
+    ref = obl.pw_bloch_vgl(s.gvecs, s.coef, s.k, pos)
+    for g, r, tol in zip(got, ref, (0.02, 0.05, 0.05)):
+        assert np.abs(g - r).mean() / np.abs(r).mean() < tol
+
+
+# ---------------------------------------------------------------- launch shapes, values only, degenerate cases
+VARIANTS = [("sep_bspline", False), ("sep_lagrange", False), ("bloch", True), ("bloch_sep_lagrange", True)]
+
+
+def _variant(name, dtype):
+    s = bloch_cases()[1] if name.startswith("bloch") else real_cases()[0]
+    if name == "bloch":
+        kind = "derivative"
+    elif name == "bloch_sep_lagrange":
+        kind = "separate_lagrange"
+    else:
+        kind = None
+    if kind is not None:
+        _, tabs = bloch_tables(s, kind)
+        d = bloch_desc(s, kind, dtype)
+    else:
+        basis = "bspline" if name == "sep_bspline" else "lagrange"
+        _, tabs = case_tables(s, basis)
+        d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype, has_lap=True, sep_grad=True, basis=basis)
+    return s, d, upload(d, tabs, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("name,bloch", VARIANTS)
+def test_variant_outputs_identical_for_every_tile(name, bloch, dtype):
+    s, d, table = _variant(name, dtype)
+    pos = points(s, 333)
+    opls = {"f64": (1, 2), "f32": (1, 2, 4), "bf16": (2, 4, 8)}[dtype]
+    base = None
+    for g in (2, 8, 64, 256):
+        for opl in opls:
+            if bloch and opl % 2:
+                continue
+            out = gpu_eval(d, table, pos, tile=(g, opl))
+            if base is None:
+                base = out
+            else:
+                for a, b in zip(out, base):
+                    assert np.array_equal(a, b, equal_nan=True), (g, opl)
+    v = gpu_eval(d, table, pos, what="v")[0]
+    assert np.array_equal(v, base[0], equal_nan=True)
+
+
+@pytest.mark.parametrize("name,bloch", VARIANTS)
+def test_variant_nan_points_and_empty(name, bloch):
+    s, d, table = _variant(name, "f32")
+    pos = points(s, 40)
+    pos[3] = [np.nan, 0.0, 1.0]
+    pos[7] = [np.inf, 2.0, 1.0]
+    got = gpu_eval(d, table, pos)
+    for o in got:
+        assert np.all(np.isnan(o[3])) and np.all(np.isnan(o[7]))
+        assert np.all(np.isfinite(np.delete(o, [3, 7], axis=0)))
+    empty = torch.empty((0, 3), dtype=torch.float64, device=DEV)
+    out = P.spline_eval_vgl(d, table, empty)
+    torch.cuda.synchronize()
+    assert all(o.shape[0] == 0 for o in out)
+
+
+# ---------------------------------------------------------------- smoothing build of the variants
+def test_smoothing_separate_gradients_and_bloch_match_oracle():
+    cases = [make_system("sm-sep", SKEW, (10, 12, 14), 4, 2.0, 2.0, (43, 1)),
+             make_system("sm-bloch", SKEW, (10, 12, 14), 3, 2.0, 2.0, (43, 2), kvec=(0.21, -0.13, 0.33))]
+    for s in cases:
+        assert s.nyquist_ok()
+        for sep in (False, True):
+            d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, "f64", has_lap=True, sep_grad=sep,
+                                   kvec=s.k if s.bloch else None)
+            say("smoothing", s.name, "sep", sep)
+            tab = P.spline_build_smoothing(d, torch.from_numpy(s.miller.astype(np.int32)).to(DEV),
+                                           torch.from_numpy(s.coef).to(DEV))
+            torch.cuda.synchronize()
+            t = tab.cpu().numpy()
+            q = s.qvecs
+            mults = [np.ones(s.n_g)] + ([1j * q[:, a] for a in range(3)] if sep else []) + [-(q * q).sum(1)]
+            assert len(mults) == d.n_tables
+            for i, m in enumerate(mults):
+                ref = cols(osm.build_smoothing(s.miller, s.coef * m[None, :], s.grid, keep_complex=s.bloch))
+                assert np.abs(t[i, ..., :d.n_col] - ref).max() <= 1e-12 * np.abs(ref).max(), (s.name, sep, i)
+            assert np.all(t[..., d.n_col:] == 0)

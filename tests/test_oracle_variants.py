@@ -47,6 +47,15 @@ def test_lagrange_weights_match_printed_polynomials():
         np.testing.assert_allclose(w[:, a], centred(t - l), atol=1e-15)
 
 
+def test_lagrange_derivative_weights_match_printed_polynomials():
+    rows, _ = _golden_lagrange()
+    t = np.linspace(0.0, 0.999, 101)
+    dw = lagrange.weights(t, 1)
+    for a, l in enumerate((-1, 0, 1, 2)):
+        np.testing.assert_allclose(dw[:, a], np.polyval(np.polyder(rows[l]), t), atol=1e-14)
+    np.testing.assert_allclose(dw.sum(1), 0.0, atol=1e-14)
+
+
 def test_lagrange_interpolates_and_reproduces_cubics():
     np.testing.assert_array_equal(lagrange.weights(np.array([0.0]))[0], [0.0, 1.0, 0.0, 0.0])
     rng = np.random.default_rng(60)

@@ -29,6 +29,9 @@ Plain numpy in float64, written for a reader to check against the paper by eye:
              (direct approximations of the derivatives, Sec. III A, Fig. 1)
   bloch      Bloch orbitals e^{ik.r} u(r): planewave sums and the product rule
              over a complex periodic interpolant (Sec. I)
+  ppspline   piecewise-polynomial form of the interpolating cubic spline: 8
+             numbers per grid point, 2x2x2 corners per point (App. A,
+             Piecewise-polynomial-form splines)
 
 Basis normalization: the paper scales the cubic B-spline so that its maximum is
 1 (C = 3/2 in the recurrence of App. A); this oracle uses the standard
@@ -37,4 +40,4 @@ The spline *function* is the same either way; only the stored coefficients
 differ, by the constant factor (3/2)^3.
 """
 from . import bspline, pw, build, evaluate, adjoint, quantize, smoothing, fit  # noqa: F401
-from . import lagrange, separate, bloch  # noqa: F401
+from . import lagrange, separate, bloch, ppspline  # noqa: F401

@@ -286,3 +286,69 @@ def test_bloch_and_gradient_grid_samples_equal_planewave_sums():
         np.testing.assert_allclose(pick(w), l, atol=1e-12 * np.abs(l).max())
     assert config(6).system.nyquist_ok() and config(7).system.nyquist_ok()
     assert np.all(np.linalg.norm(config(6).system.qvecs, axis=1) < 4.0)
+
+
+# ---------------------------------------------------------------- pp-spline form
+from oracle import ppspline
+
+
+def _golden_pp():
+    basis, centred = {}, {}
+    with open(os.path.join(GOLDEN, "ppspline_basis_paper.txt")) as fh:
+        for line in fh:
+            f = line.split()
+            if not f or f[0].startswith("#"):
+                continue
+            if f[0] == "basis":
+                basis[(int(f[1]), int(f[2]))] = [float(Fraction(x)) for x in f[3:]]
+            elif f[0] == "centred":
+                centred[int(f[1])] = [float(Fraction(x)) for x in f[2:]]
+    return basis, centred
+
+
+def test_pp_basis_matches_printed_polynomials_and_centred_form():
+    basis, centred = _golden_pp()
+    t = np.linspace(0.0, 0.999, 101)
+    w = ppspline.basis(t)
+    for (i, kappa), c in basis.items():
+        np.testing.assert_allclose(w[:, i, kappa - 1], np.polyval(c, t), atol=1e-15)
+        # grid-centred picture: corner i sits at xi = t - i
+        np.testing.assert_allclose(w[:, i, kappa - 1], np.polyval(centred[kappa], np.abs(t - i)), atol=1e-15)
+    # the value kind interpolates linearly; the derivative kind vanishes at both corners
+    np.testing.assert_allclose(ppspline.basis(np.array([0.0, 1.0]))[:, :, 1], 0.0, atol=1e-16)
+
+
+def test_pp_build_values_and_second_differences_of_bspline_coefficients():
+    s = make_system("pp", SKEW, (9, 8, 10), 3, 2.0, 2.0, (44, 1))
+    f = s.grid_values()
+    sig = ppspline.build_pp(f)
+    beta = build.build_interp(f)
+    np.testing.assert_array_equal(sig[..., 0, :], f)
+    # at a knot the cubic B-spline's weights are (1, 4, 1)/6 for the value and (1, -2, 1) for the second
+    # derivative (grid units), so each sigma is the B-spline coefficients filtered along every axis by
+    # one of the two: sigma^{2,1,1} = D2_x B_y B_z beta, ..., sigma^{2,2,2} = D2_x D2_y D2_z beta
+    d2 = lambda a, ax: np.roll(a, 1, ax) - 2 * a + np.roll(a, -1, ax)
+    bv = lambda a, ax: (np.roll(a, 1, ax) + 4 * a + np.roll(a, -1, ax)) / 6
+    for kappa in (1, 2):
+        for mu in (1, 2):
+            for nu in (1, 2):
+                ref = beta
+                for ax, k in enumerate((kappa, mu, nu)):
+                    ref = d2(ref, ax) if k == 2 else bv(ref, ax)
+                got = sig[..., 4 * (kappa - 1) + 2 * (mu - 1) + (nu - 1), :]
+                np.testing.assert_allclose(got, ref, atol=1e-12 * np.abs(ref).max())
+
+
+def test_pp_spline_equals_interpolating_bspline_everywhere():
+    # the periodic interpolating cubic spline is unique: both forms give the same function
+    for s in (make_system("pp-skew", SKEW, (9, 8, 10), 3, 2.0, 2.0, (44, 2)), config(0).system):
+        f = s.grid_values()
+        lf = s.grid_laplacian()
+        pos = s.positions(300)
+        a = ppspline.eval_pp_vgl(ppspline.build_pp(f), s.lattice, pos, lap_sigma=ppspline.build_pp(lf))
+        b = evaluate.eval_vgl(build.build_interp(f), s.lattice, pos, lap_beta=build.build_interp(lf))
+        for x, y in zip(a, b):
+            np.testing.assert_allclose(x, y, atol=1e-11 * np.abs(y).max())
+        dflt = ppspline.eval_pp_vgl(ppspline.build_pp(f), s.lattice, pos)[2]
+        np.testing.assert_allclose(dflt, evaluate.eval_vgl(build.build_interp(f), s.lattice, pos)[2],
+                                   atol=1e-11 * np.abs(dflt).max())

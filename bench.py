@@ -10,7 +10,8 @@ Also reported on the same JSON line:
   forms     the precision forms (FP64 / FP32 / BF16 tables, with and without a separate
             Laplacian spline) on the Si cell and on the MgO-like cell (256 orbitals, 96^3
             grid, 512 x 128 points: tables of 0.45-3.6 GB, far beyond on-chip caches); on the
-            MgO-like cell also five separate tables (B-spline or Lagrange, FP64 / FP32); Bloch
+            MgO-like cell also five separate tables (B-spline or Lagrange, FP64 / FP32) and the
+            pp-spline form (FP64 / FP32); Bloch
             orbitals at a twist on the Si cell (FP64 / FP32); each with throughput, algorithmic
             bandwidth and its errors against the planewave sum and against the FP64 table's
             outputs;
@@ -112,12 +113,13 @@ class Workload:
         return out
 
 
-def run_form(wl, dtype, has_lap, steps, warmup, tune=True, tile=None, sep=None, fields=None):
+def run_form(wl, dtype, has_lap, steps, warmup, tune=True, tile=None, sep=None, fields=None, basis="bspline"):
     """Build, autotune (or take `tile`) and time one form; returns (record, desc, table, outputs).
 
-    sep: None (derivatives of the orbital table, plus a separate Laplacian table with has_lap) or
-    "bspline" / "lagrange" (five separate tables built from `fields`, the stacked device grid
-    values).  Bloch orbitals follow from the workload's crystal momentum."""
+    sep: None (derivatives of the orbital table, plus a separate Laplacian table with has_lap; basis
+    "bspline" or its piecewise-polynomial form "pp") or "bspline" / "lagrange" (five separate tables
+    built from `fields`, the stacked device grid values).  Bloch orbitals follow from the workload's
+    crystal momentum."""
     import torch
     import paper_1309_6250_amd as P
     s = wl.s
@@ -125,7 +127,7 @@ def run_form(wl, dtype, has_lap, steps, warmup, tune=True, tile=None, sep=None, 
     if sep:
         d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype, has_lap=True, sep_grad=True, basis=sep, kvec=kvec)
     else:
-        d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype, has_lap=has_lap, kvec=kvec)
+        d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype, has_lap=has_lap, kvec=kvec, basis=basis)
     work = None if sep == "lagrange" else torch.empty(d.work_bytes // 8, dtype=torch.float64, device="cuda")
     table = P.new_table(d)
     if sep:
@@ -556,12 +558,14 @@ def main():
         key, dtype, *rest = args.only.split("-")
         lap = bool(rest and rest[0] == "lap")
         sep = rest[1] if rest and rest[0] == "sep" else None
+        basis = "pp" if rest and rest[0] == "pp" else "bspline"
         wl = Workload(int(key[1:]), lap=lap)
         _gpu_ready()
         wl.upload()
         fields = grid_fields_gpu(wl.s) if sep else None
         tile = None if args.tile is None else tuple(int(x) for x in args.tile.split(","))
-        rec, *_ = run_form(wl, dtype, lap or bool(sep), args.steps, args.warmup, tile=tile, sep=sep, fields=fields)
+        rec, *_ = run_form(wl, dtype, lap or bool(sep), args.steps, args.warmup, tile=tile, sep=sep, fields=fields,
+                           basis=basis)
         print(json.dumps({"only": args.only, **rec}), flush=True)
         return
 
@@ -644,7 +648,21 @@ def main():
                     f"({100 * rec['frac_hbm_peak']:.0f}% of HBM peak)")
                 del t, o
                 torch.cuda.empty_cache()
-        del fields, wl2
+        del fields
+        torch.cuda.empty_cache()
+        # the same interpolating spline in piecewise-polynomial form: 8 numbers per grid point, the
+        # 2x2x2 corners of a point's cell (8 contiguous runs of 8 rows instead of 16 runs of 4)
+        for dtype in ("f64", "f32"):
+            rec, d, t, o = run_form(wl2, dtype, False, args.steps, args.warmup, basis="pp")
+            name = f"c2-{dtype}-pp"
+            rec["accuracy"] = accuracy(wl2, dtype, "pp", o)
+            rec["traffic"] = traffic_for(name)
+            forms[name] = rec
+            log(f"{name}: {rec['evals_per_s']:.3e} evals/s, {rec['alg_GBps']:.0f} GB/s "
+                f"({100 * rec['frac_hbm_peak']:.0f}% of HBM peak)")
+            del t, o
+            torch.cuda.empty_cache()
+        del wl2
         torch.cuda.empty_cache()
         # Bloch orbitals at a twist: complex orbitals, twice the columns of config 1
         wl7 = Workload(7).upload()

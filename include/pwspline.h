@@ -74,7 +74,7 @@ enum {
 enum { SPL_DETERMINISTIC = 1 };
 
 /* basis of the interpolant (spl_desc.basis) */
-enum { SPL_BSPLINE = 0, SPL_LAGRANGE = 1 };
+enum { SPL_BSPLINE = 0, SPL_LAGRANGE = 1, SPL_PPSPLINE = 2 };
 
 /*
  * Descriptor of one coefficient table.  The caller fills the first block and
@@ -88,9 +88,11 @@ typedef struct spl_desc {
   int32_t n_orb;          /* number of orbitals (>= 1) */
   int32_t dtype;          /* SPL_F64 / SPL_F32 / SPL_BF16 */
   int32_t has_lap;        /* 1: a separate Laplacian spline follows the orbital table (Sec. III A) */
-  int32_t basis;          /* SPL_BSPLINE (App. A, B-splines) or SPL_LAGRANGE (App. A, Lagrange
+  int32_t basis;          /* SPL_BSPLINE (App. A, B-splines); SPL_LAGRANGE (App. A, Lagrange
                              interpolation: the table holds grid values; needs sep_grad, since the
-                             Lagrange interpolant has no continuous derivatives) */
+                             Lagrange interpolant has no continuous derivatives); SPL_PPSPLINE (App. A,
+                             piecewise-polynomial form of the same interpolating spline: 8 numbers per
+                             grid point, [N1][N2][N3][8][o_pad] per table; no sep_grad) */
   int32_t sep_grad;       /* 1: separate gradient tables too (needs has_lap): five tables in the order
                              orbital, d/dx, d/dy, d/dz (Cartesian), Laplacian, each read by value */
   int32_t bloch;          /* 1: Bloch orbitals exp(i k.r) u(r) (Sec. I); n_orb counts complex orbitals */
@@ -102,7 +104,7 @@ typedef struct spl_desc {
   double  metric[6];      /* M = J J^T as M00 M11 M22 M01 M02 M12 */
   int32_t o_pad;          /* orbital stride of a table row: n_orb rounded up to 16 bytes of storage */
   int32_t elem_bytes;     /* 8 / 4 / 2 */
-  int64_t table_elems;    /* N1*N2*N3*o_pad: elements of ONE table */
+  int64_t table_elems;    /* N1*N2*N3*o_pad (x8 for SPL_PPSPLINE): elements of ONE table */
   int64_t table_bytes;    /* bytes of the full table buffer: n_tables * table_elems * elem_bytes */
   int64_t work_bytes;     /* bytes of the FP64 workspace spline_build needs: N1*N2*N3*n_col*8 */
   int64_t gtable_bytes;   /* bytes of a coefficient-gradient buffer: n_tables * table_elems * (8 or 4) */
@@ -115,8 +117,8 @@ typedef struct spl_desc {
  * enqueues nothing.  Errors: d == NULL, n_orb < 1, non-finite or singular lattice
  * -> SPL_EINVAL; any N_i outside [4, 1024] -> SPL_EGRID; unknown dtype ->
  * SPL_EDTYPE; has_lap, sep_grad or bloch not 0/1, unknown basis, reserved != 0,
- * sep_grad without has_lap, SPL_LAGRANGE without sep_grad, a non-finite kvec, or a
- * nonzero kvec without bloch -> SPL_EINVAL.  N_i >= 4 keeps the four rows of a
+ * sep_grad without has_lap, SPL_LAGRANGE without sep_grad, SPL_PPSPLINE with sep_grad, a
+ * non-finite kvec, or a nonzero kvec without bloch -> SPL_EINVAL.  N_i >= 4 keeps the four rows of a
  * point's block distinct along each axis.
  */
 int spline_desc_init(spl_desc* d);
@@ -135,6 +137,9 @@ int spline_desc_init(spl_desc* d);
  *   table      device, d->table_bytes, written completely (padding zeroed)
  *   work       device, d->work_bytes of scratch FP64, contents undefined afterwards
  * grid_vals and lap_vals are not modified.  None of the buffers may overlap.
+ * SPL_PPSPLINE: the same solve kept in FP64, then the 8 numbers of every grid point (the value,
+ * second and mixed derivatives of the spline at the knot in grid units, Eq. pp-splinecoefficients3),
+ * each the coefficients filtered along every axis by the knot weights (1, 4, 1)/6 or (1, -2, 1).
  * For SPL_LAGRANGE or sep_grad descriptors use spline_build_tables (-> SPL_EINVAL here).
  */
 int spline_build(const spl_desc* d, const double* grid_vals, const double* lap_vals,
@@ -147,9 +152,9 @@ int spline_build(const spl_desc* d, const double* grid_vals, const double* lap_v
  *          at r = a (i/N1, j/N2, k/N3) (with bloch: periodic parts, (re, im) per orbital)
  *   table  device, d->table_bytes, written completely (padding zeroed)
  *   work   device, d->work_bytes of scratch FP64 (unused for SPL_LAGRANGE, may be NULL then)
- * SPL_BSPLINE tables are interpolating coefficients, solved as in spline_build; SPL_LAGRANGE
- * tables are the grid values themselves, rounded once into the storage dtype (App. A,
- * Eq. lagrangeinterpolation3).  vals is not modified.
+ * SPL_BSPLINE and SPL_PPSPLINE tables are built as in spline_build; SPL_LAGRANGE tables are the
+ * grid values themselves, rounded once into the storage dtype (App. A, Eq. lagrangeinterpolation3).
+ * vals is not modified.
  */
 int spline_build_tables(const spl_desc* d, const double* vals, void* table, void* work, void* stream);
 
@@ -169,7 +174,7 @@ int spline_build_tables(const spl_desc* d, const double* vals, void* table, void
  *   work    device, spline_smoothing_work_bytes() bytes, 256-byte aligned, scratch
  * The tables after the first hold the smoothing splines of the gradient's periodic parts,
  * coefficients i (k+G)_c c_G (sep_grad), and of the Laplacian's, -|k+G|^2 c_G (has_lap).
- * SPL_LAGRANGE descriptors -> SPL_EINVAL.  The grid must give every G its own Fourier bin
+ * SPL_LAGRANGE and SPL_PPSPLINE descriptors -> SPL_EINVAL.  The grid must give every G its own Fourier bin
  * (N_i > 2 max |n_i|); planewaves that share a bin are added.  Computed in FP64 by separable
  * inverse DFTs, rounded once into the storage dtype.
  */
@@ -185,8 +190,9 @@ int spline_smoothing_work_bytes(const spl_desc* d, int64_t* bytes);
  *   table  device, as written by spline_build
  *   pos    device, FP64 [n_pts][3]
  *   v      device, [n_pts][n_col] (FP64 for SPL_F64 tables, else FP32)
- * SPL_LAGRANGE tables use the Lagrange weights (App. A, Eq. lagrangeinterpolation3); Bloch
- * orbitals are multiplied by exp(i k.r).  n_pts == 0 is a no-op.
+ * SPL_LAGRANGE tables use the Lagrange weights (App. A, Eq. lagrangeinterpolation3), SPL_PPSPLINE
+ * tables the 2x2x2 corners and the pp basis (Eq. pp-splineinterpolation3); Bloch orbitals are
+ * multiplied by exp(i k.r).  n_pts == 0 is a no-op.
  */
 int spline_eval_v(const spl_desc* d, const void* table, int64_t n_pts, const double* pos,
                   void* v, void* stream);

@@ -15,7 +15,7 @@ The phase uses the unfolded Cartesian position r.
 """
 import numpy as np
 
-from . import evaluate, separate
+from . import evaluate, separate, ppspline
 
 
 def pw_bloch_vgl(gvecs, coef, kvec, pos, chunk=256):
@@ -44,23 +44,30 @@ def phase(kvec, pos):
     return np.exp(1j * (np.asarray(pos, dtype=np.float64) @ np.asarray(kvec, dtype=np.float64)))
 
 
-def _complex_vgl(beta, lattice, pos, lap_beta=None):
+def _complex_vgl(beta, lattice, pos, lap_beta=None, form="bspline"):
     """V, grad, lap of a complex-coefficient spline: real and imaginary parts evaluated apart."""
     beta = np.asarray(beta)
     lre = None if lap_beta is None else np.ascontiguousarray(np.real(lap_beta))
     lim = None if lap_beta is None else np.ascontiguousarray(np.imag(lap_beta))
-    re = evaluate.eval_vgl(np.ascontiguousarray(beta.real), lattice, pos, lap_beta=lre)
-    im = evaluate.eval_vgl(np.ascontiguousarray(beta.imag), lattice, pos, lap_beta=lim)
+    if form == "bspline":
+        re = evaluate.eval_vgl(np.ascontiguousarray(beta.real), lattice, pos, lap_beta=lre)
+        im = evaluate.eval_vgl(np.ascontiguousarray(beta.imag), lattice, pos, lap_beta=lim)
+    elif form == "pp":
+        re = ppspline.eval_pp_vgl(np.ascontiguousarray(beta.real), lattice, pos, lap_sigma=lre)
+        im = ppspline.eval_pp_vgl(np.ascontiguousarray(beta.imag), lattice, pos, lap_sigma=lim)
+    else:
+        raise ValueError(form)
     return tuple(a + 1j * b for a, b in zip(re, im))
 
 
-def eval_bloch_vgl(beta, lattice, kvec, pos, lap_beta=None):
-    """Bloch orbital from complex B-spline coefficients beta [N1][N2][N3][O] of u.
+def eval_bloch_vgl(beta, lattice, kvec, pos, lap_beta=None, form="bspline"):
+    """Bloch orbital from complex spline coefficients of u: B-spline coefficients beta
+    [N1][N2][N3][O], or with form="pp" the pp-spline numbers [N1][N2][N3][8][O].
 
     Without lap_beta the Laplacian comes from second derivatives of u; with it (complex
     coefficients of w) from w's value.  Returns complex V [P,O], grad [P,3,O], lap [P,O]."""
     k = np.asarray(kvec, dtype=np.float64)
-    u, gu, lu = _complex_vgl(beta, lattice, pos, lap_beta)
+    u, gu, lu = _complex_vgl(beta, lattice, pos, lap_beta, form)
     e = phase(k, pos)[:, None]
     v = e * u
     grad = e[:, None, :] * (gu + 1j * k[None, :, None] * u[:, None, :])

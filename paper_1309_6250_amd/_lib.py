@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(HERE, "libpwspline.so")
 SPL_F64, SPL_F32, SPL_BF16 = 0, 1, 2
 SPL_OK, SPL_EINVAL, SPL_EGRID, SPL_EDTYPE, SPL_ENOMEM, SPL_EHIP, SPL_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 SPL_DETERMINISTIC = 1
-SPL_BSPLINE, SPL_LAGRANGE = 0, 1
+SPL_BSPLINE, SPL_LAGRANGE, SPL_PPSPLINE = 0, 1, 2
 
 ERROR_NAMES = {
     SPL_EINVAL: "SPL_EINVAL", SPL_EGRID: "SPL_EGRID", SPL_EDTYPE: "SPL_EDTYPE", SPL_ENOMEM: "SPL_ENOMEM",

@@ -8,10 +8,11 @@ import ctypes
 
 import torch
 
-from ._lib import (SplDesc, SplItem, check, lib, SPL_F64, SPL_F32, SPL_BF16, SPL_BSPLINE, SPL_LAGRANGE)
+from ._lib import (SplDesc, SplItem, check, lib, SPL_F64, SPL_F32, SPL_BF16, SPL_BSPLINE, SPL_LAGRANGE,
+                   SPL_PPSPLINE)
 
 DTYPES = {"f64": SPL_F64, "f32": SPL_F32, "bf16": SPL_BF16}
-BASES = {"bspline": SPL_BSPLINE, "lagrange": SPL_LAGRANGE}
+BASES = {"bspline": SPL_BSPLINE, "lagrange": SPL_LAGRANGE, "pp": SPL_PPSPLINE}
 STORE_TORCH = {SPL_F64: torch.float64, SPL_F32: torch.float32, SPL_BF16: torch.bfloat16}
 OUT_TORCH = {SPL_F64: torch.float64, SPL_F32: torch.float32, SPL_BF16: torch.float32}
 
@@ -50,7 +51,8 @@ def _need(t, name, dtype, numel=None, device=None):
 def spline_desc_init(lattice, grid, n_orb, dtype="f64", has_lap=False, basis="bspline", sep_grad=False, kvec=None):
     """Validated descriptor (ctypes struct) of one coefficient table set.
 
-    basis: "bspline" or "lagrange" (the latter needs sep_grad and has_lap); sep_grad: five
+    basis: "bspline", "lagrange" (needs sep_grad and has_lap) or "pp" (the interpolating spline in
+    piecewise-polynomial form, 8 numbers per grid point); sep_grad: five
     tables (orbital, gradient x/y/z, Laplacian) read by value; kvec: crystal momentum (1/bohr)
     of Bloch orbitals exp(i k.r) u(r), whose n_orb complex orbitals take two columns each.
     """
@@ -82,6 +84,8 @@ def spline_desc_init(lattice, grid, n_orb, dtype="f64", has_lap=False, basis="bs
 
 
 def table_shape(desc):
+    if desc.basis == SPL_PPSPLINE:
+        return (desc.n_tables, desc.grid[0], desc.grid[1], desc.grid[2], 8, desc.o_pad)
     return (desc.n_tables, desc.grid[0], desc.grid[1], desc.grid[2], desc.o_pad)
 
 

@@ -43,7 +43,7 @@ Geom make_geom(const spl_desc* d) {
   memcpy(g.metric, d->metric, sizeof(g.metric));
   for (int i = 0; i < 3; ++i) g.n[i] = d->grid[i];
   g.o_pad = d->o_pad;
-  g.s1 = (int64_t)d->grid[2] * d->o_pad;
+  g.s1 = (int64_t)d->grid[2] * d->o_pad * (d->basis == SPL_PPSPLINE ? 8 : 1);
   g.s0 = (int64_t)d->grid[1] * g.s1;
   return g;
 }
@@ -60,7 +60,9 @@ static int derive(spl_desc* d) {
   if (d->has_lap != 0 && d->has_lap != 1) return fail(SPL_EINVAL, "has_lap must be 0 or 1");
   if (d->sep_grad != 0 && d->sep_grad != 1) return fail(SPL_EINVAL, "sep_grad must be 0 or 1");
   if (d->bloch != 0 && d->bloch != 1) return fail(SPL_EINVAL, "bloch must be 0 or 1");
-  if (d->basis != SPL_BSPLINE && d->basis != SPL_LAGRANGE) return fail(SPL_EINVAL, "unknown basis %d", d->basis);
+  if (d->basis != SPL_BSPLINE && d->basis != SPL_LAGRANGE && d->basis != SPL_PPSPLINE)
+    return fail(SPL_EINVAL, "unknown basis %d", d->basis);
+  if (d->basis == SPL_PPSPLINE && d->sep_grad) return fail(SPL_EINVAL, "pp-spline tables take no separate gradients");
   if (d->reserved != 0) return fail(SPL_EINVAL, "reserved must be 0");
   if (d->sep_grad && !d->has_lap) return fail(SPL_EINVAL, "sep_grad needs has_lap (five tables)");
   if (d->basis == SPL_LAGRANGE && !d->sep_grad)
@@ -105,7 +107,7 @@ static int derive(spl_desc* d) {
   const int per16 = 16 / d->elem_bytes;
   d->o_pad = (d->n_col + per16 - 1) / per16 * per16;
   const int64_t pts = (int64_t)d->grid[0] * d->grid[1] * d->grid[2];
-  d->table_elems = pts * d->o_pad;
+  d->table_elems = pts * d->o_pad * (d->basis == SPL_PPSPLINE ? 8 : 1);
   d->table_bytes = d->n_tables * d->table_elems * d->elem_bytes;
   d->work_bytes = pts * d->n_col * 8;
   d->gtable_bytes = d->n_tables * d->table_elems * (d->dtype == SPL_F64 ? 8 : 4);
@@ -195,6 +197,7 @@ int launch_backward(const spl_desc* d, const void* table, int64_t n_pts, const d
                     const void* ggrad, const void* glap, void* gtable, double* gpos, hipStream_t stream);
 int build_one(const spl_desc* d, const double* vals, void* table, double* work, hipStream_t stream);
 int cast_one(const spl_desc* d, const double* vals, void* table, hipStream_t stream);
+int build_one_pp(const spl_desc* d, const double* vals, void* table, double* work, hipStream_t stream);
 int sorted_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes);
 int64_t smoothing_work_bytes(const spl_desc* d);
 int build_smoothing(const spl_desc* d, int64_t n_g, const int32_t* miller, const double* coef, void* table,
@@ -245,7 +248,7 @@ int spline_build(const spl_desc* d, const double* grid_vals, const double* lap_v
   clear_error();
   int rc = check_desc(d);
   if (rc) return rc;
-  if (d->basis != SPL_BSPLINE || d->sep_grad)
+  if (d->basis == SPL_LAGRANGE || d->sep_grad)
     return fail(SPL_EINVAL, "Lagrange or separate-gradient descriptors are built with spline_build_tables");
   if (!grid_vals || !table || !work) return fail(SPL_EINVAL, "grid_vals, table and work must be non-NULL");
   if (d->has_lap && !lap_vals) return fail(SPL_EINVAL, "has_lap = 1 needs lap_vals");
@@ -253,10 +256,11 @@ int spline_build(const spl_desc* d, const double* grid_vals, const double* lap_v
   if (!aligned(grid_vals, 8) || !aligned(work, 8) || !aligned(table, 16) || (lap_vals && !aligned(lap_vals, 8)))
     return fail(SPL_EINVAL, "misaligned buffer (grid values/work need 8 bytes, table 16)");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if ((rc = build_one(d, grid_vals, table, static_cast<double*>(work), s))) return rc;
+  auto one = d->basis == SPL_PPSPLINE ? build_one_pp : build_one;
+  if ((rc = one(d, grid_vals, table, static_cast<double*>(work), s))) return rc;
   if (d->has_lap) {
     char* lt = static_cast<char*>(table) + d->table_elems * d->elem_bytes;
-    if ((rc = build_one(d, lap_vals, lt, static_cast<double*>(work), s))) return rc;
+    if ((rc = one(d, lap_vals, lt, static_cast<double*>(work), s))) return rc;
   }
   return SPL_OK;
 }
@@ -274,7 +278,10 @@ int spline_build_tables(const spl_desc* d, const double* vals, void* table, void
   for (int t = 0; t < d->n_tables; ++t) {
     const double* v = vals + t * per_vals;
     void* dst = static_cast<char*>(table) + t * d->table_elems * d->elem_bytes;
-    if ((rc = lagr ? cast_one(d, v, dst, s) : build_one(d, v, dst, static_cast<double*>(work), s))) return rc;
+    double* w = static_cast<double*>(work);
+    if ((rc = lagr ? cast_one(d, v, dst, s)
+                   : (d->basis == SPL_PPSPLINE ? build_one_pp(d, v, dst, w, s) : build_one(d, v, dst, w, s))))
+      return rc;
   }
   return SPL_OK;
 }

@@ -191,6 +191,85 @@ int build_one(const spl_desc* d, const double* vals, void* table, double* work, 
   return SPL_OK;
 }
 
+// pp-spline table (App. A, Piecewise-polynomial-form splines) from B-spline coefficients beta, FP64
+// [N1][N2][N3][n_col].  At a knot the cubic B-spline's value weights are (1, 4, 1)/6 and its
+// second-derivative weights (1, -2, 1) in grid units, so each of the 8 numbers of a grid point,
+// sigma^{kx ky kz} (Eq. pp-splinecoefficients3), filters beta along every axis with one of the two;
+// the three filters are applied one axis after the other (z, then y, then x).  Stored at
+// [point][q][o_pad], q = 4 (kx - 1) + 2 (ky - 1) + (kz - 1); padding columns are zeroed.
+template <int OUT>
+__global__ __launch_bounds__(256) void k_pp_sigma(const double* beta, void* table, int32_t n1, int32_t n2,
+                                                  int32_t n3, int32_t n_col, int32_t o_pad) {
+  const int64_t pts = (int64_t)n1 * n2 * n3;
+  const int64_t total = pts * o_pad;
+  const double sixth = 1.0 / 6.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = i / o_pad;
+    const int c = (int)(i - p * o_pad);
+    double sig[8];
+    if (c < n_col) {
+      const int i3 = (int)(p % n3);
+      const int64_t r = p / n3;
+      const int i2 = (int)(r % n2);
+      const int i1 = (int)(r / n2);
+      const int xi[3] = {i1 == 0 ? n1 - 1 : i1 - 1, i1, i1 + 1 == n1 ? 0 : i1 + 1};
+      const int yi[3] = {i2 == 0 ? n2 - 1 : i2 - 1, i2, i2 + 1 == n2 ? 0 : i2 + 1};
+      const int zi[3] = {i3 == 0 ? n3 - 1 : i3 - 1, i3, i3 + 1 == n3 ? 0 : i3 + 1};
+      double zs[2][3][3];   // [kind][x][y] after the z filter: kind 0 value, 1 second difference
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          const double* row = beta + ((int64_t)xi[a] * n2 + yi[b]) * n3 * n_col + c;
+          const double m = row[(int64_t)zi[0] * n_col], z0 = row[(int64_t)zi[1] * n_col], pl = row[(int64_t)zi[2] * n_col];
+          zs[0][a][b] = sixth * fmaa(4.0, z0, m + pl);
+          zs[1][a][b] = fmaa(-2.0, z0, m + pl);
+        }
+      double ys[2][2][3];   // [ky kind][kz kind][x]
+      for (int kz = 0; kz < 2; ++kz)
+        for (int a = 0; a < 3; ++a) {
+          const double m = zs[kz][a][0], y0 = zs[kz][a][1], pl = zs[kz][a][2];
+          ys[0][kz][a] = sixth * fmaa(4.0, y0, m + pl);
+          ys[1][kz][a] = fmaa(-2.0, y0, m + pl);
+        }
+      for (int ky = 0; ky < 2; ++ky)
+        for (int kz = 0; kz < 2; ++kz) {
+          const double m = ys[ky][kz][0], x0 = ys[ky][kz][1], pl = ys[ky][kz][2];
+          sig[2 * ky + kz] = sixth * fmaa(4.0, x0, m + pl);
+          sig[4 + 2 * ky + kz] = fmaa(-2.0, x0, m + pl);
+        }
+    } else {
+      for (int q = 0; q < 8; ++q) sig[q] = 0.0;
+    }
+    for (int q = 0; q < 8; ++q) {
+      const int64_t idx = (p * 8 + q) * o_pad + c;
+      if constexpr (OUT == OUT_TABLE_F64) static_cast<double*>(table)[idx] = sig[q];
+      else if constexpr (OUT == OUT_TABLE_F32) static_cast<float*>(table)[idx] = (float)sig[q];
+      else static_cast<uint16_t*>(table)[idx] = f32_to_bf16_rne((float)sig[q]);
+    }
+  }
+}
+
+// One pp-spline table: the B-spline solve of build_one kept in FP64 in `work`, then the knot filters.
+int build_one_pp(const spl_desc* d, const double* vals, void* table, double* work, hipStream_t stream) {
+  const int64_t n1 = d->grid[0], n2 = d->grid[1], n3 = d->grid[2], no = d->n_col;
+  int rc;
+  if ((rc = launch_axis(OUT_F64_WORK, vals, work, 1, (int)n1, n2 * n3 * no, 0, stream))) return rc;
+  if ((rc = launch_axis(OUT_F64_WORK, work, work, n1, (int)n2, n3 * no, 0, stream))) return rc;
+  if ((rc = launch_axis(OUT_F64_WORK, work, work, n1 * n2, (int)n3, no, 0, stream))) return rc;
+  const int64_t total = n1 * n2 * n3 * d->o_pad;
+  const dim3 grid((unsigned)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536));
+  if (d->dtype == SPL_F64)
+    hipLaunchKernelGGL(k_pp_sigma<OUT_TABLE_F64>, grid, dim3(256), 0, stream, work, table, (int)n1, (int)n2,
+                       (int)n3, d->n_col, d->o_pad);
+  else if (d->dtype == SPL_F32)
+    hipLaunchKernelGGL(k_pp_sigma<OUT_TABLE_F32>, grid, dim3(256), 0, stream, work, table, (int)n1, (int)n2,
+                       (int)n3, d->n_col, d->o_pad);
+  else
+    hipLaunchKernelGGL(k_pp_sigma<OUT_TABLE_BF16>, grid, dim3(256), 0, stream, work, table, (int)n1, (int)n2,
+                       (int)n3, d->n_col, d->o_pad);
+  return hip_fail(hipGetLastError(), "pp-spline table launch");
+}
+
 // One Lagrange table: grid values [N1][N2][N3][n_col] cast into the padded table.
 int cast_one(const spl_desc* d, const double* vals, void* table, hipStream_t stream) {
   const int64_t rows = (int64_t)d->grid[0] * d->grid[1] * d->grid[2];

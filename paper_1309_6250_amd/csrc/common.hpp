@@ -115,6 +115,32 @@ __device__ __forceinline__ void lagrange_values(A t, A w[4]) {
   w[3] = sixth * (tp * t * tm);
 }
 
+// pp-spline basis (App. A, Eq. pp-splinebasis) at reduced coordinate t in [0,1), in the order
+// (grid point i0, value), (i0, second derivative), (i0+1, value), (i0+1, second derivative):
+// 1 - t, -t^3/6 + t^2/2 - t/3, t, t^3/6 - t/6; with first and second derivatives in t.
+template <typename A>
+__device__ __forceinline__ void pp_values(A t, A w[4]) {
+  const A sixth = A(1) / A(6);
+  w[0] = A(1) - t;
+  w[1] = t * fmaa(t, fmaa(-sixth, t, A(0.5)), A(-1) / A(3));
+  w[2] = t;
+  w[3] = sixth * (t * fmaa(t, t, A(-1)));
+}
+
+template <typename A>
+__device__ __forceinline__ void pp_weights(A t, A w[4], A dw[4], A d2w[4]) {
+  pp_values<A>(t, w);
+  const A sixth = A(1) / A(6);
+  dw[0] = A(-1);
+  dw[1] = fmaa(t, fmaa(A(-0.5), t, A(1)), A(-1) / A(3));
+  dw[2] = A(1);
+  dw[3] = fmaa(A(0.5), t * t, -sixth);
+  d2w[0] = A(0);
+  d2w[1] = A(1) - t;
+  d2w[2] = A(0);
+  d2w[3] = t;
+}
+
 // Four-term dot product in a fixed order: w0 x0 + w1 x1 + w2 x2 + w3 x3.
 template <typename A>
 __device__ __forceinline__ A dot4(const A w[4], A x0, A x1, A x2, A x3) {

@@ -57,7 +57,8 @@ void fill_eval_args(const spl_desc* d, const void* table, int64_t n_pts, const d
 // Kernel of one forward evaluation of descriptor d (nullptr if the tile has none).
 EvalKernel eval_kernel_for(const spl_desc* d, int values_only, const int32_t tile[2]) {
   const int mode = values_only ? MODE_V : (d->sep_grad ? MODE_SEP : (d->has_lap ? MODE_VGL_SEPLAP : MODE_VGL));
-  const int var = (d->basis == SPL_LAGRANGE ? VAR_LAGRANGE : 0) | (d->bloch ? VAR_BLOCH : 0);
+  const int var = (d->basis == SPL_LAGRANGE ? VAR_LAGRANGE : 0) | (d->basis == SPL_PPSPLINE ? VAR_PP : 0) |
+                  (d->bloch ? VAR_BLOCH : 0);
   if (var == 0 && mode != MODE_SEP) {
     if (d->dtype == SPL_F64) return pick_eval_f64(mode, tile[0], tile[1]);
     if (d->dtype == SPL_F32) return pick_eval_f32(mode, tile[0], tile[1]);

@@ -22,6 +22,11 @@
 // vector loads in flight with a register budget that leaves room for several waves per SIMD.
 // No matrix cores: the work is a gather followed by a short dot product, bound by memory.
 //
+// pp-spline tables (App. A, Piecewise-polynomial-form splines) hold 8 numbers per grid point; a
+// point reads the 2x2x2 corners of its cell, which is again a 4x4x4 arrangement of 64 rows per
+// orbital (per axis: corner i0 or i0+1, times value or second derivative), so the same contraction
+// serves with the pp basis and corner addressing.
+//
 // Variants.  MODE_SEP reads five tables (orbital, d/dx, d/dy, d/dz, Laplacian) by value, with
 // B-spline or Lagrange weights.  Bloch orbitals keep (Re u, Im u) in adjacent columns, so a lane
 // with an even OPL holds whole pairs; after the contraction the product rule and the phase
@@ -47,8 +52,8 @@ struct EvalArgs {
 };
 
 enum { MODE_V = 0, MODE_VGL = 1, MODE_VGL_SEPLAP = 2, MODE_SEP = 3 };
-// variant bits of a kernel: Lagrange weights instead of B-spline, Bloch phase
-enum { VAR_LAGRANGE = 1, VAR_BLOCH = 2 };
+// variant bits of a kernel: Lagrange weights instead of B-spline, Bloch phase, pp-spline layout
+enum { VAR_LAGRANGE = 1, VAR_BLOCH = 2, VAR_PP = 4 };
 
 // ---------------------------------------------------------------- loads of OPL stored values
 template <typename TS, int OPL> struct RowN;
@@ -136,18 +141,26 @@ __device__ __forceinline__ A pick4(int l, A a0, A a1, A a2, A a3) {
   return l == 0 ? a0 : (l == 1 ? a1 : (l == 2 ? a2 : a3));
 }
 
+// Element offset of the first-axis slab l of a point's block: row ix[l] of the B-spline block, or
+// the pp-spline's precomputed corner-and-kind offset xo[l].
+template <bool PP>
+__device__ __forceinline__ int64_t slab_offset(int l, const int ix[4], const int64_t xo[4], int64_t s0) {
+  if constexpr (PP) return pick4(l, xo[0], xo[1], xo[2], xo[3]);
+  else return (int64_t)pick4(l, ix[0], ix[1], ix[2], ix[3]) * s0;
+}
+
 // Value of one table at a point for OPL consecutive columns: sum_lmn w_l w_m w_n beta_lmn.
 // `tab` points at the column o of table row 0; the first-axis loop stays rolled (16 loads in
 // flight per slab).
-template <typename TS, int OPL, typename A>
-__device__ __forceinline__ void value_pass(const TS* __restrict__ tab, const int ix[4], const int64_t ry[4],
-                                           const int64_t rz[4], int64_t s0, const A wx[4], const A wy[4],
-                                           const A wz[4], A out[OPL]) {
+template <typename TS, int OPL, typename A, bool PP>
+__device__ __forceinline__ void value_pass(const TS* __restrict__ tab, const int ix[4], const int64_t xo[4],
+                                           const int64_t ry[4], const int64_t rz[4], int64_t s0, const A wx[4],
+                                           const A wy[4], const A wz[4], A out[OPL]) {
 #pragma unroll
   for (int j = 0; j < OPL; ++j) out[j] = A(0);
 #pragma unroll 1
   for (int l = 0; l < 4; ++l) {
-    const TS* slab = tab + (int64_t)pick4(l, ix[0], ix[1], ix[2], ix[3]) * s0;
+    const TS* slab = tab + slab_offset<PP>(l, ix, xo, s0);
     A r[4][4][OPL];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -188,8 +201,10 @@ __device__ __forceinline__ void eval_point(const EvalArgs& a, const int p, const
   using O = typename Out<TS>::type;
   constexpr bool LAGR = (VAR & VAR_LAGRANGE) != 0;
   constexpr bool BLOCH = (VAR & VAR_BLOCH) != 0;
+  constexpr bool PP = (VAR & VAR_PP) != 0;
   constexpr bool DERIV = MODE == MODE_VGL || MODE == MODE_VGL_SEPLAP;
   static_assert(!(LAGR && DERIV), "Lagrange tables are read by value only");
+  static_assert(!(PP && (LAGR || MODE == MODE_SEP)), "pp-spline tables: B-spline function, no separate gradients");
   static_assert(!BLOCH || OPL % 2 == 0, "Bloch orbitals need whole (re, im) pairs per lane");
   constexpr int NQ = (MODE == MODE_VGL) ? 10 : 4;
   const TS* __restrict__ tab = static_cast<const TS*>(a.table);
@@ -203,11 +218,30 @@ __device__ __forceinline__ void eval_point(const EvalArgs& a, const int p, const
   wrap4(i0[0], a.g.n[0], ix);
   wrap4(i0[1], a.g.n[1], iy);
   wrap4(i0[2], a.g.n[2], iz);
-  int64_t ry[4], rz[4];
+  int64_t xo[4], ry[4], rz[4];
+  if constexpr (PP) {
+    // corners i0 = idx[1] and i0 + 1 = idx[2] per axis; the 8 numbers of a grid point are rows
+    // q = 4 (kx - 1) + 2 (ky - 1) + (kz - 1) of o_pad elements each
+    const int64_t op = a.g.o_pad;
+    xo[0] = (int64_t)ix[1] * a.g.s0;
+    xo[1] = xo[0] + 4 * op;
+    xo[2] = (int64_t)ix[2] * a.g.s0;
+    xo[3] = xo[2] + 4 * op;
+    ry[0] = (int64_t)iy[1] * a.g.s1;
+    ry[1] = ry[0] + 2 * op;
+    ry[2] = (int64_t)iy[2] * a.g.s1;
+    ry[3] = ry[2] + 2 * op;
+    rz[0] = (int64_t)iz[1] * 8 * op;
+    rz[1] = rz[0] + op;
+    rz[2] = (int64_t)iz[2] * 8 * op;
+    rz[3] = rz[2] + op;
+  } else {
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    ry[m] = (int64_t)iy[m] * a.g.s1;
-    rz[m] = (int64_t)iz[m] * a.g.o_pad;
+    for (int m = 0; m < 4; ++m) {
+      xo[m] = 0;
+      ry[m] = (int64_t)iy[m] * a.g.s1;
+      rz[m] = (int64_t)iz[m] * a.g.o_pad;
+    }
   }
 
   A ph_c = A(1), ph_s = A(0);   // exp(i k.r), Bloch variants
@@ -224,11 +258,19 @@ __device__ __forceinline__ void eval_point(const EvalArgs& a, const int p, const
       lagrange_values<A>((A)t[0], wx);
       lagrange_values<A>((A)t[1], wy);
       lagrange_values<A>((A)t[2], wz);
+    } else if constexpr (PP) {
+      pp_values<A>((A)t[0], wx);
+      pp_values<A>((A)t[1], wy);
+      pp_values<A>((A)t[2], wz);
     } else {
       bspline_values<A>((A)t[0], wx);
       bspline_values<A>((A)t[1], wy);
       bspline_values<A>((A)t[2], wz);
     }
+  } else if constexpr (PP) {
+    pp_weights<A>((A)t[0], wx, dwx, d2wx);
+    pp_weights<A>((A)t[1], wy, dwy, d2wy);
+    pp_weights<A>((A)t[2], wz, dwz, d2wz);
   } else {
     bspline_weights<A>((A)t[0], wx, dwx, d2wx);
     bspline_weights<A>((A)t[1], wy, dwy, d2wy);
@@ -242,7 +284,7 @@ __device__ __forceinline__ void eval_point(const EvalArgs& a, const int p, const
     const int o = c * OPL;
     if constexpr (MODE == MODE_V) {
       A val[OPL];
-      value_pass<TS, OPL, A>(tab + o, ix, ry, rz, a.g.s0, wx, wy, wz, val);
+      value_pass<TS, OPL, A, PP>(tab + o, ix, xo, ry, rz, a.g.s0, wx, wy, wz, val);
       if constexpr (BLOCH) phase_pairs<A, OPL>(ph_c, ph_s, val);
       O ov[OPL];
       to_out<O, A, OPL>(val, ok, ov);
@@ -252,7 +294,7 @@ __device__ __forceinline__ void eval_point(const EvalArgs& a, const int p, const
       A val[5][OPL];
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
-        value_pass<TS, OPL, A>(tab + q * a.tab_stride + o, ix, ry, rz, a.g.s0, wx, wy, wz, val[q]);
+        value_pass<TS, OPL, A, false>(tab + q * a.tab_stride + o, ix, xo, ry, rz, a.g.s0, wx, wy, wz, val[q]);
         if constexpr (BLOCH) phase_pairs<A, OPL>(ph_c, ph_s, val[q]);
       }
       O y[OPL];
@@ -276,7 +318,7 @@ __device__ __forceinline__ void eval_point(const EvalArgs& a, const int p, const
 
 #pragma unroll 1
       for (int l = 0; l < 4; ++l) {
-        const TS* slab = tab + (int64_t)pick4(l, ix[0], ix[1], ix[2], ix[3]) * a.g.s0 + o;
+        const TS* slab = tab + slab_offset<PP>(l, ix, xo, a.g.s0) + o;
         A r[4][4][OPL];
 #pragma unroll
         for (int m = 0; m < 4; ++m)
@@ -323,7 +365,7 @@ __device__ __forceinline__ void eval_point(const EvalArgs& a, const int p, const
       A lacc[OPL];
       if constexpr (MODE == MODE_VGL_SEPLAP) {
         // Laplacian = value of the separate Laplacian spline (same block, value weights)
-        value_pass<TS, OPL, A>(tab + a.tab_stride + o, ix, ry, rz, a.g.s0, wx, wy, wz, lacc);
+        value_pass<TS, OPL, A, PP>(tab + a.tab_stride + o, ix, xo, ry, rz, a.g.s0, wx, wy, wz, lacc);
       }
       // chain rule (Sec. II): grad = J^T grad_t, lap = sum_ij M_ij H_ij
       const A j00 = (A)a.g.jac[0], j01 = (A)a.g.jac[1], j02 = (A)a.g.jac[2];
@@ -499,7 +541,7 @@ inline EvalKernel pick_mode(int mode, int g, int opl) {
   }
 }
 
-// Everything else: Lagrange weights, five separate tables, Bloch orbitals.
+// Everything else: Lagrange weights, five separate tables, Bloch orbitals, pp-spline layout.
 template <typename TS>
 inline EvalKernel pick_mode_variant(int mode, int var, int g, int opl) {
   if (mode == MODE_SEP) {
@@ -516,12 +558,22 @@ inline EvalKernel pick_mode_variant(int mode, int var, int g, int opl) {
       case VAR_LAGRANGE: return pick_opl<TS, MODE_V, VAR_LAGRANGE>(g, opl);
       case VAR_BLOCH: return pick_opl<TS, MODE_V, VAR_BLOCH>(g, opl);
       case VAR_BLOCH | VAR_LAGRANGE: return pick_opl<TS, MODE_V, VAR_BLOCH | VAR_LAGRANGE>(g, opl);
+      case VAR_PP: return pick_opl<TS, MODE_V, VAR_PP>(g, opl);
+      case VAR_PP | VAR_BLOCH: return pick_opl<TS, MODE_V, VAR_PP | VAR_BLOCH>(g, opl);
       default: return nullptr;
     }
   }
-  if (var != VAR_BLOCH) return nullptr;
-  return mode == MODE_VGL ? pick_opl<TS, MODE_VGL, VAR_BLOCH>(g, opl)
-                          : pick_opl<TS, MODE_VGL_SEPLAP, VAR_BLOCH>(g, opl);
+  const bool lap = mode == MODE_VGL_SEPLAP;
+  switch (var) {
+    case VAR_BLOCH:
+      return lap ? pick_opl<TS, MODE_VGL_SEPLAP, VAR_BLOCH>(g, opl) : pick_opl<TS, MODE_VGL, VAR_BLOCH>(g, opl);
+    case VAR_PP:
+      return lap ? pick_opl<TS, MODE_VGL_SEPLAP, VAR_PP>(g, opl) : pick_opl<TS, MODE_VGL, VAR_PP>(g, opl);
+    case VAR_PP | VAR_BLOCH:
+      return lap ? pick_opl<TS, MODE_VGL_SEPLAP, VAR_PP | VAR_BLOCH>(g, opl)
+                 : pick_opl<TS, MODE_VGL, VAR_PP | VAR_BLOCH>(g, opl);
+    default: return nullptr;
+  }
 }
 
 template <typename TS, int MODE>

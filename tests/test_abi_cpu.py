@@ -202,6 +202,10 @@ def test_desc_sizes_of_the_representations():
     assert list(d.kvec) == [0.1, -0.2, 0.3]
     d = P.spline_desc_init(LAT, (8, 9, 10), 3, "bf16", has_lap=True, kvec=(0.0, 0.0, 0.5))
     assert d.n_col == 6 and d.o_pad == 8 and d.n_tables == 2
+    d = P.spline_desc_init(LAT, (8, 9, 10), 5, "f32", has_lap=True, basis="pp")
+    assert d.basis == P.SPL_PPSPLINE and d.table_elems == 8 * 9 * 10 * 8 * 8
+    assert d.table_bytes == 2 * d.table_elems * 4 and d.work_bytes == 8 * 9 * 10 * 5 * 8
+    assert P.table_shape(d) == (2, 8, 9, 10, 8, 8)
 
 
 def _unchecked_desc(**kw):
@@ -221,9 +225,11 @@ def _unchecked_desc(**kw):
 
 
 @pytest.mark.parametrize("kw", [
-    dict(basis=2), dict(sep_grad=2), dict(bloch=2), dict(reserved=1),
+    dict(sep_grad=2), dict(bloch=2), dict(reserved=1),
     dict(sep_grad=1),                                   # five tables need has_lap
     dict(basis=1, has_lap=1),                           # Lagrange needs separate gradients
+    dict(basis=2, has_lap=1, sep_grad=1),               # pp-spline tables take no separate gradients
+    dict(basis=3),
     dict(kvec=(0.1, 0.0, 0.0)),                         # k without bloch
     dict(bloch=1, kvec=(float("nan"), 0.0, 0.0)),
 ])
@@ -236,7 +242,7 @@ def test_desc_rejects_inconsistent_representations(kw):
 def test_adjoint_and_batch_reject_other_representations():
     fake = ctypes.c_void_p(256)        # never dereferenced: every call fails validation first
     for kw in (dict(kvec=(0.1, 0.0, 0.0)), dict(has_lap=True, sep_grad=True),
-               dict(has_lap=True, sep_grad=True, basis="lagrange")):
+               dict(has_lap=True, sep_grad=True, basis="lagrange"), dict(basis="pp")):
         d = P.spline_desc_init(LAT, (8, 8, 8), 4, "f32", **kw)
         nb = ctypes.c_int64()
         assert P.lib().spline_backward_work_bytes(ctypes.byref(d), 10, 0, ctypes.byref(nb)) == P.SPL_EUNSUPPORTED
@@ -257,6 +263,9 @@ def test_build_entry_points_check_the_representation():
     assert P.lib().spline_build_smoothing(ctypes.byref(d), 5, fake, ctypes.c_void_p(512), fake, fake,
                                           None) == P.SPL_EINVAL
     assert P.lib().spline_build_tables(ctypes.byref(d), None, fake, None, None) == P.SPL_EINVAL
+    d = P.spline_desc_init(LAT, (8, 8, 8), 4, "f32", basis="pp")
+    assert P.lib().spline_build_smoothing(ctypes.byref(d), 5, fake, ctypes.c_void_p(512), fake, fake,
+                                          None) == P.SPL_EINVAL
 
 
 def test_bloch_tiles_need_whole_pairs():

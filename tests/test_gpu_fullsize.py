@@ -227,3 +227,26 @@ def test_mgo96_separate_tables_full_size(mgo96, mgo96_grad, basis):
     got = [g.double().cpu().numpy() for g in got]
     for g, r in zip(got, ref):
         assert normwise(g, r) <= 1e-5
+
+
+@pytest.mark.timeout(600)
+def test_mgo96_pp_full_size(mgo96):
+    """pp-spline form of all 256 orbitals on the 96^3 grid (FP32, 8 numbers per grid point): the
+    bench's pp form at its autotuned tile, sampled against the oracle's pp build and evaluation."""
+    from oracle import ppspline as opp
+    s = mgo96["s"]
+    d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, "f32", basis="pp")
+    say("full size pp-spline", s.name)
+    tab = P.spline_build(d, mgo96["f_dev"])
+    out = P.spline_eval_vgl(d, tab, mgo96["pos_dev"])
+    tile = P.spline_autotune(d, tab, mgo96["pos_dev"], *out)
+    out = P.spline_eval_vgl(d, tab, mgo96["pos_dev"], *out, tile=tile)
+    torch.cuda.synchronize()
+    k_orb = 16
+    sig = opp.build_pp(np.ascontiguousarray(mgo96["f"][..., :k_orb]))
+    idx = _sample(mgo96["pos"].shape[0])
+    ref = opp.eval_pp_vgl(sig, s.lattice, mgo96["pos"][idx])
+    got = [out[0][idx, :k_orb], out[1][idx, :, :k_orb], out[2][idx, :k_orb]]
+    got = [g.double().cpu().numpy() for g in got]
+    for g, r in zip(got, ref):
+        assert normwise(g, r) <= 1e-5

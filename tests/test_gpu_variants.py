@@ -9,7 +9,7 @@ import torch
 
 import paper_1309_6250_amd as P
 from oracle import build as obuild, evaluate as oeval, lagrange as olag, separate as osep, bloch as obl
-from oracle import smoothing as osm, quantize as oq
+from oracle import smoothing as osm, quantize as oq, ppspline as opp
 from workloads import config, make_system
 from gpu_helpers import say, to_dev, normwise, assert_elementwise, coordinate_rounding, DEV, U_ACC
 
@@ -240,10 +240,17 @@ def test_bloch_gpu_approaches_planewave():
 
 
 # ---------------------------------------------------------------- launch shapes, values only, degenerate cases
-VARIANTS = [("sep_bspline", False), ("sep_lagrange", False), ("bloch", True), ("bloch_sep_lagrange", True)]
+VARIANTS = [("sep_bspline", False), ("sep_lagrange", False), ("bloch", True), ("bloch_sep_lagrange", True),
+            ("pp", False), ("pp_bloch_lap", True)]
 
 
 def _variant(name, dtype):
+    if name.startswith("pp"):
+        bl = name == "pp_bloch_lap"
+        s = bloch_cases()[1] if bl else real_cases()[0]
+        _, tabs = pp_tables(s, bl)
+        d = pp_desc(s, dtype, bl)
+        return s, d, upload(d, tabs, dtype)
     s = bloch_cases()[1] if name.startswith("bloch") else real_cases()[0]
     if name == "bloch":
         kind = "derivative"
@@ -319,3 +326,133 @@ def test_smoothing_separate_gradients_and_bloch_match_oracle():
                 ref = cols(osm.build_smoothing(s.miller, s.coef * m[None, :], s.grid, keep_complex=s.bloch))
                 assert np.abs(t[i, ..., :d.n_col] - ref).max() <= 1e-12 * np.abs(ref).max(), (s.name, sep, i)
             assert np.all(t[..., d.n_col:] == 0)
+
+
+# ---------------------------------------------------------------- pp-spline form
+def pp_desc(s, dtype, lap):
+    return P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype, has_lap=lap, basis="pp",
+                              kvec=s.k if s.bloch else None)
+
+
+def pp_build(f):
+    if np.iscomplexobj(f):
+        return opp.build_pp(np.ascontiguousarray(f.real)) + 1j * opp.build_pp(np.ascontiguousarray(f.imag))
+    return opp.build_pp(f)
+
+
+def pp_tables(s, lap):
+    key = (s.name, "pp", lap)
+    if key not in _cache:
+        g = [s.grid_values()] + ([s.grid_laplacian()] if lap else [])
+        _cache[key] = (g, [pp_build(x) for x in g])
+    return _cache[key]
+
+
+def pp_oracle(s, tabs, pos):
+    lap = tabs[1] if len(tabs) > 1 else None
+    if s.bloch:
+        return obl.eval_bloch_vgl(tabs[0], s.lattice, s.k, pos, lap_beta=lap, form="pp")
+    return opp.eval_pp_vgl(tabs[0], s.lattice, pos, lap_sigma=lap)
+
+
+PP_CASES = [(0, False, False), (1, False, True), (0, True, False), (1, True, True)]   # (case, bloch, lap)
+# The pp form keeps values and second derivatives as independent numbers: once rounded to BF16 the
+# interpolant is no longer exactly C1 across knot planes and its gradient carries the rounding of
+# differences of neighbouring values (about 1.2e-2 normwise on these cases against 3.4e-3 for the
+# same spline stored as B-spline coefficients).  Its BF16 gate on the gradient is therefore 3e-2.
+GATE_PP = {"f64": (1e-10,) * 3, "f32": (1e-5,) * 3, "bf16": (5e-3, 3e-2, 5e-2)}
+GATE_PP_SEPLAP = {"f64": (1e-10,) * 3, "f32": (1e-5,) * 3, "bf16": (5e-3, 3e-2, 5e-3)}
+
+
+def knot_sides(s, pos, tol=1e-9, nudge=1e-8):
+    """Points within `tol` grid units of a knot plane (where rounding in the coordinate reduction
+    may put them in either neighbouring cell) and, for each, the point itself followed by copies
+    nudged by `nudge` grid units to both sides of every such plane (all combinations)."""
+    n = np.array(s.grid, dtype=np.float64)
+    u = np.linalg.solve(s.lattice.T, pos.T).T * n
+    off = u - np.round(u)
+    near = np.abs(off) < tol
+    out = {}
+    for p in np.nonzero(near.any(axis=1))[0]:
+        axes = np.nonzero(near[p])[0]
+        cands = [pos[p]]
+        for signs in np.ndindex(*([2] * len(axes))):
+            du = np.zeros(3)
+            for a, sg in zip(axes, signs):
+                du[a] = (np.round(u[p, a]) - u[p, a]) + (nudge if sg else -nudge)
+            cands.append(pos[p] + (du / n) @ s.lattice)
+        out[int(p)] = np.array(cands)
+    return out
+
+
+def one_sided_reference(s, tabs, pos, got, oracle):
+    """The oracle at every point; at points on a knot plane, the candidate closest to the GPU result
+    among the point itself and its one-sided copies: any of them is a correct value (to within the
+    nudge) of a representation whose rounded coefficients jump across the plane."""
+    ref = [np.array(x) for x in oracle(s, tabs, pos)]
+    for p, cands in knot_sides(s, pos).items():
+        opts = oracle(s, tabs, cands)
+        errs = [max(np.abs(np.asarray(o)[c] - g[p]).max() for o, g in zip(opts, got)) for c in range(len(cands))]
+        c = int(np.argmin(errs))
+        for r, o in zip(ref, opts):
+            r[p] = np.asarray(o)[c]
+    return ref
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("k,bloch,lap", PP_CASES)
+def test_pp_kernel_parity(k, bloch, lap, dtype):
+    s = (bloch_cases() if bloch else real_cases())[k]
+    _, tabs = pp_tables(s, lap)
+    pos = points(s)
+    d = pp_desc(s, dtype, lap)
+    got = gpu_eval(d, upload(d, tabs, dtype), pos)
+    ref = one_sided_reference(s, [quant(t, dtype) for t in tabs], pos, got, pp_oracle)
+    for g, r, name in zip(got, ref, ("V", "grad", "lap")):
+        assert normwise(g, r) <= PARITY[dtype], (name, normwise(g, r))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("k,bloch,lap", PP_CASES)
+def test_pp_build_and_end_to_end(k, bloch, lap, dtype):
+    s = (bloch_cases() if bloch else real_cases())[k]
+    grids, tabs = pp_tables(s, lap)
+    d = pp_desc(s, dtype, lap)
+    say("pp build", s.name, dtype, lap)
+    cdt = torch.complex128 if bloch else torch.float64
+    table = P.spline_build(d, to_dev(grids[0], cdt), to_dev(grids[1], cdt) if lap else None)
+    torch.cuda.synchronize()
+    t = (table.float() if dtype == "bf16" else table).double().cpu().numpy()
+    for q, tab in enumerate(tabs):
+        ref = quant(cols(tab), dtype)
+        got = t[q, ..., :d.n_col]
+        for kind in range(8):
+            scale = np.abs(ref[..., kind, :]).max()
+            err = np.abs(got[..., kind, :] - ref[..., kind, :])
+            if dtype == "f64":
+                assert err.max() <= 1e-12 * scale, (q, kind)
+            else:
+                ulp = (2.0**-23 if dtype == "f32" else 2.0**-7) * np.abs(ref[..., kind, :])
+                assert np.all(err <= ulp + 1e-12 * scale), (q, kind)
+    assert np.all(t[..., d.n_col:] == 0)
+    pos = points(s)
+    got = gpu_eval(d, table, pos)
+    ref = pp_oracle(s, tabs, pos)
+    gates = GATE_PP_SEPLAP[dtype] if lap else GATE_PP[dtype]
+    for g, r, gate, name in zip(got, ref, gates, ("V", "grad", "lap")):
+        assert normwise(g, r) <= gate, (name, normwise(g, r))
+
+
+@pytest.mark.parametrize("bloch", [False, True])
+def test_pp_and_bspline_tables_give_the_same_function(bloch):
+    s = bloch_cases()[0] if bloch else real_cases()[1]
+    cdt = torch.complex128 if bloch else torch.float64
+    f = to_dev(s.grid_values(), cdt)
+    kv = s.k if bloch else None
+    dp = P.spline_desc_init(s.lattice, s.grid, s.n_orb, "f64", basis="pp", kvec=kv)
+    db = P.spline_desc_init(s.lattice, s.grid, s.n_orb, "f64", kvec=kv)
+    pos = points(s)
+    a = gpu_eval(dp, P.spline_build(dp, f), pos)
+    b = gpu_eval(db, P.spline_build(db, f), pos)
+    for x, y in zip(a, b):
+        assert normwise(x, y) <= 1e-11

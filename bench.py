@@ -155,6 +155,36 @@ def run_form(wl, dtype, has_lap, steps, warmup, tune=True, tile=None, sep=None, 
     return rec, d, table, outs
 
 
+OPLS = {"f64": (1, 2), "f32": (1, 2, 4), "bf16": (2, 4, 8)}
+
+
+def sorted_form(wl, d, table, outs, dtype, steps, warmup, tile=None):
+    """The same evaluation through spline_eval_vgl_sorted: Morton cell keys, radix sort and the
+    permuted kernel, all inside every timed call.  The tile is the fastest of a sweep (three timed
+    calls each).  alg_GBps counts each point's 64 rows as if read from memory, as for the other
+    forms; rows reused from L2 or the Infinity Cache can take it past the HBM peak."""
+    import torch
+    import paper_1309_6250_amd as P
+    n_pts = int(wl.pos.shape[0])
+    work = torch.empty(P.spline_sorted_work_bytes(d, n_pts), dtype=torch.uint8, device="cuda")
+    if tile is None:
+        best = None
+        for opl in OPLS[dtype]:
+            for g in (4, 8, 16, 32, 64, 128, 256):
+                ms = time_launches(lambda: P.spline_eval_vgl_sorted(d, table, wl.pos, *outs, work=work, tile=(g, opl)),
+                                   3, 1)
+                if best is None or ms < best[0]:
+                    best = (ms, (g, opl))
+        tile = best[1]
+    ms = time_launches(lambda: P.spline_eval_vgl_sorted(d, table, wl.pos, *outs, work=work, tile=tile), steps, warmup)
+    evals = n_pts * d.n_orb
+    alg = evals * bytes_per_eval(dtype, d.n_tables) + 24 * n_pts
+    return {"evals_per_s": evals / (ms * 1e-3), "ms_per_sweep": ms, "alg_bytes_per_sweep": alg,
+            "alg_GBps": alg / (ms * 1e-3) / 1e9, "frac_hbm_peak": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "tile": list(tile), "table_bytes": int(d.table_bytes),
+            "note": "spline_eval_vgl_sorted; the sort of the points runs inside every timed call"}
+
+
 def grid_fields_gpu(system, chunk=16):
     """Fixture for the five-table forms: grid samples of the orbital (u for Bloch orbitals), of the
     periodic parts of its gradient, sum_G i(k+G) c_G e^{iG.r}, and of its Laplacian,
@@ -554,6 +584,23 @@ def main():
         log("copy calibration: 3 copies of 1 GiB (1073741824 bytes read + written each)")
         del src, dst
 
+    if args.only and args.only.endswith("-sorted"):
+        # locality-ordered call only (for profiling runs: the sorted kernel's launches alone)
+        import paper_1309_6250_amd as P
+        key, dtype, *rest = args.only[:-len("-sorted")].split("-")
+        lap = bool(rest and rest[0] == "lap")
+        wl = Workload(int(key[1:]), lap=lap)
+        _gpu_ready()
+        wl.upload()
+        s_ = wl.s
+        d = P.spline_desc_init(s_.lattice, s_.grid, s_.n_orb, dtype, has_lap=lap)
+        table = P.spline_build(d, wl.f, wl.lf if lap else None)
+        outs = P.spline_eval_vgl(d, table, wl.pos)
+        tile = None if args.tile is None else tuple(int(x) for x in args.tile.split(","))
+        rec = sorted_form(wl, d, table, outs, dtype, args.steps, args.warmup, tile=tile)
+        print(json.dumps({"only": args.only, **rec}), flush=True)
+        return
+
     if args.only:
         key, dtype, *rest = args.only.split("-")
         lap = bool(rest and rest[0] == "lap")
@@ -594,12 +641,16 @@ def main():
     forms = {"c1-f64": head}
     rows = {}
     if not args.quick:
+        forms["c1-f64-sorted"] = sorted_form(wl1, d1, t1, o1, "f64", args.steps, args.warmup)
+        log(f"c1-f64-sorted: {forms['c1-f64-sorted']['evals_per_s']:.3e} evals/s")
         for dtype in ("f32", "bf16"):
             rec, d, t, o = run_form(wl1, dtype, False, args.steps, args.warmup)
             rec["accuracy"] = accuracy(wl1, dtype, "derivative", o)
             rec["speedup_vs_f64"] = rec["evals_per_s"] / head["evals_per_s"]
             forms[f"c1-{dtype}"] = rec
             log(f"c1-{dtype}: {rec['evals_per_s']:.3e} evals/s, {rec['alg_GBps']:.0f} GB/s")
+            forms[f"c1-{dtype}-sorted"] = sorted_form(wl1, d, t, o, dtype, args.steps, args.warmup)
+            log(f"c1-{dtype}-sorted: {forms[f'c1-{dtype}-sorted']['evals_per_s']:.3e} evals/s")
             del t, o
         rows = rows_measurements(wl1, args.steps, args.warmup)
         rows["batched_persistent_graph_f32"] = batched_row(args.steps, args.warmup)
@@ -629,6 +680,9 @@ def main():
                 forms[name] = rec
                 log(f"{name}: {rec['evals_per_s']:.3e} evals/s, {rec['alg_GBps']:.0f} GB/s "
                     f"({100 * rec['frac_hbm_peak']:.0f}% of HBM peak)")
+                if not lap or dtype == "f32":
+                    forms[name + "-sorted"] = sorted_form(wl2, d, t, o, dtype, args.steps, args.warmup)
+                    log(f"{name}-sorted: {forms[name + '-sorted']['evals_per_s']:.3e} evals/s")
                 del t, o
                 torch.cuda.empty_cache()
         # the representations the paper compares, with direct approximations of the gradient and the

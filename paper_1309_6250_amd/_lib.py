@@ -24,6 +24,7 @@ EXPORTS = (
     "spline_batch_graph_launch", "spline_batch_autotune", "spline_batch_plan_destroy", "spline_batch_plan_info", "spline_autotune",
     "spline_tile_for", "spline_last_error", "spline_version", "spline_backward_work_bytes",
     "spline_build_smoothing", "spline_smoothing_work_bytes", "spline_build_tables",
+    "spline_eval_vgl_sorted", "spline_sorted_work_bytes",
 )
 
 
@@ -89,6 +90,8 @@ def lib():
             "spline_desc_init": (ctypes.c_int, [pd]),
             "spline_build": (ctypes.c_int, [pd, vp, vp, vp, vp, vp]),
             "spline_build_tables": (ctypes.c_int, [pd, vp, vp, vp, vp]),
+            "spline_eval_vgl_sorted": (ctypes.c_int, [pd, vp, i64, vp, vp, vp, vp, i32p, vp, i64, vp]),
+            "spline_sorted_work_bytes": (ctypes.c_int, [pd, i64, ctypes.POINTER(i64)]),
             "spline_eval_v": (ctypes.c_int, [pd, vp, i64, vp, vp, vp]),
             "spline_eval_vgl": (ctypes.c_int, [pd, vp, i64, vp, vp, vp, vp, vp]),
             "spline_eval_vgl_tile": (ctypes.c_int, [pd, vp, i64, vp, vp, vp, vp, i32p, vp]),

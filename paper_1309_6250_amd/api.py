@@ -231,6 +231,30 @@ def spline_eval_vgl(desc, table, pos, v=None, grad=None, lap=None, stream=None, 
     return _as_complex(desc, v), _as_complex(desc, grad), _as_complex(desc, lap)
 
 
+def spline_sorted_work_bytes(desc, n_pts):
+    out = ctypes.c_int64()
+    check(lib().spline_sorted_work_bytes(ctypes.byref(desc), int(n_pts), ctypes.byref(out)), "spline_sorted_work_bytes")
+    return out.value
+
+
+def spline_eval_vgl_sorted(desc, table, pos, v=None, grad=None, lap=None, work=None, tile=None, stream=None):
+    """spline_eval_vgl with the points evaluated in Morton order of their cells (same outputs, in
+    the caller's order).  `work` (uint8 device tensor of spline_sorted_work_bytes bytes) is
+    allocated if not given; pass one to keep allocation out of repeated calls."""
+    n = _check_inputs(desc, table, pos)
+    v, grad, lap = _outputs(desc, n, pos.device, v, grad, lap)
+    nbytes = spline_sorted_work_bytes(desc, n)
+    if work is None:
+        work = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=pos.device)
+    if work.numel() * work.element_size() < nbytes:
+        raise ValueError(f"work must hold {nbytes} bytes")
+    t = None if tile is None else (ctypes.c_int32 * 2)(int(tile[0]), int(tile[1]))
+    check(lib().spline_eval_vgl_sorted(ctypes.byref(desc), _ptr(table), n, _ptr(pos), _ptr(v), _ptr(grad), _ptr(lap),
+                                       t, _ptr(work), int(work.numel() * work.element_size()), _stream(stream)),
+          "spline_eval_vgl_sorted")
+    return v, grad, lap
+
+
 def spline_eval_vgl_backward(desc, table, pos, gv=None, ggrad=None, glap=None, gtable=None, gpos=None,
                              want_table=True, want_pos=True, flags=0, stream=None):
     """Returns (gtable, gpos).  gtable is accumulated into (a fresh zero table if not given)."""

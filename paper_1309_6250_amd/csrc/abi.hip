@@ -406,6 +406,39 @@ int spline_autotune(const spl_desc* d, const void* table, int64_t n_pts, const d
   return hip_fail(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
+int spline_sorted_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes) {
+  clear_error();
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if (!bytes) return fail(SPL_EINVAL, "bytes is NULL");
+  if (n_pts < 0 || n_pts > 0x7fffffffLL) return fail(SPL_EINVAL, "n_pts = %lld outside [0, 2^31)", (long long)n_pts);
+  *bytes = 0;
+  return n_pts == 0 ? SPL_OK : sorted_eval_work_bytes(d, n_pts, bytes);
+}
+
+int spline_eval_vgl_sorted(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, void* v,
+                           void* grad, void* lap, const int32_t* tile, void* work, int64_t work_bytes, void* stream) {
+  clear_error();
+  int rc = check_eval_args(d, table, n_pts, pos);
+  if (rc) return rc;
+  if (d->basis != SPL_BSPLINE || d->sep_grad || d->bloch)
+    return fail(SPL_EUNSUPPORTED, "locality-ordered evaluation covers real B-spline tables without separate gradients");
+  if (n_pts == 0) return SPL_OK;
+  if ((rc = check_vgl_outputs(d, v, grad, lap))) return rc;
+  if (!work) return fail(SPL_EINVAL, "work is NULL (size from spline_sorted_work_bytes)");
+  if (!aligned(work, 256)) return fail(SPL_EINVAL, "workspace must be 256-byte aligned");
+  int32_t t[2];
+  if (tile) {
+    t[0] = tile[0];
+    t[1] = tile[1];
+  } else {
+    tile_for(d, t);
+  }
+  if (!tile_valid_for(d, t)) return fail(SPL_EINVAL, "invalid tile");
+  return launch_eval_sorted(d, table, n_pts, pos, v, grad, lap, 0, t, work, work_bytes,
+                            static_cast<hipStream_t>(stream));
+}
+
 int spline_backward_work_bytes(const spl_desc* d, int64_t n_pts, int32_t flags, int64_t* bytes) {
   clear_error();
   int rc = check_desc(d);

@@ -433,9 +433,10 @@ __device__ __forceinline__ void eval_point(const EvalArgs& a, const int p, const
 template <typename TS, int MODE, int G, int OPL, int VAR>
 __global__ __launch_bounds__(256) void k_eval(EvalArgs a) {
   constexpr int GPB = 256 / G;
-  int p = (int)blockIdx.x * GPB + (int)threadIdx.x / G;
+  const int64_t q = (int64_t)blockIdx.x * GPB + (int)threadIdx.x / G;
+  if (q >= a.n_pts) return;
+  int p = (int)q;
   if constexpr (G >= 64) p = __builtin_amdgcn_readfirstlane(p);
-  if (p >= a.n_pts) return;
   eval_point<TS, MODE, G, OPL, VAR>(a, p, (int)threadIdx.x % G);
 }
 

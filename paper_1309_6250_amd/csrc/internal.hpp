@@ -17,6 +17,11 @@ void fill_eval_args(const spl_desc* d, const void* table, int64_t n_pts, const d
 int launch_eval(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, void* v, void* grad,
                 void* lap, int values_only, const int32_t tile[2], hipStream_t stream);
 
+int sorted_eval_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes);
+int launch_eval_sorted(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, void* v, void* grad,
+                       void* lap, int values_only, const int32_t tile[2], void* work, int64_t work_bytes,
+                       hipStream_t stream);
+
 BatchKernel pick_batch_f64(int mode, int g, int opl);
 BatchKernel pick_batch_f32(int mode, int g, int opl);
 BatchKernel pick_batch_bf16(int mode, int g, int opl);

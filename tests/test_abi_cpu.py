@@ -275,3 +275,22 @@ def test_bloch_tiles_need_whole_pairs():
     assert P.lib().spline_eval_vgl_tile(ctypes.byref(d), fake, 10, fake, fake, fake, fake, odd, None) == P.SPL_EINVAL
     t = (ctypes.c_int32 * 2)()
     assert P.lib().spline_tile_for(ctypes.byref(d), 10, t) == 0 and t[1] % 2 == 0
+
+
+def test_sorted_evaluation_validates_before_any_launch():
+    fake = ctypes.c_void_p(256)
+    d = P.spline_desc_init(LAT, (8, 8, 8), 4, "f64", kvec=(0.1, 0.0, 0.0))
+    assert P.lib().spline_eval_vgl_sorted(ctypes.byref(d), fake, 10, fake, fake, fake, fake, None, fake, 1 << 20,
+                                          None) == P.SPL_EUNSUPPORTED
+    d = P.spline_desc_init(LAT, (8, 8, 8), 4, "f64")
+    assert P.lib().spline_eval_vgl_sorted(ctypes.byref(d), fake, 10, fake, fake, fake, fake, None, None, 0,
+                                          None) == P.SPL_EINVAL
+    assert P.lib().spline_eval_vgl_sorted(ctypes.byref(d), fake, 10, fake, fake, fake, fake, None,
+                                          ctypes.c_void_p(256 + 8), 1 << 20, None) == P.SPL_EINVAL
+    bad = (ctypes.c_int32 * 2)(3, 1)
+    assert P.lib().spline_eval_vgl_sorted(ctypes.byref(d), fake, 10, fake, fake, fake, fake, bad, fake, 1 << 20,
+                                          None) == P.SPL_EINVAL
+    assert P.lib().spline_eval_vgl_sorted(ctypes.byref(d), None, 0, None, None, None, None, None, None, 0,
+                                          None) == P.SPL_OK
+    nb = ctypes.c_int64(7)
+    assert P.lib().spline_sorted_work_bytes(ctypes.byref(d), 0, ctypes.byref(nb)) == P.SPL_OK and nb.value == 0

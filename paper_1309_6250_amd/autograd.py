@@ -9,13 +9,21 @@ table's dtype; keep FP32 master coefficients when training.
 """
 import torch
 
-from .api import spline_eval_vgl, spline_eval_vgl_backward, OUT_TORCH
+from .api import spline_eval_vgl, spline_eval_vgl_sorted, spline_eval_vgl_backward, OUT_TORCH
 
 
 class SplineVGL(torch.autograd.Function):
+    """Outputs a loss does not use get no gradient tensor (None reaches the adjoint as NULL, so
+    that term is skipped instead of read as zeros).  sorted_forward runs the forward through
+    spline_eval_vgl_sorted (the same outputs, bitwise, evaluated in locality order)."""
+
     @staticmethod
-    def forward(ctx, table, pos, desc, flags=0):
-        v, g, l = spline_eval_vgl(desc, table, pos)
+    def forward(ctx, table, pos, desc, flags=0, sorted_forward=False):
+        ctx.set_materialize_grads(False)
+        if sorted_forward:
+            v, g, l = spline_eval_vgl_sorted(desc, table, pos)
+        else:
+            v, g, l = spline_eval_vgl(desc, table, pos)
         ctx.save_for_backward(table, pos)
         ctx.desc = desc
         ctx.flags = flags
@@ -29,14 +37,15 @@ class SplineVGL(torch.autograd.Function):
         prep = [None if g is None else g.to(od).contiguous() for g in (gv, gg, gl)]
         want_t, want_p = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         if not (want_t or want_p):
-            return None, None, None, None
+            return None, None, None, None, None
         gtable, gpos = spline_eval_vgl_backward(desc, table, pos, *prep, want_table=want_t, want_pos=want_p,
                                                 flags=ctx.flags)
-        return gtable, gpos, None, None
+        return gtable, gpos, None, None, None
 
 
-def spline_vgl(table, pos, desc, deterministic=False):
+def spline_vgl(table, pos, desc, deterministic=False, sorted_forward=False):
     """Differentiable (v, grad, lap) of the spline `table` at `pos`.  deterministic=True makes the
-    coefficient gradient bitwise reproducible (cell-sorted accumulation instead of atomics)."""
+    coefficient gradient bitwise reproducible (cell-sorted accumulation instead of atomics);
+    sorted_forward=True evaluates the points in locality order (same outputs)."""
     from ._lib import SPL_DETERMINISTIC
-    return SplineVGL.apply(table, pos, desc, SPL_DETERMINISTIC if deterministic else 0)
+    return SplineVGL.apply(table, pos, desc, SPL_DETERMINISTIC if deterministic else 0, sorted_forward)

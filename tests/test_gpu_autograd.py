@@ -133,3 +133,29 @@ def test_adam_fit_lowers_the_loss(dtype):
     assert np.all(np.isfinite(losses))
     # padding columns stay exactly zero
     assert torch.all(fitted[..., s.n_orb:] == 0)
+
+
+def test_sorted_forward_and_unused_outputs():
+    """The locality-ordered forward gives the same outputs and gradients, bitwise; an output the loss
+    does not use contributes nothing (its gradient reaches the adjoint as NULL)."""
+    rng, beta, pos, d = _case(303, n_pts=2000)
+    n, o = pos.shape[0], d.n_orb
+    A = to_dev(rng.standard_normal((n, o)))
+    table = table_from_oracle(d, beta, "f64")
+    res = []
+    for sorted_forward in (False, True):
+        t = table.clone().requires_grad_(True)
+        x = to_dev(pos).requires_grad_(True)
+        v, g, l = P.SplineVGL.apply(t, x, d, P.SPL_DETERMINISTIC, sorted_forward)
+        (v * A).sum().backward()                                   # grad and lap unused
+        torch.cuda.synchronize()
+        res.append((v.detach(), t.grad, x.grad))
+    for a, b in zip(*res):
+        assert torch.equal(a, b)
+    # the same loss with explicit zero upstream gradients for grad and lap
+    zg = torch.zeros((n, 3, o), dtype=torch.float64, device=DEV)
+    zl = torch.zeros((n, o), dtype=torch.float64, device=DEV)
+    gt, gp = P.spline_eval_vgl_backward(d, table, to_dev(pos), A, zg, zl, flags=P.SPL_DETERMINISTIC)
+    torch.cuda.synchronize()
+    assert torch.allclose(gt, res[0][1], rtol=0, atol=1e-14 * float(gt.abs().max()))
+    assert torch.allclose(gp, res[0][2], rtol=0, atol=1e-14 * float(gp.abs().max()))

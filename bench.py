@@ -194,6 +194,8 @@ def sorted_form(wl, d, table, outs, dtype, steps, warmup, tile=None):
     if tile is None:
         best = None
         for opl in OPLS[dtype]:
+            if d.bloch and opl % 2:
+                continue                       # Bloch lanes hold whole (re, im) pairs
             for g in (4, 8, 16, 32, 64, 128, 256):
                 ms = time_launches(lambda: P.spline_eval_vgl_sorted(d, table, wl.pos, *outs, work=work, tile=(g, opl)),
                                    3, 1)
@@ -202,7 +204,7 @@ def sorted_form(wl, d, table, outs, dtype, steps, warmup, tile=None):
         tile = best[1]
     ms = time_launches(lambda: P.spline_eval_vgl_sorted(d, table, wl.pos, *outs, work=work, tile=tile), steps, warmup)
     evals = n_pts * d.n_orb
-    alg = evals * bytes_per_eval(dtype, d.n_tables) + 24 * n_pts
+    alg = evals * bytes_per_eval(dtype, d.n_tables, 2 if d.bloch else 1) + 24 * n_pts
     return {"evals_per_s": evals / (ms * 1e-3), "ms_per_sweep": ms, "alg_bytes_per_sweep": alg,
             "alg_GBps": alg / (ms * 1e-3) / 1e9, "frac_hbm_peak": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "tile": list(tile), "table_bytes": int(d.table_bytes),
@@ -775,7 +777,7 @@ def main():
                 forms[name] = rec
                 log(f"{name}: {rec['evals_per_s']:.3e} evals/s, {rec['alg_GBps']:.0f} GB/s "
                     f"({100 * rec['frac_hbm_peak']:.0f}% of HBM peak)")
-                if not lap or dtype == "f32":
+                if not lap or dtype != "bf16":
                     forms[name + "-sorted"] = sorted_form(wl2, d, t, o, dtype, args.steps, args.warmup)
                     log(f"{name}-sorted: {forms[name + '-sorted']['evals_per_s']:.3e} evals/s")
                 del t, o
@@ -795,6 +797,9 @@ def main():
                 forms[name] = rec
                 log(f"{name}: {rec['evals_per_s']:.3e} evals/s, {rec['alg_GBps']:.0f} GB/s "
                     f"({100 * rec['frac_hbm_peak']:.0f}% of HBM peak)")
+                if dtype == "f32":
+                    forms[name + "-sorted"] = sorted_form(wl2, d, t, o, dtype, args.steps, args.warmup)
+                    log(f"{name}-sorted: {forms[name + '-sorted']['evals_per_s']:.3e} evals/s")
                 del t, o
                 torch.cuda.empty_cache()
         del fields
@@ -809,6 +814,9 @@ def main():
             forms[name] = rec
             log(f"{name}: {rec['evals_per_s']:.3e} evals/s, {rec['alg_GBps']:.0f} GB/s "
                 f"({100 * rec['frac_hbm_peak']:.0f}% of HBM peak)")
+            if dtype == "f32":
+                forms[name + "-sorted"] = sorted_form(wl2, d, t, o, dtype, args.steps, args.warmup)
+                log(f"{name}-sorted: {forms[name + '-sorted']['evals_per_s']:.3e} evals/s")
             del t, o
             torch.cuda.empty_cache()
         del wl2
@@ -823,6 +831,8 @@ def main():
             forms[name] = rec
             log(f"{name}: {rec['evals_per_s']:.3e} evals/s, {rec['alg_GBps']:.0f} GB/s "
                 f"({100 * rec['frac_hbm_peak']:.0f}% of HBM peak)")
+            forms[name + "-sorted"] = sorted_form(wl7, d, t, o, dtype, args.steps, args.warmup)
+            log(f"{name}-sorted: {forms[name + '-sorted']['evals_per_s']:.3e} evals/s")
             del t, o
         del wl7
         torch.cuda.empty_cache()

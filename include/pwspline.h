@@ -236,8 +236,7 @@ int spline_eval_vgl_tile(const spl_desc* d, const void* table, int64_t n_pts, co
  *   tile       NULL = the tile spline_eval_vgl would use, else as in spline_eval_vgl_tile
  *   work       device workspace, 256-byte aligned, at least spline_sorted_work_bytes() bytes,
  *              contents undefined afterwards
- * Real B-spline tables (with or without a separate Laplacian) only: other descriptors ->
- * SPL_EUNSUPPORTED.  Allocates nothing.
+ * Every representation a descriptor can describe is accepted.  Allocates nothing.
  */
 int spline_eval_vgl_sorted(const spl_desc* d, const void* table, int64_t n_pts, const double* pos,
                            void* v, void* grad, void* lap, const int32_t* tile,

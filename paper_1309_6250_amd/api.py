@@ -252,7 +252,7 @@ def spline_eval_vgl_sorted(desc, table, pos, v=None, grad=None, lap=None, work=N
     check(lib().spline_eval_vgl_sorted(ctypes.byref(desc), _ptr(table), n, _ptr(pos), _ptr(v), _ptr(grad), _ptr(lap),
                                        t, _ptr(work), int(work.numel() * work.element_size()), _stream(stream)),
           "spline_eval_vgl_sorted")
-    return v, grad, lap
+    return _as_complex(desc, v), _as_complex(desc, grad), _as_complex(desc, lap)
 
 
 def spline_eval_vgl_backward(desc, table, pos, gv=None, ggrad=None, glap=None, gtable=None, gpos=None,

@@ -421,8 +421,6 @@ int spline_eval_vgl_sorted(const spl_desc* d, const void* table, int64_t n_pts, 
   clear_error();
   int rc = check_eval_args(d, table, n_pts, pos);
   if (rc) return rc;
-  if (d->basis != SPL_BSPLINE || d->sep_grad || d->bloch)
-    return fail(SPL_EUNSUPPORTED, "locality-ordered evaluation covers real B-spline tables without separate gradients");
   if (n_pts == 0) return SPL_OK;
   if ((rc = check_vgl_outputs(d, v, grad, lap))) return rc;
   if (!work) return fail(SPL_EINVAL, "work is NULL (size from spline_sorted_work_bytes)");

@@ -52,6 +52,8 @@ void fill_eval_args(const spl_desc* d, const void* table, int64_t n_pts, const d
   a->vec_store = (d->n_col % opl) == 0 && al;
   a->tab_stride = d->table_elems;
   for (int c = 0; c < 3; ++c) a->k[c] = d->kvec[c];
+  a->perm = nullptr;
+  a->per_xcd = 0;
 }
 
 // Kernel of one forward evaluation of descriptor d (nullptr if the tile has none).

@@ -49,6 +49,8 @@ struct EvalArgs {
   int32_t vec_store;  // n_orb % OPL == 0 and outputs 16-byte aligned: whole-vector stores
   int64_t tab_stride; // elements of one table: table q (separate Laplacian, gradients) starts at q * tab_stride
   double k[3];        // crystal momentum of Bloch orbitals (Bloch variants only)
+  const int32_t* perm;  // locality order of the points (sorted evaluation), or null: point q is perm[q]
+  int32_t per_xcd;      // with perm: tiles per XCD (workgroup b takes tile (b mod 8) * per_xcd + b / 8)
 };
 
 enum { MODE_V = 0, MODE_VGL = 1, MODE_VGL_SEPLAP = 2, MODE_SEP = 3 };
@@ -429,13 +431,17 @@ __device__ __forceinline__ void eval_point(const EvalArgs& a, const int p, const
   }
 }
 
-// One launch over one table: groups of G lanes, one point per group.
+// One launch over one table: groups of G lanes, one point per group.  With a permutation (sorted
+// evaluation) the points are taken in its order, and workgroups, which the hardware hands to the 8
+// XCDs in turn, are remapped so that each XCD walks a contiguous stretch of that order.
 template <typename TS, int MODE, int G, int OPL, int VAR>
 __global__ __launch_bounds__(256) void k_eval(EvalArgs a) {
   constexpr int GPB = 256 / G;
-  const int64_t q = (int64_t)blockIdx.x * GPB + (int)threadIdx.x / G;
+  const int b = (int)blockIdx.x;
+  const int64_t tile = a.perm ? (int64_t)(b & 7) * a.per_xcd + (b >> 3) : (int64_t)b;
+  const int64_t q = tile * GPB + (int)threadIdx.x / G;
   if (q >= a.n_pts) return;
-  int p = (int)q;
+  int p = a.perm ? a.perm[q] : (int)q;
   if constexpr (G >= 64) p = __builtin_amdgcn_readfirstlane(p);
   eval_point<TS, MODE, G, OPL, VAR>(a, p, (int)threadIdx.x % G);
 }

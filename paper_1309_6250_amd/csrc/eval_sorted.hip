@@ -1,16 +1,22 @@
-// spline_eval_vgl_sorted: cell keys along a Morton curve, radix sort, forward kernel through the
-// permutation (the kernels live in eval_sorted_impl.hpp).  The sort covers only the key bits the
-// grid needs (3 x ceil(log2 max N) + 1), so a 48^3 grid sorts 19-bit keys.
+// spline_eval_vgl_sorted: locality-ordered forward evaluation.
+//
+// Points arrive in any order (walkers x electrons, spread over the whole cell), so consecutive
+// points rarely share table rows and every block is gathered from memory.  On average a row of the
+// table belongs to the blocks of several points (64 P / N1 N2 N3 of them), so evaluating the points
+// in the order of a space-filling curve over the grid cells lets the points that one workgroup,
+// and one XCD, handle in sequence find most rows of their blocks already in L2 or the Infinity
+// Cache.  Steps: a Morton key of each point's cell (three grid indices interleaved), a stable radix
+// sort of (key, point index) over only the key bits the grid needs (3 x ceil(log2 max N) + 1: a
+// 48^3 grid sorts 19-bit keys), then the forward kernel of the descriptor's representation through
+// the permutation, with each XCD on a contiguous stretch of it.  Each point's outputs go to its own
+// row, in the caller's order, with the arithmetic of the unsorted launch: bitwise the same results.
 #include <hipcub/hipcub.hpp>
 
 #include "internal.hpp"
-#include "eval_sorted_impl.hpp"
 
 namespace pws {
 
-PermKernel pick_perm_f64(int mode, int g, int opl);
-PermKernel pick_perm_f32(int mode, int g, int opl);
-PermKernel pick_perm_bf16(int mode, int g, int opl);
+EvalKernel eval_kernel_for(const spl_desc* d, int values_only, const int32_t tile[2]);
 
 // Spread the low 10 bits of x to every third bit.
 __device__ __forceinline__ uint32_t spread3(uint32_t x) {
@@ -88,12 +94,8 @@ int launch_eval_sorted(const spl_desc* d, const void* table, int64_t n_pts, cons
   if (work_bytes < (int64_t)L.total)
     return fail(SPL_EINVAL, "workspace of %lld bytes is smaller than the %lld needed", (long long)work_bytes,
                 (long long)L.total);
-  const int mode = values_only ? MODE_V : (d->has_lap ? MODE_VGL_SEPLAP : MODE_VGL);
-  PermKernel k = nullptr;
-  if (d->dtype == SPL_F64) k = pick_perm_f64(mode, tile[0], tile[1]);
-  else if (d->dtype == SPL_F32) k = pick_perm_f32(mode, tile[0], tile[1]);
-  else k = pick_perm_bf16(mode, tile[0], tile[1]);
-  if (!k || !tile_valid_for(d, tile)) return fail(SPL_EINVAL, "invalid tile shape (%d, %d)", tile[0], tile[1]);
+  EvalKernel k = tile_valid_for(d, tile) ? eval_kernel_for(d, values_only, tile) : nullptr;
+  if (!k) return fail(SPL_EINVAL, "invalid tile shape (%d, %d)", tile[0], tile[1]);
   char* w = static_cast<char*>(work);
   uint32_t* keys_in = reinterpret_cast<uint32_t*>(w + L.keys_in);
   uint32_t* keys_out = reinterpret_cast<uint32_t*>(w + L.keys_out);
@@ -113,8 +115,9 @@ int launch_eval_sorted(const spl_desc* d, const void* table, int64_t n_pts, cons
   fill_eval_args(d, table, n_pts, pos, v, grad, lap, values_only, tile[1], &a);
   const int64_t gpb = 256 / tile[0];
   const int64_t n_tiles = (n_pts + gpb - 1) / gpb;
-  const int32_t per_xcd = (int32_t)((n_tiles + 7) / 8);
-  hipLaunchKernelGGL(k, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, stream, a, vals_out, per_xcd);
+  a.perm = vals_out;
+  a.per_xcd = (int32_t)((n_tiles + 7) / 8);
+  hipLaunchKernelGGL(k, dim3((unsigned)(8 * a.per_xcd)), dim3(256), 0, stream, a);
   return hip_fail(hipGetLastError(), "sorted evaluation launch");
 }
 

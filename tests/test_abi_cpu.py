@@ -279,9 +279,6 @@ def test_bloch_tiles_need_whole_pairs():
 
 def test_sorted_evaluation_validates_before_any_launch():
     fake = ctypes.c_void_p(256)
-    d = P.spline_desc_init(LAT, (8, 8, 8), 4, "f64", kvec=(0.1, 0.0, 0.0))
-    assert P.lib().spline_eval_vgl_sorted(ctypes.byref(d), fake, 10, fake, fake, fake, fake, None, fake, 1 << 20,
-                                          None) == P.SPL_EUNSUPPORTED
     d = P.spline_desc_init(LAT, (8, 8, 8), 4, "f64")
     assert P.lib().spline_eval_vgl_sorted(ctypes.byref(d), fake, 10, fake, fake, fake, fake, None, None, 0,
                                           None) == P.SPL_EINVAL

@@ -96,3 +96,36 @@ def test_sorted_full_size_equals_unsorted(key, dtype):
     b = P.spline_eval_vgl_sorted(d, table, pos, tile=tile)
     torch.cuda.synchronize()
     assert _same(a, b)
+
+
+@pytest.mark.parametrize("kind", ["pp", "pp_lap", "sep_bspline", "sep_lagrange", "bloch", "bloch_lap", "bloch_pp"])
+@pytest.mark.parametrize("dtype", ["f64", "bf16"])
+def test_sorted_equals_unsorted_for_every_representation(kind, dtype):
+    bloch = kind.startswith("bloch")
+    s = make_system("sorted-var", SKEW, (10, 9, 11), 5, 2.0, 2.0, (45, 2),
+                    kvec=(0.21, -0.13, 0.33) if bloch else None)
+    cdt = torch.complex128 if bloch else torch.float64
+    kv = s.k if bloch else None
+    if kind.startswith("sep"):
+        d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype, has_lap=True, sep_grad=True,
+                               basis=kind.split("_")[1])
+        grids = [s.grid_values()] + list(s.grid_gradient()) + [s.grid_laplacian()]
+        table = P.spline_build_tables(d, [to_dev(g, cdt) for g in grids])
+    else:
+        lap = kind.endswith("lap")
+        d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype, has_lap=lap,
+                               basis="pp" if "pp" in kind else "bspline", kvec=kv)
+        table = P.spline_build(d, to_dev(s.grid_values(), cdt), to_dev(s.grid_laplacian(), cdt) if lap else None)
+    pos = to_dev(_points(s, 700, 48))
+    opls = {"f64": (1, 2), "bf16": (2, 4, 8)}[dtype]
+    for g in (4, 64):
+        for opl in opls:
+            if bloch and opl % 2:
+                continue
+            say("sorted vs unsorted", kind, dtype, g, opl)
+            a = P.spline_eval_vgl(d, table, pos, tile=(g, opl))
+            b = P.spline_eval_vgl_sorted(d, table, pos, tile=(g, opl))
+            torch.cuda.synchronize()
+            if bloch:
+                a, b = [torch.view_as_real(x) for x in a], [torch.view_as_real(x) for x in b]
+            assert _same(a, b), (kind, g, opl)

@@ -228,11 +228,12 @@ int spline_eval_vgl_tile(const spl_desc* d, const void* table, int64_t n_pts, co
  * spline_eval_vgl with the points evaluated in locality order: the same outputs, bitwise, in the
  * caller's point order.  Points arrive spread over the whole cell, so consecutive points rarely
  * share rows of the table, although each row belongs to the blocks of 64 n_pts / (N1 N2 N3)
- * points on average (Sec. III B: every evaluation reads its 4x4x4 block).  Here each point's
- * cell gets a Morton key (its three grid indices, 10 bits each, interleaved), a stable radix sort
- * orders the points by key, and the forward kernel runs through that permutation with each XCD
- * taking a contiguous stretch of the curve, so neighbouring points share their rows in L2 and the
- * Infinity Cache.  The sort runs on `stream` inside the call.
+ * points on average (Sec. III B: every evaluation reads its 4x4x4 block).  Here a counting sort
+ * puts the points into buckets of cells numbered along a Morton curve (at most 2^18 buckets;
+ * larger grids group 2^k cells per axis), and the forward kernel runs through that permutation
+ * with each XCD taking a contiguous stretch of the curve, so neighbouring points share their rows
+ * in L2 and the Infinity Cache.  The sort runs on `stream` inside the call; the order within a
+ * bucket may differ between calls, the outputs do not.
  *   tile       NULL = the tile spline_eval_vgl would use, else as in spline_eval_vgl_tile
  *   work       device workspace, 256-byte aligned, at least spline_sorted_work_bytes() bytes,
  *              contents undefined afterwards
@@ -242,8 +243,8 @@ int spline_eval_vgl_sorted(const spl_desc* d, const void* table, int64_t n_pts, 
                            void* v, void* grad, void* lap, const int32_t* tile,
                            void* work, int64_t work_bytes, void* stream);
 
-/* Workspace size (bytes) of spline_eval_vgl_sorted for n_pts points (keys, permutation and the
- * radix sort's scratch).  Host only; may query the current HIP device. */
+/* Workspace size (bytes) of spline_eval_vgl_sorted for n_pts points (bucket of each point, bucket
+ * counts and offsets, permutation, the scan's scratch).  Host only; may query the current HIP device. */
 int spline_sorted_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes);
 
 /*

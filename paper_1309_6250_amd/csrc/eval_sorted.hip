@@ -5,11 +5,11 @@
 // table belongs to the blocks of several points (64 P / N1 N2 N3 of them), so evaluating the points
 // in the order of a space-filling curve over the grid cells lets the points that one workgroup,
 // and one XCD, handle in sequence find most rows of their blocks already in L2 or the Infinity
-// Cache.  Steps: a Morton key of each point's cell (three grid indices interleaved), a stable radix
-// sort of (key, point index) over only the key bits the grid needs (3 x ceil(log2 max N) + 1: a
-// 48^3 grid sorts 19-bit keys), then the forward kernel of the descriptor's representation through
-// the permutation, with each XCD on a contiguous stretch of it.  Each point's outputs go to its own
-// row, in the caller's order, with the arithmetic of the unsorted launch: bitwise the same results.
+// Cache.  Steps: a counting sort of the points into buckets of cells numbered along a Morton curve
+// (clear, count with atomics, exclusive scan, scatter), then the forward kernel of the descriptor's
+// representation through the resulting permutation, with each XCD on a contiguous stretch of it.
+// Each point's outputs go to its own row, in the caller's order, with the arithmetic of the unsorted
+// launch: bitwise the same results.
 #include <hipcub/hipcub.hpp>
 
 #include "internal.hpp"
@@ -28,48 +28,74 @@ __device__ __forceinline__ uint32_t spread3(uint32_t x) {
   return x;
 }
 
-// Key of a point: the Morton index of its cell (i0 interleaved, `bits` <= 10 bits per axis);
-// points with non-finite coordinates get 2^(3 bits) and sort last.
-__global__ __launch_bounds__(256) void k_morton_keys(Geom g, const double* pos, int32_t n_pts, int32_t bits,
-                                                     uint32_t* keys, int32_t* vals) {
+// Buckets: cells grouped 2^shift per axis and numbered along the Morton curve (3 x `bits` bits, at most
+// 18), so the bucket index space has at most 2^18 entries; points with non-finite coordinates go to
+// the extra last bucket.  A counting sort into buckets gives the locality order; the order inside a
+// bucket is whatever the scatter's atomics produce, which changes no output (every point's arithmetic
+// is independent of the lane and workgroup that run it).
+struct BucketGeom {
+  int bits;     // bits per axis of a bucket coordinate
+  int shift;    // cells per bucket along an axis: 2^shift
+  int n_buckets;
+};
+
+static BucketGeom bucket_geom(const spl_desc* d) {
+  const int n = std::max(d->grid[0], std::max(d->grid[1], d->grid[2]));
+  int b = 1;
+  while ((1 << b) < n) ++b;
+  BucketGeom bg;
+  bg.shift = b > 6 ? b - 6 : 0;
+  bg.bits = b - bg.shift;
+  bg.n_buckets = (1 << (3 * bg.bits)) + 1;
+  return bg;
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero_i32(int32_t* x, int32_t n) {
+  for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < n; i += (int)(gridDim.x * blockDim.x)) x[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_bucket_count(Geom g, const double* pos, int32_t n_pts, int32_t shift,
+                                                      int32_t sentinel, int32_t* bucket, int32_t* counts) {
   const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (p >= n_pts) return;
   int i0[3];
   double t[3];
   const bool ok = reduce_point(g, pos[3 * (int64_t)p], pos[3 * (int64_t)p + 1], pos[3 * (int64_t)p + 2], i0, t);
-  keys[p] = ok ? (spread3((uint32_t)i0[0]) << 2) | (spread3((uint32_t)i0[1]) << 1) | spread3((uint32_t)i0[2])
-               : (1u << (3 * bits));
-  vals[p] = p;
+  const int32_t b = ok ? (int32_t)((spread3((uint32_t)(i0[0] >> shift)) << 2) |
+                                   (spread3((uint32_t)(i0[1] >> shift)) << 1) | spread3((uint32_t)(i0[2] >> shift)))
+                       : sentinel;
+  bucket[p] = b;
+  atomicAdd(&counts[b], 1);
+}
+
+// offsets holds each bucket's first slot on entry and is used as its cursor.
+__global__ __launch_bounds__(256) void k_bucket_scatter(int32_t n_pts, const int32_t* bucket, int32_t* offsets,
+                                                        int32_t* perm) {
+  const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (p >= n_pts) return;
+  perm[atomicAdd(&offsets[bucket[p]], 1)] = p;
 }
 
 struct PermLayout {
-  size_t keys_in, keys_out, vals_in, vals_out, temp, temp_bytes, total;
+  size_t bucket, counts, offsets, perm, temp, temp_bytes, total;
+  BucketGeom bg;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Bits per axis of the Morton key: enough for the largest grid index.
-static int key_bits(const spl_desc* d) {
-  const int n = std::max(d->grid[0], std::max(d->grid[1], d->grid[2]));
-  int b = 1;
-  while ((1 << b) < n) ++b;
-  return b;
-}
-
 static int perm_layout(const spl_desc* d, int64_t n_pts, PermLayout* L) {
+  L->bg = bucket_geom(d);
   size_t t = 0;
-  const int end_bit = 3 * key_bits(d) + 1;
-  int rc = hip_fail(hipcub::DeviceRadixSort::SortPairs(nullptr, t, (const uint32_t*)nullptr, (uint32_t*)nullptr,
-                                                       (const int32_t*)nullptr, (int32_t*)nullptr, (int)n_pts, 0,
-                                                       end_bit, (hipStream_t)0),
-                    "radix sort size query");
+  int rc = hip_fail(hipcub::DeviceScan::ExclusiveSum(nullptr, t, (const int32_t*)nullptr, (int32_t*)nullptr,
+                                                     L->bg.n_buckets, (hipStream_t)0),
+                    "scan size query");
   if (rc) return rc;
-  const size_t n = (size_t)n_pts;
+  const size_t n = (size_t)n_pts, nb = (size_t)L->bg.n_buckets;
   size_t off = 0;
-  L->keys_in = off; off = align256(off + 4 * n);
-  L->keys_out = off; off = align256(off + 4 * n);
-  L->vals_in = off; off = align256(off + 4 * n);
-  L->vals_out = off; off = align256(off + 4 * n);
+  L->bucket = off; off = align256(off + 4 * n);
+  L->counts = off; off = align256(off + 4 * nb);
+  L->offsets = off; off = align256(off + 4 * nb);
+  L->perm = off; off = align256(off + 4 * n);
   L->temp = off; off = align256(off + t);
   L->temp_bytes = t;
   L->total = off;
@@ -97,25 +123,30 @@ int launch_eval_sorted(const spl_desc* d, const void* table, int64_t n_pts, cons
   EvalKernel k = tile_valid_for(d, tile) ? eval_kernel_for(d, values_only, tile) : nullptr;
   if (!k) return fail(SPL_EINVAL, "invalid tile shape (%d, %d)", tile[0], tile[1]);
   char* w = static_cast<char*>(work);
-  uint32_t* keys_in = reinterpret_cast<uint32_t*>(w + L.keys_in);
-  uint32_t* keys_out = reinterpret_cast<uint32_t*>(w + L.keys_out);
-  int32_t* vals_in = reinterpret_cast<int32_t*>(w + L.vals_in);
-  int32_t* vals_out = reinterpret_cast<int32_t*>(w + L.vals_out);
+  int32_t* bucket = reinterpret_cast<int32_t*>(w + L.bucket);
+  int32_t* counts = reinterpret_cast<int32_t*>(w + L.counts);
+  int32_t* offsets = reinterpret_cast<int32_t*>(w + L.offsets);
+  int32_t* perm = reinterpret_cast<int32_t*>(w + L.perm);
+  const int nb = L.bg.n_buckets;
+  const unsigned pblocks = (unsigned)((n_pts + 255) / 256);
+  hipLaunchKernelGGL(k_fill_zero_i32, dim3((unsigned)std::min(1024, (nb + 255) / 256)), dim3(256), 0, stream, counts,
+                     nb);
+  if ((rc = hip_fail(hipGetLastError(), "bucket clear launch"))) return rc;
   const Geom geo = make_geom(d);
-  const int bits = key_bits(d);
-  hipLaunchKernelGGL(k_morton_keys, dim3((unsigned)((n_pts + 255) / 256)), dim3(256), 0, stream, geo, pos,
-                     (int32_t)n_pts, (int32_t)bits, keys_in, vals_in);
-  if ((rc = hip_fail(hipGetLastError(), "cell key launch"))) return rc;
+  hipLaunchKernelGGL(k_bucket_count, dim3(pblocks), dim3(256), 0, stream, geo, pos, (int32_t)n_pts,
+                     (int32_t)L.bg.shift, (int32_t)(nb - 1), bucket, counts);
+  if ((rc = hip_fail(hipGetLastError(), "bucket count launch"))) return rc;
   size_t temp_bytes = L.temp_bytes;
-  if ((rc = hip_fail(hipcub::DeviceRadixSort::SortPairs(w + L.temp, temp_bytes, keys_in, keys_out, vals_in, vals_out,
-                                                        (int)n_pts, 0, 3 * bits + 1, stream),
-                     "radix sort")))
+  if ((rc = hip_fail(hipcub::DeviceScan::ExclusiveSum(w + L.temp, temp_bytes, counts, offsets, nb, stream),
+                     "bucket scan")))
     return rc;
+  hipLaunchKernelGGL(k_bucket_scatter, dim3(pblocks), dim3(256), 0, stream, (int32_t)n_pts, bucket, offsets, perm);
+  if ((rc = hip_fail(hipGetLastError(), "bucket scatter launch"))) return rc;
   EvalArgs a;
   fill_eval_args(d, table, n_pts, pos, v, grad, lap, values_only, tile[1], &a);
   const int64_t gpb = 256 / tile[0];
   const int64_t n_tiles = (n_pts + gpb - 1) / gpb;
-  a.perm = vals_out;
+  a.perm = perm;
   a.per_xcd = (int32_t)((n_tiles + 7) / 8);
   hipLaunchKernelGGL(k, dim3((unsigned)(8 * a.per_xcd)), dim3(256), 0, stream, a);
   return hip_fail(hipGetLastError(), "sorted evaluation launch");

@@ -76,7 +76,7 @@ def test_sorted_matches_oracle_and_edge_cases():
                                         P.api._ptr(v), P.api._ptr(g), P.api._ptr(l), None, P.api._ptr(small), 16,
                                         None)
     assert rc == P.SPL_EINVAL
-    assert P.spline_sorted_work_bytes(d, 10**6) > 12 * 10**6
+    assert P.spline_sorted_work_bytes(d, 10**6) >= 8 * 10**6          # bucket and slot of every point
 
 
 @pytest.mark.timeout(600)

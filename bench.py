@@ -611,12 +611,19 @@ def batched_row(steps, warmup):
     n_tiles, n_evals = plan.info()
     ms = time_launches(plan.run_graph, steps, warmup)
     ms_eager = time_launches(plan.run, steps, warmup)
-    alg = sum(it[2].shape[0] * it[0].n_orb * bytes_per_eval("f32", False) + 24 * it[2].shape[0] for it in items)
+    alg = sum(it[2].shape[0] * it[0].n_orb * bytes_per_eval("f32") + 24 * it[2].shape[0] for it in items)
+    # the same plan with every item's points in locality order (sort inside every launch), retuned
+    plan.sort(True)
+    tile_s = plan.autotune()
+    ms_sorted = time_launches(plan.run_graph, steps, warmup)
     plan.close()
     return {"systems": len(items), "evals_per_launch": n_evals, "tiles": n_tiles, "tile": list(tile),
             "ms_graph": ms, "ms_eager": ms_eager, "evals_per_s": n_evals / (ms * 1e-3),
             "alg_GBps": alg / (ms * 1e-3) / 1e9, "frac_hbm_peak": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "table_bytes": table_bytes}
+            "table_bytes": table_bytes,
+            "sorted": {"tile": list(tile_s), "ms_graph": ms_sorted, "evals_per_s": n_evals / (ms_sorted * 1e-3),
+                       "speedup": ms / ms_sorted,
+                       "note": "spline_batch_plan_sort: counting sort of every item's points inside each launch"}}
 
 
 def _gpu_ready():
@@ -751,7 +758,8 @@ def main():
             del t, o
         rows = rows_measurements(wl1, args.steps, args.warmup)
         rows["batched_persistent_graph_f32"] = batched_row(args.steps, args.warmup)
-        log(f"batched: {rows['batched_persistent_graph_f32']['evals_per_s']:.3e} evals/s")
+        log(f"batched: {rows['batched_persistent_graph_f32']['evals_per_s']:.3e} evals/s, sorted "
+            f"{rows['batched_persistent_graph_f32']['sorted']['evals_per_s']:.3e}")
         torch.cuda.empty_cache()
         rows.update(fit_rows(args.steps, args.warmup))
         log(f"fit: {rows['smoothing_fit_adam_f32']['ms_per_step']:.2f} ms per Adam step, loss "

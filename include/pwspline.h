@@ -322,6 +322,16 @@ int spline_batch_graph_launch(void* plan, void* stream);
  * the plan and return it in tile_out.  Outputs are overwritten with valid results. */
 int spline_batch_autotune(void* plan, void* stream, int32_t tile_out[2]);
 
+/* Evaluate the plan's points in locality order (enable = 1) or in their given order (0, the
+ * default).  Sorted launches first counting-sort every item's points into buckets of its cells
+ * numbered along a Morton curve (at most 2^15 per item), as spline_eval_vgl_sorted does for one
+ * system, then run the persistent kernel through each item's permutation; outputs are bitwise the
+ * same.  The first enable allocates the plan-owned sort state (per-point buckets and permutation,
+ * bucket counts and offsets, scan scratch) and synchronizes `stream`; toggling drops the captured
+ * graph.  Sorted launches stay graph-capturable.  Errors: NULL plan or enable not 0/1 ->
+ * SPL_EINVAL; allocation failure -> SPL_ENOMEM. */
+int spline_batch_plan_sort(void* plan, int32_t enable, void* stream);
+
 /* Release a plan and everything it owns (synchronizes the device first). */
 void spline_batch_plan_destroy(void* plan);
 

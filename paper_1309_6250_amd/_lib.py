@@ -24,7 +24,7 @@ EXPORTS = (
     "spline_batch_graph_launch", "spline_batch_autotune", "spline_batch_plan_destroy", "spline_batch_plan_info", "spline_autotune",
     "spline_tile_for", "spline_last_error", "spline_version", "spline_backward_work_bytes",
     "spline_build_smoothing", "spline_smoothing_work_bytes", "spline_build_tables",
-    "spline_eval_vgl_sorted", "spline_sorted_work_bytes",
+    "spline_eval_vgl_sorted", "spline_sorted_work_bytes", "spline_batch_plan_sort",
 )
 
 
@@ -105,6 +105,7 @@ def lib():
             "spline_batch_graph_launch": (ctypes.c_int, [vp, vp]),
             "spline_batch_autotune": (ctypes.c_int, [vp, vp, i32p]),
             "spline_batch_plan_destroy": (None, [vp]),
+            "spline_batch_plan_sort": (ctypes.c_int, [vp, i32, vp]),
             "spline_batch_plan_info": (ctypes.c_int, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
             "spline_autotune": (ctypes.c_int, [pd, vp, i64, vp, vp, vp, vp, vp, i32p]),
             "spline_tile_for": (ctypes.c_int, [pd, i64, i32p]),

@@ -344,6 +344,10 @@ class BatchPlan:
         check(lib().spline_batch_autotune(self._plan, _stream(stream), t), "spline_batch_autotune")
         return (t[0], t[1])
 
+    def sort(self, enable=True, stream=None):
+        """Evaluate the points in locality order from now on (same outputs); allocates once."""
+        check(lib().spline_batch_plan_sort(self._plan, 1 if enable else 0, _stream(stream)), "spline_batch_plan_sort")
+
     def info(self):
         a, b = ctypes.c_int64(), ctypes.c_int64()
         check(lib().spline_batch_plan_info(self._plan, ctypes.byref(a), ctypes.byref(b)), "spline_batch_plan_info")

@@ -5,6 +5,17 @@
 // tile), the exclusive prefix of tiles per item and the work counter.  A launch is two kernels
 // on one stream: k_batch_reset (zeroes the counter, so no memset node is needed in a graph) and
 // k_eval_batch (the persistent kernel, one workgroup per resident slot of the GPU).
+//
+// Sorted plans (spline_batch_plan_sort) first put every item's points in locality order, as the
+// single-system sorted call does: one counting sort over all items at once.  Item j owns the
+// global buckets [bucket_base_j, bucket_base_j + buckets_j), cells grouped 2^shift per axis and
+// numbered along a Morton curve (at most 2^15 per item, plus one for non-finite points), so the
+// slots of its points form the contiguous range [point_start_j, point_start_j + n_pts_j) of the
+// permutation, which holds item-local indices.  The kernels: clear the counts, count (each point
+// finds its item by binary search), exclusive scan, scatter; then the persistent launch reads each
+// item's slice of the permutation.
+#include <hipcub/hipcub.hpp>
+
 #include <algorithm>
 #include <numeric>
 #include <vector>
@@ -12,6 +23,54 @@
 #include "internal.hpp"
 
 namespace pws {
+
+__global__ __launch_bounds__(256) void k_fill_zero_i32(int32_t* x, int32_t n);
+
+struct SortItem {
+  Geom g;
+  const double* pos;
+  int32_t n_pts;
+  int32_t shift;        // cells per bucket along an axis: 2^shift
+  int32_t bucket_base;  // first global bucket of the item
+  int32_t sentinel;     // the item's bucket of points with non-finite coordinates (its last)
+  int32_t point_start;  // first slot of the item in the permutation
+};
+
+__device__ __forceinline__ int sort_item_of(const SortItem* items, int n_items, int p) {
+  int lo = 0, hi = n_items - 1;                      // last item whose first slot <= p
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].point_start <= p) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_batch_bucket_count(const SortItem* items, int32_t n_items, int32_t n_total,
+                                                            int32_t* bucket, int32_t* counts) {
+  const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (p >= n_total) return;
+  const SortItem& it = items[sort_item_of(items, n_items, p)];
+  const int q = p - it.point_start;
+  int i0[3];
+  double t[3];
+  const bool ok = reduce_point(it.g, it.pos[3 * (int64_t)q], it.pos[3 * (int64_t)q + 1], it.pos[3 * (int64_t)q + 2],
+                               i0, t);
+  const int32_t b = ok ? it.bucket_base + (int32_t)((spread3((uint32_t)(i0[0] >> it.shift)) << 2) |
+                                                    (spread3((uint32_t)(i0[1] >> it.shift)) << 1) |
+                                                    spread3((uint32_t)(i0[2] >> it.shift)))
+                       : it.sentinel;
+  bucket[p] = b;
+  atomicAdd(&counts[b], 1);
+}
+
+__global__ __launch_bounds__(256) void k_batch_bucket_scatter(const SortItem* items, int32_t n_items, int32_t n_total,
+                                                              const int32_t* bucket, int32_t* offsets, int32_t* perm) {
+  const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (p >= n_total) return;
+  const SortItem& it = items[sort_item_of(items, n_items, p)];
+  perm[atomicAdd(&offsets[bucket[p]], 1)] = p - it.point_start;
+}
 
 // Zero the work counter with an ordinary vector store (a kernel node, so a captured graph holds
 // no memset node).
@@ -37,6 +96,18 @@ struct Plan {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // sorted plans
+  bool sort_on = false;
+  SortItem* d_sort = nullptr;
+  int32_t* d_bucket = nullptr;
+  int32_t* d_counts = nullptr;
+  int32_t* d_offsets = nullptr;
+  int32_t* d_perm = nullptr;
+  void* d_scan_temp = nullptr;
+  size_t scan_temp_bytes = 0;
+  int32_t n_points = 0;
+  int32_t n_buckets = 0;
+  std::vector<int32_t> point_start;
 };
 
 static BatchKernel pick_batch(int dtype, int mode, int g, int opl) {
@@ -67,6 +138,7 @@ static int plan_set_tile(Plan* pl, const int32_t tile[2], hipStream_t stream) {
   for (int j = 0; j < n; ++j) {
     const spl_item& it = pl->items[j];
     fill_eval_args(&pl->descs[j], it.table, it.n_pts, it.pos, it.v, it.grad, it.lap, 0, tile[1], &pl->args[j]);
+    if (pl->sort_on) pl->args[j].perm = pl->d_perm + pl->point_start[j];
     pl->tile_start[j] = (int32_t)tiles;
     tiles += (it.n_pts + per_tile - 1) / per_tile;
   }
@@ -99,8 +171,27 @@ static int plan_set_tile(Plan* pl, const int32_t tile[2], hipStream_t stream) {
 
 static int plan_launch(Plan* pl, hipStream_t stream) {
   if (pl->n_tiles == 0) return SPL_OK;
+  int rc;
+  if (pl->sort_on) {
+    const int n_items = (int)pl->items.size();
+    const unsigned pb = (unsigned)((pl->n_points + 255) / 256);
+    hipLaunchKernelGGL(k_fill_zero_i32, dim3((unsigned)std::min(1024, (pl->n_buckets + 255) / 256)), dim3(256), 0,
+                       stream, pl->d_counts, pl->n_buckets);
+    if ((rc = hip_fail(hipGetLastError(), "bucket clear launch"))) return rc;
+    hipLaunchKernelGGL(k_batch_bucket_count, dim3(pb), dim3(256), 0, stream, pl->d_sort, (int32_t)n_items,
+                       pl->n_points, pl->d_bucket, pl->d_counts);
+    if ((rc = hip_fail(hipGetLastError(), "bucket count launch"))) return rc;
+    size_t tb = pl->scan_temp_bytes;
+    if ((rc = hip_fail(hipcub::DeviceScan::ExclusiveSum(pl->d_scan_temp, tb, pl->d_counts, pl->d_offsets,
+                                                        pl->n_buckets, stream),
+                       "bucket scan")))
+      return rc;
+    hipLaunchKernelGGL(k_batch_bucket_scatter, dim3(pb), dim3(256), 0, stream, pl->d_sort, (int32_t)n_items,
+                       pl->n_points, pl->d_bucket, pl->d_offsets, pl->d_perm);
+    if ((rc = hip_fail(hipGetLastError(), "bucket scatter launch"))) return rc;
+  }
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, stream, pl->d_counter);
-  int rc = hip_fail(hipGetLastError(), "batch counter reset launch");
+  rc = hip_fail(hipGetLastError(), "batch counter reset launch");
   if (rc) return rc;
   BatchArgs b;
   b.items = pl->d_items;
@@ -120,7 +211,54 @@ static void plan_free(Plan* pl) {
   if (pl->d_items) hipFree(pl->d_items);
   if (pl->d_tile_start) hipFree(pl->d_tile_start);
   if (pl->d_counter) hipFree(pl->d_counter);
+  for (void* p : {(void*)pl->d_sort, (void*)pl->d_bucket, (void*)pl->d_counts, (void*)pl->d_offsets,
+                  (void*)pl->d_perm, pl->d_scan_temp})
+    if (p) hipFree(p);
   delete pl;
+}
+
+// Allocate and fill the sorting state of a plan (once).
+static int plan_sort_setup(Plan* pl, hipStream_t stream) {
+  if (pl->d_sort) return SPL_OK;
+  const int n = (int)pl->items.size();
+  std::vector<SortItem> si(n);
+  pl->point_start.assign(n, 0);
+  int64_t pts = 0, buckets = 0;
+  for (int j = 0; j < n; ++j) {
+    const spl_desc& d = pl->descs[j];
+    const int nmax = std::max(d.grid[0], std::max(d.grid[1], d.grid[2]));
+    int b = 1;
+    while ((1 << b) < nmax) ++b;
+    const int shift = b > 5 ? b - 5 : 0;
+    si[j].g = make_geom(&d);
+    si[j].pos = pl->items[j].pos;
+    si[j].n_pts = (int32_t)pl->items[j].n_pts;
+    si[j].shift = shift;
+    si[j].bucket_base = (int32_t)buckets;
+    buckets += (int64_t)1 << (3 * (b - shift));
+    si[j].sentinel = (int32_t)buckets;
+    buckets += 1;
+    si[j].point_start = (int32_t)pts;
+    pl->point_start[j] = (int32_t)pts;
+    pts += pl->items[j].n_pts;
+  }
+  if (pts > 0x7fffffffLL || buckets > 0x7fffffffLL) return fail(SPL_EINVAL, "batch too large to sort");
+  pl->n_points = (int32_t)pts;
+  pl->n_buckets = (int32_t)buckets;
+  int rc = hip_fail(hipcub::DeviceScan::ExclusiveSum(nullptr, pl->scan_temp_bytes, (const int32_t*)nullptr,
+                                                     (int32_t*)nullptr, pl->n_buckets, stream),
+                    "scan size query");
+  if (rc) return rc;
+  const size_t np = (size_t)std::max<int64_t>(pts, 1), nb = (size_t)buckets;
+  if (hipMalloc(&pl->d_sort, sizeof(SortItem) * n) != hipSuccess || hipMalloc(&pl->d_bucket, 4 * np) != hipSuccess ||
+      hipMalloc(&pl->d_counts, 4 * nb) != hipSuccess || hipMalloc(&pl->d_offsets, 4 * nb) != hipSuccess ||
+      hipMalloc(&pl->d_perm, 4 * np) != hipSuccess ||
+      hipMalloc(&pl->d_scan_temp, std::max<size_t>(pl->scan_temp_bytes, 1)) != hipSuccess)
+    return fail(SPL_ENOMEM, "sorted batch: device allocation failed");
+  if ((rc = hip_fail(hipMemcpyAsync(pl->d_sort, si.data(), sizeof(SortItem) * n, hipMemcpyHostToDevice, stream),
+                     "upload sort items")))
+    return rc;
+  return hip_fail(hipStreamSynchronize(stream), "hipStreamSynchronize");
 }
 
 }  // namespace pws
@@ -270,6 +408,19 @@ int spline_batch_autotune(void* plan, void* stream, int32_t tile_out[2]) {
 }
 
 void spline_batch_plan_destroy(void* plan) { plan_free(static_cast<Plan*>(plan)); }
+
+int spline_batch_plan_sort(void* plan, int32_t enable, void* stream) {
+  clear_error();
+  if (!plan) return fail(SPL_EINVAL, "plan is NULL");
+  if (enable != 0 && enable != 1) return fail(SPL_EINVAL, "enable must be 0 or 1");
+  Plan* pl = static_cast<Plan*>(plan);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc;
+  if (enable && (rc = plan_sort_setup(pl, s))) return rc;
+  pl->sort_on = enable != 0;
+  const int32_t t[2] = {pl->tile[0], pl->tile[1]};
+  return plan_set_tile(pl, t, s);                    // refreshes the items' permutation pointers, drops the graph
+}
 
 int spline_batch_plan_info(void* plan, int64_t* n_tiles, int64_t* n_evals) {
   clear_error();

@@ -147,6 +147,16 @@ __device__ __forceinline__ A dot4(const A w[4], A x0, A x1, A x2, A x3) {
   return fmaa(w[3], x3, fmaa(w[2], x2, fmaa(w[1], x1, w[0] * x0)));
 }
 
+// Spread the low 10 bits of x to every third bit (one coordinate of a 3D Morton index).
+__device__ __forceinline__ uint32_t spread3(uint32_t x) {
+  x &= 0x3ffu;
+  x = (x | (x << 16)) & 0x030000ffu;
+  x = (x | (x << 8)) & 0x0300f00fu;
+  x = (x | (x << 4)) & 0x030c30c3u;
+  x = (x | (x << 2)) & 0x09249249u;
+  return x;
+}
+
 // Row indices i0-1 .. i0+2 modulo n (n >= 4, 0 <= i0 < n).
 __device__ __forceinline__ void wrap4(int i0, int n, int idx[4]) {
   idx[0] = (i0 == 0) ? n - 1 : i0 - 1;

@@ -451,7 +451,8 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs a) {
 // [tile_start[j], tile_start[j+1]), a tile being the 256 / G points one workgroup covers in one
 // pass.  Workgroups take tiles from a device counter until it passes n_tiles, so the launch is
 // load-balanced however uneven the items are; every workgroup leaves the loop once the counter
-// is exhausted.  Items are ordered by decreasing cost per tile on the host (largest first).
+// is exhausted.  Items are ordered by decreasing cost per tile on the host (largest first).  With a
+// permutation per item (sorted plans) each item's points are taken in locality order.
 struct BatchArgs {
   const EvalArgs* items;      // device array [n_items]
   const int32_t* tile_start;  // device array [n_items + 1], exclusive prefix of tiles per item
@@ -478,8 +479,11 @@ __global__ __launch_bounds__(256) void k_eval_batch(BatchArgs b) {
     }
     const EvalArgs& a = b.items[lo];
     int p = (tile - b.tile_start[lo]) * GPB + (int)threadIdx.x / G;
-    if constexpr (G >= 64) p = __builtin_amdgcn_readfirstlane(p);
-    if (p < a.n_pts) eval_point<TS, MODE, G, OPL, 0>(a, p, (int)threadIdx.x % G);
+    if (p < a.n_pts) {
+      if (a.perm) p = a.perm[p];                       // the item's points in locality order
+      if constexpr (G >= 64) p = __builtin_amdgcn_readfirstlane(p);
+      eval_point<TS, MODE, G, OPL, 0>(a, p, (int)threadIdx.x % G);
+    }
   }
 }
 

@@ -18,16 +18,6 @@ namespace pws {
 
 EvalKernel eval_kernel_for(const spl_desc* d, int values_only, const int32_t tile[2]);
 
-// Spread the low 10 bits of x to every third bit.
-__device__ __forceinline__ uint32_t spread3(uint32_t x) {
-  x &= 0x3ffu;
-  x = (x | (x << 16)) & 0x030000ffu;
-  x = (x | (x << 8)) & 0x0300f00fu;
-  x = (x | (x << 4)) & 0x030c30c3u;
-  x = (x | (x << 2)) & 0x09249249u;
-  return x;
-}
-
 // Buckets: cells grouped 2^shift per axis and numbered along the Morton curve (3 x `bits` bits, at most
 // 18), so the bucket index space has at most 2^18 entries; points with non-finite coordinates go to
 // the extra last bucket.  A counting sort into buckets gives the locality order; the order inside a
@@ -50,7 +40,7 @@ static BucketGeom bucket_geom(const spl_desc* d) {
   return bg;
 }
 
-__global__ __launch_bounds__(256) void k_fill_zero_i32(int32_t* x, int32_t n) {
+__global__ __launch_bounds__(256) void k_fill_zero_i32(int32_t* x, int32_t n) {  // also used by batch.hip
   for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < n; i += (int)(gridDim.x * blockDim.x)) x[i] = 0;
 }
 

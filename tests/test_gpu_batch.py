@@ -168,3 +168,53 @@ def test_batched_workload_subset_against_oracle():
         assert normwise(g.double().cpu().numpy()[idx], rg) < 1e-5
         assert normwise(l.double().cpu().numpy()[idx], rl) < 1e-5
     plan.close()
+
+
+@pytest.mark.parametrize("dtype,has_lap", [("f64", False), ("f32", True), ("bf16", False)])
+def test_sorted_batch_equals_single_system_kernel(dtype, has_lap):
+    """Sorted plans (points in locality order per item) give the same outputs bitwise; the option can
+    be switched off and on again."""
+    items, refs = make_items(dtype, has_lap, seed=206)
+    items[0][2][5] = float("nan")                      # a non-finite point in one item
+    opl = {"f64": 2, "f32": 4, "bf16": 4}[dtype]
+    for tile in ((8, opl), (64, opl)):
+        say("sorted batch", dtype, has_lap, tile)
+        plan = P.BatchPlan(items, tile=tile)
+        ref = single(items, tile)
+        for enable in (True, False, True):
+            for it in items:
+                for x in it[3:]:
+                    x.fill_(1234.5)
+            plan.sort(enable)
+            plan.run()
+            torch.cuda.synchronize()
+            for (d, tab, pos, v, g, l), r in zip(items, ref):
+                if r is None:
+                    continue
+                for a, b in zip((v, g, l), r):
+                    assert torch.equal(torch.nan_to_num(a, nan=7.0), torch.nan_to_num(b, nan=7.0))
+        plan.close()
+
+
+def test_sorted_batch_graph_replays_match_eager():
+    items, _ = make_items("f32", False, seed=207)
+    plan = P.BatchPlan(items, tile=(32, 2))
+    plan.sort(True)
+    say("sorted batch eager reference")
+    plan.run()
+    torch.cuda.synchronize()
+    ref = [[x.clone() for x in it[3:]] for it in items]
+    assert_same(items, single(items, (32, 2)))
+    for rep in range(4):
+        for it in items:
+            for x in it[3:]:
+                x.fill_(np.nan)
+        torch.cuda.synchronize()
+        say("sorted graph replay", rep)
+        plan.run_graph()
+        torch.cuda.synchronize()
+        for it, r in zip(items, ref):
+            for a, b in zip(it[3:], r):
+                assert torch.equal(a, b)
+        _ = torch.ones(1000, device=DEV).sum().item()
+    plan.close()

@@ -128,6 +128,15 @@ def test_batched_48_systems_full_size():
     for (d, tab, pos, v, g, l) in items:
         rv, rg, rl = P.spline_eval_vgl(d, tab, pos, tile=tile)
         assert torch.equal(v, rv) and torch.equal(g, rg) and torch.equal(l, rl)
+    say("sorted batched graph launch", tile)
+    plan.sort(True)
+    for (d, tab, pos, v, g, l) in items:
+        v.fill_(1.5)
+    plan.run_graph()
+    torch.cuda.synchronize()
+    for (d, tab, pos, v, g, l) in items:
+        rv, rg, rl = P.spline_eval_vgl(d, tab, pos, tile=tile)
+        assert torch.equal(v, rv) and torch.equal(g, rg) and torch.equal(l, rl)
     for (d, tab, pos, v, g, l), (s, f, pos_h) in zip(items[:3], host[:3]):
         idx = _sample(pos_h.shape[0], k=32)
         beta = obuild.build_interp(np.ascontiguousarray(f[..., :12]))

@@ -339,7 +339,8 @@ void spline_batch_plan_destroy(void* plan);
 int spline_batch_plan_info(void* plan, int64_t* n_tiles, int64_t* n_evals);
 
 /*
- * Time every valid tile shape of spline_eval_vgl_tile on the caller's buffers
+ * Time the tile shapes of spline_eval_vgl_tile on the caller's buffers (lanes per point from 4
+ * up to one row per pass, every orbitals-per-lane choice)
  * (each several times, HIP events on `stream`; synchronizes), keep the fastest in
  * the process-wide cache keyed by (dtype, has_lap, o_pad, grid), and return it in
  * tile_out[0..1].  The outputs are overwritten with valid results.  If the

@@ -373,7 +373,7 @@ int spline_autotune(const spl_desc* d, const void* table, int64_t n_pts, const d
     const int chunks = d->o_pad / opl;
     int gmax = 2;
     while (gmax < chunks && gmax < 256) gmax <<= 1;
-    for (int g = (gmax >= 16 ? gmax / 8 : 2); g <= gmax && !rc; g <<= 1) {
+    for (int g = (gmax >= 4 ? 4 : 2); g <= gmax && !rc; g <<= 1) {
       const int32_t tile[2] = {g, opl};
       if ((rc = launch_eval(d, table, n_pts, pos, v, grad, lap, 0, tile, s))) break;   // warm-up
       float times[3];

@@ -56,11 +56,14 @@ void fill_eval_args(const spl_desc* d, const void* table, int64_t n_pts, const d
   a->per_xcd = 0;
 }
 
-// Kernel of one forward evaluation of descriptor d (nullptr if the tile has none).
-EvalKernel eval_kernel_for(const spl_desc* d, int values_only, const int32_t tile[2]) {
+// Kernel of one forward evaluation of descriptor d (nullptr if the tile has none).  cached: the
+// gather is expected to be served from cache (sorted call), so FP64 B-spline tables take the
+// instances without slab prefetch.
+EvalKernel eval_kernel_for(const spl_desc* d, int values_only, const int32_t tile[2], int cached) {
   const int mode = values_only ? MODE_V : (d->sep_grad ? MODE_SEP : (d->has_lap ? MODE_VGL_SEPLAP : MODE_VGL));
-  const int var = (d->basis == SPL_LAGRANGE ? VAR_LAGRANGE : 0) | (d->basis == SPL_PPSPLINE ? VAR_PP : 0) |
-                  (d->bloch ? VAR_BLOCH : 0);
+  int var = (d->basis == SPL_LAGRANGE ? VAR_LAGRANGE : 0) | (d->basis == SPL_PPSPLINE ? VAR_PP : 0) |
+            (d->bloch ? VAR_BLOCH : 0);
+  if (cached && d->dtype == SPL_F64 && mode != MODE_SEP && (var == 0 || var == VAR_BLOCH)) var |= VAR_NOPF;
   if (var == 0 && mode != MODE_SEP) {
     if (d->dtype == SPL_F64) return pick_eval_f64(mode, tile[0], tile[1]);
     if (d->dtype == SPL_F32) return pick_eval_f32(mode, tile[0], tile[1]);
@@ -79,7 +82,7 @@ int launch_eval(const spl_desc* d, const void* table, int64_t n_pts, const doubl
   if (!tile_valid_for(d, tile)) return fail(SPL_EINVAL, "invalid tile shape (%d, %d)", tile[0], tile[1]);
   EvalArgs a;
   fill_eval_args(d, table, n_pts, pos, v, grad, lap, values_only, tile[1], &a);
-  EvalKernel k = eval_kernel_for(d, values_only, tile);
+  EvalKernel k = eval_kernel_for(d, values_only, tile, 0);
   if (!k) return fail(SPL_EINVAL, "invalid tile shape (%d, %d)", tile[0], tile[1]);
   const int64_t per_block = 256 / tile[0];
   const dim3 grid((unsigned)((n_pts + per_block - 1) / per_block));

@@ -16,7 +16,7 @@
 
 namespace pws {
 
-EvalKernel eval_kernel_for(const spl_desc* d, int values_only, const int32_t tile[2]);
+EvalKernel eval_kernel_for(const spl_desc* d, int values_only, const int32_t tile[2], int cached);
 
 // Buckets: cells grouped 2^shift per axis and numbered along the Morton curve (3 x `bits` bits, at most
 // 18), so the bucket index space has at most 2^18 entries; points with non-finite coordinates go to
@@ -110,7 +110,7 @@ int launch_eval_sorted(const spl_desc* d, const void* table, int64_t n_pts, cons
   if (work_bytes < (int64_t)L.total)
     return fail(SPL_EINVAL, "workspace of %lld bytes is smaller than the %lld needed", (long long)work_bytes,
                 (long long)L.total);
-  EvalKernel k = tile_valid_for(d, tile) ? eval_kernel_for(d, values_only, tile) : nullptr;
+  EvalKernel k = tile_valid_for(d, tile) ? eval_kernel_for(d, values_only, tile, 1) : nullptr;
   if (!k) return fail(SPL_EINVAL, "invalid tile shape (%d, %d)", tile[0], tile[1]);
   char* w = static_cast<char*>(work);
   int32_t* bucket = reinterpret_cast<int32_t*>(w + L.bucket);

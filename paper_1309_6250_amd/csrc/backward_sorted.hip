@@ -7,17 +7,20 @@
 //     non-finite coordinates get a key past all classes;
 //  2. a stable radix sort orders points by key (then by index), and a run-length encoding
 //     lists the occupied cells with the range of their points;
-//  3. for each colour class in turn, one lane group per (cell, orbital chunk) accumulates the
-//     contributions of all of the cell's points to its 64 rows in registers, in point order,
-//     then adds them to the gradient table with ordinary loads and stores.
+//  3. for each colour class in turn, one wave per (cell, orbital group) forms the contributions
+//     of all of the cell's points to its 64 rows as a matrix product on the matrix cores, in
+//     point order, then adds them to the gradient table with ordinary loads and stores.
 //
 // Colour classes: along an axis of N cells, cell i has colour i mod 4 when i < 4 floor(N/4), and
 // a colour of its own (4, 5, 6) for the last N mod 4 cells.  Two cells of one class are at least
 // 4 apart along every axis, also across the periodic wrap, so their blocks (rows i-1 .. i+2) are
-// disjoint: within a class no two lane groups touch the same row, and classes run one after the
+// disjoint: within a class no two waves touch the same row, and classes run one after the
 // other.  The result is bitwise reproducible, and each row is written once per occupied cell
 // rather than once per point.
 #include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cstring>
 
 #include "common.hpp"
 
@@ -30,7 +33,7 @@ __host__ __device__ inline int axis_colour(int i, int n) {
 __host__ __device__ inline int axis_colours(int n) { return 4 + (n & 3); }
 
 struct SortLayout {
-  size_t keys_in, keys_out, vals_in, vals_out, uniq, counts, offsets, num_runs, class_start, temp;
+  size_t keys_in, keys_out, vals_in, vals_out, uniq, counts, offsets, num_runs, class_start, pts, temp;
   size_t temp_bytes, total;
   int n_classes;
   int64_t n_cells;
@@ -72,6 +75,7 @@ static int sort_layout(const spl_desc* d, int64_t n_pts, SortLayout* L) {
   L->offsets = off; off = align_up(off + 4 * n);
   L->num_runs = off; off = align_up(off + 4);
   L->class_start = off; off = align_up(off + 4 * (size_t)(L->n_classes + 2));
+  L->pts = off; off = align_up(off + (d->dtype == SPL_F64 ? 32 : 16) * n);
   L->temp = off; off = align_up(off + L->temp_bytes);
   L->total = off;
   return SPL_OK;
@@ -107,56 +111,121 @@ __global__ void k_class_starts(const int64_t* uniq, const int32_t* num_runs, int
   class_start[c] = lo;
 }
 
+// A point in sorted order: its reduced coordinates within its cell and its index.
+template <typename A>
+struct SortedPoint {
+  A t[3];
+  int32_t p;
+};
+static_assert(sizeof(SortedPoint<float>) == 16 && sizeof(SortedPoint<double>) == 32, "sorted point record size");
+
+template <typename A>
+__global__ __launch_bounds__(256) void k_sorted_points(Geom g, const double* pos, const int32_t* perm, int32_t n,
+                                                       SortedPoint<A>* out) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= n) return;
+  const int p = perm[i];
+  int i0[3];
+  double t[3];
+  reduce_point(g, pos[3 * (int64_t)p], pos[3 * (int64_t)p + 1], pos[3 * (int64_t)p + 2], i0, t);
+  SortedPoint<A> sp;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) sp.t[ax] = (A)t[ax];
+  sp.p = p;
+  out[i] = sp;
+}
+
+// Terms of the upstream gradient: the value, the three Cartesian gradient components and the
+// Laplacian.  Each has its own weight on the 64 rows of a block (the transpose of its row of
+// the forward contraction).
+enum { TERM_VAL = 0, TERM_GX = 1, TERM_GY = 2, TERM_GZ = 3, TERM_LAP = 4 };
+
 struct CellArgs {
   Geom g;
   const double* pos;
-  const void* gv;
-  const void* ggrad;
-  const void* glap;
-  void* gtable;        // base of the table this pass writes (orbital or Laplacian table)
+  const void* src[5];      // upstream gradient of each term, point-major, in the gradient type
+  int64_t src_stride[5];   // elements from one point to the next (n_orb, or 3 n_orb for the gradient)
+  int32_t kind[5];         // TERM_* of each term
+  int32_t n_terms;
+  void* gtable;            // base of the table this pass writes (orbital or Laplacian table)
   const int64_t* uniq;
   const int32_t* counts;
   const int32_t* offsets;
-  const int32_t* perm;
+  const void* pts;         // SortedPoint records in sorted order
   const int32_t* class_start;
   int64_t n_cells;
   int32_t cls;
   int32_t n_orb;
-  int32_t n_chunks;
+  int32_t n_groups;        // orbital groups of 16 OT per cell
   int32_t pad_;
 };
 
-template <typename A>
-__device__ __forceinline__ A pick4c(int l, A a0, A a1, A a2, A a3) {
-  return l == 0 ? a0 : (l == 1 ? a1 : (l == 2 ? a2 : a3));
-}
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// SEPLAP: the Laplacian's gradient goes to the separate table (orbital pass ignores gL);
-// LAPTAB: this pass accumulates the separate Laplacian table (value weights times gL).
-template <typename TS, bool SEPLAP, bool LAPTAB, int G, int OPL>
-__global__ __launch_bounds__(256) void k_bwd_cells(CellArgs a) {
-  using A = typename Acc<TS>::type;
-  using GO = typename Out<TS>::type;
-  constexpr int GPB = 256 / G;
-  const int grp = threadIdx.x / G;
-  const int lane = threadIdx.x % G;
+// 16x16x4 matrix-core step D = A B + C in the gradient's precision.  Operand layout of one
+// wave: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16].  Element r of lane l's
+// accumulator is D[row(l / 16, r)][l % 16], with row = 4 (l / 16) + r for FP32 and
+// (l / 16) + 4 r for FP64.
+template <typename A> struct Mfma;
+template <> struct Mfma<float> {
+  using acc = f32x4;
+  __device__ __forceinline__ static int row(int grp, int r) { return 4 * grp + r; }
+  __device__ __forceinline__ static acc step(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<double> {
+  using acc = f64x4;
+  __device__ __forceinline__ static int row(int grp, int r) { return grp + 4 * r; }
+  __device__ __forceinline__ static acc step(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+// One wave per (occupied cell of the colour class, group of 16 OT orbitals).  For a cell the
+// gradient of its 64 rows is a dense product
+//     d beta[row][o] += sum over (point, term) W_term(point)[row] g_term[point][o],
+// done on the matrix cores: 4 row tiles of 16 (row = 16 l + 4 m + n for the block offsets
+// l, m, n) times OT orbital tiles of 16, with K running over (point, term) pairs four points at
+// a time (lane group k of the wave takes point 4q + k).
+//
+// The cell's points arrive as sorted records (reduced coordinates and index, one coalesced
+// load) in batches of at most CELL_PB; their 1-D weights go to LDS once per point.  The
+// upstream values of the next four points are loaded while the current ones are multiplied,
+// and the update of the 64 rows loads every old value before it stores.  The summation order is fixed by
+// the sorted point order, so the result is reproducible bit for bit.
+constexpr int CELL_PB = 32;         // most points per batch
+
+template <typename A, int OT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_bwd_cells(CellArgs a) {
+  using M = Mfma<A>;
+  using Acc = typename M::acc;
+  constexpr int BW = 16 * OT;                        // orbitals of a wave
+  __shared__ int s_p[CELL_PB];
+  __shared__ A s_w[CELL_PB][36];                     // per point: x, y, z  x  (w[4], w'[4], w''[4])
+  const int lane = (int)threadIdx.x;
+  const int grp = lane >> 4;
+  const int col = lane & 15;
+  const int m_ = col >> 2, n_ = col & 3;
   const int r0 = a.class_start[a.cls];
   const int r1 = a.class_start[a.cls + 1];
-  const int64_t n_work = (int64_t)(r1 - r0) * a.n_chunks;
-  const GO* gvp = static_cast<const GO*>(a.gv);
-  const GO* ggp = static_cast<const GO*>(a.ggrad);
-  const GO* glp = static_cast<const GO*>(a.glap);
-  GO* gtab = static_cast<GO*>(a.gtable);
+  const int64_t n_work = (int64_t)(r1 - r0) * a.n_groups;
+  const int nt = a.n_terms;
+  const SortedPoint<A>* pts = static_cast<const SortedPoint<A>*>(a.pts);
+  A* gtab = static_cast<A*>(a.gtable);
   A jm[9], mt[6];
 #pragma unroll
   for (int i = 0; i < 9; ++i) jm[i] = (A)a.g.jac[i];
 #pragma unroll
   for (int i = 0; i < 6; ++i) mt[i] = (A)a.g.metric[i];
 
-  for (int64_t w = (int64_t)blockIdx.x * GPB + grp; w < n_work; w += (int64_t)gridDim.x * GPB) {
-    const int r = r0 + (int)(w / a.n_chunks);
-    const int cb = (int)(w % a.n_chunks) * G * OPL;
+  for (int64_t w = blockIdx.x; w < n_work; w += gridDim.x) {
+    const int r = r0 + (int)(w / a.n_groups);
+    const int ob = (int)(w % a.n_groups) * BW;
     const int64_t cell = a.uniq[r] - (int64_t)a.cls * a.n_cells;
+    const int start = a.offsets[r];
+    const int cnt = a.counts[r];
     const int iz0 = (int)(cell % a.g.n[2]);
     const int iy0 = (int)((cell / a.g.n[2]) % a.g.n[1]);
     const int ix0 = (int)(cell / ((int64_t)a.g.n[2] * a.g.n[1]));
@@ -164,108 +233,128 @@ __global__ __launch_bounds__(256) void k_bwd_cells(CellArgs a) {
     wrap4(ix0, a.g.n[0], ix);
     wrap4(iy0, a.g.n[1], iy);
     wrap4(iz0, a.g.n[2], iz);
-    int oj[OPL];
-    bool inj[OPL];
+    // this cell's block: no other wave of the class touches these rows
+    bool ocol[OT];
 #pragma unroll
-    for (int j = 0; j < OPL; ++j) {
-      oj[j] = cb + lane + j * G;
-      inj[j] = oj[j] < a.n_orb;
-    }
-    A acc[64][OPL];
-#pragma unroll
-    for (int q = 0; q < 64; ++q)
-#pragma unroll
-      for (int j = 0; j < OPL; ++j) acc[q][j] = A(0);
+    for (int ot = 0; ot < OT; ++ot) ocol[ot] = ob + ot * 16 + col < a.n_orb;
+    auto row_ptr = [&](int rt, int e) {
+      const int i = M::row(grp, e);                      // 4 m + n within the row tile
+      return gtab + (int64_t)ix[rt] * a.g.s0 + (int64_t)iy[i >> 2] * a.g.s1 + (int64_t)iz[i & 3] * a.g.o_pad + ob + col;
+    };
 
-    const int start = a.offsets[r];
-    const int cnt = a.counts[r];
-    for (int i = 0; i < cnt; ++i) {
-      const int p = a.perm[start + i];
-      int i0[3];
-      double t[3];
-      reduce_point(a.g, a.pos[3 * (int64_t)p], a.pos[3 * (int64_t)p + 1], a.pos[3 * (int64_t)p + 2], i0, t);
-      A wx[4], wy[4], wz[4], dwx[4], dwy[4], dwz[4], d2wx[4], d2wy[4], d2wz[4];
-      bspline_weights<A>((A)t[0], wx, dwx, d2wx);
-      bspline_weights<A>((A)t[1], wy, dwy, d2wy);
-      bspline_weights<A>((A)t[2], wz, dwz, d2wz);
+    Acc acc[4][OT];
 #pragma unroll
-      for (int j = 0; j < OPL; ++j) {
-        const bool in = inj[j];
-        const int64_t po = (int64_t)p * a.n_orb + oj[j];
-        const int64_t pg = (int64_t)p * 3 * a.n_orb + oj[j];
-        const A gL = (in && glp) ? (A)glp[po] : A(0);
-        if constexpr (LAPTAB) {
+    for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-          for (int l = 0; l < 4; ++l)
+      for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = Acc{};
+
+    for (int b0 = 0; b0 < cnt; b0 += CELL_PB) {
+      const int nb = min(CELL_PB, cnt - b0);
+      __syncthreads();                                   // the previous batch is consumed
+      if (lane < nb) {
+        const SortedPoint<A> sp = pts[start + b0 + lane];
+        s_p[lane] = sp.p;
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-              const A xy = gL * (wx[l] * wy[m]);
+        for (int ax = 0; ax < 3; ++ax) {
+          A w4[4], d4[4], dd4[4];
+          bspline_weights<A>(sp.t[ax], w4, d4, dd4);
 #pragma unroll
-              for (int n = 0; n < 4; ++n) acc[(l * 4 + m) * 4 + n][j] = fmaa(xy, wz[n], acc[(l * 4 + m) * 4 + n][j]);
-            }
-        } else {
-          const A gV = (in && gvp) ? (A)gvp[po] : A(0);
-          const A g0 = (in && ggp) ? (A)ggp[pg] : A(0);
-          const A g1 = (in && ggp) ? (A)ggp[pg + a.n_orb] : A(0);
-          const A g2 = (in && ggp) ? (A)ggp[pg + 2 * a.n_orb] : A(0);
-          A gt[3];
-#pragma unroll
-          for (int k = 0; k < 3; ++k) gt[k] = fmaa(jm[3 * k + 2], g2, fmaa(jm[3 * k + 1], g1, jm[3 * k] * g0));
-          const A cl = SEPLAP ? A(0) : gL;
-#pragma unroll
-          for (int l = 0; l < 4; ++l) {
-            const A e0 = fmaa(mt[0] * cl, d2wx[l], fmaa(gt[0], dwx[l], gV * wx[l]));
-            const A e1 = fmaa(A(2) * mt[3] * cl, dwx[l], gt[1] * wx[l]);
-            const A e2 = fmaa(A(2) * mt[4] * cl, dwx[l], gt[2] * wx[l]);
-            const A e3 = (mt[1] * cl) * wx[l];
-            const A e4 = (mt[2] * cl) * wx[l];
-            const A e5 = (A(2) * mt[5] * cl) * wx[l];
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-              const A f0 = fmaa(e3, d2wy[m], fmaa(e1, dwy[m], e0 * wy[m]));
-              const A f1 = fmaa(e5, dwy[m], e2 * wy[m]);
-              const A f2 = e4 * wy[m];
-#pragma unroll
-              for (int n = 0; n < 4; ++n)
-                acc[(l * 4 + m) * 4 + n][j] += fmaa(f2, d2wz[n], fmaa(f1, dwz[n], f0 * wz[n]));
-            }
+          for (int i = 0; i < 4; ++i) {
+            s_w[lane][12 * ax + i] = w4[i];
+            s_w[lane][12 * ax + 4 + i] = d4[i];
+            s_w[lane][12 * ax + 8 + i] = dd4[i];
           }
         }
       }
+      __syncthreads();
+      // upstream values of lane group k's point 4q + k, for every term and orbital tile
+      auto load_b = [&](int q, A (&bv)[5][OT]) {
+        const int j = q + grp;
+        const bool live = j < nb;
+        const int64_t p = live ? (int64_t)s_p[j] : 0;
+#pragma unroll
+        for (int c = 0; c < 5; ++c)
+#pragma unroll
+          for (int ot = 0; ot < OT; ++ot) {
+            const A* src = static_cast<const A*>(a.src[c]);
+            bv[c][ot] = (c < nt && live && ocol[ot]) ? src[p * a.src_stride[c] + ob + ot * 16 + col] : A(0);
+          }
+      };
+      A bcur[5][OT];
+      load_b(0, bcur);
+      for (int q = 0; q < nb; q += 4) {
+        A bnext[5][OT];
+        if (q + 4 < nb) load_b(q + 4, bnext);
+        const A* wp = s_w[min(q + grp, nb - 1)];        // a dead lane group multiplies zeros
+        A wx[4], dwx[4], d2wx[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          wx[i] = wp[i];
+          dwx[i] = wp[4 + i];
+          d2wx[i] = wp[8 + i];
+        }
+        const A wy = wp[12 + m_], dwy = wp[16 + m_], d2wy = wp[20 + m_];
+        const A wz = wp[24 + n_], dwz = wp[28 + n_], d2wz = wp[32 + n_];
+        const A yz = wy * wz;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          if (c >= nt) break;
+          // row weight of this term: Q0 w_x + Q1 w_x' + Q2 w_x'' on the lane's (m, n), per row tile l
+          const int kind = a.kind[c];
+          A q0, q1 = A(0), q2 = A(0);
+          if (kind == TERM_VAL) {
+            q0 = yz;
+          } else if (kind == TERM_LAP) {
+            q2 = mt[0] * yz;
+            q1 = A(2) * fmaa(mt[3] * dwy, wz, mt[4] * wy * dwz);
+            q0 = fmaa(mt[1] * d2wy, wz, fmaa(mt[2] * wy, d2wz, A(2) * mt[5] * dwy * dwz));
+          } else {
+            const int k = kind - TERM_GX;
+            q1 = jm[k] * yz;
+            q0 = fmaa(jm[3 + k] * dwy, wz, jm[6 + k] * wy * dwz);
+          }
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt) {
+            const A av = fmaa(q2, d2wx[rt], fmaa(q1, dwx[rt], q0 * wx[rt]));
+#pragma unroll
+            for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = M::step(av, bcur[c][ot], acc[rt][ot]);
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c)
+#pragma unroll
+          for (int ot = 0; ot < OT; ++ot) bcur[c][ot] = bnext[c][ot];
+      }
     }
-    // this cell's block: no other lane group of the class touches these rows
+    // every old value is loaded before the first store: one memory latency for the update
+    A old[4][4][OT];
 #pragma unroll
-    for (int l = 0; l < 4; ++l)
+    for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        GO* rp = gtab + (int64_t)ix[l] * a.g.s0 + (int64_t)iy[m] * a.g.s1;
+      for (int e = 0; e < 4; ++e) {
+        const A* rp = row_ptr(rt, e);
 #pragma unroll
-        for (int n = 0; n < 4; ++n)
+        for (int ot = 0; ot < OT; ++ot) old[rt][e][ot] = ocol[ot] ? rp[16 * ot] : A(0);
+      }
 #pragma unroll
-          for (int j = 0; j < OPL; ++j)
-            if (inj[j]) {
-              GO* q = rp + (int64_t)iz[n] * a.g.o_pad + oj[j];
-              *q = *q + (GO)acc[(l * 4 + m) * 4 + n][j];
-            }
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        A* rp = row_ptr(rt, e);
+#pragma unroll
+        for (int ot = 0; ot < OT; ++ot)
+          if (ocol[ot]) rp[16 * ot] = old[rt][e][ot] + acc[rt][ot][e];
       }
   }
 }
 
 typedef void (*CellKernel)(CellArgs);
 
-template <typename TS, bool SEPLAP, bool LAPTAB>
-static CellKernel pick_cells(int g) {
-  switch (g) {
-    case 4: return k_bwd_cells<TS, SEPLAP, LAPTAB, 4, 1>;
-    case 16: return k_bwd_cells<TS, SEPLAP, LAPTAB, 16, 1>;
-    default: return k_bwd_cells<TS, SEPLAP, LAPTAB, 64, 1>;
-  }
-}
-
-template <typename TS>
-static CellKernel pick_cells_t(bool seplap, bool laptab, int g) {
-  if (laptab) return pick_cells<TS, true, true>(g);
-  return seplap ? pick_cells<TS, true, false>(g) : pick_cells<TS, false, false>(g);
+template <typename A>
+static CellKernel pick_cells(int ot) {
+  if constexpr (sizeof(A) == 4)
+    if (ot >= 4) return k_bwd_cells<A, 4>;
+  return ot == 1 ? k_bwd_cells<A, 1> : k_bwd_cells<A, 2>;
 }
 
 int sorted_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes) {
@@ -295,6 +384,7 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
   int32_t* offsets = reinterpret_cast<int32_t*>(W + L.offsets);
   int32_t* num_runs = reinterpret_cast<int32_t*>(W + L.num_runs);
   int32_t* class_start = reinterpret_cast<int32_t*>(W + L.class_start);
+  void* pts = W + L.pts;
   void* temp = W + L.temp;
   const Geom g = make_geom(d);
   const int n = (int)n_pts;
@@ -314,35 +404,66 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
   hipLaunchKernelGGL(k_class_starts, dim3((L.n_classes + 1 + 255) / 256), dim3(256), 0, stream, uniq, num_runs,
                      L.n_cells, (int32_t)L.n_classes, class_start);
   if ((rc = hip_fail(hipGetLastError(), "class start launch"))) return rc;
+  if (d->dtype == SPL_F64)
+    hipLaunchKernelGGL(k_sorted_points<double>, dim3((n + 255) / 256), dim3(256), 0, stream, g, pos, vals_out,
+                       (int32_t)n, static_cast<SortedPoint<double>*>(pts));
+  else
+    hipLaunchKernelGGL(k_sorted_points<float>, dim3((n + 255) / 256), dim3(256), 0, stream, g, pos, vals_out,
+                       (int32_t)n, static_cast<SortedPoint<float>*>(pts));
+  if ((rc = hip_fail(hipGetLastError(), "sorted point launch"))) return rc;
 
-  const int gl = d->n_orb <= 4 ? 4 : (d->n_orb <= 16 ? 16 : 64);
+  // orbital tiles per wave: enough waves per class launch to cover the chip, at most 4 (FP32) or
+  // 2 (FP64) tiles of accumulators per wave
+  const int tiles = (d->n_orb + 15) / 16;
+  const int64_t occupied = std::min<int64_t>(n_pts, L.n_cells) / L.n_classes;
+  int ot = d->dtype == SPL_F64 ? 2 : 4;
+  while (ot > 1 && (ot >= 2 * tiles || occupied * ((tiles + ot - 1) / ot) < 2048)) ot >>= 1;
   CellArgs a;
+  memset(&a, 0, sizeof(a));
   a.g = g;
   a.pos = pos;
-  a.gv = gv;
-  a.ggrad = ggrad;
-  a.glap = glap;
   a.uniq = uniq;
   a.counts = counts;
   a.offsets = offsets;
-  a.perm = vals_out;
+  a.pts = pts;
   a.class_start = class_start;
   a.n_cells = L.n_cells;
   a.n_orb = d->n_orb;
-  a.n_chunks = (d->n_orb + gl - 1) / gl;
-  a.pad_ = 0;
-  const int passes = d->has_lap ? 2 : 1;
+  a.n_groups = (tiles + ot - 1) / ot;
+  const int64_t no = d->n_orb;
   const size_t gsz = d->dtype == SPL_F64 ? 8 : 4;
+  const int passes = d->has_lap ? 2 : 1;
   for (int pass = 0; pass < passes; ++pass) {
-    const bool laptab = pass == 1;
-    a.gtable = static_cast<char*>(gtable) + (laptab ? d->table_elems * gsz : 0);
-    CellKernel k;
-    if (d->dtype == SPL_F64) k = pick_cells_t<double>(d->has_lap, laptab, gl);
-    else if (d->dtype == SPL_F32) k = pick_cells_t<float>(d->has_lap, laptab, gl);
-    else k = pick_cells_t<uint16_t>(d->has_lap, laptab, gl);
+    // pass 0: the orbital table (value, gradient, and the Laplacian unless it has its own table);
+    // pass 1: the separate Laplacian table, whose rows carry the value weights of gL
+    int nt = 0;
+    auto term = [&](const void* src, int64_t stride, int kind) {
+      a.src[nt] = src;
+      a.src_stride[nt] = stride;
+      a.kind[nt] = kind;
+      ++nt;
+    };
+    if (pass == 0) {
+      if (gv) term(gv, no, TERM_VAL);
+      if (ggrad) {
+        const char* gb = static_cast<const char*>(ggrad);
+        term(gb, 3 * no, TERM_GX);
+        term(gb + no * gsz, 3 * no, TERM_GY);
+        term(gb + 2 * no * gsz, 3 * no, TERM_GZ);
+      }
+      if (glap && !d->has_lap) term(glap, no, TERM_LAP);
+    } else if (glap) {
+      term(glap, no, TERM_VAL);
+    }
+    if (nt == 0) continue;
+    a.n_terms = nt;
+    a.gtable = static_cast<char*>(gtable) + (pass == 1 ? d->table_elems * gsz : 0);
+    const CellKernel k = d->dtype == SPL_F64 ? pick_cells<double>(ot) : pick_cells<float>(ot);
+    const int64_t waves = occupied * a.n_groups;
+    const int grid = (int)std::max<int64_t>(256, std::min<int64_t>(waves, 8192));
     for (int c = 0; c < L.n_classes; ++c) {
       a.cls = c;
-      hipLaunchKernelGGL(k, dim3(512), dim3(256), 0, stream, a);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, stream, a);
       if ((rc = hip_fail(hipGetLastError(), "cell gradient launch"))) return rc;
     }
   }

@@ -277,6 +277,28 @@ int spline_eval_vgl_backward(const spl_desc* d, const void* table, int64_t n_pts
  * SPL_DETERMINISTIC).  Host only; may query the current HIP device. */
 int spline_backward_work_bytes(const spl_desc* d, int64_t n_pts, int32_t flags, int64_t* bytes);
 
+/*
+ * Data term of the least-squares fit of coefficients to orbital samples, the regression
+ * counterpart of App. A's smoothing spline that exercises the adjoint: for n outputs y of
+ * spline_eval_vgl (values or Laplacians at the fit points) and their targets t,
+ *   *loss += w sum_i (y_i - t_i)^2,      g_i = 2 w (y_i - t_i)  (the upstream gradient of that
+ *                                        term, input to spline_eval_vgl_backward).
+ *   n     number of output values (n_pts n_col for a whole output array); 0 is a no-op
+ *   y, t  device, n values of the descriptor's output type (FP64 for SPL_F64, else FP32)
+ *   w     the term's weight, finite (a mean over the outputs passes 1/n times its weight)
+ *   g     device, n values, OVERWRITTEN; may be y itself
+ *   loss  device, one FP64, ACCUMULATED into
+ *   work  device, spline_misfit_work_bytes() bytes, 8-byte aligned (partial sums)
+ * Residuals are formed in the output type, their squares and sums in FP64 in a fixed order,
+ * so *loss is reproducible bit for bit.  Errors: NULL pointer, n < 0, non-finite w, short work,
+ * misaligned pointer -> SPL_EINVAL.  Allocates nothing.
+ */
+int spline_misfit(const spl_desc* d, int64_t n, const void* y, const void* t, double w, void* g, double* loss,
+                  void* work, int64_t work_bytes, void* stream);
+
+/* Workspace bytes of spline_misfit (a fixed number of FP64 partial sums).  Host only. */
+int spline_misfit_work_bytes(const spl_desc* d, int64_t n, int64_t* bytes);
+
 /* ---------------------------------------------------------------------------
  * Batched evaluation: many independent systems (tables of different sizes and
  * orbital counts, point sets of different sizes) in ONE persistent launch.

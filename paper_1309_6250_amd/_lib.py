@@ -24,7 +24,8 @@ EXPORTS = (
     "spline_batch_graph_launch", "spline_batch_autotune", "spline_batch_plan_destroy", "spline_batch_plan_info", "spline_autotune",
     "spline_tile_for", "spline_last_error", "spline_version", "spline_backward_work_bytes",
     "spline_build_smoothing", "spline_smoothing_work_bytes", "spline_build_tables",
-    "spline_eval_vgl_sorted", "spline_sorted_work_bytes", "spline_batch_plan_sort",
+    "spline_eval_vgl_sorted", "spline_sorted_work_bytes", "spline_batch_plan_sort", "spline_misfit",
+    "spline_misfit_work_bytes",
 )
 
 
@@ -97,6 +98,8 @@ def lib():
             "spline_eval_vgl_tile": (ctypes.c_int, [pd, vp, i64, vp, vp, vp, vp, i32p, vp]),
             "spline_eval_vgl_backward": (ctypes.c_int, [pd, vp, i64, vp, vp, vp, vp, vp, vp, i32, vp, i64, vp]),
             "spline_backward_work_bytes": (ctypes.c_int, [pd, i64, i32, ctypes.POINTER(i64)]),
+            "spline_misfit": (ctypes.c_int, [pd, i64, vp, vp, ctypes.c_double, vp, vp, vp, i64, vp]),
+            "spline_misfit_work_bytes": (ctypes.c_int, [pd, i64, ctypes.POINTER(i64)]),
             "spline_build_smoothing": (ctypes.c_int, [pd, i64, vp, vp, vp, vp, vp]),
             "spline_smoothing_work_bytes": (ctypes.c_int, [pd, ctypes.POINTER(i64)]),
             "spline_batch_plan_create": (ctypes.c_int, [ctypes.POINTER(SplItem), i32, i32p, vp,

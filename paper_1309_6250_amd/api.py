@@ -256,8 +256,9 @@ def spline_eval_vgl_sorted(desc, table, pos, v=None, grad=None, lap=None, work=N
 
 
 def spline_eval_vgl_backward(desc, table, pos, gv=None, ggrad=None, glap=None, gtable=None, gpos=None,
-                             want_table=True, want_pos=True, flags=0, stream=None):
-    """Returns (gtable, gpos).  gtable is accumulated into (a fresh zero table if not given)."""
+                             want_table=True, want_pos=True, flags=0, stream=None, work=None):
+    """Returns (gtable, gpos).  gtable is accumulated into (a fresh zero table if not given).
+    work: uint8 device tensor of spline_backward_work_bytes bytes (allocated if not given)."""
     n = _check_inputs(desc, table, pos)
     od = OUT_TORCH[desc.dtype]
     for name, g, numel in (("gv", gv, n * desc.n_orb), ("ggrad", ggrad, 3 * n * desc.n_orb),
@@ -272,10 +273,13 @@ def spline_eval_vgl_backward(desc, table, pos, gv=None, ggrad=None, glap=None, g
         gpos = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
     if gpos is not None:
         _need(gpos, "gpos", torch.float64, 3 * n)
-    work = None
     nbytes = spline_backward_work_bytes(desc, n, flags)
-    if nbytes:
+    if not nbytes:
+        work = None
+    elif work is None:
         work = torch.empty(nbytes, dtype=torch.uint8, device=pos.device)     # caller-owned workspace
+    elif work.numel() * work.element_size() < nbytes:
+        raise ValueError(f"work must hold {nbytes} bytes")
     check(lib().spline_eval_vgl_backward(ctypes.byref(desc), _ptr(table), n, _ptr(pos), _ptr(gv), _ptr(ggrad),
                                          _ptr(glap), _ptr(gtable), _ptr(gpos), int(flags), _ptr(work), int(nbytes),
                                          _stream(stream)),
@@ -288,6 +292,30 @@ def spline_backward_work_bytes(desc, n_pts, flags=0):
     check(lib().spline_backward_work_bytes(ctypes.byref(desc), int(n_pts), int(flags), ctypes.byref(out)),
           "spline_backward_work_bytes")
     return out.value
+
+
+def spline_misfit_work_bytes(desc, n):
+    out = ctypes.c_int64()
+    check(lib().spline_misfit_work_bytes(ctypes.byref(desc), int(n), ctypes.byref(out)), "spline_misfit_work_bytes")
+    return out.value
+
+
+def spline_misfit(desc, y, t, w, loss, g=None, work=None, stream=None):
+    """loss (FP64 device scalar) += w sum (y - t)^2; returns g = 2 w (y - t) (written into `g`,
+    which may be `y` itself, or a new tensor).  y, t: the descriptor's output dtype, same size."""
+    od = OUT_TORCH[desc.dtype]
+    n = y.numel()
+    _need(y, "y", od, n)
+    _need(t, "t", od, n)
+    _need(loss, "loss", torch.float64, 1)
+    if g is None:
+        g = torch.empty_like(y)
+    _need(g, "g", od, n)
+    if work is None:
+        work = torch.empty(spline_misfit_work_bytes(desc, n), dtype=torch.uint8, device=y.device)
+    check(lib().spline_misfit(ctypes.byref(desc), n, _ptr(y), _ptr(t), float(w), _ptr(g), _ptr(loss), _ptr(work),
+                              int(work.numel() * work.element_size()), _stream(stream)), "spline_misfit")
+    return g
 
 
 def spline_autotune(desc, table, pos, v=None, grad=None, lap=None, stream=None):

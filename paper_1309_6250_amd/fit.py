@@ -7,16 +7,22 @@ Minimizes over the coefficient table beta (FP32 or FP64)
             / (N1 N2 N3 n_orb mean V_t^2)
 
 with wV = 1 / mean V_t^2 and wL = 1 / mean lap_t^2 (or 0), periodic second differences,
-by Adam.  V and lap come from the library's forward kernel and the gradient of the misfit
-terms from its adjoint kernel (SplineVGL); the penalty, the reductions and the Adam update
-are small elementwise tensor operations on the table.  The residuals are formed in the
-kernel's output precision (FP64 for FP64 tables, FP32 otherwise) and their squares summed in
-FP64.
+by Adam.  Two forms of the same loss:
+
+- FitProblem.loss_and_grad, used by fit_adam: every pass over the point-sized arrays runs in
+  the library's kernels (the locality-ordered forward, spline_misfit on V and on lap, which
+  forms the upstream gradients in place and sums the squared residuals in FP64 in a fixed
+  order, and the adjoint); only the penalty and the Adam update are tensor operations, on the
+  table.  Buffers are allocated once.
+- make_loss, a differentiable function of the table built on SplineVGL, for use inside a
+  larger autograd graph.  Its residuals are formed in the kernel's output precision and
+  their squares summed in FP64.
 """
 import torch
 
 from ._lib import SPL_DETERMINISTIC
-from .api import OUT_TORCH
+from .api import (OUT_TORCH, new_gtable, spline_eval_vgl_backward, spline_eval_vgl_sorted, spline_misfit,
+                  spline_misfit_work_bytes, spline_sorted_work_bytes, spline_backward_work_bytes)
 from .autograd import SplineVGL
 
 
@@ -24,18 +30,26 @@ def second_difference(beta, dim):
     return torch.roll(beta, 1, dims=dim) - 2.0 * beta + torch.roll(beta, -1, dims=dim)
 
 
+def _weights(desc, v_t, lap_t, lam, use_lap):
+    v64 = v_t.to(torch.float64)
+    mv = torch.mean(v64 * v64)
+    w_v = 1.0 / mv
+    if use_lap:
+        l64 = lap_t.to(torch.float64)
+        w_l = 1.0 / torch.mean(l64 * l64)
+    else:
+        w_l = torch.zeros((), dtype=torch.float64, device=v_t.device)
+    pts = desc.grid[0] * desc.grid[1] * desc.grid[2]
+    reg_scale = lam / (pts * desc.n_orb * mv)
+    return w_v, w_l, reg_scale
+
+
 def make_loss(desc, pos, v_t, lap_t, lam=1e-3, use_lap=True, deterministic=True, sorted_forward=True):
     n_orb = desc.n_orb
-    v64 = v_t.to(torch.float64)
-    l64 = lap_t.to(torch.float64)
-    w_v = 1.0 / torch.mean(v64 * v64)
-    w_l = (1.0 / torch.mean(l64 * l64)) if use_lap else torch.zeros((), dtype=torch.float64, device=v_t.device)
-    pts = desc.grid[0] * desc.grid[1] * desc.grid[2]
-    reg_scale = lam / (pts * n_orb * torch.mean(v64 * v64))
+    w_v, w_l, reg_scale = _weights(desc, v_t, lap_t, lam, use_lap)
     od = OUT_TORCH[desc.dtype]
     v_t = v_t.to(od).contiguous()
     lap_t = lap_t.to(od).contiguous()
-    del v64, l64
 
     flags = SPL_DETERMINISTIC if deterministic else 0
 
@@ -55,24 +69,74 @@ def make_loss(desc, pos, v_t, lap_t, lam=1e-3, use_lap=True, deterministic=True,
     return loss_fn
 
 
+class FitProblem:
+    """The fit's loss and its coefficient gradient at fixed points pos [P][3] with targets
+    v_t, lap_t [P][n_orb], without autograd.  loss_and_grad(beta) returns (loss, grad) as
+    device tensors (FP64 scalar; the gradient table, FP32 for FP32 and BF16 tables); both are
+    reused by the next call."""
+
+    def __init__(self, desc, pos, v_t, lap_t, lam=1e-3, use_lap=True, deterministic=True):
+        self.desc, self.pos, self.lam, self.use_lap = desc, pos, lam, use_lap
+        self.flags = SPL_DETERMINISTIC if deterministic else 0
+        w_v, w_l, reg_scale = _weights(desc, v_t, lap_t, lam, use_lap)
+        n, o = pos.shape[0], desc.n_orb
+        self.w_v, self.w_l = float(w_v) / (n * o), float(w_l) / (n * o)
+        self.reg_scale = float(reg_scale)
+        od = OUT_TORCH[desc.dtype]
+        dev = pos.device
+        self.v_t = v_t.to(od).contiguous()
+        self.lap_t = lap_t.to(od).contiguous()
+        self.v = torch.empty((n, o), dtype=od, device=dev)
+        self.grad = torch.empty((n, 3, o), dtype=od, device=dev)
+        self.lap = torch.empty((n, o), dtype=od, device=dev)
+        self.gtable = new_gtable(desc, dev)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.sort_work = torch.empty(max(1, spline_sorted_work_bytes(desc, n)), dtype=torch.uint8, device=dev)
+        self.misfit_work = torch.empty(spline_misfit_work_bytes(desc, n * o), dtype=torch.uint8, device=dev)
+        self.bwd_work = torch.empty(max(1, spline_backward_work_bytes(desc, n, self.flags)), dtype=torch.uint8,
+                                    device=dev)
+
+    def loss_and_grad(self, beta):
+        d = self.desc
+        self.loss.zero_()
+        spline_eval_vgl_sorted(d, beta, self.pos, self.v, self.grad, self.lap, work=self.sort_work)
+        gv = spline_misfit(d, self.v, self.v_t, self.w_v, self.loss, g=self.v, work=self.misfit_work)
+        gl = None
+        if self.use_lap:
+            gl = spline_misfit(d, self.lap, self.lap_t, self.w_l, self.loss, g=self.lap, work=self.misfit_work)
+        self.gtable.zero_()
+        spline_eval_vgl_backward(d, beta, self.pos, gv, None, gl, self.gtable, None, want_pos=False, flags=self.flags,
+                                 work=self.bwd_work)
+        if self.lam:
+            n_orb = d.n_orb
+            core = beta[0, ..., :n_orb].to(torch.float64)
+            reg = torch.zeros((), dtype=torch.float64, device=beta.device)
+            greg = torch.zeros_like(core)
+            for dim in range(3):
+                d2 = second_difference(core, dim)
+                reg = reg + torch.sum(d2 * d2)
+                # d/dbeta sum (D2 beta)^2 = 2 D2 (D2 beta): D2 is symmetric under the periodic wrap
+                greg += second_difference(d2, dim)
+            self.loss += self.reg_scale * reg
+            self.gtable[0, ..., :n_orb] += (2.0 * self.reg_scale * greg).to(self.gtable.dtype)
+        return self.loss, self.gtable
+
+
 def fit_adam(desc, table, pos, v_t, lap_t, steps=200, lam=1e-3, lr=None, use_lap=True, callback=None,
-             deterministic=True, sorted_forward=True):
+             deterministic=True):
     """Adam from `table` (not modified); returns (fitted table, list of losses per step).
-    deterministic: bitwise-reproducible coefficient gradients (cell-sorted accumulation);
-    sorted_forward: forward evaluation in locality order (same outputs)."""
+    deterministic: bitwise-reproducible coefficient gradients (cell-sorted accumulation)."""
+    prob = FitProblem(desc, pos, v_t, lap_t, lam=lam, use_lap=use_lap, deterministic=deterministic)
     beta = table.detach().clone().requires_grad_(True)
-    loss_fn = make_loss(desc, pos, v_t, lap_t, lam=lam, use_lap=use_lap, deterministic=deterministic,
-                        sorted_forward=sorted_forward)
     if lr is None:
         lr = 1e-3 * float(torch.sqrt(torch.mean(table.detach().to(torch.float64) ** 2)))
     opt = torch.optim.Adam([beta], lr=lr, betas=(0.9, 0.999))
     losses = []
     for step in range(steps):
-        opt.zero_grad(set_to_none=True)
-        loss = loss_fn(beta)
-        loss.backward()
+        loss, g = prob.loss_and_grad(beta.detach())
+        beta.grad = g if g.dtype == beta.dtype else g.to(beta.dtype)
         opt.step()
-        losses.append(float(loss.detach()))
+        losses.append(loss.clone())
         if callback is not None:
-            callback(step, losses[-1])
-    return beta.detach(), losses
+            callback(step, float(losses[-1]))
+    return beta.detach(), [float(x) for x in torch.cat(losses).cpu()]

@@ -291,3 +291,31 @@ def test_sorted_evaluation_validates_before_any_launch():
                                           None) == P.SPL_OK
     nb = ctypes.c_int64(7)
     assert P.lib().spline_sorted_work_bytes(ctypes.byref(d), 0, ctypes.byref(nb)) == P.SPL_OK and nb.value == 0
+
+
+def test_misfit_validates_before_any_launch():
+    fake = ctypes.c_void_p(256)
+    d = P.spline_desc_init(LAT, (8, 8, 8), 4, "f32")
+    ref = ctypes.byref(d)
+    lib = P.lib()
+    nb = ctypes.c_int64(-1)
+    assert lib.spline_misfit_work_bytes(ref, 100, ctypes.byref(nb)) == P.SPL_OK and nb.value > 0
+    assert lib.spline_misfit_work_bytes(ref, -1, ctypes.byref(nb)) == P.SPL_EINVAL
+    w = nb.value
+    # n == 0 is a no-op even with NULL arrays
+    assert lib.spline_misfit(ref, 0, None, None, 1.0, None, None, None, 0, None) == P.SPL_OK
+    assert lib.spline_misfit(ref, -1, fake, fake, 1.0, fake, fake, fake, w, None) == P.SPL_EINVAL
+    for k in range(5):                      # each of y, t, g, loss, work NULL in turn
+        args = [fake] * 5
+        args[k] = None
+        y, t, g, loss, work = args
+        assert lib.spline_misfit(ref, 10, y, t, 1.0, g, loss, work, w, None) == P.SPL_EINVAL
+    assert lib.spline_misfit(ref, 10, fake, fake, float("nan"), fake, fake, fake, w, None) == P.SPL_EINVAL
+    assert lib.spline_misfit(ref, 10, fake, fake, float("inf"), fake, fake, fake, w, None) == P.SPL_EINVAL
+    assert lib.spline_misfit(ref, 10, fake, fake, 1.0, fake, fake, fake, w - 8, None) == P.SPL_EINVAL
+    assert b"work" in lib.spline_last_error()
+    assert lib.spline_misfit(ref, 10, ctypes.c_void_p(258), fake, 1.0, fake, fake, fake, w, None) == P.SPL_EINVAL
+    assert lib.spline_misfit(ref, 10, fake, fake, 1.0, fake, ctypes.c_void_p(260), fake, w, None) == P.SPL_EINVAL
+    d64 = P.spline_desc_init(LAT, (8, 8, 8), 4, "f64")
+    assert lib.spline_misfit(ctypes.byref(d64), 10, ctypes.c_void_p(260), fake, 1.0, fake, fake, fake, w,
+                             None) == P.SPL_EINVAL

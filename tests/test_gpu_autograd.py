@@ -5,7 +5,7 @@ import pytest
 import torch
 
 import paper_1309_6250_amd as P
-from paper_1309_6250_amd.fit import make_loss, fit_adam
+from paper_1309_6250_amd.fit import make_loss, fit_adam, FitProblem
 from oracle import build as obuild, adjoint as oadj, fit as ofit, pw as opw, quantize as oq
 from workloads import make_system
 from workloads.configs import cubic, A_SI
@@ -119,6 +119,54 @@ def test_fit_loss_and_gradient_match_oracle():
     rloss, rgrad = ofit.loss_and_grad(beta0, s.lattice, pos, v_t, l_t, w_v, w_l, lam=0.3)
     assert abs(float(loss.detach()) - rloss) <= 1e-11 * abs(rloss)
     assert normwise(table.grad.cpu().numpy()[0, ..., :s.n_orb], rgrad) < 1e-10
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_misfit_kernel(dtype):
+    """spline_misfit: g = 2 w (y - t) exactly as the arithmetic states it in the output type, the
+    loss sum in FP64 to summation accuracy, accumulated into, bitwise repeatable, in place."""
+    d = P.spline_desc_init(SKEW, (8, 8, 8), 4, dtype)
+    od = torch.float64 if dtype == "f64" else torch.float32
+    nd = np.float64 if dtype == "f64" else np.float32
+    rng = np.random.default_rng(106)
+    for n in (1, 1000, 262144 * 4 + 37, 3_000_001):       # below, at and past the fixed grid's stride
+        y = rng.standard_normal(n).astype(nd)
+        t = rng.standard_normal(n).astype(nd)
+        w = 0.37
+        say("misfit", dtype, n)
+        loss = torch.full((1,), 1.5, dtype=torch.float64, device=DEV)
+        g = P.spline_misfit(d, to_dev(y, od), to_dev(t, od), w, loss)
+        loss2 = torch.full((1,), 1.5, dtype=torch.float64, device=DEV)
+        yd = to_dev(y, od)
+        g2 = P.spline_misfit(d, yd, to_dev(t, od), w, loss2, g=yd)        # in place over y
+        torch.cuda.synchronize()
+        r = y - t                                                        # residual in the output type
+        want_g = nd(2.0 * w) * r
+        assert np.array_equal(g.cpu().numpy(), want_g)
+        assert np.array_equal(g2.cpu().numpy(), want_g)
+        ref = 1.5 + w * np.sum(r.astype(np.float64) ** 2)
+        assert abs(float(loss) - ref) <= 1e-12 * ref
+        assert float(loss) == float(loss2)
+
+
+def test_fit_problem_matches_oracle():
+    """The fused fit path (forward, misfit kernels, deterministic adjoint, penalty) gives the loss
+    and coefficient gradient of the oracle's fit, like the autograd form."""
+    s, pos, v_t, l_t, beta0 = _fit_case()
+    d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, "f64")
+    table = table_from_oracle(d, beta0, "f64")
+    prob = FitProblem(d, to_dev(pos), to_dev(v_t), to_dev(l_t), lam=0.3)
+    say("fused fit loss + gradient")
+    loss, grad = prob.loss_and_grad(table)
+    loss2, grad2 = float(loss), grad.clone()
+    loss, grad = prob.loss_and_grad(table)
+    torch.cuda.synchronize()
+    w_v, w_l = ofit.weights_from_targets(v_t, l_t)
+    rloss, rgrad = ofit.loss_and_grad(beta0, s.lattice, pos, v_t, l_t, w_v, w_l, lam=0.3)
+    assert abs(float(loss) - rloss) <= 1e-11 * abs(rloss)
+    assert normwise(grad.cpu().numpy()[0, ..., :s.n_orb], rgrad) < 1e-10
+    assert float(loss) == loss2 and torch.equal(grad, grad2)          # reused buffers, repeatable
+    assert torch.all(grad[..., s.n_orb:] == 0)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])

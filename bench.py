@@ -656,8 +656,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--quick", action="store_true", help="headline only: no extra forms, rows or CPU baseline")
     ap.add_argument("--only", default=None,
-                    help="time only one form, e.g. c2-f32, c2-bf16-lap, c2-f32-sep-lagrange or c7-f64-bloch "
-                         "(for profiling runs)")
+                    help="time only one form, e.g. c2-f32, c2-bf16-lap, c2-f32-sep-lagrange or c7-f64-bloch, "
+                         "or 'fit' for the differentiation rows (for profiling runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tile", default=None, help="with --only: fixed tile 'G,OPL' instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -679,6 +679,12 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 copies of 1 GiB (1073741824 bytes read + written each)")
         del src, dst
+
+    if args.only == "fit":
+        # differentiation form only (for profiling runs): adjoint in both modes, misfit, Adam fit
+        _gpu_ready()
+        print(json.dumps({"only": "fit", **fit_rows(args.steps, args.warmup)}), flush=True)
+        return
 
     if args.only and args.only.endswith("-sorted"):
         # locality-ordered call only (for profiling runs: the sorted kernel's launches alone)

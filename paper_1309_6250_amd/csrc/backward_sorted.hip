@@ -191,13 +191,14 @@ template <> struct Mfma<double> {
 // a time (lane group k of the wave takes point 4q + k).
 //
 // The cell's points arrive as sorted records (reduced coordinates and index, one coalesced
-// load) in batches of at most CELL_PB; their 1-D weights go to LDS once per point.  The
-// upstream values of the next four points are loaded while the current ones are multiplied,
-// and the update of the 64 rows loads every old value before it stores.  The summation order is fixed by
-// the sorted point order, so the result is reproducible bit for bit.
+// load) in batches of at most CELL_PB; their 1-D weights go to LDS once per point.  With at
+// most two terms (NT = 2: the fit's value and Laplacian) all upstream values of a batch are
+// loaded at once; with more, those of the next four points are loaded while the current ones
+// are multiplied.  The update of the 64 rows loads every old value before it stores.  The
+// summation order is fixed by the sorted point order, so the result is reproducible bit for bit.
 constexpr int CELL_PB = 32;         // most points per batch
 
-template <typename A, int OT>
+template <typename A, int OT, int NT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_bwd_cells(CellArgs a) {
   using M = Mfma<A>;
   using Acc = typename M::acc;
@@ -267,24 +268,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         }
       }
       __syncthreads();
-      // upstream values of lane group k's point 4q + k, for every term and orbital tile
-      auto load_b = [&](int q, A (&bv)[5][OT]) {
+      // upstream values of lane group k's point 4q + k, for terms c0 .. c0 + NC - 1 and every orbital tile
+      auto load_b = [&](int q, auto& bv) {
+        constexpr int NC = sizeof(bv) / sizeof(bv[0]);
         const int j = q + grp;
         const bool live = j < nb;
         const int64_t p = live ? (int64_t)s_p[j] : 0;
 #pragma unroll
-        for (int c = 0; c < 5; ++c)
+        for (int c = 0; c < NC; ++c)
 #pragma unroll
           for (int ot = 0; ot < OT; ++ot) {
             const A* src = static_cast<const A*>(a.src[c]);
             bv[c][ot] = (c < nt && live && ocol[ot]) ? src[p * a.src_stride[c] + ob + ot * 16 + col] : A(0);
           }
       };
-      A bcur[5][OT];
-      load_b(0, bcur);
-      for (int q = 0; q < nb; q += 4) {
-        A bnext[5][OT];
-        if (q + 4 < nb) load_b(q + 4, bnext);
+      // the products of one step of four points: every term's row weights times its upstream values
+      auto multiply = [&](int q, const auto& bv) {
+        constexpr int NC = sizeof(bv) / sizeof(bv[0]);
         const A* wp = s_w[min(q + grp, nb - 1)];        // a dead lane group multiplies zeros
         A wx[4], dwx[4], d2wx[4];
 #pragma unroll
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         const A wz = wp[24 + n_], dwz = wp[28 + n_], d2wz = wp[32 + n_];
         const A yz = wy * wz;
 #pragma unroll
-        for (int c = 0; c < 5; ++c) {
+        for (int c = 0; c < NC; ++c) {
           if (c >= nt) break;
           // row weight of this term: Q0 w_x + Q1 w_x' + Q2 w_x'' on the lane's (m, n), per row tile l
           const int kind = a.kind[c];
@@ -317,13 +317,31 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
           for (int rt = 0; rt < 4; ++rt) {
             const A av = fmaa(q2, d2wx[rt], fmaa(q1, dwx[rt], q0 * wx[rt]));
 #pragma unroll
-            for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = M::step(av, bcur[c][ot], acc[rt][ot]);
+            for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = M::step(av, bv[c][ot], acc[rt][ot]);
           }
         }
+      };
+      if constexpr (NT <= 2) {
+        // at most two terms: the whole batch's upstream values are loaded at once
+        A bq[CELL_PB / 4][NT][OT];
 #pragma unroll
-        for (int c = 0; c < 5; ++c)
+        for (int qi = 0; qi < CELL_PB / 4; ++qi) load_b(4 * qi, bq[qi]);
 #pragma unroll
-          for (int ot = 0; ot < OT; ++ot) bcur[c][ot] = bnext[c][ot];
+        for (int qi = 0; qi < CELL_PB / 4; ++qi)
+          if (4 * qi < nb) multiply(4 * qi, bq[qi]);
+      } else {
+        // up to five terms: the next step's values are loaded while the current ones are multiplied
+        A bcur[5][OT];
+        load_b(0, bcur);
+        for (int q = 0; q < nb; q += 4) {
+          A bnext[5][OT];
+          if (q + 4 < nb) load_b(q + 4, bnext);
+          multiply(q, bcur);
+#pragma unroll
+          for (int c = 0; c < 5; ++c)
+#pragma unroll
+            for (int ot = 0; ot < OT; ++ot) bcur[c][ot] = bnext[c][ot];
+        }
       }
     }
     // every old value is loaded before the first store: one memory latency for the update
@@ -350,11 +368,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 
 typedef void (*CellKernel)(CellArgs);
 
-template <typename A>
-static CellKernel pick_cells(int ot) {
+template <typename A, int NT>
+static CellKernel pick_cells_nt(int ot) {
   if constexpr (sizeof(A) == 4)
-    if (ot >= 4) return k_bwd_cells<A, 4>;
-  return ot == 1 ? k_bwd_cells<A, 1> : k_bwd_cells<A, 2>;
+    if (ot >= 4) return k_bwd_cells<A, 4, NT>;
+  return ot == 1 ? k_bwd_cells<A, 1, NT> : k_bwd_cells<A, 2, NT>;
+}
+
+template <typename A>
+static CellKernel pick_cells(int ot, int n_terms) {
+  return n_terms <= 2 ? pick_cells_nt<A, 2>(ot) : pick_cells_nt<A, 5>(ot);
 }
 
 int sorted_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes) {
@@ -458,7 +481,7 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
     if (nt == 0) continue;
     a.n_terms = nt;
     a.gtable = static_cast<char*>(gtable) + (pass == 1 ? d->table_elems * gsz : 0);
-    const CellKernel k = d->dtype == SPL_F64 ? pick_cells<double>(ot) : pick_cells<float>(ot);
+    const CellKernel k = d->dtype == SPL_F64 ? pick_cells<double>(ot, nt) : pick_cells<float>(ot, nt);
     const int64_t waves = occupied * a.n_groups;
     const int grid = (int)std::max<int64_t>(256, std::min<int64_t>(waves, 8192));
     for (int c = 0; c < L.n_classes; ++c) {

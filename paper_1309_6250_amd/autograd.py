@@ -9,16 +9,19 @@ table's dtype; keep FP32 master coefficients when training.
 """
 import torch
 
+from ._lib import SPL_DETERMINISTIC
 from .api import spline_eval_vgl, spline_eval_vgl_sorted, spline_eval_vgl_backward, OUT_TORCH
 
 
 class SplineVGL(torch.autograd.Function):
     """Outputs a loss does not use get no gradient tensor (None reaches the adjoint as NULL, so
-    that term is skipped instead of read as zeros).  sorted_forward runs the forward through
+    that term is skipped instead of read as zeros).  flags: SPL_DETERMINISTIC (the default: the
+    cell-sorted adjoint, bitwise reproducible and also the faster one, at every point density
+    measured) or 0 (float atomics).  sorted_forward runs the forward through
     spline_eval_vgl_sorted (the same outputs, bitwise, evaluated in locality order)."""
 
     @staticmethod
-    def forward(ctx, table, pos, desc, flags=0, sorted_forward=False):
+    def forward(ctx, table, pos, desc, flags=SPL_DETERMINISTIC, sorted_forward=False):
         ctx.set_materialize_grads(False)
         if sorted_forward:
             v, g, l = spline_eval_vgl_sorted(desc, table, pos)
@@ -43,9 +46,8 @@ class SplineVGL(torch.autograd.Function):
         return gtable, gpos, None, None, None
 
 
-def spline_vgl(table, pos, desc, deterministic=False, sorted_forward=False):
-    """Differentiable (v, grad, lap) of the spline `table` at `pos`.  deterministic=True makes the
-    coefficient gradient bitwise reproducible (cell-sorted accumulation instead of atomics);
-    sorted_forward=True evaluates the points in locality order (same outputs)."""
-    from ._lib import SPL_DETERMINISTIC
+def spline_vgl(table, pos, desc, deterministic=True, sorted_forward=False):
+    """Differentiable (v, grad, lap) of the spline `table` at `pos`.  deterministic=True (default):
+    the coefficient gradient is accumulated cell by cell, bitwise reproducible; False: float
+    atomics.  sorted_forward=True evaluates the points in locality order (same outputs)."""
     return SplineVGL.apply(table, pos, desc, SPL_DETERMINISTIC if deterministic else 0, sorted_forward)

@@ -26,16 +26,17 @@ def _case(seed, grid=(9, 8, 10), n_orb=5, n_pts=300, dtype="f64"):
     return rng, beta, pos, d
 
 
+@pytest.mark.parametrize("flags", [None, 0], ids=["default-deterministic", "atomic"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_autograd_matches_oracle_adjoint(dtype):
+def test_autograd_matches_oracle_adjoint(dtype, flags):
     rng, beta, pos, d = _case(300, dtype=dtype)
     n, o = pos.shape[0], d.n_orb
     A, B, C = rng.standard_normal((n, o)), rng.standard_normal((n, 3, o)), rng.standard_normal((n, o))
     od = torch.float64 if dtype == "f64" else torch.float32
     table = table_from_oracle(d, beta, dtype).requires_grad_(True)
     x = to_dev(pos).requires_grad_(True)
-    say("SplineVGL forward/backward", dtype)
-    v, g, l = P.SplineVGL.apply(table, x, d)
+    say("SplineVGL forward/backward", dtype, flags)
+    v, g, l = P.SplineVGL.apply(table, x, d) if flags is None else P.SplineVGL.apply(table, x, d, flags)
     loss = (v * to_dev(A, od)).sum() + (g * to_dev(B, od)).sum() + (l * to_dev(C, od)).sum()
     loss.backward()
     torch.cuda.synchronize()

@@ -123,20 +123,45 @@ class FitProblem:
 
 
 def fit_adam(desc, table, pos, v_t, lap_t, steps=200, lam=1e-3, lr=None, use_lap=True, callback=None,
-             deterministic=True):
-    """Adam from `table` (not modified); returns (fitted table, list of losses per step).
-    deterministic: bitwise-reproducible coefficient gradients (cell-sorted accumulation)."""
+             deterministic=True, checkpoint=None, checkpoint_every=0):
+    """Adam from `table` (not modified); returns (fitted table, list of losses of every step run so
+    far, including those before a resume).
+    deterministic: bitwise-reproducible coefficient gradients (cell-sorted accumulation).
+    checkpoint: file path.  If it exists, the fit resumes from it (coefficients, Adam moments and
+    step count, loaded with torch.load(weights_only=True)); every `checkpoint_every` steps (and
+    after the last step) the state is written there, to a temporary file first and then renamed.
+    With the deterministic gradient a resumed fit retraces the uninterrupted one bit for bit."""
+    import os
     prob = FitProblem(desc, pos, v_t, lap_t, lam=lam, use_lap=use_lap, deterministic=deterministic)
     beta = table.detach().clone().requires_grad_(True)
     if lr is None:
         lr = 1e-3 * float(torch.sqrt(torch.mean(table.detach().to(torch.float64) ** 2)))
     opt = torch.optim.Adam([beta], lr=lr, betas=(0.9, 0.999))
+    start, done = 0, []
+    if checkpoint is not None and os.path.exists(checkpoint):
+        state = torch.load(checkpoint, map_location=beta.device, weights_only=True)
+        if tuple(state["beta"].shape) != tuple(beta.shape) or state["beta"].dtype != beta.dtype:
+            raise ValueError(f"{checkpoint} holds a table of another shape or dtype")
+        with torch.no_grad():
+            beta.copy_(state["beta"])
+        opt.load_state_dict(state["adam"])
+        start, done = int(state["step"]), [float(x) for x in state["losses"]]
+
+    def save(step, losses):
+        tmp = checkpoint + ".tmp"
+        torch.save({"beta": beta.detach(), "adam": opt.state_dict(), "step": step,
+                    "losses": torch.tensor(done + [float(x) for x in torch.cat(losses).cpu()] if losses else done,
+                                           dtype=torch.float64)}, tmp)
+        os.replace(tmp, checkpoint)
+
     losses = []
-    for step in range(steps):
+    for step in range(start, steps):
         loss, g = prob.loss_and_grad(beta.detach())
         beta.grad = g if g.dtype == beta.dtype else g.to(beta.dtype)
         opt.step()
         losses.append(loss.clone())
         if callback is not None:
             callback(step, float(losses[-1]))
-    return beta.detach(), [float(x) for x in torch.cat(losses).cpu()]
+        if checkpoint is not None and (step + 1 == steps or (checkpoint_every and (step + 1) % checkpoint_every == 0)):
+            save(step + 1, losses)
+    return beta.detach(), done + ([float(x) for x in torch.cat(losses).cpu()] if losses else [])

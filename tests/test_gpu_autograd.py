@@ -208,3 +208,33 @@ def test_sorted_forward_and_unused_outputs():
     torch.cuda.synchronize()
     assert torch.allclose(gt, res[0][1], rtol=0, atol=1e-14 * float(gt.abs().max()))
     assert torch.allclose(gp, res[0][2], rtol=0, atol=1e-14 * float(gp.abs().max()))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fit_checkpoint_resume_is_bitwise(tmp_path, dtype):
+    """A fit stopped after a checkpoint and resumed from it ends on the same coefficients and
+    losses, bit for bit, as one run straight through (deterministic gradient and misfit)."""
+    s, pos, v_t, l_t, beta0 = _fit_case()
+    d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype)
+    table = table_from_oracle(d, beta0, dtype)
+    args = (d, table, to_dev(pos), to_dev(v_t), to_dev(l_t))
+    say("fit checkpoint / resume", dtype)
+    straight, l_straight = fit_adam(*args, steps=10, lam=0.1)
+    ck = str(tmp_path / "fit.pt")
+
+    class Stop(Exception):
+        pass
+
+    def kill_at_5(step, loss):
+        if step == 4:
+            raise Stop()
+
+    with pytest.raises(Stop):
+        fit_adam(*args, steps=10, lam=0.1, callback=kill_at_5, checkpoint=ck, checkpoint_every=3)
+    state = torch.load(ck, weights_only=True)
+    assert int(state["step"]) == 3 and len(state["losses"]) == 3
+    resumed, l_resumed = fit_adam(*args, steps=10, lam=0.1, checkpoint=ck, checkpoint_every=3)
+    torch.cuda.synchronize()
+    assert torch.equal(resumed, straight)
+    assert l_resumed == l_straight
+    assert int(torch.load(ck, weights_only=True)["step"]) == 10

@@ -257,10 +257,13 @@ int spline_sorted_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes);
  *                    SPL_F64 tables, else FP32; ACCUMULATED into (zero it first for a plain
  *                    gradient); may be NULL to skip; padding columns are never written
  *   gpos             device, FP64 [n_pts][3], OVERWRITTEN; may be NULL to skip
- *   flags            0: the coefficient gradient is summed with hardware float atomics (fast,
- *                    order of summation not reproducible); SPL_DETERMINISTIC: points are sorted
- *                    by grid cell and each cell's block is accumulated in registers and written
- *                    class by class with ordinary stores: bitwise reproducible
+ *   flags            0: the coefficient gradient is summed with hardware float atomics (order
+ *                    of summation not reproducible; no workspace); SPL_DETERMINISTIC: points are
+ *                    sorted by grid cell and each cell's 64-row block is formed on the matrix
+ *                    cores in point order, then either added class by class with ordinary
+ *                    stores (cells of one class have disjoint blocks) or, at 4 or more points
+ *                    per cell, stored per cell and gathered per table row in a fixed order:
+ *                    bitwise reproducible, and the faster of the two at every density measured
  *   work, work_bytes device workspace for SPL_DETERMINISTIC, 256-byte aligned, at least
  *                    spline_backward_work_bytes() bytes, contents undefined afterwards; may be
  *                    NULL (0 bytes) without that flag
@@ -274,7 +277,9 @@ int spline_eval_vgl_backward(const spl_desc* d, const void* table, int64_t n_pts
                              void* work, int64_t work_bytes, void* stream);
 
 /* Workspace size (bytes) spline_eval_vgl_backward needs for n_pts points and `flags` (0 without
- * SPL_DETERMINISTIC).  Host only; may query the current HIP device. */
+ * SPL_DETERMINISTIC).  With it: the sort's keys, runs and point records, and, when n_pts >=
+ * 4 N1 N2 N3 and they fit in 4 GiB, the per-cell blocks (N1 N2 N3 64 o_pad gradient values).
+ * Host only; may query the current HIP device. */
 int spline_backward_work_bytes(const spl_desc* d, int64_t n_pts, int32_t flags, int64_t* bytes);
 
 /*

@@ -33,9 +33,10 @@ __host__ __device__ inline int axis_colour(int i, int n) {
 __host__ __device__ inline int axis_colours(int n) { return 4 + (n & 3); }
 
 struct SortLayout {
-  size_t keys_in, keys_out, vals_in, vals_out, uniq, counts, offsets, num_runs, class_start, pts, temp;
+  size_t keys_in, keys_out, vals_in, vals_out, uniq, counts, offsets, num_runs, class_start, pts, occ, blocks, temp;
   size_t temp_bytes, total;
   int n_classes;
+  int dense;           // 1: per-cell blocks in the workspace and a per-row gather instead of colour classes
   int64_t n_cells;
   int end_bit;
 };
@@ -76,6 +77,12 @@ static int sort_layout(const spl_desc* d, int64_t n_pts, SortLayout* L) {
   L->num_runs = off; off = align_up(off + 4);
   L->class_start = off; off = align_up(off + 4 * (size_t)(L->n_classes + 2));
   L->pts = off; off = align_up(off + (d->dtype == SPL_F64 ? 32 : 16) * n);
+  // dense points (at least 4 per cell on average): every cell's 64-row block gets its own place
+  const size_t gsz = d->dtype == SPL_F64 ? 8 : 4;
+  const size_t block_bytes = (size_t)L->n_cells * 64 * (size_t)d->o_pad * gsz;
+  L->dense = n_pts >= 4 * L->n_cells && block_bytes <= ((size_t)4 << 30);
+  L->occ = off; off = align_up(off + (L->dense ? 4 * (size_t)L->n_cells : 0));
+  L->blocks = off; off = align_up(off + (L->dense ? block_bytes : 0));
   L->temp = off; off = align_up(off + L->temp_bytes);
   L->total = off;
   return SPL_OK;
@@ -157,7 +164,11 @@ struct CellArgs {
   int32_t cls;
   int32_t n_orb;
   int32_t n_groups;        // orbital groups of 16 OT per cell
-  int32_t pad_;
+  int32_t n_classes;
+  int32_t dense;           // 1: all occupied cells at once, blocks written to `blocks`, `occ` marked
+  int32_t o_pad;
+  void* blocks;            // [n_cells][64][o_pad] per-cell gradient blocks (dense)
+  int32_t* occ;            // [n_cells] 1 where the cell holds points (dense)
 };
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -209,8 +220,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   const int grp = lane >> 4;
   const int col = lane & 15;
   const int m_ = col >> 2, n_ = col & 3;
-  const int r0 = a.class_start[a.cls];
-  const int r1 = a.class_start[a.cls + 1];
+  const int r0 = a.dense ? 0 : a.class_start[a.cls];
+  const int r1 = a.dense ? a.class_start[a.n_classes] : a.class_start[a.cls + 1];
   const int64_t n_work = (int64_t)(r1 - r0) * a.n_groups;
   const int nt = a.n_terms;
   const SortedPoint<A>* pts = static_cast<const SortedPoint<A>*>(a.pts);
@@ -224,7 +235,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   for (int64_t w = blockIdx.x; w < n_work; w += gridDim.x) {
     const int r = r0 + (int)(w / a.n_groups);
     const int ob = (int)(w % a.n_groups) * BW;
-    const int64_t cell = a.uniq[r] - (int64_t)a.cls * a.n_cells;
+    const int64_t cell = a.uniq[r] % a.n_cells;         // key = class n_cells + cell
     const int start = a.offsets[r];
     const int cnt = a.counts[r];
     const int iz0 = (int)(cell % a.g.n[2]);
@@ -344,6 +355,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         }
       }
     }
+    if (a.dense) {
+      // the cell's own block: plain stores, each element written once
+      A* bp = static_cast<A*>(a.blocks) + (int64_t)cell * 64 * a.o_pad + ob + col;
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          A* rp = bp + (int64_t)(16 * rt + M::row(grp, e)) * a.o_pad;
+#pragma unroll
+          for (int ot = 0; ot < OT; ++ot)
+            if (ocol[ot]) rp[16 * ot] = acc[rt][ot][e];
+        }
+      if (lane == 0) a.occ[cell] = 1;
+      continue;
+    }
     // every old value is loaded before the first store: one memory latency for the update
     A old[4][4][OT];
 #pragma unroll
@@ -364,6 +390,48 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
           if (ocol[ot]) rp[16 * ot] = old[rt][e][ot] + acc[rt][ot][e];
       }
   }
+}
+
+// Dense points, second step: table row (X, Y, Z) receives the blocks of the 64 cells whose
+// 4x4x4 block contains it, cell (X - l + 1, Y - m + 1, Z - n + 1) at its row 16 l + 4 m + n, summed
+// in that fixed (l, m, n) order and added to the gradient table.  One thread per (row, orbital).
+template <typename A>
+__global__ __launch_bounds__(256) void k_bwd_gather(Geom g, const A* blocks, const int32_t* occ, int32_t n_orb,
+                                                    int32_t o_pad, int64_t n_rows, A* gtab) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t row = t / o_pad;
+  const int o = (int)(t % o_pad);
+  if (row >= n_rows || o >= n_orb) return;
+  const int Z = (int)(row % g.n[2]);
+  const int Y = (int)((row / g.n[2]) % g.n[1]);
+  const int X = (int)(row / ((int64_t)g.n[2] * g.n[1]));
+  int cx[4], cy[4], cz[4];                       // cell of block offset l: X - l + 1 (periodic)
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    cx[l] = (X - l + 1 + 2 * g.n[0]) % g.n[0];
+    cy[l] = (Y - l + 1 + 2 * g.n[1]) % g.n[1];
+    cz[l] = (Z - l + 1 + 2 * g.n[2]) % g.n[2];
+  }
+  A sum = A(0);
+#pragma unroll
+  for (int l = 0; l < 4; ++l)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      A part[4];
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        const int64_t c = ((int64_t)cx[l] * g.n[1] + cy[m]) * g.n[2] + cz[n];
+        part[n] = occ[c] ? blocks[(c * 64 + 16 * l + 4 * m + n) * o_pad + o] : A(0);
+      }
+#pragma unroll
+      for (int n = 0; n < 4; ++n) sum += part[n];
+    }
+  gtab[row * o_pad + o] += sum;
+}
+
+__global__ void k_bwd_zero_i32(int32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 typedef void (*CellKernel)(CellArgs);
@@ -453,6 +521,16 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
   a.n_cells = L.n_cells;
   a.n_orb = d->n_orb;
   a.n_groups = (tiles + ot - 1) / ot;
+  a.n_classes = L.n_classes;
+  a.o_pad = d->o_pad;
+  a.dense = L.dense;
+  if (L.dense) {
+    a.blocks = W + L.blocks;
+    a.occ = reinterpret_cast<int32_t*>(W + L.occ);
+    hipLaunchKernelGGL(k_bwd_zero_i32, dim3((unsigned)((L.n_cells + 255) / 256)), dim3(256), 0, stream, a.occ,
+                       L.n_cells);
+    if ((rc = hip_fail(hipGetLastError(), "occupancy clear launch"))) return rc;
+  }
   const int64_t no = d->n_orb;
   const size_t gsz = d->dtype == SPL_F64 ? 8 : 4;
   const int passes = d->has_lap ? 2 : 1;
@@ -482,6 +560,25 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
     a.n_terms = nt;
     a.gtable = static_cast<char*>(gtable) + (pass == 1 ? d->table_elems * gsz : 0);
     const CellKernel k = d->dtype == SPL_F64 ? pick_cells<double>(ot, nt) : pick_cells<float>(ot, nt);
+    if (L.dense) {
+      // every occupied cell at once into its own block, then one gather per table row
+      const int64_t waves = L.n_cells * a.n_groups;
+      const int grid = (int)std::min<int64_t>(waves, 1 << 16);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, stream, a);
+      if ((rc = hip_fail(hipGetLastError(), "cell block launch"))) return rc;
+      const int64_t threads = L.n_cells * d->o_pad;
+      const int gblocks = (int)((threads + 255) / 256);
+      if (d->dtype == SPL_F64)
+        hipLaunchKernelGGL(k_bwd_gather<double>, dim3(gblocks), dim3(256), 0, stream, g,
+                           static_cast<const double*>(a.blocks), a.occ, d->n_orb, d->o_pad, L.n_cells,
+                           static_cast<double*>(a.gtable));
+      else
+        hipLaunchKernelGGL(k_bwd_gather<float>, dim3(gblocks), dim3(256), 0, stream, g,
+                           static_cast<const float*>(a.blocks), a.occ, d->n_orb, d->o_pad, L.n_cells,
+                           static_cast<float*>(a.gtable));
+      if ((rc = hip_fail(hipGetLastError(), "row gather launch"))) return rc;
+      continue;
+    }
     const int64_t waves = occupied * a.n_groups;
     const int grid = (int)std::max<int64_t>(256, std::min<int64_t>(waves, 8192));
     for (int c = 0; c < L.n_classes; ++c) {

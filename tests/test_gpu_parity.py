@@ -344,3 +344,38 @@ def test_backward_deterministic_many_points_per_cell():
     rb, _, _ = oadj.vgl_backward(beta, SKEW, pos, gv)
     assert normwise(a.cpu().numpy()[0, ..., :33], rb) < 1e-12
     assert normwise(b.cpu().numpy()[0, ..., :33], rb) < 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_backward_deterministic_dense_path(dtype):
+    """At 4 or more points per cell the deterministic adjoint writes every cell's 64-row block to the
+    workspace and gathers them per table row (no colour classes): oracle parity with the separate
+    Laplacian table and every upstream term, an odd orbital count, ragged grid, repeatable bit for bit."""
+    rng = np.random.default_rng(107)
+    grid, n_orb, n = (6, 5, 7), 37, 2000
+    beta = rng.standard_normal(grid + (n_orb,))
+    lbeta = rng.standard_normal(grid + (n_orb,))
+    d = P.spline_desc_init(SKEW, grid, n_orb, dtype, has_lap=True)
+    tab = table_from_oracle(d, beta, dtype, lbeta)
+    bq, lq = oq.quantized(beta, dtype), oq.quantized(lbeta, dtype)
+    pos = rng.uniform(-3, 3, size=(n, 3)) @ SKEW / 3.0
+    pos[17] = np.nan                                    # a non-finite point contributes nothing
+    gv, gg, gl = rng.standard_normal((n, n_orb)), rng.standard_normal((n, 3, n_orb)), rng.standard_normal((n, n_orb))
+    od = torch.float64 if dtype == "f64" else torch.float32
+    args = (to_dev(gv, od), to_dev(gg, od), to_dev(gl, od))
+    nb = P.spline_backward_work_bytes(d, n, P.SPL_DETERMINISTIC)
+    assert nb >= grid[0] * grid[1] * grid[2] * 64 * d.o_pad * (8 if dtype == "f64" else 4)   # the block workspace
+    say("deterministic backward, dense path", dtype)
+    runs = []
+    for _ in range(2):
+        gt, _ = P.spline_eval_vgl_backward(d, tab, to_dev(pos), *args, want_pos=False, flags=P.SPL_DETERMINISTIC)
+        torch.cuda.synchronize()
+        runs.append(gt.clone())
+    assert torch.equal(runs[0], runs[1])
+    ok = np.all(np.isfinite(pos), axis=1)
+    rb, rlb, _ = oadj.vgl_backward(bq, SKEW, pos[ok], gv[ok], gg[ok], gl[ok], lap_beta=lq)
+    got = runs[0].double().cpu().numpy()
+    tol = 1e-12 if dtype == "f64" else 2e-5
+    assert normwise(got[0, ..., :n_orb], rb) <= tol
+    assert normwise(got[1, ..., :n_orb], rlb) <= tol
+    assert np.all(got[..., n_orb:] == 0.0)

@@ -394,14 +394,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 
 // Dense points, second step: table row (X, Y, Z) receives the blocks of the 64 cells whose
 // 4x4x4 block contains it, cell (X - l + 1, Y - m + 1, Z - n + 1) at its row 16 l + 4 m + n, summed
-// in that fixed (l, m, n) order and added to the gradient table.  One thread per (row, orbital).
+// in that fixed (l, m, n) order and added to the gradient table.  One workgroup per row (so the
+// cell lookups are uniform), its threads over the orbitals.
 template <typename A>
 __global__ __launch_bounds__(256) void k_bwd_gather(Geom g, const A* blocks, const int32_t* occ, int32_t n_orb,
-                                                    int32_t o_pad, int64_t n_rows, A* gtab) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t row = t / o_pad;
-  const int o = (int)(t % o_pad);
-  if (row >= n_rows || o >= n_orb) return;
+                                                    int32_t o_pad, A* gtab) {
+  const int64_t row = blockIdx.x;
   const int Z = (int)(row % g.n[2]);
   const int Y = (int)((row / g.n[2]) % g.n[1]);
   const int X = (int)(row / ((int64_t)g.n[2] * g.n[1]));
@@ -412,21 +410,23 @@ __global__ __launch_bounds__(256) void k_bwd_gather(Geom g, const A* blocks, con
     cy[l] = (Y - l + 1 + 2 * g.n[1]) % g.n[1];
     cz[l] = (Z - l + 1 + 2 * g.n[2]) % g.n[2];
   }
-  A sum = A(0);
+  for (int o = threadIdx.x; o < n_orb; o += blockDim.x) {
+    A sum = A(0);
 #pragma unroll
-  for (int l = 0; l < 4; ++l)
+    for (int l = 0; l < 4; ++l)
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      A part[4];
+      for (int m = 0; m < 4; ++m) {
+        A part[4];
 #pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        const int64_t c = ((int64_t)cx[l] * g.n[1] + cy[m]) * g.n[2] + cz[n];
-        part[n] = occ[c] ? blocks[(c * 64 + 16 * l + 4 * m + n) * o_pad + o] : A(0);
+        for (int n = 0; n < 4; ++n) {
+          const int64_t c = ((int64_t)cx[l] * g.n[1] + cy[m]) * g.n[2] + cz[n];
+          part[n] = occ[c] ? blocks[(c * 64 + 16 * l + 4 * m + n) * o_pad + o] : A(0);
+        }
+#pragma unroll
+        for (int n = 0; n < 4; ++n) sum += part[n];
       }
-#pragma unroll
-      for (int n = 0; n < 4; ++n) sum += part[n];
-    }
-  gtab[row * o_pad + o] += sum;
+    gtab[row * o_pad + o] += sum;
+  }
 }
 
 __global__ void k_bwd_zero_i32(int32_t* p, int64_t n) {
@@ -507,8 +507,9 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
   // 2 (FP64) tiles of accumulators per wave
   const int tiles = (d->n_orb + 15) / 16;
   const int64_t occupied = std::min<int64_t>(n_pts, L.n_cells) / L.n_classes;
+  // (the dense form launches every cell at once, so only the orbital count limits the tiles)
   int ot = d->dtype == SPL_F64 ? 2 : 4;
-  while (ot > 1 && (ot >= 2 * tiles || occupied * ((tiles + ot - 1) / ot) < 2048)) ot >>= 1;
+  while (ot > 1 && (ot >= 2 * tiles || (!L.dense && occupied * ((tiles + ot - 1) / ot) < 2048))) ot >>= 1;
   CellArgs a;
   memset(&a, 0, sizeof(a));
   a.g = g;
@@ -566,15 +567,14 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
       const int grid = (int)std::min<int64_t>(waves, 1 << 16);
       hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, stream, a);
       if ((rc = hip_fail(hipGetLastError(), "cell block launch"))) return rc;
-      const int64_t threads = L.n_cells * d->o_pad;
-      const int gblocks = (int)((threads + 255) / 256);
+      const int gthreads = d->o_pad >= 256 ? 256 : (d->o_pad + 63) / 64 * 64;
       if (d->dtype == SPL_F64)
-        hipLaunchKernelGGL(k_bwd_gather<double>, dim3(gblocks), dim3(256), 0, stream, g,
-                           static_cast<const double*>(a.blocks), a.occ, d->n_orb, d->o_pad, L.n_cells,
+        hipLaunchKernelGGL(k_bwd_gather<double>, dim3((unsigned)L.n_cells), dim3(gthreads), 0, stream, g,
+                           static_cast<const double*>(a.blocks), a.occ, d->n_orb, d->o_pad,
                            static_cast<double*>(a.gtable));
       else
-        hipLaunchKernelGGL(k_bwd_gather<float>, dim3(gblocks), dim3(256), 0, stream, g,
-                           static_cast<const float*>(a.blocks), a.occ, d->n_orb, d->o_pad, L.n_cells,
+        hipLaunchKernelGGL(k_bwd_gather<float>, dim3((unsigned)L.n_cells), dim3(gthreads), 0, stream, g,
+                           static_cast<const float*>(a.blocks), a.occ, d->n_orb, d->o_pad,
                            static_cast<float*>(a.gtable));
       if ((rc = hip_fail(hipGetLastError(), "row gather launch"))) return rc;
       continue;

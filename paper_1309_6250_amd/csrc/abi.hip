@@ -234,7 +234,7 @@ using namespace pws;
 
 extern "C" {
 
-int spline_version(void) { return 10100; }
+int spline_version(void) { return 10200; }
 
 const char* spline_last_error(void) { return g_last_error.c_str(); }
 

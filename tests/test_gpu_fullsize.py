@@ -259,3 +259,27 @@ def test_mgo96_pp_full_size(mgo96):
     got = [g.double().cpu().numpy() for g in got]
     for g, r in zip(got, ref):
         assert normwise(g, r) <= 1e-5
+
+
+@pytest.mark.timeout(600)
+def test_fused_fit_matches_autograd_form_at_fit_size():
+    """At 10^6 points the fused fit path (forward, misfit kernels, adjoint) and the autograd form
+    (SplineVGL + tensor ops) give the same loss and coefficient gradient to FP32 accuracy."""
+    from paper_1309_6250_amd.fit import FitProblem, make_loss
+    w = config(4)
+    s = w.system
+    pos = to_dev(w.positions())
+    d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, "f32")
+    tab = P.spline_build(d, to_dev(s.grid_values()))
+    g = torch.Generator(device=DEV).manual_seed(406)
+    v_t = torch.randn((pos.shape[0], s.n_orb), device=DEV, generator=g, dtype=torch.float64)
+    l_t = 30.0 * torch.randn((pos.shape[0], s.n_orb), device=DEV, generator=g, dtype=torch.float64)
+    say("fused fit against autograd at 1e6 points")
+    prob = FitProblem(d, pos, v_t, l_t, lam=1e-3)
+    loss, grad = prob.loss_and_grad(tab)
+    beta = tab.clone().requires_grad_(True)
+    ref = make_loss(d, pos, v_t, l_t, lam=1e-3)(beta)
+    ref.backward()
+    torch.cuda.synchronize()
+    assert abs(float(loss) - float(ref.detach())) <= 1e-6 * abs(float(ref.detach()))
+    assert normwise(grad.double().cpu().numpy(), beta.grad.double().cpu().numpy()) < 1e-5

@@ -301,6 +301,23 @@ int spline_backward_work_bytes(const spl_desc* d, int64_t n_pts, int32_t flags, 
 int spline_misfit(const spl_desc* d, int64_t n, const void* y, const void* t, double w, void* g, double* loss,
                   void* work, int64_t work_bytes, void* stream);
 
+/*
+ * Smoothness penalty of the same fit: with D the periodic second difference along one grid axis
+ * (beta_{i-1} - 2 beta_i + beta_{i+1}), over the orbital table's real orbitals o < n_orb,
+ *   *loss  += w sum over the 3 axes, the grid points and the orbitals of (D beta)^2
+ *   gtable += 2 w sum over the axes of D (D beta)   (the gradient; D is symmetric under the wrap)
+ *   table   device, as written by spline_build (real B-spline; other descriptors -> SPL_EUNSUPPORTED)
+ *   w       the penalty's weight, finite
+ *   gtable  device, the gradient table of spline_eval_vgl_backward; its orbital table is
+ *           ACCUMULATED into, padding columns untouched
+ *   loss    device, one FP64, ACCUMULATED into
+ *   work    device, spline_misfit_work_bytes() bytes, 8-byte aligned
+ * Computed in FP64 whatever the storage type; the sum is reduced in a fixed order (bitwise
+ * reproducible).  Errors: NULL pointer, non-finite w, short work, misalignment -> SPL_EINVAL.
+ */
+int spline_smoothness_penalty(const spl_desc* d, const void* table, double w, void* gtable, double* loss,
+                              void* work, int64_t work_bytes, void* stream);
+
 /* Workspace bytes of spline_misfit (a fixed number of FP64 partial sums).  Host only. */
 int spline_misfit_work_bytes(const spl_desc* d, int64_t n, int64_t* bytes);
 

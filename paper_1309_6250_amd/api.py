@@ -318,6 +318,22 @@ def spline_misfit(desc, y, t, w, loss, g=None, work=None, stream=None):
     return g
 
 
+def spline_smoothness_penalty(desc, table, w, loss, gtable=None, work=None, stream=None):
+    """loss (FP64 device scalar) += w sum (D beta)^2 over axes, grid points and real orbitals of the
+    orbital table; gtable (allocated as zeros if not given) += its gradient.  Returns gtable."""
+    if gtable is None:
+        gtable = new_gtable(desc, table.device)
+    _need(table, "table", None)
+    _need(gtable, "gtable", OUT_TORCH[desc.dtype], desc.table_elems * desc.n_tables)
+    _need(loss, "loss", torch.float64, 1)
+    if work is None:
+        work = torch.empty(spline_misfit_work_bytes(desc, 0), dtype=torch.uint8, device=table.device)
+    check(lib().spline_smoothness_penalty(ctypes.byref(desc), _ptr(table), float(w), _ptr(gtable), _ptr(loss),
+                                          _ptr(work), int(work.numel() * work.element_size()), _stream(stream)),
+          "spline_smoothness_penalty")
+    return gtable
+
+
 def spline_autotune(desc, table, pos, v=None, grad=None, lap=None, stream=None):
     n = _check_inputs(desc, table, pos)
     v, grad, lap = _outputs(desc, n, pos.device, v, grad, lap)

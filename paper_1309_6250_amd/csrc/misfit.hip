@@ -1,5 +1,6 @@
-// spline_misfit: the data term of the least-squares fit of coefficients to orbital samples.
+// The two terms of the least-squares fit of coefficients to orbital samples.
 //
+// spline_misfit, the data term.
 // For n outputs y (values or Laplacians of the spline at the fit points) and their targets t:
 //     loss += w sum_i (y_i - t_i)^2,        g_i = 2 w (y_i - t_i),
 // g being the upstream gradient that spline_eval_vgl_backward turns into the gradient of the
@@ -63,6 +64,63 @@ __global__ __launch_bounds__(MISFIT_THREADS) void k_misfit_total(const double* p
   if (threadIdx.x == 0) *loss += w * red[0];
 }
 
+// spline_smoothness_penalty, the regularizer: with D the periodic second difference along one grid
+// axis, for the orbital table beta and its real orbitals o < n_orb,
+//     loss  += w sum over axes, grid points and orbitals of (D beta)^2
+//     gbeta += 2 w sum over axes of D (D beta)        (D is symmetric under the periodic wrap;
+//              D D = the five-point stencil 1 -4 6 -4 1)
+// One thread per (grid point, orbital), in FP64 whatever the storage type; the sum over the
+// fixed grid of MISFIT_BLOCKS workgroups is reduced like the misfit's.
+template <typename TS> struct Coef;
+template <> struct Coef<double> {
+  __device__ __forceinline__ static double at(const double* p) { return *p; }
+};
+template <> struct Coef<float> {
+  __device__ __forceinline__ static double at(const float* p) { return (double)*p; }
+};
+template <> struct Coef<uint16_t> {   // BF16 bits
+  __device__ __forceinline__ static double at(const uint16_t* p) { return (double)__uint_as_float((uint32_t)*p << 16); }
+};
+
+template <typename TS, typename GO>
+__global__ __launch_bounds__(MISFIT_THREADS) void k_penalty(Geom g, const TS* beta, int32_t n_orb, double w,
+                                                            GO* gbeta, double* partial) {
+  __shared__ double red[MISFIT_THREADS];
+  const int64_t n = (int64_t)g.n[0] * g.n[1] * g.n[2] * n_orb;
+  const int64_t stride = (int64_t)MISFIT_BLOCKS * MISFIT_THREADS;
+  const int64_t step[3] = {g.s0, g.s1, g.o_pad};
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * MISFIT_THREADS + threadIdx.x; i < n; i += stride) {
+    const int o = (int)(i % n_orb);
+    const int64_t pt = i / n_orb;
+    const int idx[3] = {(int)(pt / ((int64_t)g.n[1] * g.n[2])), (int)((pt / g.n[2]) % g.n[1]), (int)(pt % g.n[2])};
+    const int64_t base = idx[0] * g.s0 + idx[1] * g.s1 + idx[2] * (int64_t)g.o_pad + o;
+    const double b0 = Coef<TS>::at(beta + base);
+    double grad = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const int N = g.n[ax];
+      auto at = [&](int k) {               // beta at offset k along this axis, periodic
+        const int j = (idx[ax] + k + 2 * N) % N;
+        return Coef<TS>::at(beta + base + (int64_t)(j - idx[ax]) * step[ax]);
+      };
+      const double m2 = at(-2), m1 = at(-1), p1 = at(1), p2 = at(2);
+      const double d2 = m1 - 2.0 * b0 + p1;
+      s += d2 * d2;
+      grad += (m2 + p2) - 4.0 * (m1 + p1) + 6.0 * b0;
+    }
+    GO* gp = gbeta + base;
+    *gp = (GO)((double)*gp + 2.0 * w * grad);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = MISFIT_THREADS / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 }  // namespace pws
 
 using namespace pws;
@@ -106,6 +164,38 @@ int spline_misfit(const spl_desc* d, int64_t n, const void* y, const void* t, do
   if ((rc = hip_fail(hipGetLastError(), "misfit launch"))) return rc;
   hipLaunchKernelGGL(k_misfit_total, dim3(1), dim3(MISFIT_THREADS), 0, s, partial, w, loss);
   return hip_fail(hipGetLastError(), "misfit total launch");
+}
+
+int spline_smoothness_penalty(const spl_desc* d, const void* table, double w, void* gtable, double* loss,
+                              void* work, int64_t work_bytes, void* stream) {
+  clear_error();
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if (d->basis != SPL_BSPLINE || d->sep_grad || d->bloch)
+    return fail(SPL_EUNSUPPORTED, "the penalty covers real B-spline tables without separate gradients");
+  if (!std::isfinite(w)) return fail(SPL_EINVAL, "weight is not finite");
+  if (!table || !gtable || !loss || !work) return fail(SPL_EINVAL, "NULL table, gtable, loss or work");
+  if (work_bytes < (int64_t)MISFIT_BLOCKS * (int64_t)sizeof(double))
+    return fail(SPL_EINVAL, "work must hold %d bytes", MISFIT_BLOCKS * (int)sizeof(double));
+  const size_t gs = d->dtype == SPL_F64 ? 8 : 4;
+  if ((uintptr_t)table % (size_t)d->elem_bytes || (uintptr_t)gtable % gs || (uintptr_t)loss % 8 ||
+      (uintptr_t)work % 8)
+    return fail(SPL_EINVAL, "table, gtable, loss or work misaligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* partial = static_cast<double*>(work);
+  const Geom g = make_geom(d);
+  if (d->dtype == SPL_F64)
+    hipLaunchKernelGGL((k_penalty<double, double>), dim3(MISFIT_BLOCKS), dim3(MISFIT_THREADS), 0, s, g,
+                       static_cast<const double*>(table), d->n_orb, w, static_cast<double*>(gtable), partial);
+  else if (d->dtype == SPL_F32)
+    hipLaunchKernelGGL((k_penalty<float, float>), dim3(MISFIT_BLOCKS), dim3(MISFIT_THREADS), 0, s, g,
+                       static_cast<const float*>(table), d->n_orb, w, static_cast<float*>(gtable), partial);
+  else
+    hipLaunchKernelGGL((k_penalty<uint16_t, float>), dim3(MISFIT_BLOCKS), dim3(MISFIT_THREADS), 0, s, g,
+                       static_cast<const uint16_t*>(table), d->n_orb, w, static_cast<float*>(gtable), partial);
+  if ((rc = hip_fail(hipGetLastError(), "penalty launch"))) return rc;
+  hipLaunchKernelGGL(k_misfit_total, dim3(1), dim3(MISFIT_THREADS), 0, s, partial, w, loss);
+  return hip_fail(hipGetLastError(), "penalty total launch");
 }
 
 }  // extern "C"

@@ -9,11 +9,11 @@ Minimizes over the coefficient table beta (FP32 or FP64)
 with wV = 1 / mean V_t^2 and wL = 1 / mean lap_t^2 (or 0), periodic second differences,
 by Adam.  Two forms of the same loss:
 
-- FitProblem.loss_and_grad, used by fit_adam: every pass over the point-sized arrays runs in
-  the library's kernels (the locality-ordered forward, spline_misfit on V and on lap, which
-  forms the upstream gradients in place and sums the squared residuals in FP64 in a fixed
-  order, and the adjoint); only the penalty and the Adam update are tensor operations, on the
-  table.  Buffers are allocated once.
+- FitProblem.loss_and_grad, used by fit_adam: every term runs in the library's kernels (the
+  locality-ordered forward, spline_misfit on V and on lap, which forms the upstream gradients in
+  place and sums the squared residuals in FP64 in a fixed order, the adjoint, and
+  spline_smoothness_penalty on the table); only the Adam update is a tensor operation.  Buffers
+  are allocated once.
 - make_loss, a differentiable function of the table built on SplineVGL, for use inside a
   larger autograd graph.  Its residuals are formed in the kernel's output precision and
   their squares summed in FP64.
@@ -22,7 +22,8 @@ import torch
 
 from ._lib import SPL_DETERMINISTIC
 from .api import (OUT_TORCH, new_gtable, spline_eval_vgl_backward, spline_eval_vgl_sorted, spline_misfit,
-                  spline_misfit_work_bytes, spline_sorted_work_bytes, spline_backward_work_bytes)
+                  spline_misfit_work_bytes, spline_smoothness_penalty, spline_sorted_work_bytes,
+                  spline_backward_work_bytes)
 from .autograd import SplineVGL
 
 
@@ -108,17 +109,7 @@ class FitProblem:
         spline_eval_vgl_backward(d, beta, self.pos, gv, None, gl, self.gtable, None, want_pos=False, flags=self.flags,
                                  work=self.bwd_work)
         if self.lam:
-            n_orb = d.n_orb
-            core = beta[0, ..., :n_orb].to(torch.float64)
-            reg = torch.zeros((), dtype=torch.float64, device=beta.device)
-            greg = torch.zeros_like(core)
-            for dim in range(3):
-                d2 = second_difference(core, dim)
-                reg = reg + torch.sum(d2 * d2)
-                # d/dbeta sum (D2 beta)^2 = 2 D2 (D2 beta): D2 is symmetric under the periodic wrap
-                greg += second_difference(d2, dim)
-            self.loss += self.reg_scale * reg
-            self.gtable[0, ..., :n_orb] += (2.0 * self.reg_scale * greg).to(self.gtable.dtype)
+            spline_smoothness_penalty(d, beta, self.reg_scale, self.loss, gtable=self.gtable, work=self.misfit_work)
         return self.loss, self.gtable
 
 

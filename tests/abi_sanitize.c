@@ -158,6 +158,14 @@ int main(void) {
   expect(spline_misfit(&d, 10, (char*)fake + 4, fake, 1.0, fake, (double*)fake, fake, bytes, NULL), SPL_EINVAL,
          "misfit misaligned");
 
+  /* smoothness penalty */
+  expect(spline_smoothness_penalty(&d32, fake, 1.0, NULL, (double*)fake, fake, bytes, NULL), SPL_EINVAL,
+         "penalty NULL gtable");
+  expect(spline_smoothness_penalty(&d32, fake, INFINITY, fake, (double*)fake, fake, bytes, NULL), SPL_EINVAL,
+         "penalty inf w");
+  expect(spline_smoothness_penalty(&dp, fake, 1.0, fake, (double*)fake, fake, bytes, NULL), SPL_EUNSUPPORTED,
+         "penalty pp");
+
   /* batched plans */
   void* plan = fake;
   expect(spline_batch_plan_create(NULL, 1, NULL, NULL, &plan), SPL_EINVAL, "plan NULL items");

@@ -319,3 +319,24 @@ def test_misfit_validates_before_any_launch():
     d64 = P.spline_desc_init(LAT, (8, 8, 8), 4, "f64")
     assert lib.spline_misfit(ctypes.byref(d64), 10, ctypes.c_void_p(260), fake, 1.0, fake, fake, fake, w,
                              None) == P.SPL_EINVAL
+
+
+def test_smoothness_penalty_validates_before_any_launch():
+    fake = ctypes.c_void_p(256)
+    d = P.spline_desc_init(LAT, (8, 8, 8), 4, "f32")
+    ref = ctypes.byref(d)
+    lib = P.lib()
+    nb = ctypes.c_int64(-1)
+    assert lib.spline_misfit_work_bytes(ref, 0, ctypes.byref(nb)) == P.SPL_OK
+    w = nb.value
+    for k in range(4):                      # each of table, gtable, loss, work NULL in turn
+        args = [fake] * 4
+        args[k] = None
+        table, gtable, loss, work = args
+        assert lib.spline_smoothness_penalty(ref, table, 1.0, gtable, loss, work, w, None) == P.SPL_EINVAL
+    assert lib.spline_smoothness_penalty(ref, fake, float("nan"), fake, fake, fake, w, None) == P.SPL_EINVAL
+    assert lib.spline_smoothness_penalty(ref, fake, 1.0, fake, fake, fake, w - 8, None) == P.SPL_EINVAL
+    assert lib.spline_smoothness_penalty(ref, fake, 1.0, ctypes.c_void_p(258), fake, fake, w, None) == P.SPL_EINVAL
+    dp = P.spline_desc_init(LAT, (8, 8, 8), 4, "f32", basis="pp")
+    assert lib.spline_smoothness_penalty(ctypes.byref(dp), fake, 1.0, fake, fake, fake, w,
+                                         None) == P.SPL_EUNSUPPORTED

@@ -150,6 +150,34 @@ def test_misfit_kernel(dtype):
         assert float(loss) == float(loss2)
 
 
+@pytest.mark.parametrize("grid", [(5, 6, 7), (4, 9, 4)])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_smoothness_penalty_kernel(dtype, grid):
+    """spline_smoothness_penalty against its definition, numpy second differences with the periodic
+    wrap (a 4-point axis makes the +-2 neighbours one point): loss and gradient, padding untouched."""
+    rng = np.random.default_rng(108)
+    n_orb = 37
+    beta = rng.standard_normal(grid + (n_orb,))
+    d = P.spline_desc_init(SKEW, grid, n_orb, dtype)
+    tab = table_from_oracle(d, beta, dtype)
+    bq = oq.quantized(beta, dtype)
+    w = 0.013
+    loss = torch.full((1,), 2.0, dtype=torch.float64, device=DEV)
+    say("smoothness penalty", dtype, grid)
+    g = P.spline_smoothness_penalty(d, tab, w, loss)
+    torch.cuda.synchronize()
+
+    def d2(a, ax):
+        return np.roll(a, 1, axis=ax) - 2.0 * a + np.roll(a, -1, axis=ax)
+    ref_loss = 2.0 + w * sum(np.sum(d2(bq, ax) ** 2) for ax in range(3))
+    ref_grad = 2.0 * w * sum(d2(d2(bq, ax), ax) for ax in range(3))
+    assert abs(float(loss) - ref_loss) <= 1e-12 * ref_loss
+    got = g.double().cpu().numpy()
+    tol = 1e-14 if dtype == "f64" else 1e-7
+    assert normwise(got[0, ..., :n_orb], ref_grad) <= tol
+    assert np.all(got[0, ..., n_orb:] == 0.0)
+
+
 def test_fit_problem_matches_oracle():
     """The fused fit path (forward, misfit kernels, deterministic adjoint, penalty) gives the loss
     and coefficient gradient of the oracle's fit, like the autograd form."""

@@ -248,6 +248,26 @@ int spline_eval_vgl_sorted(const spl_desc* d, const void* table, int64_t n_pts, 
 int spline_sorted_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes);
 
 /*
+ * Values, gradients and Laplacians as spline_eval_vgl, computed cell by cell: the points are
+ * sorted by grid cell (stable radix sort), and for the points of one cell the outputs are a dense
+ * product of their 64 row weights with the cell's 4x4x4 block (Eq. b-splineapproximation with
+ * the chain rule of Sec. II), done on the matrix cores with each block read once per cell.  For
+ * point sets with several points per cell (fits, dense sampling); QMC walkers rarely share cells.
+ * The outputs equal spline_eval_vgl's up to the order of summation, in the caller's point order.
+ *   v, grad, lap  device, as for spline_eval_vgl; each may be NULL to skip it (not all three)
+ *   work          device workspace, 256-byte aligned, at least spline_cells_work_bytes() bytes,
+ *                 contents undefined afterwards
+ * Non-finite points get NaN.  Real B-spline tables only (with or without a separate Laplacian
+ * table); other descriptors -> SPL_EUNSUPPORTED.  Allocates nothing.
+ */
+int spline_eval_vgl_cells(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, void* v,
+                          void* grad, void* lap, void* work, int64_t work_bytes, void* stream);
+
+/* Workspace bytes of spline_eval_vgl_cells for n_pts points (the sort's keys, runs and point
+ * records).  Host only; may query the current HIP device. */
+int spline_cells_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes);
+
+/*
  * Adjoint of spline_eval_vgl: given dL/dv, dL/dgrad, dL/dlap of a scalar loss L,
  *   gtable += dL/dtable   (the transpose of the 64-coefficient gather, periodic wrap)
  *   gpos    = dL/dpos     (through grad, Hessian and gradient of the Laplacian)

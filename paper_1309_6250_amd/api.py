@@ -255,6 +255,40 @@ def spline_eval_vgl_sorted(desc, table, pos, v=None, grad=None, lap=None, work=N
     return _as_complex(desc, v), _as_complex(desc, grad), _as_complex(desc, lap)
 
 
+def spline_cells_work_bytes(desc, n_pts):
+    out = ctypes.c_int64()
+    check(lib().spline_cells_work_bytes(ctypes.byref(desc), int(n_pts), ctypes.byref(out)), "spline_cells_work_bytes")
+    return out.value
+
+
+def spline_eval_vgl_cells(desc, table, pos, v=None, grad=None, lap=None, outputs="vgl", work=None, stream=None):
+    """spline_eval_vgl computed cell by cell on the matrix cores (for several points per cell).
+    `outputs` names the ones wanted ('v', 'g', 'l' in any combination); returns (v, grad, lap) with
+    None for the others.  Equal to spline_eval_vgl up to the order of summation."""
+    n = _check_inputs(desc, table, pos)
+    od = OUT_TORCH[desc.dtype]
+    dev = pos.device
+    o = desc.n_orb
+    if "v" in outputs and v is None:
+        v = torch.empty((n, o), dtype=od, device=dev)
+    if "g" in outputs and grad is None:
+        grad = torch.empty((n, 3, o), dtype=od, device=dev)
+    if "l" in outputs and lap is None:
+        lap = torch.empty((n, o), dtype=od, device=dev)
+    for name, t, k in (("v", v, 1), ("grad", grad, 3), ("lap", lap, 1)):
+        if t is not None:
+            _need(t, name, od, k * n * o)
+    nbytes = spline_cells_work_bytes(desc, n)
+    if work is None:
+        work = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    if work.numel() * work.element_size() < nbytes:
+        raise ValueError(f"work must hold {nbytes} bytes")
+    check(lib().spline_eval_vgl_cells(ctypes.byref(desc), _ptr(table), n, _ptr(pos), _ptr(v), _ptr(grad), _ptr(lap),
+                                      _ptr(work), int(work.numel() * work.element_size()), _stream(stream)),
+          "spline_eval_vgl_cells")
+    return v, grad, lap
+
+
 def spline_eval_vgl_backward(desc, table, pos, gv=None, ggrad=None, glap=None, gtable=None, gpos=None,
                              want_table=True, want_pos=True, flags=0, stream=None, work=None):
     """Returns (gtable, gpos).  gtable is accumulated into (a fresh zero table if not given).

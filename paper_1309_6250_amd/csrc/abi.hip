@@ -204,6 +204,9 @@ int build_smoothing(const spl_desc* d, int64_t n_g, const int32_t* miller, const
                     void* work, hipStream_t stream);
 int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, const void* gv, const void* ggrad,
                            const void* glap, void* gtable, void* work, int64_t work_bytes, hipStream_t stream);
+int cells_eval_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes);
+int launch_eval_cells(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, void* v, void* grad,
+                      void* lap, void* work, int64_t work_bytes, hipStream_t stream);
 
 int check_eval_args(const spl_desc* d, const void* table, int64_t n_pts, const double* pos) {
   int rc = check_desc(d);
@@ -449,6 +452,34 @@ int spline_backward_work_bytes(const spl_desc* d, int64_t n_pts, int32_t flags, 
   *bytes = 0;
   if (!(flags & SPL_DETERMINISTIC) || n_pts == 0) return SPL_OK;
   return sorted_work_bytes(d, n_pts, bytes);
+}
+
+int spline_cells_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes) {
+  clear_error();
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if (!bytes || n_pts < 0 || n_pts > 0x7fffffffLL) return fail(SPL_EINVAL, "bytes is NULL or n_pts out of range");
+  if (n_pts == 0) {
+    *bytes = 0;
+    return SPL_OK;
+  }
+  return cells_eval_work_bytes(d, n_pts, bytes);
+}
+
+int spline_eval_vgl_cells(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, void* v,
+                          void* grad, void* lap, void* work, int64_t work_bytes, void* stream) {
+  clear_error();
+  int rc = check_eval_args(d, table, n_pts, pos);
+  if (rc) return rc;
+  if (d->basis != SPL_BSPLINE || d->sep_grad || d->bloch)
+    return fail(SPL_EUNSUPPORTED, "the cell-wise evaluation covers real B-spline tables without separate gradients");
+  if (n_pts == 0) return SPL_OK;
+  if (!v && !grad && !lap) return fail(SPL_EINVAL, "no output requested");
+  for (const void* o : {static_cast<const void*>(v), static_cast<const void*>(grad), static_cast<const void*>(lap)})
+    if (o && !out_align_ok(d, o)) return fail(SPL_EINVAL, "output not aligned to its element size");
+  if (!work) return fail(SPL_EINVAL, "work is NULL (size from spline_cells_work_bytes)");
+  if (!aligned(work, 256)) return fail(SPL_EINVAL, "workspace must be 256-byte aligned");
+  return launch_eval_cells(d, table, n_pts, pos, v, grad, lap, work, work_bytes, static_cast<hipStream_t>(stream));
 }
 
 int spline_eval_vgl_backward(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, const void* gv,

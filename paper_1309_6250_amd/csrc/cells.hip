@@ -43,7 +43,7 @@ struct SortLayout {
 
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-static int sort_layout(const spl_desc* d, int64_t n_pts, SortLayout* L) {
+static int sort_layout(const spl_desc* d, int64_t n_pts, SortLayout* L, bool adjoint_blocks = true) {
   L->n_cells = (int64_t)d->grid[0] * d->grid[1] * d->grid[2];
   L->n_classes = axis_colours(d->grid[0]) * axis_colours(d->grid[1]) * axis_colours(d->grid[2]);
   const uint64_t max_key = (uint64_t)(L->n_classes + 1) * (uint64_t)L->n_cells;
@@ -80,7 +80,7 @@ static int sort_layout(const spl_desc* d, int64_t n_pts, SortLayout* L) {
   // dense points (at least 4 per cell on average): every cell's 64-row block gets its own place
   const size_t gsz = d->dtype == SPL_F64 ? 8 : 4;
   const size_t block_bytes = (size_t)L->n_cells * 64 * (size_t)d->o_pad * gsz;
-  L->dense = n_pts >= 4 * L->n_cells && block_bytes <= ((size_t)4 << 30);
+  L->dense = adjoint_blocks && n_pts >= 4 * L->n_cells && block_bytes <= ((size_t)4 << 30);
   L->occ = off; off = align_up(off + (L->dense ? 4 * (size_t)L->n_cells : 0));
   L->blocks = off; off = align_up(off + (L->dense ? block_bytes : 0));
   L->temp = off; off = align_up(off + L->temp_bytes);
@@ -448,23 +448,22 @@ static CellKernel pick_cells(int ot, int n_terms) {
   return n_terms <= 2 ? pick_cells_nt<A, 2>(ot) : pick_cells_nt<A, 5>(ot);
 }
 
-int sorted_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes) {
-  SortLayout L;
-  int rc = sort_layout(d, n_pts, &L);
-  if (rc) return rc;
-  *bytes = (int64_t)L.total;
-  return SPL_OK;
-}
+// The points sorted by (colour class, cell): keys, permutation, runs of one cell with their point
+// ranges, the first run of each class, and each sorted point's record.
+struct CellSort {
+  int64_t* keys;         // sorted keys (class n_cells + cell; non-finite points: sentinel, last)
+  int32_t* perm;         // sorted position -> point index
+  int64_t* uniq;         // key of each run
+  int32_t* counts;       // points in each run
+  int32_t* offsets;      // first sorted position of each run
+  int32_t* class_start;  // first run of each class (n_classes + 1 entries)
+  void* pts;             // SortedPoint records in sorted order
+  char* base;            // the workspace
+};
 
-// Deterministic coefficient gradient (accumulated into gtable).  work: sorted_work_bytes bytes.
-int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, const void* gv, const void* ggrad,
-                           const void* glap, void* gtable, void* work, int64_t work_bytes, hipStream_t stream) {
-  if (n_pts == 0 || !gtable) return SPL_OK;
-  SortLayout L;
-  int rc = sort_layout(d, n_pts, &L);
-  if (rc) return rc;
-  if (!work || work_bytes < (int64_t)L.total)
-    return fail(SPL_EINVAL, "deterministic backward needs a workspace of %lld bytes", (long long)L.total);
+static int cell_sort(const spl_desc* d, int64_t n_pts, const double* pos, void* work, const SortLayout& L,
+                     hipStream_t stream, CellSort* cs) {
+  int rc;
   char* W = static_cast<char*>(work);
   int64_t* keys_in = reinterpret_cast<int64_t*>(W + L.keys_in);
   int64_t* keys_out = reinterpret_cast<int64_t*>(W + L.keys_out);
@@ -502,6 +501,37 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
     hipLaunchKernelGGL(k_sorted_points<float>, dim3((n + 255) / 256), dim3(256), 0, stream, g, pos, vals_out,
                        (int32_t)n, static_cast<SortedPoint<float>*>(pts));
   if ((rc = hip_fail(hipGetLastError(), "sorted point launch"))) return rc;
+
+  *cs = CellSort{keys_out, vals_out, uniq, counts, offsets, class_start, pts, W};
+  return SPL_OK;
+}
+
+int sorted_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes) {
+  SortLayout L;
+  int rc = sort_layout(d, n_pts, &L);
+  if (rc) return rc;
+  *bytes = (int64_t)L.total;
+  return SPL_OK;
+}
+
+// Deterministic coefficient gradient (accumulated into gtable).  work: sorted_work_bytes bytes.
+int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, const void* gv, const void* ggrad,
+                           const void* glap, void* gtable, void* work, int64_t work_bytes, hipStream_t stream) {
+  if (n_pts == 0 || !gtable) return SPL_OK;
+  SortLayout L;
+  int rc = sort_layout(d, n_pts, &L);
+  if (rc) return rc;
+  if (!work || work_bytes < (int64_t)L.total)
+    return fail(SPL_EINVAL, "deterministic backward needs a workspace of %lld bytes", (long long)L.total);
+  CellSort cs;
+  if ((rc = cell_sort(d, n_pts, pos, work, L, stream, &cs))) return rc;
+  char* W = cs.base;
+  int64_t* uniq = cs.uniq;
+  int32_t* counts = cs.counts;
+  int32_t* offsets = cs.offsets;
+  int32_t* class_start = cs.class_start;
+  void* pts = cs.pts;
+  const Geom g = make_geom(d);
 
   // orbital tiles per wave: enough waves per class launch to cover the chip, at most 4 (FP32) or
   // 2 (FP64) tiles of accumulators per wave
@@ -588,6 +618,276 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
     }
   }
   return SPL_OK;
+}
+
+
+// ---------------------------------------------------------------------------------------------
+// Forward evaluation cell by cell (spline_eval_vgl_cells).  For the points of one cell the
+// outputs are a dense product: out_term[point][o] = sum over the 64 rows of the cell's block of
+// W_term(point)[row] beta[row][o] (Eq. b-splineapproximation with the chain rule of Sec. II), so
+// a wave loads the block once, as matrix-core B operands (k-step ks covers rows 4 ks .. 4 ks + 3:
+// block offsets l = ks / 4, m = ks mod 4 and n = the lane group), and multiplies it with the row
+// weights of up to 32 of the cell's points (two M tiles of 16) per batch.  Where points are
+// dense each block row is read once per cell instead of once per point.
+
+struct FwdArgs {
+  Geom g;
+  const void* table;       // orbital table; the Laplacian table follows at lap_off elements
+  int64_t lap_off;
+  void* out[5];            // output base of each term (point-major)
+  int64_t out_stride[5];   // elements from one point to the next
+  int32_t kind[5];         // TERM_* of each term (TERM_VAL of the Laplacian table for a separate one)
+  int32_t src[5];          // 0: the orbital table, 1: the Laplacian table
+  int32_t n_terms;
+  int32_t use_lap_table;
+  const int64_t* uniq;
+  const int32_t* counts;
+  const int32_t* offsets;
+  const void* pts;
+  const int32_t* class_start;
+  int64_t n_cells;
+  int32_t n_classes;
+  int32_t n_orb;
+  int32_t n_groups;
+  int32_t pad_;
+};
+
+template <typename TS> struct Stored;
+template <> struct Stored<double> {
+  __device__ __forceinline__ static double at(const double* p) { return *p; }
+};
+template <> struct Stored<float> {
+  __device__ __forceinline__ static float at(const float* p) { return *p; }
+};
+template <> struct Stored<uint16_t> {   // BF16 bits -> FP32
+  __device__ __forceinline__ static float at(const uint16_t* p) { return __uint_as_float((uint32_t)*p << 16); }
+};
+
+template <typename TS, typename A, int OT, int NT>
+__global__ __launch_bounds__(64) void k_fwd_cells(FwdArgs a) {
+  using M = Mfma<A>;
+  using Acc = typename M::acc;
+  constexpr int BW = 16 * OT;
+  constexpr int WS = 37;                             // weight row stride in LDS (odd: no bank conflicts)
+  __shared__ int s_p[32];
+  __shared__ A s_w[32 * WS];                         // per point: x, y, z  x  (w[4], w'[4], w''[4])
+  const int lane = (int)threadIdx.x;
+  const int grp = lane >> 4;
+  const int col = lane & 15;
+  const int n_runs = a.class_start[a.n_classes];     // every run before the non-finite points
+  const int64_t n_work = (int64_t)n_runs * a.n_groups;
+  const int nt = a.n_terms;
+  const SortedPoint<A>* pts = static_cast<const SortedPoint<A>*>(a.pts);
+  const TS* tab = static_cast<const TS*>(a.table);
+  A jm[9], mt[6];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) jm[i] = (A)a.g.jac[i];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) mt[i] = (A)a.g.metric[i];
+
+  for (int64_t w = blockIdx.x; w < n_work; w += gridDim.x) {
+    const int r = (int)(w / a.n_groups);
+    const int ob = (int)(w % a.n_groups) * BW;
+    const int64_t cell = a.uniq[r] % a.n_cells;
+    const int start = a.offsets[r];
+    const int cnt = a.counts[r];
+    const int iz0 = (int)(cell % a.g.n[2]);
+    const int iy0 = (int)((cell / a.g.n[2]) % a.g.n[1]);
+    const int ix0 = (int)(cell / ((int64_t)a.g.n[2] * a.g.n[1]));
+    int ix[4], iy[4], iz[4];
+    wrap4(ix0, a.g.n[0], ix);
+    wrap4(iy0, a.g.n[1], iy);
+    wrap4(iz0, a.g.n[2], iz);
+    bool ocol[OT];
+#pragma unroll
+    for (int ot = 0; ot < OT; ++ot) ocol[ot] = ob + ot * 16 + col < a.n_orb;
+    // the cell's block as B operands, of the orbital table and (when used) the Laplacian table
+    A b0[16][OT], b1[16][OT];
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+      const int64_t row = (int64_t)ix[ks >> 2] * a.g.s0 + (int64_t)iy[ks & 3] * a.g.s1 + (int64_t)iz[grp] * a.g.o_pad;
+#pragma unroll
+      for (int ot = 0; ot < OT; ++ot) {
+        const int64_t at = row + ob + ot * 16 + col;
+        b0[ks][ot] = ocol[ot] ? (A)Stored<TS>::at(tab + at) : A(0);
+        b1[ks][ot] = (ocol[ot] && a.use_lap_table) ? (A)Stored<TS>::at(tab + a.lap_off + at) : A(0);
+      }
+    }
+    for (int b0p = 0; b0p < cnt; b0p += 32) {
+      const int nb = min(32, cnt - b0p);
+      __syncthreads();                                   // the previous batch is written out
+      if (lane < nb) {
+        const SortedPoint<A> sp = pts[start + b0p + lane];
+        s_p[lane] = sp.p;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          A w4[4], d4[4], dd4[4];
+          bspline_weights<A>(sp.t[ax], w4, d4, dd4);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            s_w[lane * WS + 12 * ax + i] = w4[i];
+            s_w[lane * WS + 12 * ax + 4 + i] = d4[i];
+            s_w[lane * WS + 12 * ax + 8 + i] = dd4[i];
+          }
+        }
+      }
+      __syncthreads();
+      const int tiles = nb > 16 ? 2 : 1;
+      Acc acc[2][NT][OT];
+#pragma unroll
+      for (int mt_ = 0; mt_ < 2; ++mt_)
+#pragma unroll
+        for (int c = 0; c < NT; ++c)
+#pragma unroll
+          for (int ot = 0; ot < OT; ++ot) acc[mt_][c][ot] = Acc{};
+#pragma unroll
+      for (int ks = 0; ks < 16; ++ks) {
+        const int l = ks >> 2, m = ks & 3, n = grp;
+#pragma unroll
+        for (int mt_ = 0; mt_ < 2; ++mt_) {
+          if (mt_ >= tiles) break;
+          const A* wp = s_w + min(mt_ * 16 + col, nb - 1) * WS;   // points past nb multiply valid weights
+          const A wx = wp[l], dwx = wp[4 + l], d2wx = wp[8 + l];
+          const A wy = wp[12 + m], dwy = wp[16 + m], d2wy = wp[20 + m];
+          const A wz = wp[24 + n], dwz = wp[28 + n], d2wz = wp[32 + n];
+#pragma unroll
+          for (int c = 0; c < NT; ++c) {
+            if (c >= nt) break;
+            const int kind = a.kind[c];
+            A av;
+            if (kind == TERM_VAL) {
+              av = wx * wy * wz;
+            } else if (kind == TERM_LAP) {
+              av = fmaa(mt[0] * d2wx, wy * wz,
+                        fmaa(mt[1] * wx, d2wy * wz,
+                             fmaa(mt[2] * wx, wy * d2wz,
+                                  A(2) * fmaa(mt[3] * dwx, dwy * wz, fmaa(mt[4] * dwx, wy * dwz, mt[5] * wx * dwy * dwz)))));
+            } else {
+              const int k = kind - TERM_GX;
+              av = fmaa(jm[k] * dwx, wy * wz, fmaa(jm[3 + k] * wx, dwy * wz, jm[6 + k] * wx * wy * dwz));
+            }
+            const bool lt = a.src[c] != 0;
+#pragma unroll
+            for (int ot = 0; ot < OT; ++ot) acc[mt_][c][ot] = M::step(av, lt ? b1[ks][ot] : b0[ks][ot], acc[mt_][c][ot]);
+          }
+        }
+      }
+      // out[point][o]: element e of lane (grp, col) is point row(grp, e) of the tile, orbital col
+#pragma unroll
+      for (int mt_ = 0; mt_ < 2; ++mt_) {
+        if (mt_ >= tiles) break;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int j = mt_ * 16 + M::row(grp, e);
+          if (j >= nb) continue;
+          const int64_t p = s_p[j];
+#pragma unroll
+          for (int c = 0; c < NT; ++c) {
+            if (c >= nt) break;
+            A* out = static_cast<A*>(a.out[c]) + p * a.out_stride[c] + ob + col;
+#pragma unroll
+            for (int ot = 0; ot < OT; ++ot)
+              if (ocol[ot]) out[16 * ot] = acc[mt_][c][ot][e];
+          }
+        }
+      }
+    }
+  }
+}
+
+// Non-finite points (sorted last under the sentinel key) get NaN in every requested output.
+template <typename A>
+__global__ __launch_bounds__(256) void k_fwd_nan(const int64_t* keys, const int32_t* perm, int32_t n, int64_t sentinel,
+                                                 FwdArgs a) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= n || keys[i] != sentinel) return;
+  const int64_t p = perm[i];
+  const A nan = __builtin_nan("");
+  for (int c = 0; c < a.n_terms; ++c) {
+    A* out = static_cast<A*>(a.out[c]) + p * a.out_stride[c];
+    for (int o = 0; o < a.n_orb; ++o) out[o] = nan;
+  }
+}
+
+typedef void (*FwdKernel)(FwdArgs);
+
+template <typename TS, typename A>
+static FwdKernel pick_fwd(int nt) {
+  constexpr int OT = sizeof(A) == 8 ? 1 : 2;
+  return nt <= 2 ? k_fwd_cells<TS, A, OT, 2> : k_fwd_cells<TS, A, OT, 5>;
+}
+
+int cells_eval_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes) {
+  SortLayout L;
+  int rc = sort_layout(d, n_pts, &L, false);
+  if (rc) return rc;
+  *bytes = (int64_t)L.total;
+  return SPL_OK;
+}
+
+int launch_eval_cells(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, void* v, void* grad,
+                      void* lap, void* work, int64_t work_bytes, hipStream_t stream) {
+  if (n_pts == 0) return SPL_OK;
+  SortLayout L;
+  int rc = sort_layout(d, n_pts, &L, false);
+  if (rc) return rc;
+  if (!work || work_bytes < (int64_t)L.total)
+    return fail(SPL_EINVAL, "spline_eval_vgl_cells needs a workspace of %lld bytes", (long long)L.total);
+  CellSort cs;
+  if ((rc = cell_sort(d, n_pts, pos, work, L, stream, &cs))) return rc;
+  FwdArgs a;
+  memset(&a, 0, sizeof(a));
+  a.g = make_geom(d);
+  a.table = table;
+  a.lap_off = d->has_lap ? d->table_elems : 0;
+  const int64_t no = d->n_orb;
+  const size_t os = d->dtype == SPL_F64 ? 8 : 4;
+  int nt = 0;
+  auto term = [&](void* out, int64_t stride, int kind, int src) {
+    a.out[nt] = out;
+    a.out_stride[nt] = stride;
+    a.kind[nt] = kind;
+    a.src[nt] = src;
+    ++nt;
+  };
+  if (v) term(v, no, TERM_VAL, 0);
+  if (grad) {
+    char* gb = static_cast<char*>(grad);
+    term(gb, 3 * no, TERM_GX, 0);
+    term(gb + no * os, 3 * no, TERM_GY, 0);
+    term(gb + 2 * no * os, 3 * no, TERM_GZ, 0);
+  }
+  if (lap) {
+    if (d->has_lap) term(lap, no, TERM_VAL, 1);
+    else term(lap, no, TERM_LAP, 0);
+  }
+  a.n_terms = nt;
+  a.use_lap_table = d->has_lap && lap;
+  a.uniq = cs.uniq;
+  a.counts = cs.counts;
+  a.offsets = cs.offsets;
+  a.pts = cs.pts;
+  a.class_start = cs.class_start;
+  a.n_cells = L.n_cells;
+  a.n_classes = L.n_classes;
+  a.n_orb = d->n_orb;
+  const int ot = d->dtype == SPL_F64 ? 1 : 2;
+  a.n_groups = (d->n_orb + 16 * ot - 1) / (16 * ot);
+  FwdKernel k;
+  if (d->dtype == SPL_F64) k = pick_fwd<double, double>(nt);
+  else if (d->dtype == SPL_F32) k = pick_fwd<float, float>(nt);
+  else k = pick_fwd<uint16_t, float>(nt);
+  const int grid = (int)std::min<int64_t>(std::min<int64_t>(n_pts, L.n_cells) * a.n_groups, 1 << 16);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, stream, a);
+  if ((rc = hip_fail(hipGetLastError(), "cell forward launch"))) return rc;
+  const int n = (int)n_pts;
+  if (d->dtype == SPL_F64)
+    hipLaunchKernelGGL(k_fwd_nan<double>, dim3((n + 255) / 256), dim3(256), 0, stream, cs.keys, cs.perm, n,
+                       (int64_t)L.n_classes * L.n_cells, a);
+  else
+    hipLaunchKernelGGL(k_fwd_nan<float>, dim3((n + 255) / 256), dim3(256), 0, stream, cs.keys, cs.perm, n,
+                       (int64_t)L.n_classes * L.n_cells, a);
+  return hip_fail(hipGetLastError(), "non-finite point launch");
 }
 
 }  // namespace pws

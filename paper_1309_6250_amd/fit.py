@@ -10,8 +10,8 @@ with wV = 1 / mean V_t^2 and wL = 1 / mean lap_t^2 (or 0), periodic second diffe
 by Adam.  Two forms of the same loss:
 
 - FitProblem.loss_and_grad, used by fit_adam: every term runs in the library's kernels (the
-  locality-ordered forward, spline_misfit on V and on lap, which forms the upstream gradients in
-  place and sums the squared residuals in FP64 in a fixed order, the adjoint, and
+  cell-wise forward of V and lap only, spline_misfit on each, which forms the upstream gradients
+  in place and sums the squared residuals in FP64 in a fixed order, the adjoint, and
   spline_smoothness_penalty on the table); only the Adam update is a tensor operation.  Buffers
   are allocated once.
 - make_loss, a differentiable function of the table built on SplineVGL, for use inside a
@@ -21,8 +21,8 @@ by Adam.  Two forms of the same loss:
 import torch
 
 from ._lib import SPL_DETERMINISTIC
-from .api import (OUT_TORCH, new_gtable, spline_eval_vgl_backward, spline_eval_vgl_sorted, spline_misfit,
-                  spline_misfit_work_bytes, spline_smoothness_penalty, spline_sorted_work_bytes,
+from .api import (OUT_TORCH, new_gtable, spline_eval_vgl_backward, spline_eval_vgl_cells, spline_misfit,
+                  spline_misfit_work_bytes, spline_smoothness_penalty, spline_cells_work_bytes,
                   spline_backward_work_bytes)
 from .autograd import SplineVGL
 
@@ -88,11 +88,10 @@ class FitProblem:
         self.v_t = v_t.to(od).contiguous()
         self.lap_t = lap_t.to(od).contiguous()
         self.v = torch.empty((n, o), dtype=od, device=dev)
-        self.grad = torch.empty((n, 3, o), dtype=od, device=dev)
         self.lap = torch.empty((n, o), dtype=od, device=dev)
         self.gtable = new_gtable(desc, dev)
         self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
-        self.sort_work = torch.empty(max(1, spline_sorted_work_bytes(desc, n)), dtype=torch.uint8, device=dev)
+        self.cells_work = torch.empty(max(1, spline_cells_work_bytes(desc, n)), dtype=torch.uint8, device=dev)
         self.misfit_work = torch.empty(spline_misfit_work_bytes(desc, n * o), dtype=torch.uint8, device=dev)
         self.bwd_work = torch.empty(max(1, spline_backward_work_bytes(desc, n, self.flags)), dtype=torch.uint8,
                                     device=dev)
@@ -100,7 +99,8 @@ class FitProblem:
     def loss_and_grad(self, beta):
         d = self.desc
         self.loss.zero_()
-        spline_eval_vgl_sorted(d, beta, self.pos, self.v, self.grad, self.lap, work=self.sort_work)
+        spline_eval_vgl_cells(d, beta, self.pos, self.v, None, self.lap if self.use_lap else None,
+                              outputs="vl" if self.use_lap else "v", work=self.cells_work)
         gv = spline_misfit(d, self.v, self.v_t, self.w_v, self.loss, g=self.v, work=self.misfit_work)
         gl = None
         if self.use_lap:

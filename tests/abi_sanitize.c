@@ -128,6 +128,14 @@ int main(void) {
   expect(spline_eval_vgl_sorted(&d, NULL, 0, NULL, NULL, NULL, NULL, NULL, NULL, 0, NULL), SPL_OK, "sorted n == 0");
   expect(spline_sorted_work_bytes(&d, 0, &bytes), SPL_OK, "sorted work bytes");
 
+  /* cell-wise forward */
+  expect(spline_cells_work_bytes(&d, 0, &bytes), SPL_OK, "cells work bytes");
+  expect(spline_eval_vgl_cells(&d, fake, 10, fpos, NULL, NULL, NULL, fake, 1 << 20, NULL), SPL_EINVAL,
+         "cells no output");
+  expect(spline_eval_vgl_cells(&d, fake, 10, fpos, fake, NULL, NULL, NULL, 0, NULL), SPL_EINVAL, "cells NULL work");
+  expect(spline_eval_vgl_cells(&dp, fake, 10, fpos, fake, NULL, NULL, fake, 1 << 20, NULL), SPL_EUNSUPPORTED,
+         "cells pp");
+
   /* build */
   expect(spline_build(&d, fake, fake, fake, fake, NULL), SPL_EINVAL, "build lap values without lap table");
   expect(spline_build(&d32, fake, NULL, fake, fake, NULL), SPL_EINVAL, "build lap table without values");

@@ -340,3 +340,24 @@ def test_smoothness_penalty_validates_before_any_launch():
     dp = P.spline_desc_init(LAT, (8, 8, 8), 4, "f32", basis="pp")
     assert lib.spline_smoothness_penalty(ctypes.byref(dp), fake, 1.0, fake, fake, fake, w,
                                          None) == P.SPL_EUNSUPPORTED
+
+
+def test_cells_forward_validates_before_any_launch():
+    fake = ctypes.c_void_p(256)
+    lib = P.lib()
+    d = P.spline_desc_init(LAT, (8, 8, 8), 4, "f32")
+    ref = ctypes.byref(d)
+    nb = ctypes.c_int64(-1)
+    assert lib.spline_cells_work_bytes(ref, 0, ctypes.byref(nb)) == P.SPL_OK and nb.value == 0
+    assert lib.spline_cells_work_bytes(ref, -1, ctypes.byref(nb)) == P.SPL_EINVAL
+    assert lib.spline_eval_vgl_cells(ref, None, 0, None, None, None, None, None, 0, None) == P.SPL_OK
+    assert lib.spline_eval_vgl_cells(ref, fake, 10, fake, None, None, None, fake, 1 << 20, None) == P.SPL_EINVAL
+    assert b"no output" in lib.spline_last_error()
+    assert lib.spline_eval_vgl_cells(ref, fake, 10, fake, fake, None, None, None, 0, None) == P.SPL_EINVAL
+    assert lib.spline_eval_vgl_cells(ref, fake, 10, fake, fake, None, None, ctypes.c_void_p(264), 1 << 20,
+                                     None) == P.SPL_EINVAL
+    assert lib.spline_eval_vgl_cells(ref, fake, 10, fake, ctypes.c_void_p(258), None, None, fake, 1 << 20,
+                                     None) == P.SPL_EINVAL
+    dp = P.spline_desc_init(LAT, (8, 8, 8), 4, "f32", basis="pp")
+    assert lib.spline_eval_vgl_cells(ctypes.byref(dp), fake, 10, fake, fake, None, None, fake, 1 << 20,
+                                     None) == P.SPL_EUNSUPPORTED

@@ -28,8 +28,11 @@ def _run(cmd, **kw):
 
 @pytest.mark.timeout(600)
 def test_validation_paths_clean_under_host_sanitizers(tmp_path):
-    objs = [o for o in glob.glob(os.path.join(PKG, "_build", "*.o"))
-            if os.path.basename(o)[:-len(".o")] not in UNITS]
+    sources = {os.path.basename(f) for f in glob.glob(os.path.join(PKG, "csrc", "*.hip"))}
+    objs = [os.path.join(PKG, "_build", f + ".o") for f in sorted(sources - set(UNITS))]
+    objs = [o for o in objs if os.path.exists(o)]
+    if len(objs) != len(sources) - len(UNITS):
+        objs = []
     runtime = glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so")
     if not objs or not shutil.which(HIPCC) or not os.path.exists(CLANG) or not runtime:
         pytest.skip("needs the built library objects, hipcc, clang and its ASan runtime")

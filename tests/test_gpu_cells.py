@@ -1,0 +1,87 @@
+"""spline_eval_vgl_cells: the forward evaluation cell by cell on the matrix cores, against the
+per-point kernel (spline_eval_vgl) and the FP64 oracle, on dense and sparse point sets."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1309_6250_amd as P
+from oracle import evaluate as oeval, quantize as oq
+from workloads import config
+from gpu_helpers import say, to_dev, table_from_oracle, normwise, DEV
+
+pytestmark = pytest.mark.gpu
+
+SKEW = np.array([[7.0, 0.4, -0.3], [1.1, 6.2, 0.5], [-0.6, 0.9, 8.3]])
+TOL = {"f64": 1e-12, "f32": 3e-6, "bf16": 3e-6}      # against the per-point kernel (other summation order)
+
+
+def _case(grid, n_orb, n, dtype, has_lap, seed):
+    rng = np.random.default_rng(seed)
+    beta = rng.standard_normal(grid + (n_orb,))
+    lbeta = rng.standard_normal(grid + (n_orb,)) if has_lap else None
+    d = P.spline_desc_init(SKEW, grid, n_orb, dtype, has_lap=has_lap)
+    tab = table_from_oracle(d, beta, dtype, lbeta)
+    pos = rng.uniform(-1.5, 1.5, size=(n, 3)) @ SKEW
+    return d, tab, pos, beta, lbeta
+
+
+@pytest.mark.parametrize("has_lap", [False, True], ids=["lap-from-derivatives", "lap-table"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("shape", [((6, 5, 7), 37, 2000), ((16, 16, 16), 20, 300)], ids=["dense", "sparse"])
+def test_cells_match_per_point_kernel(shape, dtype, has_lap):
+    grid, n_orb, n = shape
+    d, tab, pos, _, _ = _case(grid, n_orb, n, dtype, has_lap, 110)
+    pos[5] = np.nan
+    pos[n - 3] = [1e300, 0.0, 0.0]
+    x = to_dev(pos)
+    say("cells forward", grid, n_orb, n, dtype, has_lap)
+    rv, rg, rl = P.spline_eval_vgl(d, tab, x)
+    v, g, l = P.spline_eval_vgl_cells(d, tab, x)
+    torch.cuda.synchronize()
+    bad = ~np.all(np.isfinite(pos), axis=1)      # a huge finite coordinate folds into the cell like any other
+    for got, ref in ((v, rv), (g, rg), (l, rl)):
+        got, ref = got.double().cpu().numpy(), ref.double().cpu().numpy()
+        assert np.isnan(got[bad]).all()
+        assert normwise(got[~bad], ref[~bad]) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("outputs", ["v", "l", "vl", "g"])
+def test_cells_skip_outputs(outputs):
+    d, tab, pos, _, _ = _case((6, 5, 7), 37, 1500, "f32", False, 111)
+    x = to_dev(pos)
+    say("cells forward, outputs", outputs)
+    rv, rg, rl = P.spline_eval_vgl(d, tab, x)
+    v, g, l = P.spline_eval_vgl_cells(d, tab, x, outputs=outputs)
+    torch.cuda.synchronize()
+    for key, got, ref in (("v", v, rv), ("g", g, rg), ("l", l, rl)):
+        if key in outputs:
+            assert normwise(got.double().cpu().numpy(), ref.double().cpu().numpy()) <= TOL["f32"]
+        else:
+            assert got is None
+
+
+def test_cells_match_oracle():
+    d, tab, pos, beta, _ = _case((6, 5, 7), 37, 1200, "f64", False, 112)
+    say("cells forward against the oracle")
+    v, g, l = P.spline_eval_vgl_cells(d, tab, to_dev(pos))
+    torch.cuda.synchronize()
+    ov, og, ol = oeval.eval_vgl(beta, SKEW, pos)
+    assert normwise(v.cpu().numpy(), ov) < 1e-12
+    assert normwise(g.cpu().numpy(), og) < 1e-12
+    assert normwise(l.cpu().numpy(), ol) < 1e-12
+
+
+@pytest.mark.timeout(600)
+def test_cells_at_fit_size():
+    """10^6 points in 32^3 cells (FP32): value and Laplacian against the per-point kernel."""
+    w = config(4)
+    s = w.system
+    x = to_dev(w.positions())
+    d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, "f32")
+    tab = P.spline_build(d, to_dev(s.grid_values()))
+    say("cells forward at 1e6 points")
+    v, _, l = P.spline_eval_vgl_cells(d, tab, x, outputs="vl")
+    rv, _, rl = P.spline_eval_vgl(d, tab, x)
+    torch.cuda.synchronize()
+    assert normwise(v.double().cpu().numpy(), rv.double().cpu().numpy()) < 3e-6
+    assert normwise(l.double().cpu().numpy(), rl.double().cpu().numpy()) < 3e-6

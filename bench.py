@@ -487,6 +487,19 @@ def fit_rows(steps, warmup, adam_steps=50):
                                                               flags=flags), max(3, steps // 4), 1)
         out[f"spline_eval_vgl_backward_fit_{name}"] = {
             "ms": ms, "evals_per_s": n * s.n_orb / (ms * 1e-3), "points": n, "n_orb": s.n_orb, "grid": list(s.grid)}
+    # the forward on the fit's dense points: per-point kernel (sorted call) against the cell-wise one
+    cw = torch.empty(max(1, P.spline_cells_work_bytes(d, n)), dtype=torch.uint8, device="cuda")
+    sw = torch.empty(max(1, P.spline_sorted_work_bytes(d, n)), dtype=torch.uint8, device="cuda")
+    outs = P.spline_eval_vgl(d, table, pos)
+    ms_sorted = time_launches(lambda: P.spline_eval_vgl_sorted(d, table, pos, *outs, work=sw), max(3, steps // 4), 1)
+    ms_vgl = time_launches(lambda: P.spline_eval_vgl_cells(d, table, pos, *outs, work=cw), max(3, steps // 4), 1)
+    ms_vl = time_launches(lambda: P.spline_eval_vgl_cells(d, table, pos, outs[0], None, outs[2], outputs="vl",
+                                                          work=cw), max(3, steps // 4), 1)
+    out["spline_eval_vgl_cells_fit_f32"] = {
+        "ms_vl": ms_vl, "ms_vgl": ms_vgl, "ms_sorted_per_point_vgl": ms_sorted,
+        "evals_per_s_vl": n * s.n_orb / (ms_vl * 1e-3), "points": n, "n_orb": s.n_orb, "grid": list(s.grid),
+        "note": "matrix-core products of each cell's block with its points' row weights (30 points per cell)"}
+    del outs, sw
     v_t, lap_t = planewave_targets_gpu(s, pos)
     # the misfit kernel alone: one pass over outputs and targets (12 B per FP32 value)
     od = P.OUT_TORCH[d.dtype]

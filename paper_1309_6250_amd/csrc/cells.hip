@@ -811,11 +811,15 @@ __global__ __launch_bounds__(256) void k_fwd_nan(const int64_t* keys, const int3
 
 typedef void (*FwdKernel)(FwdArgs);
 
+// FP32 with at most two terms: two orbital tiles per wave; otherwise one (accumulator registers)
 template <typename TS, typename A>
 static FwdKernel pick_fwd(int nt) {
-  constexpr int OT = sizeof(A) == 8 ? 1 : 2;
-  return nt <= 2 ? k_fwd_cells<TS, A, OT, 2> : k_fwd_cells<TS, A, OT, 5>;
+  if constexpr (sizeof(A) == 4)
+    if (nt <= 2) return k_fwd_cells<TS, A, 2, 2>;
+  return nt <= 2 ? k_fwd_cells<TS, A, 1, 2> : k_fwd_cells<TS, A, 1, 5>;
 }
+
+static int fwd_tiles(int dtype, int nt) { return dtype != SPL_F64 && nt <= 2 ? 2 : 1; }
 
 int cells_eval_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes) {
   SortLayout L;
@@ -871,7 +875,7 @@ int launch_eval_cells(const spl_desc* d, const void* table, int64_t n_pts, const
   a.n_cells = L.n_cells;
   a.n_classes = L.n_classes;
   a.n_orb = d->n_orb;
-  const int ot = d->dtype == SPL_F64 ? 1 : 2;
+  const int ot = fwd_tiles(d->dtype, nt);
   a.n_groups = (d->n_orb + 16 * ot - 1) / (16 * ot);
   FwdKernel k;
   if (d->dtype == SPL_F64) k = pick_fwd<double, double>(nt);

@@ -740,35 +740,48 @@ __global__ __launch_bounds__(64) void k_fwd_cells(FwdArgs a) {
         for (int c = 0; c < NT; ++c)
 #pragma unroll
           for (int ot = 0; ot < OT; ++ot) acc[mt_][c][ot] = Acc{};
+      // row (l, m, n) of k-step 4 l + m, lane group n: per point and m each term's weight is
+      // Q2 w_x''[l] + Q1 w_x'[l] + Q0 w_x[l], with Q0..Q2 from the y and z weights (as in the adjoint)
 #pragma unroll
-      for (int ks = 0; ks < 16; ++ks) {
-        const int l = ks >> 2, m = ks & 3, n = grp;
+      for (int mt_ = 0; mt_ < 2; ++mt_) {
+        if (mt_ >= tiles) break;
+        const A* wp = s_w + min(mt_ * 16 + col, nb - 1) * WS;     // points past nb multiply valid weights
+        A wx[4], dwx[4], d2wx[4];
 #pragma unroll
-        for (int mt_ = 0; mt_ < 2; ++mt_) {
-          if (mt_ >= tiles) break;
-          const A* wp = s_w + min(mt_ * 16 + col, nb - 1) * WS;   // points past nb multiply valid weights
-          const A wx = wp[l], dwx = wp[4 + l], d2wx = wp[8 + l];
+        for (int i = 0; i < 4; ++i) {
+          wx[i] = wp[i];
+          dwx[i] = wp[4 + i];
+          d2wx[i] = wp[8 + i];
+        }
+        const A wz = wp[24 + grp], dwz = wp[28 + grp], d2wz = wp[32 + grp];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
           const A wy = wp[12 + m], dwy = wp[16 + m], d2wy = wp[20 + m];
-          const A wz = wp[24 + n], dwz = wp[28 + n], d2wz = wp[32 + n];
+          const A yz = wy * wz;
 #pragma unroll
           for (int c = 0; c < NT; ++c) {
             if (c >= nt) break;
             const int kind = a.kind[c];
-            A av;
+            A q0, q1 = A(0), q2 = A(0);
             if (kind == TERM_VAL) {
-              av = wx * wy * wz;
+              q0 = yz;
             } else if (kind == TERM_LAP) {
-              av = fmaa(mt[0] * d2wx, wy * wz,
-                        fmaa(mt[1] * wx, d2wy * wz,
-                             fmaa(mt[2] * wx, wy * d2wz,
-                                  A(2) * fmaa(mt[3] * dwx, dwy * wz, fmaa(mt[4] * dwx, wy * dwz, mt[5] * wx * dwy * dwz)))));
+              q2 = mt[0] * yz;
+              q1 = A(2) * fmaa(mt[3] * dwy, wz, mt[4] * wy * dwz);
+              q0 = fmaa(mt[1] * d2wy, wz, fmaa(mt[2] * wy, d2wz, A(2) * mt[5] * dwy * dwz));
             } else {
               const int k = kind - TERM_GX;
-              av = fmaa(jm[k] * dwx, wy * wz, fmaa(jm[3 + k] * wx, dwy * wz, jm[6 + k] * wx * wy * dwz));
+              q1 = jm[k] * yz;
+              q0 = fmaa(jm[3 + k] * dwy, wz, jm[6 + k] * wy * dwz);
             }
             const bool lt = a.src[c] != 0;
 #pragma unroll
-            for (int ot = 0; ot < OT; ++ot) acc[mt_][c][ot] = M::step(av, lt ? b1[ks][ot] : b0[ks][ot], acc[mt_][c][ot]);
+            for (int l = 0; l < 4; ++l) {
+              const A av = fmaa(q2, d2wx[l], fmaa(q1, dwx[l], q0 * wx[l]));
+#pragma unroll
+              for (int ot = 0; ot < OT; ++ot)
+                acc[mt_][c][ot] = M::step(av, lt ? b1[4 * l + m][ot] : b0[4 * l + m][ot], acc[mt_][c][ot]);
+            }
           }
         }
       }

@@ -20,10 +20,13 @@ import numpy as np
 
 
 def gamma_axis(theta):
-    """(2/3) * 3 [3 - 4 cos(theta) + cos(2 theta)] / theta^4, with its limit 1 at theta = 0."""
+    """(2/3) * 24 sin^4(theta/2) / theta^4 (the paper's second printed form), with its limit 1 at
+    theta = 0.  The first form, 3 [3 - 4 cos theta + cos 2 theta] / theta^4, is the same number
+    (3 - 4 cos theta + cos 2 theta = 8 sin^4(theta/2)) but its numerator cancels: about
+    1e-16 / theta^4 relative error, 1e-10 for the first harmonic of a 200-point axis."""
     theta = np.asarray(theta, dtype=np.float64)
     safe = np.where(theta == 0.0, 1.0, theta)
-    val = (2.0 / 3.0) * 3.0 * (3.0 - 4.0 * np.cos(safe) + np.cos(2.0 * safe)) / safe**4
+    val = (2.0 / 3.0) * 24.0 * (np.sin(0.5 * safe) / safe) ** 4
     return np.where(theta == 0.0, 1.0, val)
 
 

@@ -59,6 +59,17 @@ def test_gamma_printed_forms_agree_and_limit():
     assert smoothing.gamma_axis(np.array([0.0]))[0] == 1.0
 
 
+def test_gamma_accurate_for_long_axes():
+    """First harmonics of long axes (theta = 2 pi / N, N up to 1024): gamma_axis against the Taylor
+    series of sinc^4(theta/2), sinc(x) = sum_k (-1)^k x^2k / (2k+1)!, to rounding."""
+    from math import factorial
+    for n in (24, 96, 200, 1024):
+        theta = 2.0 * np.pi / n
+        x = theta / 2.0
+        sinc = sum((-1) ** k * x ** (2 * k) / factorial(2 * k + 1) for k in range(8))
+        assert abs(smoothing.gamma_axis(np.array([theta]))[0] - sinc ** 4) <= 2e-15   # the cos form: 2e-14 at N = 24
+
+
 def test_smoothing_fourier_components_match_planewave():
     # fundamental Fourier component of the smoothing spline at G, by Gauss-Legendre quadrature of
     # phi(r) exp(-i G.r) over the cell (exact to rounding: smooth integrand per grid cell)

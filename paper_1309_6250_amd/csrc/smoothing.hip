@@ -156,6 +156,89 @@ __global__ __launch_bounds__(256) void k_idft_axis(DftArgs a) {
   }
 }
 
+// The same stage as a matrix product on the FP64 matrix cores: along the axis, Y = W X with
+// W[k][j] = exp(+2 pi i j k / n) and X the n samples of each line.  One wave owns 16 whole lines
+// (so the in-place update is safe): it stages their samples in LDS, then forms each tile of 16
+// outputs x 16 lines with 16x16x4 steps over j, four real products per step (complex multiply).
+typedef double f64x4_s __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f64x4_s mfma64(double a, double b, f64x4_s c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int OUT>
+__global__ __launch_bounds__(64) void k_idft_mfma(DftArgs a) {
+  extern __shared__ double lds_raw[];
+  const int n = a.n;
+  const int n_pad = (n + 3) & ~3;
+  double* tw_c = lds_raw;                 // [n]
+  double* tw_s = lds_raw + n;             // [n]
+  double* xr = lds_raw + 2 * n;           // [n_pad][16] real parts of the 16 lines
+  double* xi = xr + 16 * n_pad;           // imaginary parts
+  const int lane = (int)threadIdx.x;
+  const int grp = lane >> 4, col = lane & 15;
+  for (int k = lane; k < n; k += 64) {
+    tw_c[k] = a.cs[k];
+    tw_s[k] = a.sn[k];
+  }
+  const int64_t line0 = (int64_t)blockIdx.x * 16;
+  for (int e = lane; e < 16 * n_pad; e += 64) {
+    const int j = e >> 4, c = e & 15;
+    const int64_t line = line0 + c;
+    c2v v{0.0, 0.0};
+    if (j < n && line < a.n_lines) {
+      const int64_t outer = line / a.inner;
+      v = a.data[outer * (int64_t)n * a.inner + (line - outer * a.inner) + (int64_t)j * a.inner];
+    }
+    xr[e] = v.x;
+    xi[e] = v.y;
+  }
+  __syncthreads();
+  // this lane's output line (column of the result tile)
+  const int64_t line = line0 + col;
+  const bool line_ok = line < a.n_lines;
+  const int64_t outer = line_ok ? line / a.inner : 0;
+  const int64_t in = line_ok ? line - outer * a.inner : 0;
+  const int64_t base = outer * (int64_t)n * a.inner + in;
+  for (int k0 = 0; k0 < n; k0 += 16) {
+    f64x4_s acc_r = {0.0, 0.0, 0.0, 0.0}, acc_i = {0.0, 0.0, 0.0, 0.0};
+    const int kk = k0 + col;              // A row: output index (past n: any finite value, not written)
+    for (int j0 = 0; j0 < n_pad; j0 += 4) {
+      const int j = j0 + grp;             // A column / B row: sample index (past n: X is zero)
+      const int idx = (int)(((int64_t)kk * j) % n);
+      const double c = tw_c[idx], sn = tw_s[idx];
+      const double br = xr[j * 16 + col], bi = xi[j * 16 + col];
+      acc_r = mfma64(c, br, acc_r);
+      acc_r = mfma64(-sn, bi, acc_r);
+      acc_i = mfma64(sn, br, acc_i);
+      acc_i = mfma64(c, bi, acc_i);
+    }
+    if (!line_ok) continue;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = k0 + grp + 4 * e;     // FP64 result layout: row grp + 4 e, column col
+      if (k >= n) continue;
+      const double re = acc_r[e], im = acc_i[e];
+      if constexpr (OUT == DFT_INPLACE) {
+        a.data[base + (int64_t)k * a.inner] = c2v{re, im};
+      } else {
+        const int64_t row = (outer * (int64_t)n + k) * a.o_pad;      // inner == n_orb here
+        const int64_t t = a.bloch ? row + 2 * in : row + in;
+        if constexpr (OUT == DFT_TABLE_F64) {
+          static_cast<double*>(a.table)[t] = re;
+          if (a.bloch) static_cast<double*>(a.table)[t + 1] = im;
+        } else if constexpr (OUT == DFT_TABLE_F32) {
+          static_cast<float*>(a.table)[t] = (float)re;
+          if (a.bloch) static_cast<float*>(a.table)[t + 1] = (float)im;
+        } else {
+          static_cast<uint16_t*>(a.table)[t] = f32_to_bf16_rne_s((float)re);
+          if (a.bloch) static_cast<uint16_t*>(a.table)[t + 1] = f32_to_bf16_rne_s((float)im);
+        }
+      }
+    }
+  }
+}
+
 template <typename TS>
 __global__ __launch_bounds__(256) void k_zero_pad_s(TS* table, int64_t n_rows, int32_t n_col, int32_t o_pad) {
   const int32_t width = o_pad - n_col;
@@ -185,6 +268,18 @@ static int launch_idft(int out, c2v* data, void* table, const double* cs, const 
   a.n = n;
   a.o_pad = o_pad;
   a.bloch = bloch;
+  if (n <= 192) {
+    // matrix-core form: 16 lines per wave, staged samples and twiddles in LDS (at most 52 KB)
+    const size_t shm = (size_t)(2 * n + 32 * ((n + 3) & ~3)) * sizeof(double);
+    const dim3 g((unsigned)((a.n_lines + 15) / 16));
+    switch (out) {
+      case DFT_INPLACE: hipLaunchKernelGGL(k_idft_mfma<DFT_INPLACE>, g, dim3(64), shm, stream, a); break;
+      case DFT_TABLE_F64: hipLaunchKernelGGL(k_idft_mfma<DFT_TABLE_F64>, g, dim3(64), shm, stream, a); break;
+      case DFT_TABLE_F32: hipLaunchKernelGGL(k_idft_mfma<DFT_TABLE_F32>, g, dim3(64), shm, stream, a); break;
+      default: hipLaunchKernelGGL(k_idft_mfma<DFT_TABLE_BF16>, g, dim3(64), shm, stream, a); break;
+    }
+    return hip_fail(hipGetLastError(), "inverse DFT launch");
+  }
   const int tile = dft_tile(n);
   const size_t shmem = (size_t)tile * n * 16 + (size_t)n * 16;
   const dim3 grid((unsigned)((a.n_lines + tile - 1) / tile));

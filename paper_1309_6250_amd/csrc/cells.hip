@@ -1,22 +1,30 @@
-// Deterministic coefficient gradient of spline_eval_vgl_backward (flag SPL_DETERMINISTIC).
-//
-// The gradient of a coefficient is a sum over every point whose 4x4x4 block contains it.
-// Float atomics make the order of that sum, and so its rounding, depend on scheduling.  Here:
+// Work on the points grouped by grid cell: the deterministic coefficient gradient of
+// spline_eval_vgl_backward (flag SPL_DETERMINISTIC) and the cell-wise forward evaluation
+// spline_eval_vgl_cells.  Both start from the same sort:
 //
 //  1. every point gets the key (colour class, cell) of the grid cell it falls in; points with
 //     non-finite coordinates get a key past all classes;
-//  2. a stable radix sort orders points by key (then by index), and a run-length encoding
-//     lists the occupied cells with the range of their points;
-//  3. for each colour class in turn, one wave per (cell, orbital group) forms the contributions
-//     of all of the cell's points to its 64 rows as a matrix product on the matrix cores, in
-//     point order, then adds them to the gradient table with ordinary loads and stores.
+//  2. a stable radix sort orders points by key (then by index), a run-length encoding lists the
+//     occupied cells with the range of their points, and each sorted point gets a record of its
+//     reduced coordinates and index.
 //
-// Colour classes: along an axis of N cells, cell i has colour i mod 4 when i < 4 floor(N/4), and
-// a colour of its own (4, 5, 6) for the last N mod 4 cells.  Two cells of one class are at least
-// 4 apart along every axis, also across the periodic wrap, so their blocks (rows i-1 .. i+2) are
-// disjoint: within a class no two waves touch the same row, and classes run one after the
-// other.  The result is bitwise reproducible, and each row is written once per occupied cell
-// rather than once per point.
+// Summed over the points of one cell, both directions are dense products between the cell's 64
+// block rows and its points (row weights from the 1-D B-spline weights), done on the matrix cores.
+//
+// Adjoint.  The gradient of a coefficient is a sum over every point whose 4x4x4 block contains it;
+// float atomics would make its order, and so its rounding, depend on scheduling.  Here each cell's
+// block is formed in point order and then added to the table either
+//  - colour class by colour class: along an axis of N cells, cell i has colour i mod 4 when
+//    i < 4 floor(N/4), and a colour of its own (4, 5, 6) for the last N mod 4 cells.  Two cells
+//    of one class are at least 4 apart along every axis, also across the periodic wrap, so
+//    their blocks (rows i-1 .. i+2) are disjoint: within a class no two waves touch the same
+//    row, and classes run one after the other; or
+//  - with 4 or more points per cell, all cells at once into the workspace, followed by a gather
+//    in which every table row sums the blocks that contain it in a fixed order.
+// Either way the result is reproducible bit for bit.
+//
+// Forward.  A wave loads a cell's block once and multiplies it with the row weights of the
+// cell's points, so each block row is read once per cell instead of once per point.
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>

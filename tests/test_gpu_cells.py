@@ -85,3 +85,36 @@ def test_cells_at_fit_size():
     torch.cuda.synchronize()
     assert normwise(v.double().cpu().numpy(), rv.double().cpu().numpy()) < 3e-6
     assert normwise(l.double().cpu().numpy(), rl.double().cpu().numpy()) < 3e-6
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_cells_smallest_grid_and_all_nonfinite(dtype):
+    """N = 4 along two axes (a cell's block then covers the whole axis): cell-wise forward against
+    the per-point kernel and the oracle; the deterministic adjoint's dense form against the oracle;
+    a call whose points are all non-finite gives NaN everywhere and adds nothing."""
+    from oracle import adjoint as oadj
+    d, tab, pos, beta, _ = _case((4, 5, 4), 9, 800, dtype, False, 113)
+    x = to_dev(pos)
+    say("cells on a 4x5x4 grid", dtype)
+    rv, rg, rl = P.spline_eval_vgl(d, tab, x)
+    v, g, l = P.spline_eval_vgl_cells(d, tab, x)
+    torch.cuda.synchronize()
+    for got, ref in ((v, rv), (g, rg), (l, rl)):
+        assert normwise(got.double().cpu().numpy(), ref.double().cpu().numpy()) <= TOL[dtype]
+    if dtype == "f64":
+        ov, og, ol = oeval.eval_vgl(beta, SKEW, pos)
+        assert normwise(v.cpu().numpy(), ov) < 1e-12 and normwise(l.cpu().numpy(), ol) < 1e-12
+    rng = np.random.default_rng(114)
+    gv = rng.standard_normal((pos.shape[0], 9))
+    od = torch.float64 if dtype == "f64" else torch.float32
+    gt, _ = P.spline_eval_vgl_backward(d, tab, x, to_dev(gv, od), want_pos=False, flags=P.SPL_DETERMINISTIC)
+    torch.cuda.synchronize()
+    rb, _, _ = oadj.vgl_backward(oq.quantized(beta, dtype), SKEW, pos, gv)
+    assert normwise(gt.double().cpu().numpy()[0, ..., :9], rb) <= (1e-12 if dtype == "f64" else 2e-5)
+    bad = to_dev(np.full((50, 3), np.nan))
+    v, g, l = P.spline_eval_vgl_cells(d, tab, bad)
+    gt, _ = P.spline_eval_vgl_backward(d, tab, bad, torch.ones((50, 9), dtype=od, device=DEV), want_pos=False,
+                                       flags=P.SPL_DETERMINISTIC)
+    torch.cuda.synchronize()
+    assert torch.isnan(v).all() and torch.isnan(g).all() and torch.isnan(l).all()
+    assert torch.count_nonzero(gt) == 0

@@ -70,8 +70,15 @@ enum {
   SPL_EUNSUPPORTED = -6  /* valid request that this build does not implement */
 };
 
-/* flags of spline_eval_vgl_backward */
-enum { SPL_DETERMINISTIC = 1 };
+/* flags of spline_eval_vgl_backward (and SPL_REUSE_SORT of spline_eval_vgl_cells) */
+enum {
+  SPL_DETERMINISTIC = 1,  /* cell-sorted, bitwise-reproducible coefficient gradient */
+  SPL_REUSE_SORT = 2      /* the workspace already holds the cell sort of these same points (same
+                             descriptor, n_pts and pos), made by an earlier spline_eval_vgl_cells or
+                             deterministic spline_eval_vgl_backward call: skip sorting.  A workspace
+                             that holds something else gives wrong results, never an access outside
+                             the caller's arrays (every index read from it is bounded) */
+};
 
 /* basis of the interpolant (spl_desc.basis) */
 enum { SPL_BSPLINE = 0, SPL_LAGRANGE = 1, SPL_PPSPLINE = 2 };
@@ -255,13 +262,15 @@ int spline_sorted_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes);
  * point sets with several points per cell (fits, dense sampling); QMC walkers rarely share cells.
  * The outputs equal spline_eval_vgl's up to the order of summation, in the caller's point order.
  *   v, grad, lap  device, as for spline_eval_vgl; each may be NULL to skip it (not all three)
- *   work          device workspace, 256-byte aligned, at least spline_cells_work_bytes() bytes,
- *                 contents undefined afterwards
+ *   flags         0 or SPL_REUSE_SORT
+ *   work          device workspace, 256-byte aligned, at least spline_cells_work_bytes() bytes; it
+ *                 holds the cell sort afterwards (a deterministic spline_eval_vgl_backward of the same
+ *                 points may reuse it, given spline_backward_work_bytes() bytes)
  * Non-finite points get NaN.  Real B-spline tables only (with or without a separate Laplacian
  * table); other descriptors -> SPL_EUNSUPPORTED.  Allocates nothing.
  */
 int spline_eval_vgl_cells(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, void* v,
-                          void* grad, void* lap, void* work, int64_t work_bytes, void* stream);
+                          void* grad, void* lap, int32_t flags, void* work, int64_t work_bytes, void* stream);
 
 /* Workspace bytes of spline_eval_vgl_cells for n_pts points (the sort's keys, runs and point
  * records).  Host only; may query the current HIP device. */
@@ -284,8 +293,10 @@ int spline_cells_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes);
  *                    stores (cells of one class have disjoint blocks) or, at 4 or more points
  *                    per cell, stored per cell and gathered per table row in a fixed order:
  *                    bitwise reproducible, and the faster of the two at every density measured
+ *                    SPL_REUSE_SORT (with SPL_DETERMINISTIC): the workspace already holds the
+ *                    cell sort of these points
  *   work, work_bytes device workspace for SPL_DETERMINISTIC, 256-byte aligned, at least
- *                    spline_backward_work_bytes() bytes, contents undefined afterwards; may be
+ *                    spline_backward_work_bytes() bytes; holds the cell sort afterwards; may be
  *                    NULL (0 bytes) without that flag
  * The position gradient is deterministic either way.  Points with non-finite coordinates
  * contribute nothing to gtable and get NaN in gpos.  Descriptors with basis, sep_grad or

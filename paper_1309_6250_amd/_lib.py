@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(HERE, "libpwspline.so")
 SPL_F64, SPL_F32, SPL_BF16 = 0, 1, 2
 SPL_OK, SPL_EINVAL, SPL_EGRID, SPL_EDTYPE, SPL_ENOMEM, SPL_EHIP, SPL_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 SPL_DETERMINISTIC = 1
+SPL_REUSE_SORT = 2
 SPL_BSPLINE, SPL_LAGRANGE, SPL_PPSPLINE = 0, 1, 2
 
 ERROR_NAMES = {
@@ -101,7 +102,7 @@ def lib():
             "spline_misfit": (ctypes.c_int, [pd, i64, vp, vp, ctypes.c_double, vp, vp, vp, i64, vp]),
             "spline_misfit_work_bytes": (ctypes.c_int, [pd, i64, ctypes.POINTER(i64)]),
             "spline_smoothness_penalty": (ctypes.c_int, [pd, vp, ctypes.c_double, vp, vp, vp, i64, vp]),
-            "spline_eval_vgl_cells": (ctypes.c_int, [pd, vp, i64, vp, vp, vp, vp, vp, i64, vp]),
+            "spline_eval_vgl_cells": (ctypes.c_int, [pd, vp, i64, vp, vp, vp, vp, i32, vp, i64, vp]),
             "spline_cells_work_bytes": (ctypes.c_int, [pd, i64, ctypes.POINTER(i64)]),
             "spline_build_smoothing": (ctypes.c_int, [pd, i64, vp, vp, vp, vp, vp]),
             "spline_smoothing_work_bytes": (ctypes.c_int, [pd, ctypes.POINTER(i64)]),

@@ -261,10 +261,12 @@ def spline_cells_work_bytes(desc, n_pts):
     return out.value
 
 
-def spline_eval_vgl_cells(desc, table, pos, v=None, grad=None, lap=None, outputs="vgl", work=None, stream=None):
+def spline_eval_vgl_cells(desc, table, pos, v=None, grad=None, lap=None, outputs="vgl", work=None, flags=0,
+                          stream=None):
     """spline_eval_vgl computed cell by cell on the matrix cores (for several points per cell).
     `outputs` names the ones wanted ('v', 'g', 'l' in any combination); returns (v, grad, lap) with
-    None for the others.  Equal to spline_eval_vgl up to the order of summation."""
+    None for the others.  Equal to spline_eval_vgl up to the order of summation.  flags:
+    SPL_REUSE_SORT when `work` already holds the cell sort of these same points."""
     n = _check_inputs(desc, table, pos)
     od = OUT_TORCH[desc.dtype]
     dev = pos.device
@@ -284,7 +286,7 @@ def spline_eval_vgl_cells(desc, table, pos, v=None, grad=None, lap=None, outputs
     if work.numel() * work.element_size() < nbytes:
         raise ValueError(f"work must hold {nbytes} bytes")
     check(lib().spline_eval_vgl_cells(ctypes.byref(desc), _ptr(table), n, _ptr(pos), _ptr(v), _ptr(grad), _ptr(lap),
-                                      _ptr(work), int(work.numel() * work.element_size()), _stream(stream)),
+                                      int(flags), _ptr(work), int(work.numel() * work.element_size()), _stream(stream)),
           "spline_eval_vgl_cells")
     return v, grad, lap
 
@@ -315,7 +317,8 @@ def spline_eval_vgl_backward(desc, table, pos, gv=None, ggrad=None, glap=None, g
     elif work.numel() * work.element_size() < nbytes:
         raise ValueError(f"work must hold {nbytes} bytes")
     check(lib().spline_eval_vgl_backward(ctypes.byref(desc), _ptr(table), n, _ptr(pos), _ptr(gv), _ptr(ggrad),
-                                         _ptr(glap), _ptr(gtable), _ptr(gpos), int(flags), _ptr(work), int(nbytes),
+                                         _ptr(glap), _ptr(gtable), _ptr(gpos), int(flags), _ptr(work),
+                                         0 if work is None else int(work.numel() * work.element_size()),
                                          _stream(stream)),
           "spline_eval_vgl_backward")
     return gtable, gpos

@@ -203,10 +203,11 @@ int64_t smoothing_work_bytes(const spl_desc* d);
 int build_smoothing(const spl_desc* d, int64_t n_g, const int32_t* miller, const double* coef, void* table,
                     void* work, hipStream_t stream);
 int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, const void* gv, const void* ggrad,
-                           const void* glap, void* gtable, void* work, int64_t work_bytes, hipStream_t stream);
+                           const void* glap, void* gtable, void* work, int64_t work_bytes, bool reuse,
+                           hipStream_t stream);
 int cells_eval_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes);
 int launch_eval_cells(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, void* v, void* grad,
-                      void* lap, void* work, int64_t work_bytes, hipStream_t stream);
+                      void* lap, void* work, int64_t work_bytes, bool reuse, hipStream_t stream);
 
 int check_eval_args(const spl_desc* d, const void* table, int64_t n_pts, const double* pos) {
   int rc = check_desc(d);
@@ -446,7 +447,7 @@ int spline_backward_work_bytes(const spl_desc* d, int64_t n_pts, int32_t flags, 
   if (rc) return rc;
   if (!bytes) return fail(SPL_EINVAL, "bytes is NULL");
   if (n_pts < 0 || n_pts > 0x7fffffffLL) return fail(SPL_EINVAL, "n_pts = %lld outside [0, 2^31)", (long long)n_pts);
-  if (flags & ~SPL_DETERMINISTIC) return fail(SPL_EINVAL, "unknown flags 0x%x", flags);
+  if (flags & ~(SPL_DETERMINISTIC | SPL_REUSE_SORT)) return fail(SPL_EINVAL, "unknown flags 0x%x", flags);
   if (d->basis != SPL_BSPLINE || d->sep_grad || d->bloch)
     return fail(SPL_EUNSUPPORTED, "the adjoint covers real B-spline tables without separate gradients");
   *bytes = 0;
@@ -467,10 +468,11 @@ int spline_cells_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes) {
 }
 
 int spline_eval_vgl_cells(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, void* v,
-                          void* grad, void* lap, void* work, int64_t work_bytes, void* stream) {
+                          void* grad, void* lap, int32_t flags, void* work, int64_t work_bytes, void* stream) {
   clear_error();
   int rc = check_eval_args(d, table, n_pts, pos);
   if (rc) return rc;
+  if (flags & ~SPL_REUSE_SORT) return fail(SPL_EINVAL, "unknown flags 0x%x", flags);
   if (d->basis != SPL_BSPLINE || d->sep_grad || d->bloch)
     return fail(SPL_EUNSUPPORTED, "the cell-wise evaluation covers real B-spline tables without separate gradients");
   if (n_pts == 0) return SPL_OK;
@@ -479,7 +481,8 @@ int spline_eval_vgl_cells(const spl_desc* d, const void* table, int64_t n_pts, c
     if (o && !out_align_ok(d, o)) return fail(SPL_EINVAL, "output not aligned to its element size");
   if (!work) return fail(SPL_EINVAL, "work is NULL (size from spline_cells_work_bytes)");
   if (!aligned(work, 256)) return fail(SPL_EINVAL, "workspace must be 256-byte aligned");
-  return launch_eval_cells(d, table, n_pts, pos, v, grad, lap, work, work_bytes, static_cast<hipStream_t>(stream));
+  return launch_eval_cells(d, table, n_pts, pos, v, grad, lap, work, work_bytes, (flags & SPL_REUSE_SORT) != 0,
+                           static_cast<hipStream_t>(stream));
 }
 
 int spline_eval_vgl_backward(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, const void* gv,
@@ -488,7 +491,9 @@ int spline_eval_vgl_backward(const spl_desc* d, const void* table, int64_t n_pts
   clear_error();
   int rc = check_eval_args(d, table, n_pts, pos);
   if (rc) return rc;
-  if (flags & ~SPL_DETERMINISTIC) return fail(SPL_EINVAL, "unknown flags 0x%x", flags);
+  if (flags & ~(SPL_DETERMINISTIC | SPL_REUSE_SORT)) return fail(SPL_EINVAL, "unknown flags 0x%x", flags);
+  if ((flags & SPL_REUSE_SORT) && !(flags & SPL_DETERMINISTIC))
+    return fail(SPL_EINVAL, "SPL_REUSE_SORT needs SPL_DETERMINISTIC");
   if (d->basis != SPL_BSPLINE || d->sep_grad || d->bloch)
     return fail(SPL_EUNSUPPORTED, "the adjoint covers real B-spline tables without separate gradients");
   if (n_pts == 0) return SPL_OK;
@@ -502,7 +507,9 @@ int spline_eval_vgl_backward(const spl_desc* d, const void* table, int64_t n_pts
   if (gtable) {
     if (!work) return fail(SPL_EINVAL, "SPL_DETERMINISTIC needs a workspace (spline_backward_work_bytes)");
     if (!aligned(work, 256)) return fail(SPL_EINVAL, "workspace must be 256-byte aligned");
-    if ((rc = launch_backward_sorted(d, n_pts, pos, gv, ggrad, glap, gtable, work, work_bytes, s))) return rc;
+    if ((rc = launch_backward_sorted(d, n_pts, pos, gv, ggrad, glap, gtable, work, work_bytes,
+                                     (flags & SPL_REUSE_SORT) != 0, s)))
+      return rc;
   }
   // the position gradient is deterministic as computed (fixed-order reduction per point)
   return gpos ? launch_backward(d, table, n_pts, pos, gv, ggrad, glap, nullptr, gpos, s) : SPL_OK;

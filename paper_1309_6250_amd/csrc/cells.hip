@@ -173,6 +173,7 @@ struct CellArgs {
   int32_t n_orb;
   int32_t n_groups;        // orbital groups of 16 OT per cell
   int32_t n_classes;
+  int32_t n_pts;           // every index read from the sort is checked against this and n_cells
   int32_t dense;           // 1: all occupied cells at once, blocks written to `blocks`, `occ` marked
   int32_t o_pad;
   void* blocks;            // [n_cells][64][o_pad] per-cell gradient blocks (dense)
@@ -228,8 +229,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   const int grp = lane >> 4;
   const int col = lane & 15;
   const int m_ = col >> 2, n_ = col & 3;
-  const int r0 = a.dense ? 0 : a.class_start[a.cls];
-  const int r1 = a.dense ? a.class_start[a.n_classes] : a.class_start[a.cls + 1];
+  // run range, bounded so that a workspace holding anything else still stays inside the arrays
+  const int r0 = a.dense ? 0 : min(max(a.class_start[a.cls], 0), a.n_pts);
+  const int r1 = min(max(a.dense ? a.class_start[a.n_classes] : a.class_start[a.cls + 1], r0), a.n_pts);
   const int64_t n_work = (int64_t)(r1 - r0) * a.n_groups;
   const int nt = a.n_terms;
   const SortedPoint<A>* pts = static_cast<const SortedPoint<A>*>(a.pts);
@@ -246,6 +248,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const int64_t cell = a.uniq[r] % a.n_cells;         // key = class n_cells + cell
     const int start = a.offsets[r];
     const int cnt = a.counts[r];
+    if (cell < 0 || start < 0 || cnt < 0 || start > a.n_pts - cnt) continue;
     const int iz0 = (int)(cell % a.g.n[2]);
     const int iy0 = (int)((cell / a.g.n[2]) % a.g.n[1]);
     const int ix0 = (int)(cell / ((int64_t)a.g.n[2] * a.g.n[1]));
@@ -273,7 +276,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       __syncthreads();                                   // the previous batch is consumed
       if (lane < nb) {
         const SortedPoint<A> sp = pts[start + b0 + lane];
-        s_p[lane] = sp.p;
+        s_p[lane] = (unsigned)sp.p < (unsigned)a.n_pts ? sp.p : -1;   // -1: contributes nothing
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
           A w4[4], d4[4], dd4[4];
@@ -291,8 +294,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       auto load_b = [&](int q, auto& bv) {
         constexpr int NC = sizeof(bv) / sizeof(bv[0]);
         const int j = q + grp;
-        const bool live = j < nb;
-        const int64_t p = live ? (int64_t)s_p[j] : 0;
+        const int pj = j < nb ? s_p[j] : -1;
+        const bool live = pj >= 0;
+        const int64_t p = live ? (int64_t)pj : 0;
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -469,8 +473,22 @@ struct CellSort {
   char* base;            // the workspace
 };
 
+// The sort's arrays in a workspace laid out by L (no kernels run).
+static CellSort cell_sort_view(void* work, const SortLayout& L) {
+  char* W = static_cast<char*>(work);
+  return CellSort{reinterpret_cast<int64_t*>(W + L.keys_out), reinterpret_cast<int32_t*>(W + L.vals_out),
+                  reinterpret_cast<int64_t*>(W + L.uniq), reinterpret_cast<int32_t*>(W + L.counts),
+                  reinterpret_cast<int32_t*>(W + L.offsets), reinterpret_cast<int32_t*>(W + L.class_start),
+                  W + L.pts, W};
+}
+
+// Sorts the points into the workspace (or, with reuse, takes the sort an earlier call left there).
 static int cell_sort(const spl_desc* d, int64_t n_pts, const double* pos, void* work, const SortLayout& L,
-                     hipStream_t stream, CellSort* cs) {
+                     bool reuse, hipStream_t stream, CellSort* cs) {
+  if (reuse) {
+    *cs = cell_sort_view(work, L);
+    return SPL_OK;
+  }
   int rc;
   char* W = static_cast<char*>(work);
   int64_t* keys_in = reinterpret_cast<int64_t*>(W + L.keys_in);
@@ -510,7 +528,7 @@ static int cell_sort(const spl_desc* d, int64_t n_pts, const double* pos, void* 
                        (int32_t)n, static_cast<SortedPoint<float>*>(pts));
   if ((rc = hip_fail(hipGetLastError(), "sorted point launch"))) return rc;
 
-  *cs = CellSort{keys_out, vals_out, uniq, counts, offsets, class_start, pts, W};
+  *cs = cell_sort_view(work, L);
   return SPL_OK;
 }
 
@@ -524,7 +542,8 @@ int sorted_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes) {
 
 // Deterministic coefficient gradient (accumulated into gtable).  work: sorted_work_bytes bytes.
 int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, const void* gv, const void* ggrad,
-                           const void* glap, void* gtable, void* work, int64_t work_bytes, hipStream_t stream) {
+                           const void* glap, void* gtable, void* work, int64_t work_bytes, bool reuse,
+                           hipStream_t stream) {
   if (n_pts == 0 || !gtable) return SPL_OK;
   SortLayout L;
   int rc = sort_layout(d, n_pts, &L);
@@ -532,7 +551,7 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
   if (!work || work_bytes < (int64_t)L.total)
     return fail(SPL_EINVAL, "deterministic backward needs a workspace of %lld bytes", (long long)L.total);
   CellSort cs;
-  if ((rc = cell_sort(d, n_pts, pos, work, L, stream, &cs))) return rc;
+  if ((rc = cell_sort(d, n_pts, pos, work, L, reuse, stream, &cs))) return rc;
   char* W = cs.base;
   int64_t* uniq = cs.uniq;
   int32_t* counts = cs.counts;
@@ -561,6 +580,7 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
   a.n_orb = d->n_orb;
   a.n_groups = (tiles + ot - 1) / ot;
   a.n_classes = L.n_classes;
+  a.n_pts = (int32_t)n_pts;
   a.o_pad = d->o_pad;
   a.dense = L.dense;
   if (L.dense) {
@@ -657,7 +677,7 @@ struct FwdArgs {
   int32_t n_classes;
   int32_t n_orb;
   int32_t n_groups;
-  int32_t pad_;
+  int32_t n_pts;           // every index read from the sort is checked against this and n_cells
 };
 
 template <typename TS> struct Stored;
@@ -682,7 +702,7 @@ __global__ __launch_bounds__(64) void k_fwd_cells(FwdArgs a) {
   const int lane = (int)threadIdx.x;
   const int grp = lane >> 4;
   const int col = lane & 15;
-  const int n_runs = a.class_start[a.n_classes];     // every run before the non-finite points
+  const int n_runs = min(max(a.class_start[a.n_classes], 0), a.n_pts);   // every run before the non-finite points
   const int64_t n_work = (int64_t)n_runs * a.n_groups;
   const int nt = a.n_terms;
   const SortedPoint<A>* pts = static_cast<const SortedPoint<A>*>(a.pts);
@@ -699,6 +719,7 @@ __global__ __launch_bounds__(64) void k_fwd_cells(FwdArgs a) {
     const int64_t cell = a.uniq[r] % a.n_cells;
     const int start = a.offsets[r];
     const int cnt = a.counts[r];
+    if (cell < 0 || start < 0 || cnt < 0 || start > a.n_pts - cnt) continue;
     const int iz0 = (int)(cell % a.g.n[2]);
     const int iy0 = (int)((cell / a.g.n[2]) % a.g.n[1]);
     const int ix0 = (int)(cell / ((int64_t)a.g.n[2] * a.g.n[1]));
@@ -726,7 +747,7 @@ __global__ __launch_bounds__(64) void k_fwd_cells(FwdArgs a) {
       __syncthreads();                                   // the previous batch is written out
       if (lane < nb) {
         const SortedPoint<A> sp = pts[start + b0p + lane];
-        s_p[lane] = sp.p;
+        s_p[lane] = (unsigned)sp.p < (unsigned)a.n_pts ? sp.p : -1;   // -1: not written
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
           A w4[4], d4[4], dd4[4];
@@ -800,7 +821,7 @@ __global__ __launch_bounds__(64) void k_fwd_cells(FwdArgs a) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int j = mt_ * 16 + M::row(grp, e);
-          if (j >= nb) continue;
+          if (j >= nb || s_p[j] < 0) continue;
           const int64_t p = s_p[j];
 #pragma unroll
           for (int c = 0; c < NT; ++c) {
@@ -823,6 +844,7 @@ __global__ __launch_bounds__(256) void k_fwd_nan(const int64_t* keys, const int3
   const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (i >= n || keys[i] != sentinel) return;
   const int64_t p = perm[i];
+  if (p < 0 || p >= n) return;
   const A nan = __builtin_nan("");
   for (int c = 0; c < a.n_terms; ++c) {
     A* out = static_cast<A*>(a.out[c]) + p * a.out_stride[c];
@@ -851,7 +873,7 @@ int cells_eval_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes) {
 }
 
 int launch_eval_cells(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, void* v, void* grad,
-                      void* lap, void* work, int64_t work_bytes, hipStream_t stream) {
+                      void* lap, void* work, int64_t work_bytes, bool reuse, hipStream_t stream) {
   if (n_pts == 0) return SPL_OK;
   SortLayout L;
   int rc = sort_layout(d, n_pts, &L, false);
@@ -859,7 +881,7 @@ int launch_eval_cells(const spl_desc* d, const void* table, int64_t n_pts, const
   if (!work || work_bytes < (int64_t)L.total)
     return fail(SPL_EINVAL, "spline_eval_vgl_cells needs a workspace of %lld bytes", (long long)L.total);
   CellSort cs;
-  if ((rc = cell_sort(d, n_pts, pos, work, L, stream, &cs))) return rc;
+  if ((rc = cell_sort(d, n_pts, pos, work, L, reuse, stream, &cs))) return rc;
   FwdArgs a;
   memset(&a, 0, sizeof(a));
   a.g = make_geom(d);
@@ -895,6 +917,7 @@ int launch_eval_cells(const spl_desc* d, const void* table, int64_t n_pts, const
   a.class_start = cs.class_start;
   a.n_cells = L.n_cells;
   a.n_classes = L.n_classes;
+  a.n_pts = (int32_t)n_pts;
   a.n_orb = d->n_orb;
   const int ot = fwd_tiles(d->dtype, nt);
   a.n_groups = (d->n_orb + 16 * ot - 1) / (16 * ot);

@@ -20,7 +20,7 @@ by Adam.  Two forms of the same loss:
 """
 import torch
 
-from ._lib import SPL_DETERMINISTIC
+from ._lib import SPL_DETERMINISTIC, SPL_REUSE_SORT
 from .api import (OUT_TORCH, new_gtable, spline_eval_vgl_backward, spline_eval_vgl_cells, spline_misfit,
                   spline_misfit_work_bytes, spline_smoothness_penalty, spline_cells_work_bytes,
                   spline_backward_work_bytes)
@@ -91,23 +91,29 @@ class FitProblem:
         self.lap = torch.empty((n, o), dtype=od, device=dev)
         self.gtable = new_gtable(desc, dev)
         self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
-        self.cells_work = torch.empty(max(1, spline_cells_work_bytes(desc, n)), dtype=torch.uint8, device=dev)
+        # one workspace for the forward and the adjoint: the points never move, so the cell sort
+        # made by the first forward serves every later call (SPL_REUSE_SORT)
         self.misfit_work = torch.empty(spline_misfit_work_bytes(desc, n * o), dtype=torch.uint8, device=dev)
-        self.bwd_work = torch.empty(max(1, spline_backward_work_bytes(desc, n, self.flags)), dtype=torch.uint8,
-                                    device=dev)
+        self.reuse = deterministic
+        nb = max(spline_cells_work_bytes(desc, n), spline_backward_work_bytes(desc, n, self.flags))
+        self.work = torch.empty(max(1, nb), dtype=torch.uint8, device=dev)
+        self.sorted = False
 
     def loss_and_grad(self, beta):
         d = self.desc
         self.loss.zero_()
         spline_eval_vgl_cells(d, beta, self.pos, self.v, None, self.lap if self.use_lap else None,
-                              outputs="vl" if self.use_lap else "v", work=self.cells_work)
+                              outputs="vl" if self.use_lap else "v", work=self.work,
+                              flags=SPL_REUSE_SORT if self.sorted else 0)
+        self.sorted = self.reuse
         gv = spline_misfit(d, self.v, self.v_t, self.w_v, self.loss, g=self.v, work=self.misfit_work)
         gl = None
         if self.use_lap:
             gl = spline_misfit(d, self.lap, self.lap_t, self.w_l, self.loss, g=self.lap, work=self.misfit_work)
         self.gtable.zero_()
-        spline_eval_vgl_backward(d, beta, self.pos, gv, None, gl, self.gtable, None, want_pos=False, flags=self.flags,
-                                 work=self.bwd_work)
+        spline_eval_vgl_backward(d, beta, self.pos, gv, None, gl, self.gtable, None, want_pos=False,
+                                 flags=self.flags | (SPL_REUSE_SORT if self.sorted else 0),
+                                 work=self.work if self.flags else None)
         if self.lam:
             spline_smoothness_penalty(d, beta, self.reg_scale, self.loss, gtable=self.gtable, work=self.misfit_work)
         return self.loss, self.gtable

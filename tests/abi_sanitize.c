@@ -130,11 +130,15 @@ int main(void) {
 
   /* cell-wise forward */
   expect(spline_cells_work_bytes(&d, 0, &bytes), SPL_OK, "cells work bytes");
-  expect(spline_eval_vgl_cells(&d, fake, 10, fpos, NULL, NULL, NULL, fake, 1 << 20, NULL), SPL_EINVAL,
+  expect(spline_eval_vgl_cells(&d, fake, 10, fpos, NULL, NULL, NULL, 0, fake, 1 << 20, NULL), SPL_EINVAL,
          "cells no output");
-  expect(spline_eval_vgl_cells(&d, fake, 10, fpos, fake, NULL, NULL, NULL, 0, NULL), SPL_EINVAL, "cells NULL work");
-  expect(spline_eval_vgl_cells(&dp, fake, 10, fpos, fake, NULL, NULL, fake, 1 << 20, NULL), SPL_EUNSUPPORTED,
+  expect(spline_eval_vgl_cells(&d, fake, 10, fpos, fake, NULL, NULL, 0, NULL, 0, NULL), SPL_EINVAL, "cells NULL work");
+  expect(spline_eval_vgl_cells(&dp, fake, 10, fpos, fake, NULL, NULL, 0, fake, 1 << 20, NULL), SPL_EUNSUPPORTED,
          "cells pp");
+  expect(spline_eval_vgl_cells(&d, fake, 10, fpos, fake, NULL, NULL, 5, fake, 1 << 20, NULL), SPL_EINVAL,
+         "cells flags");
+  expect(spline_eval_vgl_backward(&d, fake, 10, fpos, NULL, NULL, NULL, fake, NULL, SPL_REUSE_SORT, fake, 1 << 20,
+                                  NULL), SPL_EINVAL, "reuse without deterministic");
 
   /* build */
   expect(spline_build(&d, fake, fake, fake, fake, NULL), SPL_EINVAL, "build lap values without lap table");

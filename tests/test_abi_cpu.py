@@ -350,14 +350,28 @@ def test_cells_forward_validates_before_any_launch():
     nb = ctypes.c_int64(-1)
     assert lib.spline_cells_work_bytes(ref, 0, ctypes.byref(nb)) == P.SPL_OK and nb.value == 0
     assert lib.spline_cells_work_bytes(ref, -1, ctypes.byref(nb)) == P.SPL_EINVAL
-    assert lib.spline_eval_vgl_cells(ref, None, 0, None, None, None, None, None, 0, None) == P.SPL_OK
-    assert lib.spline_eval_vgl_cells(ref, fake, 10, fake, None, None, None, fake, 1 << 20, None) == P.SPL_EINVAL
+    assert lib.spline_eval_vgl_cells(ref, None, 0, None, None, None, None, 0, None, 0, None) == P.SPL_OK
+    assert lib.spline_eval_vgl_cells(ref, fake, 10, fake, None, None, None, 0, fake, 1 << 20, None) == P.SPL_EINVAL
     assert b"no output" in lib.spline_last_error()
-    assert lib.spline_eval_vgl_cells(ref, fake, 10, fake, fake, None, None, None, 0, None) == P.SPL_EINVAL
-    assert lib.spline_eval_vgl_cells(ref, fake, 10, fake, fake, None, None, ctypes.c_void_p(264), 1 << 20,
+    assert lib.spline_eval_vgl_cells(ref, fake, 10, fake, fake, None, None, 0, None, 0, None) == P.SPL_EINVAL
+    assert lib.spline_eval_vgl_cells(ref, fake, 10, fake, fake, None, None, 0, ctypes.c_void_p(264), 1 << 20,
                                      None) == P.SPL_EINVAL
-    assert lib.spline_eval_vgl_cells(ref, fake, 10, fake, ctypes.c_void_p(258), None, None, fake, 1 << 20,
+    assert lib.spline_eval_vgl_cells(ref, fake, 10, fake, ctypes.c_void_p(258), None, None, 0, fake, 1 << 20,
                                      None) == P.SPL_EINVAL
     dp = P.spline_desc_init(LAT, (8, 8, 8), 4, "f32", basis="pp")
-    assert lib.spline_eval_vgl_cells(ctypes.byref(dp), fake, 10, fake, fake, None, None, fake, 1 << 20,
+    assert lib.spline_eval_vgl_cells(ctypes.byref(dp), fake, 10, fake, fake, None, None, 0, fake, 1 << 20,
                                      None) == P.SPL_EUNSUPPORTED
+
+
+def test_sort_reuse_flag_validation():
+    fake = ctypes.c_void_p(256)
+    lib = P.lib()
+    d = P.spline_desc_init(LAT, (8, 8, 8), 4, "f32")
+    ref = ctypes.byref(d)
+    # the forward takes only SPL_REUSE_SORT; the adjoint takes it only with SPL_DETERMINISTIC
+    assert lib.spline_eval_vgl_cells(ref, fake, 10, fake, fake, None, None, 1, fake, 1 << 20, None) == P.SPL_EINVAL
+    assert lib.spline_eval_vgl_backward(ref, fake, 10, fake, fake, None, None, fake, None, P.SPL_REUSE_SORT, fake,
+                                        1 << 20, None) == P.SPL_EINVAL
+    assert b"needs SPL_DETERMINISTIC" in lib.spline_last_error()
+    nb = ctypes.c_int64(-1)            # the flag is accepted by the size query (alone: no workspace)
+    assert lib.spline_backward_work_bytes(ref, 10, P.SPL_REUSE_SORT, ctypes.byref(nb)) == P.SPL_OK and nb.value == 0

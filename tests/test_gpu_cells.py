@@ -118,3 +118,30 @@ def test_cells_smallest_grid_and_all_nonfinite(dtype):
     torch.cuda.synchronize()
     assert torch.isnan(v).all() and torch.isnan(g).all() and torch.isnan(l).all()
     assert torch.count_nonzero(gt) == 0
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sort_reuse_is_bitwise(dtype):
+    """SPL_REUSE_SORT: the forward and the deterministic adjoint on a workspace that already holds
+    the cell sort of the same points (made by either call) give the same bits as with a fresh sort,
+    in the dense and in the sparse adjoint form."""
+    od = torch.float64 if dtype == "f64" else torch.float32
+    for grid, n in (((6, 5, 7), 2000), ((16, 16, 16), 300)):
+        d, tab, pos, _, _ = _case(grid, 37, n, dtype, True, 115)
+        pos[7] = np.nan
+        x = to_dev(pos)
+        rng = np.random.default_rng(116)
+        gv, gl = to_dev(rng.standard_normal((n, 37)), od), to_dev(rng.standard_normal((n, 37)), od)
+        say("sort reuse", grid, n, dtype)
+        nb = max(P.spline_cells_work_bytes(d, n), P.spline_backward_work_bytes(d, n, P.SPL_DETERMINISTIC))
+        work = torch.empty(nb, dtype=torch.uint8, device=DEV)
+        fresh_f = P.spline_eval_vgl_cells(d, tab, x)
+        fresh_b, _ = P.spline_eval_vgl_backward(d, tab, x, gv, None, gl, want_pos=False, flags=P.SPL_DETERMINISTIC)
+        P.spline_eval_vgl_cells(d, tab, x, work=work)                       # sorts into work
+        reuse_b, _ = P.spline_eval_vgl_backward(d, tab, x, gv, None, gl, want_pos=False, work=work,
+                                                flags=P.SPL_DETERMINISTIC | P.SPL_REUSE_SORT)
+        reuse_f = P.spline_eval_vgl_cells(d, tab, x, work=work, flags=P.SPL_REUSE_SORT)
+        torch.cuda.synchronize()
+        assert torch.equal(reuse_b, fresh_b)
+        for a, b in zip(reuse_f, fresh_f):
+            assert torch.equal(torch.nan_to_num(a, nan=3.0), torch.nan_to_num(b, nan=3.0))

@@ -272,9 +272,34 @@ int spline_sorted_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes);
 int spline_eval_vgl_cells(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, void* v,
                           void* grad, void* lap, int32_t flags, void* work, int64_t work_bytes, void* stream);
 
-/* Workspace bytes of spline_eval_vgl_cells for n_pts points (the sort's keys, runs and point
- * records).  Host only; may query the current HIP device. */
+/* Workspace bytes of spline_eval_vgl_cells and spline_fit_terms_cells for n_pts points (the sort's
+ * keys, runs and point records, one FP64 partial sum per cell and 16 orbitals).  Host only; may
+ * query the current HIP device. */
 int spline_cells_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes);
+
+/*
+ * The data terms of the least-squares fit (spline_misfit) computed straight from the cell-wise
+ * evaluation, so values and Laplacians never pass through memory: for the n_pts fit points,
+ * with y_v, y_lap the values and Laplacians spline_eval_vgl_cells would write,
+ *   g_v    = 2 w_v (y_v - t_v),        g_lap = 2 w_lap (y_lap - t_lap)     (OVERWRITTEN)
+ *   *loss += w_v sum (y_v - t_v)^2 + w_lap sum (y_lap - t_lap)^2           (ACCUMULATED)
+ *   t_v, g_v      device, [n_pts][n_orb] of the output type (FP64 for SPL_F64, else FP32), the
+ *                 caller's point order; both NULL to leave out the value term
+ *   t_lap, g_lap  likewise for the Laplacian term (at least one term is required)
+ *   w_v, w_lap    the terms' weights, finite
+ *   loss          device, one FP64
+ *   flags, work   as for spline_eval_vgl_cells (the workspace holds the cell sort afterwards)
+ * g equals what spline_misfit makes of spline_eval_vgl_cells' outputs bit for bit (the residuals
+ * are the same numbers in the output type); the loss is summed in FP64 per cell and 16 orbitals
+ * and then in a fixed order, so it is reproducible bit for bit and agrees with spline_misfit's to
+ * rounding.  A non-finite point gets NaN gradients and makes the loss NaN.  Errors as for
+ * spline_eval_vgl_cells, plus: a target without its gradient or the reverse, no term, non-finite
+ * weight, NULL or misaligned loss -> SPL_EINVAL.  Allocates nothing.
+ */
+int spline_fit_terms_cells(const spl_desc* d, const void* table, int64_t n_pts, const double* pos,
+                           const void* t_v, double w_v, void* g_v, const void* t_lap, double w_lap,
+                           void* g_lap, double* loss, int32_t flags, void* work, int64_t work_bytes,
+                           void* stream);
 
 /*
  * Adjoint of spline_eval_vgl: given dL/dv, dL/dgrad, dL/dlap of a scalar loss L,

@@ -291,6 +291,38 @@ def spline_eval_vgl_cells(desc, table, pos, v=None, grad=None, lap=None, outputs
     return v, grad, lap
 
 
+def spline_fit_terms_cells(desc, table, pos, t_v=None, w_v=0.0, t_lap=None, w_lap=0.0, g_v=None, g_lap=None,
+                           loss=None, work=None, flags=0, stream=None):
+    """The misfit of values and Laplacians against targets t_v, t_lap ([n_pts, n_orb], output type)
+    straight from the cell-wise evaluation: returns (g_v, g_lap, loss) with g = 2 w (y - t) (None for
+    a term without a target) and loss (a one-element FP64 device tensor) accumulated into.  flags:
+    SPL_REUSE_SORT when `work` already holds the cell sort of these same points."""
+    n = _check_inputs(desc, table, pos)
+    od = OUT_TORCH[desc.dtype]
+    dev = pos.device
+    o = desc.n_orb
+    if t_v is not None and g_v is None:
+        g_v = torch.empty((n, o), dtype=od, device=dev)
+    if t_lap is not None and g_lap is None:
+        g_lap = torch.empty((n, o), dtype=od, device=dev)
+    for name, t in (("t_v", t_v), ("g_v", g_v), ("t_lap", t_lap), ("g_lap", g_lap)):
+        if t is not None:
+            _need(t, name, od, n * o)
+    if loss is None:
+        loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    _need(loss, "loss", torch.float64, 1)
+    nbytes = spline_cells_work_bytes(desc, n)
+    if work is None:
+        work = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    if work.numel() * work.element_size() < nbytes:
+        raise ValueError(f"work must hold {nbytes} bytes")
+    check(lib().spline_fit_terms_cells(ctypes.byref(desc), _ptr(table), n, _ptr(pos), _ptr(t_v), float(w_v),
+                                       _ptr(g_v), _ptr(t_lap), float(w_lap), _ptr(g_lap), _ptr(loss), int(flags),
+                                       _ptr(work), int(work.numel() * work.element_size()), _stream(stream)),
+          "spline_fit_terms_cells")
+    return g_v, g_lap, loss
+
+
 def spline_eval_vgl_backward(desc, table, pos, gv=None, ggrad=None, glap=None, gtable=None, gpos=None,
                              want_table=True, want_pos=True, flags=0, stream=None, work=None):
     """Returns (gtable, gpos).  gtable is accumulated into (a fresh zero table if not given).

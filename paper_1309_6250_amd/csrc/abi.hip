@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "cells.hpp"
 #include "internal.hpp"
 
 namespace pws {
@@ -205,9 +206,6 @@ int build_smoothing(const spl_desc* d, int64_t n_g, const int32_t* miller, const
 int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, const void* gv, const void* ggrad,
                            const void* glap, void* gtable, void* work, int64_t work_bytes, bool reuse,
                            hipStream_t stream);
-int cells_eval_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes);
-int launch_eval_cells(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, void* v, void* grad,
-                      void* lap, void* work, int64_t work_bytes, bool reuse, hipStream_t stream);
 
 int check_eval_args(const spl_desc* d, const void* table, int64_t n_pts, const double* pos) {
   int rc = check_desc(d);
@@ -238,7 +236,7 @@ using namespace pws;
 
 extern "C" {
 
-int spline_version(void) { return 10200; }
+int spline_version(void) { return 10300; }
 
 const char* spline_last_error(void) { return g_last_error.c_str(); }
 
@@ -482,7 +480,30 @@ int spline_eval_vgl_cells(const spl_desc* d, const void* table, int64_t n_pts, c
   if (!work) return fail(SPL_EINVAL, "work is NULL (size from spline_cells_work_bytes)");
   if (!aligned(work, 256)) return fail(SPL_EINVAL, "workspace must be 256-byte aligned");
   return launch_eval_cells(d, table, n_pts, pos, v, grad, lap, work, work_bytes, (flags & SPL_REUSE_SORT) != 0,
-                           static_cast<hipStream_t>(stream));
+                           static_cast<hipStream_t>(stream), nullptr);
+}
+
+int spline_fit_terms_cells(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, const void* t_v,
+                           double w_v, void* g_v, const void* t_lap, double w_lap, void* g_lap, double* loss,
+                           int32_t flags, void* work, int64_t work_bytes, void* stream) {
+  clear_error();
+  int rc = check_eval_args(d, table, n_pts, pos);
+  if (rc) return rc;
+  if (flags & ~SPL_REUSE_SORT) return fail(SPL_EINVAL, "unknown flags 0x%x", flags);
+  if (d->basis != SPL_BSPLINE || d->sep_grad || d->bloch)
+    return fail(SPL_EUNSUPPORTED, "the fit terms cover real B-spline tables without separate gradients");
+  if (!isfinite(w_v) || !isfinite(w_lap)) return fail(SPL_EINVAL, "weight is not finite");
+  if (!t_v != !g_v || !t_lap != !g_lap) return fail(SPL_EINVAL, "a term needs both its target and its gradient");
+  if (!t_v && !t_lap) return fail(SPL_EINVAL, "no term requested");
+  if (n_pts == 0) return SPL_OK;
+  for (const void* o : {t_v, static_cast<const void*>(g_v), t_lap, static_cast<const void*>(g_lap)})
+    if (o && !out_align_ok(d, o)) return fail(SPL_EINVAL, "target or gradient not aligned to its element size");
+  if (!loss || (uintptr_t)loss % 8) return fail(SPL_EINVAL, "loss is NULL or not 8-byte aligned");
+  if (!work) return fail(SPL_EINVAL, "work is NULL (size from spline_cells_work_bytes)");
+  if (!aligned(work, 256)) return fail(SPL_EINVAL, "workspace must be 256-byte aligned");
+  FitTerms fit{t_v, w_v, t_lap, w_lap, loss};
+  return launch_eval_cells(d, table, n_pts, pos, g_v, nullptr, g_lap, work, work_bytes,
+                           (flags & SPL_REUSE_SORT) != 0, static_cast<hipStream_t>(stream), &fit);
 }
 
 int spline_eval_vgl_backward(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, const void* gv,

@@ -30,6 +30,7 @@
 #include <algorithm>
 #include <cstring>
 
+#include "cells.hpp"
 #include "common.hpp"
 
 namespace pws {
@@ -41,7 +42,8 @@ __host__ __device__ inline int axis_colour(int i, int n) {
 __host__ __device__ inline int axis_colours(int n) { return 4 + (n & 3); }
 
 struct SortLayout {
-  size_t keys_in, keys_out, vals_in, vals_out, uniq, counts, offsets, num_runs, class_start, pts, occ, blocks, temp;
+  size_t keys_in, keys_out, vals_in, vals_out, uniq, counts, offsets, num_runs, class_start, pts, occ, blocks,
+      partials, temp;
   size_t temp_bytes, total;
   int n_classes;
   int dense;           // 1: per-cell blocks in the workspace and a per-row gather instead of colour classes
@@ -91,6 +93,11 @@ static int sort_layout(const spl_desc* d, int64_t n_pts, SortLayout* L, bool adj
   L->dense = adjoint_blocks && n_pts >= 4 * L->n_cells && block_bytes <= ((size_t)4 << 30);
   L->occ = off; off = align_up(off + (L->dense ? 4 * (size_t)L->n_cells : 0));
   L->blocks = off; off = align_up(off + (L->dense ? block_bytes : 0));
+  // forward only: one FP64 partial sum per work item of the fit terms, at most min(n, cells) runs
+  // times the 16-orbital tiles
+  L->partials = off;
+  if (!adjoint_blocks)
+    off = align_up(off + 8 * (size_t)std::min<int64_t>(n_pts, L->n_cells) * (size_t)((d->n_orb + 15) / 16));
   L->temp = off; off = align_up(off + L->temp_bytes);
   L->total = off;
   return SPL_OK;
@@ -678,6 +685,11 @@ struct FwdArgs {
   int32_t n_orb;
   int32_t n_groups;
   int32_t n_pts;           // every index read from the sort is checked against this and n_cells
+  // fit terms (spline_fit_terms_cells): a term with a target writes 2 w (y - t) instead of y and
+  // adds w (y - t)^2 to its work item's FP64 partial sum
+  const void* target[5];
+  double w[5];
+  double* partial;         // one slot per work item (NULL: plain outputs)
 };
 
 template <typename TS> struct Stored;
@@ -691,7 +703,9 @@ template <> struct Stored<uint16_t> {   // BF16 bits -> FP32
   __device__ __forceinline__ static float at(const uint16_t* p) { return __uint_as_float((uint32_t)*p << 16); }
 };
 
-template <typename TS, typename A, int OT, int NT>
+// FIT: every term has a target (spline_fit_terms_cells); the targets of a batch are loaded before
+// its products, so their latency hides behind the matrix-core work
+template <typename TS, typename A, int OT, int NT, bool FIT>
 __global__ __launch_bounds__(64) void k_fwd_cells(FwdArgs a) {
   using M = Mfma<A>;
   using Acc = typename M::acc;
@@ -702,7 +716,8 @@ __global__ __launch_bounds__(64) void k_fwd_cells(FwdArgs a) {
   const int lane = (int)threadIdx.x;
   const int grp = lane >> 4;
   const int col = lane & 15;
-  const int n_runs = min(max(a.class_start[a.n_classes], 0), a.n_pts);   // every run before the non-finite points
+  // every run before the non-finite points (at most one per occupied cell)
+  const int n_runs = (int)min((int64_t)min(max(a.class_start[a.n_classes], 0), a.n_pts), a.n_cells);
   const int64_t n_work = (int64_t)n_runs * a.n_groups;
   const int nt = a.n_terms;
   const SortedPoint<A>* pts = static_cast<const SortedPoint<A>*>(a.pts);
@@ -719,7 +734,11 @@ __global__ __launch_bounds__(64) void k_fwd_cells(FwdArgs a) {
     const int64_t cell = a.uniq[r] % a.n_cells;
     const int start = a.offsets[r];
     const int cnt = a.counts[r];
-    if (cell < 0 || start < 0 || cnt < 0 || start > a.n_pts - cnt) continue;
+    double sq = 0.0;                                     // this lane's share of the fit terms' sum
+    if (cell < 0 || start < 0 || cnt < 0 || start > a.n_pts - cnt) {
+      if (FIT && lane == 0) a.partial[w] = 0.0;
+      continue;
+    }
     const int iz0 = (int)(cell % a.g.n[2]);
     const int iy0 = (int)((cell / a.g.n[2]) % a.g.n[1]);
     const int ix0 = (int)(cell / ((int64_t)a.g.n[2] * a.g.n[1]));
@@ -762,6 +781,29 @@ __global__ __launch_bounds__(64) void k_fwd_cells(FwdArgs a) {
       }
       __syncthreads();
       const int tiles = nb > 16 ? 2 : 1;
+      // fit: every lane loads the targets of its outputs without branching (an entry with no
+      // output reads element 0 instead and goes unused), so the loads stay countable and one
+      // wait after the products covers them
+      A tg[FIT ? 2 : 1][FIT ? NT : 1][OT][4];
+      if constexpr (FIT) {
+#pragma unroll
+        for (int mt_ = 0; mt_ < 2; ++mt_)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int j = mt_ * 16 + M::row(grp, e);
+            const int64_t p = j < nb ? s_p[j] : -1;
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+              const int cc = c < nt ? c : 0;
+              const A* base = static_cast<const A*>(a.target[cc]);
+#pragma unroll
+              for (int ot = 0; ot < OT; ++ot) {
+                const bool ok = mt_ < tiles && c < nt && p >= 0 && ocol[ot];
+                tg[mt_][c][ot][e] = base[ok ? p * a.out_stride[cc] + ob + 16 * ot + col : 0];
+              }
+            }
+          }
+      }
       Acc acc[2][NT][OT];
 #pragma unroll
       for (int mt_ = 0; mt_ < 2; ++mt_)
@@ -814,6 +856,8 @@ __global__ __launch_bounds__(64) void k_fwd_cells(FwdArgs a) {
           }
         }
       }
+      // vmcnt(0): the targets have arrived (the products took far longer than the loads)
+      if constexpr (FIT) __builtin_amdgcn_s_waitcnt(0x0f70);
       // out[point][o]: element e of lane (grp, col) is point row(grp, e) of the tile, orbital col
 #pragma unroll
       for (int mt_ = 0; mt_ < 2; ++mt_) {
@@ -827,14 +871,50 @@ __global__ __launch_bounds__(64) void k_fwd_cells(FwdArgs a) {
           for (int c = 0; c < NT; ++c) {
             if (c >= nt) break;
             A* out = static_cast<A*>(a.out[c]) + p * a.out_stride[c] + ob + col;
+            if constexpr (FIT) {
+              const A two_w = (A)(2.0 * a.w[c]);
 #pragma unroll
-            for (int ot = 0; ot < OT; ++ot)
-              if (ocol[ot]) out[16 * ot] = acc[mt_][c][ot][e];
+              for (int ot = 0; ot < OT; ++ot)
+                if (ocol[ot]) {
+                  const A res = acc[mt_][c][ot][e] - tg[mt_][c][ot][e];
+                  out[16 * ot] = two_w * res;
+                  sq = fma(a.w[c] * (double)res, (double)res, sq);
+                }
+            } else {
+#pragma unroll
+              for (int ot = 0; ot < OT; ++ot)
+                if (ocol[ot]) out[16 * ot] = acc[mt_][c][ot][e];
+            }
           }
         }
       }
     }
+    if constexpr (FIT) {
+      // the wave's sum in a fixed butterfly order, one slot per work item
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
+      if (lane == 0) a.partial[w] = sq;
+    }
   }
+}
+
+// loss += the work items' partial sums, in a fixed order; NaN when a point is not finite (its terms
+// are NaN, as the misfit of its NaN outputs would be)
+__global__ __launch_bounds__(256) void k_fit_total(const int32_t* class_start, int32_t n_classes, int32_t n_pts,
+                                                   int64_t n_cells, int32_t n_groups, const int64_t* keys,
+                                                   int64_t sentinel, const double* partial, double* loss) {
+  __shared__ double red[256];
+  const int64_t n_runs = min((int64_t)min(max(class_start[n_classes], 0), n_pts), n_cells);
+  const int64_t n_work = n_runs * n_groups;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n_work; i += 256) s += partial[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss += keys[n_pts - 1] == sentinel ? (double)__builtin_nan("") : red[0];
 }
 
 // Non-finite points (sorted last under the sentinel key) get NaN in every requested output.
@@ -855,11 +935,16 @@ __global__ __launch_bounds__(256) void k_fwd_nan(const int64_t* keys, const int3
 typedef void (*FwdKernel)(FwdArgs);
 
 // FP32 with at most two terms: two orbital tiles per wave; otherwise one (accumulator registers)
+// (the fit terms come in at most two: values and Laplacians)
 template <typename TS, typename A>
-static FwdKernel pick_fwd(int nt) {
+static FwdKernel pick_fwd(int nt, bool fit) {
+  if (fit) {
+    if constexpr (sizeof(A) == 4) return k_fwd_cells<TS, A, 2, 2, true>;
+    else return k_fwd_cells<TS, A, 1, 2, true>;
+  }
   if constexpr (sizeof(A) == 4)
-    if (nt <= 2) return k_fwd_cells<TS, A, 2, 2>;
-  return nt <= 2 ? k_fwd_cells<TS, A, 1, 2> : k_fwd_cells<TS, A, 1, 5>;
+    if (nt <= 2) return k_fwd_cells<TS, A, 2, 2, false>;
+  return nt <= 2 ? k_fwd_cells<TS, A, 1, 2, false> : k_fwd_cells<TS, A, 1, 5, false>;
 }
 
 static int fwd_tiles(int dtype, int nt) { return dtype != SPL_F64 && nt <= 2 ? 2 : 1; }
@@ -873,7 +958,8 @@ int cells_eval_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes) {
 }
 
 int launch_eval_cells(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, void* v, void* grad,
-                      void* lap, void* work, int64_t work_bytes, bool reuse, hipStream_t stream) {
+                      void* lap, void* work, int64_t work_bytes, bool reuse, hipStream_t stream,
+                      const FitTerms* fit) {
   if (n_pts == 0) return SPL_OK;
   SortLayout L;
   int rc = sort_layout(d, n_pts, &L, false);
@@ -890,13 +976,27 @@ int launch_eval_cells(const spl_desc* d, const void* table, int64_t n_pts, const
   const int64_t no = d->n_orb;
   const size_t os = d->dtype == SPL_F64 ? 8 : 4;
   int nt = 0;
-  auto term = [&](void* out, int64_t stride, int kind, int src) {
+  auto term = [&](void* out, int64_t stride, int kind, int src, const void* target = nullptr, double w = 0.0) {
     a.out[nt] = out;
     a.out_stride[nt] = stride;
     a.kind[nt] = kind;
     a.src[nt] = src;
+    a.target[nt] = target;
+    a.w[nt] = w;
+    if (src == 1) a.use_lap_table = 1;
     ++nt;
   };
+  if (fit) {
+    // fit terms: v and lap receive the upstream gradients of the misfit of values and Laplacians
+    if (v) term(v, no, TERM_VAL, 0, fit->t_v, fit->w_v);
+    if (lap) {
+      if (d->has_lap) term(lap, no, TERM_VAL, 1, fit->t_lap, fit->w_lap);
+      else term(lap, no, TERM_LAP, 0, fit->t_lap, fit->w_lap);
+    }
+    v = grad = nullptr;
+    lap = nullptr;
+    a.partial = reinterpret_cast<double*>(static_cast<char*>(work) + L.partials);
+  }
   if (v) term(v, no, TERM_VAL, 0);
   if (grad) {
     char* gb = static_cast<char*>(grad);
@@ -909,7 +1009,6 @@ int launch_eval_cells(const spl_desc* d, const void* table, int64_t n_pts, const
     else term(lap, no, TERM_LAP, 0);
   }
   a.n_terms = nt;
-  a.use_lap_table = d->has_lap && lap;
   a.uniq = cs.uniq;
   a.counts = cs.counts;
   a.offsets = cs.offsets;
@@ -922,13 +1021,18 @@ int launch_eval_cells(const spl_desc* d, const void* table, int64_t n_pts, const
   const int ot = fwd_tiles(d->dtype, nt);
   a.n_groups = (d->n_orb + 16 * ot - 1) / (16 * ot);
   FwdKernel k;
-  if (d->dtype == SPL_F64) k = pick_fwd<double, double>(nt);
-  else if (d->dtype == SPL_F32) k = pick_fwd<float, float>(nt);
-  else k = pick_fwd<uint16_t, float>(nt);
+  if (d->dtype == SPL_F64) k = pick_fwd<double, double>(nt, fit != nullptr);
+  else if (d->dtype == SPL_F32) k = pick_fwd<float, float>(nt, fit != nullptr);
+  else k = pick_fwd<uint16_t, float>(nt, fit != nullptr);
   const int grid = (int)std::min<int64_t>(std::min<int64_t>(n_pts, L.n_cells) * a.n_groups, 1 << 16);
   hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, stream, a);
   if ((rc = hip_fail(hipGetLastError(), "cell forward launch"))) return rc;
   const int n = (int)n_pts;
+  if (fit) {
+    hipLaunchKernelGGL(k_fit_total, dim3(1), dim3(256), 0, stream, cs.class_start, (int32_t)L.n_classes, a.n_pts,
+                       L.n_cells, a.n_groups, cs.keys, (int64_t)L.n_classes * L.n_cells, a.partial, fit->loss);
+    if ((rc = hip_fail(hipGetLastError(), "fit total launch"))) return rc;
+  }
   if (d->dtype == SPL_F64)
     hipLaunchKernelGGL(k_fwd_nan<double>, dim3((n + 255) / 256), dim3(256), 0, stream, cs.keys, cs.perm, n,
                        (int64_t)L.n_classes * L.n_cells, a);

@@ -9,11 +9,12 @@ Minimizes over the coefficient table beta (FP32 or FP64)
 with wV = 1 / mean V_t^2 and wL = 1 / mean lap_t^2 (or 0), periodic second differences,
 by Adam.  Two forms of the same loss:
 
-- FitProblem.loss_and_grad, used by fit_adam: every term runs in the library's kernels (the
-  cell-wise forward of V and lap only, spline_misfit on each, which forms the upstream gradients
-  in place and sums the squared residuals in FP64 in a fixed order, the adjoint, and
-  spline_smoothness_penalty on the table); only the Adam update is a tensor operation.  Buffers
-  are allocated once.
+- FitProblem.loss_and_grad, used by fit_adam: every term runs in the library's kernels
+  (spline_fit_terms_cells, the cell-wise forward of V and lap that forms the upstream gradients
+  2 w (y - t) as it evaluates and sums the squared residuals in FP64 in a fixed order; the
+  adjoint; spline_smoothness_penalty on the table); only the Adam update is a tensor operation.
+  Buffers are allocated once.  With fused=False the forward writes V and lap and spline_misfit
+  forms the same gradients from them in a second pass.
 - make_loss, a differentiable function of the table built on SplineVGL, for use inside a
   larger autograd graph.  Its residuals are formed in the kernel's output precision and
   their squares summed in FP64.
@@ -21,8 +22,8 @@ by Adam.  Two forms of the same loss:
 import torch
 
 from ._lib import SPL_DETERMINISTIC, SPL_REUSE_SORT
-from .api import (OUT_TORCH, new_gtable, spline_eval_vgl_backward, spline_eval_vgl_cells, spline_misfit,
-                  spline_misfit_work_bytes, spline_smoothness_penalty, spline_cells_work_bytes,
+from .api import (OUT_TORCH, new_gtable, spline_eval_vgl_backward, spline_eval_vgl_cells, spline_fit_terms_cells,
+                  spline_misfit, spline_misfit_work_bytes, spline_smoothness_penalty, spline_cells_work_bytes,
                   spline_backward_work_bytes)
 from .autograd import SplineVGL
 
@@ -76,8 +77,8 @@ class FitProblem:
     device tensors (FP64 scalar; the gradient table, FP32 for FP32 and BF16 tables); both are
     reused by the next call."""
 
-    def __init__(self, desc, pos, v_t, lap_t, lam=1e-3, use_lap=True, deterministic=True):
-        self.desc, self.pos, self.lam, self.use_lap = desc, pos, lam, use_lap
+    def __init__(self, desc, pos, v_t, lap_t, lam=1e-3, use_lap=True, deterministic=True, fused=True):
+        self.desc, self.pos, self.lam, self.use_lap, self.fused = desc, pos, lam, use_lap, fused
         self.flags = SPL_DETERMINISTIC if deterministic else 0
         w_v, w_l, reg_scale = _weights(desc, v_t, lap_t, lam, use_lap)
         n, o = pos.shape[0], desc.n_orb
@@ -102,14 +103,21 @@ class FitProblem:
     def loss_and_grad(self, beta):
         d = self.desc
         self.loss.zero_()
-        spline_eval_vgl_cells(d, beta, self.pos, self.v, None, self.lap if self.use_lap else None,
-                              outputs="vl" if self.use_lap else "v", work=self.work,
-                              flags=SPL_REUSE_SORT if self.sorted else 0)
+        reuse = SPL_REUSE_SORT if self.sorted else 0
+        lap = self.lap if self.use_lap else None
+        if self.fused:
+            # the residuals and their sum straight from the cell-wise evaluation
+            gv, gl, _ = spline_fit_terms_cells(d, beta, self.pos, self.v_t, self.w_v,
+                                               self.lap_t if self.use_lap else None, self.w_l, g_v=self.v,
+                                               g_lap=lap, loss=self.loss, work=self.work, flags=reuse)
+        else:
+            spline_eval_vgl_cells(d, beta, self.pos, self.v, None, lap, outputs="vl" if self.use_lap else "v",
+                                  work=self.work, flags=reuse)
+            gv = spline_misfit(d, self.v, self.v_t, self.w_v, self.loss, g=self.v, work=self.misfit_work)
+            gl = None
+            if self.use_lap:
+                gl = spline_misfit(d, self.lap, self.lap_t, self.w_l, self.loss, g=self.lap, work=self.misfit_work)
         self.sorted = self.reuse
-        gv = spline_misfit(d, self.v, self.v_t, self.w_v, self.loss, g=self.v, work=self.misfit_work)
-        gl = None
-        if self.use_lap:
-            gl = spline_misfit(d, self.lap, self.lap_t, self.w_l, self.loss, g=self.lap, work=self.misfit_work)
         self.gtable.zero_()
         spline_eval_vgl_backward(d, beta, self.pos, gv, None, gl, self.gtable, None, want_pos=False,
                                  flags=self.flags | (SPL_REUSE_SORT if self.sorted else 0),

@@ -140,6 +140,20 @@ int main(void) {
   expect(spline_eval_vgl_backward(&d, fake, 10, fpos, NULL, NULL, NULL, fake, NULL, SPL_REUSE_SORT, fake, 1 << 20,
                                   NULL), SPL_EINVAL, "reuse without deterministic");
 
+  /* fit terms from the cell-wise forward */
+  expect(spline_fit_terms_cells(&d, fake, 10, fpos, fake, 1.0, NULL, NULL, 0.0, NULL, fake, 0, fake, 1 << 20, NULL),
+         SPL_EINVAL, "fit terms target without gradient");
+  expect(spline_fit_terms_cells(&d, fake, 10, fpos, NULL, 1.0, NULL, NULL, 0.0, NULL, fake, 0, fake, 1 << 20, NULL),
+         SPL_EINVAL, "fit terms no term");
+  expect(spline_fit_terms_cells(&d, fake, 10, fpos, fake, 1.0, fake, NULL, 0.0, NULL, NULL, 0, fake, 1 << 20, NULL),
+         SPL_EINVAL, "fit terms NULL loss");
+  expect(spline_fit_terms_cells(&d, fake, 10, fpos, fake, 1.0, fake, NULL, 0.0, NULL, fake, 0, NULL, 0, NULL),
+         SPL_EINVAL, "fit terms NULL work");
+  expect(spline_fit_terms_cells(&dp, fake, 10, fpos, fake, 1.0, fake, NULL, 0.0, NULL, fake, 0, fake, 1 << 20, NULL),
+         SPL_EUNSUPPORTED, "fit terms pp");
+  expect(spline_fit_terms_cells(&d, fake, 0, fpos, fake, 1.0, fake, NULL, 0.0, NULL, fake, 0, NULL, 0, NULL), SPL_OK,
+         "fit terms n == 0");
+
   /* build */
   expect(spline_build(&d, fake, fake, fake, fake, NULL), SPL_EINVAL, "build lap values without lap table");
   expect(spline_build(&d32, fake, NULL, fake, fake, NULL), SPL_EINVAL, "build lap table without values");

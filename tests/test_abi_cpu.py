@@ -363,6 +363,36 @@ def test_cells_forward_validates_before_any_launch():
                                      None) == P.SPL_EUNSUPPORTED
 
 
+def test_fit_terms_validate_before_any_launch():
+    fake = ctypes.c_void_p(256)
+    lib = P.lib()
+    d = P.spline_desc_init(LAT, (8, 8, 8), 4, "f32")
+    ref = ctypes.byref(d)
+    f = lib.spline_fit_terms_cells
+    big = 1 << 20
+    # (t_v, w_v, g_v, t_lap, w_lap, g_lap, loss, flags, work) -> expected code, message fragment
+    cases = [
+        ((fake, 1.0, fake, None, 0.0, None, fake, 4, fake), P.SPL_EINVAL, b"unknown flags"),
+        ((fake, float("nan"), fake, None, 0.0, None, fake, 0, fake), P.SPL_EINVAL, b"not finite"),
+        ((fake, 1.0, fake, fake, float("inf"), fake, fake, 0, fake), P.SPL_EINVAL, b"not finite"),
+        ((fake, 1.0, None, None, 0.0, None, fake, 0, fake), P.SPL_EINVAL, b"both"),
+        ((None, 1.0, None, None, 0.0, fake, fake, 0, fake), P.SPL_EINVAL, b"both"),
+        ((None, 1.0, None, None, 0.0, None, fake, 0, fake), P.SPL_EINVAL, b"no term"),
+        ((ctypes.c_void_p(258), 1.0, fake, None, 0.0, None, fake, 0, fake), P.SPL_EINVAL, b"aligned"),
+        ((fake, 1.0, fake, None, 0.0, None, None, 0, fake), P.SPL_EINVAL, b"loss"),
+        ((fake, 1.0, fake, None, 0.0, None, ctypes.c_void_p(260), 0, fake), P.SPL_EINVAL, b"loss"),
+        ((fake, 1.0, fake, None, 0.0, None, fake, 0, None), P.SPL_EINVAL, b"work"),
+        ((fake, 1.0, fake, None, 0.0, None, fake, 0, ctypes.c_void_p(264)), P.SPL_EINVAL, b"256-byte"),
+    ]
+    for (tv, wv, gv, tl, wl, gl, loss, flags, work), code, msg in cases:
+        assert f(ref, fake, 10, fake, tv, wv, gv, tl, wl, gl, loss, flags, work, big, None) == code
+        assert msg in lib.spline_last_error()
+    assert f(ref, None, 0, None, fake, 1.0, fake, None, 0.0, None, fake, 0, None, 0, None) == P.SPL_OK
+    dp = P.spline_desc_init(LAT, (8, 8, 8), 4, "f32", basis="pp")
+    assert f(ctypes.byref(dp), fake, 10, fake, fake, 1.0, fake, None, 0.0, None, fake, 0, fake, big,
+             None) == P.SPL_EUNSUPPORTED
+
+
 def test_sort_reuse_flag_validation():
     fake = ctypes.c_void_p(256)
     lib = P.lib()

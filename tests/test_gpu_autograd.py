@@ -199,6 +199,25 @@ def test_fit_problem_matches_oracle():
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fit_problem_fused_terms_equal_two_pass(dtype):
+    """FitProblem with the misfit formed inside the cell-wise forward (spline_fit_terms_cells) and
+    with the two-pass form (forward, then spline_misfit): the same coefficient gradient bit for
+    bit (the upstream gradients are the same numbers), the loss to FP64 summation accuracy."""
+    s, pos, v_t, l_t, beta0 = _fit_case()
+    d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype)
+    table = table_from_oracle(d, beta0, dtype)
+    say("fit problem, fused and two-pass terms", dtype)
+    out = []
+    for fused in (True, False):
+        prob = FitProblem(d, to_dev(pos), to_dev(v_t), to_dev(l_t), lam=0.3, fused=fused)
+        loss, grad = prob.loss_and_grad(table)
+        out.append((float(loss), grad.clone()))
+    torch.cuda.synchronize()
+    assert torch.equal(out[0][1], out[1][1])
+    assert abs(out[0][0] - out[1][0]) <= 1e-13 * abs(out[1][0])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_adam_fit_lowers_the_loss(dtype):
     s, pos, v_t, l_t, beta0 = _fit_case()
     d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, dtype)

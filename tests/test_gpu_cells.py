@@ -1,5 +1,7 @@
 """spline_eval_vgl_cells: the forward evaluation cell by cell on the matrix cores, against the
 per-point kernel (spline_eval_vgl) and the FP64 oracle, on dense and sparse point sets."""
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -145,3 +147,89 @@ def test_sort_reuse_is_bitwise(dtype):
         assert torch.equal(reuse_b, fresh_b)
         for a, b in zip(reuse_f, fresh_f):
             assert torch.equal(torch.nan_to_num(a, nan=3.0), torch.nan_to_num(b, nan=3.0))
+
+
+@pytest.mark.parametrize("terms", ["vl", "v", "l"])
+@pytest.mark.parametrize("has_lap", [False, True], ids=["lap-from-derivatives", "lap-table"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("shape", [((6, 5, 7), 37, 2000), ((16, 16, 16), 20, 300)], ids=["dense", "sparse"])
+def test_fit_terms_match_forward_then_misfit(shape, dtype, has_lap, terms):
+    """spline_fit_terms_cells against the two-pass form (cell-wise forward, then spline_misfit on
+    each output): the gradients 2 w (y - t) bit for bit, the loss (accumulated into) to FP64
+    summation accuracy, and the loss itself repeatable bit for bit, also on a reused sort."""
+    grid, n_orb, n = shape
+    d, tab, pos, _, _ = _case(grid, n_orb, n, dtype, has_lap, 117)
+    x = to_dev(pos)
+    od = torch.float64 if dtype == "f64" else torch.float32
+    rng = np.random.default_rng(118)
+    tv = to_dev(rng.standard_normal((n, n_orb)), od) if "v" in terms else None
+    tl = to_dev(3.0 * rng.standard_normal((n, n_orb)), od) if "l" in terms else None
+    wv, wl = 0.37, 0.011
+    say("fit terms", grid, n_orb, n, dtype, has_lap, terms)
+    v, _, l = P.spline_eval_vgl_cells(d, tab, x, outputs=terms)
+    ref_loss = torch.full((1,), 1.5, dtype=torch.float64, device=DEV)
+    rgv = P.spline_misfit(d, v, tv, wv, ref_loss) if tv is not None else None
+    rgl = P.spline_misfit(d, l, tl, wl, ref_loss) if tl is not None else None
+    nb = P.spline_cells_work_bytes(d, n)
+    work = torch.empty(nb, dtype=torch.uint8, device=DEV)
+    loss = torch.full((1,), 1.5, dtype=torch.float64, device=DEV)
+    gv, gl, _ = P.spline_fit_terms_cells(d, tab, x, tv, wv, tl, wl, loss=loss, work=work)
+    loss2 = torch.full((1,), 1.5, dtype=torch.float64, device=DEV)
+    gv2, gl2, _ = P.spline_fit_terms_cells(d, tab, x, tv, wv, tl, wl, loss=loss2, work=work, flags=P.SPL_REUSE_SORT)
+    torch.cuda.synchronize()
+    for got, got2, ref in ((gv, gv2, rgv), (gl, gl2, rgl)):
+        if ref is None:
+            assert got is None and got2 is None
+        else:
+            assert torch.equal(got, ref) and torch.equal(got2, ref)
+    assert abs(float(loss) - float(ref_loss)) <= 1e-13 * float(ref_loss)
+    assert float(loss) == float(loss2)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fit_terms_against_oracle(dtype):
+    """The loss of spline_fit_terms_cells against the oracle's values and Laplacians: w_v sum
+    (V - t_v)^2 + w_lap sum (lap - t_lap)^2 with V and lap evaluated in FP64 from the table the
+    kernel reads (within the output type's rounding of each residual)."""
+    d, tab, pos, beta, _ = _case((6, 5, 7), 37, 1500, dtype, False, 119)
+    n = pos.shape[0]
+    rng = np.random.default_rng(120)
+    ov, _, ol = oeval.eval_vgl(oq.quantized(beta, dtype), SKEW, pos)
+    t_v = ov + 0.1 * rng.standard_normal(ov.shape)
+    t_l = ol + 0.5 * rng.standard_normal(ol.shape)
+    od = torch.float64 if dtype == "f64" else torch.float32
+    nd = np.float64 if dtype == "f64" else np.float32
+    wv, wl = 0.7, 0.05
+    say("fit terms against the oracle", dtype)
+    gv, gl, loss = P.spline_fit_terms_cells(d, tab, to_dev(pos), to_dev(t_v, od), wv, to_dev(t_l, od), wl)
+    torch.cuda.synchronize()
+    tv, tl = t_v.astype(nd).astype(np.float64), t_l.astype(nd).astype(np.float64)
+    ref = wv * np.sum((ov - tv) ** 2) + wl * np.sum((ol - tl) ** 2)
+    tol = 1e-11 if dtype == "f64" else 1e-5
+    assert abs(float(loss) - ref) <= tol * ref
+    assert normwise(gv.double().cpu().numpy(), 2 * wv * (ov - tv)) <= tol
+    assert normwise(gl.double().cpu().numpy(), 2 * wl * (ol - tl)) <= tol
+
+
+def test_fit_terms_nonfinite_points():
+    """A non-finite point: its gradient rows are NaN and the loss is NaN; all points non-finite
+    likewise; the finite points' gradients are unaffected."""
+    d, tab, pos, _, _ = _case((6, 5, 7), 9, 700, "f32", False, 121)
+    pos[11] = [np.inf, 0.0, 0.0]
+    x = to_dev(pos)
+    rng = np.random.default_rng(122)
+    tv = to_dev(rng.standard_normal((700, 9)), torch.float32)
+    say("fit terms, non-finite points")
+    gv, _, loss = P.spline_fit_terms_cells(d, tab, x, tv, 1.0)
+    v, _, _ = P.spline_eval_vgl_cells(d, tab, x, outputs="v")
+    rl = torch.zeros(1, dtype=torch.float64, device=DEV)
+    rg = P.spline_misfit(d, v, tv, 1.0, rl)
+    bad = to_dev(np.full((40, 3), np.nan))
+    tb = torch.zeros((40, 9), dtype=torch.float32, device=DEV)
+    gb, _, lb = P.spline_fit_terms_cells(d, tab, bad, tb, 1.0)
+    torch.cuda.synchronize()
+    assert torch.isnan(gv[11]).all() and math.isnan(float(loss))
+    keep = torch.ones(700, dtype=torch.bool)
+    keep[11] = False
+    assert torch.equal(gv[keep.to(DEV)], rg[keep.to(DEV)])
+    assert torch.isnan(gb).all() and math.isnan(float(lb))

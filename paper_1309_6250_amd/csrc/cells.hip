@@ -706,7 +706,8 @@ template <> struct Stored<uint16_t> {   // BF16 bits -> FP32
 // FIT: every term has a target (spline_fit_terms_cells); the targets of a batch are loaded before
 // its products, so their latency hides behind the matrix-core work
 template <typename TS, typename A, int OT, int NT, bool FIT>
-__global__ __launch_bounds__(64) void k_fwd_cells(FwdArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIT && sizeof(A) == 4 ? 3 : 1)))
+void k_fwd_cells(FwdArgs a) {
   using M = Mfma<A>;
   using Acc = typename M::acc;
   constexpr int BW = 16 * OT;
@@ -781,13 +782,16 @@ __global__ __launch_bounds__(64) void k_fwd_cells(FwdArgs a) {
       }
       __syncthreads();
       const int tiles = nb > 16 ? 2 : 1;
-      // fit: every lane loads the targets of its outputs without branching (an entry with no
-      // output reads element 0 instead and goes unused), so the loads stay countable and one
-      // wait after the products covers them
-      A tg[FIT ? 2 : 1][FIT ? NT : 1][OT][4];
-      if constexpr (FIT) {
+      // one tile of 16 points at a time (targets, products, write-out): half the registers of
+      // both tiles at once
 #pragma unroll
-        for (int mt_ = 0; mt_ < 2; ++mt_)
+      for (int mt_ = 0; mt_ < 2; ++mt_) {
+        if (mt_ >= tiles) break;
+        // fit: every lane loads the targets of its outputs without branching (an entry with no
+        // output reads element 0 instead and goes unused), so the loads stay countable and one
+        // wait after the products covers them
+        A tg[FIT ? NT : 1][OT][4];
+        if constexpr (FIT) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int j = mt_ * 16 + M::row(grp, e);
@@ -798,24 +802,19 @@ __global__ __launch_bounds__(64) void k_fwd_cells(FwdArgs a) {
               const A* base = static_cast<const A*>(a.target[cc]);
 #pragma unroll
               for (int ot = 0; ot < OT; ++ot) {
-                const bool ok = mt_ < tiles && c < nt && p >= 0 && ocol[ot];
-                tg[mt_][c][ot][e] = base[ok ? p * a.out_stride[cc] + ob + 16 * ot + col : 0];
+                const bool ok = c < nt && p >= 0 && ocol[ot];
+                tg[c][ot][e] = base[ok ? p * a.out_stride[cc] + ob + 16 * ot + col : 0];
               }
             }
           }
-      }
-      Acc acc[2][NT][OT];
-#pragma unroll
-      for (int mt_ = 0; mt_ < 2; ++mt_)
+        }
+        Acc acc[NT][OT];
 #pragma unroll
         for (int c = 0; c < NT; ++c)
 #pragma unroll
-          for (int ot = 0; ot < OT; ++ot) acc[mt_][c][ot] = Acc{};
-      // row (l, m, n) of k-step 4 l + m, lane group n: per point and m each term's weight is
-      // Q2 w_x''[l] + Q1 w_x'[l] + Q0 w_x[l], with Q0..Q2 from the y and z weights (as in the adjoint)
-#pragma unroll
-      for (int mt_ = 0; mt_ < 2; ++mt_) {
-        if (mt_ >= tiles) break;
+          for (int ot = 0; ot < OT; ++ot) acc[c][ot] = Acc{};
+        // row (l, m, n) of k-step 4 l + m, lane group n: per point and m each term's weight is
+        // Q2 w_x''[l] + Q1 w_x'[l] + Q0 w_x[l], with Q0..Q2 from the y and z weights (as in the adjoint)
         const A* wp = s_w + min(mt_ * 16 + col, nb - 1) * WS;     // points past nb multiply valid weights
         A wx[4], dwx[4], d2wx[4];
 #pragma unroll
@@ -851,17 +850,13 @@ __global__ __launch_bounds__(64) void k_fwd_cells(FwdArgs a) {
               const A av = fmaa(q2, d2wx[l], fmaa(q1, dwx[l], q0 * wx[l]));
 #pragma unroll
               for (int ot = 0; ot < OT; ++ot)
-                acc[mt_][c][ot] = M::step(av, lt ? b1[4 * l + m][ot] : b0[4 * l + m][ot], acc[mt_][c][ot]);
+                acc[c][ot] = M::step(av, lt ? b1[4 * l + m][ot] : b0[4 * l + m][ot], acc[c][ot]);
             }
           }
         }
-      }
-      // vmcnt(0): the targets have arrived (the products took far longer than the loads)
-      if constexpr (FIT) __builtin_amdgcn_s_waitcnt(0x0f70);
-      // out[point][o]: element e of lane (grp, col) is point row(grp, e) of the tile, orbital col
-#pragma unroll
-      for (int mt_ = 0; mt_ < 2; ++mt_) {
-        if (mt_ >= tiles) break;
+        // vmcnt(0): the targets have arrived (the products took far longer than the loads)
+        if constexpr (FIT) __builtin_amdgcn_s_waitcnt(0x0f70);
+        // out[point][o]: element e of lane (grp, col) is point row(grp, e) of the tile, orbital col
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int j = mt_ * 16 + M::row(grp, e);
@@ -876,14 +871,14 @@ __global__ __launch_bounds__(64) void k_fwd_cells(FwdArgs a) {
 #pragma unroll
               for (int ot = 0; ot < OT; ++ot)
                 if (ocol[ot]) {
-                  const A res = acc[mt_][c][ot][e] - tg[mt_][c][ot][e];
+                  const A res = acc[c][ot][e] - tg[c][ot][e];
                   out[16 * ot] = two_w * res;
                   sq = fma(a.w[c] * (double)res, (double)res, sq);
                 }
             } else {
 #pragma unroll
               for (int ot = 0; ot < OT; ++ot)
-                if (ocol[ot]) out[16 * ot] = acc[mt_][c][ot][e];
+                if (ocol[ot]) out[16 * ot] = acc[c][ot][e];
             }
           }
         }
@@ -899,18 +894,28 @@ __global__ __launch_bounds__(64) void k_fwd_cells(FwdArgs a) {
 }
 
 // loss += the work items' partial sums, in a fixed order; NaN when a point is not finite (its terms
-// are NaN, as the misfit of its NaN outputs would be)
-__global__ __launch_bounds__(256) void k_fit_total(const int32_t* class_start, int32_t n_classes, int32_t n_pts,
-                                                   int64_t n_cells, int32_t n_groups, const int64_t* keys,
-                                                   int64_t sentinel, const double* partial, double* loss) {
-  __shared__ double red[256];
+// are NaN, as the misfit of its NaN outputs would be).  Each of the 1024 threads keeps 8 running
+// sums over its strided share, so 8 loads are in flight per thread; then a fixed tree in LDS.
+constexpr int FIT_TOTAL_THREADS = 1024;
+__global__ __launch_bounds__(FIT_TOTAL_THREADS) void k_fit_total(const int32_t* class_start, int32_t n_classes,
+                                                                 int32_t n_pts, int64_t n_cells, int32_t n_groups,
+                                                                 const int64_t* keys, int64_t sentinel,
+                                                                 const double* partial, double* loss) {
+  __shared__ double red[FIT_TOTAL_THREADS];
   const int64_t n_runs = min((int64_t)min(max(class_start[n_classes], 0), n_pts), n_cells);
   const int64_t n_work = n_runs * n_groups;
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n_work; i += 256) s += partial[i];
-  red[threadIdx.x] = s;
+  constexpr int64_t T = FIT_TOTAL_THREADS;
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int64_t i = threadIdx.x;
+  for (; i + 7 * T < n_work; i += 8 * T)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] += partial[i + u * T];
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+    if (i + u * T < n_work) acc[u] += partial[i + u * T];
+  red[threadIdx.x] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
+  for (int h = FIT_TOTAL_THREADS / 2; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
@@ -1029,8 +1034,8 @@ int launch_eval_cells(const spl_desc* d, const void* table, int64_t n_pts, const
   if ((rc = hip_fail(hipGetLastError(), "cell forward launch"))) return rc;
   const int n = (int)n_pts;
   if (fit) {
-    hipLaunchKernelGGL(k_fit_total, dim3(1), dim3(256), 0, stream, cs.class_start, (int32_t)L.n_classes, a.n_pts,
-                       L.n_cells, a.n_groups, cs.keys, (int64_t)L.n_classes * L.n_cells, a.partial, fit->loss);
+    hipLaunchKernelGGL(k_fit_total, dim3(1), dim3(FIT_TOTAL_THREADS), 0, stream, cs.class_start,
+                       (int32_t)L.n_classes, a.n_pts, L.n_cells, a.n_groups, cs.keys, (int64_t)L.n_classes * L.n_cells, a.partial, fit->loss);
     if ((rc = hip_fail(hipGetLastError(), "fit total launch"))) return rc;
   }
   if (d->dtype == SPL_F64)

@@ -705,7 +705,8 @@ template <> struct Stored<uint16_t> {   // BF16 bits -> FP32
 
 // FIT: every term has a target (spline_fit_terms_cells); the targets of a batch are loaded before
 // its products, so their latency hides behind the matrix-core work
-template <typename TS, typename A, int OT, int NT, bool FIT>
+// LT: some term reads the separate Laplacian table (else its operands take no registers)
+template <typename TS, typename A, int OT, int NT, bool FIT, bool LT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIT && sizeof(A) == 4 ? 3 : 1)))
 void k_fwd_cells(FwdArgs a) {
   using M = Mfma<A>;
@@ -751,7 +752,7 @@ void k_fwd_cells(FwdArgs a) {
 #pragma unroll
     for (int ot = 0; ot < OT; ++ot) ocol[ot] = ob + ot * 16 + col < a.n_orb;
     // the cell's block as B operands, of the orbital table and (when used) the Laplacian table
-    A b0[16][OT], b1[16][OT];
+    A b0[16][OT], b1[LT ? 16 : 1][OT];
 #pragma unroll
     for (int ks = 0; ks < 16; ++ks) {
       const int64_t row = (int64_t)ix[ks >> 2] * a.g.s0 + (int64_t)iy[ks & 3] * a.g.s1 + (int64_t)iz[grp] * a.g.o_pad;
@@ -759,7 +760,7 @@ void k_fwd_cells(FwdArgs a) {
       for (int ot = 0; ot < OT; ++ot) {
         const int64_t at = row + ob + ot * 16 + col;
         b0[ks][ot] = ocol[ot] ? (A)Stored<TS>::at(tab + at) : A(0);
-        b1[ks][ot] = (ocol[ot] && a.use_lap_table) ? (A)Stored<TS>::at(tab + a.lap_off + at) : A(0);
+        if constexpr (LT) b1[ks][ot] = ocol[ot] ? (A)Stored<TS>::at(tab + a.lap_off + at) : A(0);
       }
     }
     for (int b0p = 0; b0p < cnt; b0p += 32) {
@@ -850,7 +851,7 @@ void k_fwd_cells(FwdArgs a) {
               const A av = fmaa(q2, d2wx[l], fmaa(q1, dwx[l], q0 * wx[l]));
 #pragma unroll
               for (int ot = 0; ot < OT; ++ot)
-                acc[c][ot] = M::step(av, lt ? b1[4 * l + m][ot] : b0[4 * l + m][ot], acc[c][ot]);
+                acc[c][ot] = M::step(av, (LT && lt) ? b1[LT ? 4 * l + m : 0][ot] : b0[4 * l + m][ot], acc[c][ot]);
             }
           }
         }
@@ -941,15 +942,20 @@ typedef void (*FwdKernel)(FwdArgs);
 
 // FP32 with at most two terms: two orbital tiles per wave; otherwise one (accumulator registers)
 // (the fit terms come in at most two: values and Laplacians)
-template <typename TS, typename A>
-static FwdKernel pick_fwd(int nt, bool fit) {
+template <typename TS, typename A, bool LT>
+static FwdKernel pick_fwd_lt(int nt, bool fit) {
   if (fit) {
-    if constexpr (sizeof(A) == 4) return k_fwd_cells<TS, A, 2, 2, true>;
-    else return k_fwd_cells<TS, A, 1, 2, true>;
+    if constexpr (sizeof(A) == 4) return k_fwd_cells<TS, A, 2, 2, true, LT>;
+    else return k_fwd_cells<TS, A, 1, 2, true, LT>;
   }
   if constexpr (sizeof(A) == 4)
-    if (nt <= 2) return k_fwd_cells<TS, A, 2, 2, false>;
-  return nt <= 2 ? k_fwd_cells<TS, A, 1, 2, false> : k_fwd_cells<TS, A, 1, 5, false>;
+    if (nt <= 2) return k_fwd_cells<TS, A, 2, 2, false, LT>;
+  return nt <= 2 ? k_fwd_cells<TS, A, 1, 2, false, LT> : k_fwd_cells<TS, A, 1, 5, false, LT>;
+}
+
+template <typename TS, typename A>
+static FwdKernel pick_fwd(int nt, bool fit, bool lt) {
+  return lt ? pick_fwd_lt<TS, A, true>(nt, fit) : pick_fwd_lt<TS, A, false>(nt, fit);
 }
 
 static int fwd_tiles(int dtype, int nt) { return dtype != SPL_F64 && nt <= 2 ? 2 : 1; }
@@ -1026,9 +1032,10 @@ int launch_eval_cells(const spl_desc* d, const void* table, int64_t n_pts, const
   const int ot = fwd_tiles(d->dtype, nt);
   a.n_groups = (d->n_orb + 16 * ot - 1) / (16 * ot);
   FwdKernel k;
-  if (d->dtype == SPL_F64) k = pick_fwd<double, double>(nt, fit != nullptr);
-  else if (d->dtype == SPL_F32) k = pick_fwd<float, float>(nt, fit != nullptr);
-  else k = pick_fwd<uint16_t, float>(nt, fit != nullptr);
+  const bool lt = a.use_lap_table != 0;
+  if (d->dtype == SPL_F64) k = pick_fwd<double, double>(nt, fit != nullptr, lt);
+  else if (d->dtype == SPL_F32) k = pick_fwd<float, float>(nt, fit != nullptr, lt);
+  else k = pick_fwd<uint16_t, float>(nt, fit != nullptr, lt);
   const int grid = (int)std::min<int64_t>(std::min<int64_t>(n_pts, L.n_cells) * a.n_groups, 1 << 16);
   hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, stream, a);
   if ((rc = hip_fail(hipGetLastError(), "cell forward launch"))) return rc;

@@ -549,7 +549,7 @@ def fit_rows(steps, warmup, adam_steps=50):
                                      "deterministic_gradient": True, "heldout": res,
                                      "note": "per step: spline_fit_terms_cells (cell-wise forward with the misfit "
                                              "of V and lap), deterministic adjoint and smoothness penalty on the "
-                                             "cell sort of the first step; Adam update as tensor ops on the "
+                                             "cell sort of the first step; torch's fused Adam on the "
                                              "16.8 MB table; after 2 untimed steps"}
     return out
 

@@ -12,7 +12,7 @@ by Adam.  Two forms of the same loss:
 - FitProblem.loss_and_grad, used by fit_adam: every term runs in the library's kernels
   (spline_fit_terms_cells, the cell-wise forward of V and lap that forms the upstream gradients
   2 w (y - t) as it evaluates and sums the squared residuals in FP64 in a fixed order; the
-  adjoint; spline_smoothness_penalty on the table); only the Adam update is a tensor operation.
+  adjoint; spline_smoothness_penalty on the table); the Adam update is torch's fused Adam.
   Buffers are allocated once.  With fused=False the forward writes V and lap and spline_misfit
   forms the same gradients from them in a second pass.
 - make_loss, a differentiable function of the table built on SplineVGL, for use inside a
@@ -141,7 +141,8 @@ def fit_adam(desc, table, pos, v_t, lap_t, steps=200, lam=1e-3, lr=None, use_lap
     beta = table.detach().clone().requires_grad_(True)
     if lr is None:
         lr = 1e-3 * float(torch.sqrt(torch.mean(table.detach().to(torch.float64) ** 2)))
-    opt = torch.optim.Adam([beta], lr=lr, betas=(0.9, 0.999))
+    # torch's fused Adam: the whole update of the table in one kernel
+    opt = torch.optim.Adam([beta], lr=lr, betas=(0.9, 0.999), fused=beta.is_cuda)
     start, done = 0, []
     if checkpoint is not None and os.path.exists(checkpoint):
         state = torch.load(checkpoint, map_location=beta.device, weights_only=True)

@@ -24,7 +24,10 @@
 // Either way the result is reproducible bit for bit.
 //
 // Forward.  A wave loads a cell's block once and multiplies it with the row weights of the
-// cell's points, so each block row is read once per cell instead of once per point.
+// cell's points, so each block row is read once per cell instead of once per point.  For the
+// least-squares fit (spline_fit_terms_cells) the same kernel compares its outputs with targets as it
+// writes them: it stores the misfit's upstream gradients instead of the outputs and adds the squared
+// residuals to one FP64 partial sum per work item, summed afterwards in a fixed order.
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>

@@ -56,6 +56,10 @@ struct SortLayout {
 
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
+// the fit terms' loss: workgroups of the first summing step, and threads of both steps
+constexpr int FIT_SUM_BLOCKS = 256;
+constexpr int FIT_SUM_THREADS = 256;
+
 static int sort_layout(const spl_desc* d, int64_t n_pts, SortLayout* L, bool adjoint_blocks = true) {
   L->n_cells = (int64_t)d->grid[0] * d->grid[1] * d->grid[2];
   L->n_classes = axis_colours(d->grid[0]) * axis_colours(d->grid[1]) * axis_colours(d->grid[2]);
@@ -97,10 +101,10 @@ static int sort_layout(const spl_desc* d, int64_t n_pts, SortLayout* L, bool adj
   L->occ = off; off = align_up(off + (L->dense ? 4 * (size_t)L->n_cells : 0));
   L->blocks = off; off = align_up(off + (L->dense ? block_bytes : 0));
   // forward only: one FP64 partial sum per work item of the fit terms, at most min(n, cells) runs
-  // times the 16-orbital tiles
+  // times the 16-orbital tiles, then one per workgroup of the first summing step (FIT_SUM_BLOCKS)
   L->partials = off;
   if (!adjoint_blocks)
-    off = align_up(off + 8 * (size_t)std::min<int64_t>(n_pts, L->n_cells) * (size_t)((d->n_orb + 15) / 16));
+    off = align_up(off + 8 * ((size_t)std::min<int64_t>(n_pts, L->n_cells) * (size_t)((d->n_orb + 15) / 16) + FIT_SUM_BLOCKS));
   L->temp = off; off = align_up(off + L->temp_bytes);
   L->total = off;
   return SPL_OK;
@@ -897,33 +901,44 @@ void k_fwd_cells(FwdArgs a) {
   }
 }
 
-// loss += the work items' partial sums, in a fixed order; NaN when a point is not finite (its terms
-// are NaN, as the misfit of its NaN outputs would be).  Each of the 1024 threads keeps 8 running
-// sums over its strided share, so 8 loads are in flight per thread; then a fixed tree in LDS.
-constexpr int FIT_TOTAL_THREADS = 1024;
-__global__ __launch_bounds__(FIT_TOTAL_THREADS) void k_fit_total(const int32_t* class_start, int32_t n_classes,
-                                                                 int32_t n_pts, int64_t n_cells, int32_t n_groups,
-                                                                 const int64_t* keys, int64_t sentinel,
-                                                                 const double* partial, double* loss) {
-  __shared__ double red[FIT_TOTAL_THREADS];
-  const int64_t n_runs = min((int64_t)min(max(class_start[n_classes], 0), n_pts), n_cells);
-  const int64_t n_work = n_runs * n_groups;
-  constexpr int64_t T = FIT_TOTAL_THREADS;
-  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  int64_t i = threadIdx.x;
-  for (; i + 7 * T < n_work; i += 8 * T)
-#pragma unroll
-    for (int u = 0; u < 8; ++u) acc[u] += partial[i + u * T];
-#pragma unroll
-  for (int u = 0; u < 8; ++u)
-    if (i + u * T < n_work) acc[u] += partial[i + u * T];
-  red[threadIdx.x] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+// loss += the work items' partial sums, in a fixed order, in two steps.  First FIT_SUM_BLOCKS
+// workgroups: thread t of workgroup b sums the partials b T + t + k (FIT_SUM_BLOCKS T), then a fixed
+// tree in LDS gives block sum b.  Then one workgroup adds the block sums in a fixed tree to *loss,
+// or NaN when a point is not finite (its terms are NaN, as the misfit of its NaN outputs would be).
+__device__ __forceinline__ double block_tree_sum(double v, double* red) {
+  red[threadIdx.x] = v;
   __syncthreads();
-  for (int h = FIT_TOTAL_THREADS / 2; h > 0; h >>= 1) {
+  for (int h = FIT_SUM_THREADS / 2; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *loss += keys[n_pts - 1] == sentinel ? (double)__builtin_nan("") : red[0];
+  return red[0];
+}
+
+__global__ __launch_bounds__(FIT_SUM_THREADS) void k_fit_blocks(const int32_t* class_start, int32_t n_classes,
+                                                                int32_t n_pts, int64_t n_cells, int32_t n_groups,
+                                                                const double* partial, double* block_sum) {
+  __shared__ double red[FIT_SUM_THREADS];
+  const int64_t n_runs = min((int64_t)min(max(class_start[n_classes], 0), n_pts), n_cells);
+  const int64_t n_work = n_runs * n_groups;
+  constexpr int64_t S = (int64_t)FIT_SUM_BLOCKS * FIT_SUM_THREADS;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int64_t i = (int64_t)blockIdx.x * FIT_SUM_THREADS + threadIdx.x;
+  for (; i + 3 * S < n_work; i += 4 * S)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] += partial[i + u * S];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (i + u * S < n_work) acc[u] += partial[i + u * S];
+  const double s = block_tree_sum((acc[0] + acc[1]) + (acc[2] + acc[3]), red);
+  if (threadIdx.x == 0) block_sum[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(FIT_SUM_THREADS) void k_fit_total(const double* block_sum, const int64_t* keys,
+                                                               int32_t n_pts, int64_t sentinel, double* loss) {
+  __shared__ double red[FIT_SUM_THREADS];
+  const double s = block_tree_sum(threadIdx.x < FIT_SUM_BLOCKS ? block_sum[threadIdx.x] : 0.0, red);
+  if (threadIdx.x == 0) *loss += keys[n_pts - 1] == sentinel ? (double)__builtin_nan("") : s;
 }
 
 // Non-finite points (sorted last under the sentinel key) get NaN in every requested output.
@@ -1044,8 +1059,13 @@ int launch_eval_cells(const spl_desc* d, const void* table, int64_t n_pts, const
   if ((rc = hip_fail(hipGetLastError(), "cell forward launch"))) return rc;
   const int n = (int)n_pts;
   if (fit) {
-    hipLaunchKernelGGL(k_fit_total, dim3(1), dim3(FIT_TOTAL_THREADS), 0, stream, cs.class_start,
-                       (int32_t)L.n_classes, a.n_pts, L.n_cells, a.n_groups, cs.keys, (int64_t)L.n_classes * L.n_cells, a.partial, fit->loss);
+    // the block sums follow the work items' partials (at most min(n, cells) runs x 16-orbital tiles)
+    double* block_sum = a.partial + std::min<int64_t>(n_pts, L.n_cells) * (int64_t)((d->n_orb + 15) / 16);
+    hipLaunchKernelGGL(k_fit_blocks, dim3(FIT_SUM_BLOCKS), dim3(FIT_SUM_THREADS), 0, stream, cs.class_start,
+                       (int32_t)L.n_classes, a.n_pts, L.n_cells, a.n_groups, a.partial, block_sum);
+    if ((rc = hip_fail(hipGetLastError(), "fit block sums launch"))) return rc;
+    hipLaunchKernelGGL(k_fit_total, dim3(1), dim3(FIT_SUM_THREADS), 0, stream, block_sum, cs.keys, a.n_pts,
+                       (int64_t)L.n_classes * L.n_cells, fit->loss);
     if ((rc = hip_fail(hipGetLastError(), "fit total launch"))) return rc;
   }
   if (d->dtype == SPL_F64)

@@ -291,12 +291,13 @@ def spline_eval_vgl_cells(desc, table, pos, v=None, grad=None, lap=None, outputs
     return v, grad, lap
 
 
-def spline_fit_terms_cells(desc, table, pos, t_v=None, w_v=0.0, t_lap=None, w_lap=0.0, g_v=None, g_lap=None,
+def spline_fit_terms_cells(desc, table, pos, t_v=None, w_v=1.0, t_lap=None, w_lap=1.0, g_v=None, g_lap=None,
                            loss=None, work=None, flags=0, stream=None):
     """The misfit of values and Laplacians against targets t_v, t_lap ([n_pts, n_orb], output type)
     straight from the cell-wise evaluation: returns (g_v, g_lap, loss) with g = 2 w (y - t) (None for
-    a term without a target) and loss (a one-element FP64 device tensor) accumulated into.  flags:
-    SPL_REUSE_SORT when `work` already holds the cell sort of these same points."""
+    a term without a target) and loss (a one-element FP64 device tensor, zero if not given)
+    accumulated into.  flags: SPL_REUSE_SORT when `work` already holds the cell sort of these same
+    points."""
     n = _check_inputs(desc, table, pos)
     od = OUT_TORCH[desc.dtype]
     dev = pos.device

@@ -714,7 +714,8 @@ template <> struct Stored<uint16_t> {   // BF16 bits -> FP32
 // its products, so their latency hides behind the matrix-core work
 // LT: some term reads the separate Laplacian table (else its operands take no registers)
 template <typename TS, typename A, int OT, int NT, bool FIT, bool LT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIT && sizeof(A) == 4 ? 3 : 1)))
+__global__ __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(sizeof(A) == 4 && (FIT || (OT == 2 && NT == 5 && !LT)) ? 3 : 1)))
 void k_fwd_cells(FwdArgs a) {
   using M = Mfma<A>;
   using Acc = typename M::acc;
@@ -966,8 +967,10 @@ static FwdKernel pick_fwd_lt(int nt, bool fit) {
     if constexpr (sizeof(A) == 4) return k_fwd_cells<TS, A, 2, 2, true, LT>;
     else return k_fwd_cells<TS, A, 1, 2, true, LT>;
   }
-  if constexpr (sizeof(A) == 4)
+  if constexpr (sizeof(A) == 4) {
     if (nt <= 2) return k_fwd_cells<TS, A, 2, 2, false, LT>;
+    if constexpr (!LT) return k_fwd_cells<TS, A, 2, 5, false, LT>;
+  }
   return nt <= 2 ? k_fwd_cells<TS, A, 1, 2, false, LT> : k_fwd_cells<TS, A, 1, 5, false, LT>;
 }
 
@@ -976,7 +979,7 @@ static FwdKernel pick_fwd(int nt, bool fit, bool lt) {
   return lt ? pick_fwd_lt<TS, A, true>(nt, fit) : pick_fwd_lt<TS, A, false>(nt, fit);
 }
 
-static int fwd_tiles(int dtype, int nt) { return dtype != SPL_F64 && nt <= 2 ? 2 : 1; }
+static int fwd_tiles(int dtype, int nt, bool lt) { return dtype != SPL_F64 && (nt <= 2 || !lt) ? 2 : 1; }
 
 int cells_eval_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes) {
   SortLayout L;
@@ -1047,7 +1050,7 @@ int launch_eval_cells(const spl_desc* d, const void* table, int64_t n_pts, const
   a.n_classes = L.n_classes;
   a.n_pts = (int32_t)n_pts;
   a.n_orb = d->n_orb;
-  const int ot = fwd_tiles(d->dtype, nt);
+  const int ot = fwd_tiles(d->dtype, nt, a.use_lap_table != 0);
   a.n_groups = (d->n_orb + 16 * ot - 1) / (16 * ot);
   FwdKernel k;
   const bool lt = a.use_lap_table != 0;

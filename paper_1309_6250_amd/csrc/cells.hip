@@ -29,6 +29,7 @@
 // writes them: it stores the misfit's upstream gradients instead of the outputs and adds the squared
 // residuals to one FP64 partial sum per work item, summed afterwards in a fixed order.
 #include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include <algorithm>
 #include <cstring>
@@ -56,6 +57,19 @@ struct SortLayout {
 
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
+// The stable sort of the cell keys (point index as value).  rocPRIM's radix sort uses a block sort
+// followed by merge passes up to 2^20 items; at the fit's 10^6 points that path took about 190 us
+// (ten merge passes) and onesweep about 100 us less, while at 65 536 points the merge path is the
+// faster by about 40 us.  So merge sort up to 2^18 items, onesweep above.  Both are stable: the
+// sorted order, and every sum formed in it, is the same either way.
+using CellSortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
+                                                  rocprim::default_config, (size_t)1 << 18>;
+static hipError_t sort_cell_keys(void* temp, size_t& bytes, const int64_t* keys_in, int64_t* keys_out,
+                                 const int32_t* vals_in, int32_t* vals_out, int n, int end_bit, hipStream_t stream) {
+  return rocprim::radix_sort_pairs<CellSortConfig>(temp, bytes, keys_in, keys_out, vals_in, vals_out, n, 0,
+                                                   (unsigned)end_bit, stream);
+}
+
 // the fit terms' loss: workgroups of the first summing step, and threads of both steps
 constexpr int FIT_SUM_BLOCKS = 256;
 constexpr int FIT_SUM_THREADS = 256;
@@ -69,9 +83,7 @@ static int sort_layout(const spl_desc* d, int64_t n_pts, SortLayout* L, bool adj
   L->end_bit = bits;
   const size_t n = (size_t)n_pts;
   size_t t1 = 0, t2 = 0, t3 = 0;
-  int rc = hip_fail(hipcub::DeviceRadixSort::SortPairs(nullptr, t1, (const int64_t*)nullptr, (int64_t*)nullptr,
-                                                       (const int32_t*)nullptr, (int32_t*)nullptr, (int)n, 0,
-                                                       L->end_bit, (hipStream_t)0),
+  int rc = hip_fail(sort_cell_keys(nullptr, t1, nullptr, nullptr, nullptr, nullptr, (int)n, L->end_bit, nullptr),
                     "radix sort size query");
   if (rc) return rc;
   rc = hip_fail(hipcub::DeviceRunLengthEncode::Encode(nullptr, t2, (const int64_t*)nullptr, (int64_t*)nullptr,
@@ -522,8 +534,8 @@ static int cell_sort(const spl_desc* d, int64_t n_pts, const double* pos, void* 
                      (int64_t)L.n_classes * L.n_cells, keys_in, vals_in);
   if ((rc = hip_fail(hipGetLastError(), "cell key launch"))) return rc;
   size_t tb = L.temp_bytes;
-  if ((rc = hip_fail(hipcub::DeviceRadixSort::SortPairs(temp, tb, keys_in, keys_out, vals_in, vals_out, n, 0,
-                                                        L.end_bit, stream), "radix sort")))
+  if ((rc = hip_fail(sort_cell_keys(temp, tb, keys_in, keys_out, vals_in, vals_out, n, L.end_bit, stream),
+                     "radix sort")))
     return rc;
   tb = L.temp_bytes;
   if ((rc = hip_fail(hipcub::DeviceRunLengthEncode::Encode(temp, tb, keys_out, uniq, counts, num_runs, n, stream),

@@ -749,11 +749,16 @@ void k_fwd_cells(FwdArgs a) {
   using M = Mfma<A>;
   using Acc = typename M::acc;
   constexpr int BW = 16 * OT;
-  // BF16 tables with two tiles: tile ot holds the orbitals ob + 2 col + ot, so each lane's pair is
-  // adjacent and its coefficients come in one 4-byte load instead of two 2-byte ones.  Otherwise
-  // tile ot holds ob + 16 ot + col: a store instruction then covers 64 contiguous bytes, where the
-  // interleaved tiles write every other word of 128 (FP32 fit terms 0.78 -> 0.82 ms with pairs)
-  constexpr bool PAIR = OT == 2 && sizeof(TS) == 2;
+  // two tiles: tile ot holds the orbitals ob + 2 col + ot, so each lane's two orbitals are adjacent:
+  // their coefficients come in one load and, where the output allows it, their results leave in
+  // one 8-byte store (a store instruction then covers 128 contiguous bytes).  Otherwise tile ot
+  // holds ob + 16 ot + col.  Not for the FP32 fit terms: their targets load as single values, and
+  // with interleaved tiles each such load covers every other word of 128 bytes (0.78 -> 0.82 ms).
+  constexpr bool PAIR = OT == 2 && (!FIT || sizeof(TS) == 2);
+  bool pst[NT];                                      // term c's outputs take 8-byte stores
+#pragma unroll
+  for (int c = 0; c < NT; ++c)
+    pst[c] = PAIR && c < a.n_terms && ((uintptr_t)a.out[c] & 7) == 0 && (a.out_stride[c] & 1) == 0;
   constexpr int WS = 37;                             // weight row stride in LDS (odd: no bank conflicts)
   __shared__ int s_p[32];
   __shared__ A s_w[32 * WS];                         // per point: x, y, z  x  (w[4], w'[4], w''[4])
@@ -925,20 +930,28 @@ void k_fwd_cells(FwdArgs a) {
           for (int c = 0; c < NT; ++c) {
             if (c >= nt) break;
             A* out = static_cast<A*>(a.out[c]) + p * a.out_stride[c];
+            A y[OT];
             if constexpr (FIT) {
               const A two_w = (A)(2.0 * a.w[c]);
 #pragma unroll
-              for (int ot = 0; ot < OT; ++ot)
-                if (ocol[ot]) {
-                  const A res = acc[c][ot][e] - tg[c][ot][e];
-                  out[orb[ot]] = two_w * res;
-                  sq = fma(a.w[c] * (double)res, (double)res, sq);
-                }
+              for (int ot = 0; ot < OT; ++ot) {
+                const A res = acc[c][ot][e] - tg[c][ot][e];
+                y[ot] = two_w * res;
+                if (ocol[ot]) sq = fma(a.w[c] * (double)res, (double)res, sq);
+              }
             } else {
 #pragma unroll
-              for (int ot = 0; ot < OT; ++ot)
-                if (ocol[ot]) out[orb[ot]] = acc[c][ot][e];
+              for (int ot = 0; ot < OT; ++ot) y[ot] = acc[c][ot][e];
             }
+            if constexpr (PAIR) {
+              if (pst[c] && ocol[1]) {
+                *reinterpret_cast<float2*>(out + orb[0]) = make_float2(y[0], y[1]);
+                continue;
+              }
+            }
+#pragma unroll
+            for (int ot = 0; ot < OT; ++ot)
+              if (ocol[ot]) out[orb[ot]] = y[ot];
           }
         }
       }

@@ -233,3 +233,35 @@ def test_fit_terms_nonfinite_points():
     keep[11] = False
     assert torch.equal(gv[keep.to(DEV)], rg[keep.to(DEV)])
     assert torch.isnan(gb).all() and math.isnan(float(lb))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_cells_outputs_at_odd_offsets(dtype):
+    """Outputs (and the fit terms' targets and gradients) one element past an 8-byte boundary, with
+    an even orbital count: the same bits as aligned buffers (the kernel then stores value by value
+    instead of in pairs)."""
+    n, n_orb = 1500, 20
+    d, tab, pos, _, _ = _case((6, 5, 7), n_orb, n, dtype, False, 123)
+    x = to_dev(pos)
+    m = n * n_orb
+
+    def odd(k=1):
+        return torch.empty(k * m + 1, dtype=torch.float32, device=DEV)[1:]
+    say("cells forward, outputs at odd offsets", dtype)
+    v, g, l = P.spline_eval_vgl_cells(d, tab, x)
+    vo, go, lo = odd(), odd(3), odd()
+    P.spline_eval_vgl_cells(d, tab, x, vo, go, lo)
+    rng = np.random.default_rng(124)
+    tv = to_dev(rng.standard_normal((n, n_orb)), torch.float32)
+    tl = to_dev(rng.standard_normal((n, n_orb)), torch.float32)
+    gv, gl, loss = P.spline_fit_terms_cells(d, tab, x, tv, 0.5, tl, 0.25)
+    tvo, tlo = odd(), odd()
+    tvo.copy_(tv.reshape(-1))
+    tlo.copy_(tl.reshape(-1))
+    gvo, glo = odd(), odd()
+    _, _, loss_o = P.spline_fit_terms_cells(d, tab, x, tvo, 0.5, tlo, 0.25, g_v=gvo, g_lap=glo)
+    torch.cuda.synchronize()
+    assert vo.data_ptr() % 8 == 4
+    for a, b in ((v, vo), (g, go), (l, lo), (gv, gvo), (gl, glo)):
+        assert torch.equal(a.reshape(-1), b)
+    assert float(loss) == float(loss_o)

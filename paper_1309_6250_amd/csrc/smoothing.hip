@@ -94,7 +94,34 @@ struct DftArgs {
   int32_t n;
   int32_t o_pad;
   int32_t bloch;         // final axis: store (re, im) into columns (2o, 2o+1) instead of re into o
+  // lines whose samples are all zero, skipped (they stay zero): line (outer, in) holds a nonzero
+  // sample only if mask[in / mask_div] != 0; NULL: every line is computed
+  const int32_t* mask;
+  int64_t mask_div;
 };
+
+__device__ __forceinline__ bool line_live(const DftArgs& a, int64_t line) {
+  if (line >= a.n_lines) return false;
+  return !a.mask || a.mask[(line % a.inner) / a.mask_div] != 0;
+}
+
+__global__ __launch_bounds__(256) void k_mask_zero(int32_t* m, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    m[i] = 0;
+}
+
+// Which lines of the first two DFT stages can hold nonzero samples: before the first stage (along
+// axis 0) the grid is nonzero only in the columns (b1, b2) of the planewaves' Fourier bins, before
+// the second (along axis 1) only in their planes b2.
+__global__ __launch_bounds__(256) void k_line_masks(const int32_t* miller, int64_t n_g, Geom geo, int32_t* col12,
+                                                    int32_t* plane2) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_g) return;
+  const int b1 = ((miller[3 * g + 1] % geo.n[1]) + geo.n[1]) % geo.n[1];
+  const int b2 = ((miller[3 * g + 2] % geo.n[2]) + geo.n[2]) % geo.n[2];
+  col12[(int64_t)b1 * geo.n[2] + b2] = 1;
+  plane2[b2] = 1;
+}
 
 enum { DFT_INPLACE = 0, DFT_TABLE_F64 = 1, DFT_TABLE_F32 = 2, DFT_TABLE_BF16 = 3 };
 
@@ -121,7 +148,7 @@ __global__ __launch_bounds__(256) void k_idft_axis(DftArgs a) {
   }
   __syncthreads();                        // every thread of the block reaches this barrier
   const int64_t line = (int64_t)blockIdx.x * tile + tid;
-  if (line >= a.n_lines) return;
+  if (!line_live(a, line)) return;
   const int64_t outer = line / a.inner;
   const int64_t in = line - outer * a.inner;
   const int64_t base = outer * (int64_t)n * a.inner + in;
@@ -177,11 +204,13 @@ __global__ __launch_bounds__(64) void k_idft_mfma(DftArgs a) {
   double* xi = xr + 16 * n_pad;           // imaginary parts
   const int lane = (int)threadIdx.x;
   const int grp = lane >> 4, col = lane & 15;
+  const int64_t line0 = (int64_t)blockIdx.x * 16;
+  // the workgroup is this one wave: if none of its 16 lines can be nonzero, they stay zero
+  if (!__any(line_live(a, line0 + col))) return;
   for (int k = lane; k < n; k += 64) {
     tw_c[k] = a.cs[k];
     tw_s[k] = a.sn[k];
   }
-  const int64_t line0 = (int64_t)blockIdx.x * 16;
   for (int e = lane; e < 16 * n_pad; e += 64) {
     const int j = e >> 4, c = e & 15;
     const int64_t line = line0 + c;
@@ -257,8 +286,11 @@ static int dft_tile(int n) {
 
 // One inverse-DFT stage along the middle axis of [outer][n][inner] (twiddles in the workspace).
 static int launch_idft(int out, c2v* data, void* table, const double* cs, const double* sn, int64_t outer, int n,
-                       int64_t inner, int o_pad, int bloch, hipStream_t stream) {
+                       int64_t inner, int o_pad, int bloch, const int32_t* mask, int64_t mask_div,
+                       hipStream_t stream) {
   DftArgs a;
+  a.mask = mask;
+  a.mask_div = mask_div;
   a.data = data;
   a.table = table;
   a.cs = cs;
@@ -293,7 +325,8 @@ static int launch_idft(int out, c2v* data, void* table, const double* cs, const 
 }
 
 int build_smoothing_one(const spl_desc* d, int64_t n_g, const int32_t* miller, const double* coef, int comp,
-                        void* table, void* work, const double* twiddles, hipStream_t stream) {
+                        void* table, void* work, const double* twiddles, const int32_t* col12,
+                        const int32_t* plane2, hipStream_t stream) {
   const int64_t n1 = d->grid[0], n2 = d->grid[1], n3 = d->grid[2], no = d->n_orb;
   c2v* grid = static_cast<c2v*>(work);
   const int64_t cells = n1 * n2 * n3 * no;
@@ -312,10 +345,16 @@ int build_smoothing_one(const spl_desc* d, int64_t n_g, const int32_t* miller, c
   const double* tw0 = twiddles;
   const double* tw1 = tw0 + 2 * n1;
   const double* tw2 = tw1 + 2 * n2;
-  if ((rc = launch_idft(DFT_INPLACE, grid, nullptr, tw0, tw0 + n1, 1, (int)n1, n2 * n3 * no, 0, 0, stream))) return rc;
-  if ((rc = launch_idft(DFT_INPLACE, grid, nullptr, tw1, tw1 + n2, n1, (int)n2, n3 * no, 0, 0, stream))) return rc;
+  // stage 1 lines (b1, b2, o) and stage 2 lines (x, b2, o): only those of occupied columns / planes
+  if ((rc = launch_idft(DFT_INPLACE, grid, nullptr, tw0, tw0 + n1, 1, (int)n1, n2 * n3 * no, 0, 0, col12, no,
+                        stream)))
+    return rc;
+  if ((rc = launch_idft(DFT_INPLACE, grid, nullptr, tw1, tw1 + n2, n1, (int)n2, n3 * no, 0, 0, plane2, no, stream)))
+    return rc;
   const int out = d->dtype == SPL_F64 ? DFT_TABLE_F64 : d->dtype == SPL_F32 ? DFT_TABLE_F32 : DFT_TABLE_BF16;
-  if ((rc = launch_idft(out, grid, table, tw2, tw2 + n3, n1 * n2, (int)n3, no, d->o_pad, d->bloch, stream))) return rc;
+  if ((rc = launch_idft(out, grid, table, tw2, tw2 + n3, n1 * n2, (int)n3, no, d->o_pad, d->bloch, nullptr, 1,
+                        stream)))
+    return rc;
   if (d->o_pad > d->n_col) {
     const int64_t rows = n1 * n2 * n3;
     const int64_t total = rows * (d->o_pad - d->n_col);
@@ -343,9 +382,12 @@ __global__ void k_twiddles(double* tw, int32_t n0, int32_t n1, int32_t n2) {
   tw[base + n + kk] = sin(ang);
 }
 
+// workspace: the complex grid, 256-byte aligned twiddles, then the two line masks
 int64_t smoothing_work_bytes(const spl_desc* d) {
   const int64_t cells = (int64_t)d->grid[0] * d->grid[1] * d->grid[2] * d->n_orb;
-  return cells * 16 + 16 * (int64_t)(d->grid[0] + d->grid[1] + d->grid[2]) + 256;
+  const int64_t tw = 16 * (int64_t)(d->grid[0] + d->grid[1] + d->grid[2]);
+  return ((cells * 16 + 255) & ~int64_t(255)) + ((tw + 255) & ~int64_t(255)) +
+         4 * ((int64_t)d->grid[1] * d->grid[2] + d->grid[2]);
 }
 
 int build_smoothing(const spl_desc* d, int64_t n_g, const int32_t* miller, const double* coef, void* table,
@@ -356,11 +398,24 @@ int build_smoothing(const spl_desc* d, int64_t n_g, const int32_t* miller, const
   hipLaunchKernelGGL(k_twiddles, dim3((nt + 255) / 256), dim3(256), 0, stream, tw, d->grid[0], d->grid[1], d->grid[2]);
   int rc = hip_fail(hipGetLastError(), "twiddle launch");
   if (rc) return rc;
+  // line masks after the twiddles (the same for every table: they depend on the planewaves only)
+  int32_t* col12 = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(tw) + ((16 * (int64_t)nt + 255) & ~int64_t(255)));
+  const int64_t n12 = (int64_t)d->grid[1] * d->grid[2];
+  int32_t* plane2 = col12 + n12;
+  const int64_t n_mask = n12 + d->grid[2];
+  hipLaunchKernelGGL(k_mask_zero, dim3((unsigned)std::min<int64_t>((n_mask + 255) / 256, 4096)), dim3(256), 0, stream,
+                     col12, n_mask);
+  if ((rc = hip_fail(hipGetLastError(), "mask clear launch"))) return rc;
+  if (n_g > 0) {
+    hipLaunchKernelGGL(k_line_masks, dim3((unsigned)((n_g + 255) / 256)), dim3(256), 0, stream, miller, n_g,
+                       make_geom(d), col12, plane2);
+    if ((rc = hip_fail(hipGetLastError(), "line mask launch"))) return rc;
+  }
   // tables in order: orbital, gradient components x, y, z (sep_grad), Laplacian (has_lap)
   for (int t = 0; t < d->n_tables; ++t) {
     const int comp = t == 0 ? COMP_VALUE : (d->sep_grad && t <= 3 ? t : COMP_LAP);
     char* dst = static_cast<char*>(table) + t * d->table_elems * d->elem_bytes;
-    if ((rc = build_smoothing_one(d, n_g, miller, coef, comp, dst, work, tw, stream))) return rc;
+    if ((rc = build_smoothing_one(d, n_g, miller, coef, comp, dst, work, tw, col12, plane2, stream))) return rc;
   }
   return SPL_OK;
 }

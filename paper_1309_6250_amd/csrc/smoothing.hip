@@ -229,6 +229,8 @@ __global__ __launch_bounds__(64) void k_idft_mfma(DftArgs a) {
   const int64_t outer = line_ok ? line / a.inner : 0;
   const int64_t in = line_ok ? line - outer * a.inner : 0;
   const int64_t base = outer * (int64_t)n * a.inner + in;
+  // the last stage of a real table stores the real part only: the imaginary products are skipped
+  const bool need_im = OUT == DFT_INPLACE || a.bloch;
   for (int k0 = 0; k0 < n; k0 += 16) {
     f64x4_s acc_r = {0.0, 0.0, 0.0, 0.0}, acc_i = {0.0, 0.0, 0.0, 0.0};
     const int kk = k0 + col;              // A row: output index (past n: any finite value, not written)
@@ -239,8 +241,10 @@ __global__ __launch_bounds__(64) void k_idft_mfma(DftArgs a) {
       const double br = xr[j * 16 + col], bi = xi[j * 16 + col];
       acc_r = mfma64(c, br, acc_r);
       acc_r = mfma64(-sn, bi, acc_r);
-      acc_i = mfma64(sn, br, acc_i);
-      acc_i = mfma64(c, bi, acc_i);
+      if (need_im) {
+        acc_i = mfma64(sn, br, acc_i);
+        acc_i = mfma64(c, bi, acc_i);
+      }
     }
     if (!line_ok) continue;
 #pragma unroll

@@ -98,6 +98,10 @@ struct DftArgs {
   // sample only if mask[in / mask_div] != 0; NULL: every line is computed
   const int32_t* mask;
   int64_t mask_div;
+  // along the axis, samples j with kb < j < n - kb are zero (kb = band[axis], the largest |Miller
+  // index| on that axis): steps over such samples only are skipped.  NULL: none skipped
+  const int32_t* band;
+  int32_t axis;
 };
 
 __device__ __forceinline__ bool line_live(const DftArgs& a, int64_t line) {
@@ -113,14 +117,17 @@ __global__ __launch_bounds__(256) void k_mask_zero(int32_t* m, int64_t n) {
 // Which lines of the first two DFT stages can hold nonzero samples: before the first stage (along
 // axis 0) the grid is nonzero only in the columns (b1, b2) of the planewaves' Fourier bins, before
 // the second (along axis 1) only in their planes b2.
+// Also the band of each axis: the largest |Miller index| along it.
 __global__ __launch_bounds__(256) void k_line_masks(const int32_t* miller, int64_t n_g, Geom geo, int32_t* col12,
-                                                    int32_t* plane2) {
+                                                    int32_t* plane2, int32_t* band) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n_g) return;
   const int b1 = ((miller[3 * g + 1] % geo.n[1]) + geo.n[1]) % geo.n[1];
   const int b2 = ((miller[3 * g + 2] % geo.n[2]) + geo.n[2]) % geo.n[2];
   col12[(int64_t)b1 * geo.n[2] + b2] = 1;
   plane2[b2] = 1;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) atomicMax(band + c, abs(miller[3 * g + c]));
 }
 
 enum { DFT_INPLACE = 0, DFT_TABLE_F64 = 1, DFT_TABLE_F32 = 2, DFT_TABLE_BF16 = 3 };
@@ -153,10 +160,16 @@ __global__ __launch_bounds__(256) void k_idft_axis(DftArgs a) {
   const int64_t in = line - outer * a.inner;
   const int64_t base = outer * (int64_t)n * a.inner + in;
   for (int j = 0; j < n; ++j) x[j * tile] = a.data[base + (int64_t)j * a.inner];
+  const int kb = a.band ? min(a.band[a.axis], n) : n;
   for (int k = 0; k < n; ++k) {
     double re = 0.0, im = 0.0;
     int idx = 0;                          // (j k) mod n
     for (int j = 0; j < n; ++j) {
+      if (j > kb && j < n - kb) {         // zero samples: jump to the upper end of the band
+        idx = (int)(((int64_t)k * (n - kb)) % n);
+        j = n - kb - 1;
+        continue;
+      }
       const c2v v = x[j * tile];
       const double c = tw_c[idx], s = tw_s[idx];
       re = fmaa(v.x, c, fmaa(-v.y, s, re));
@@ -231,10 +244,12 @@ __global__ __launch_bounds__(64) void k_idft_mfma(DftArgs a) {
   const int64_t base = outer * (int64_t)n * a.inner + in;
   // the last stage of a real table stores the real part only: the imaginary products are skipped
   const bool need_im = OUT == DFT_INPLACE || a.bloch;
+  const int kb = a.band ? min(a.band[a.axis], n) : n;
   for (int k0 = 0; k0 < n; k0 += 16) {
     f64x4_s acc_r = {0.0, 0.0, 0.0, 0.0}, acc_i = {0.0, 0.0, 0.0, 0.0};
     const int kk = k0 + col;              // A row: output index (past n: any finite value, not written)
     for (int j0 = 0; j0 < n_pad; j0 += 4) {
+      if (j0 > kb && j0 + 3 < n - kb) continue;   // four zero samples
       const int j = j0 + grp;             // A column / B row: sample index (past n: X is zero)
       const int idx = (int)(((int64_t)kk * j) % n);
       const double c = tw_c[idx], sn = tw_s[idx];
@@ -291,10 +306,12 @@ static int dft_tile(int n) {
 // One inverse-DFT stage along the middle axis of [outer][n][inner] (twiddles in the workspace).
 static int launch_idft(int out, c2v* data, void* table, const double* cs, const double* sn, int64_t outer, int n,
                        int64_t inner, int o_pad, int bloch, const int32_t* mask, int64_t mask_div,
-                       hipStream_t stream) {
+                       const int32_t* band, int axis, hipStream_t stream) {
   DftArgs a;
   a.mask = mask;
   a.mask_div = mask_div;
+  a.band = band;
+  a.axis = axis;
   a.data = data;
   a.table = table;
   a.cs = cs;
@@ -330,7 +347,7 @@ static int launch_idft(int out, c2v* data, void* table, const double* cs, const 
 
 int build_smoothing_one(const spl_desc* d, int64_t n_g, const int32_t* miller, const double* coef, int comp,
                         void* table, void* work, const double* twiddles, const int32_t* col12,
-                        const int32_t* plane2, hipStream_t stream) {
+                        const int32_t* plane2, const int32_t* band, hipStream_t stream) {
   const int64_t n1 = d->grid[0], n2 = d->grid[1], n3 = d->grid[2], no = d->n_orb;
   c2v* grid = static_cast<c2v*>(work);
   const int64_t cells = n1 * n2 * n3 * no;
@@ -351,13 +368,14 @@ int build_smoothing_one(const spl_desc* d, int64_t n_g, const int32_t* miller, c
   const double* tw2 = tw1 + 2 * n2;
   // stage 1 lines (b1, b2, o) and stage 2 lines (x, b2, o): only those of occupied columns / planes
   if ((rc = launch_idft(DFT_INPLACE, grid, nullptr, tw0, tw0 + n1, 1, (int)n1, n2 * n3 * no, 0, 0, col12, no,
-                        stream)))
+                        band, 0, stream)))
     return rc;
-  if ((rc = launch_idft(DFT_INPLACE, grid, nullptr, tw1, tw1 + n2, n1, (int)n2, n3 * no, 0, 0, plane2, no, stream)))
+  if ((rc = launch_idft(DFT_INPLACE, grid, nullptr, tw1, tw1 + n2, n1, (int)n2, n3 * no, 0, 0, plane2, no, band, 1,
+                        stream)))
     return rc;
   const int out = d->dtype == SPL_F64 ? DFT_TABLE_F64 : d->dtype == SPL_F32 ? DFT_TABLE_F32 : DFT_TABLE_BF16;
-  if ((rc = launch_idft(out, grid, table, tw2, tw2 + n3, n1 * n2, (int)n3, no, d->o_pad, d->bloch, nullptr, 1,
-                        stream)))
+  if ((rc = launch_idft(out, grid, table, tw2, tw2 + n3, n1 * n2, (int)n3, no, d->o_pad, d->bloch, nullptr, 1, band,
+                        2, stream)))
     return rc;
   if (d->o_pad > d->n_col) {
     const int64_t rows = n1 * n2 * n3;
@@ -386,12 +404,12 @@ __global__ void k_twiddles(double* tw, int32_t n0, int32_t n1, int32_t n2) {
   tw[base + n + kk] = sin(ang);
 }
 
-// workspace: the complex grid, 256-byte aligned twiddles, then the two line masks
+// workspace: the complex grid, 256-byte aligned twiddles, then the two line masks and the bands
 int64_t smoothing_work_bytes(const spl_desc* d) {
   const int64_t cells = (int64_t)d->grid[0] * d->grid[1] * d->grid[2] * d->n_orb;
   const int64_t tw = 16 * (int64_t)(d->grid[0] + d->grid[1] + d->grid[2]);
   return ((cells * 16 + 255) & ~int64_t(255)) + ((tw + 255) & ~int64_t(255)) +
-         4 * ((int64_t)d->grid[1] * d->grid[2] + d->grid[2]);
+         4 * ((int64_t)d->grid[1] * d->grid[2] + d->grid[2] + 3);
 }
 
 int build_smoothing(const spl_desc* d, int64_t n_g, const int32_t* miller, const double* coef, void* table,
@@ -406,20 +424,21 @@ int build_smoothing(const spl_desc* d, int64_t n_g, const int32_t* miller, const
   int32_t* col12 = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(tw) + ((16 * (int64_t)nt + 255) & ~int64_t(255)));
   const int64_t n12 = (int64_t)d->grid[1] * d->grid[2];
   int32_t* plane2 = col12 + n12;
-  const int64_t n_mask = n12 + d->grid[2];
+  int32_t* band = plane2 + d->grid[2];
+  const int64_t n_mask = n12 + d->grid[2] + 3;
   hipLaunchKernelGGL(k_mask_zero, dim3((unsigned)std::min<int64_t>((n_mask + 255) / 256, 4096)), dim3(256), 0, stream,
                      col12, n_mask);
   if ((rc = hip_fail(hipGetLastError(), "mask clear launch"))) return rc;
   if (n_g > 0) {
     hipLaunchKernelGGL(k_line_masks, dim3((unsigned)((n_g + 255) / 256)), dim3(256), 0, stream, miller, n_g,
-                       make_geom(d), col12, plane2);
+                       make_geom(d), col12, plane2, band);
     if ((rc = hip_fail(hipGetLastError(), "line mask launch"))) return rc;
   }
   // tables in order: orbital, gradient components x, y, z (sep_grad), Laplacian (has_lap)
   for (int t = 0; t < d->n_tables; ++t) {
     const int comp = t == 0 ? COMP_VALUE : (d->sep_grad && t <= 3 ? t : COMP_LAP);
     char* dst = static_cast<char*>(table) + t * d->table_elems * d->elem_bytes;
-    if ((rc = build_smoothing_one(d, n_g, miller, coef, comp, dst, work, tw, col12, plane2, stream))) return rc;
+    if ((rc = build_smoothing_one(d, n_g, miller, coef, comp, dst, work, tw, col12, plane2, band, stream))) return rc;
   }
   return SPL_OK;
 }

@@ -224,11 +224,12 @@ __global__ __launch_bounds__(64) void k_idft_mfma(DftArgs a) {
     tw_c[k] = a.cs[k];
     tw_s[k] = a.sn[k];
   }
+  const int kb = a.band ? min(a.band[a.axis], n) : n;
   for (int e = lane; e < 16 * n_pad; e += 64) {
     const int j = e >> 4, c = e & 15;
     const int64_t line = line0 + c;
     c2v v{0.0, 0.0};
-    if (j < n && line < a.n_lines) {
+    if (j < n && line < a.n_lines && !(j > kb && j < n - kb)) {   // samples outside the band are zero
       const int64_t outer = line / a.inner;
       v = a.data[outer * (int64_t)n * a.inner + (line - outer * a.inner) + (int64_t)j * a.inner];
     }
@@ -244,7 +245,6 @@ __global__ __launch_bounds__(64) void k_idft_mfma(DftArgs a) {
   const int64_t base = outer * (int64_t)n * a.inner + in;
   // the last stage of a real table stores the real part only: the imaginary products are skipped
   const bool need_im = OUT == DFT_INPLACE || a.bloch;
-  const int kb = a.band ? min(a.band[a.axis], n) : n;
   for (int k0 = 0; k0 < n; k0 += 16) {
     f64x4_s acc_r = {0.0, 0.0, 0.0, 0.0}, acc_i = {0.0, 0.0, 0.0, 0.0};
     const int kk = k0 + col;              // A row: output index (past n: any finite value, not written)

@@ -24,11 +24,6 @@ namespace pws {
 
 typedef double c2v __attribute__((ext_vector_type(2)));   // (re, im)
 
-__global__ __launch_bounds__(256) void k_czero(c2v* w, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    w[i] = c2v{0.0, 0.0};
-}
-
 __device__ __forceinline__ double sinc4_half(double theta) {
   if (theta == 0.0) return 1.0;
   const double h = 0.5 * theta;
@@ -109,6 +104,22 @@ __device__ __forceinline__ bool line_live(const DftArgs& a, int64_t line) {
   return !a.mask || a.mask[(line % a.inner) / a.mask_div] != 0;
 }
 
+// Zero the grid rows every stage may read: only samples with b2 inside the axis-2 band are ever
+// loaded (stage 3 along axis 2 loads no other; stages 1 and 2 load only lines in occupied columns
+// and planes, which lie inside that band).  One workgroup per (b0, b1): the one or two contiguous
+// runs of b2 = 0 .. kb and n3 - kb .. n3 - 1, all orbitals.
+__global__ __launch_bounds__(256) void k_czero_band(c2v* grid, int32_t n3, int64_t n_orb, const int32_t* band) {
+  const int kb = band[2];
+  const int64_t col = blockIdx.x;                        // b0 n2 + b1
+  c2v* base = grid + col * n3 * n_orb;
+  const bool all = 2 * kb + 1 >= n3;
+  const int64_t len0 = (all ? n3 : kb + 1) * n_orb;
+  for (int64_t i = threadIdx.x; i < len0; i += blockDim.x) base[i] = c2v{0.0, 0.0};
+  if (all) return;
+  c2v* hi = base + (int64_t)(n3 - kb) * n_orb;
+  for (int64_t i = threadIdx.x; i < (int64_t)kb * n_orb; i += blockDim.x) hi[i] = c2v{0.0, 0.0};
+}
+
 __global__ __launch_bounds__(256) void k_mask_zero(int32_t* m, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     m[i] = 0;
@@ -159,8 +170,9 @@ __global__ __launch_bounds__(256) void k_idft_axis(DftArgs a) {
   const int64_t outer = line / a.inner;
   const int64_t in = line - outer * a.inner;
   const int64_t base = outer * (int64_t)n * a.inner + in;
-  for (int j = 0; j < n; ++j) x[j * tile] = a.data[base + (int64_t)j * a.inner];
   const int kb = a.band ? min(a.band[a.axis], n) : n;
+  for (int j = 0; j < n; ++j)                       // samples outside the band are zero, not loaded
+    x[j * tile] = (j > kb && j < n - kb) ? c2v{0.0, 0.0} : a.data[base + (int64_t)j * a.inner];
   for (int k = 0; k < n; ++k) {
     double re = 0.0, im = 0.0;
     int idx = 0;                          // (j k) mod n
@@ -350,9 +362,8 @@ int build_smoothing_one(const spl_desc* d, int64_t n_g, const int32_t* miller, c
                         const int32_t* plane2, const int32_t* band, hipStream_t stream) {
   const int64_t n1 = d->grid[0], n2 = d->grid[1], n3 = d->grid[2], no = d->n_orb;
   c2v* grid = static_cast<c2v*>(work);
-  const int64_t cells = n1 * n2 * n3 * no;
   int rc;
-  hipLaunchKernelGGL(k_czero, dim3(2048), dim3(256), 0, stream, grid, cells);
+  hipLaunchKernelGGL(k_czero_band, dim3((unsigned)(n1 * n2)), dim3(256), 0, stream, grid, (int32_t)n3, no, band);
   if ((rc = hip_fail(hipGetLastError(), "zero fill launch"))) return rc;
   const Geom geo = make_geom(d);
   const int64_t sc = n_g * no;

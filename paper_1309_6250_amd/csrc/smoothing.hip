@@ -260,10 +260,12 @@ __global__ __launch_bounds__(64) void k_idft_mfma(DftArgs a) {
   for (int k0 = 0; k0 < n; k0 += 16) {
     f64x4_s acc_r = {0.0, 0.0, 0.0, 0.0}, acc_i = {0.0, 0.0, 0.0, 0.0};
     const int kk = k0 + col;              // A row: output index (past n: any finite value, not written)
-    for (int j0 = 0; j0 < n_pad; j0 += 4) {
+    // twiddle index (kk j) mod n of this lane's sample j = j0 + grp, advanced by 4 kk mod n per step
+    const int step = (int)((4 * (int64_t)kk) % n);
+    int idx = (int)(((int64_t)kk * grp) % n);
+    for (int j0 = 0; j0 < n_pad; j0 += 4, idx = idx + step >= n ? idx + step - n : idx + step) {
       if (j0 > kb && j0 + 3 < n - kb) continue;   // four zero samples
       const int j = j0 + grp;             // A column / B row: sample index (past n: X is zero)
-      const int idx = (int)(((int64_t)kk * j) % n);
       const double c = tw_c[idx], sn = tw_s[idx];
       const double br = xr[j * 16 + col], bi = xi[j * 16 + col];
       acc_r = mfma64(c, br, acc_r);

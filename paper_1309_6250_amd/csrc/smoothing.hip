@@ -209,17 +209,20 @@ __global__ __launch_bounds__(256) void k_idft_axis(DftArgs a) {
 }
 
 // The same stage as a matrix product on the FP64 matrix cores: along the axis, Y = W X with
-// W[k][j] = exp(+2 pi i j k / n) and X the n samples of each line.  One wave owns 16 whole lines
-// (so the in-place update is safe): it stages their samples in LDS, then forms each tile of 16
-// outputs x 16 lines with 16x16x4 steps over j, four real products per step (complex multiply).
+// W[k][j] = exp(+2 pi i j k / n) and X the n samples of each line.  One workgroup owns 16 whole
+// lines (so the in-place update is safe): it stages their samples in LDS, then its waves form
+// alternate tiles of 16 outputs x 16 lines with 16x16x4 steps over j, four real products per step
+// (complex multiply).
 typedef double f64x4_s __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ f64x4_s mfma64(double a, double b, f64x4_s c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+constexpr int DFT_WAVES = 2;             // waves per workgroup, sharing the staged lines
+
 template <int OUT>
-__global__ __launch_bounds__(64) void k_idft_mfma(DftArgs a) {
+__global__ __launch_bounds__(64 * DFT_WAVES) void k_idft_mfma(DftArgs a) {
   extern __shared__ double lds_raw[];
   const int n = a.n;
   const int n_pad = (n + 3) & ~3;
@@ -227,17 +230,18 @@ __global__ __launch_bounds__(64) void k_idft_mfma(DftArgs a) {
   double* tw_s = lds_raw + n;             // [n]
   double* xr = lds_raw + 2 * n;           // [n_pad][16] real parts of the 16 lines
   double* xi = xr + 16 * n_pad;           // imaginary parts
-  const int lane = (int)threadIdx.x;
+  const int tid = (int)threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int grp = lane >> 4, col = lane & 15;
   const int64_t line0 = (int64_t)blockIdx.x * 16;
-  // the workgroup is this one wave: if none of its 16 lines can be nonzero, they stay zero
+  // if none of the workgroup's 16 lines can be nonzero, they stay zero (every wave decides alike)
   if (!__any(line_live(a, line0 + col))) return;
-  for (int k = lane; k < n; k += 64) {
+  for (int k = tid; k < n; k += 64 * DFT_WAVES) {
     tw_c[k] = a.cs[k];
     tw_s[k] = a.sn[k];
   }
   const int kb = a.band ? min(a.band[a.axis], n) : n;
-  for (int e = lane; e < 16 * n_pad; e += 64) {
+  for (int e = tid; e < 16 * n_pad; e += 64 * DFT_WAVES) {
     const int j = e >> 4, c = e & 15;
     const int64_t line = line0 + c;
     c2v v{0.0, 0.0};
@@ -257,7 +261,8 @@ __global__ __launch_bounds__(64) void k_idft_mfma(DftArgs a) {
   const int64_t base = outer * (int64_t)n * a.inner + in;
   // the last stage of a real table stores the real part only: the imaginary products are skipped
   const bool need_im = OUT == DFT_INPLACE || a.bloch;
-  for (int k0 = 0; k0 < n; k0 += 16) {
+  // every sample is in LDS before the barrier above, so the waves may overwrite the lines in place
+  for (int k0 = 16 * wave; k0 < n; k0 += 16 * DFT_WAVES) {
     f64x4_s acc_r = {0.0, 0.0, 0.0, 0.0}, acc_i = {0.0, 0.0, 0.0, 0.0};
     const int kk = k0 + col;              // A row: output index (past n: any finite value, not written)
     // twiddle index (kk j) mod n of this lane's sample j = j0 + grp, advanced by 4 kk mod n per step
@@ -336,14 +341,14 @@ static int launch_idft(int out, c2v* data, void* table, const double* cs, const 
   a.o_pad = o_pad;
   a.bloch = bloch;
   if (n <= 192) {
-    // matrix-core form: 16 lines per wave, staged samples and twiddles in LDS (at most 52 KB)
+    // matrix-core form: 16 lines per workgroup of two waves, staged samples and twiddles in LDS (at most 52 KB)
     const size_t shm = (size_t)(2 * n + 32 * ((n + 3) & ~3)) * sizeof(double);
-    const dim3 g((unsigned)((a.n_lines + 15) / 16));
+    const dim3 g((unsigned)((a.n_lines + 15) / 16)), b(64 * DFT_WAVES);
     switch (out) {
-      case DFT_INPLACE: hipLaunchKernelGGL(k_idft_mfma<DFT_INPLACE>, g, dim3(64), shm, stream, a); break;
-      case DFT_TABLE_F64: hipLaunchKernelGGL(k_idft_mfma<DFT_TABLE_F64>, g, dim3(64), shm, stream, a); break;
-      case DFT_TABLE_F32: hipLaunchKernelGGL(k_idft_mfma<DFT_TABLE_F32>, g, dim3(64), shm, stream, a); break;
-      default: hipLaunchKernelGGL(k_idft_mfma<DFT_TABLE_BF16>, g, dim3(64), shm, stream, a); break;
+      case DFT_INPLACE: hipLaunchKernelGGL(k_idft_mfma<DFT_INPLACE>, g, b, shm, stream, a); break;
+      case DFT_TABLE_F64: hipLaunchKernelGGL(k_idft_mfma<DFT_TABLE_F64>, g, b, shm, stream, a); break;
+      case DFT_TABLE_F32: hipLaunchKernelGGL(k_idft_mfma<DFT_TABLE_F32>, g, b, shm, stream, a); break;
+      default: hipLaunchKernelGGL(k_idft_mfma<DFT_TABLE_BF16>, g, b, shm, stream, a); break;
     }
     return hip_fail(hipGetLastError(), "inverse DFT launch");
   }

@@ -219,7 +219,9 @@ __device__ __forceinline__ f64x4_s mfma64(double a, double b, f64x4_s c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-constexpr int DFT_WAVES = 2;             // waves per workgroup, sharing the staged lines
+// waves per workgroup sharing the staged lines: 3 splits the output tiles of 48, 96, 144 and 192
+// points evenly (three waves 6.8 ms on the MgO-like cell, six 6.7, two 7.8, one 10.4)
+constexpr int DFT_WAVES = 3;
 
 template <int OUT>
 __global__ __launch_bounds__(64 * DFT_WAVES) void k_idft_mfma(DftArgs a) {
@@ -341,7 +343,7 @@ static int launch_idft(int out, c2v* data, void* table, const double* cs, const 
   a.o_pad = o_pad;
   a.bloch = bloch;
   if (n <= 192) {
-    // matrix-core form: 16 lines per workgroup of two waves, staged samples and twiddles in LDS (at most 52 KB)
+    // matrix-core form: 16 lines per workgroup, staged samples and twiddles in LDS (at most 52 KB)
     const size_t shm = (size_t)(2 * n + 32 * ((n + 3) & ~3)) * sizeof(double);
     const dim3 g((unsigned)((a.n_lines + 15) / 16)), b(64 * DFT_WAVES);
     switch (out) {

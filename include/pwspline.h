@@ -172,7 +172,7 @@ int spline_build_tables(const spl_desc* d, const double* vals, void* table, void
  * with gamma_G = prod_m sinc^4(theta_m / 2), theta_m = 2 pi n_m / N_m (the Fourier transform of
  * one standard-normalized tensor-product basis function), so the spline's fundamental Fourier
  * components equal c_G.  With has_lap, the second table uses (-|G|^2) c_G.
- *   n_g     number of planewaves
+ *   n_g     number of planewaves, 1 <= n_g < 2^31
  *   miller  device, int32 [n_g][3]: Miller indices n of G = 2 pi lattice^-1 n
  *   coef    device, FP64 [n_orb][n_g][2]: complex coefficients (re, im), conjugate-symmetric
  *           in G for real orbitals (the real part of the sum is stored); with bloch, the

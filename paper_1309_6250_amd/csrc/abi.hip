@@ -303,7 +303,7 @@ int spline_build_smoothing(const spl_desc* d, int64_t n_g, const int32_t* miller
   int rc = check_desc(d);
   if (rc) return rc;
   if (d->basis != SPL_BSPLINE) return fail(SPL_EINVAL, "smoothing coefficients are B-spline coefficients");
-  if (n_g < 1) return fail(SPL_EINVAL, "n_g = %lld < 1", (long long)n_g);
+  if (n_g < 1 || n_g > 0x7fffffffLL) return fail(SPL_EINVAL, "n_g = %lld outside [1, 2^31)", (long long)n_g);
   if ((double)n_g * d->n_orb > 9.0e18) return fail(SPL_EINVAL, "too many coefficients");
   if (!miller || !coef || !table || !work) return fail(SPL_EINVAL, "miller, coef, table and work must be non-NULL");
   if (!aligned(miller, 4) || !aligned(coef, 16) || !aligned(table, 16) || !aligned(work, 256))

@@ -40,17 +40,31 @@ enum { COMP_VALUE = 0, COMP_LAP = 4 };   // 1, 2, 3: Cartesian gradient componen
 
 // grid[bin(n)][o] += coef[o][g] * scale(g): scale = 1 / gamma_G, times i (k+G)_c for a gradient
 // component c, or -|k+G|^2 for the Laplacian.
+// One workgroup per tile of 32 planewaves x 32 orbitals: the coefficients are read along g
+// (coef is [o][g]) into LDS, each planewave's scale, wave vector and bin are formed once, and the
+// grid is updated along o, so both the reads and the atomic adds are contiguous.
+constexpr int SCAT_T = 32;
+
 __global__ __launch_bounds__(256) void k_scatter_coef(const int32_t* miller, const c2v* coef, int64_t n_g,
                                                       int32_t n_orb, Geom geo, int32_t comp, Kvec kv, c2v* grid) {
-  const int64_t total = n_g * n_orb;
+  __shared__ c2v tile[SCAT_T][SCAT_T + 1];           // [o][g], padded against bank conflicts
+  __shared__ double s_scale[SCAT_T], s_mul[SCAT_T];  // per planewave: 1/gamma, and the factor of comp
+  __shared__ int64_t s_bin[SCAT_T];
+  const int64_t g0 = (int64_t)blockIdx.x * SCAT_T;
+  const int o0 = (int)blockIdx.y * SCAT_T;
+  const int t = (int)threadIdx.x;
   const double two_pi = 6.283185307179586476925286766559;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t g = idx / n_orb;
-    const int o = (int)(idx - g * n_orb);
+  for (int e = t; e < SCAT_T * SCAT_T; e += 256) {
+    const int oo = e / SCAT_T, gg = e % SCAT_T;
+    const int64_t g = g0 + gg;
+    const int o = o0 + oo;
+    tile[oo][gg] = (g < n_g && o < n_orb) ? coef[(int64_t)o * n_g + g] : c2v{0.0, 0.0};
+  }
+  if (t < SCAT_T && g0 + t < n_g) {
+    const int64_t g = g0 + t;
     const int n0 = miller[3 * g], n1 = miller[3 * g + 1], n2 = miller[3 * g + 2];
-    const double scale = 1.0 / (sinc4_half(two_pi * n0 / geo.n[0]) * sinc4_half(two_pi * n1 / geo.n[1]) *
-                                sinc4_half(two_pi * n2 / geo.n[2]));
+    s_scale[t] = 1.0 / (sinc4_half(two_pi * n0 / geo.n[0]) * sinc4_half(two_pi * n1 / geo.n[1]) *
+                        sinc4_half(two_pi * n2 / geo.n[2]));
     double q[3], qsq = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -58,22 +72,31 @@ __global__ __launch_bounds__(256) void k_scatter_coef(const int32_t* miller, con
       q[c] = kv.k[c] + two_pi * fmaa(geo.ainv[6 + c], (double)n2, fmaa(geo.ainv[3 + c], (double)n1, geo.ainv[c] * n0));
       qsq = fmaa(q[c], q[c], qsq);
     }
+    // value: 1; Laplacian: -|k+G|^2 (real); gradient component c: i q_c (applied below)
+    s_mul[t] = comp == COMP_LAP ? -qsq : (comp == COMP_VALUE ? 1.0 : q[comp - 1]);
     const int b0 = ((n0 % geo.n[0]) + geo.n[0]) % geo.n[0];
     const int b1 = ((n1 % geo.n[1]) + geo.n[1]) % geo.n[1];
     const int b2 = ((n2 % geo.n[2]) + geo.n[2]) % geo.n[2];
-    const int64_t bin = ((int64_t)b0 * geo.n[1] + b1) * geo.n[2] + b2;
-    const c2v c = coef[(int64_t)o * n_g + g];
-    double re = c.x * scale, im = c.y * scale;
+    s_bin[t] = ((int64_t)b0 * geo.n[1] + b1) * geo.n[2] + b2;
+  }
+  __syncthreads();
+  for (int e = t; e < SCAT_T * SCAT_T; e += 256) {
+    const int gg = e / SCAT_T, oo = e % SCAT_T;
+    const int64_t g = g0 + gg;
+    const int o = o0 + oo;
+    if (g >= n_g || o >= n_orb) continue;
+    const c2v c = tile[oo][gg];
+    double re = c.x * s_scale[gg], im = c.y * s_scale[gg];
     if (comp == COMP_LAP) {
-      re *= -qsq;
-      im *= -qsq;
+      re *= s_mul[gg];
+      im *= s_mul[gg];
     } else if (comp != COMP_VALUE) {
-      const double qc = q[comp - 1];            // i q_c (re + i im) = -q_c im + i q_c re
-      const double t = re;
+      const double qc = s_mul[gg];              // i q_c (re + i im) = -q_c im + i q_c re
+      const double tr = re;
       re = -qc * im;
-      im = qc * t;
+      im = qc * tr;
     }
-    double* dst = reinterpret_cast<double*>(grid + bin * n_orb + o);
+    double* dst = reinterpret_cast<double*>(grid + s_bin[gg] * n_orb + o);
     unsafeAtomicAdd(dst, re);                    // planewaves sharing a bin (too coarse a grid) add up
     unsafeAtomicAdd(dst + 1, im);
   }
@@ -375,13 +398,14 @@ int build_smoothing_one(const spl_desc* d, int64_t n_g, const int32_t* miller, c
   hipLaunchKernelGGL(k_czero_band, dim3((unsigned)(n1 * n2)), dim3(256), 0, stream, grid, (int32_t)n3, no, band);
   if ((rc = hip_fail(hipGetLastError(), "zero fill launch"))) return rc;
   const Geom geo = make_geom(d);
-  const int64_t sc = n_g * no;
-  const unsigned sblocks = (unsigned)std::min<int64_t>((sc + 255) / 256, 65536);
   Kvec kv;
   for (int c = 0; c < 3; ++c) kv.k[c] = d->kvec[c];
-  hipLaunchKernelGGL(k_scatter_coef, dim3(sblocks), dim3(256), 0, stream, miller,
-                     reinterpret_cast<const c2v*>(coef), n_g, (int32_t)no, geo, (int32_t)comp, kv, grid);
-  if ((rc = hip_fail(hipGetLastError(), "coefficient scatter launch"))) return rc;
+  if (n_g > 0) {
+    const dim3 sg((unsigned)((n_g + SCAT_T - 1) / SCAT_T), (unsigned)((no + SCAT_T - 1) / SCAT_T));
+    hipLaunchKernelGGL(k_scatter_coef, sg, dim3(256), 0, stream, miller, reinterpret_cast<const c2v*>(coef), n_g,
+                       (int32_t)no, geo, (int32_t)comp, kv, grid);
+    if ((rc = hip_fail(hipGetLastError(), "coefficient scatter launch"))) return rc;
+  }
   // twiddles: [axis][cos n | sin n] packed one axis after the other
   const double* tw0 = twiddles;
   const double* tw1 = tw0 + 2 * n1;

@@ -23,6 +23,8 @@ Plain numpy in float64, written for a reader to check against the paper by eye:
   smoothing  Fourier-matched (smoothing) B-spline coefficients (App. A,
              Eq. b-splinecoefficients)
   fit        weighted least-squares misfit with a second-difference penalty
+  projection closed-form L2 projection onto the spline space: the limit of
+             that fit with values only, no penalty and dense points
   lagrange   cubic Lagrange interpolation of grid values (App. A, Lagrange
              interpolation)
   separate   value, gradient and Laplacian from five separate interpolants
@@ -40,4 +42,4 @@ The spline *function* is the same either way; only the stored coefficients
 differ, by the constant factor (3/2)^3.
 """
 from . import bspline, pw, build, evaluate, adjoint, quantize, smoothing, fit  # noqa: F401
-from . import lagrange, separate, bloch, ppspline  # noqa: F401
+from . import lagrange, separate, bloch, ppspline, projection  # noqa: F401

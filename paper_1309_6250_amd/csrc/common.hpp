@@ -39,14 +39,15 @@ template <> struct Acc<double> { using type = double; };
 // ---------------------------------------------------------------- device helpers
 // Every fused multiply-add in device code is written out (the library is built with
 // -ffp-contract=off), so all kernels sharing a code path round identically.
-__device__ __forceinline__ double fmaa(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ __forceinline__ float fmaa(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__host__ __device__ __forceinline__ double fmaa(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__host__ __device__ __forceinline__ float fmaa(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 // Reduced coordinates (Sec. II, Eq. reducedcoordinate): s = a^-1 r folded into [0,1),
 // u = N s, i0 = floor(u), t = u - i0.  Always FP64.  A non-finite point returns false
-// with i0 = 0, t = 0 so every later index stays inside the table.
-__device__ __forceinline__ bool reduce_point(const Geom& g, double r0, double r1, double r2,
-                                             int i0[3], double t[3]) {
+// with i0 = 0, t = 0 so every later index stays inside the table.  Host and device: the
+// host build serves a CPU check of the indices over adversarial positions.
+__host__ __device__ __forceinline__ bool reduce_point(const Geom& g, double r0, double r1, double r2,
+                                                      int i0[3], double t[3]) {
   bool ok = __builtin_isfinite(r0) && __builtin_isfinite(r1) && __builtin_isfinite(r2);
   if (!ok) { r0 = 0.0; r1 = 0.0; r2 = 0.0; }
   double s[3];
@@ -158,7 +159,7 @@ __device__ __forceinline__ uint32_t spread3(uint32_t x) {
 }
 
 // Row indices i0-1 .. i0+2 modulo n (n >= 4, 0 <= i0 < n).
-__device__ __forceinline__ void wrap4(int i0, int n, int idx[4]) {
+__host__ __device__ __forceinline__ void wrap4(int i0, int n, int idx[4]) {
   idx[0] = (i0 == 0) ? n - 1 : i0 - 1;
   idx[1] = i0;
   idx[2] = (i0 + 1 >= n) ? i0 + 1 - n : i0 + 1;

@@ -453,6 +453,17 @@ int spline_autotune(const spl_desc* d, const void* table, int64_t n_pts, const d
 /* Tile shape spline_eval_vgl would use for this descriptor (cache hit or default). */
 int spline_tile_for(const spl_desc* d, int64_t n_pts, int32_t tile_out[2]);
 
+/*
+ * Read-rate probe (measurement aid, not part of the method): reads `bytes` bytes of `buf` once, as a
+ * linear stream of 16-byte loads spread over the whole device, and writes nothing but (practically
+ * never) 4 bytes at `sink`.  Timed by the caller, it gives the achievable read bandwidth of device
+ * memory, the ceiling for the gather of Sec. III B, which reads and hardly writes.
+ *   buf    device, 16-byte aligned; bytes a multiple of 16 (0: no-op)
+ *   sink   device, 4 bytes, 4-byte aligned
+ * Errors: negative or unaligned sizes, NULL or misaligned pointers -> SPL_EINVAL; launch -> SPL_EHIP.
+ */
+int spline_stream_read(const void* buf, int64_t bytes, void* sink, void* stream);
+
 /* Human-readable description of the last error on this thread ("" if none). */
 const char* spline_last_error(void);
 

@@ -12,7 +12,8 @@ from .api import (spline_desc_init, spline_build, spline_build_tables, spline_ev
                   spline_cells_work_bytes, spline_fit_terms_cells,
                   spline_eval_vgl_backward,
                   spline_autotune, spline_tile_for, spline_backward_work_bytes, spline_build_smoothing,
-                  spline_smoothing_work_bytes, spline_misfit, spline_misfit_work_bytes, spline_smoothness_penalty, BatchPlan, new_table,
+                  spline_smoothing_work_bytes, spline_misfit, spline_misfit_work_bytes, spline_smoothness_penalty,
+                  spline_stream_read, BatchPlan, new_table,
                   new_gtable, table_shape,
                   STORE_TORCH, OUT_TORCH, DTYPES)
 from .autograd import SplineVGL, spline_vgl
@@ -22,7 +23,8 @@ __all__ = [
     "spline_eval_vgl_cells", "spline_cells_work_bytes", "spline_fit_terms_cells",
     "spline_sorted_work_bytes", "spline_eval_vgl", "spline_eval_vgl_backward",
     "spline_autotune", "spline_tile_for", "spline_backward_work_bytes", "spline_build_smoothing",
-    "spline_smoothing_work_bytes", "spline_misfit", "spline_misfit_work_bytes", "spline_smoothness_penalty", "BatchPlan", "new_table", "new_gtable", "table_shape", "SplineError",
+    "spline_smoothing_work_bytes", "spline_misfit", "spline_misfit_work_bytes", "spline_smoothness_penalty",
+    "spline_stream_read", "BatchPlan", "new_table", "new_gtable", "table_shape", "SplineError",
     "SplDesc", "lib", "EXPORTS", "LIB_PATH", "SPL_F64", "SPL_F32", "SPL_BF16", "SPL_OK", "SPL_EINVAL", "SPL_EGRID",
     "SPL_EDTYPE", "SPL_ENOMEM", "SPL_EHIP", "SPL_EUNSUPPORTED", "SPL_DETERMINISTIC", "SPL_REUSE_SORT", "SPL_BSPLINE", "SPL_LAGRANGE", "SPL_PPSPLINE", "STORE_TORCH", "OUT_TORCH",
     "DTYPES", "SplineVGL", "spline_vgl",

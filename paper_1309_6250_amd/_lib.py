@@ -27,7 +27,7 @@ EXPORTS = (
     "spline_build_smoothing", "spline_smoothing_work_bytes", "spline_build_tables",
     "spline_eval_vgl_sorted", "spline_sorted_work_bytes", "spline_batch_plan_sort", "spline_misfit",
     "spline_misfit_work_bytes", "spline_smoothness_penalty", "spline_eval_vgl_cells", "spline_cells_work_bytes",
-    "spline_fit_terms_cells",
+    "spline_fit_terms_cells", "spline_stream_read",
 )
 
 
@@ -119,6 +119,7 @@ def lib():
             "spline_batch_plan_info": (ctypes.c_int, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
             "spline_autotune": (ctypes.c_int, [pd, vp, i64, vp, vp, vp, vp, vp, i32p]),
             "spline_tile_for": (ctypes.c_int, [pd, i64, i32p]),
+            "spline_stream_read": (ctypes.c_int, [vp, i64, vp, vp]),
             "spline_last_error": (ctypes.c_char_p, []),
             "spline_version": (ctypes.c_int, []),
         }

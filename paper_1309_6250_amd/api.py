@@ -404,6 +404,17 @@ def spline_smoothness_penalty(desc, table, w, loss, gtable=None, work=None, stre
     return gtable
 
 
+def spline_stream_read(buf, sink, stream=None):
+    """Read-rate probe: reads every byte of the contiguous device tensor `buf` (its size a multiple of
+    16 bytes) once; `sink` is a device tensor of at least 4 bytes that is (practically) never written."""
+    _need(buf, "buf", None)
+    _need(sink, "sink", None)
+    if sink.numel() * sink.element_size() < 4:
+        raise ValueError("sink must hold at least 4 bytes")
+    check(lib().spline_stream_read(_ptr(buf), int(buf.numel() * buf.element_size()), _ptr(sink), _stream(stream)),
+          "spline_stream_read")
+
+
 def spline_autotune(desc, table, pos, v=None, grad=None, lap=None, stream=None):
     n = _check_inputs(desc, table, pos)
     v, grad, lap = _outputs(desc, n, pos.device, v, grad, lap)

@@ -19,6 +19,8 @@ by Adam.  Two forms of the same loss:
   larger autograd graph.  Its residuals are formed in the kernel's output precision and
   their squares summed in FP64.
 """
+import math
+
 import torch
 
 from ._lib import SPL_DETERMINISTIC, SPL_REUSE_SORT
@@ -128,9 +130,12 @@ class FitProblem:
 
 
 def fit_adam(desc, table, pos, v_t, lap_t, steps=200, lam=1e-3, lr=None, use_lap=True, callback=None,
-             deterministic=True, checkpoint=None, checkpoint_every=0):
+             deterministic=True, checkpoint=None, checkpoint_every=0, schedule="constant", lr_min_frac=0.01):
     """Adam from `table` (not modified); returns (fitted table, list of losses of every step run so
     far, including those before a resume).
+    lr: the step size (default 1e-3 rms(table)); schedule "constant", or "cosine": step k of `steps` uses
+    lr_min + (lr - lr_min)(1 + cos(pi k / steps)) / 2 with lr_min = lr_min_frac lr (a function of k
+    alone, so a resumed fit takes the same steps).
     deterministic: bitwise-reproducible coefficient gradients (cell-sorted accumulation).
     checkpoint: file path.  If it exists, the fit resumes from it (coefficients, Adam moments and
     step count, loaded with torch.load(weights_only=True)); every `checkpoint_every` steps (and
@@ -160,8 +165,14 @@ def fit_adam(desc, table, pos, v_t, lap_t, steps=200, lam=1e-3, lr=None, use_lap
                                            dtype=torch.float64)}, tmp)
         os.replace(tmp, checkpoint)
 
+    if schedule not in ("constant", "cosine"):
+        raise ValueError(f"unknown schedule {schedule!r}")
+    lr_min = lr_min_frac * lr
     losses = []
     for step in range(start, steps):
+        if schedule == "cosine":
+            for grp in opt.param_groups:
+                grp["lr"] = lr_min + (lr - lr_min) * 0.5 * (1.0 + math.cos(math.pi * step / steps))
         loss, g = prob.loss_and_grad(beta.detach())
         beta.grad = g if g.dtype == beta.dtype else g.to(beta.dtype)
         opt.step()
@@ -171,3 +182,37 @@ def fit_adam(desc, table, pos, v_t, lap_t, steps=200, lam=1e-3, lr=None, use_lap
         if checkpoint is not None and (step + 1 == steps or (checkpoint_every and (step + 1) % checkpoint_every == 0)):
             save(step + 1, losses)
     return beta.detach(), done + ([float(x) for x in torch.cat(losses).cpu()] if losses else [])
+
+
+def fit_optimum_cg(desc, table, pos, v_t, lap_t, lam=1e-3, use_lap=True, iters=300, rtol=1e-9):
+    """The minimizer of the fit loss, by conjugate gradients from `table`.  The loss is a quadratic
+    in the coefficients, L(beta) = beta^T H beta / 2 - b^T beta + c, so its gradient g(beta) = H beta - b
+    is linear and H p = g(p) - g(0): one gradient per iteration (the library's fit terms, adjoint and
+    penalty kernels).  Stops when the residual norm falls below rtol times its first value.  Returns
+    (beta, loss at beta, iterations run, relative residual)."""
+    if table.dtype not in (torch.float32, torch.float64):
+        raise ValueError("conjugate gradients need an FP32 or FP64 table (H p must be formed from p exactly)")
+    prob = FitProblem(desc, pos, v_t, lap_t, lam=lam, use_lap=use_lap, deterministic=True)
+    x = table.detach().clone()
+    _, g = prob.loss_and_grad(torch.zeros_like(x))
+    b = -g.clone()
+    _, g = prob.loss_and_grad(x)
+    r = -g.clone()
+    p = r.clone()
+    rs = torch.sum(r.double() * r.double())
+    rs0 = float(rs)
+    it = 0
+    for it in range(1, iters + 1):
+        _, gp = prob.loss_and_grad(p)
+        hp = gp + b
+        alpha = rs / torch.sum(p.double() * hp.double())
+        x += alpha.to(x.dtype) * p
+        r -= alpha.to(r.dtype) * hp
+        rs_new = torch.sum(r.double() * r.double())
+        if float(rs_new) <= rtol * rtol * rs0:
+            rs = rs_new
+            break
+        p = r + (rs_new / rs).to(r.dtype) * p
+        rs = rs_new
+    loss, _ = prob.loss_and_grad(x)
+    return x, float(loss), it, math.sqrt(float(rs) / rs0) if rs0 > 0 else 0.0

@@ -205,6 +205,15 @@ int main(void) {
   expect(spline_batch_plan_create(&item, 1, NULL, NULL, &plan), SPL_EUNSUPPORTED, "plan pp item");
   expect(spline_batch_plan_sort(NULL, 1, NULL), SPL_EINVAL, "plan sort NULL");
 
+  /* read-rate probe */
+  expect(spline_stream_read(NULL, 16, fake, NULL), SPL_EINVAL, "stream NULL buf");
+  expect(spline_stream_read(fake, 16, NULL, NULL), SPL_EINVAL, "stream NULL sink");
+  expect(spline_stream_read(fake, 15, fake, NULL), SPL_EINVAL, "stream size not a multiple of 16");
+  expect(spline_stream_read(fake, -16, fake, NULL), SPL_EINVAL, "stream negative size");
+  expect(spline_stream_read((const void*)(uintptr_t)4104, 16, fake, NULL), SPL_EINVAL, "stream misaligned buf");
+  expect(spline_stream_read(fake, 16, (void*)(uintptr_t)4098, NULL), SPL_EINVAL, "stream misaligned sink");
+  expect(spline_stream_read(NULL, 0, NULL, NULL), SPL_OK, "stream zero bytes");
+
   if (spline_version() <= 0) {
     fprintf(stderr, "version\n");
     ++failures;

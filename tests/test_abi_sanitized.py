@@ -1,6 +1,6 @@
 """The C ABI's argument validation under host AddressSanitizer and UndefinedBehaviorSanitizer.
 
-The two translation units that hold the entry points' checks (abi.hip, misfit.hip) are rebuilt
+The translation units that hold the entry points' checks (abi.hip, misfit.hip, stream.hip) are rebuilt
 with the sanitizers on their host code only, linked with the library's other objects into a
 scratch library, and driven by tests/abi_sanitize.c through every validation path.  Nothing
 reaches a GPU, so this runs on the CPU; a sanitizer report aborts the driver."""
@@ -17,7 +17,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CLANG = "/opt/rocm/llvm/bin/clang"
 SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
        "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
-UNITS = ("abi.hip", "misfit.hip")
+UNITS = ("abi.hip", "misfit.hip", "stream.hip")
 
 
 def _run(cmd, **kw):

@@ -18,6 +18,10 @@ a Gaussian spectral decay stand in for them, on cells of the same shape.
      4 complex orbitals, 16^3 grid, 8 + 4096 points (small case).
   7  Bloch orbitals in config 1's cell at the supercell zone-corner twist k = (pi/L)(1,1,1),
      L = 2a: 128 complex orbitals, 48^3 grid, 256 walkers x 256 electrons.
+  8  64-atom Al-like cell at the scale of 1: the fcc primitive cell (a = 4.05 A) repeated
+     4x4x4 along its own (non-orthogonal) lattice vectors, 3 valence electrons per atom,
+     so 96 orbitals and 192 electrons; Gcut 4, 50^3 grid (spacing 0.43 bohr, as in 1),
+     256 walkers x 192 electrons.
 """
 from __future__ import annotations
 
@@ -78,11 +82,13 @@ CONFIGS = {
     7: dict(name="si64-cubic-48-twist", lattice=lambda: cubic(2.0 * A_SI), grid=(48, 48, 48), n_orb=128,
             gcut=4.0, decay=2.0, walkers=256, elec=256, extra=0, dtypes=("f64", "f32"), has_lap=False,
             kvec=lambda: (np.pi / (2.0 * A_SI)) * np.ones(3)),
+    8: dict(name="al64-fcc-4x4x4-50", lattice=lambda: 4.0 * fcc_primitive(A_AL), grid=(50, 50, 50), n_orb=96,
+            gcut=4.0, decay=2.0, walkers=256, elec=192, extra=0, dtypes=("f64", "f32", "bf16"), has_lap=False),
 }
 
 
 def config(key: int) -> Workload:
-    """The named single-system workload ``key`` (0, 1, 2, 4, 5, 6 or 7)."""
+    """The named single-system workload ``key`` (0, 1, 2, 4, 5, 6, 7 or 8)."""
     c = CONFIGS[key]
     kvec = c["kvec"]() if "kvec" in c else None
     sysm = make_system(c["name"], c["lattice"](), c["grid"], c["n_orb"], c["gcut"], c["decay"],

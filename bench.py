@@ -42,8 +42,8 @@ PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = ("paper_1309_6250_amd/csrc/eval_impl.hpp", "paper_1309_6250_amd/csrc/common.hpp")
 STORE_BYTES = {"f64": 8, "f32": 4, "bf16": 2}
 # Adam on the fit: step size relative to the rms of the interpolating table, and its schedule
-FIT_LR = 1e-3
-FIT_SCHEDULE = "constant"
+FIT_LR = 0.1
+FIT_SCHEDULE = "cosine"
 
 
 def log(*a):

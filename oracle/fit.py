@@ -22,8 +22,8 @@ def second_difference(beta, axis):
     return np.roll(beta, 1, axis=axis) - 2.0 * beta + np.roll(beta, -1, axis=axis)
 
 
-def loss_and_grad(beta, lattice, pos, v_pw, lap_pw, w_v, w_l, lam):
-    """Returns (loss, dloss/dbeta)."""
+def loss_and_grad(beta, lattice, pos, v_pw, lap_pw, w_v, w_l, lam, want_grad=True):
+    """Returns (loss, dloss/dbeta); the gradient is None when want_grad is False."""
     beta = np.asarray(beta, dtype=np.float64)
     n_pts, n_orb = v_pw.shape
     v, _, lap = eval_vgl(beta, lattice, pos)
@@ -33,7 +33,7 @@ def loss_and_grad(beta, lattice, pos, v_pw, lap_pw, w_v, w_l, lam):
     loss = w_v * norm * np.sum(rv * rv) + w_l * norm * np.sum(rl * rl)
     gv = 2.0 * w_v * norm * rv
     gl = 2.0 * w_l * norm * rl
-    gbeta, _, _ = vgl_backward(beta, lattice, pos, gv=gv, glap=gl)
+    gbeta = vgl_backward(beta, lattice, pos, gv=gv, glap=gl)[0] if want_grad else None
     if lam:
         scale = lam / (beta[..., 0].size * n_orb * np.mean(v_pw * v_pw))
         reg = 0.0
@@ -41,7 +41,8 @@ def loss_and_grad(beta, lattice, pos, v_pw, lap_pw, w_v, w_l, lam):
             d2 = second_difference(beta, axis)
             reg += np.sum(d2 * d2)
             # d/dbeta sum (D2 beta)^2 = 2 D2^T D2 beta, and D2 is symmetric under periodic wrap
-            gbeta = gbeta + 2.0 * scale * second_difference(d2, axis)
+            if want_grad:
+                gbeta = gbeta + 2.0 * scale * second_difference(d2, axis)
         loss += scale * reg
     return loss, gbeta
 

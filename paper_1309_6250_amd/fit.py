@@ -130,10 +130,12 @@ class FitProblem:
 
 
 def fit_adam(desc, table, pos, v_t, lap_t, steps=200, lam=1e-3, lr=None, use_lap=True, callback=None,
-             deterministic=True, checkpoint=None, checkpoint_every=0, schedule="constant", lr_min_frac=0.01):
+             deterministic=True, checkpoint=None, checkpoint_every=0, schedule="cosine", lr_min_frac=0.01):
     """Adam from `table` (not modified); returns (fitted table, list of losses of every step run so
     far, including those before a resume).
-    lr: the step size (default 1e-3 rms(table)); schedule "constant", or "cosine": step k of `steps` uses
+    lr: the step size (default 0.1 rms(table): on the 64-atom fit workload 200 steps from the
+    interpolating spline then reach the loss of the exact optimum, where 1e-3 rms closes a few per
+    cent of that gap); schedule "constant", or "cosine" (default): step k of `steps` uses
     lr_min + (lr - lr_min)(1 + cos(pi k / steps)) / 2 with lr_min = lr_min_frac lr (a function of k
     alone, so a resumed fit takes the same steps).
     deterministic: bitwise-reproducible coefficient gradients (cell-sorted accumulation).
@@ -145,7 +147,7 @@ def fit_adam(desc, table, pos, v_t, lap_t, steps=200, lam=1e-3, lr=None, use_lap
     prob = FitProblem(desc, pos, v_t, lap_t, lam=lam, use_lap=use_lap, deterministic=deterministic)
     beta = table.detach().clone().requires_grad_(True)
     if lr is None:
-        lr = 1e-3 * float(torch.sqrt(torch.mean(table.detach().to(torch.float64) ** 2)))
+        lr = 0.1 * float(torch.sqrt(torch.mean(table.detach().to(torch.float64) ** 2)))
     # torch's fused Adam: the whole update of the table in one kernel
     opt = torch.optim.Adam([beta], lr=lr, betas=(0.9, 0.999), fused=beta.is_cuda)
     start, done = 0, []

@@ -6,7 +6,7 @@ import torch
 
 import paper_1309_6250_amd as P
 from paper_1309_6250_amd.fit import make_loss, fit_adam, FitProblem
-from oracle import build as obuild, adjoint as oadj, fit as ofit, pw as opw, quantize as oq
+from oracle import build as obuild, adjoint as oadj, fit as ofit, pw as opw, quantize as oq, projection as oproj
 from workloads import make_system
 from workloads.configs import cubic, A_SI
 from gpu_helpers import say, to_dev, table_from_oracle, normwise, DEV
@@ -285,3 +285,30 @@ def test_fit_checkpoint_resume_is_bitwise(tmp_path, dtype):
     assert torch.equal(resumed, straight)
     assert l_resumed == l_straight
     assert int(torch.load(ck, weights_only=True)["step"]) == 10
+
+
+def test_adam_fit_approaches_l2_projection():
+    """With no smoothness term and no Laplacian term the fit is the least-squares projection of the
+    orbitals onto the spline space at the fit points; with dense uniform points its optimum tends to
+    the continuous L2 projection (oracle.projection, pinned on the CPU).  200 Adam steps from the
+    interpolating spline (default step size and schedule) must start at the oracle's loss of that
+    spline, lower it, and close most of the gap to the oracle's loss of the projection."""
+    s = make_system("proj-small", cubic(8.0), (12, 12, 12), 4, 3.5, 2.0, (1309, 6250, 4, 7))
+    assert np.abs(s.miller).max() * 2 < 12
+    pos = s.positions(40_000)                         # 23 points per cell
+    v_t = opw.pw_value(s.gvecs, s.coef, pos)
+    lap_t = np.zeros_like(v_t)
+    beta_int = obuild.build_interp(s.grid_values())
+    w_v = 1.0 / np.mean(v_t * v_t)
+    loss_int, _ = ofit.loss_and_grad(beta_int, s.lattice, pos, v_t, lap_t, w_v, 0.0, 0.0, want_grad=False)
+    beta_proj = oproj.project(s.miller, s.coef, s.grid)
+    loss_proj, _ = ofit.loss_and_grad(beta_proj, s.lattice, pos, v_t, lap_t, w_v, 0.0, 0.0, want_grad=False)
+    assert loss_proj < 0.8 * loss_int                 # the interpolant is not the projection
+    d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, "f64")
+    table = table_from_oracle(d, beta_int, "f64")
+    say("Adam fit toward the L2 projection")
+    fitted, losses = fit_adam(d, table, to_dev(pos), to_dev(v_t), to_dev(lap_t), steps=200, lam=0.0, use_lap=False)
+    torch.cuda.synchronize()
+    assert abs(losses[0] - loss_int) <= 1e-11 * loss_int
+    assert losses[-1] < losses[0]
+    assert losses[-1] - loss_proj <= 0.1 * (loss_int - loss_proj), (loss_int, losses[-1], loss_proj)

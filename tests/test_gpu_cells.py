@@ -73,6 +73,27 @@ def test_cells_match_oracle():
     assert normwise(l.cpu().numpy(), ol) < 1e-12
 
 
+@pytest.mark.parametrize("has_lap", [False, True], ids=["lap-from-derivatives", "lap-table"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_cells_match_oracle_elementwise(dtype, has_lap):
+    """Kernel parity of the matrix-core forward against the oracle on the same stored (quantized)
+    table, element by element: |err| <= 2 * 64 * u_acc * sum |w| |beta| plus the movement allowed by
+    rounding of the grid coordinate (the per-point kernel's bound; oracle.evaluate.eval_abs_bound)."""
+    from gpu_helpers import assert_elementwise, coordinate_rounding, U_ACC
+    d, tab, pos, beta, lbeta = _case((6, 5, 7), 37, 1200, dtype, has_lap, 115)
+    say("cells forward against the oracle, elementwise", dtype, has_lap)
+    v, g, l = P.spline_eval_vgl_cells(d, tab, to_dev(pos))
+    torch.cuda.synchronize()
+    bq = oq.quantized(beta, dtype)
+    lq = None if lbeta is None else oq.quantized(lbeta, dtype)
+    ref = oeval.eval_vgl(bq, SKEW, pos, lap_beta=lq)
+    bnd = oeval.eval_abs_bound(bq, SKEW, pos, lap_beta=lq)
+    crd = oeval.coordinate_error_bound(bq, SKEW, pos, coordinate_rounding(d, SKEW, pos, dtype), lap_beta=lq)
+    fac = 2 * 64 * U_ACC[dtype] + (0.0 if dtype == "f64" else 2.0**-24)
+    for name, got, r, b, c in zip(("V", "grad", "lap"), (v, g, l), ref, bnd, crd):
+        assert_elementwise(got.double().cpu().numpy(), r, b + c / fac, fac, name)
+
+
 @pytest.mark.timeout(600)
 def test_cells_at_fit_size():
     """10^6 points in 32^3 cells (FP32): value and Laplacian against the per-point kernel."""

@@ -256,6 +256,53 @@ def test_backward_matches_oracle(case, dtype, which):
     assert normwise(gp[smooth], rp[smooth]) <= (1e-10 if dtype == "f64" else 1e-4)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_backward_position_gradient_on_knots(dtype):
+    """Points on a knot plane and within 1e-9 grid units of one.  The position gradient of the
+    Laplacian term uses the third derivative, which jumps across a knot plane, so at such a point
+    the gradient has two one-sided values: the oracle's on either side (1e-11 grid units away, where
+    the continuous terms have not moved measurably).  The GPU must match one of them per component
+    (the side its own rounding of the grid coordinate picks); points off the plane by 1e-9 must
+    match the side they lie on."""
+    rng = np.random.default_rng(107)
+    grid = (7, 6, 8)
+    n_orb = 5
+    n = np.array(grid)
+    beta = rng.standard_normal(grid + (n_orb,))
+    d = P.spline_desc_init(SKEW, grid, n_orb, dtype)
+    tab = table_from_oracle(d, beta, dtype)
+    bq = oq.quantized(beta, dtype)
+    m = 240
+    cells = rng.integers(0, n, size=(m, 3))
+    u = cells + rng.uniform(0.2, 0.8, size=(m, 3))
+    axis = rng.integers(0, 3, size=m)
+    offset = np.choose(np.arange(m) % 3, [0.0, 1e-9, -1e-9])
+    u[np.arange(m), axis] = cells[np.arange(m), axis] + offset
+    pos = (u / n) @ SKEW
+    gv = rng.standard_normal((m, n_orb))
+    gg = rng.standard_normal((m, 3, n_orb))
+    gl = rng.standard_normal((m, n_orb))
+    od = torch.float64 if dtype == "f64" else torch.float32
+    say("position gradient on knot planes", dtype)
+    _, gpos = P.spline_eval_vgl_backward(d, tab, to_dev(pos), to_dev(gv, od), to_dev(gg, od), to_dev(gl, od))
+    torch.cuda.synchronize()
+    gp = gpos.cpu().numpy()
+    step = np.zeros((m, 3))
+    step[np.arange(m), axis] = 1e-11
+    side = []
+    for sgn in (-1.0, 1.0):
+        _, _, rp = oadj.vgl_backward(bq, SKEW, ((u + sgn * step) / n) @ SKEW, gv, gg, gl)
+        side.append(rp)
+    scale = np.abs(np.concatenate(side)).max()
+    tol = (1e-10 if dtype == "f64" else 1e-4) * scale
+    near = [np.abs(gp - r) <= tol for r in side]
+    on_plane = offset == 0.0
+    assert np.all((near[0] | near[1])[on_plane])
+    assert np.all(near[0][offset < 0]) and np.all(near[1][offset > 0])
+    # the two sides do differ on the plane (the test would be empty otherwise)
+    assert np.abs(side[0] - side[1])[on_plane].max() > 100 * tol
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("n_orb", [1, 3, 4, 8, 12])
 def test_no_writes_past_outputs(dtype, n_orb):

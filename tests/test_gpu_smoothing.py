@@ -20,7 +20,10 @@ def systems():
             make_system("smooth-skew", SKEW, (10, 12, 14), 5, 2.0, 2.0, (31, 1)),
             make_system("smooth-mgo", cubic(2 * A_MGO), (24, 24, 24), 12, 4.0, 8.0, (31, 2)),
             # an axis longer than 192 points: that stage takes the per-line kernel, the others the matrix cores
-            make_system("smooth-long", np.diag([40.0, 5.0, 5.0]), (200, 6, 6), 3, 2.0, 2.0, (31, 3))]
+            make_system("smooth-long", np.diag([40.0, 5.0, 5.0]), (200, 6, 6), 3, 2.0, 2.0, (31, 3)),
+            # more orbitals than one 32-wide tile of the coefficient scatter, the last tile partial (70 = 2 x 32
+            # + 6), and several hundred planewaves
+            make_system("smooth-wide", SKEW, (12, 12, 14), 70, 2.6, 2.0, (31, 4))]
 
 
 def _gpu_smoothing(s, dtype, has_lap):
@@ -32,7 +35,7 @@ def _gpu_smoothing(s, dtype, has_lap):
     return d, tab
 
 
-@pytest.mark.parametrize("k", [0, 1, 2, 3])
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("has_lap", [False, True])
 def test_smoothing_table_matches_oracle(k, has_lap):
     s = systems()[k]

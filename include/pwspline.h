@@ -255,6 +255,20 @@ int spline_eval_vgl_sorted(const spl_desc* d, const void* table, int64_t n_pts, 
 int spline_sorted_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes);
 
 /*
+ * spline_eval_vgl_sorted for callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same computation and outputs, bit for bit, with the
+ * workspace taken from a static device array of the library (16 MiB per device, held until the process
+ * ends) instead of a caller buffer.  Calls no allocating routine; the first call on a device looks up
+ * that device's copy of the array.  All arguments as for spline_eval_vgl_sorted (no work, work_bytes).
+ * Limit: the workspace of n_pts points must fit in 16 MiB, about 1.8 million points; more ->
+ * SPL_EINVAL before anything is enqueued (use spline_eval_vgl_sorted).  Every call on a device shares
+ * that device's array and leaves it dirty: calls that overlap on one device (other streams, other host
+ * threads) race and must be serialized by the caller.
+ */
+int spline_eval_vgl_sorted_noalloc(const spl_desc* d, const void* table, int64_t n_pts, const double* pos,
+                                   void* v, void* grad, void* lap, const int32_t* tile, void* stream);
+
+/*
  * Values, gradients and Laplacians as spline_eval_vgl, computed cell by cell: the points are
  * sorted by grid cell (stable radix sort), and for the points of one cell the outputs are a dense
  * product of their 64 row weights with the cell's 4x4x4 block (Eq. b-splineapproximation with

@@ -27,7 +27,7 @@ EXPORTS = (
     "spline_build_smoothing", "spline_smoothing_work_bytes", "spline_build_tables",
     "spline_eval_vgl_sorted", "spline_sorted_work_bytes", "spline_batch_plan_sort", "spline_misfit",
     "spline_misfit_work_bytes", "spline_smoothness_penalty", "spline_eval_vgl_cells", "spline_cells_work_bytes",
-    "spline_fit_terms_cells", "spline_stream_read",
+    "spline_fit_terms_cells", "spline_stream_read", "spline_eval_vgl_sorted_noalloc",
 )
 
 
@@ -95,6 +95,7 @@ def lib():
             "spline_build_tables": (ctypes.c_int, [pd, vp, vp, vp, vp]),
             "spline_eval_vgl_sorted": (ctypes.c_int, [pd, vp, i64, vp, vp, vp, vp, i32p, vp, i64, vp]),
             "spline_sorted_work_bytes": (ctypes.c_int, [pd, i64, ctypes.POINTER(i64)]),
+            "spline_eval_vgl_sorted_noalloc": (ctypes.c_int, [pd, vp, i64, vp, vp, vp, vp, i32p, vp]),
             "spline_eval_v": (ctypes.c_int, [pd, vp, i64, vp, vp, vp]),
             "spline_eval_vgl": (ctypes.c_int, [pd, vp, i64, vp, vp, vp, vp, vp]),
             "spline_eval_vgl_tile": (ctypes.c_int, [pd, vp, i64, vp, vp, vp, vp, i32p, vp]),

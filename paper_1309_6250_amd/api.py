@@ -255,6 +255,19 @@ def spline_eval_vgl_sorted(desc, table, pos, v=None, grad=None, lap=None, work=N
     return _as_complex(desc, v), _as_complex(desc, grad), _as_complex(desc, lap)
 
 
+def spline_eval_vgl_sorted_noalloc(desc, table, pos, v, grad, lap, tile=None, stream=None):
+    """spline_eval_vgl_sorted with the library's static device scratch as workspace: allocates
+    nothing, so the outputs v, grad, lap must be given.  Calls that overlap on one device race."""
+    n = _check_inputs(desc, table, pos)
+    if v is None or grad is None or lap is None:
+        raise ValueError("spline_eval_vgl_sorted_noalloc allocates nothing: pass v, grad and lap")
+    v, grad, lap = _outputs(desc, n, pos.device, v, grad, lap)
+    t = None if tile is None else (ctypes.c_int32 * 2)(int(tile[0]), int(tile[1]))
+    check(lib().spline_eval_vgl_sorted_noalloc(ctypes.byref(desc), _ptr(table), n, _ptr(pos), _ptr(v), _ptr(grad),
+                                               _ptr(lap), t, _stream(stream)), "spline_eval_vgl_sorted_noalloc")
+    return _as_complex(desc, v), _as_complex(desc, grad), _as_complex(desc, lap)
+
+
 def spline_cells_work_bytes(desc, n_pts):
     out = ctypes.c_int64()
     check(lib().spline_cells_work_bytes(ctypes.byref(desc), int(n_pts), ctypes.byref(out)), "spline_cells_work_bytes")

@@ -12,6 +12,8 @@
 // launch: bitwise the same results.
 #include <hipcub/hipcub.hpp>
 
+#include <mutex>
+
 #include "internal.hpp"
 
 namespace pws {
@@ -142,4 +144,63 @@ int launch_eval_sorted(const spl_desc* d, const void* table, int64_t n_pts, cons
   return hip_fail(hipGetLastError(), "sorted evaluation launch");
 }
 
+// ---------------------------------------------------------------- variant that allocates nothing
+// The workspace of the sorted evaluation (per-point buckets and permutation, bucket counts and
+// offsets, the scan's scratch) in a fixed device array instead of a caller buffer, for callers that
+// cannot allocate.  Each device holds its own copy of the array at its own address, taken once per
+// device with the device current; host code uses only that address.  Every call on a device shares
+// its copy, so calls that overlap on one device race.
+constexpr int64_t NOALLOC_SCRATCH_BYTES = int64_t(16) << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+static int scratch_for_current_device(void** out) {
+  int dev = -1;
+  int rc = hip_fail(hipGetDevice(&dev), "hipGetDevice");
+  if (rc) return rc;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+    return fail(SPL_EUNSUPPORTED, "device %d is beyond the %d the scratch table covers", dev, NOALLOC_MAX_DEVICES);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if ((rc = hip_fail(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"))) return rc;
+    if (!p) return fail(SPL_EHIP, "hipGetSymbolAddress(scratch) returned a null address");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SPL_OK;
+}
+
 }  // namespace pws
+
+using namespace pws;
+
+extern "C" int spline_eval_vgl_sorted_noalloc(const spl_desc* d, const void* table, int64_t n_pts, const double* pos,
+                                              void* v, void* grad, void* lap, const int32_t* tile, void* stream) {
+  clear_error();
+  int rc = check_eval_args(d, table, n_pts, pos);
+  if (rc) return rc;
+  if (n_pts == 0) return SPL_OK;
+  if ((rc = check_vgl_outputs(d, v, grad, lap))) return rc;
+  int32_t t[2];
+  if (tile) {
+    t[0] = tile[0];
+    t[1] = tile[1];
+  } else {
+    tile_for(d, t);
+  }
+  if (!tile_valid_for(d, t)) return fail(SPL_EINVAL, "invalid tile");
+  PermLayout L;
+  if ((rc = perm_layout(d, n_pts, &L))) return rc;
+  if ((int64_t)L.total > NOALLOC_SCRATCH_BYTES)
+    return fail(SPL_EINVAL, "%lld points need %lld bytes of workspace; the static scratch holds %lld bytes "
+                "(about %lld points): use spline_eval_vgl_sorted with a caller workspace",
+                (long long)n_pts, (long long)L.total, (long long)NOALLOC_SCRATCH_BYTES,
+                (long long)((NOALLOC_SCRATCH_BYTES - ((int64_t)L.total - 8 * n_pts)) / 8));
+  void* w = nullptr;
+  if ((rc = scratch_for_current_device(&w))) return rc;
+  return launch_eval_sorted(d, table, n_pts, pos, v, grad, lap, 0, t, w, NOALLOC_SCRATCH_BYTES,
+                            static_cast<hipStream_t>(stream));
+}

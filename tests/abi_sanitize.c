@@ -205,6 +205,17 @@ int main(void) {
   expect(spline_batch_plan_create(&item, 1, NULL, NULL, &plan), SPL_EUNSUPPORTED, "plan pp item");
   expect(spline_batch_plan_sort(NULL, 1, NULL), SPL_EINVAL, "plan sort NULL");
 
+  /* the sorted evaluation without allocation: rejected arguments, and no points (a no-op) */
+  expect(spline_eval_vgl_sorted_noalloc(NULL, fake, 4, fpos, fake, fake, fake, NULL, NULL), SPL_EINVAL,
+         "noalloc NULL desc");
+  expect(spline_eval_vgl_sorted_noalloc(&d, NULL, 4, fpos, fake, fake, fake, NULL, NULL), SPL_EINVAL,
+         "noalloc NULL table");
+  expect(spline_eval_vgl_sorted_noalloc(&d, fake, -1, fpos, fake, fake, fake, NULL, NULL), SPL_EINVAL,
+         "noalloc negative n_pts");
+  expect(spline_eval_vgl_sorted_noalloc(&d, fake, 4, fpos, NULL, fake, fake, NULL, NULL), SPL_EINVAL,
+         "noalloc NULL output");
+  expect(spline_eval_vgl_sorted_noalloc(&d, fake, 0, fpos, fake, fake, fake, NULL, NULL), SPL_OK, "noalloc no points");
+
   /* read-rate probe */
   expect(spline_stream_read(NULL, 16, fake, NULL), SPL_EINVAL, "stream NULL buf");
   expect(spline_stream_read(fake, 16, NULL, NULL), SPL_EINVAL, "stream NULL sink");

@@ -431,10 +431,24 @@ int spline_batch_eval_vgl(void* plan, void* stream);
  * replay the same graph; changing the plan's tile drops it. */
 int spline_batch_graph_launch(void* plan, void* stream);
 
-/* Time every batch tile shape (lanes per point 8..256 x the dtype's orbitals-per-lane
- * choices) with whole persistent launches on `stream` (synchronizes), keep the fastest in
- * the plan and return it in tile_out.  Outputs are overwritten with valid results. */
+/* Choose the plan's tile shapes by timing on `stream` (synchronizes): every common shape (lanes per
+ * point 8..256 x the dtype's orbitals-per-lane choices) with whole persistent launches, then, for
+ * each orbitals-per-lane choice, per-item shapes (each item's lanes per point the fastest for that
+ * item alone, timed with the single-system kernel on its own buffers) again as whole launches.  The
+ * fastest is kept in the plan; tile_out gets the common shape, or (0, orbitals per lane) when items
+ * keep their own lanes per point (spline_batch_plan_get_tiles lists them).  Every shape gives the same
+ * outputs bit for bit; they are overwritten with valid results. */
 int spline_batch_autotune(void* plan, void* stream, int32_t tile_out[2]);
+
+/* Each item's tile shape in the caller's item order: tiles_out[2 j] = lanes per point of item j,
+ * tiles_out[2 j + 1] = orbitals per lane (common to all items).  Host only. */
+int spline_batch_plan_get_tiles(void* plan, int32_t* tiles_out);
+
+/* Give each item its own lanes per point: tiles[2 j], tiles[2 j + 1] as above, in the caller's item
+ * order (a power of two in 8..256; one orbitals-per-lane value for all items, valid for the dtype).
+ * Synchronizes `stream` (uploads the plan's records); drops the captured graph.  Errors: NULL plan
+ * or tiles, an invalid shape, or differing orbitals per lane -> SPL_EINVAL. */
+int spline_batch_plan_set_tiles(void* plan, const int32_t* tiles, void* stream);
 
 /* Evaluate the plan's points in locality order (enable = 1) or in their given order (0, the
  * default).  Sorted launches first counting-sort every item's points into buckets of its cells

@@ -28,6 +28,7 @@ EXPORTS = (
     "spline_eval_vgl_sorted", "spline_sorted_work_bytes", "spline_batch_plan_sort", "spline_misfit",
     "spline_misfit_work_bytes", "spline_smoothness_penalty", "spline_eval_vgl_cells", "spline_cells_work_bytes",
     "spline_fit_terms_cells", "spline_stream_read", "spline_eval_vgl_sorted_noalloc",
+    "spline_batch_plan_get_tiles", "spline_batch_plan_set_tiles",
 )
 
 
@@ -118,6 +119,8 @@ def lib():
             "spline_batch_plan_destroy": (None, [vp]),
             "spline_batch_plan_sort": (ctypes.c_int, [vp, i32, vp]),
             "spline_batch_plan_info": (ctypes.c_int, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+            "spline_batch_plan_get_tiles": (ctypes.c_int, [vp, i32p]),
+            "spline_batch_plan_set_tiles": (ctypes.c_int, [vp, i32p, vp]),
             "spline_autotune": (ctypes.c_int, [pd, vp, i64, vp, vp, vp, vp, vp, i32p]),
             "spline_tile_for": (ctypes.c_int, [pd, i64, i32p]),
             "spline_stream_read": (ctypes.c_int, [vp, i64, vp, vp]),

@@ -482,6 +482,17 @@ class BatchPlan:
         check(lib().spline_batch_autotune(self._plan, _stream(stream), t), "spline_batch_autotune")
         return (t[0], t[1])
 
+    def tiles(self):
+        """Each item's (lanes per point, orbitals per lane), in the order the items were given."""
+        t = (ctypes.c_int32 * (2 * len(self._descs)))()
+        check(lib().spline_batch_plan_get_tiles(self._plan, t), "spline_batch_plan_get_tiles")
+        return [(t[2 * j], t[2 * j + 1]) for j in range(len(self._descs))]
+
+    def set_tiles(self, tiles, stream=None):
+        """Give item j the shape tiles[j] = (lanes per point, orbitals per lane); one orbitals per lane for all."""
+        flat = (ctypes.c_int32 * (2 * len(self._descs)))(*[int(x) for t in tiles for x in t])
+        check(lib().spline_batch_plan_set_tiles(self._plan, flat, _stream(stream)), "spline_batch_plan_set_tiles")
+
     def sort(self, enable=True, stream=None):
         """Evaluate the points in locality order from now on (same outputs); allocates once."""
         check(lib().spline_batch_plan_sort(self._plan, 1 if enable else 0, _stream(stream)), "spline_batch_plan_sort")

@@ -81,7 +81,9 @@ __global__ void k_batch_reset(int32_t* counter) {
 struct Plan {
   int dtype = 0;
   int mode = MODE_VGL;
-  int32_t tile[2] = {0, 0};
+  int32_t tile[2] = {0, 0};           // the common shape; tile[0] = 0: per-item lanes (lanes[])
+  std::vector<int32_t> lanes;         // lanes per point of each item (sorted order)
+  std::vector<int> order;             // sorted position -> caller's item index
   std::vector<spl_desc> descs;        // copies of the items' descriptors (sorted order)
   std::vector<spl_item> items;        // caller's items (sorted order)
   std::vector<EvalArgs> args;         // per-item kernel arguments for the current tile
@@ -123,21 +125,29 @@ static void drop_graph(Plan* pl) {
   pl->graph = nullptr;
 }
 
-// (Re)derive kernel arguments, the tile prefix and the launch grid for tile shape `tile`, and
-// upload them.  Synchronous on `stream`.
-static int plan_set_tile(Plan* pl, const int32_t tile[2], hipStream_t stream) {
-  if (!tile_valid(pl->dtype, tile) || tile[0] < 8)
-    return fail(SPL_EINVAL, "invalid batch tile (%d, %d): lanes per point must be 8..256", tile[0], tile[1]);
-  BatchKernel k = pick_batch(pl->dtype, pl->mode, tile[0], tile[1]);
-  if (!k) return fail(SPL_EINVAL, "invalid batch tile (%d, %d)", tile[0], tile[1]);
+// (Re)derive kernel arguments, the tile prefix and the launch grid, and upload them: with
+// tile[0] > 0 every item takes the shape `tile`; with tile[0] == 0 item j (sorted order) takes
+// lanes[j] lanes per point and tile[1] orbitals per lane.  Synchronous on `stream`.
+static int plan_set_shapes(Plan* pl, const int32_t tile[2], const int32_t* lanes, hipStream_t stream) {
   const int n = (int)pl->items.size();
-  const int per_tile = 256 / tile[0];
+  const bool multi = tile[0] == 0;
+  for (int j = 0; j < (multi ? n : 1); ++j) {
+    const int32_t t[2] = {multi ? lanes[j] : tile[0], tile[1]};
+    if (!tile_valid(pl->dtype, t) || t[0] < 8)
+      return fail(SPL_EINVAL, "invalid batch tile (%d, %d): lanes per point must be 8..256", t[0], t[1]);
+  }
+  BatchKernel k = pick_batch(pl->dtype, pl->mode, multi ? 0 : tile[0], tile[1]);
+  if (!k) return fail(SPL_EINVAL, "invalid batch tile (%d, %d)", tile[0], tile[1]);
   pl->args.resize(n);
   pl->tile_start.assign(n + 1, 0);
+  pl->lanes.resize(n);
   int64_t tiles = 0;
   for (int j = 0; j < n; ++j) {
     const spl_item& it = pl->items[j];
+    pl->lanes[j] = multi ? lanes[j] : tile[0];
+    const int per_tile = 256 / pl->lanes[j];
     fill_eval_args(&pl->descs[j], it.table, it.n_pts, it.pos, it.v, it.grad, it.lap, 0, tile[1], &pl->args[j]);
+    pl->args[j].lanes = pl->lanes[j];
     if (pl->sort_on) pl->args[j].perm = pl->d_perm + pl->point_start[j];
     pl->tile_start[j] = (int32_t)tiles;
     tiles += (it.n_pts + per_tile - 1) / per_tile;
@@ -167,6 +177,11 @@ static int plan_set_tile(Plan* pl, const int32_t tile[2], hipStream_t stream) {
   pl->tile[1] = tile[1];
   drop_graph(pl);
   return SPL_OK;
+}
+
+static int plan_set_tile(Plan* pl, const int32_t tile[2], hipStream_t stream) {
+  if (tile[0] == 0) return fail(SPL_EINVAL, "invalid batch tile (0, %d): lanes per point must be 8..256", tile[1]);
+  return plan_set_shapes(pl, tile, nullptr, stream);
 }
 
 static int plan_launch(Plan* pl, hipStream_t stream) {
@@ -201,6 +216,23 @@ static int plan_launch(Plan* pl, hipStream_t stream) {
   b.n_tiles = pl->n_tiles;
   hipLaunchKernelGGL(pl->kernel, dim3(pl->grid), dim3(256), 0, stream, b);
   return hip_fail(hipGetLastError(), "batch launch");
+}
+
+// Median of three timed launches (after one untimed), ms.
+static int time_plan(Plan* pl, hipStream_t s, hipEvent_t e0, hipEvent_t e1, float* ms) {
+  int rc = plan_launch(pl, s);
+  float times[3];
+  for (int r = 0; r < 3 && !rc; ++r) {
+    hipEventRecord(e0, s);
+    rc = plan_launch(pl, s);
+    hipEventRecord(e1, s);
+    if (!rc) rc = hip_fail(hipEventSynchronize(e1), "hipEventSynchronize");
+    if (!rc) rc = hip_fail(hipEventElapsedTime(&times[r], e0, e1), "hipEventElapsedTime");
+  }
+  if (rc) return rc;
+  std::sort(times, times + 3);
+  *ms = times[1];
+  return SPL_OK;
 }
 
 static void plan_free(Plan* pl) {
@@ -295,6 +327,7 @@ int spline_batch_plan_create(const spl_item* items, int32_t n_items, const int32
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return items[a].d->o_pad > items[b].d->o_pad; });
   int best = 0;
+  pl->order = order;
   for (int j : order) {
     pl->descs.push_back(*items[j].d);
     pl->items.push_back(items[j]);
@@ -373,38 +406,99 @@ int spline_batch_autotune(void* plan, void* stream, int32_t tile_out[2]) {
     hipEventDestroy(e0);
     return rc;
   }
+  const int n = (int)pl->items.size();
   float best = 1e30f;
   int32_t best_tile[2] = {pl->tile[0], pl->tile[1]};
+  std::vector<int32_t> best_lanes;
+  // one shape for every item
   for (int k = 0; k < 3 && !rc; ++k) {
     if (k > 0 && set[k] == set[k - 1]) continue;
     for (int g = 8; g <= 256 && !rc; g <<= 1) {
       const int32_t t[2] = {g, set[k]};
-      if ((rc = plan_set_tile(pl, t, s))) break;
-      if ((rc = plan_launch(pl, s))) break;       // warm-up
-      float times[3];
-      for (int r = 0; r < 3 && !rc; ++r) {
-        hipEventRecord(e0, s);
-        rc = plan_launch(pl, s);
-        hipEventRecord(e1, s);
-        if (!rc) rc = hip_fail(hipEventSynchronize(e1), "hipEventSynchronize");
-        if (!rc) rc = hip_fail(hipEventElapsedTime(&times[r], e0, e1), "hipEventElapsedTime");
-      }
-      if (rc) break;
-      std::sort(times, times + 3);
-      if (times[1] < best) {
-        best = times[1];
+      float ms = 0.f;
+      if ((rc = plan_set_tile(pl, t, s)) || (rc = time_plan(pl, s, e0, e1, &ms))) break;
+      if (ms < best) {
+        best = ms;
         best_tile[0] = t[0];
         best_tile[1] = t[1];
       }
     }
   }
+  // per item: at each orbitals-per-lane choice, the lanes per point that run the item fastest on its
+  // own (the single-system kernel on the item's buffers); then the whole launch with those shapes
+  for (int k = 0; k < 3 && !rc; ++k) {
+    if (k > 0 && set[k] == set[k - 1]) continue;
+    std::vector<int32_t> lanes(n, 8);
+    for (int j = 0; j < n && !rc; ++j) {
+      const spl_item& it = pl->items[j];
+      if (it.n_pts == 0) continue;
+      float bj = 1e30f;
+      for (int g = 8; g <= 256 && !rc; g <<= 1) {
+        const int32_t t[2] = {g, set[k]};
+        if (!tile_valid_for(&pl->descs[j], t)) continue;
+        rc = launch_eval(&pl->descs[j], it.table, it.n_pts, it.pos, it.v, it.grad, it.lap, 0, t, s);
+        float times[3];
+        for (int r = 0; r < 3 && !rc; ++r) {
+          hipEventRecord(e0, s);
+          rc = launch_eval(&pl->descs[j], it.table, it.n_pts, it.pos, it.v, it.grad, it.lap, 0, t, s);
+          hipEventRecord(e1, s);
+          if (!rc) rc = hip_fail(hipEventSynchronize(e1), "hipEventSynchronize");
+          if (!rc) rc = hip_fail(hipEventElapsedTime(&times[r], e0, e1), "hipEventElapsedTime");
+        }
+        if (rc) break;
+        std::sort(times, times + 3);
+        if (times[1] < bj) {
+          bj = times[1];
+          lanes[j] = g;
+        }
+      }
+    }
+    if (rc) break;
+    const int32_t t[2] = {0, set[k]};
+    float ms = 0.f;
+    if ((rc = plan_set_shapes(pl, t, lanes.data(), s)) || (rc = time_plan(pl, s, e0, e1, &ms))) break;
+    if (ms < best) {
+      best = ms;
+      best_tile[0] = 0;
+      best_tile[1] = set[k];
+      best_lanes = lanes;
+    }
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (rc) return rc;
-  if ((rc = plan_set_tile(pl, best_tile, s))) return rc;
+  if ((rc = plan_set_shapes(pl, best_tile, best_lanes.empty() ? nullptr : best_lanes.data(), s))) return rc;
   tile_out[0] = best_tile[0];
   tile_out[1] = best_tile[1];
   return SPL_OK;
+}
+
+int spline_batch_plan_get_tiles(void* plan, int32_t* tiles_out) {
+  clear_error();
+  if (!plan || !tiles_out) return fail(SPL_EINVAL, "plan and tiles_out must be non-NULL");
+  Plan* pl = static_cast<Plan*>(plan);
+  for (size_t j = 0; j < pl->items.size(); ++j) {
+    tiles_out[2 * pl->order[j]] = pl->lanes[j];
+    tiles_out[2 * pl->order[j] + 1] = pl->tile[1];
+  }
+  return SPL_OK;
+}
+
+int spline_batch_plan_set_tiles(void* plan, const int32_t* tiles, void* stream) {
+  clear_error();
+  if (!plan || !tiles) return fail(SPL_EINVAL, "plan and tiles must be non-NULL");
+  Plan* pl = static_cast<Plan*>(plan);
+  const int n = (int)pl->items.size();
+  std::vector<int32_t> lanes(n);
+  for (int j = 0; j < n; ++j) {
+    const int c = pl->order[j];
+    if (tiles[2 * c + 1] != tiles[1])
+      return fail(SPL_EINVAL, "item %d: every item of a plan takes the same orbitals per lane (%d, not %d)", c, tiles[1],
+                  tiles[2 * c + 1]);
+    lanes[j] = tiles[2 * c];
+  }
+  const int32_t t[2] = {0, tiles[1]};
+  return plan_set_shapes(pl, t, lanes.data(), static_cast<hipStream_t>(stream));
 }
 
 void spline_batch_plan_destroy(void* plan) { plan_free(static_cast<Plan*>(plan)); }
@@ -419,7 +513,8 @@ int spline_batch_plan_sort(void* plan, int32_t enable, void* stream) {
   if (enable && (rc = plan_sort_setup(pl, s))) return rc;
   pl->sort_on = enable != 0;
   const int32_t t[2] = {pl->tile[0], pl->tile[1]};
-  return plan_set_tile(pl, t, s);                    // refreshes the items' permutation pointers, drops the graph
+  const std::vector<int32_t> lanes = pl->lanes;
+  return plan_set_shapes(pl, t, lanes.data(), s);   // refreshes the items' permutation pointers, drops the graph
 }
 
 int spline_batch_plan_info(void* plan, int64_t* n_tiles, int64_t* n_evals) {

@@ -46,11 +46,11 @@ __host__ __device__ inline int axis_colour(int i, int n) {
 __host__ __device__ inline int axis_colours(int n) { return 4 + (n & 3); }
 
 struct SortLayout {
-  size_t keys_in, keys_out, vals_in, vals_out, uniq, counts, offsets, num_runs, class_start, pts, occ, blocks,
+  size_t keys_in, keys_out, vals_in, vals_out, uniq, counts, offsets, num_runs, class_start, pts, cell_run, blocks,
       partials, temp;
   size_t temp_bytes, total;
   int n_classes;
-  int dense;           // 1: per-cell blocks in the workspace and a per-row gather instead of colour classes
+  int dense;           // 1: brick regions in the workspace and a per-row gather instead of colour classes
   int64_t n_cells;
   int end_bit;
 };
@@ -106,11 +106,13 @@ static int sort_layout(const spl_desc* d, int64_t n_pts, SortLayout* L, bool adj
   L->num_runs = off; off = align_up(off + 4);
   L->class_start = off; off = align_up(off + 4 * (size_t)(L->n_classes + 2));
   L->pts = off; off = align_up(off + (d->dtype == SPL_F64 ? 32 : 16) * n);
-  // dense points (at least 4 per cell on average): every cell's 64-row block gets its own place
+  // dense points (at least 4 per cell on average): the 5 x 5 x 5-row region of every brick of 2 x 2 x 2
+  // cells gets its own place, and every cell the index of its run
   const size_t gsz = d->dtype == SPL_F64 ? 8 : 4;
-  const size_t block_bytes = (size_t)L->n_cells * 64 * (size_t)d->o_pad * gsz;
+  const size_t n_bricks = (size_t)((d->grid[0] + 1) / 2) * ((d->grid[1] + 1) / 2) * ((d->grid[2] + 1) / 2);
+  const size_t block_bytes = n_bricks * 125 * (size_t)d->o_pad * gsz;
   L->dense = adjoint_blocks && n_pts >= 4 * L->n_cells && block_bytes <= ((size_t)4 << 30);
-  L->occ = off; off = align_up(off + (L->dense ? 4 * (size_t)L->n_cells : 0));
+  L->cell_run = off; off = align_up(off + (L->dense ? 4 * (size_t)L->n_cells : 0));
   L->blocks = off; off = align_up(off + (L->dense ? block_bytes : 0));
   // forward only: one FP64 partial sum per work item of the fit terms, at most min(n, cells) runs
   // times the 16-orbital tiles, then one per workgroup of the first summing step (FIT_SUM_BLOCKS)
@@ -200,10 +202,9 @@ struct CellArgs {
   int32_t n_groups;        // orbital groups of 16 OT per cell
   int32_t n_classes;
   int32_t n_pts;           // every index read from the sort is checked against this and n_cells
-  int32_t dense;           // 1: all occupied cells at once, blocks written to `blocks`, `occ` marked
   int32_t o_pad;
-  void* blocks;            // [n_cells][64][o_pad] per-cell gradient blocks (dense)
-  int32_t* occ;            // [n_cells] 1 where the cell holds points (dense)
+  void* blocks;            // dense: [n_bricks][125][o_pad] gradient regions of the bricks of 2 x 2 x 2 cells
+  const int32_t* cell_run; // dense: [n_cells] run of each cell's points, -1 for an empty cell
 };
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -244,6 +245,139 @@ template <> struct Mfma<double> {
 // summation order is fixed by the sorted point order, so the result is reproducible bit for bit.
 constexpr int CELL_PB = 32;         // most points per batch
 
+// The gradient block of one cell: the sum over its points (sorted positions start .. start + cnt - 1,
+// in that order) of every term's row weights times its upstream values, for the orbitals
+// ob + 16 ot + col, into acc (4 row tiles of 16 rows x OT orbital tiles).  s_p and s_w are the
+// wave's LDS staging of a batch's point indices and 1-D weights.
+template <typename A, int OT, int NT>
+__device__ __forceinline__ void cell_block(const CellArgs& a, int start, int cnt, int ob, const bool (&ocol)[OT],
+                                           const A (&jm)[9], const A (&mt)[6], int* s_p, A (*s_w)[36],
+                                           typename Mfma<A>::acc (&acc)[4][OT]) {
+  using M = Mfma<A>;
+  using Acc = typename M::acc;
+  const int lane = (int)threadIdx.x & 63;            // the lane's role in the matrix-core steps
+  const int grp = lane >> 4;
+  const int col = lane & 15;
+  const int m_ = col >> 2, n_ = col & 3;
+  const int nt = a.n_terms;
+  const SortedPoint<A>* pts = static_cast<const SortedPoint<A>*>(a.pts);
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = Acc{};
+
+  for (int b0 = 0; b0 < cnt; b0 += CELL_PB) {
+    const int nb = min(CELL_PB, cnt - b0);
+    __syncthreads();                                   // every wave has consumed the previous batch
+    if ((int)threadIdx.x < nb) {                       // the first wave stages the batch for all waves
+      const int j = (int)threadIdx.x;
+      const SortedPoint<A> sp = pts[start + b0 + j];
+      s_p[j] = (unsigned)sp.p < (unsigned)a.n_pts ? sp.p : -1;   // -1: contributes nothing
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        A w4[4], d4[4], dd4[4];
+        bspline_weights<A>(sp.t[ax], w4, d4, dd4);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          s_w[j][12 * ax + i] = w4[i];
+          s_w[j][12 * ax + 4 + i] = d4[i];
+          s_w[j][12 * ax + 8 + i] = dd4[i];
+        }
+      }
+    }
+    __syncthreads();
+    // upstream values of lane group k's point 4q + k, for terms c0 .. c0 + NC - 1 and every orbital tile
+    auto load_b = [&](int q, auto& bv) {
+      constexpr int NC = sizeof(bv) / sizeof(bv[0]);
+      const int j = q + grp;
+      const int pj = j < nb ? s_p[j] : -1;
+      const bool live = pj >= 0;
+      const int64_t p = live ? (int64_t)pj : 0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int ot = 0; ot < OT; ++ot) {
+          const A* src = static_cast<const A*>(a.src[c]);
+          bv[c][ot] = (c < nt && live && ocol[ot]) ? src[p * a.src_stride[c] + ob + ot * 16 + col] : A(0);
+        }
+    };
+    // the products of one step of four points: every term's row weights times its upstream values
+    auto multiply = [&](int q, const auto& bv) {
+      constexpr int NC = sizeof(bv) / sizeof(bv[0]);
+      const A* wp = s_w[min(q + grp, nb - 1)];        // a dead lane group multiplies zeros
+      A wx[4], dwx[4], d2wx[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        wx[i] = wp[i];
+        dwx[i] = wp[4 + i];
+        d2wx[i] = wp[8 + i];
+      }
+      const A wy = wp[12 + m_], dwy = wp[16 + m_], d2wy = wp[20 + m_];
+      const A wz = wp[24 + n_], dwz = wp[28 + n_], d2wz = wp[32 + n_];
+      const A yz = wy * wz;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        if (c >= nt) break;
+        // row weight of this term: Q0 w_x + Q1 w_x' + Q2 w_x'' on the lane's (m, n), per row tile l
+        const int kind = a.kind[c];
+        A q0, q1 = A(0), q2 = A(0);
+        if (kind == TERM_VAL) {
+          q0 = yz;
+        } else if (kind == TERM_LAP) {
+          q2 = mt[0] * yz;
+          q1 = A(2) * fmaa(mt[3] * dwy, wz, mt[4] * wy * dwz);
+          q0 = fmaa(mt[1] * d2wy, wz, fmaa(mt[2] * wy, d2wz, A(2) * mt[5] * dwy * dwz));
+        } else {
+          const int k = kind - TERM_GX;
+          q1 = jm[k] * yz;
+          q0 = fmaa(jm[3 + k] * dwy, wz, jm[6 + k] * wy * dwz);
+        }
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+          const A av = fmaa(q2, d2wx[rt], fmaa(q1, dwx[rt], q0 * wx[rt]));
+#pragma unroll
+          for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = M::step(av, bv[c][ot], acc[rt][ot]);
+        }
+      }
+    };
+    if constexpr (NT <= 2) {
+      // at most two terms: the whole batch's upstream values are loaded at once
+      A bq[CELL_PB / 4][NT][OT];
+#pragma unroll
+      for (int qi = 0; qi < CELL_PB / 4; ++qi) load_b(4 * qi, bq[qi]);
+#pragma unroll
+      for (int qi = 0; qi < CELL_PB / 4; ++qi)
+        if (4 * qi < nb) multiply(4 * qi, bq[qi]);
+    } else {
+      // up to five terms: the next step's values are loaded while the current ones are multiplied
+      A bcur[5][OT];
+      load_b(0, bcur);
+      for (int q = 0; q < nb; q += 4) {
+        A bnext[5][OT];
+        if (q + 4 < nb) load_b(q + 4, bnext);
+        multiply(q, bcur);
+#pragma unroll
+        for (int c = 0; c < 5; ++c)
+#pragma unroll
+          for (int ot = 0; ot < OT; ++ot) bcur[c][ot] = bnext[c][ot];
+      }
+    }
+  }
+}
+
+// Sparse points: one wave per (occupied cell of the colour class, group of 16 OT orbitals).  For a
+// cell the gradient of its 64 rows is a dense product
+//     d beta[row][o] += sum over (point, term) W_term(point)[row] g_term[point][o],
+// done on the matrix cores: 4 row tiles of 16 (row = 16 l + 4 m + n for the block offsets
+// l, m, n) times OT orbital tiles of 16, with K running over (point, term) pairs four points at
+// a time (lane group k of the wave takes point 4q + k).
+//
+// The cell's points arrive as sorted records (reduced coordinates and index, one coalesced
+// load) in batches of at most CELL_PB; their 1-D weights go to LDS once per point.  With at
+// most two terms (NT = 2: the fit's value and Laplacian) all upstream values of a batch are
+// loaded at once; with more, those of the next four points are loaded while the current ones
+// are multiplied.  The update of the 64 rows loads every old value before it stores.  The
+// summation order is fixed by the sorted point order, so the result is reproducible bit for bit.
 template <typename A, int OT, int NT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_bwd_cells(CellArgs a) {
   using M = Mfma<A>;
@@ -254,13 +388,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   const int lane = (int)threadIdx.x;
   const int grp = lane >> 4;
   const int col = lane & 15;
-  const int m_ = col >> 2, n_ = col & 3;
   // run range, bounded so that a workspace holding anything else still stays inside the arrays
-  const int r0 = a.dense ? 0 : min(max(a.class_start[a.cls], 0), a.n_pts);
-  const int r1 = min(max(a.dense ? a.class_start[a.n_classes] : a.class_start[a.cls + 1], r0), a.n_pts);
+  const int r0 = min(max(a.class_start[a.cls], 0), a.n_pts);
+  const int r1 = min(max(a.class_start[a.cls + 1], r0), a.n_pts);
   const int64_t n_work = (int64_t)(r1 - r0) * a.n_groups;
-  const int nt = a.n_terms;
-  const SortedPoint<A>* pts = static_cast<const SortedPoint<A>*>(a.pts);
   A* gtab = static_cast<A*>(a.gtable);
   A jm[9], mt[6];
 #pragma unroll
@@ -290,124 +421,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       const int i = M::row(grp, e);                      // 4 m + n within the row tile
       return gtab + (int64_t)ix[rt] * a.g.s0 + (int64_t)iy[i >> 2] * a.g.s1 + (int64_t)iz[i & 3] * a.g.o_pad + ob + col;
     };
-
     Acc acc[4][OT];
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-      for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = Acc{};
-
-    for (int b0 = 0; b0 < cnt; b0 += CELL_PB) {
-      const int nb = min(CELL_PB, cnt - b0);
-      __syncthreads();                                   // the previous batch is consumed
-      if (lane < nb) {
-        const SortedPoint<A> sp = pts[start + b0 + lane];
-        s_p[lane] = (unsigned)sp.p < (unsigned)a.n_pts ? sp.p : -1;   // -1: contributes nothing
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-          A w4[4], d4[4], dd4[4];
-          bspline_weights<A>(sp.t[ax], w4, d4, dd4);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            s_w[lane][12 * ax + i] = w4[i];
-            s_w[lane][12 * ax + 4 + i] = d4[i];
-            s_w[lane][12 * ax + 8 + i] = dd4[i];
-          }
-        }
-      }
-      __syncthreads();
-      // upstream values of lane group k's point 4q + k, for terms c0 .. c0 + NC - 1 and every orbital tile
-      auto load_b = [&](int q, auto& bv) {
-        constexpr int NC = sizeof(bv) / sizeof(bv[0]);
-        const int j = q + grp;
-        const int pj = j < nb ? s_p[j] : -1;
-        const bool live = pj >= 0;
-        const int64_t p = live ? (int64_t)pj : 0;
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-          for (int ot = 0; ot < OT; ++ot) {
-            const A* src = static_cast<const A*>(a.src[c]);
-            bv[c][ot] = (c < nt && live && ocol[ot]) ? src[p * a.src_stride[c] + ob + ot * 16 + col] : A(0);
-          }
-      };
-      // the products of one step of four points: every term's row weights times its upstream values
-      auto multiply = [&](int q, const auto& bv) {
-        constexpr int NC = sizeof(bv) / sizeof(bv[0]);
-        const A* wp = s_w[min(q + grp, nb - 1)];        // a dead lane group multiplies zeros
-        A wx[4], dwx[4], d2wx[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          wx[i] = wp[i];
-          dwx[i] = wp[4 + i];
-          d2wx[i] = wp[8 + i];
-        }
-        const A wy = wp[12 + m_], dwy = wp[16 + m_], d2wy = wp[20 + m_];
-        const A wz = wp[24 + n_], dwz = wp[28 + n_], d2wz = wp[32 + n_];
-        const A yz = wy * wz;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          if (c >= nt) break;
-          // row weight of this term: Q0 w_x + Q1 w_x' + Q2 w_x'' on the lane's (m, n), per row tile l
-          const int kind = a.kind[c];
-          A q0, q1 = A(0), q2 = A(0);
-          if (kind == TERM_VAL) {
-            q0 = yz;
-          } else if (kind == TERM_LAP) {
-            q2 = mt[0] * yz;
-            q1 = A(2) * fmaa(mt[3] * dwy, wz, mt[4] * wy * dwz);
-            q0 = fmaa(mt[1] * d2wy, wz, fmaa(mt[2] * wy, d2wz, A(2) * mt[5] * dwy * dwz));
-          } else {
-            const int k = kind - TERM_GX;
-            q1 = jm[k] * yz;
-            q0 = fmaa(jm[3 + k] * dwy, wz, jm[6 + k] * wy * dwz);
-          }
-#pragma unroll
-          for (int rt = 0; rt < 4; ++rt) {
-            const A av = fmaa(q2, d2wx[rt], fmaa(q1, dwx[rt], q0 * wx[rt]));
-#pragma unroll
-            for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = M::step(av, bv[c][ot], acc[rt][ot]);
-          }
-        }
-      };
-      if constexpr (NT <= 2) {
-        // at most two terms: the whole batch's upstream values are loaded at once
-        A bq[CELL_PB / 4][NT][OT];
-#pragma unroll
-        for (int qi = 0; qi < CELL_PB / 4; ++qi) load_b(4 * qi, bq[qi]);
-#pragma unroll
-        for (int qi = 0; qi < CELL_PB / 4; ++qi)
-          if (4 * qi < nb) multiply(4 * qi, bq[qi]);
-      } else {
-        // up to five terms: the next step's values are loaded while the current ones are multiplied
-        A bcur[5][OT];
-        load_b(0, bcur);
-        for (int q = 0; q < nb; q += 4) {
-          A bnext[5][OT];
-          if (q + 4 < nb) load_b(q + 4, bnext);
-          multiply(q, bcur);
-#pragma unroll
-          for (int c = 0; c < 5; ++c)
-#pragma unroll
-            for (int ot = 0; ot < OT; ++ot) bcur[c][ot] = bnext[c][ot];
-        }
-      }
-    }
-    if (a.dense) {
-      // the cell's own block: plain stores, each element written once
-      A* bp = static_cast<A*>(a.blocks) + (int64_t)cell * 64 * a.o_pad + ob + col;
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          A* rp = bp + (int64_t)(16 * rt + M::row(grp, e)) * a.o_pad;
-#pragma unroll
-          for (int ot = 0; ot < OT; ++ot)
-            if (ocol[ot]) rp[16 * ot] = acc[rt][ot][e];
-        }
-      if (lane == 0) a.occ[cell] = 1;
-      continue;
-    }
+    cell_block<A, OT, NT>(a, start, cnt, ob, ocol, jm, mt, s_p, s_w, acc);
     // every old value is loaded before the first store: one memory latency for the update
     A old[4][4][OT];
 #pragma unroll
@@ -430,49 +445,181 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   }
 }
 
-// Dense points, second step: table row (X, Y, Z) receives the blocks of the 64 cells whose
-// 4x4x4 block contains it, cell (X - l + 1, Y - m + 1, Z - n + 1) at its row 16 l + 4 m + n, summed
-// in that fixed (l, m, n) order and added to the gradient table.  One workgroup per row (so the
-// cell lookups are uniform), its threads over the orbitals.
+// Dense points (4 or more per cell): the cells are taken in bricks of 2 x 2 x 2 (the last brick of
+// an axis with an odd count holds one cell along it).  The blocks of a brick's cells cover a
+// region of 5 x 5 x 5 table rows (rows 2 b - 1 .. 2 b + 3 along each axis, before the periodic
+// wrap).  One workgroup of BRICK_WAVES waves per (brick, group of BRICK_WAVES x 16 OT orbitals):
+// the first wave stages each batch of points (indices and 1-D weights) for all, and each wave forms
+// every cell's block for its own 16 OT orbitals (cell_block, cells in a fixed order) and adds it
+// into its columns of the region, held in LDS; the region then goes to the workspace once.  A
+// second kernel gathers, for every table row, the regions of the bricks that cover it.  So each
+// table row crosses memory about 2^3 to 3^3 times instead of 64 times (once per cell block
+// containing it), and the order of every sum stays fixed.
+constexpr int BRICK_ROWS = 125;
+constexpr int BRICK_WAVES = 4;
+
+template <typename A, int OT, int NT>
+__global__ __launch_bounds__(64 * BRICK_WAVES) void k_bwd_bricks(CellArgs a) {
+  using M = Mfma<A>;
+  using Acc = typename M::acc;
+  constexpr int BW = 16 * OT;                          // orbitals of a wave
+  constexpr int WBW = BRICK_WAVES * BW;                // orbitals of a workgroup
+  __shared__ int s_p[CELL_PB];
+  __shared__ A s_w[CELL_PB][36];
+  __shared__ A s_reg[BRICK_ROWS * WBW];                // the brick's region: [row][orbital of the workgroup]
+  const int wave = (int)threadIdx.x >> 6;
+  const int lane = (int)threadIdx.x & 63;
+  const int grp = lane >> 4;
+  const int col = lane & 15;
+  const int nbx = (a.g.n[0] + 1) >> 1, nby = (a.g.n[1] + 1) >> 1, nbz = (a.g.n[2] + 1) >> 1;
+  const int64_t n_bricks = (int64_t)nbx * nby * nbz;
+  const int n_wg = (a.n_groups + BRICK_WAVES - 1) / BRICK_WAVES;   // orbital groups of a workgroup
+  const int64_t n_work = n_bricks * n_wg;
+  // runs before the non-finite points, bounded like every index read from the workspace
+  const int n_runs = (int)min((int64_t)min(max(a.class_start[a.n_classes], 0), a.n_pts), a.n_cells);
+  A jm[9], mt[6];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) jm[i] = (A)a.g.jac[i];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) mt[i] = (A)a.g.metric[i];
+
+  for (int64_t w = blockIdx.x; w < n_work; w += gridDim.x) {
+    const int64_t brick = w / n_wg;
+    const int obw = (int)(w % n_wg) * WBW;             // first orbital of the workgroup
+    const int ob = obw + wave * BW;                    // first orbital of this wave
+    const int bz = (int)(brick % nbz);
+    const int by = (int)((brick / nbz) % nby);
+    const int bx = (int)(brick / ((int64_t)nbz * nby));
+    bool ocol[OT];
+#pragma unroll
+    for (int ot = 0; ot < OT; ++ot) ocol[ot] = ob + ot * 16 + col < a.n_orb;
+    __syncthreads();                                   // the previous region is written out
+    for (int i = (int)threadIdx.x; i < BRICK_ROWS * WBW; i += 64 * BRICK_WAVES) s_reg[i] = A(0);
+    for (int c8 = 0; c8 < 8; ++c8) {
+      const int cx = c8 >> 2, cy = (c8 >> 1) & 1, cz = c8 & 1;
+      const int X = 2 * bx + cx, Y = 2 * by + cy, Z = 2 * bz + cz;
+      if (X >= a.g.n[0] || Y >= a.g.n[1] || Z >= a.g.n[2]) continue;
+      const int64_t cell = ((int64_t)X * a.g.n[1] + Y) * a.g.n[2] + Z;
+      const int r = a.cell_run[cell];
+      if (r < 0 || r >= n_runs) continue;
+      const int start = a.offsets[r];
+      const int cnt = a.counts[r];
+      if (start < 0 || cnt < 0 || start > a.n_pts - cnt) continue;
+      Acc acc[4][OT];
+      cell_block<A, OT, NT>(a, start, cnt, ob, ocol, jm, mt, s_p, s_w, acc);
+      // add the block into the wave's columns of the region: block row (l, m, n) is region row
+      // (cx + l, cy + m, cz + n)
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = M::row(grp, e);
+          const int lrow = ((cx + rt) * 5 + cy + (i >> 2)) * 5 + cz + (i & 3);
+#pragma unroll
+          for (int ot = 0; ot < OT; ++ot) s_reg[lrow * WBW + wave * BW + ot * 16 + col] += acc[rt][ot][e];
+        }
+    }
+    __syncthreads();
+    A* out = static_cast<A*>(a.blocks) + brick * BRICK_ROWS * a.o_pad + obw;
+    for (int i = (int)threadIdx.x; i < BRICK_ROWS * WBW; i += 64 * BRICK_WAVES) {
+      const int lrow = i / WBW, c = i % WBW;
+      if (obw + c < a.n_orb) out[(int64_t)lrow * a.o_pad + c] = s_reg[i];
+    }
+  }
+}
+
+// Bricks (b, l) whose region row l (0 .. 4) lands on table row X of an axis of n rows with nb bricks:
+// region row l of brick b is row 2 b - 1 + l, taken modulo n.  Listed in a fixed order (images of X
+// from below, bricks ascending); at most 8.
+__device__ __forceinline__ int brick_rows_of(int X, int n, int nb, int bl[8], int ll[8]) {
+  int k = 0;
+  for (int img = -1; img <= 1; ++img) {
+    const int xp = X + img * n;                        // the row before the wrap
+    // 2 b - 1 <= xp <= 2 b + 3  <=>  (xp - 3) / 2 <= b <= (xp + 1) / 2
+    const int lo = (xp - 3 >= 0) ? (xp - 3 + 1) / 2 : -((3 - xp) / 2);
+    const int hi = (xp + 1 >= 0) ? (xp + 1) / 2 : -((-(xp + 1) + 1) / 2);
+    for (int b = max(lo, 0); b <= min(hi, nb - 1); ++b) {
+      const int l = xp - (2 * b - 1);
+      if (l >= 0 && l <= 4 && k < 8) {
+        bl[k] = b;
+        ll[k] = l;
+        ++k;
+      }
+    }
+  }
+  return k;
+}
+
+// Dense points, second step: table row (X, Y, Z) receives every brick region row that lands on it
+// (at most 3 along each axis), summed in a fixed order and added to the gradient table.  One
+// workgroup per row (so the lookups are uniform), its threads over the orbitals; every region row
+// is loaded before the sum, so the loads are in flight together.
+constexpr int GATHER_MAX = 27;
+
 template <typename A>
-__global__ __launch_bounds__(256) void k_bwd_gather(Geom g, const A* blocks, const int32_t* occ, int32_t n_orb,
-                                                    int32_t o_pad, A* gtab) {
+__global__ __launch_bounds__(256) void k_bwd_brick_gather(Geom g, const A* regions, int32_t n_orb, int32_t o_pad,
+                                                          A* gtab) {
   const int64_t row = blockIdx.x;
   const int Z = (int)(row % g.n[2]);
   const int Y = (int)((row / g.n[2]) % g.n[1]);
   const int X = (int)(row / ((int64_t)g.n[2] * g.n[1]));
-  int cx[4], cy[4], cz[4];                       // cell of block offset l: X - l + 1 (periodic)
+  const int nbx = (g.n[0] + 1) >> 1, nby = (g.n[1] + 1) >> 1, nbz = (g.n[2] + 1) >> 1;
+  int bx[8], lx[8], by[8], ly[8], bz[8], lz[8];
+  const int kx = min(brick_rows_of(X, g.n[0], nbx, bx, lx), 3);
+  const int ky = min(brick_rows_of(Y, g.n[1], nby, by, ly), 3);
+  const int kz = min(brick_rows_of(Z, g.n[2], nbz, bz, lz), 3);
+  int32_t off[GATHER_MAX];           // first element of each region row (< 2^31: regions are capped at 4 GiB)
+  int cnt = 0;
 #pragma unroll
-  for (int l = 0; l < 4; ++l) {
-    cx[l] = (X - l + 1 + 2 * g.n[0]) % g.n[0];
-    cy[l] = (Y - l + 1 + 2 * g.n[1]) % g.n[1];
-    cz[l] = (Z - l + 1 + 2 * g.n[2]) % g.n[2];
-  }
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const bool live = i < kx && j < ky && k < kz;
+        const int64_t brick = live ? ((int64_t)bx[i] * nby + by[j]) * nbz + bz[k] : 0;
+        const int lrow = live ? (lx[i] * 5 + ly[j]) * 5 + lz[k] : 0;
+        off[9 * i + 3 * j + k] = live ? (int32_t)((brick * BRICK_ROWS + lrow) * o_pad) : -1;
+        cnt += live;
+      }
+  (void)cnt;
   for (int o = threadIdx.x; o < n_orb; o += blockDim.x) {
+    A part[GATHER_MAX];
+#pragma unroll
+    for (int c = 0; c < GATHER_MAX; ++c) part[c] = off[c] >= 0 ? regions[(int64_t)off[c] + o] : A(0);
     A sum = A(0);
 #pragma unroll
-    for (int l = 0; l < 4; ++l)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        A part[4];
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-          const int64_t c = ((int64_t)cx[l] * g.n[1] + cy[m]) * g.n[2] + cz[n];
-          part[n] = occ[c] ? blocks[(c * 64 + 16 * l + 4 * m + n) * o_pad + o] : A(0);
-        }
-#pragma unroll
-        for (int n = 0; n < 4; ++n) sum += part[n];
-      }
+    for (int c = 0; c < GATHER_MAX; ++c) sum += part[c];
     gtab[row * o_pad + o] += sum;
   }
 }
 
-__global__ void k_bwd_zero_i32(int32_t* p, int64_t n) {
+__global__ void k_cell_run_index(const int64_t* uniq, const int32_t* class_start, int64_t n_cells, int32_t n_classes,
+                                 int32_t n_pts, int32_t* cell_run) {
+  const int n_runs = (int)min((int64_t)min(max(class_start[n_classes], 0), n_pts), n_cells);
+  const int r = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (r >= n_runs) return;
+  const int64_t cell = uniq[r] % n_cells;
+  if (cell >= 0) cell_run[cell] = r;
+}
+
+__global__ void k_bwd_fill_i32(int32_t* p, int64_t n, int32_t value) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0;
+  if (i < n) p[i] = value;
 }
 
 typedef void (*CellKernel)(CellArgs);
+
+// brick regions: FP32 two orbital tiles per wave, FP64 one (64 KB of LDS for a workgroup's region either way)
+template <typename A, int NT>
+static CellKernel pick_bricks() {
+  if constexpr (sizeof(A) == 4) return k_bwd_bricks<A, 2, NT>;
+  else return k_bwd_bricks<A, 1, NT>;
+}
+template <typename A>
+static int brick_ot() {
+  return sizeof(A) == 4 ? 2 : 1;
+}
 
 template <typename A, int NT>
 static CellKernel pick_cells_nt(int ot) {
@@ -587,12 +734,12 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
   const Geom g = make_geom(d);
 
   // orbital tiles per wave: enough waves per class launch to cover the chip, at most 4 (FP32) or
-  // 2 (FP64) tiles of accumulators per wave
+  // 2 (FP64) tiles of accumulators per wave; the dense (brick) form has its own
   const int tiles = (d->n_orb + 15) / 16;
   const int64_t occupied = std::min<int64_t>(n_pts, L.n_cells) / L.n_classes;
-  // (the dense form launches every cell at once, so only the orbital count limits the tiles)
   int ot = d->dtype == SPL_F64 ? 2 : 4;
-  while (ot > 1 && (ot >= 2 * tiles || (!L.dense && occupied * ((tiles + ot - 1) / ot) < 2048))) ot >>= 1;
+  while (ot > 1 && (ot >= 2 * tiles || occupied * ((tiles + ot - 1) / ot) < 2048)) ot >>= 1;
+  if (L.dense) ot = d->dtype == SPL_F64 ? brick_ot<double>() : brick_ot<float>();
   CellArgs a;
   memset(&a, 0, sizeof(a));
   a.g = g;
@@ -608,13 +755,18 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
   a.n_classes = L.n_classes;
   a.n_pts = (int32_t)n_pts;
   a.o_pad = d->o_pad;
-  a.dense = L.dense;
   if (L.dense) {
+    // each cell's run (-1: empty), from the sort
+    int32_t* cell_run = reinterpret_cast<int32_t*>(W + L.cell_run);
     a.blocks = W + L.blocks;
-    a.occ = reinterpret_cast<int32_t*>(W + L.occ);
-    hipLaunchKernelGGL(k_bwd_zero_i32, dim3((unsigned)((L.n_cells + 255) / 256)), dim3(256), 0, stream, a.occ,
-                       L.n_cells);
-    if ((rc = hip_fail(hipGetLastError(), "occupancy clear launch"))) return rc;
+    a.cell_run = cell_run;
+    hipLaunchKernelGGL(k_bwd_fill_i32, dim3((unsigned)((L.n_cells + 255) / 256)), dim3(256), 0, stream, cell_run,
+                       L.n_cells, -1);
+    if ((rc = hip_fail(hipGetLastError(), "cell run clear launch"))) return rc;
+    const int max_runs = (int)std::min<int64_t>(n_pts, L.n_cells);
+    hipLaunchKernelGGL(k_cell_run_index, dim3((unsigned)((max_runs + 255) / 256)), dim3(256), 0, stream, uniq,
+                       class_start, L.n_cells, (int32_t)L.n_classes, (int32_t)n_pts, cell_run);
+    if ((rc = hip_fail(hipGetLastError(), "cell run index launch"))) return rc;
   }
   const int64_t no = d->n_orb;
   const size_t gsz = d->dtype == SPL_F64 ? 8 : 4;
@@ -644,25 +796,26 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
     if (nt == 0) continue;
     a.n_terms = nt;
     a.gtable = static_cast<char*>(gtable) + (pass == 1 ? d->table_elems * gsz : 0);
-    const CellKernel k = d->dtype == SPL_F64 ? pick_cells<double>(ot, nt) : pick_cells<float>(ot, nt);
     if (L.dense) {
-      // every occupied cell at once into its own block, then one gather per table row
-      const int64_t waves = L.n_cells * a.n_groups;
-      const int grid = (int)std::min<int64_t>(waves, 1 << 16);
-      hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, stream, a);
-      if ((rc = hip_fail(hipGetLastError(), "cell block launch"))) return rc;
+      // every brick at once into its region, then one gather per table row
+      const CellKernel kb = d->dtype == SPL_F64 ? (nt <= 2 ? pick_bricks<double, 2>() : pick_bricks<double, 5>())
+                                                : (nt <= 2 ? pick_bricks<float, 2>() : pick_bricks<float, 5>());
+      const int64_t n_bricks = (int64_t)((d->grid[0] + 1) / 2) * ((d->grid[1] + 1) / 2) * ((d->grid[2] + 1) / 2);
+      const int64_t n_wg = (a.n_groups + BRICK_WAVES - 1) / BRICK_WAVES;
+      const int grid = (int)std::min<int64_t>(n_bricks * n_wg, 1 << 16);
+      hipLaunchKernelGGL(kb, dim3(grid), dim3(64 * BRICK_WAVES), 0, stream, a);
+      if ((rc = hip_fail(hipGetLastError(), "brick region launch"))) return rc;
       const int gthreads = d->o_pad >= 256 ? 256 : (d->o_pad + 63) / 64 * 64;
       if (d->dtype == SPL_F64)
-        hipLaunchKernelGGL(k_bwd_gather<double>, dim3((unsigned)L.n_cells), dim3(gthreads), 0, stream, g,
-                           static_cast<const double*>(a.blocks), a.occ, d->n_orb, d->o_pad,
-                           static_cast<double*>(a.gtable));
+        hipLaunchKernelGGL(k_bwd_brick_gather<double>, dim3((unsigned)L.n_cells), dim3(gthreads), 0, stream, g,
+                           static_cast<const double*>(a.blocks), d->n_orb, d->o_pad, static_cast<double*>(a.gtable));
       else
-        hipLaunchKernelGGL(k_bwd_gather<float>, dim3((unsigned)L.n_cells), dim3(gthreads), 0, stream, g,
-                           static_cast<const float*>(a.blocks), a.occ, d->n_orb, d->o_pad,
-                           static_cast<float*>(a.gtable));
+        hipLaunchKernelGGL(k_bwd_brick_gather<float>, dim3((unsigned)L.n_cells), dim3(gthreads), 0, stream, g,
+                           static_cast<const float*>(a.blocks), d->n_orb, d->o_pad, static_cast<float*>(a.gtable));
       if ((rc = hip_fail(hipGetLastError(), "row gather launch"))) return rc;
       continue;
     }
+    const CellKernel k = d->dtype == SPL_F64 ? pick_cells<double>(ot, nt) : pick_cells<float>(ot, nt);
     const int64_t waves = occupied * a.n_groups;
     const int grid = (int)std::max<int64_t>(256, std::min<int64_t>(waves, 8192));
     for (int c = 0; c < L.n_classes; ++c) {

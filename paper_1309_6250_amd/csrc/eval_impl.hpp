@@ -52,6 +52,7 @@ struct EvalArgs {
   double k[3];        // crystal momentum of Bloch orbitals (Bloch variants only)
   const int32_t* perm;  // locality order of the points (sorted evaluation), or null: point q is perm[q]
   int32_t per_xcd;      // with perm: tiles per XCD (workgroup b takes tile (b mod 8) * per_xcd + b / 8)
+  int32_t lanes;        // batched launches with per-item shapes: lanes per point of this item (8 .. 256)
 };
 
 enum { MODE_V = 0, MODE_VGL = 1, MODE_VGL_SEPLAP = 2, MODE_SEP = 3 };
@@ -500,28 +501,67 @@ struct BatchArgs {
   int32_t n_tiles;
 };
 
+// One tile of a batched launch: 256 / G points of item `a`, G lanes per point; rel is the tile's
+// index within the item.
+template <typename TS, int MODE, int G, int OPL>
+__device__ __forceinline__ void batch_tile(const EvalArgs& a, int rel) {
+  int p = rel * (256 / G) + (int)threadIdx.x / G;
+  if (p < a.n_pts) {
+    if (a.perm) p = a.perm[p];                         // the item's points in locality order
+    if constexpr (G >= 64) p = __builtin_amdgcn_readfirstlane(p);
+    eval_point<TS, MODE, G, OPL, 0>(a, p, (int)threadIdx.x % G);
+  }
+}
+
+// The next tile of a persistent launch and its item (the last item whose first tile <= tile), or
+// tile >= n_tiles when the work is done.  Uniform over the workgroup.
+__device__ __forceinline__ int batch_next(const BatchArgs& b, int32_t* s_tile, int* item) {
+  if (threadIdx.x == 0) *s_tile = atomicAdd(b.counter, 1);
+  __syncthreads();
+  const int tile = __builtin_amdgcn_readfirstlane(*s_tile);
+  __syncthreads();                                   // s_tile is rewritten next iteration
+  int lo = 0, hi = b.n_items - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (b.tile_start[mid] <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  *item = lo;
+  return tile;
+}
+
 template <typename TS, int MODE, int G, int OPL>
 __global__ __launch_bounds__(256) void k_eval_batch(BatchArgs b) {
-  constexpr int GPB = 256 / G;
   __shared__ int32_t s_tile;
   for (;;) {
-    if (threadIdx.x == 0) s_tile = atomicAdd(b.counter, 1);
-    __syncthreads();
-    const int tile = __builtin_amdgcn_readfirstlane(s_tile);
-    __syncthreads();                                   // s_tile is rewritten next iteration
+    int lo;
+    const int tile = batch_next(b, &s_tile, &lo);
     if (tile >= b.n_tiles) break;                      // uniform: the whole workgroup leaves
-    int lo = 0, hi = b.n_items - 1;                    // last item whose first tile <= tile
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (b.tile_start[mid] <= tile) lo = mid;
-      else hi = mid - 1;
-    }
+    batch_tile<TS, MODE, G, OPL>(b.items[lo], tile - b.tile_start[lo]);
+  }
+}
+
+// The same persistent launch with every item's own lanes per point (EvalArgs::lanes) and a common
+// OPL: items with few orbitals take short lane groups and more points per tile.  Every shape runs
+// the same per-point arithmetic, so each item's outputs equal the single-system kernel's at its
+// shape, bit for bit.
+template <typename TS, int MODE, int OPL>
+__global__ __launch_bounds__(256) void k_eval_batch_multi(BatchArgs b) {
+  __shared__ int32_t s_tile;
+  for (;;) {
+    int lo;
+    const int tile = batch_next(b, &s_tile, &lo);
+    if (tile >= b.n_tiles) break;
     const EvalArgs& a = b.items[lo];
-    int p = (tile - b.tile_start[lo]) * GPB + (int)threadIdx.x / G;
-    if (p < a.n_pts) {
-      if (a.perm) p = a.perm[p];                       // the item's points in locality order
-      if constexpr (G >= 64) p = __builtin_amdgcn_readfirstlane(p);
-      eval_point<TS, MODE, G, OPL, 0>(a, p, (int)threadIdx.x % G);
+    const int rel = tile - b.tile_start[lo];
+    switch (__builtin_amdgcn_readfirstlane(a.lanes)) {
+      case 8: batch_tile<TS, MODE, 8, OPL>(a, rel); break;
+      case 16: batch_tile<TS, MODE, 16, OPL>(a, rel); break;
+      case 32: batch_tile<TS, MODE, 32, OPL>(a, rel); break;
+      case 64: batch_tile<TS, MODE, 64, OPL>(a, rel); break;
+      case 128: batch_tile<TS, MODE, 128, OPL>(a, rel); break;
+      case 256: batch_tile<TS, MODE, 256, OPL>(a, rel); break;
+      default: break;                                  // not reachable: the plan validates every shape
     }
   }
 }
@@ -529,9 +569,11 @@ __global__ __launch_bounds__(256) void k_eval_batch(BatchArgs b) {
 typedef void (*EvalKernel)(EvalArgs);
 typedef void (*BatchKernel)(BatchArgs);
 
+// g = 0: per-item lanes per point (k_eval_batch_multi)
 template <typename TS, int MODE, int OPL>
 inline BatchKernel pick_batch_g(int g) {
   switch (g) {
+    case 0: return k_eval_batch_multi<TS, MODE, OPL>;
     case 8: return k_eval_batch<TS, MODE, 8, OPL>;
     case 16: return k_eval_batch<TS, MODE, 16, OPL>;
     case 32: return k_eval_batch<TS, MODE, 32, OPL>;

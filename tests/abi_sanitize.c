@@ -204,6 +204,8 @@ int main(void) {
   item.v = item.grad = item.lap = fake;
   expect(spline_batch_plan_create(&item, 1, NULL, NULL, &plan), SPL_EUNSUPPORTED, "plan pp item");
   expect(spline_batch_plan_sort(NULL, 1, NULL), SPL_EINVAL, "plan sort NULL");
+  expect(spline_batch_plan_get_tiles(NULL, tile), SPL_EINVAL, "plan get tiles NULL");
+  expect(spline_batch_plan_set_tiles(NULL, tile, NULL), SPL_EINVAL, "plan set tiles NULL");
 
   /* the sorted evaluation without allocation: rejected arguments, and no points (a no-op) */
   expect(spline_eval_vgl_sorted_noalloc(NULL, fake, 4, fpos, fake, fake, fake, NULL, NULL), SPL_EINVAL,

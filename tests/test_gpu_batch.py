@@ -218,3 +218,48 @@ def test_sorted_batch_graph_replays_match_eager():
                 assert torch.equal(a, b)
         _ = torch.ones(1000, device=DEV).sum().item()
     plan.close()
+
+
+@pytest.mark.parametrize("dtype,has_lap", [("f64", False), ("f32", False), ("bf16", False), ("f32", True)])
+def test_per_item_tiles_equal_single_system_kernel(dtype, has_lap):
+    """Items with their own lanes per point in one persistent launch (eager and graph replay, in the
+    given order and in locality order): each item's outputs equal the single-system kernel's at that
+    item's shape, bit for bit.  Also after the autotuner picks the shapes."""
+    items, _ = make_items(dtype, has_lap, seed=205)
+    opl = {"f64": 2, "f32": 4, "bf16": 4}[dtype]
+    lanes = [8, 16, 32, 64, 128, 256, 8]
+    shapes = [(g, opl) for g in lanes]
+    plan = P.BatchPlan(items)
+    plan.set_tiles(shapes)
+    assert plan.tiles() == shapes
+    ref = [None if pos.shape[0] == 0 else [x.clone() for x in P.spline_eval_vgl(d, tab, pos, tile=t)]
+           for (d, tab, pos, *_), t in zip(items, shapes)]
+    torch.cuda.synchronize()
+    for how in ("eager", "graph", "sorted graph"):
+        for (_, _, _, v, g, l) in items:
+            v.fill_(np.nan), g.fill_(np.nan), l.fill_(np.nan)
+        say("per-item tiles", dtype, has_lap, how)
+        if how == "sorted graph":
+            plan.sort(True)
+        if how == "eager":
+            plan.run()
+        else:
+            plan.run_graph()
+        torch.cuda.synchronize()
+        assert plan.tiles() == shapes
+        assert_same(items, ref)
+    say("batch autotune with per-item shapes", dtype, has_lap)
+    plan.autotune()
+    chosen = plan.tiles()
+    assert len({t[1] for t in chosen}) == 1
+    for (_, _, _, v, g, l) in items:
+        v.fill_(np.nan), g.fill_(np.nan), l.fill_(np.nan)
+    plan.run_graph()
+    torch.cuda.synchronize()
+    assert_same(items, [None if pos.shape[0] == 0 else [x.clone() for x in P.spline_eval_vgl(d, tab, pos, tile=t)]
+                        for (d, tab, pos, *_), t in zip(items, chosen)])
+    with pytest.raises(P.SplineError):
+        plan.set_tiles([(8, opl)] * (len(items) - 1) + [(8, 1 if opl != 1 else 2)])      # mixed orbitals per lane
+    with pytest.raises(P.SplineError):
+        plan.set_tiles([(4, opl)] * len(items))                                         # fewer than 8 lanes
+    plan.close()

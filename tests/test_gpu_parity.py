@@ -395,9 +395,11 @@ def test_backward_deterministic_many_points_per_cell():
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_backward_deterministic_dense_path(dtype):
-    """At 4 or more points per cell the deterministic adjoint writes every cell's 64-row block to the
-    workspace and gathers them per table row (no colour classes): oracle parity with the separate
-    Laplacian table and every upstream term, an odd orbital count, ragged grid, repeatable bit for bit."""
+    """At 4 or more points per cell the deterministic adjoint sums the cell blocks of every brick of
+    2 x 2 x 2 cells into a 5 x 5 x 5-row region in the workspace and gathers the regions per table row
+    (no colour classes): oracle parity with the separate Laplacian table and every upstream term, an
+    odd orbital count, a ragged grid (odd cell counts leave partial bricks; 5 cells wrap a region onto
+    itself), repeatable bit for bit."""
     rng = np.random.default_rng(107)
     grid, n_orb, n = (6, 5, 7), 37, 2000
     beta = rng.standard_normal(grid + (n_orb,))
@@ -411,7 +413,8 @@ def test_backward_deterministic_dense_path(dtype):
     od = torch.float64 if dtype == "f64" else torch.float32
     args = (to_dev(gv, od), to_dev(gg, od), to_dev(gl, od))
     nb = P.spline_backward_work_bytes(d, n, P.SPL_DETERMINISTIC)
-    assert nb >= grid[0] * grid[1] * grid[2] * 64 * d.o_pad * (8 if dtype == "f64" else 4)   # the block workspace
+    n_bricks = np.prod([(k + 1) // 2 for k in grid])
+    assert nb >= n_bricks * 125 * d.o_pad * (8 if dtype == "f64" else 4)   # the region workspace
     say("deterministic backward, dense path", dtype)
     runs = []
     for _ in range(2):

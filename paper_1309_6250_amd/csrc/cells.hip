@@ -528,32 +528,28 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) void k_bwd_bricks(CellArgs a) {
   }
 }
 
-// Bricks (b, l) whose region row l (0 .. 4) lands on table row X of an axis of n rows with nb bricks:
-// region row l of brick b is row 2 b - 1 + l, taken modulo n.  Listed in a fixed order (images of X
-// from below, bricks ascending); at most 8.
-__device__ __forceinline__ int brick_rows_of(int X, int n, int nb, int bl[8], int ll[8]) {
+// The region rows that land on table row X along one axis of n rows and nb bricks: region row l
+// (0 .. 4) of brick b is row 2 b - 1 + l, taken modulo n.  Each is returned as its share of the
+// element offset, b * stride_b + l * stride_l, in a fixed order (images of X from below, bricks
+// ascending); at most 3 (a 5-row window moving by 2 covers a row at most 3 times).
+__device__ __forceinline__ int brick_parts(int X, int n, int nb, int32_t stride_b, int32_t stride_l, int32_t part[3]) {
   int k = 0;
   for (int img = -1; img <= 1; ++img) {
     const int xp = X + img * n;                        // the row before the wrap
-    // 2 b - 1 <= xp <= 2 b + 3  <=>  (xp - 3) / 2 <= b <= (xp + 1) / 2
-    const int lo = (xp - 3 >= 0) ? (xp - 3 + 1) / 2 : -((3 - xp) / 2);
-    const int hi = (xp + 1 >= 0) ? (xp + 1) / 2 : -((-(xp + 1) + 1) / 2);
-    for (int b = max(lo, 0); b <= min(hi, nb - 1); ++b) {
-      const int l = xp - (2 * b - 1);
-      if (l >= 0 && l <= 4 && k < 8) {
-        bl[k] = b;
-        ll[k] = l;
-        ++k;
-      }
-    }
+    if (xp < -1 || xp > 2 * nb + 2) continue;
+    // 2 b - 1 <= xp <= 2 b + 3  <=>  ceil((xp - 3) / 2) <= b <= floor((xp + 1) / 2)
+    const int lo = max((xp - 2) >> 1, 0);              // arithmetic shifts: floor division by 2
+    const int hi = min((xp + 1) >> 1, nb - 1);
+    for (int b = lo; b <= hi && k < 3; ++b) part[k++] = b * stride_b + (xp - (2 * b - 1)) * stride_l;
   }
   return k;
 }
 
 // Dense points, second step: table row (X, Y, Z) receives every brick region row that lands on it
 // (at most 3 along each axis), summed in a fixed order and added to the gradient table.  One
-// workgroup per row (so the lookups are uniform), its threads over the orbitals; every region row
-// is loaded before the sum, so the loads are in flight together.
+// workgroup per row (so the lookups are uniform), its threads over the orbitals; the offset of a
+// region row is the sum of its three axis shares, and every region row is loaded before the sum,
+// so the loads are in flight together.
 constexpr int GATHER_MAX = 27;
 
 template <typename A>
@@ -564,29 +560,23 @@ __global__ __launch_bounds__(256) void k_bwd_brick_gather(Geom g, const A* regio
   const int Y = (int)((row / g.n[2]) % g.n[1]);
   const int X = (int)(row / ((int64_t)g.n[2] * g.n[1]));
   const int nbx = (g.n[0] + 1) >> 1, nby = (g.n[1] + 1) >> 1, nbz = (g.n[2] + 1) >> 1;
-  int bx[8], lx[8], by[8], ly[8], bz[8], lz[8];
-  const int kx = min(brick_rows_of(X, g.n[0], nbx, bx, lx), 3);
-  const int ky = min(brick_rows_of(Y, g.n[1], nby, by, ly), 3);
-  const int kz = min(brick_rows_of(Z, g.n[2], nbz, bz, lz), 3);
-  int32_t off[GATHER_MAX];           // first element of each region row (< 2^31: regions are capped at 4 GiB)
-  int cnt = 0;
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const bool live = i < kx && j < ky && k < kz;
-        const int64_t brick = live ? ((int64_t)bx[i] * nby + by[j]) * nbz + bz[k] : 0;
-        const int lrow = live ? (lx[i] * 5 + ly[j]) * 5 + lz[k] : 0;
-        off[9 * i + 3 * j + k] = live ? (int32_t)((brick * BRICK_ROWS + lrow) * o_pad) : -1;
-        cnt += live;
-      }
-  (void)cnt;
+  // element offsets fit in 32 bits: the regions are capped at 4 GiB
+  const int32_t sz = BRICK_ROWS * o_pad, sy = nbz * sz, sx = nby * sy;
+  int32_t px[3], py[3], pz[3];
+  const int kx = brick_parts(X, g.n[0], nbx, sx, 25 * o_pad, px);
+  const int ky = brick_parts(Y, g.n[1], nby, sy, 5 * o_pad, py);
+  const int kz = brick_parts(Z, g.n[2], nbz, sz, o_pad, pz);
   for (int o = threadIdx.x; o < n_orb; o += blockDim.x) {
     A part[GATHER_MAX];
 #pragma unroll
-    for (int c = 0; c < GATHER_MAX; ++c) part[c] = off[c] >= 0 ? regions[(int64_t)off[c] + o] : A(0);
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const bool live = i < kx && j < ky && k < kz;
+          part[9 * i + 3 * j + k] = live ? regions[(int64_t)(px[i] + py[j] + pz[k]) + o] : A(0);
+        }
     A sum = A(0);
 #pragma unroll
     for (int c = 0; c < GATHER_MAX; ++c) sum += part[c];

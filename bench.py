@@ -331,7 +331,7 @@ def parity_sample(n_pts, n_sample=1024):
     return np.sort(np.random.default_rng(1309).choice(n_pts, size=n_sample, replace=False))
 
 
-def cpu_baseline(wl, n_sample=16384, max_workers=16):
+def cpu_baseline(wl, n_sample=32768, max_workers=16):
     """The FP64 oracle (eval_vgl on the oracle's own interpolating table) on the host cores, over a
     seeded sample of the workload's points (its first n_sample points: the positions are already
     uniform random) and all its orbitals, split across forked worker processes.  Also returns the
@@ -489,7 +489,7 @@ def planewave_targets_gpu(system, pos, chunk=16384):
     return v, lap
 
 
-def fit_rows(steps, warmup, adam_steps=200):
+def fit_rows(steps, warmup, adam_steps=200, cg_iters=400):
     """Differentiation form on the fit workload (128 orbitals, 32^3 FP32 table, 10^6 points): the
     adjoint in both summation modes, the fit's terms, 200 Adam steps of the least-squares fit from the
     interpolating spline, and the fit's exact optimum (conjugate gradients on the same loss, FP64
@@ -569,7 +569,7 @@ def fit_rows(steps, warmup, adam_steps=200):
     d64 = P.spline_desc_init(s.lattice, s.grid, s.n_orb, "f64")
     t64 = P.spline_build(d64, torch.from_numpy(s.grid_values()).cuda())
     t0 = time.time()
-    opt64, loss_opt, cg_iters, cg_res = fit_optimum_cg(d64, t64, pos, v_t, lap_t, lam=1e-3, iters=400, rtol=1e-8)
+    opt64, loss_opt, cg_done, cg_res = fit_optimum_cg(d64, t64, pos, v_t, lap_t, lam=1e-3, iters=cg_iters, rtol=1e-8)
     torch.cuda.synchronize()
     cg_s = time.time() - t0
     # held-out points: error of the interpolating start and of the fitted table against the planewaves
@@ -585,7 +585,7 @@ def fit_rows(steps, warmup, adam_steps=200):
                                      "gap_closed": (losses[0] - losses[-1]) / (losses[0] - loss_opt),
                                      "lr": lr, "lr_over_rms_table": FIT_LR, "schedule": FIT_SCHEDULE,
                                      "optimum": {"method": "conjugate gradients on the same loss, FP64 table",
-                                                 "iterations": cg_iters, "relative_residual": cg_res, "s": cg_s},
+                                                 "iterations": cg_done, "relative_residual": cg_res, "s": cg_s},
                                      "lambda": 1e-3, "deterministic_gradient": True, "heldout": res,
                                      "note": "per step: spline_fit_terms_cells (cell-wise forward with the misfit "
                                              "of V and lap), deterministic adjoint and smoothness penalty on the "
@@ -702,6 +702,7 @@ def batched_row(steps, warmup):
     log(f"batched workload: {len(items)} systems ready in {time.time() - t0:.1f} s")
     plan = P.BatchPlan(items)
     tile = plan.autotune()
+    item_tiles = plan.tiles()
     n_tiles, n_evals = plan.info()
     ms = time_launches(plan.run_graph, steps, warmup)
     ms_eager = time_launches(plan.run, steps, warmup)
@@ -711,7 +712,11 @@ def batched_row(steps, warmup):
     tile_s = plan.autotune()
     ms_sorted = time_launches(plan.run_graph, steps, warmup)
     plan.close()
+    lanes = sorted({t[0] for t in item_tiles})
     return {"systems": len(items), "evals_per_launch": n_evals, "tiles": n_tiles, "tile": list(tile),
+            "per_item_lanes": lanes if tile[0] == 0 else None,
+            "shapes": "one shape for all items" if tile[0] != 0 else
+                      f"per-item lanes per point {lanes}, {tile[1]} orbitals per lane",
             "ms_graph": ms, "ms_eager": ms_eager, "evals_per_s": n_evals / (ms * 1e-3),
             "alg_GBps": alg / (ms * 1e-3) / 1e9,
             "effective_frac_hbm_peak": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -751,11 +756,14 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline only: no extra forms, rows or CPU baseline")
     ap.add_argument("--only", default=None,
                     help="time only one form, e.g. c2-f32, c2-bf16-lap, c2-f32-sep-lagrange, c2-f64-pp, "
-                         "c7-f64-bloch or c8-f32, or 'fit' for the differentiation rows (for profiling runs)")
+                         "c7-f64-bloch or c8-f32, 'fit' for the differentiation rows or 'c1-adjoint' for the "
+                         "adjoint at QMC density (for profiling runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tile", default=None, help="with --only: fixed tile 'G,OPL' instead of autotuning")
     ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
                     help="where the full record (every form and row) is written")
+    ap.add_argument("--fit-steps", type=int, default=200, help="Adam steps of the fit row")
+    ap.add_argument("--cg-iters", type=int, default=400, help="conjugate-gradient iterations of the fit's optimum")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (scales memory counters)")
     args = ap.parse_args()
@@ -779,7 +787,17 @@ def main():
     if args.only == "fit":
         # differentiation form only (for profiling runs): adjoint in both modes, misfit, Adam fit
         _gpu_ready()
-        print(json.dumps({"only": "fit", **fit_rows(args.steps, args.warmup)}), flush=True)
+        print(json.dumps({"only": "fit", **fit_rows(args.steps, args.warmup, args.fit_steps, args.cg_iters)}),
+              flush=True)
+        return
+
+    if args.only == "c1-adjoint":
+        # the adjoint at QMC density only (for profiling runs): the Si-like cell's 65 536 points,
+        # atomic and deterministic forms, together with the other rows of that cell
+        wl1 = Workload(1)
+        _gpu_ready()
+        wl1.upload()
+        print(json.dumps({"only": "c1-adjoint", **rows_measurements(wl1, args.steps, args.warmup)}), flush=True)
         return
 
     if args.only and args.only.endswith("-sorted"):

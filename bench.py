@@ -194,8 +194,8 @@ OPLS = {"f64": (1, 2), "f32": (1, 2, 4), "bf16": (2, 4, 8)}
 
 
 def sorted_form(wl, d, table, outs, dtype, steps, warmup, tile=None):
-    """The same evaluation through spline_eval_vgl_sorted: Morton cell keys, radix sort and the
-    permuted kernel, all inside every timed call.  The tile is the fastest of a sweep (three timed
+    """The same evaluation through spline_eval_vgl_sorted: a counting sort of the points into Morton
+    buckets of cells and the permuted kernel, all inside every timed call.  The tile is the fastest of a sweep (three timed
     calls each).  alg_GBps counts each point's 64 rows as if read from memory, as for the other
     forms; rows reused from L2 or the Infinity Cache can take it past the HBM peak."""
     import torch
@@ -359,8 +359,8 @@ def cpu_baseline(wl, n_sample=32768, max_workers=16):
     _CPU_BETA = None
     return ({"value": evals / wall, "unit": "orbital-VGL evals/s", "cores": workers, "kind": "oracle",
              "sample": f"first {n} of the {wl.pos_host.shape[0]} points x all {wl.s.n_orb} orbitals of {wl.s.name} "
-                       f"(FP64 table), {workers} processes, {wall:.1f} s wall; oracle build {build_s:.0f} s not "
-                       "included",
+                       f"(FP64 table), {workers} processes, {wall:.1f} s wall ({workers * wall:.0f} core-s); oracle build "
+                       f"{build_s:.0f} s not included",
              "wall_s": wall}, (idx, ref))
 
 
@@ -867,6 +867,9 @@ def main():
                 "kernel_hash": kernel_hash()}
     flops = FLOPS_PER_EVAL * n_pts * wl2.s.n_orb
     roofline["valu_frac_fp64"] = flops / (head["ms_per_sweep"] * 1e-3) / 1e12 / 78.6
+    if not args.quick:
+        forms["c2-f64-sorted"] = sorted_form(wl2, d2, t2, o2, "f64", args.steps, args.warmup)
+        log(f"c2-f64-sorted: {forms['c2-f64-sorted']['evals_per_s']:.3e} evals/s (effective)")
     del t2, o2
     torch.cuda.empty_cache()
 

@@ -46,7 +46,7 @@ __host__ __device__ inline int axis_colour(int i, int n) {
 __host__ __device__ inline int axis_colours(int n) { return 4 + (n & 3); }
 
 struct SortLayout {
-  size_t keys_in, keys_out, vals_in, vals_out, uniq, counts, offsets, num_runs, class_start, pts, cell_run, blocks,
+  size_t keys_in, keys_out, vals_in, vals_out, uniq, counts, offsets, num_runs, class_start, pts, cell_range, blocks,
       partials, temp;
   size_t temp_bytes, total;
   int n_classes;
@@ -107,12 +107,12 @@ static int sort_layout(const spl_desc* d, int64_t n_pts, SortLayout* L, bool adj
   L->class_start = off; off = align_up(off + 4 * (size_t)(L->n_classes + 2));
   L->pts = off; off = align_up(off + (d->dtype == SPL_F64 ? 32 : 16) * n);
   // dense points (at least 4 per cell on average): the 5 x 5 x 5-row region of every brick of 2 x 2 x 2
-  // cells gets its own place, and every cell the index of its run
+  // cells gets its own place, and every cell its sorted point range
   const size_t gsz = d->dtype == SPL_F64 ? 8 : 4;
   const size_t n_bricks = (size_t)((d->grid[0] + 1) / 2) * ((d->grid[1] + 1) / 2) * ((d->grid[2] + 1) / 2);
   const size_t block_bytes = n_bricks * 125 * (size_t)d->o_pad * gsz;
   L->dense = adjoint_blocks && n_pts >= 4 * L->n_cells && block_bytes <= ((size_t)4 << 30);
-  L->cell_run = off; off = align_up(off + (L->dense ? 4 * (size_t)L->n_cells : 0));
+  L->cell_range = off; off = align_up(off + (L->dense ? 8 * (size_t)L->n_cells : 0));
   L->blocks = off; off = align_up(off + (L->dense ? block_bytes : 0));
   // forward only: one FP64 partial sum per work item of the fit terms, at most min(n, cells) runs
   // times the 16-orbital tiles, then one per workgroup of the first summing step (FIT_SUM_BLOCKS)
@@ -203,8 +203,10 @@ struct CellArgs {
   int32_t n_classes;
   int32_t n_pts;           // every index read from the sort is checked against this and n_cells
   int32_t o_pad;
-  void* blocks;            // dense: [n_bricks][125][o_pad] gradient regions of the bricks of 2 x 2 x 2 cells
-  const int32_t* cell_run; // dense: [n_cells] run of each cell's points, -1 for an empty cell
+  void* blocks;              // dense: [n_bricks][125][o_pad] gradient regions of the bricks of 2 x 2 x 2 cells
+  const int32_t* cell_range; // dense: [n_cells][2] first sorted point and count of each cell (0 if empty)
+  int32_t src_bytes[5];      // dense: bytes of each term's upstream array from src[c] to its last value, or
+                             // -1 when one reaches 2 GiB (then the brick kernel uses 64-bit addresses)
 };
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -229,6 +231,28 @@ template <> struct Mfma<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
 };
+
+// Row-weight factors of one term on a lane's (m, n) pair of block offsets: the weight of block row
+// (l, m, n) is Q0 w_x[l] + Q1 w_x'[l] + Q2 w_x''[l], from the point's 1-D weights on the second and
+// third axes (the transpose of the term's row of the forward contraction with the chain rule).
+template <typename A>
+__device__ __forceinline__ void term_factors(int kind, A wy, A dwy, A d2wy, A wz, A dwz, A d2wz, const A (&jm)[9],
+                                             const A (&mt)[6], A& q0, A& q1, A& q2) {
+  const A yz = wy * wz;
+  q1 = A(0);
+  q2 = A(0);
+  if (kind == TERM_VAL) {
+    q0 = yz;
+  } else if (kind == TERM_LAP) {
+    q2 = mt[0] * yz;
+    q1 = A(2) * fmaa(mt[3] * dwy, wz, mt[4] * wy * dwz);
+    q0 = fmaa(mt[1] * d2wy, wz, fmaa(mt[2] * wy, d2wz, A(2) * mt[5] * dwy * dwz));
+  } else {
+    const int k = kind - TERM_GX;
+    q1 = jm[k] * yz;
+    q0 = fmaa(jm[3 + k] * dwy, wz, jm[6 + k] * wy * dwz);
+  }
+}
 
 // One wave per (occupied cell of the colour class, group of 16 OT orbitals).  For a cell the
 // gradient of its 64 rows is a dense product
@@ -314,24 +338,12 @@ __device__ __forceinline__ void cell_block(const CellArgs& a, int start, int cnt
       }
       const A wy = wp[12 + m_], dwy = wp[16 + m_], d2wy = wp[20 + m_];
       const A wz = wp[24 + n_], dwz = wp[28 + n_], d2wz = wp[32 + n_];
-      const A yz = wy * wz;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         if (c >= nt) break;
         // row weight of this term: Q0 w_x + Q1 w_x' + Q2 w_x'' on the lane's (m, n), per row tile l
-        const int kind = a.kind[c];
-        A q0, q1 = A(0), q2 = A(0);
-        if (kind == TERM_VAL) {
-          q0 = yz;
-        } else if (kind == TERM_LAP) {
-          q2 = mt[0] * yz;
-          q1 = A(2) * fmaa(mt[3] * dwy, wz, mt[4] * wy * dwz);
-          q0 = fmaa(mt[1] * d2wy, wz, fmaa(mt[2] * wy, d2wz, A(2) * mt[5] * dwy * dwz));
-        } else {
-          const int k = kind - TERM_GX;
-          q1 = jm[k] * yz;
-          q0 = fmaa(jm[3 + k] * dwy, wz, jm[6 + k] * wy * dwz);
-        }
+        A q0, q1, q2;
+        term_factors<A>(a.kind[c], wy, dwy, d2wy, wz, dwz, d2wz, jm, mt, q0, q1, q2);
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
           const A av = fmaa(q2, d2wx[rt], fmaa(q1, dwx[rt], q0 * wx[rt]));
@@ -448,35 +460,83 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 // Dense points (4 or more per cell): the cells are taken in bricks of 2 x 2 x 2 (the last brick of
 // an axis with an odd count holds one cell along it).  The blocks of a brick's cells cover a
 // region of 5 x 5 x 5 table rows (rows 2 b - 1 .. 2 b + 3 along each axis, before the periodic
-// wrap).  One workgroup of BRICK_WAVES waves per (brick, group of BRICK_WAVES x 16 OT orbitals):
-// the first wave stages each batch of points (indices and 1-D weights) for all, and each wave forms
-// every cell's block for its own 16 OT orbitals (cell_block, cells in a fixed order) and adds it
-// into its columns of the region, held in LDS; the region then goes to the workspace once.  A
-// second kernel gathers, for every table row, the regions of the bricks that cover it.  So each
-// table row crosses memory about 2^3 to 3^3 times instead of 64 times (once per cell block
-// containing it), and the order of every sum stays fixed.
+// wrap).  One workgroup of BRICK_WAVES waves per (brick, group of BRICK_WAVES x 16 OT orbitals)
+// forms every cell's block (each wave for its own 16 OT orbitals) and adds it into its columns of
+// the region, held in LDS; the region then goes to the workspace once.  A second kernel gathers,
+// for every table row, the regions of the bricks that cover it.  So each table row crosses memory
+// about 2^3 to 3^3 times instead of 64 times (once per cell block containing it), and the order of
+// every sum stays fixed.
+//
+// The brick's points are taken in batches of at most CELL_PB (the cells in a fixed order, each
+// cell's points in sorted order), and the memory accesses of later batches overlap the matrix-core
+// work of the current one: the cells' point ranges come in one load per brick; the first 3 CELL_PB
+// threads (one per point and axis) hold the sorted-point records of the next two batches in
+// registers, loaded while the batch before is multiplied, and stage each batch's indices and 1-D
+// weights in LDS; and (with at most two terms) every wave loads the next batch's upstream values
+// before it multiplies the current one.  Each batch is multiplied exactly as in cell_block, so the
+// sums are the same.
 constexpr int BRICK_ROWS = 125;
 constexpr int BRICK_WAVES = 4;
 
-template <typename A, int OT, int NT>
+// A 4- or 8-byte load through a raw buffer resource (a byte offset past the resource's size reads 0).
+template <typename A> struct BufLoad;
+template <> struct BufLoad<float> {
+  __device__ __forceinline__ static float load(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+  }
+};
+template <> struct BufLoad<double> {
+  __device__ __forceinline__ static double load(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+  }
+};
+
+// The term set of the fit (value and Laplacian upstream gradients, in that order) takes its row
+// weights without a choice at run time; any other set reads each term's kind from CellArgs.
+enum { TSET_ANY = 0, TSET_VL = 1 };
+
+// Position in a brick's sequence of batches: cell c (0..7; 8 once the sequence is exhausted) and the
+// batch's first point b0 within that cell.
+struct BrickBatch {
+  int c, b0;
+};
+
+template <typename A, int OT, int NT, int TSET, bool BUF, bool PAIR>
 __global__ __launch_bounds__(64 * BRICK_WAVES) void k_bwd_bricks(CellArgs a) {
   using M = Mfma<A>;
   using Acc = typename M::acc;
   constexpr int BW = 16 * OT;                          // orbitals of a wave
   constexpr int WBW = BRICK_WAVES * BW;                // orbitals of a workgroup
-  __shared__ int s_p[CELL_PB];
-  __shared__ A s_w[CELL_PB][36];
+  constexpr int NQ = CELL_PB / 4;                      // steps of four points in a full batch
+  constexpr int NB = NT <= 2 ? NT : 5;                 // upstream values per point and orbital tile
+  constexpr bool AHEAD = NT <= 2;                      // next batch's upstream values loaded ahead
+  constexpr int NBUF = AHEAD ? 2 : 1;                  // batch buffers of upstream values
+  constexpr int NQB = AHEAD ? NQ : 1;                  // (more than two terms: none, only one step's)
+  // FP32 with the upstream values loaded ahead: the weights of two batches in LDS, so the next
+  // batch is staged while the current one is multiplied, with one barrier per batch (an FP64
+  // workgroup has no room for the second buffer: two workgroups per CU need under 80 KB each)
+  constexpr int NW = (AHEAD && sizeof(A) == 4) ? 2 : 1;
+  static_assert(TSET == TSET_ANY || NT == 2, "the value-and-Laplacian term set has two terms");
+  static_assert(!PAIR || (OT == 2 && sizeof(A) == 4), "paired orbital columns: FP32, two tiles");
+  __shared__ int s_p[2][CELL_PB];                      // point indices of two consecutive batches
+  __shared__ A s_w[NW][CELL_PB][36];                   // per point: x, y, z  x  (w[4], w'[4], w''[4])
+  __shared__ int s_rng[16];                            // first sorted point and count of the brick's cells
   __shared__ A s_reg[BRICK_ROWS * WBW];                // the brick's region: [row][orbital of the workgroup]
-  const int wave = (int)threadIdx.x >> 6;
-  const int lane = (int)threadIdx.x & 63;
+  const int tid = (int)threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
   const int grp = lane >> 4;
   const int col = lane & 15;
+  const int m_ = col >> 2, n_ = col & 3;
+  // the orbital (within the wave's 16 OT) of the lane's column in orbital tile ot: 16 apart, or with
+  // PAIR adjacent (tile ot holds ob + 2 col + ot, so both come in one 8-byte load)
+  auto orb_col = [&](int ot) { return PAIR ? 2 * col + ot : ot * 16 + col; };
   const int nbx = (a.g.n[0] + 1) >> 1, nby = (a.g.n[1] + 1) >> 1, nbz = (a.g.n[2] + 1) >> 1;
   const int64_t n_bricks = (int64_t)nbx * nby * nbz;
   const int n_wg = (a.n_groups + BRICK_WAVES - 1) / BRICK_WAVES;   // orbital groups of a workgroup
   const int64_t n_work = n_bricks * n_wg;
-  // runs before the non-finite points, bounded like every index read from the workspace
-  const int n_runs = (int)min((int64_t)min(max(a.class_start[a.n_classes], 0), a.n_pts), a.n_cells);
+  const int nt = TSET == TSET_VL ? 2 : a.n_terms;     // terms in use (the fit's set: a constant)
+  const SortedPoint<A>* pts = static_cast<const SortedPoint<A>*>(a.pts);
   A jm[9], mt[6];
 #pragma unroll
   for (int i = 0; i < 9; ++i) jm[i] = (A)a.g.jac[i];
@@ -492,23 +552,178 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) void k_bwd_bricks(CellArgs a) {
     const int bx = (int)(brick / ((int64_t)nbz * nby));
     bool ocol[OT];
 #pragma unroll
-    for (int ot = 0; ot < OT; ++ot) ocol[ot] = ob + ot * 16 + col < a.n_orb;
+    for (int ot = 0; ot < OT; ++ot) ocol[ot] = ob + orb_col(ot) < a.n_orb;
     __syncthreads();                                   // the previous region is written out
-    for (int i = (int)threadIdx.x; i < BRICK_ROWS * WBW; i += 64 * BRICK_WAVES) s_reg[i] = A(0);
-    for (int c8 = 0; c8 < 8; ++c8) {
-      const int cx = c8 >> 2, cy = (c8 >> 1) & 1, cz = c8 & 1;
-      const int X = 2 * bx + cx, Y = 2 * by + cy, Z = 2 * bz + cz;
-      if (X >= a.g.n[0] || Y >= a.g.n[1] || Z >= a.g.n[2]) continue;
-      const int64_t cell = ((int64_t)X * a.g.n[1] + Y) * a.g.n[2] + Z;
-      const int r = a.cell_run[cell];
-      if (r < 0 || r >= n_runs) continue;
-      const int start = a.offsets[r];
-      const int cnt = a.counts[r];
-      if (start < 0 || cnt < 0 || start > a.n_pts - cnt) continue;
-      Acc acc[4][OT];
-      cell_block<A, OT, NT>(a, start, cnt, ob, ocol, jm, mt, s_p, s_w, acc);
-      // add the block into the wave's columns of the region: block row (l, m, n) is region row
-      // (cx + l, cy + m, cz + n)
+    for (int i = tid; i < BRICK_ROWS * WBW; i += 64 * BRICK_WAVES) s_reg[i] = A(0);
+    if (tid < 8) {
+      // each cell's sorted point range, bounded like every index read from the workspace
+      const int X = 2 * bx + (tid >> 2), Y = 2 * by + ((tid >> 1) & 1), Z = 2 * bz + (tid & 1);
+      int start = 0, cnt = 0;
+      if (X < a.g.n[0] && Y < a.g.n[1] && Z < a.g.n[2]) {
+        const int64_t cell = ((int64_t)X * a.g.n[1] + Y) * a.g.n[2] + Z;
+        start = a.cell_range[2 * cell];
+        cnt = a.cell_range[2 * cell + 1];
+        if (start < 0 || cnt < 0 || start > a.n_pts - cnt) cnt = 0;
+      }
+      s_rng[tid] = start;
+      s_rng[8 + tid] = cnt;
+    }
+    __syncthreads();
+    // lane k (mod 8) holds cell k's range; a wave-uniform cell index reads it with one lane read
+    const int lane_start = s_rng[lane & 7], lane_count = s_rng[8 + (lane & 7)];
+    auto start_of = [&](int c) { return __builtin_amdgcn_readlane(lane_start, c); };
+    auto count_of = [&](int c) { return __builtin_amdgcn_readlane(lane_count, c); };
+    auto advance = [&](BrickBatch& b) {
+      if (b.c >= 8) return;
+      b.b0 += CELL_PB;
+      if (b.b0 >= count_of(b.c)) {
+        b.b0 = 0;
+        ++b.c;
+        while (b.c < 8 && count_of(b.c) == 0) ++b.c;
+      }
+    };
+    auto count = [&](const BrickBatch& b) { return b.c < 8 ? min(CELL_PB, count_of(b.c) - b.b0) : 0; };
+    // the staging of a batch is shared by 3 CELL_PB threads: thread 3 j + ax holds point j's reduced
+    // coordinate on axis ax (and, for ax = 0, its index)
+    const int sj = tid / 3, sax = tid - 3 * sj;
+    struct Staged {
+      A t;
+      int p;
+    };
+    // every thread loads, from an index clamped into the sorted points (threads past the batch
+    // discard what they read): a conditional load into these loop-carried registers would make the
+    // compiler wait for it at once, where the old and the new value merge
+    auto load_points = [&](const BrickBatch& b, Staged& sp) {
+      const int64_t k = min(max((int64_t)start_of(min(b.c, 7)) + b.b0 + sj, (int64_t)0), (int64_t)a.n_pts - 1);
+      const SortedPoint<A>* rec = pts + k;
+      sp.t = rec->t[sax];
+      sp.p = rec->p;
+    };
+    auto stage_index = [&](const BrickBatch& b, const Staged& sp, int* sp_out) {
+      if (sax == 0 && sj < count(b)) sp_out[sj] = (unsigned)sp.p < (unsigned)a.n_pts ? sp.p : -1;   // -1: nothing
+    };
+    auto stage_weights = [&](const BrickBatch& b, const Staged& sp, A (*sw)[36]) {
+      if (sj < count(b)) {
+        A w4[4], d4[4], dd4[4];
+        bspline_weights<A>(sp.t, w4, d4, dd4);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          sw[sj][12 * sax + i] = w4[i];
+          sw[sj][12 * sax + 4 + i] = d4[i];
+          sw[sj][12 * sax + 8 + i] = dd4[i];
+        }
+      }
+    };
+    // upstream values of one step of a batch: lane group k takes point q + k of it.  With BUF (every
+    // array under 2 GiB) they are buffer loads with 32-bit byte offsets: the offset of a value is
+    // under 2^31, and a dead lane or an orbital past n_orb sets bit 31, which puts the offset beyond
+    // the array, so it reads 0 with no branch.
+    uint32_t col_off[OT], col_flag[OT];                // byte offset of the lane's orbital in a row
+#pragma unroll
+    for (int ot = 0; ot < OT; ++ot) {
+      col_off[ot] = ocol[ot] ? (uint32_t)(ob + orb_col(ot)) * (uint32_t)sizeof(A) : 0u;
+      col_flag[ot] = ocol[ot] ? 0u : 0x80000000u;
+    }
+    auto load_step = [&](int nb, const int* sp_in, int q, A (&bv)[NB][OT]) {
+      const int j = q + grp;
+      const int pj = j < nb ? sp_in[j] : -1;
+      const bool live = pj >= 0;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        if (c >= nt) {
+#pragma unroll
+          for (int ot = 0; ot < OT; ++ot) bv[c][ot] = A(0);
+          continue;
+        }
+        if constexpr (BUF) {
+          const __amdgpu_buffer_rsrc_t rs =
+              __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(a.src[c]), (short)0, a.src_bytes[c], 0x00020000);
+          const uint32_t row = live ? (uint32_t)pj * (uint32_t)(a.src_stride[c] * sizeof(A)) : 0u;
+          const uint32_t flag = live ? 0u : 0x80000000u;
+          if constexpr (PAIR) {
+            // n_orb is even, so both orbitals of a pair are in range or neither is
+            const auto v2 = __builtin_amdgcn_raw_buffer_load_b64(rs, (row + col_off[0]) | flag | col_flag[0], 0, 0);
+            bv[c][0] = __uint_as_float(v2[0]);
+            bv[c][1] = __uint_as_float(v2[1]);
+          } else {
+#pragma unroll
+            for (int ot = 0; ot < OT; ++ot) bv[c][ot] = BufLoad<A>::load(rs, (row + col_off[ot]) | flag | col_flag[ot]);
+          }
+        } else {
+          const A* src = static_cast<const A*>(a.src[c]);
+          const int64_t p = live ? (int64_t)pj : 0;
+          if constexpr (PAIR) {
+            f2v v2 = f2v{0.0f, 0.0f};
+            if (live && ocol[0]) v2 = *reinterpret_cast<const f2v*>(src + p * a.src_stride[c] + ob + orb_col(0));
+            bv[c][0] = v2.x;
+            bv[c][1] = v2.y;
+          } else {
+#pragma unroll
+            for (int ot = 0; ot < OT; ++ot)
+              bv[c][ot] = (live && ocol[ot]) ? src[p * a.src_stride[c] + ob + orb_col(ot)] : A(0);
+          }
+        }
+      }
+    };
+    auto load_upstream = [&](int nb, const int* sp_in, A (&bv)[NQB][NB][OT]) {
+#pragma unroll
+      for (int qi = 0; qi < NQB; ++qi) load_step(nb, sp_in, 4 * qi, bv[qi]);
+    };
+    Acc acc[4][OT];
+    // the products of one step of four points (as cell_block): every term's row weights times its
+    // upstream values
+    auto multiply_step = [&](int nb, int q, const A (*sw)[36], const A (&bv)[NB][OT]) {
+      const A* wp = sw[min(q + grp, nb - 1)];         // a dead lane group multiplies zeros
+      A wx[4], dwx[4], d2wx[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        wx[i] = wp[i];
+        dwx[i] = wp[4 + i];
+        d2wx[i] = wp[8 + i];
+      }
+      const A wy = wp[12 + m_], dwy = wp[16 + m_], d2wy = wp[20 + m_];
+      const A wz = wp[24 + n_], dwz = wp[28 + n_], d2wz = wp[32 + n_];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        if (c >= nt) break;
+        A q0, q1, q2;
+        const int kind = TSET == TSET_VL ? (c == 0 ? TERM_VAL : TERM_LAP) : a.kind[c];
+        term_factors<A>(kind, wy, dwy, d2wy, wz, dwz, d2wz, jm, mt, q0, q1, q2);
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+          // the value term of the fit's set: Q1 = Q2 = 0, and with finite non-negative weights the
+          // two vanishing products change no bit of q0 w_x
+          const A av = (TSET == TSET_VL && c == 0) ? q0 * wx[rt] : fmaa(q2, d2wx[rt], fmaa(q1, dwx[rt], q0 * wx[rt]));
+#pragma unroll
+          for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = M::step(av, bv[c][ot], acc[rt][ot]);
+        }
+      }
+    };
+    // one batch: with its upstream values already loaded, or (more than two terms) loading each
+    // step's values while the step before is multiplied
+    auto multiply = [&](int nb, const int* sp_in, const A (*sw)[36], const A (&bv)[NQB][NB][OT]) {
+      if constexpr (AHEAD) {
+#pragma unroll
+        for (int qi = 0; qi < NQB; ++qi)
+          if (4 * qi < nb) multiply_step(nb, 4 * qi, sw, bv[qi]);
+      } else {
+        A bcur[NB][OT];
+        load_step(nb, sp_in, 0, bcur);
+        for (int q = 0; q < nb; q += 4) {
+          A bnext[NB][OT];
+          if (q + 4 < nb) load_step(nb, sp_in, q + 4, bnext);
+          multiply_step(nb, q, sw, bcur);
+#pragma unroll
+          for (int c = 0; c < NB; ++c)
+#pragma unroll
+            for (int ot = 0; ot < OT; ++ot) bcur[c][ot] = bnext[c][ot];
+        }
+      }
+    };
+    // add the block of cell c into the wave's columns of the region: block row (l, m, n) is region
+    // row (cx + l, cy + m, cz + n)
+    auto add_block = [&](int c) {
+      const int cx = c >> 2, cy = (c >> 1) & 1, cz = c & 1;
 #pragma unroll
       for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
@@ -516,12 +731,77 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) void k_bwd_bricks(CellArgs a) {
           const int i = M::row(grp, e);
           const int lrow = ((cx + rt) * 5 + cy + (i >> 2)) * 5 + cz + (i & 3);
 #pragma unroll
-          for (int ot = 0; ot < OT; ++ot) s_reg[lrow * WBW + wave * BW + ot * 16 + col] += acc[rt][ot][e];
+          for (int ot = 0; ot < OT; ++ot) s_reg[lrow * WBW + wave * BW + orb_col(ot)] += acc[rt][ot][e];
         }
+    };
+
+    // the first four batches: b0 is multiplied now, b1 is staged, b2 and b3 are in flight
+    BrickBatch b0{0, 0};
+    while (b0.c < 8 && count_of(b0.c) == 0) ++b0.c;
+    BrickBatch b1 = b0;
+    advance(b1);
+    BrickBatch b2 = b1;
+    advance(b2);
+    BrickBatch b3 = b2;
+    advance(b3);
+    Staged sp0, sp_next, sp_after;                     // batches b0, b1 and b2 (used below 3 CELL_PB)
+    load_points(b0, sp0);
+    load_points(b1, sp_next);
+    load_points(b2, sp_after);
+    if (tid < 3 * CELL_PB) {
+      stage_index(b0, sp0, s_p[0]);
+      stage_weights(b0, sp0, s_w[0]);
+      stage_index(b1, sp_next, s_p[1]);
+    }
+    __syncthreads();
+    A bq[NBUF][NQB][NB][OT];
+    if constexpr (AHEAD) load_upstream(count(b0), s_p[0], bq[0]);
+    // one batch: multiply b0, add the block if b0 ends its cell, stage b1's weights and b2's indices,
+    // and shift the sequence; `cur` holds b0's upstream values, `nxt` receives b1's
+    auto step = [&](int buf, A (&cur)[NQB][NB][OT], A (&nxt)[NQB][NB][OT]) {
+      const int nb = count(b0);
+      if constexpr (AHEAD) load_upstream(count(b1), s_p[buf ^ 1], nxt);
+      if constexpr (NW == 2) {
+        // b1's weights go to the other buffer and b2's indices over b0's (b0's upstream values
+        // were loaded in the previous step), both while b0 is multiplied
+        if (tid < 3 * CELL_PB) {
+          stage_weights(b1, sp_next, s_w[buf ^ 1]);
+          stage_index(b2, sp_after, s_p[buf]);
+        }
+        sp_next = sp_after;
+        load_points(b3, sp_after);
+      }
+      if (b0.b0 == 0) {
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+          for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = Acc{};
+      }
+      multiply(nb, s_p[buf], s_w[NW == 2 ? buf : 0], cur);
+      if (b0.b0 + CELL_PB >= count_of(b0.c)) add_block(b0.c);
+      __syncthreads();                                 // every wave is done with b0's weights and indices
+      if constexpr (NW == 1) {
+        if (tid < 3 * CELL_PB) {
+          stage_weights(b1, sp_next, s_w[0]);
+          stage_index(b2, sp_after, s_p[buf]);
+        }
+        sp_next = sp_after;
+        load_points(b3, sp_after);
+        __syncthreads();
+      }
+      b0 = b1;
+      b1 = b2;
+      b2 = b3;
+      advance(b3);
+    };
+    while (b0.c < 8) {
+      step(0, bq[0], bq[NBUF - 1]);
+      if (b0.c >= 8) break;
+      step(1, bq[NBUF - 1], bq[0]);
     }
     __syncthreads();
     A* out = static_cast<A*>(a.blocks) + brick * BRICK_ROWS * a.o_pad + obw;
-    for (int i = (int)threadIdx.x; i < BRICK_ROWS * WBW; i += 64 * BRICK_WAVES) {
+    for (int i = tid; i < BRICK_ROWS * WBW; i += 64 * BRICK_WAVES) {
       const int lrow = i / WBW, c = i % WBW;
       if (obw + c < a.n_orb) out[(int64_t)lrow * a.o_pad + c] = s_reg[i];
     }
@@ -584,13 +864,19 @@ __global__ __launch_bounds__(256) void k_bwd_brick_gather(Geom g, const A* regio
   }
 }
 
-__global__ void k_cell_run_index(const int64_t* uniq, const int32_t* class_start, int64_t n_cells, int32_t n_classes,
-                                 int32_t n_pts, int32_t* cell_run) {
+// Each occupied cell's sorted point range (first point, count) from its run; the runs past the
+// finite points' (the non-finite points' sentinel key) are left out.
+__global__ void k_cell_ranges(const int64_t* uniq, const int32_t* counts, const int32_t* offsets,
+                              const int32_t* class_start, int64_t n_cells, int32_t n_classes, int32_t n_pts,
+                              int32_t* cell_range) {
   const int n_runs = (int)min((int64_t)min(max(class_start[n_classes], 0), n_pts), n_cells);
   const int r = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (r >= n_runs) return;
   const int64_t cell = uniq[r] % n_cells;
-  if (cell >= 0) cell_run[cell] = r;
+  if (cell >= 0) {
+    cell_range[2 * cell] = offsets[r];
+    cell_range[2 * cell + 1] = counts[r];
+  }
 }
 
 __global__ void k_bwd_fill_i32(int32_t* p, int64_t n, int32_t value) {
@@ -601,10 +887,19 @@ __global__ void k_bwd_fill_i32(int32_t* p, int64_t n, int32_t value) {
 typedef void (*CellKernel)(CellArgs);
 
 // brick regions: FP32 two orbital tiles per wave, FP64 one (64 KB of LDS for a workgroup's region either way)
-template <typename A, int NT>
-static CellKernel pick_bricks() {
-  if constexpr (sizeof(A) == 4) return k_bwd_bricks<A, 2, NT>;
-  else return k_bwd_bricks<A, 1, NT>;
+template <typename A, bool BUF, bool PAIR>
+static CellKernel pick_bricks_buf(int nt, bool vl) {
+  constexpr int OT = sizeof(A) == 4 ? 2 : 1;
+  if (vl) return k_bwd_bricks<A, OT, 2, TSET_VL, BUF, PAIR>;
+  return nt <= 2 ? k_bwd_bricks<A, OT, 2, TSET_ANY, BUF, PAIR> : k_bwd_bricks<A, OT, 5, TSET_ANY, BUF, PAIR>;
+}
+// pair: FP32 with an even orbital count and 8-byte aligned upstream arrays
+template <typename A>
+static CellKernel pick_bricks(int nt, bool vl, bool buf, bool pair) {
+  if constexpr (sizeof(A) == 4) {
+    if (pair) return buf ? pick_bricks_buf<A, true, true>(nt, vl) : pick_bricks_buf<A, false, true>(nt, vl);
+  }
+  return buf ? pick_bricks_buf<A, true, false>(nt, vl) : pick_bricks_buf<A, false, false>(nt, vl);
 }
 template <typename A>
 static int brick_ot() {
@@ -746,17 +1041,17 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
   a.n_pts = (int32_t)n_pts;
   a.o_pad = d->o_pad;
   if (L.dense) {
-    // each cell's run (-1: empty), from the sort
-    int32_t* cell_run = reinterpret_cast<int32_t*>(W + L.cell_run);
+    // each cell's sorted point range (empty cells: none), from the sort
+    int32_t* cell_range = reinterpret_cast<int32_t*>(W + L.cell_range);
     a.blocks = W + L.blocks;
-    a.cell_run = cell_run;
-    hipLaunchKernelGGL(k_bwd_fill_i32, dim3((unsigned)((L.n_cells + 255) / 256)), dim3(256), 0, stream, cell_run,
-                       L.n_cells, -1);
-    if ((rc = hip_fail(hipGetLastError(), "cell run clear launch"))) return rc;
+    a.cell_range = cell_range;
+    hipLaunchKernelGGL(k_bwd_fill_i32, dim3((unsigned)((2 * L.n_cells + 255) / 256)), dim3(256), 0, stream,
+                       cell_range, 2 * L.n_cells, 0);
+    if ((rc = hip_fail(hipGetLastError(), "cell range clear launch"))) return rc;
     const int max_runs = (int)std::min<int64_t>(n_pts, L.n_cells);
-    hipLaunchKernelGGL(k_cell_run_index, dim3((unsigned)((max_runs + 255) / 256)), dim3(256), 0, stream, uniq,
-                       class_start, L.n_cells, (int32_t)L.n_classes, (int32_t)n_pts, cell_run);
-    if ((rc = hip_fail(hipGetLastError(), "cell run index launch"))) return rc;
+    hipLaunchKernelGGL(k_cell_ranges, dim3((unsigned)((max_runs + 255) / 256)), dim3(256), 0, stream, uniq, counts,
+                       offsets, class_start, L.n_cells, (int32_t)L.n_classes, (int32_t)n_pts, cell_range);
+    if ((rc = hip_fail(hipGetLastError(), "cell range launch"))) return rc;
   }
   const int64_t no = d->n_orb;
   const size_t gsz = d->dtype == SPL_F64 ? 8 : 4;
@@ -785,11 +1080,22 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
     }
     if (nt == 0) continue;
     a.n_terms = nt;
+    for (int c = 0; c < 5; ++c) {
+      // from src[c] to the last point's last orbital
+      const int64_t bytes = c < nt ? ((int64_t)(n_pts - 1) * a.src_stride[c] + no) * (int64_t)gsz : 0;
+      a.src_bytes[c] = bytes < ((int64_t)1 << 31) - 4096 ? (int32_t)bytes : -1;
+    }
     a.gtable = static_cast<char*>(gtable) + (pass == 1 ? d->table_elems * gsz : 0);
     if (L.dense) {
       // every brick at once into its region, then one gather per table row
-      const CellKernel kb = d->dtype == SPL_F64 ? (nt <= 2 ? pick_bricks<double, 2>() : pick_bricks<double, 5>())
-                                                : (nt <= 2 ? pick_bricks<float, 2>() : pick_bricks<float, 5>());
+      const bool vl = nt == 2 && a.kind[0] == TERM_VAL && a.kind[1] == TERM_LAP;
+      bool buf = true, pair = d->n_orb % 2 == 0;
+      for (int c = 0; c < nt; ++c) {
+        buf = buf && a.src_bytes[c] >= 0;
+        pair = pair && a.src_stride[c] % 2 == 0 && reinterpret_cast<uintptr_t>(a.src[c]) % 8 == 0;
+      }
+      const CellKernel kb = d->dtype == SPL_F64 ? pick_bricks<double>(nt, vl, buf, false)
+                                                : pick_bricks<float>(nt, vl, buf, pair);
       const int64_t n_bricks = (int64_t)((d->grid[0] + 1) / 2) * ((d->grid[1] + 1) / 2) * ((d->grid[2] + 1) / 2);
       const int64_t n_wg = (a.n_groups + BRICK_WAVES - 1) / BRICK_WAVES;
       const int grid = (int)std::min<int64_t>(n_bricks * n_wg, 1 << 16);

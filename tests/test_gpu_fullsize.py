@@ -13,7 +13,8 @@ import torch
 
 import paper_1309_6250_amd as P
 from oracle import build as obuild, evaluate as oeval, quantize as oq
-from workloads import config, batched_systems
+from workloads import config, batched_systems, make_system
+from workloads.configs import cubic
 from gpu_helpers import say, to_dev, normwise, DEV
 
 pytestmark = pytest.mark.gpu
@@ -182,6 +183,39 @@ def test_deterministic_adjoint_at_fit_size():
     torch.cuda.synchronize()
     assert torch.equal(a, b)
     assert normwise(a.double().cpu().numpy(), c.double().cpu().numpy()) < 1e-5
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("terms", ["value-laplacian", "gradient"])
+def test_deterministic_adjoint_upstream_arrays_over_2gib(terms):
+    """Upstream arrays of 2 GiB or more: the dense path's brick kernel addresses them with 64-bit
+    offsets instead of buffer loads.  FP32 table, 16^3 cells, 48 orbitals; 12 x 10^6 points with value
+    and Laplacian terms (2.3 GB each), or 4 x 10^6 with the three gradient terms (one 2.3 GB array):
+    bitwise repeatable, and equal to the atomic form to FP32 summation accuracy (which, with about
+    2 x 10^5 contributions per table row, is looser than at the fit's 2 x 10^3)."""
+    s = make_system("large-upstream", cubic(16 * 0.43), (16, 16, 16), 48, 4.0, 2.0, (1309, 6250, 77))
+    d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, "f32")
+    tab = P.spline_build(d, to_dev(s.grid_values()))
+    n = 12_000_000 if terms == "value-laplacian" else 4_000_000
+    g = torch.Generator(device=DEV).manual_seed(406)
+    pos = (torch.rand((n, 3), device=DEV, generator=g, dtype=torch.float64) @ to_dev(s.lattice))
+    if terms == "value-laplacian":
+        up = (torch.randn((n, s.n_orb), device=DEV, generator=g), None,
+              torch.randn((n, s.n_orb), device=DEV, generator=g))
+    else:
+        up = (None, torch.randn((n, 3, s.n_orb), device=DEV, generator=g), None)
+    big = max(t.numel() * 4 for t in up if t is not None)
+    assert big >= 2 ** 31
+    say("deterministic adjoint, upstream arrays over 2 GiB", terms)
+    a, _ = P.spline_eval_vgl_backward(d, tab, pos, *up, want_pos=False, flags=P.SPL_DETERMINISTIC)
+    b, _ = P.spline_eval_vgl_backward(d, tab, pos, *up, want_pos=False, flags=P.SPL_DETERMINISTIC)
+    c, _ = P.spline_eval_vgl_backward(d, tab, pos, *up, want_pos=False)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    # two FP32 sums of about 64 n / 16^3 random contributions per row, in different orders: their
+    # rounding errors grow like the square root of that count
+    per_row = 64 * n / 16 ** 3
+    assert normwise(a.double().cpu().numpy(), c.double().cpu().numpy()) < 8 * 2.0 ** -24 * np.sqrt(per_row)
 
 
 # ---------------------------------------------------------------- the other representations at full size

@@ -393,15 +393,16 @@ def test_backward_deterministic_many_points_per_cell():
     assert normwise(b.cpu().numpy()[0, ..., :33], rb) < 1e-12
 
 
+@pytest.mark.parametrize("n_orb", [37, 38])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_backward_deterministic_dense_path(dtype):
+def test_backward_deterministic_dense_path(dtype, n_orb):
     """At 4 or more points per cell the deterministic adjoint sums the cell blocks of every brick of
     2 x 2 x 2 cells into a 5 x 5 x 5-row region in the workspace and gathers the regions per table row
     (no colour classes): oracle parity with the separate Laplacian table and every upstream term, an
-    odd orbital count, a ragged grid (odd cell counts leave partial bricks; 5 cells wrap a region onto
-    itself), repeatable bit for bit."""
+    odd or even orbital count, a ragged grid (odd cell counts leave partial bricks; 5 cells wrap a region onto
+    itself), repeatable bit for bit.  An even orbital count takes FP32's paired columns."""
     rng = np.random.default_rng(107)
-    grid, n_orb, n = (6, 5, 7), 37, 2000
+    grid, n = (6, 5, 7), 2000
     beta = rng.standard_normal(grid + (n_orb,))
     lbeta = rng.standard_normal(grid + (n_orb,))
     d = P.spline_desc_init(SKEW, grid, n_orb, dtype, has_lap=True)
@@ -428,4 +429,43 @@ def test_backward_deterministic_dense_path(dtype):
     tol = 1e-12 if dtype == "f64" else 2e-5
     assert normwise(got[0, ..., :n_orb], rb) <= tol
     assert normwise(got[1, ..., :n_orb], rlb) <= tol
+    assert np.all(got[..., n_orb:] == 0.0)
+
+
+@pytest.mark.parametrize("n_orb", [45, 46])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_backward_dense_value_and_laplacian_terms(dtype, n_orb):
+    """The fit's term set (value and Laplacian upstream gradients, derivative Laplacian) on the dense
+    path, whose row weights are fixed at compile time: clustered points, so that some cells hold
+    several batches of 32 points and many cells and whole bricks hold none; oracle parity and a
+    bitwise repeat.  An even orbital count takes FP32's paired columns (two adjacent orbitals per
+    lane), with a partly filled last group of orbitals."""
+    rng = np.random.default_rng(109)
+    grid = (10, 8, 9)
+    beta = rng.standard_normal(grid + (n_orb,))
+    d = P.spline_desc_init(SKEW, grid, n_orb, dtype)
+    tab = table_from_oracle(d, beta, dtype)
+    bq = oq.quantized(beta, dtype)
+    centers = rng.uniform(0, 1, size=(6, 3))
+    n = 4 * int(np.prod(grid))                          # 4 points per cell on average: the dense path
+    s = (centers[rng.integers(0, 6, n)] + rng.normal(0, 0.04, size=(n, 3))) % 1.0
+    pos = s @ SKEW
+    i0, _, _ = oeval.reduced_coordinates(SKEW, grid, pos)
+    per_cell = np.bincount(np.ravel_multi_index(i0.T, grid), minlength=int(np.prod(grid)))
+    bricks = [(k + 1) // 2 for k in grid]
+    per_brick = np.bincount(np.ravel_multi_index((i0 // 2).T, bricks), minlength=int(np.prod(bricks)))
+    assert per_cell.max() > 2 * 32 and (per_brick == 0).any()
+    gv, gl = rng.standard_normal((n, n_orb)), rng.standard_normal((n, n_orb))
+    od = torch.float64 if dtype == "f64" else torch.float32
+    say("deterministic backward, dense path, value and Laplacian terms", dtype)
+    runs = []
+    for _ in range(2):
+        gt, _ = P.spline_eval_vgl_backward(d, tab, to_dev(pos), to_dev(gv, od), None, to_dev(gl, od), want_pos=False,
+                                           flags=P.SPL_DETERMINISTIC)
+        torch.cuda.synchronize()
+        runs.append(gt.clone())
+    assert torch.equal(runs[0], runs[1])
+    rb, _, _ = oadj.vgl_backward(bq, SKEW, pos, gv, None, gl)
+    got = runs[0].double().cpu().numpy()
+    assert normwise(got[0, ..., :n_orb], rb) <= (1e-12 if dtype == "f64" else 2e-5)
     assert np.all(got[..., n_orb:] == 0.0)

@@ -723,15 +723,16 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) void k_bwd_bricks(CellArgs a) {
     // add the block of cell c into the wave's columns of the region: block row (l, m, n) is region
     // row (cx + l, cy + m, cz + n)
     auto add_block = [&](int c) {
-      const int cx = c >> 2, cy = (c >> 1) & 1, cz = c & 1;
+      // region row (cx + l, cy + m, cz + n) = the cell's corner row (uniform) + that of (l, m, n)
+      A* corner = s_reg + (((c >> 2) * 5 + ((c >> 1) & 1)) * 5 + (c & 1)) * WBW + wave * BW;
 #pragma unroll
       for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int i = M::row(grp, e);
-          const int lrow = ((cx + rt) * 5 + cy + (i >> 2)) * 5 + cz + (i & 3);
+          A* rp = corner + ((rt * 5 + (i >> 2)) * 5 + (i & 3)) * WBW;
 #pragma unroll
-          for (int ot = 0; ot < OT; ++ot) s_reg[lrow * WBW + wave * BW + orb_col(ot)] += acc[rt][ot][e];
+          for (int ot = 0; ot < OT; ++ot) rp[orb_col(ot)] += acc[rt][ot][e];
         }
     };
 

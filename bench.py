@@ -556,7 +556,27 @@ def fit_rows(steps, warmup, adam_steps=200, cg_iters=400):
     out["spline_fit_terms_cells_fit_f32"] = {
         "ms": ms_fused, "ms_forward_then_misfit": ms_two, "points": n, "n_orb": s.n_orb,
         "note": "V and lap misfit gradients and loss from the cell-wise forward, sort reused"}
-    del tv, tl, yv, yl, cw
+    # the fit's loss terms and their coefficient gradient: fit terms then the deterministic adjoint
+    # (one workspace, one sort), against the one pass (forward, misfit and adjoint in one kernel)
+    ww = torch.empty(max(P.spline_cells_work_bytes(d, n), P.spline_backward_work_bytes(d, n, P.SPL_DETERMINISTIC)),
+                     dtype=torch.uint8, device="cuda")
+    fw = torch.empty(P.spline_fit_gradient_work_bytes(d, n), dtype=torch.uint8, device="cuda")
+    gtab = P.new_gtable(d)
+    P.spline_fit_terms_cells(d, table, pos, tv, 1.0, tl, 1.0, g_v=yv, g_lap=yl, loss=loss, work=ww)
+    P.spline_fit_gradient_cells(d, table, pos, tv, 1.0, tl, 1.0, gtable=gtab, loss=loss, work=fw)
+
+    def terms_then_adjoint():
+        P.spline_fit_terms_cells(d, table, pos, tv, 1.0, tl, 1.0, g_v=yv, g_lap=yl, loss=loss, work=ww, flags=reuse)
+        P.spline_eval_vgl_backward(d, table, pos, yv, None, yl, gtab, None, want_pos=False,
+                                   flags=P.SPL_DETERMINISTIC | reuse, work=ww)
+    ms_pair = time_launches(terms_then_adjoint, max(3, steps // 4), 1)
+    ms_one = time_launches(lambda: P.spline_fit_gradient_cells(d, table, pos, tv, 1.0, tl, 1.0, gtable=gtab, loss=loss,
+                                                               work=fw, flags=reuse), max(3, steps // 4), 1)
+    out["spline_fit_gradient_cells_fit_f32"] = {
+        "ms": ms_one, "ms_terms_then_adjoint": ms_pair, "points": n, "n_orb": s.n_orb,
+        "note": "loss terms of V and lap and their coefficient gradient; one pass: forward, misfit and adjoint of "
+                "each batch of points in one kernel (the same bits as the two kernels), sort reused"}
+    del tv, tl, yv, yl, cw, ww, fw, gtab
     rms = float(torch.sqrt(torch.mean(table.double() ** 2)))
     lr = FIT_LR * rms
     fit_adam(d, table, pos, v_t, lap_t, steps=2, lam=1e-3, lr=lr)     # untimed: first-use allocations
@@ -587,8 +607,8 @@ def fit_rows(steps, warmup, adam_steps=200, cg_iters=400):
                                      "optimum": {"method": "conjugate gradients on the same loss, FP64 table",
                                                  "iterations": cg_done, "relative_residual": cg_res, "s": cg_s},
                                      "lambda": 1e-3, "deterministic_gradient": True, "heldout": res,
-                                     "note": "per step: spline_fit_terms_cells (cell-wise forward with the misfit "
-                                             "of V and lap), deterministic adjoint and smoothness penalty on the "
+                                     "note": "per step: spline_fit_gradient_cells (cell-wise forward, misfit of V "
+                                             "and lap, and adjoint in one pass) and the smoothness penalty on the "
                                              "cell sort of the first step; torch's fused Adam on the "
                                              "16.8 MB table; after 2 untimed steps"}
     return out

@@ -316,6 +316,36 @@ int spline_fit_terms_cells(const spl_desc* d, const void* table, int64_t n_pts, 
                            void* stream);
 
 /*
+ * The data terms of the least-squares fit and their coefficient gradient in one pass: for the
+ * n_pts fit points, with y_v, y_lap the values and Laplacians of the table there,
+ *   *loss  += w_v sum (y_v - t_v)^2 + w_lap sum (y_lap - t_lap)^2                (ACCUMULATED)
+ *   gtable += d/dtable of those two sums                                            (ACCUMULATED)
+ * that is, spline_fit_terms_cells followed by spline_eval_vgl_backward (SPL_DETERMINISTIC) of its
+ * upstream gradients, with the same results bit for bit, but the upstream gradients are never
+ * stored: each batch of a cell's points is evaluated, compared with its targets and multiplied back
+ * on the matrix cores in one kernel.  (The fit's regression counterpart of the smoothing spline of
+ * App. A; the adjoint is the transpose of Eq. b-splineapproximation.)
+ *   t_v, t_lap   device, FP32 [n_pts][n_orb] in the caller's point order (both required)
+ *   w_v, w_lap   the terms' weights, finite
+ *   gtable       device, d->gtable_bytes, FP32 [N1][N2][N3][o_pad]; padding columns are never written
+ *   loss         device, one FP64
+ *   flags        SPL_REUSE_SORT: the workspace holds the cell sort of these points from an earlier
+ *                call of this function (the layout differs from spline_cells_work_bytes')
+ *   work         device, 256-byte aligned, spline_fit_gradient_work_bytes() bytes
+ * Supported: FP32 B-spline tables without a separate Laplacian table, at least 4 points per cell
+ * on average, and the table and each target array under 2 GiB; otherwise SPL_EUNSUPPORTED (use
+ * spline_fit_terms_cells and spline_eval_vgl_backward).  A non-finite point contributes nothing to
+ * gtable and makes the loss NaN.  Other errors as for spline_fit_terms_cells.  Allocates nothing.
+ */
+int spline_fit_gradient_cells(const spl_desc* d, const void* table, int64_t n_pts, const double* pos,
+                              const void* t_v, double w_v, const void* t_lap, double w_lap, void* gtable,
+                              double* loss, int32_t flags, void* work, int64_t work_bytes, void* stream);
+
+/* Workspace bytes of spline_fit_gradient_cells for n_pts points (the cell sort, each cell's point
+ * range, the brick regions and the loss partial sums).  Host only; may query the current HIP device. */
+int spline_fit_gradient_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes);
+
+/*
  * Adjoint of spline_eval_vgl: given dL/dv, dL/dgrad, dL/dlap of a scalar loss L,
  *   gtable += dL/dtable   (the transpose of the 64-coefficient gather, periodic wrap)
  *   gpos    = dL/dpos     (through grad, Hessian and gradient of the Laplacian)

@@ -337,6 +337,42 @@ def spline_fit_terms_cells(desc, table, pos, t_v=None, w_v=1.0, t_lap=None, w_la
     return g_v, g_lap, loss
 
 
+def spline_fit_gradient_work_bytes(desc, n_pts):
+    out = ctypes.c_int64()
+    check(lib().spline_fit_gradient_work_bytes(ctypes.byref(desc), int(n_pts), ctypes.byref(out)),
+          "spline_fit_gradient_work_bytes")
+    return out.value
+
+
+def spline_fit_gradient_cells(desc, table, pos, t_v, w_v, t_lap, w_lap, gtable=None, loss=None, work=None, flags=0,
+                              stream=None):
+    """The fit's value and Laplacian misfit and its coefficient gradient in one pass: returns
+    (gtable, loss), both accumulated into (fresh zeros if not given); the same bits as
+    spline_fit_terms_cells followed by the deterministic spline_eval_vgl_backward.  FP32 tables,
+    dense points (SPL_EUNSUPPORTED otherwise).  flags: SPL_REUSE_SORT when `work` already holds this
+    function's cell sort of these same points."""
+    n = _check_inputs(desc, table, pos)
+    od = OUT_TORCH[desc.dtype]
+    dev = pos.device
+    for name, t in (("t_v", t_v), ("t_lap", t_lap)):
+        _need(t, name, od, n * desc.n_orb)
+    if gtable is None:
+        gtable = new_gtable(desc)
+    if loss is None:
+        loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    _need(loss, "loss", torch.float64, 1)
+    nbytes = spline_fit_gradient_work_bytes(desc, n)
+    if work is None:
+        work = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    if work.numel() * work.element_size() < nbytes:
+        raise ValueError(f"work must hold {nbytes} bytes")
+    check(lib().spline_fit_gradient_cells(ctypes.byref(desc), _ptr(table), n, _ptr(pos), _ptr(t_v), float(w_v),
+                                          _ptr(t_lap), float(w_lap), _ptr(gtable), _ptr(loss), int(flags), _ptr(work),
+                                          int(work.numel() * work.element_size()), _stream(stream)),
+          "spline_fit_gradient_cells")
+    return gtable, loss
+
+
 def spline_eval_vgl_backward(desc, table, pos, gv=None, ggrad=None, glap=None, gtable=None, gpos=None,
                              want_table=True, want_pos=True, flags=0, stream=None, work=None):
     """Returns (gtable, gpos).  gtable is accumulated into (a fresh zero table if not given).

@@ -506,6 +506,40 @@ int spline_fit_terms_cells(const spl_desc* d, const void* table, int64_t n_pts, 
                            (flags & SPL_REUSE_SORT) != 0, static_cast<hipStream_t>(stream), &fit);
 }
 
+int spline_fit_gradient_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes) {
+  clear_error();
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if (!bytes || n_pts < 0 || n_pts > 0x7fffffffLL) return fail(SPL_EINVAL, "bytes is NULL or n_pts out of range");
+  if (n_pts == 0) {
+    *bytes = 0;
+    return SPL_OK;
+  }
+  return fit_gradient_work_bytes(d, n_pts, bytes);
+}
+
+int spline_fit_gradient_cells(const spl_desc* d, const void* table, int64_t n_pts, const double* pos,
+                              const void* t_v, double w_v, const void* t_lap, double w_lap, void* gtable,
+                              double* loss, int32_t flags, void* work, int64_t work_bytes, void* stream) {
+  clear_error();
+  int rc = check_eval_args(d, table, n_pts, pos);
+  if (rc) return rc;
+  if (flags & ~SPL_REUSE_SORT) return fail(SPL_EINVAL, "unknown flags 0x%x", flags);
+  if (d->basis != SPL_BSPLINE || d->sep_grad || d->bloch)
+    return fail(SPL_EUNSUPPORTED, "the fit gradient covers real B-spline tables without separate gradients");
+  if (!isfinite(w_v) || !isfinite(w_lap)) return fail(SPL_EINVAL, "weight is not finite");
+  if (!t_v || !t_lap) return fail(SPL_EINVAL, "the one-pass fit gradient needs both targets");
+  if (n_pts == 0) return SPL_OK;
+  for (const void* o : {t_v, t_lap})
+    if (!out_align_ok(d, o)) return fail(SPL_EINVAL, "target not aligned to its element size");
+  if (!gtable || !aligned(gtable, d->dtype == SPL_F64 ? 8 : 4)) return fail(SPL_EINVAL, "gtable is NULL or misaligned");
+  if (!loss || (uintptr_t)loss % 8) return fail(SPL_EINVAL, "loss is NULL or not 8-byte aligned");
+  if (!work) return fail(SPL_EINVAL, "work is NULL (size from spline_fit_gradient_work_bytes)");
+  if (!aligned(work, 256)) return fail(SPL_EINVAL, "workspace must be 256-byte aligned");
+  return launch_fit_gradient(d, table, n_pts, pos, t_v, w_v, t_lap, w_lap, gtable, loss, work, work_bytes,
+                             (flags & SPL_REUSE_SORT) != 0, static_cast<hipStream_t>(stream));
+}
+
 int spline_eval_vgl_backward(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, const void* gv,
                              const void* ggrad, const void* glap, void* gtable, double* gpos, int32_t flags,
                              void* work, int64_t work_bytes, void* stream) {

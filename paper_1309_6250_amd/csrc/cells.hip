@@ -74,7 +74,8 @@ static hipError_t sort_cell_keys(void* temp, size_t& bytes, const int64_t* keys_
 constexpr int FIT_SUM_BLOCKS = 256;
 constexpr int FIT_SUM_THREADS = 256;
 
-static int sort_layout(const spl_desc* d, int64_t n_pts, SortLayout* L, bool adjoint_blocks = true) {
+static int sort_layout(const spl_desc* d, int64_t n_pts, SortLayout* L, bool adjoint_blocks = true,
+                       bool fit_partials = false) {
   L->n_cells = (int64_t)d->grid[0] * d->grid[1] * d->grid[2];
   L->n_classes = axis_colours(d->grid[0]) * axis_colours(d->grid[1]) * axis_colours(d->grid[2]);
   const uint64_t max_key = (uint64_t)(L->n_classes + 1) * (uint64_t)L->n_cells;
@@ -112,12 +113,12 @@ static int sort_layout(const spl_desc* d, int64_t n_pts, SortLayout* L, bool adj
   const size_t n_bricks = (size_t)((d->grid[0] + 1) / 2) * ((d->grid[1] + 1) / 2) * ((d->grid[2] + 1) / 2);
   const size_t block_bytes = n_bricks * 125 * (size_t)d->o_pad * gsz;
   L->dense = adjoint_blocks && n_pts >= 4 * L->n_cells && block_bytes <= ((size_t)4 << 30);
-  L->cell_range = off; off = align_up(off + (L->dense ? 8 * (size_t)L->n_cells : 0));
+  L->cell_range = off; off = align_up(off + (L->dense ? 12 * (size_t)L->n_cells : 0));
   L->blocks = off; off = align_up(off + (L->dense ? block_bytes : 0));
-  // forward only: one FP64 partial sum per work item of the fit terms, at most min(n, cells) runs
-  // times the 16-orbital tiles, then one per workgroup of the first summing step (FIT_SUM_BLOCKS)
+  // the fit terms: one FP64 partial sum per work item, at most min(n, cells) runs times the 16-orbital
+  // tiles, then one per workgroup of the first summing step (FIT_SUM_BLOCKS)
   L->partials = off;
-  if (!adjoint_blocks)
+  if (!adjoint_blocks || fit_partials)
     off = align_up(off + 8 * ((size_t)std::min<int64_t>(n_pts, L->n_cells) * (size_t)((d->n_orb + 15) / 16) + FIT_SUM_BLOCKS));
   L->temp = off; off = align_up(off + L->temp_bytes);
   L->total = off;
@@ -204,7 +205,7 @@ struct CellArgs {
   int32_t n_pts;           // every index read from the sort is checked against this and n_cells
   int32_t o_pad;
   void* blocks;              // dense: [n_bricks][125][o_pad] gradient regions of the bricks of 2 x 2 x 2 cells
-  const int32_t* cell_range; // dense: [n_cells][2] first sorted point and count of each cell (0 if empty)
+  const int32_t* cell_range; // dense: [n_cells][3] first sorted point, count (0 if empty) and run of each cell
   int32_t src_bytes[5];      // dense: bytes of each term's upstream array from src[c] to its last value, or
                              // -1 when one reaches 2 GiB (then the brick kernel uses 64-bit addresses)
 };
@@ -561,8 +562,8 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) void k_bwd_bricks(CellArgs a) {
       int start = 0, cnt = 0;
       if (X < a.g.n[0] && Y < a.g.n[1] && Z < a.g.n[2]) {
         const int64_t cell = ((int64_t)X * a.g.n[1] + Y) * a.g.n[2] + Z;
-        start = a.cell_range[2 * cell];
-        cnt = a.cell_range[2 * cell + 1];
+        start = a.cell_range[3 * cell];
+        cnt = a.cell_range[3 * cell + 1];
         if (start < 0 || cnt < 0 || start > a.n_pts - cnt) cnt = 0;
       }
       s_rng[tid] = start;
@@ -865,7 +866,7 @@ __global__ __launch_bounds__(256) void k_bwd_brick_gather(Geom g, const A* regio
   }
 }
 
-// Each occupied cell's sorted point range (first point, count) from its run; the runs past the
+// Each occupied cell's sorted point range (first point, count) and run index; the runs past the
 // finite points' (the non-finite points' sentinel key) are left out.
 __global__ void k_cell_ranges(const int64_t* uniq, const int32_t* counts, const int32_t* offsets,
                               const int32_t* class_start, int64_t n_cells, int32_t n_classes, int32_t n_pts,
@@ -875,8 +876,9 @@ __global__ void k_cell_ranges(const int64_t* uniq, const int32_t* counts, const 
   if (r >= n_runs) return;
   const int64_t cell = uniq[r] % n_cells;
   if (cell >= 0) {
-    cell_range[2 * cell] = offsets[r];
-    cell_range[2 * cell + 1] = counts[r];
+    cell_range[3 * cell] = offsets[r];
+    cell_range[3 * cell + 1] = counts[r];
+    cell_range[3 * cell + 2] = r;
   }
 }
 
@@ -1046,8 +1048,8 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
     int32_t* cell_range = reinterpret_cast<int32_t*>(W + L.cell_range);
     a.blocks = W + L.blocks;
     a.cell_range = cell_range;
-    hipLaunchKernelGGL(k_bwd_fill_i32, dim3((unsigned)((2 * L.n_cells + 255) / 256)), dim3(256), 0, stream,
-                       cell_range, 2 * L.n_cells, 0);
+    hipLaunchKernelGGL(k_bwd_fill_i32, dim3((unsigned)((3 * L.n_cells + 255) / 256)), dim3(256), 0, stream,
+                       cell_range, 3 * L.n_cells, 0);
     if ((rc = hip_fail(hipGetLastError(), "cell range clear launch"))) return rc;
     const int max_runs = (int)std::min<int64_t>(n_pts, L.n_cells);
     hipLaunchKernelGGL(k_cell_ranges, dim3((unsigned)((max_runs + 255) / 256)), dim3(256), 0, stream, uniq, counts,
@@ -1415,6 +1417,370 @@ void k_fwd_cells(FwdArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// The fit's data-term gradient in one pass (spline_fit_gradient_cells): FP32 table, value and
+// derivative-Laplacian terms, dense points.  Per brick of 2 x 2 x 2 cells and batch of a cell's
+// points: the forward values of both terms on the matrix cores from the cell's block (as
+// k_fwd_cells), the residuals against the targets, the loss terms and the upstream gradient
+// 2 w (y - t) (as the fit terms), and at once the adjoint products of that gradient into the
+// brick's region (as k_bwd_bricks).  The upstream gradient stays in registers: the forward's output
+// layout (lane group k holds points 4 k .. 4 k + 3 of a tile) becomes the adjoint's operand layout
+// (k-step q: lane group k holds point 4 q + k) by a 4 x 4 transpose across lane groups, two rounds
+// of 32- and 16-lane swaps.  Every sum is formed as in those two kernels and in the same order, so
+// the loss partials and the region sums are the same bits as spline_fit_terms_cells followed by
+// the deterministic adjoint.
+struct FitArgs {
+  Geom g;
+  const float* table;
+  int32_t table_bytes;         // under 2 GiB (buffer loads with 32-bit offsets)
+  const float* target[2];      // t_v, t_lap: [n_pts][n_orb], the caller's point order
+  int32_t target_bytes[2];     // each under 2 GiB
+  double w[2];                 // the terms' weights
+  const int32_t* cell_range;   // [n_cells][3]: first sorted point, count (0: empty), run index
+  const void* pts;             // SortedPoint<float> records in sorted order
+  void* blocks;                // [n_bricks][125][o_pad] regions
+  double* partial;             // [runs][n_groups] loss partial sums
+  int32_t n_pts, n_orb, o_pad, n_groups, n_runs;
+};
+
+// 4 x 4 transpose across the lane groups of a wave: register e of lane group k becomes register k of
+// lane group e (lane order within a group kept).
+__device__ __forceinline__ void transpose_groups(float (&x)[4]) {
+  auto a02 = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[0]), __float_as_uint(x[2]), false, false);
+  auto a13 = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[1]), __float_as_uint(x[3]), false, false);
+  auto b01 = __builtin_amdgcn_permlane16_swap(a02[0], a13[0], false, false);
+  auto b23 = __builtin_amdgcn_permlane16_swap(a02[1], a13[1], false, false);
+  x[0] = __uint_as_float(b01[0]);
+  x[1] = __uint_as_float(b01[1]);
+  x[2] = __uint_as_float(b23[0]);
+  x[3] = __uint_as_float(b23[1]);
+}
+
+__global__ __launch_bounds__(64 * BRICK_WAVES) __attribute__((amdgpu_waves_per_eu(2))) void k_fit_bricks(FitArgs a) {
+  using A = float;
+  using M = Mfma<float>;
+  using Acc = M::acc;
+  constexpr int OT = 2;                                // orbital tiles of 16 per wave
+  constexpr int BW = 16 * OT;
+  constexpr int WBW = BRICK_WAVES * BW;
+  constexpr uint32_t RSRC = 0x00020000;                // raw buffer resource, range-checked
+  __shared__ int s_p[2][CELL_PB];
+  __shared__ A s_w[2][CELL_PB][36];
+  __shared__ int s_rng[24];
+  __shared__ A s_reg[BRICK_ROWS * WBW];
+  const int tid = (int)threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int grp = lane >> 4;
+  const int col = lane & 15;
+  const int m_ = col >> 2, n_ = col & 3;
+  const int nbx = (a.g.n[0] + 1) >> 1, nby = (a.g.n[1] + 1) >> 1, nbz = (a.g.n[2] + 1) >> 1;
+  const int64_t n_bricks = (int64_t)nbx * nby * nbz;
+  const int n_wg = (a.n_groups + BRICK_WAVES - 1) / BRICK_WAVES;
+  const int64_t n_work = n_bricks * n_wg;
+  const SortedPoint<A>* pts = static_cast<const SortedPoint<A>*>(a.pts);
+  A jm[9], mt[6];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) jm[i] = (A)a.g.jac[i];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) mt[i] = (A)a.g.metric[i];
+  const A two_w[2] = {(A)(2.0 * a.w[0]), (A)(2.0 * a.w[1])};
+  const __amdgpu_buffer_rsrc_t rs_tab =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.table), (short)0, a.table_bytes, RSRC);
+  const __amdgpu_buffer_rsrc_t rs_t0 =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.target[0]), (short)0, a.target_bytes[0], RSRC);
+  const __amdgpu_buffer_rsrc_t rs_t1 =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.target[1]), (short)0, a.target_bytes[1], RSRC);
+  const uint32_t row_bytes = (uint32_t)a.n_orb * 4u;  // target row stride
+
+  for (int64_t w = blockIdx.x; w < n_work; w += gridDim.x) {
+    const int64_t brick = w / n_wg;
+    const int obw = (int)(w % n_wg) * WBW;
+    const int ob = obw + wave * BW;                    // first orbital of this wave
+    const int group = ob / BW;                         // the wave's group of 32 orbitals (loss slot)
+    const int bz = (int)(brick % nbz);
+    const int by = (int)((brick / nbz) % nby);
+    const int bx = (int)(brick / ((int64_t)nbz * nby));
+    // the lane's orbital in tile ot: ob + 16 ot + col (as the FP32 fit terms); an orbital past
+    // n_orb sets bit 31 of its offsets, which reads 0
+    uint32_t col_off[OT], col_flag[OT];
+    bool ocol[OT];
+#pragma unroll
+    for (int ot = 0; ot < OT; ++ot) {
+      ocol[ot] = ob + 16 * ot + col < a.n_orb;
+      col_off[ot] = ocol[ot] ? (uint32_t)(ob + 16 * ot + col) * 4u : 0u;
+      col_flag[ot] = ocol[ot] ? 0u : 0x80000000u;
+    }
+    __syncthreads();                                   // the previous region is written out
+    for (int i = tid; i < BRICK_ROWS * WBW; i += 64 * BRICK_WAVES) s_reg[i] = A(0);
+    if (tid < 8) {
+      const int X = 2 * bx + (tid >> 2), Y = 2 * by + ((tid >> 1) & 1), Z = 2 * bz + (tid & 1);
+      int start = 0, cnt = 0, run = -1;
+      if (X < a.g.n[0] && Y < a.g.n[1] && Z < a.g.n[2]) {
+        const int64_t cell = ((int64_t)X * a.g.n[1] + Y) * a.g.n[2] + Z;
+        start = a.cell_range[3 * cell];
+        cnt = a.cell_range[3 * cell + 1];
+        run = a.cell_range[3 * cell + 2];
+        if (start < 0 || cnt < 0 || start > a.n_pts - cnt) cnt = 0;
+      }
+      s_rng[tid] = start;
+      s_rng[8 + tid] = cnt;
+      s_rng[16 + tid] = run;
+    }
+    __syncthreads();
+    const int lane_start = s_rng[lane & 7], lane_count = s_rng[8 + (lane & 7)], lane_run = s_rng[16 + (lane & 7)];
+    auto start_of = [&](int c) { return __builtin_amdgcn_readlane(lane_start, c); };
+    auto count_of = [&](int c) { return __builtin_amdgcn_readlane(lane_count, c); };
+    auto run_of = [&](int c) { return __builtin_amdgcn_readlane(lane_run, c); };
+    auto advance = [&](BrickBatch& b) {
+      if (b.c >= 8) return;
+      b.b0 += CELL_PB;
+      if (b.b0 >= count_of(b.c)) {
+        b.b0 = 0;
+        ++b.c;
+        while (b.c < 8 && count_of(b.c) == 0) ++b.c;
+      }
+    };
+    auto count = [&](const BrickBatch& b) { return b.c < 8 ? min(CELL_PB, count_of(b.c) - b.b0) : 0; };
+    // staging, as in k_bwd_bricks: thread 3 j + ax holds point j's coordinate on axis ax
+    const int sj = tid / 3, sax = tid - 3 * sj;
+    struct Staged {
+      A t;
+      int p;
+    };
+    auto load_points = [&](const BrickBatch& b, Staged& sp) {
+      const int64_t k = min(max((int64_t)start_of(min(b.c, 7)) + b.b0 + sj, (int64_t)0), (int64_t)a.n_pts - 1);
+      const SortedPoint<A>* rec = pts + k;
+      sp.t = rec->t[sax];
+      sp.p = rec->p;
+    };
+    auto stage_index = [&](const BrickBatch& b, const Staged& sp, int* sp_out) {
+      if (sax == 0 && sj < count(b)) sp_out[sj] = (unsigned)sp.p < (unsigned)a.n_pts ? sp.p : -1;
+    };
+    auto stage_weights = [&](const BrickBatch& b, const Staged& sp, A (*sw)[36]) {
+      if (sj < count(b)) {
+        A w4[4], d4[4], dd4[4];
+        bspline_weights<A>(sp.t, w4, d4, dd4);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          sw[sj][12 * sax + i] = w4[i];
+          sw[sj][12 * sax + 4 + i] = d4[i];
+          sw[sj][12 * sax + 8 + i] = dd4[i];
+        }
+      }
+    };
+    // the cell's block as the forward's B operands: k-step 4 l + m, lane group n holds row (l, m, n)
+    auto load_block = [&](int c, A (&blk)[16][OT]) {
+      const int X = 2 * bx + (c >> 2), Y = 2 * by + ((c >> 1) & 1), Z = 2 * bz + (c & 1);
+      int ix[4], iy[4], iz[4];
+      wrap4(min(X, a.g.n[0] - 1), a.g.n[0], ix);
+      wrap4(min(Y, a.g.n[1] - 1), a.g.n[1], iy);
+      wrap4(min(Z, a.g.n[2] - 1), a.g.n[2], iz);
+#pragma unroll
+      for (int ks = 0; ks < 16; ++ks) {
+        const uint32_t row = (uint32_t)((int64_t)ix[ks >> 2] * a.g.s0 + (int64_t)iy[ks & 3] * a.g.s1 +
+                                        (int64_t)iz[grp] * a.g.o_pad) * 4u;
+#pragma unroll
+        for (int ot = 0; ot < OT; ++ot)
+          blk[ks][ot] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs_tab, (row + col_off[ot]) | col_flag[ot], 0, 0));
+      }
+    };
+    // the targets of a batch, in the forward's output layout: tile mt, lane group k, element e is
+    // point 16 mt + 4 k + e; bit 4 mt + e of `valid` marks a point that is written (as the fit terms)
+    auto load_targets = [&](int nb, const int* sp_in, A (&tg)[2][2][OT][4], uint32_t& valid) {
+      valid = 0;
+#pragma unroll
+      for (int mt_ = 0; mt_ < 2; ++mt_)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int j = mt_ * 16 + M::row(grp, e);
+          const int pj = j < nb ? sp_in[j] : -1;
+          const bool live = pj >= 0;
+          valid |= live ? 1u << (4 * mt_ + e) : 0u;
+          const uint32_t row = live ? (uint32_t)pj * row_bytes : 0u;
+          const uint32_t flag = live ? 0u : 0x80000000u;
+#pragma unroll
+          for (int ot = 0; ot < OT; ++ot) {
+            const uint32_t off = (row + col_off[ot]) | flag | col_flag[ot];
+            tg[mt_][0][ot][e] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs_t0, off, 0, 0));
+            tg[mt_][1][ot][e] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs_t1, off, 0, 0));
+          }
+        }
+    };
+    Acc acc[4][OT];                                    // the cell's block gradient (adjoint)
+    double sq = 0.0;                                   // this lane's share of the cell's loss terms
+    A blk_cur[16][OT], blk_nxt[16][OT];
+    // forward, residuals and adjoint of one tile of 16 points of the current batch
+    auto tile = [&](int nb, int mt_, const A (*sw)[36], const A (&tg)[2][2][OT][4], uint32_t valid) {
+      Acc accf[2][OT];
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int ot = 0; ot < OT; ++ot) accf[c][ot] = Acc{};
+      {
+        // forward (as k_fwd_cells): lane col is point 16 mt + col, k-steps run over the block rows
+        const A* wp = sw[min(mt_ * 16 + col, nb - 1)];
+        A wx[4], dwx[4], d2wx[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          wx[i] = wp[i];
+          dwx[i] = wp[4 + i];
+          d2wx[i] = wp[8 + i];
+        }
+        const A wz = wp[24 + grp], dwz = wp[28 + grp], d2wz = wp[32 + grp];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const A wy = wp[12 + m], dwy = wp[16 + m], d2wy = wp[20 + m];
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            A q0, q1, q2;
+            term_factors<A>(c == 0 ? TERM_VAL : TERM_LAP, wy, dwy, d2wy, wz, dwz, d2wz, jm, mt, q0, q1, q2);
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+              // the value term: the vanishing Q1, Q2 products change no bit of q0 w_x (finite,
+              // non-negative weights)
+              const A av = c == 0 ? q0 * wx[l] : fmaa(q2, d2wx[l], fmaa(q1, dwx[l], q0 * wx[l]));
+#pragma unroll
+              for (int ot = 0; ot < OT; ++ot) accf[c][ot] = M::step(av, blk_cur[4 * l + m][ot], accf[c][ot]);
+            }
+          }
+        }
+      }
+      // residuals, loss terms and upstream gradient (as the fit terms); zero for points not written
+      A gd[2][OT][4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const bool ok = (valid >> (4 * mt_ + e)) & 1u;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int ot = 0; ot < OT; ++ot) {
+            const A res = accf[c][ot][e] - tg[mt_][c][ot][e];
+            if (ok && ocol[ot]) sq = fma(a.w[c] * (double)res, (double)res, sq);
+            gd[c][ot][e] = (ok && ocol[ot]) ? two_w[c] * res : A(0);
+          }
+      }
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int ot = 0; ot < OT; ++ot) transpose_groups(gd[c][ot]);
+      // adjoint (as k_bwd_bricks): k-step 4 mt + q takes points 16 mt + 4 q + (lane group)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int qs = mt_ * 16 + 4 * q;
+        if (qs >= nb) break;
+        const A* wp = sw[min(qs + grp, nb - 1)];
+        A wx[4], dwx[4], d2wx[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          wx[i] = wp[i];
+          dwx[i] = wp[4 + i];
+          d2wx[i] = wp[8 + i];
+        }
+        const A wy = wp[12 + m_], dwy = wp[16 + m_], d2wy = wp[20 + m_];
+        const A wz = wp[24 + n_], dwz = wp[28 + n_], d2wz = wp[32 + n_];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          A q0, q1, q2;
+          term_factors<A>(c == 0 ? TERM_VAL : TERM_LAP, wy, dwy, d2wy, wz, dwz, d2wz, jm, mt, q0, q1, q2);
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt) {
+            const A av = c == 0 ? q0 * wx[rt] : fmaa(q2, d2wx[rt], fmaa(q1, dwx[rt], q0 * wx[rt]));
+#pragma unroll
+            for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = M::step(av, gd[c][ot][q], acc[rt][ot]);
+          }
+        }
+      }
+    };
+    auto add_block = [&](int c) {
+      A* corner = s_reg + (((c >> 2) * 5 + ((c >> 1) & 1)) * 5 + (c & 1)) * WBW + wave * BW;
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = M::row(grp, e);
+          A* rp = corner + ((rt * 5 + (i >> 2)) * 5 + (i & 3)) * WBW;
+#pragma unroll
+          for (int ot = 0; ot < OT; ++ot) rp[16 * ot + col] += acc[rt][ot][e];
+        }
+    };
+
+    BrickBatch b0{0, 0};
+    while (b0.c < 8 && count_of(b0.c) == 0) ++b0.c;
+    BrickBatch b1 = b0;
+    advance(b1);
+    BrickBatch b2 = b1;
+    advance(b2);
+    BrickBatch b3 = b2;
+    advance(b3);
+    Staged sp0, sp_next, sp_after;
+    load_points(b0, sp0);
+    load_points(b1, sp_next);
+    load_points(b2, sp_after);
+    if (b0.c < 8) load_block(b0.c, blk_cur);
+    if (tid < 3 * CELL_PB) {
+      stage_index(b0, sp0, s_p[0]);
+      stage_weights(b0, sp0, s_w[0]);
+      stage_index(b1, sp_next, s_p[1]);
+    }
+    __syncthreads();
+    A tgq[2][2][2][OT][4];
+    uint32_t vq[2];
+    load_targets(count(b0), s_p[0], tgq[0], vq[0]);
+    auto step = [&](int buf, A (&tg_cur)[2][2][OT][4], uint32_t& v_cur, A (&tg_nxt)[2][2][OT][4], uint32_t& v_nxt) {
+      const int nb = count(b0);
+      load_targets(count(b1), s_p[buf ^ 1], tg_nxt, v_nxt);
+      const bool new_cell = b1.c < 8 && b1.b0 == 0;
+      if (new_cell) load_block(b1.c, blk_nxt);
+      if (tid < 3 * CELL_PB) {
+        stage_weights(b1, sp_next, s_w[buf ^ 1]);
+        stage_index(b2, sp_after, s_p[buf]);
+      }
+      sp_next = sp_after;
+      load_points(b3, sp_after);
+      if (b0.b0 == 0) {
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+          for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = Acc{};
+        sq = 0.0;
+      }
+      tile(nb, 0, s_w[buf], tg_cur, v_cur);
+      if (nb > 16) tile(nb, 1, s_w[buf], tg_cur, v_cur);
+      if (b0.b0 + CELL_PB >= count_of(b0.c)) {
+        add_block(b0.c);
+        // the cell's loss partial: the wave's sum in a fixed butterfly order (as the fit terms)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
+        const int run = run_of(b0.c);
+        if (lane == 0 && group < a.n_groups && run >= 0 && run < a.n_runs) a.partial[(int64_t)run * a.n_groups + group] = sq;
+      }
+      __syncthreads();
+      if (new_cell) {
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks)
+#pragma unroll
+          for (int ot = 0; ot < OT; ++ot) blk_cur[ks][ot] = blk_nxt[ks][ot];
+      }
+      b0 = b1;
+      b1 = b2;
+      b2 = b3;
+      advance(b3);
+    };
+    while (b0.c < 8) {
+      step(0, tgq[0], vq[0], tgq[1], vq[1]);
+      if (b0.c >= 8) break;
+      step(1, tgq[1], vq[1], tgq[0], vq[0]);
+    }
+    __syncthreads();
+    A* out = static_cast<A*>(a.blocks) + brick * BRICK_ROWS * a.o_pad + obw;
+    for (int i = tid; i < BRICK_ROWS * WBW; i += 64 * BRICK_WAVES) {
+      const int lrow = i / WBW, c = i % WBW;
+      if (obw + c < a.n_orb) out[(int64_t)lrow * a.o_pad + c] = s_reg[i];
+    }
+  }
+}
+
 // loss += the work items' partial sums, in a fixed order, in two steps.  First FIT_SUM_BLOCKS
 // workgroups: thread t of workgroup b sums the partials b T + t + k (FIT_SUM_BLOCKS T), then a fixed
 // tree in LDS gives block sum b.  Then one workgroup adds the block sums in a fixed tree to *loss,
@@ -1593,4 +1959,82 @@ int launch_eval_cells(const spl_desc* d, const void* table, int64_t n_pts, const
   return hip_fail(hipGetLastError(), "non-finite point launch");
 }
 
+int fit_gradient_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes) {
+  SortLayout L;
+  int rc = sort_layout(d, n_pts, &L, true, true);
+  if (rc) return rc;
+  *bytes = (int64_t)L.total;
+  return SPL_OK;
+}
+
+// The fit's data terms and their coefficient gradient in one pass (k_fit_bricks), then the per-row
+// gather of the brick regions and the loss sums.
+int launch_fit_gradient(const spl_desc* d, const void* table, int64_t n_pts, const double* pos, const void* t_v,
+                        double w_v, const void* t_lap, double w_lap, void* gtable, double* loss, void* work,
+                        int64_t work_bytes, bool reuse, hipStream_t stream) {
+  if (n_pts == 0) return SPL_OK;
+  if (d->dtype != SPL_F32 || d->has_lap)
+    return fail(SPL_EUNSUPPORTED, "the one-pass fit gradient covers FP32 tables with the Laplacian from derivatives");
+  const int64_t tgt = n_pts * (int64_t)d->n_orb * 4;
+  if (d->table_bytes >= ((int64_t)1 << 31) - 4096 || tgt >= ((int64_t)1 << 31) - 4096)
+    return fail(SPL_EUNSUPPORTED, "the one-pass fit gradient needs the table and each target array under 2 GiB");
+  SortLayout L;
+  int rc = sort_layout(d, n_pts, &L, true, true);
+  if (rc) return rc;
+  if (!L.dense)
+    return fail(SPL_EUNSUPPORTED, "the one-pass fit gradient needs at least 4 points per cell (%lld points, %lld cells)",
+                (long long)n_pts, (long long)L.n_cells);
+  if (!work || work_bytes < (int64_t)L.total)
+    return fail(SPL_EINVAL, "spline_fit_gradient_cells needs a workspace of %lld bytes", (long long)L.total);
+  CellSort cs;
+  if ((rc = cell_sort(d, n_pts, pos, work, L, reuse, stream, &cs))) return rc;
+  char* W = cs.base;
+  int32_t* cell_range = reinterpret_cast<int32_t*>(W + L.cell_range);
+  hipLaunchKernelGGL(k_bwd_fill_i32, dim3((unsigned)((3 * L.n_cells + 255) / 256)), dim3(256), 0, stream, cell_range,
+                     3 * L.n_cells, 0);
+  if ((rc = hip_fail(hipGetLastError(), "cell range clear launch"))) return rc;
+  const int max_runs = (int)std::min<int64_t>(n_pts, L.n_cells);
+  hipLaunchKernelGGL(k_cell_ranges, dim3((unsigned)((max_runs + 255) / 256)), dim3(256), 0, stream, cs.uniq,
+                     cs.counts, cs.offsets, cs.class_start, L.n_cells, (int32_t)L.n_classes, (int32_t)n_pts,
+                     cell_range);
+  if ((rc = hip_fail(hipGetLastError(), "cell range launch"))) return rc;
+  FitArgs a;
+  memset(&a, 0, sizeof(a));
+  a.g = make_geom(d);
+  a.table = static_cast<const float*>(table);
+  a.table_bytes = (int32_t)d->table_bytes;
+  a.target[0] = static_cast<const float*>(t_v);
+  a.target[1] = static_cast<const float*>(t_lap);
+  a.target_bytes[0] = a.target_bytes[1] = (int32_t)tgt;
+  a.w[0] = w_v;
+  a.w[1] = w_lap;
+  a.cell_range = cell_range;
+  a.pts = cs.pts;
+  a.blocks = W + L.blocks;
+  a.partial = reinterpret_cast<double*>(W + L.partials);
+  a.n_pts = (int32_t)n_pts;
+  a.n_orb = d->n_orb;
+  a.o_pad = d->o_pad;
+  a.n_groups = (d->n_orb + 31) / 32;                 // as the FP32 fit terms: 32 orbitals per work item
+  a.n_runs = max_runs;
+  const int64_t n_bricks = (int64_t)((d->grid[0] + 1) / 2) * ((d->grid[1] + 1) / 2) * ((d->grid[2] + 1) / 2);
+  const int64_t n_wg = (a.n_groups + BRICK_WAVES - 1) / BRICK_WAVES;
+  hipLaunchKernelGGL(k_fit_bricks, dim3((unsigned)std::min<int64_t>(n_bricks * n_wg, 1 << 16)),
+                     dim3(64 * BRICK_WAVES), 0, stream, a);
+  if ((rc = hip_fail(hipGetLastError(), "fit gradient launch"))) return rc;
+  const int gthreads = d->o_pad >= 256 ? 256 : (d->o_pad + 63) / 64 * 64;
+  hipLaunchKernelGGL(k_bwd_brick_gather<float>, dim3((unsigned)L.n_cells), dim3(gthreads), 0, stream, a.g,
+                     static_cast<const float*>(a.blocks), d->n_orb, d->o_pad, static_cast<float*>(gtable));
+  if ((rc = hip_fail(hipGetLastError(), "row gather launch"))) return rc;
+  // the loss: the same two fixed-order sums over the same partials as the fit terms
+  double* block_sum = a.partial + std::min<int64_t>(n_pts, L.n_cells) * (int64_t)((d->n_orb + 15) / 16);
+  hipLaunchKernelGGL(k_fit_blocks, dim3(FIT_SUM_BLOCKS), dim3(FIT_SUM_THREADS), 0, stream, cs.class_start,
+                     (int32_t)L.n_classes, a.n_pts, L.n_cells, a.n_groups, a.partial, block_sum);
+  if ((rc = hip_fail(hipGetLastError(), "fit block sums launch"))) return rc;
+  hipLaunchKernelGGL(k_fit_total, dim3(1), dim3(FIT_SUM_THREADS), 0, stream, block_sum, cs.keys, a.n_pts,
+                     (int64_t)L.n_classes * L.n_cells, loss);
+  return hip_fail(hipGetLastError(), "fit total launch");
+}
+
 }  // namespace pws
+

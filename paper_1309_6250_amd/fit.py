@@ -23,8 +23,9 @@ import math
 
 import torch
 
-from ._lib import SPL_DETERMINISTIC, SPL_REUSE_SORT
+from ._lib import SPL_DETERMINISTIC, SPL_F32, SPL_REUSE_SORT
 from .api import (OUT_TORCH, new_gtable, spline_eval_vgl_backward, spline_eval_vgl_cells, spline_fit_terms_cells,
+                  spline_fit_gradient_cells, spline_fit_gradient_work_bytes,
                   spline_misfit, spline_misfit_work_bytes, spline_smoothness_penalty, spline_cells_work_bytes,
                   spline_backward_work_bytes)
 from .autograd import SplineVGL
@@ -77,7 +78,13 @@ class FitProblem:
     """The fit's loss and its coefficient gradient at fixed points pos [P][3] with targets
     v_t, lap_t [P][n_orb], without autograd.  loss_and_grad(beta) returns (loss, grad) as
     device tensors (FP64 scalar; the gradient table, FP32 for FP32 and BF16 tables); both are
-    reused by the next call."""
+    reused by the next call.
+
+    fused: the misfit is formed inside the cell-wise forward; where spline_fit_gradient_cells
+    applies (FP32 table, Laplacian from derivatives, both terms, deterministic, at least 4 points per
+    cell, table and targets under 2 GiB) the forward, the misfit and the adjoint run as one pass,
+    with the same bits.  Otherwise, or with fused=False, the forward and spline_misfit write the
+    residual gradients, which the adjoint then reads."""
 
     def __init__(self, desc, pos, v_t, lap_t, lam=1e-3, use_lap=True, deterministic=True, fused=True):
         self.desc, self.pos, self.lam, self.use_lap, self.fused = desc, pos, lam, use_lap, fused
@@ -98,7 +105,13 @@ class FitProblem:
         # made by the first forward serves every later call (SPL_REUSE_SORT)
         self.misfit_work = torch.empty(spline_misfit_work_bytes(desc, n * o), dtype=torch.uint8, device=dev)
         self.reuse = deterministic
+        cells = desc.grid[0] * desc.grid[1] * desc.grid[2]
+        under = (1 << 31) - 4096
+        self.one_pass = (fused and deterministic and use_lap and desc.dtype == SPL_F32 and not desc.has_lap
+                         and n >= 4 * cells and desc.table_bytes < under and 4 * n * o < under)
         nb = max(spline_cells_work_bytes(desc, n), spline_backward_work_bytes(desc, n, self.flags))
+        if self.one_pass:
+            nb = max(nb, spline_fit_gradient_work_bytes(desc, n))
         self.work = torch.empty(max(1, nb), dtype=torch.uint8, device=dev)
         self.sorted = False
 
@@ -107,6 +120,16 @@ class FitProblem:
         self.loss.zero_()
         reuse = SPL_REUSE_SORT if self.sorted else 0
         lap = self.lap if self.use_lap else None
+        if self.one_pass:
+            # forward, misfit and adjoint of every batch of points in one kernel
+            self.gtable.zero_()
+            spline_fit_gradient_cells(d, beta, self.pos, self.v_t, self.w_v, self.lap_t, self.w_l, gtable=self.gtable,
+                                      loss=self.loss, work=self.work, flags=reuse)
+            self.sorted = True
+            if self.lam:
+                spline_smoothness_penalty(d, beta, self.reg_scale, self.loss, gtable=self.gtable,
+                                          work=self.misfit_work)
+            return self.loss, self.gtable
         if self.fused:
             # the residuals and their sum straight from the cell-wise evaluation
             gv, gl, _ = spline_fit_terms_cells(d, beta, self.pos, self.v_t, self.w_v,

@@ -154,6 +154,26 @@ int main(void) {
   expect(spline_fit_terms_cells(&d, fake, 0, fpos, fake, 1.0, fake, NULL, 0.0, NULL, fake, 0, NULL, 0, NULL), SPL_OK,
          "fit terms n == 0");
 
+  /* the fit's data terms and their gradient in one pass */
+  expect(spline_fit_gradient_work_bytes(&d, 0, &bytes), SPL_OK, "fit gradient work bytes");
+  expect(spline_fit_gradient_work_bytes(&d, 10, NULL), SPL_EINVAL, "fit gradient work bytes NULL");
+  expect(spline_fit_gradient_cells(&d, fake, 10, fpos, NULL, 1.0, fake, 1.0, fake, fake, 0, fake, 1 << 20, NULL),
+         SPL_EINVAL, "fit gradient without value target");
+  expect(spline_fit_gradient_cells(&d, fake, 10, fpos, fake, 1.0, fake, 1.0, NULL, fake, 0, fake, 1 << 20, NULL),
+         SPL_EINVAL, "fit gradient NULL gtable");
+  expect(spline_fit_gradient_cells(&d, fake, 10, fpos, fake, 1.0, fake, 1.0, fake, NULL, 0, fake, 1 << 20, NULL),
+         SPL_EINVAL, "fit gradient NULL loss");
+  expect(spline_fit_gradient_cells(&d, fake, 10, fpos, fake, 1.0, fake, 1.0, fake, fake, 0, NULL, 0, NULL),
+         SPL_EINVAL, "fit gradient NULL work");
+  expect(spline_fit_gradient_cells(&d, fake, 10, fpos, fake, 0.0 / 0.0, fake, 1.0, fake, fake, 0, fake, 1 << 20,
+                                   NULL), SPL_EINVAL, "fit gradient NaN weight");
+  expect(spline_fit_gradient_cells(&d, fake, 10, fpos, fake, 1.0, fake, 1.0, fake, fake, 4, fake, 1 << 20, NULL),
+         SPL_EINVAL, "fit gradient unknown flag");
+  expect(spline_fit_gradient_cells(&dp, fake, 10, fpos, fake, 1.0, fake, 1.0, fake, fake, 0, fake, 1 << 20, NULL),
+         SPL_EUNSUPPORTED, "fit gradient pp");
+  expect(spline_fit_gradient_cells(&d, fake, 0, fpos, fake, 1.0, fake, 1.0, fake, fake, 0, NULL, 0, NULL), SPL_OK,
+         "fit gradient n == 0");
+
   /* build */
   expect(spline_build(&d, fake, fake, fake, fake, NULL), SPL_EINVAL, "build lap values without lap table");
   expect(spline_build(&d32, fake, NULL, fake, fake, NULL), SPL_EINVAL, "build lap table without values");

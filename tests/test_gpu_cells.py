@@ -286,3 +286,97 @@ def test_cells_outputs_at_odd_offsets(dtype):
     for a, b in ((v, vo), (g, go), (l, lo), (gv, gvo), (gl, glo)):
         assert torch.equal(a.reshape(-1), b)
     assert float(loss) == float(loss_o)
+
+
+def _fit_gradient_reference(d, tab, x, tv, wv, tl, wl, loss0, gtable0):
+    """spline_fit_terms_cells, then the deterministic adjoint of its upstream gradients."""
+    loss = torch.full((1,), loss0, dtype=torch.float64, device=DEV)
+    gv, gl, _ = P.spline_fit_terms_cells(d, tab, x, tv, wv, tl, wl, loss=loss)
+    gt = gtable0.clone()
+    P.spline_eval_vgl_backward(d, tab, x, gv, None, gl, gt, None, want_pos=False, flags=P.SPL_DETERMINISTIC)
+    return gt, loss
+
+
+@pytest.mark.parametrize("n_orb", [45, 70, 128])
+def test_fit_gradient_one_pass_equals_terms_then_adjoint(n_orb):
+    """spline_fit_gradient_cells (forward, misfit and adjoint of each batch in one kernel) against
+    spline_fit_terms_cells followed by the deterministic adjoint: the coefficient gradient and the
+    loss, both accumulated into, bit for bit; again on a reused sort.  Clustered points, so cells hold
+    up to several batches of 32 and many cells and bricks none; a ragged grid; 45 orbitals leave a
+    partial orbital group, 70 a wave without one."""
+    rng = np.random.default_rng(131)
+    grid = (10, 8, 9)
+    beta = rng.standard_normal(grid + (n_orb,))
+    d = P.spline_desc_init(SKEW, grid, n_orb, "f32")
+    tab = table_from_oracle(d, beta, "f32")
+    centers = rng.uniform(0, 1, size=(6, 3))
+    n = 4 * int(np.prod(grid))
+    pos = ((centers[rng.integers(0, 6, n)] + rng.normal(0, 0.05, size=(n, 3))) % 1.0) @ SKEW
+    x = to_dev(pos)
+    tv = to_dev(rng.standard_normal((n, n_orb)), torch.float32)
+    tl = to_dev(5.0 * rng.standard_normal((n, n_orb)), torch.float32)
+    wv, wl = 0.37, 0.011
+    g0 = to_dev(rng.standard_normal(P.table_shape(d)), torch.float32)
+    say("one-pass fit gradient", grid, n_orb, n)
+    rgt, rloss = _fit_gradient_reference(d, tab, x, tv, wv, tl, wl, 0.25, g0)
+    work = torch.empty(P.spline_fit_gradient_work_bytes(d, n), dtype=torch.uint8, device=DEV)
+    outs = []
+    for flags in (0, P.SPL_REUSE_SORT):
+        gt = g0.clone()
+        loss = torch.full((1,), 0.25, dtype=torch.float64, device=DEV)
+        P.spline_fit_gradient_cells(d, tab, x, tv, wv, tl, wl, gtable=gt, loss=loss, work=work, flags=flags)
+        outs.append((gt, loss))
+    torch.cuda.synchronize()
+    for gt, loss in outs:
+        assert torch.equal(gt, rgt)
+        assert float(loss) == float(rloss)
+
+
+@pytest.mark.timeout(600)
+def test_fit_gradient_one_pass_at_fit_size():
+    """The 64-atom fit workload (10^6 points, 128 orbitals, 32^3 FP32 table): one pass equals fit terms
+    then adjoint bit for bit, gradient and loss."""
+    w = config(4)
+    s = w.system
+    x = to_dev(w.positions())
+    n = x.shape[0]
+    d = P.spline_desc_init(s.lattice, s.grid, s.n_orb, "f32")
+    tab = P.spline_build(d, to_dev(s.grid_values()))
+    g = torch.Generator(device=DEV).manual_seed(132)
+    tv = torch.randn((n, s.n_orb), device=DEV, generator=g)
+    tl = 10.0 * torch.randn((n, s.n_orb), device=DEV, generator=g)
+    g0 = torch.zeros(P.table_shape(d), dtype=torch.float32, device=DEV)
+    say("one-pass fit gradient at fit size")
+    rgt, rloss = _fit_gradient_reference(d, tab, x, tv, 1.0, tl, 1e-3, 0.0, g0)
+    gt, loss = P.spline_fit_gradient_cells(d, tab, x, tv, 1.0, tl, 1e-3)
+    torch.cuda.synchronize()
+    assert torch.equal(gt, rgt)
+    assert float(loss) == float(rloss)
+
+
+def test_fit_gradient_one_pass_nonfinite_and_unsupported():
+    """A non-finite point makes the loss NaN and leaves the gradient equal to the two-kernel path's;
+    FP64 tables, a separate Laplacian table and sparse points are refused with SPL_EUNSUPPORTED."""
+    rng = np.random.default_rng(133)
+    grid, n_orb, n = (6, 5, 7), 33, 1500
+    d = P.spline_desc_init(SKEW, grid, n_orb, "f32")
+    tab = table_from_oracle(d, rng.standard_normal(grid + (n_orb,)), "f32")
+    pos = rng.uniform(0, 1, size=(n, 3)) @ SKEW
+    pos[7] = [np.nan, 0.0, 0.0]
+    x = to_dev(pos)
+    tv = to_dev(rng.standard_normal((n, n_orb)), torch.float32)
+    tl = to_dev(rng.standard_normal((n, n_orb)), torch.float32)
+    g0 = torch.zeros(P.table_shape(d), dtype=torch.float32, device=DEV)
+    say("one-pass fit gradient, non-finite point and refusals")
+    rgt, rloss = _fit_gradient_reference(d, tab, x, tv, 1.0, tl, 0.5, 0.0, g0)
+    gt, loss = P.spline_fit_gradient_cells(d, tab, x, tv, 1.0, tl, 0.5)
+    torch.cuda.synchronize()
+    assert math.isnan(float(loss)) and math.isnan(float(rloss))
+    assert torch.equal(gt, rgt)
+    for dd, nn in ((P.spline_desc_init(SKEW, grid, n_orb, "f64"), n),
+                   (P.spline_desc_init(SKEW, grid, n_orb, "f32", has_lap=True), n), (d, 100)):
+        od = torch.float64 if dd.dtype == P.SPL_F64 else torch.float32
+        tt = torch.zeros((nn, n_orb), dtype=od, device=DEV)
+        with pytest.raises(P.SplineError) as err:
+            P.spline_fit_gradient_cells(dd, P.new_table(dd), x[:nn], tt, 1.0, tt, 1.0)
+        assert err.value.code == P.SPL_EUNSUPPORTED

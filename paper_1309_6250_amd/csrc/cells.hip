@@ -1609,9 +1609,11 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) __attribute__((amdgpu_waves_per_e
     };
     Acc acc[4][OT];                                    // the cell's block gradient (adjoint)
     double sq = 0.0;                                   // this lane's share of the cell's loss terms
-    A blk_cur[16][OT], blk_nxt[16][OT];
-    // forward, residuals and adjoint of one tile of 16 points of the current batch
-    auto tile = [&](int nb, int mt_, const A (*sw)[36], const A (&tg)[2][2][OT][4], uint32_t valid) {
+    A blk[16][OT];                                     // the current cell's block
+    // forward, residuals and adjoint of one tile of 16 points of the current batch; next_cell >= 0:
+    // this is the cell's last tile, and once its forward products are issued, the block registers
+    // take the next cell's block (its loads overlap the residuals and the adjoint)
+    auto tile = [&](int nb, int mt_, const A (*sw)[36], const A (&tg)[2][2][OT][4], uint32_t valid, int next_cell) {
       Acc accf[2][OT];
 #pragma unroll
       for (int c = 0; c < 2; ++c)
@@ -1641,11 +1643,12 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) __attribute__((amdgpu_waves_per_e
               // non-negative weights)
               const A av = c == 0 ? q0 * wx[l] : fmaa(q2, d2wx[l], fmaa(q1, dwx[l], q0 * wx[l]));
 #pragma unroll
-              for (int ot = 0; ot < OT; ++ot) accf[c][ot] = M::step(av, blk_cur[4 * l + m][ot], accf[c][ot]);
+              for (int ot = 0; ot < OT; ++ot) accf[c][ot] = M::step(av, blk[4 * l + m][ot], accf[c][ot]);
             }
           }
         }
       }
+      if (next_cell >= 0) load_block(next_cell, blk);
       // residuals, loss terms and upstream gradient (as the fit terms); zero for points not written
       A gd[2][OT][4];
 #pragma unroll
@@ -1717,7 +1720,7 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) __attribute__((amdgpu_waves_per_e
     load_points(b0, sp0);
     load_points(b1, sp_next);
     load_points(b2, sp_after);
-    if (b0.c < 8) load_block(b0.c, blk_cur);
+    if (b0.c < 8) load_block(b0.c, blk);
     if (tid < 3 * CELL_PB) {
       stage_index(b0, sp0, s_p[0]);
       stage_weights(b0, sp0, s_w[0]);
@@ -1730,8 +1733,8 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) __attribute__((amdgpu_waves_per_e
     auto step = [&](int buf, A (&tg_cur)[2][2][OT][4], uint32_t& v_cur, A (&tg_nxt)[2][2][OT][4], uint32_t& v_nxt) {
       const int nb = count(b0);
       load_targets(count(b1), s_p[buf ^ 1], tg_nxt, v_nxt);
-      const bool new_cell = b1.c < 8 && b1.b0 == 0;
-      if (new_cell) load_block(b1.c, blk_nxt);
+      const bool last = b0.b0 + CELL_PB >= count_of(b0.c);     // b0 ends its cell
+      const int next_cell = last && b1.c < 8 ? b1.c : -1;
       if (tid < 3 * CELL_PB) {
         stage_weights(b1, sp_next, s_w[buf ^ 1]);
         stage_index(b2, sp_after, s_p[buf]);
@@ -1745,9 +1748,9 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) __attribute__((amdgpu_waves_per_e
           for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = Acc{};
         sq = 0.0;
       }
-      tile(nb, 0, s_w[buf], tg_cur, v_cur);
-      if (nb > 16) tile(nb, 1, s_w[buf], tg_cur, v_cur);
-      if (b0.b0 + CELL_PB >= count_of(b0.c)) {
+      tile(nb, 0, s_w[buf], tg_cur, v_cur, nb > 16 ? -1 : next_cell);
+      if (nb > 16) tile(nb, 1, s_w[buf], tg_cur, v_cur, next_cell);
+      if (last) {
         add_block(b0.c);
         // the cell's loss partial: the wave's sum in a fixed butterfly order (as the fit terms)
 #pragma unroll
@@ -1756,12 +1759,6 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) __attribute__((amdgpu_waves_per_e
         if (lane == 0 && group < a.n_groups && run >= 0 && run < a.n_runs) a.partial[(int64_t)run * a.n_groups + group] = sq;
       }
       __syncthreads();
-      if (new_cell) {
-#pragma unroll
-        for (int ks = 0; ks < 16; ++ks)
-#pragma unroll
-          for (int ot = 0; ot < OT; ++ot) blk_cur[ks][ot] = blk_nxt[ks][ot];
-      }
       b0 = b1;
       b1 = b2;
       b2 = b3;

@@ -412,15 +412,15 @@ def oracle_parity(outs, parity, dtype):
     return {name: normwise(g, r) for name, g, r in zip(("V", "grad", "lap"), got, ref)}
 
 
-def traffic_for(form_key):
-    """Measured HBM bytes per launch from the committed rocprof counter summary, or None when the
-    kernel sources changed since the counters were taken."""
+def traffic_for(form_key, tile):
+    """Measured HBM bytes per launch from the committed rocprof counter summary for this form at this
+    tile, or None when the counters were taken at another tile or the kernel sources changed since."""
     try:
         with open(PROFILE_TRAFFIC) as fh:
             data = json.load(fh)
     except (OSError, ValueError):
         return None
-    ent = data.get("forms", {}).get(form_key)
+    ent = data.get("forms", {}).get(f"{form_key}@{tile[0]},{tile[1]}")
     if not ent or ent.get("kernel_hash") != kernel_hash():
         return None
     return ent.get("bytes_per_launch")
@@ -875,12 +875,12 @@ def main():
     if parity is not None:
         head["vs_oracle"] = oracle_parity(o2, parity, "f64")
     per_launch = head["alg_bytes_per_sweep"]
-    traffic = traffic_for("c2-f64")
+    traffic = traffic_for("c2-f64", head["tile"])
     roofline = {"bound": "hbm", "achieved": head["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": head["alg_GBps"] / HBM_PEAK_GBS, "traffic": traffic,
                 "traffic_source": "not measured in this run: rocprofv3 FETCH_SIZE + WRITE_SIZE per launch from "
-                                  "profiles/traffic.json, scaled by a 1 GiB copy; null when the kernel sources "
-                                  "changed since",
+                                  "profiles/traffic.json at this tile, scaled by a 1 GiB copy; null when taken at "
+                                  "another tile or the kernel sources changed since",
                 "kernel": "k_eval (spline_eval_vgl, FP64 table, VGL)", "tile": head["tile"],
                 "alg_bytes_per_launch": per_launch,
                 "per_unit": "552 B per orbital-VGL (64 x 8 B coefficients + 5 x 8 B outputs) + 24 B per point",
@@ -910,7 +910,7 @@ def main():
             rec["speedup_vs_f64"] = rec["evals_per_s"] / f64_rate[lap]
             if parity is not None and not lap:
                 rec["vs_oracle"] = oracle_parity(o, parity, dtype)
-            rec["traffic"] = traffic_for(name)
+            rec["traffic"] = traffic_for(name, rec["tile"])
             forms[name] = rec
             log(f"{name}: {rec['evals_per_s']:.3e} evals/s, {rec['alg_GBps']:.0f} GB/s "
                 f"({100 * rec['frac_hbm_peak']:.1f}% of HBM peak)")
@@ -943,7 +943,7 @@ def main():
                 rec, d, t, o = run_form(wl2, dtype, True, args.steps, args.warmup, sep=basis, fields=fields)
                 name = f"c2-{dtype}-sep-{basis}"
                 rec["accuracy"] = accuracy(wl2, dtype, "separate_" + basis, o)
-                rec["traffic"] = traffic_for(name)
+                rec["traffic"] = traffic_for(name, rec["tile"])
                 forms[name] = rec
                 log(f"{name}: {rec['evals_per_s']:.3e} evals/s, {rec['alg_GBps']:.0f} GB/s "
                     f"({100 * rec['frac_hbm_peak']:.1f}% of HBM peak)")
@@ -959,7 +959,7 @@ def main():
             rec, d, t, o = run_form(wl2, dtype, False, args.steps, args.warmup, basis="pp")
             name = f"c2-{dtype}-pp"
             rec["accuracy"] = accuracy(wl2, dtype, "pp", o)
-            rec["traffic"] = traffic_for(name)
+            rec["traffic"] = traffic_for(name, rec["tile"])
             forms[name] = rec
             log(f"{name}: {rec['evals_per_s']:.3e} evals/s, {rec['alg_GBps']:.0f} GB/s "
                 f"({100 * rec['frac_hbm_peak']:.1f}% of HBM peak)")
@@ -979,7 +979,7 @@ def main():
                 rec, d, t, o = run_form(wl, dtype, False, args.steps, args.warmup)
                 name = f"c{key}-{dtype}" + ("-bloch" if bloch else "")
                 rec["accuracy"] = accuracy(wl, dtype, "bloch" if bloch else "derivative", o)
-                rec["traffic"] = traffic_for(name)
+                rec["traffic"] = traffic_for(name, rec["tile"])
                 if dtype == "f64":
                     base = rec["evals_per_s"]
                 rec["speedup_vs_f64"] = rec["evals_per_s"] / base

@@ -711,8 +711,10 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) void k_bwd_bricks(CellArgs a) {
         A bcur[NB][OT];
         load_step(nb, sp_in, 0, bcur);
         for (int q = 0; q < nb; q += 4) {
+          // unconditional: past the batch every lane is dead and reads 0 (a conditional load into
+          // these loop-carried registers would make the compiler wait for it at once)
           A bnext[NB][OT];
-          if (q + 4 < nb) load_step(nb, sp_in, q + 4, bnext);
+          load_step(nb, sp_in, q + 4, bnext);
           multiply_step(nb, q, sw, bcur);
 #pragma unroll
           for (int c = 0; c < NB; ++c)

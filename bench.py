@@ -66,26 +66,6 @@ def bytes_per_eval(dtype, n_tables=1, cols=1):
     return cols * (64 * STORE_BYTES[dtype] * n_tables + 5 * out)
 
 
-def time_launches_cold(fn, steps, flush_bytes=512 << 20):
-    """Average ms of fn() with the Infinity Cache flushed before each call: a 512 MB buffer is
-    rewritten between calls, and only fn() sits between the two events."""
-    import torch
-    buf = torch.empty(flush_bytes // 4, dtype=torch.float32, device="cuda")
-    total = 0.0
-    for i in range(steps + 1):
-        buf.fill_(float(i))
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        fn()
-        e1.record()
-        torch.cuda.synchronize()
-        if i > 0:
-            total += e0.elapsed_time(e1)
-    del buf
-    return total / steps
-
-
 def time_launches(fn, steps, warmup):
     """Average ms per call of fn() over `steps` calls, HIP events on torch's current stream
     (the stream the library launches on), bracketed by device synchronizations."""

@@ -12,15 +12,13 @@
 // block rows and its points (row weights from the 1-D B-spline weights), done on the matrix cores.
 //
 // Adjoint.  The gradient of a coefficient is a sum over every point whose 4x4x4 block contains it;
-// float atomics would make its order, and so its rounding, depend on scheduling.  Here each cell's
-// block is formed in point order and then added to the table either
-//  - colour class by colour class: along an axis of N cells, cell i has colour i mod 4 when
-//    i < 4 floor(N/4), and a colour of its own (4, 5, 6) for the last N mod 4 cells.  Two cells
-//    of one class are at least 4 apart along every axis, also across the periodic wrap, so
-//    their blocks (rows i-1 .. i+2) are disjoint: within a class no two waves touch the same
-//    row, and classes run one after the other; or
-//  - with 4 or more points per cell, all cells at once into the workspace, followed by a gather
-//    in which every table row sums the blocks that contain it in a fixed order.
+// float atomics would make its order, and so its rounding, depend on scheduling.  Here every sum
+// is formed in a fixed order, either
+//  - with 4 or more points per cell, cell by cell: each cell's block in point order, summed per
+//    brick of 2 x 2 x 2 cells into the workspace, followed by a gather in which every table row
+//    sums the brick regions that contain it in a fixed order; or
+//  - with fewer, tile by tile: each tile of 4 x 4 x 4 rows sums the points of the cells whose
+//    blocks reach it, in cell and point order, and adds the sum to its rows once.
 // Either way the result is reproducible bit for bit.
 //
 // Forward.  A wave loads a cell's block once and multiplies it with the row weights of the
@@ -113,7 +111,8 @@ static int sort_layout(const spl_desc* d, int64_t n_pts, SortLayout* L, bool adj
   const size_t n_bricks = (size_t)((d->grid[0] + 1) / 2) * ((d->grid[1] + 1) / 2) * ((d->grid[2] + 1) / 2);
   const size_t block_bytes = n_bricks * 125 * (size_t)d->o_pad * gsz;
   L->dense = adjoint_blocks && n_pts >= 4 * L->n_cells && block_bytes <= ((size_t)4 << 30);
-  L->cell_range = off; off = align_up(off + (L->dense ? 12 * (size_t)L->n_cells : 0));
+  // every cell's sorted point range: the adjoint's brick and row-tile forms both look cells up
+  L->cell_range = off; off = align_up(off + (adjoint_blocks ? 12 * (size_t)L->n_cells : 0));
   L->blocks = off; off = align_up(off + (L->dense ? block_bytes : 0));
   // the fit terms: one FP64 partial sum per work item, at most min(n, cells) runs times the 16-orbital
   // tiles, then one per workgroup of the first summing step (FIT_SUM_BLOCKS)
@@ -205,9 +204,9 @@ struct CellArgs {
   int32_t n_pts;           // every index read from the sort is checked against this and n_cells
   int32_t o_pad;
   void* blocks;              // dense: [n_bricks][125][o_pad] gradient regions of the bricks of 2 x 2 x 2 cells
-  const int32_t* cell_range; // dense: [n_cells][3] first sorted point, count (0 if empty) and run of each cell
-  int32_t src_bytes[5];      // dense: bytes of each term's upstream array from src[c] to its last value, or
-                             // -1 when one reaches 2 GiB (then the brick kernel uses 64-bit addresses)
+  const int32_t* cell_range; // [n_cells][3] first sorted point, count (0 if empty) and run of each cell
+  int32_t src_bytes[5];      // bytes of each term's upstream array from src[c] to its last value, or -1
+                             // when one reaches 2 GiB (then the brick and tile kernels use 64-bit addresses)
 };
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -255,208 +254,9 @@ __device__ __forceinline__ void term_factors(int kind, A wy, A dwy, A d2wy, A wz
   }
 }
 
-// One wave per (occupied cell of the colour class, group of 16 OT orbitals).  For a cell the
-// gradient of its 64 rows is a dense product
-//     d beta[row][o] += sum over (point, term) W_term(point)[row] g_term[point][o],
-// done on the matrix cores: 4 row tiles of 16 (row = 16 l + 4 m + n for the block offsets
-// l, m, n) times OT orbital tiles of 16, with K running over (point, term) pairs four points at
-// a time (lane group k of the wave takes point 4q + k).
-//
-// The cell's points arrive as sorted records (reduced coordinates and index, one coalesced
-// load) in batches of at most CELL_PB; their 1-D weights go to LDS once per point.  With at
-// most two terms (NT = 2: the fit's value and Laplacian) all upstream values of a batch are
-// loaded at once; with more, those of the next four points are loaded while the current ones
-// are multiplied.  The update of the 64 rows loads every old value before it stores.  The
-// summation order is fixed by the sorted point order, so the result is reproducible bit for bit.
+// The adjoint's points are taken in batches: a batch's point records and 1-D weights are staged in
+// LDS once and shared by the waves of a workgroup, four points per matrix-core step.
 constexpr int CELL_PB = 32;         // most points per batch
-
-// The gradient block of one cell: the sum over its points (sorted positions start .. start + cnt - 1,
-// in that order) of every term's row weights times its upstream values, for the orbitals
-// ob + 16 ot + col, into acc (4 row tiles of 16 rows x OT orbital tiles).  s_p and s_w are the
-// wave's LDS staging of a batch's point indices and 1-D weights.
-template <typename A, int OT, int NT>
-__device__ __forceinline__ void cell_block(const CellArgs& a, int start, int cnt, int ob, const bool (&ocol)[OT],
-                                           const A (&jm)[9], const A (&mt)[6], int* s_p, A (*s_w)[36],
-                                           typename Mfma<A>::acc (&acc)[4][OT]) {
-  using M = Mfma<A>;
-  using Acc = typename M::acc;
-  const int lane = (int)threadIdx.x & 63;            // the lane's role in the matrix-core steps
-  const int grp = lane >> 4;
-  const int col = lane & 15;
-  const int m_ = col >> 2, n_ = col & 3;
-  const int nt = a.n_terms;
-  const SortedPoint<A>* pts = static_cast<const SortedPoint<A>*>(a.pts);
-#pragma unroll
-  for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-    for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = Acc{};
-
-  for (int b0 = 0; b0 < cnt; b0 += CELL_PB) {
-    const int nb = min(CELL_PB, cnt - b0);
-    __syncthreads();                                   // every wave has consumed the previous batch
-    if ((int)threadIdx.x < nb) {                       // the first wave stages the batch for all waves
-      const int j = (int)threadIdx.x;
-      const SortedPoint<A> sp = pts[start + b0 + j];
-      s_p[j] = (unsigned)sp.p < (unsigned)a.n_pts ? sp.p : -1;   // -1: contributes nothing
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        A w4[4], d4[4], dd4[4];
-        bspline_weights<A>(sp.t[ax], w4, d4, dd4);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          s_w[j][12 * ax + i] = w4[i];
-          s_w[j][12 * ax + 4 + i] = d4[i];
-          s_w[j][12 * ax + 8 + i] = dd4[i];
-        }
-      }
-    }
-    __syncthreads();
-    // upstream values of lane group k's point 4q + k, for terms c0 .. c0 + NC - 1 and every orbital tile
-    auto load_b = [&](int q, auto& bv) {
-      constexpr int NC = sizeof(bv) / sizeof(bv[0]);
-      const int j = q + grp;
-      const int pj = j < nb ? s_p[j] : -1;
-      const bool live = pj >= 0;
-      const int64_t p = live ? (int64_t)pj : 0;
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int ot = 0; ot < OT; ++ot) {
-          const A* src = static_cast<const A*>(a.src[c]);
-          bv[c][ot] = (c < nt && live && ocol[ot]) ? src[p * a.src_stride[c] + ob + ot * 16 + col] : A(0);
-        }
-    };
-    // the products of one step of four points: every term's row weights times its upstream values
-    auto multiply = [&](int q, const auto& bv) {
-      constexpr int NC = sizeof(bv) / sizeof(bv[0]);
-      const A* wp = s_w[min(q + grp, nb - 1)];        // a dead lane group multiplies zeros
-      A wx[4], dwx[4], d2wx[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        wx[i] = wp[i];
-        dwx[i] = wp[4 + i];
-        d2wx[i] = wp[8 + i];
-      }
-      const A wy = wp[12 + m_], dwy = wp[16 + m_], d2wy = wp[20 + m_];
-      const A wz = wp[24 + n_], dwz = wp[28 + n_], d2wz = wp[32 + n_];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        if (c >= nt) break;
-        // row weight of this term: Q0 w_x + Q1 w_x' + Q2 w_x'' on the lane's (m, n), per row tile l
-        A q0, q1, q2;
-        term_factors<A>(a.kind[c], wy, dwy, d2wy, wz, dwz, d2wz, jm, mt, q0, q1, q2);
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-          const A av = fmaa(q2, d2wx[rt], fmaa(q1, dwx[rt], q0 * wx[rt]));
-#pragma unroll
-          for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = M::step(av, bv[c][ot], acc[rt][ot]);
-        }
-      }
-    };
-    if constexpr (NT <= 2) {
-      // at most two terms: the whole batch's upstream values are loaded at once
-      A bq[CELL_PB / 4][NT][OT];
-#pragma unroll
-      for (int qi = 0; qi < CELL_PB / 4; ++qi) load_b(4 * qi, bq[qi]);
-#pragma unroll
-      for (int qi = 0; qi < CELL_PB / 4; ++qi)
-        if (4 * qi < nb) multiply(4 * qi, bq[qi]);
-    } else {
-      // up to five terms: the next step's values are loaded while the current ones are multiplied
-      A bcur[5][OT];
-      load_b(0, bcur);
-      for (int q = 0; q < nb; q += 4) {
-        A bnext[5][OT];
-        if (q + 4 < nb) load_b(q + 4, bnext);
-        multiply(q, bcur);
-#pragma unroll
-        for (int c = 0; c < 5; ++c)
-#pragma unroll
-          for (int ot = 0; ot < OT; ++ot) bcur[c][ot] = bnext[c][ot];
-      }
-    }
-  }
-}
-
-// Sparse points: one wave per (occupied cell of the colour class, group of 16 OT orbitals).  For a
-// cell the gradient of its 64 rows is a dense product
-//     d beta[row][o] += sum over (point, term) W_term(point)[row] g_term[point][o],
-// done on the matrix cores: 4 row tiles of 16 (row = 16 l + 4 m + n for the block offsets
-// l, m, n) times OT orbital tiles of 16, with K running over (point, term) pairs four points at
-// a time (lane group k of the wave takes point 4q + k).
-//
-// The cell's points arrive as sorted records (reduced coordinates and index, one coalesced
-// load) in batches of at most CELL_PB; their 1-D weights go to LDS once per point.  With at
-// most two terms (NT = 2: the fit's value and Laplacian) all upstream values of a batch are
-// loaded at once; with more, those of the next four points are loaded while the current ones
-// are multiplied.  The update of the 64 rows loads every old value before it stores.  The
-// summation order is fixed by the sorted point order, so the result is reproducible bit for bit.
-template <typename A, int OT, int NT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_bwd_cells(CellArgs a) {
-  using M = Mfma<A>;
-  using Acc = typename M::acc;
-  constexpr int BW = 16 * OT;                        // orbitals of a wave
-  __shared__ int s_p[CELL_PB];
-  __shared__ A s_w[CELL_PB][36];                     // per point: x, y, z  x  (w[4], w'[4], w''[4])
-  const int lane = (int)threadIdx.x;
-  const int grp = lane >> 4;
-  const int col = lane & 15;
-  // run range, bounded so that a workspace holding anything else still stays inside the arrays
-  const int r0 = min(max(a.class_start[a.cls], 0), a.n_pts);
-  const int r1 = min(max(a.class_start[a.cls + 1], r0), a.n_pts);
-  const int64_t n_work = (int64_t)(r1 - r0) * a.n_groups;
-  A* gtab = static_cast<A*>(a.gtable);
-  A jm[9], mt[6];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) jm[i] = (A)a.g.jac[i];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) mt[i] = (A)a.g.metric[i];
-
-  for (int64_t w = blockIdx.x; w < n_work; w += gridDim.x) {
-    const int r = r0 + (int)(w / a.n_groups);
-    const int ob = (int)(w % a.n_groups) * BW;
-    const int64_t cell = a.uniq[r] % a.n_cells;         // key = class n_cells + cell
-    const int start = a.offsets[r];
-    const int cnt = a.counts[r];
-    if (cell < 0 || start < 0 || cnt < 0 || start > a.n_pts - cnt) continue;
-    const int iz0 = (int)(cell % a.g.n[2]);
-    const int iy0 = (int)((cell / a.g.n[2]) % a.g.n[1]);
-    const int ix0 = (int)(cell / ((int64_t)a.g.n[2] * a.g.n[1]));
-    int ix[4], iy[4], iz[4];
-    wrap4(ix0, a.g.n[0], ix);
-    wrap4(iy0, a.g.n[1], iy);
-    wrap4(iz0, a.g.n[2], iz);
-    // this cell's block: no other wave of the class touches these rows
-    bool ocol[OT];
-#pragma unroll
-    for (int ot = 0; ot < OT; ++ot) ocol[ot] = ob + ot * 16 + col < a.n_orb;
-    auto row_ptr = [&](int rt, int e) {
-      const int i = M::row(grp, e);                      // 4 m + n within the row tile
-      return gtab + (int64_t)ix[rt] * a.g.s0 + (int64_t)iy[i >> 2] * a.g.s1 + (int64_t)iz[i & 3] * a.g.o_pad + ob + col;
-    };
-    Acc acc[4][OT];
-    cell_block<A, OT, NT>(a, start, cnt, ob, ocol, jm, mt, s_p, s_w, acc);
-    // every old value is loaded before the first store: one memory latency for the update
-    A old[4][4][OT];
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const A* rp = row_ptr(rt, e);
-#pragma unroll
-        for (int ot = 0; ot < OT; ++ot) old[rt][e][ot] = ocol[ot] ? rp[16 * ot] : A(0);
-      }
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        A* rp = row_ptr(rt, e);
-#pragma unroll
-        for (int ot = 0; ot < OT; ++ot)
-          if (ocol[ot]) rp[16 * ot] = old[rt][e][ot] + acc[rt][ot][e];
-      }
-  }
-}
 
 // Dense points (4 or more per cell): the cells are taken in bricks of 2 x 2 x 2 (the last brick of
 // an axis with an odd count holds one cell along it).  The blocks of a brick's cells cover a
@@ -474,8 +274,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 // threads (one per point and axis) hold the sorted-point records of the next two batches in
 // registers, loaded while the batch before is multiplied, and stage each batch's indices and 1-D
 // weights in LDS; and (with at most two terms) every wave loads the next batch's upstream values
-// before it multiplies the current one.  Each batch is multiplied exactly as in cell_block, so the
-// sums are the same.
+// before it multiplies the current one.
 constexpr int BRICK_ROWS = 125;
 constexpr int BRICK_WAVES = 4;
 
@@ -671,8 +470,7 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) void k_bwd_bricks(CellArgs a) {
       for (int qi = 0; qi < NQB; ++qi) load_step(nb, sp_in, 4 * qi, bv[qi]);
     };
     Acc acc[4][OT];
-    // the products of one step of four points (as cell_block): every term's row weights times its
-    // upstream values
+    // the products of one step of four points: every term's row weights times its upstream values
     auto multiply_step = [&](int nb, int q, const A (*sw)[36], const A (&bv)[NB][OT]) {
       const A* wp = sw[min(q + grp, nb - 1)];         // a dead lane group multiplies zeros
       A wx[4], dwx[4], d2wx[4];
@@ -868,6 +666,322 @@ __global__ __launch_bounds__(256) void k_bwd_brick_gather(Geom g, const A* regio
   }
 }
 
+// Sparse points (fewer than 4 per cell on average): the gradient formed row-tile by row-tile.  Along
+// an axis a point of cell i touches rows i - 1 .. i + 2 (Eq. b-splineapproximation), so row X
+// receives the points of cells X - 2 .. X + 1, and a tile of 4 x 4 x 4 rows those of a window of
+// 7 x 7 x 7 cells (the whole axis when it has fewer than 7 cells; the last tile of an axis holds
+// its last N mod 4 rows, or 4).  One workgroup per (tile, group of TILE_WAVES x 16 OT orbitals)
+// forms the tile's gradient as one dense product on the matrix cores,
+//     d beta[row][o] = sum over the window's points and the terms of W_term(point)[row] g_term[point][o],
+// where a point's 1-D weights are moved onto the tile rows they land on (0 on a tile row outside
+// its support), and adds it to the table once.  Every row belongs to one workgroup: no atomics,
+// no colour classes, one launch, and a fixed order of every sum (window cells in order, each
+// cell's points in sorted order).  Each point is multiplied with the whole tile, so the matrix
+// cores do about (7/4)^3 times the useful products; with under 4 points per cell that costs less
+// than reading and writing the table rows once per cell.
+//
+// The window's points are taken in batches of CELL_PB across cell boundaries (slot q of the window
+// is found by a binary search over the prefix sums of its cells' counts), with the pipeline of the
+// brick kernel: the records of later batches load while the current batch is multiplied, their
+// weights and indices are staged in a second LDS buffer, and (with at most two terms) every wave
+// loads the next batch's upstream values before it multiplies the current one.
+constexpr int TILE_WAVES = 4;
+constexpr int TILE_WIN = 7;                               // window cells per axis (at most)
+constexpr int TILE_WIN3 = TILE_WIN * TILE_WIN * TILE_WIN;
+
+template <typename A>
+__device__ __forceinline__ A select4(int l, A a0, A a1, A a2, A a3) {
+  return l == 0 ? a0 : (l == 1 ? a1 : (l == 2 ? a2 : a3));
+}
+
+template <typename A, int OT, int NT, bool BUF>
+__global__ __launch_bounds__(64 * TILE_WAVES) void k_bwd_tiles(CellArgs a) {
+  using M = Mfma<A>;
+  using Acc = typename M::acc;
+  constexpr int BW = 16 * OT;                          // orbitals of a wave
+  constexpr int WBW = TILE_WAVES * BW;                 // orbitals of a workgroup
+  constexpr int NQ = CELL_PB / 4;                      // steps of four points in a full batch
+  constexpr int NB = NT <= 2 ? NT : 5;                 // upstream values per point and orbital tile
+  constexpr bool AHEAD = NT <= 2;                      // next batch's upstream values loaded ahead
+  constexpr int NQB = AHEAD ? NQ : 1;
+  static_assert(2 * 64 * TILE_WAVES >= TILE_WIN3, "two window cells per thread");
+  __shared__ int s_start[TILE_WIN3];                   // first sorted point of each window cell
+  __shared__ int s_pre[TILE_WIN3 + 1];                 // points of the window cells before each
+  __shared__ int s_wsum[TILE_WAVES];
+  __shared__ int s_p[2][CELL_PB];                      // point indices of two consecutive batches
+  __shared__ A s_w[2][CELL_PB][36];                    // per point: x, y, z  x  tile rows of (w, w', w'')
+  const int tid = (int)threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int grp = lane >> 4;
+  const int col = lane & 15;
+  const int m_ = col >> 2, n_ = col & 3;
+  const int nt_x = (a.g.n[0] + 3) >> 2, nt_y = (a.g.n[1] + 3) >> 2, nt_z = (a.g.n[2] + 3) >> 2;
+  const int64_t n_tiles = (int64_t)nt_x * nt_y * nt_z;
+  const int n_wg = (a.n_groups + TILE_WAVES - 1) / TILE_WAVES;
+  const int64_t n_work = n_tiles * n_wg;
+  const int nw[3] = {min(a.g.n[0], TILE_WIN), min(a.g.n[1], TILE_WIN), min(a.g.n[2], TILE_WIN)};
+  const int nwin = nw[0] * nw[1] * nw[2];
+  const int nt = a.n_terms;
+  const SortedPoint<A>* pts = static_cast<const SortedPoint<A>*>(a.pts);
+  A* gtab = static_cast<A*>(a.gtable);
+  A jm[9], mt[6];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) jm[i] = (A)a.g.jac[i];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) mt[i] = (A)a.g.metric[i];
+
+  for (int64_t w = blockIdx.x; w < n_work; w += gridDim.x) {
+    const int64_t tile = w / n_wg;
+    const int ob = (int)(w % n_wg) * WBW + wave * BW;  // first orbital of this wave
+    const int x0[3] = {4 * (int)(tile / ((int64_t)nt_z * nt_y)), 4 * (int)((tile / nt_z) % nt_y),
+                       4 * (int)(tile % nt_z)};
+    // window cell k along axis ax: cell x0 - 2 + k (mod N), or cell k of an axis under 7 cells
+    auto win_cell = [&](int ax, int k) {
+      if (a.g.n[ax] < TILE_WIN) return k;
+      const int c = x0[ax] - 2 + k;
+      return c < 0 ? c + a.g.n[ax] : (c >= a.g.n[ax] ? c - a.g.n[ax] : c);
+    };
+    bool ocol[OT];
+#pragma unroll
+    for (int ot = 0; ot < OT; ++ot) ocol[ot] = ob + ot * 16 + col < a.n_orb;
+    __syncthreads();                                   // the previous tile is done with the LDS
+    // the window cells' point ranges (thread t: cells 2t and 2t + 1), bounded like every index read
+    // from the workspace, and the exclusive prefix of their counts
+    int cnt2[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = 2 * tid + h;
+      cnt2[h] = 0;
+      if (c < nwin) {
+        const int kz = c % nw[2], ky = (c / nw[2]) % nw[1], kx = c / (nw[2] * nw[1]);
+        const int64_t cell = ((int64_t)win_cell(0, kx) * a.g.n[1] + win_cell(1, ky)) * a.g.n[2] + win_cell(2, kz);
+        int start = a.cell_range[3 * cell], cnt = a.cell_range[3 * cell + 1];
+        if (start < 0 || cnt < 0 || start > a.n_pts - cnt) start = cnt = 0;
+        s_start[c] = start;
+        cnt2[h] = cnt;
+      }
+    }
+    const int mine = cnt2[0] + cnt2[1];
+    int incl = mine;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int up = __shfl_up(incl, d);
+      if (lane >= d) incl += up;
+    }
+    if (lane == 63) s_wsum[wave] = incl;
+    __syncthreads();
+    int before = 0;
+    for (int v = 0; v < wave; ++v) before += s_wsum[v];
+    const int excl = before + incl - mine;
+    if (2 * tid < nwin) s_pre[2 * tid] = excl;
+    if (2 * tid + 1 < nwin) s_pre[2 * tid + 1] = excl + cnt2[0];
+    if (2 * tid < nwin && 2 * tid + 2 >= nwin) s_pre[nwin] = excl + mine;
+    __syncthreads();
+    const int total = s_pre[nwin];
+    if (total == 0) continue;                          // no point reaches this tile: its rows stay as they are
+    const int n_bat = (total + CELL_PB - 1) / CELL_PB;
+    auto count = [&](int k) { return k < n_bat ? min(CELL_PB, total - k * CELL_PB) : 0; };
+
+    // the staging of a batch is shared by 3 CELL_PB threads: thread 3 j + ax holds point j's
+    // reduced coordinate and cell on axis ax (and, for ax = 0, its index)
+    const int sj = tid / 3, sax = tid - 3 * sj;
+    struct Staged {
+      A t;
+      int p, cell;
+    };
+    // every thread loads (slot clamped into the window, so threads past the batch read a real record)
+    auto load_points = [&](int k, Staged& sp) {
+      const int q = min(k * CELL_PB + sj, total - 1);
+      int lo = 0, hi = nwin;                           // s_pre[lo] <= q < s_pre[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_pre[mid] <= q) lo = mid;
+        else hi = mid;
+      }
+      const int s = min(max(s_start[lo] + q - s_pre[lo], 0), a.n_pts - 1);
+      const SortedPoint<A>* rec = pts + s;
+      sp.t = rec->t[sax];
+      sp.p = rec->p;
+      const int k_ax = sax == 0 ? lo / (nw[2] * nw[1]) : (sax == 1 ? (lo / nw[2]) % nw[1] : lo % nw[2]);
+      sp.cell = win_cell(sax, k_ax);
+    };
+    auto stage_index = [&](int k, const Staged& sp, int* sp_out) {
+      if (sax == 0 && sj < count(k)) sp_out[sj] = (unsigned)sp.p < (unsigned)a.n_pts ? sp.p : -1;
+    };
+    // tile row x0 + r lies at offset l = x0 + r - (cell - 1) (mod N) of the point's support; its weight
+    // is w[l] for l <= 3 and 0 otherwise
+    auto stage_weights = [&](int k, const Staged& sp, A (*sw)[36]) {
+      if (sj < count(k)) {
+        A w4[4], d4[4], dd4[4];
+        bspline_weights<A>(sp.t, w4, d4, dd4);
+        const int n = a.g.n[sax];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int l = x0[sax] + r - sp.cell + 1;
+          l = l < 0 ? l + n : (l >= n ? l - n : l);
+          const bool in = l <= 3;
+          sw[sj][12 * sax + r] = in ? select4(l, w4[0], w4[1], w4[2], w4[3]) : A(0);
+          sw[sj][12 * sax + 4 + r] = in ? select4(l, d4[0], d4[1], d4[2], d4[3]) : A(0);
+          sw[sj][12 * sax + 8 + r] = in ? select4(l, dd4[0], dd4[1], dd4[2], dd4[3]) : A(0);
+        }
+      }
+    };
+    uint32_t col_off[OT], col_flag[OT];                // byte offset of the lane's orbital in a row
+#pragma unroll
+    for (int ot = 0; ot < OT; ++ot) {
+      col_off[ot] = ocol[ot] ? (uint32_t)(ob + ot * 16 + col) * (uint32_t)sizeof(A) : 0u;
+      col_flag[ot] = ocol[ot] ? 0u : 0x80000000u;
+    }
+    // upstream values of one step of a batch (as in the brick kernel): lane group k takes point q + k
+    auto load_step = [&](int nb, const int* sp_in, int q, A (&bv)[NB][OT]) {
+      const int j = q + grp;
+      const int pj = j < nb ? sp_in[j] : -1;
+      const bool live = pj >= 0;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        if (c >= nt) {
+#pragma unroll
+          for (int ot = 0; ot < OT; ++ot) bv[c][ot] = A(0);
+          continue;
+        }
+        if constexpr (BUF) {
+          const __amdgpu_buffer_rsrc_t rs =
+              __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(a.src[c]), (short)0, a.src_bytes[c], 0x00020000);
+          const uint32_t row = live ? (uint32_t)pj * (uint32_t)(a.src_stride[c] * sizeof(A)) : 0u;
+          const uint32_t flag = live ? 0u : 0x80000000u;
+#pragma unroll
+          for (int ot = 0; ot < OT; ++ot) bv[c][ot] = BufLoad<A>::load(rs, (row + col_off[ot]) | flag | col_flag[ot]);
+        } else {
+          const A* src = static_cast<const A*>(a.src[c]);
+          const int64_t p = live ? (int64_t)pj : 0;
+#pragma unroll
+          for (int ot = 0; ot < OT; ++ot)
+            bv[c][ot] = (live && ocol[ot]) ? src[p * a.src_stride[c] + ob + ot * 16 + col] : A(0);
+        }
+      }
+    };
+    auto load_upstream = [&](int nb, const int* sp_in, A (&bv)[NQB][NB][OT]) {
+#pragma unroll
+      for (int qi = 0; qi < NQB; ++qi) load_step(nb, sp_in, 4 * qi, bv[qi]);
+    };
+    Acc acc[4][OT];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = Acc{};
+    // the products of one step of four points (as in the brick kernel, on tile rows)
+    auto multiply_step = [&](int nb, int q, const A (*sw)[36], const A (&bv)[NB][OT]) {
+      const A* wp = sw[min(q + grp, nb - 1)];         // a dead lane group multiplies zeros
+      A wx[4], dwx[4], d2wx[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        wx[i] = wp[i];
+        dwx[i] = wp[4 + i];
+        d2wx[i] = wp[8 + i];
+      }
+      const A wy = wp[12 + m_], dwy = wp[16 + m_], d2wy = wp[20 + m_];
+      const A wz = wp[24 + n_], dwz = wp[28 + n_], d2wz = wp[32 + n_];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        if (c >= nt) break;
+        A q0, q1, q2;
+        term_factors<A>(a.kind[c], wy, dwy, d2wy, wz, dwz, d2wz, jm, mt, q0, q1, q2);
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+          const A av = fmaa(q2, d2wx[rt], fmaa(q1, dwx[rt], q0 * wx[rt]));
+#pragma unroll
+          for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = M::step(av, bv[c][ot], acc[rt][ot]);
+        }
+      }
+    };
+    auto multiply = [&](int nb, const int* sp_in, const A (*sw)[36], const A (&bv)[NQB][NB][OT]) {
+      if constexpr (AHEAD) {
+#pragma unroll
+        for (int qi = 0; qi < NQB; ++qi)
+          if (4 * qi < nb) multiply_step(nb, 4 * qi, sw, bv[qi]);
+      } else {
+        A bcur[NB][OT];
+        load_step(nb, sp_in, 0, bcur);
+        for (int q = 0; q < nb; q += 4) {
+          A bnext[NB][OT];                             // unconditional: past the batch every lane reads 0
+          load_step(nb, sp_in, q + 4, bnext);
+          multiply_step(nb, q, sw, bcur);
+#pragma unroll
+          for (int c = 0; c < NB; ++c)
+#pragma unroll
+            for (int ot = 0; ot < OT; ++ot) bcur[c][ot] = bnext[c][ot];
+        }
+      }
+    };
+
+    // batch 0 is multiplied first, batch 1 is staged, batch 2's record is in flight
+    Staged sp0, sp_next, sp_after;
+    load_points(0, sp0);
+    load_points(1, sp_next);
+    load_points(2, sp_after);
+    if (tid < 3 * CELL_PB) {
+      stage_index(0, sp0, s_p[0]);
+      stage_weights(0, sp0, s_w[0]);
+      stage_index(1, sp_next, s_p[1]);
+    }
+    __syncthreads();
+    A bq[2][NQB][NB][OT];
+    if constexpr (AHEAD) load_upstream(count(0), s_p[0], bq[0]);
+    // batch k: load batch k + 1's upstream values, stage its weights and batch k + 2's indices (over
+    // batch k's: before the multiplication where batch k's upstream values are already loaded, after
+    // it where the multiplication loads them), multiply batch k
+    auto step = [&](int k, int buf, A (&cur)[NQB][NB][OT], A (&nxt)[NQB][NB][OT]) {
+      if constexpr (AHEAD) load_upstream(count(k + 1), s_p[buf ^ 1], nxt);
+      if (tid < 3 * CELL_PB) {
+        stage_weights(k + 1, sp_next, s_w[buf ^ 1]);
+        if constexpr (AHEAD) stage_index(k + 2, sp_after, s_p[buf]);
+      }
+      if constexpr (AHEAD) {
+        sp_next = sp_after;
+        load_points(k + 3, sp_after);
+      }
+      multiply(count(k), s_p[buf], s_w[buf], cur);
+      __syncthreads();                                 // every wave is done with batch k's weights and indices
+      if constexpr (!AHEAD) {
+        if (tid < 3 * CELL_PB) stage_index(k + 2, sp_after, s_p[buf]);
+        sp_next = sp_after;
+        load_points(k + 3, sp_after);
+      }
+    };
+    for (int k = 0; k < n_bat; k += 2) {
+      step(k, 0, bq[0], bq[1]);
+      if (k + 1 >= n_bat) break;
+      step(k + 1, 1, bq[1], bq[0]);
+    }
+    // the tile's rows inside the table: every old value is loaded before the first store
+    A old[4][4][OT];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = M::row(grp, e);                  // 4 m + n within the row tile
+        const int X = x0[0] + rt, Y = x0[1] + (i >> 2), Z = x0[2] + (i & 3);
+        const bool in = X < a.g.n[0] && Y < a.g.n[1] && Z < a.g.n[2];
+        const A* rp = gtab + (int64_t)X * a.g.s0 + (int64_t)Y * a.g.s1 + (int64_t)Z * a.g.o_pad + ob + col;
+#pragma unroll
+        for (int ot = 0; ot < OT; ++ot) old[rt][e][ot] = (in && ocol[ot]) ? rp[16 * ot] : A(0);
+      }
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = M::row(grp, e);
+        const int X = x0[0] + rt, Y = x0[1] + (i >> 2), Z = x0[2] + (i & 3);
+        const bool in = X < a.g.n[0] && Y < a.g.n[1] && Z < a.g.n[2];
+        A* rp = gtab + (int64_t)X * a.g.s0 + (int64_t)Y * a.g.s1 + (int64_t)Z * a.g.o_pad + ob + col;
+#pragma unroll
+        for (int ot = 0; ot < OT; ++ot)
+          if (in && ocol[ot]) rp[16 * ot] = old[rt][e][ot] + acc[rt][ot][e];
+      }
+  }
+}
+
 // Each occupied cell's sorted point range (first point, count) and run index; the runs past the
 // finite points' (the non-finite points' sentinel key) are left out.
 __global__ void k_cell_ranges(const int64_t* uniq, const int32_t* counts, const int32_t* offsets,
@@ -911,16 +1025,12 @@ static int brick_ot() {
   return sizeof(A) == 4 ? 2 : 1;
 }
 
-template <typename A, int NT>
-static CellKernel pick_cells_nt(int ot) {
-  if constexpr (sizeof(A) == 4)
-    if (ot >= 4) return k_bwd_cells<A, 4, NT>;
-  return ot == 1 ? k_bwd_cells<A, 1, NT> : k_bwd_cells<A, 2, NT>;
-}
-
+// row tiles: the orbital tiles of the brick form
 template <typename A>
-static CellKernel pick_cells(int ot, int n_terms) {
-  return n_terms <= 2 ? pick_cells_nt<A, 2>(ot) : pick_cells_nt<A, 5>(ot);
+static CellKernel pick_tiles(int nt, bool buf) {
+  constexpr int OT = sizeof(A) == 4 ? 2 : 1;
+  if (nt <= 2) return buf ? k_bwd_tiles<A, OT, 2, true> : k_bwd_tiles<A, OT, 2, false>;
+  return buf ? k_bwd_tiles<A, OT, 5, true> : k_bwd_tiles<A, OT, 5, false>;
 }
 
 // The points sorted by (colour class, cell): keys, permutation, runs of one cell with their point
@@ -1023,13 +1133,9 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
   void* pts = cs.pts;
   const Geom g = make_geom(d);
 
-  // orbital tiles per wave: enough waves per class launch to cover the chip, at most 4 (FP32) or
-  // 2 (FP64) tiles of accumulators per wave; the dense (brick) form has its own
+  // orbital tiles of 16 per wave: FP32 two, FP64 one (brick and row-tile forms alike)
   const int tiles = (d->n_orb + 15) / 16;
-  const int64_t occupied = std::min<int64_t>(n_pts, L.n_cells) / L.n_classes;
-  int ot = d->dtype == SPL_F64 ? 2 : 4;
-  while (ot > 1 && (ot >= 2 * tiles || occupied * ((tiles + ot - 1) / ot) < 2048)) ot >>= 1;
-  if (L.dense) ot = d->dtype == SPL_F64 ? brick_ot<double>() : brick_ot<float>();
+  const int ot = d->dtype == SPL_F64 ? brick_ot<double>() : brick_ot<float>();
   CellArgs a;
   memset(&a, 0, sizeof(a));
   a.g = g;
@@ -1045,10 +1151,10 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
   a.n_classes = L.n_classes;
   a.n_pts = (int32_t)n_pts;
   a.o_pad = d->o_pad;
-  if (L.dense) {
+  {
     // each cell's sorted point range (empty cells: none), from the sort
     int32_t* cell_range = reinterpret_cast<int32_t*>(W + L.cell_range);
-    a.blocks = W + L.blocks;
+    if (L.dense) a.blocks = W + L.blocks;
     a.cell_range = cell_range;
     hipLaunchKernelGGL(k_bwd_fill_i32, dim3((unsigned)((3 * L.n_cells + 255) / 256)), dim3(256), 0, stream,
                        cell_range, 3 * L.n_cells, 0);
@@ -1091,14 +1197,14 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
       a.src_bytes[c] = bytes < ((int64_t)1 << 31) - 4096 ? (int32_t)bytes : -1;
     }
     a.gtable = static_cast<char*>(gtable) + (pass == 1 ? d->table_elems * gsz : 0);
+    bool buf = true, pair = d->n_orb % 2 == 0;
+    for (int c = 0; c < nt; ++c) {
+      buf = buf && a.src_bytes[c] >= 0;
+      pair = pair && a.src_stride[c] % 2 == 0 && reinterpret_cast<uintptr_t>(a.src[c]) % 8 == 0;
+    }
     if (L.dense) {
       // every brick at once into its region, then one gather per table row
       const bool vl = nt == 2 && a.kind[0] == TERM_VAL && a.kind[1] == TERM_LAP;
-      bool buf = true, pair = d->n_orb % 2 == 0;
-      for (int c = 0; c < nt; ++c) {
-        buf = buf && a.src_bytes[c] >= 0;
-        pair = pair && a.src_stride[c] % 2 == 0 && reinterpret_cast<uintptr_t>(a.src[c]) % 8 == 0;
-      }
       const CellKernel kb = d->dtype == SPL_F64 ? pick_bricks<double>(nt, vl, buf, false)
                                                 : pick_bricks<float>(nt, vl, buf, pair);
       const int64_t n_bricks = (int64_t)((d->grid[0] + 1) / 2) * ((d->grid[1] + 1) / 2) * ((d->grid[2] + 1) / 2);
@@ -1116,14 +1222,13 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
       if ((rc = hip_fail(hipGetLastError(), "row gather launch"))) return rc;
       continue;
     }
-    const CellKernel k = d->dtype == SPL_F64 ? pick_cells<double>(ot, nt) : pick_cells<float>(ot, nt);
-    const int64_t waves = occupied * a.n_groups;
-    const int grid = (int)std::max<int64_t>(256, std::min<int64_t>(waves, 8192));
-    for (int c = 0; c < L.n_classes; ++c) {
-      a.cls = c;
-      hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, stream, a);
-      if ((rc = hip_fail(hipGetLastError(), "cell gradient launch"))) return rc;
-    }
+    // sparse points: every tile of 4 x 4 x 4 rows at once, each from its window of cells
+    const CellKernel kt = d->dtype == SPL_F64 ? pick_tiles<double>(nt, buf) : pick_tiles<float>(nt, buf);
+    const int64_t n_tiles = (int64_t)((d->grid[0] + 3) / 4) * ((d->grid[1] + 3) / 4) * ((d->grid[2] + 3) / 4);
+    const int64_t n_wg = (a.n_groups + TILE_WAVES - 1) / TILE_WAVES;
+    const int grid = (int)std::min<int64_t>(n_tiles * n_wg, 1 << 16);
+    hipLaunchKernelGGL(kt, dim3(grid), dim3(64 * TILE_WAVES), 0, stream, a);
+    if ((rc = hip_fail(hipGetLastError(), "row tile launch"))) return rc;
   }
   return SPL_OK;
 }

@@ -14,7 +14,7 @@ import torch
 import paper_1309_6250_amd as P
 from oracle import build as obuild, evaluate as oeval, quantize as oq
 from workloads import config, batched_systems, make_system
-from workloads.configs import cubic
+from workloads.configs import A_MGO, cubic
 from gpu_helpers import say, to_dev, normwise, DEV
 
 pytestmark = pytest.mark.gpu
@@ -215,6 +215,31 @@ def test_deterministic_adjoint_upstream_arrays_over_2gib(terms):
     # two FP32 sums of about 64 n / 16^3 random contributions per row, in different orders: their
     # rounding errors grow like the square root of that count
     per_row = 64 * n / 16 ** 3
+    assert normwise(a.double().cpu().numpy(), c.double().cpu().numpy()) < 8 * 2.0 ** -24 * np.sqrt(per_row)
+
+
+@pytest.mark.timeout(600)
+def test_deterministic_adjoint_sparse_upstream_arrays_over_2gib():
+    """The row-tile form (under 4 points per cell) with upstream arrays of 2 GiB or more: 64-bit offsets
+    instead of buffer loads.  FP32, the MgO-like 96^3 grid with 256 orbitals, 2.2 x 10^6 points (2.5 per
+    cell), value and Laplacian terms of 2.25 GB each.  The gradient does not depend on the table, so it
+    stays zero.  Bitwise repeatable, and equal to the atomic form to FP32 summation accuracy."""
+    grid, n_orb, n = (96, 96, 96), 256, 2_200_000
+    lattice = cubic(2.0 * A_MGO)
+    d = P.spline_desc_init(lattice, grid, n_orb, "f32")
+    tab = P.new_table(d).zero_()
+    g = torch.Generator(device=DEV).manual_seed(407)
+    pos = torch.rand((n, 3), device=DEV, generator=g, dtype=torch.float64) @ to_dev(lattice)
+    gv = torch.randn((n, n_orb), device=DEV, generator=g)
+    gl = torch.randn((n, n_orb), device=DEV, generator=g)
+    assert gv.numel() * 4 >= 2 ** 31 and n < 4 * int(np.prod(grid))
+    say("deterministic adjoint, row tiles, upstream arrays over 2 GiB")
+    a, _ = P.spline_eval_vgl_backward(d, tab, pos, gv, None, gl, want_pos=False, flags=P.SPL_DETERMINISTIC)
+    b, _ = P.spline_eval_vgl_backward(d, tab, pos, gv, None, gl, want_pos=False, flags=P.SPL_DETERMINISTIC)
+    c, _ = P.spline_eval_vgl_backward(d, tab, pos, gv, None, gl, want_pos=False)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    per_row = 64 * n / np.prod(grid)
     assert normwise(a.double().cpu().numpy(), c.double().cpu().numpy()) < 8 * 2.0 ** -24 * np.sqrt(per_row)
 
 

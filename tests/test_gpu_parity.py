@@ -337,8 +337,8 @@ def test_no_writes_past_outputs(dtype, n_orb):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 def test_backward_deterministic_matches_oracle_and_repeats(case, dtype):
-    """SPL_DETERMINISTIC: cell-sorted accumulation, colour classes with ragged tails (5, 7, 9 cells
-    per axis here), non-finite points; equal to the oracle and bitwise equal across runs."""
+    """SPL_DETERMINISTIC: cell-sorted accumulation (row tiles at these densities) with ragged tails (5,
+    7, 9 cells per axis here), non-finite points; equal to the oracle and bitwise equal across runs."""
     d = _desc(case, dtype)
     tab = table_from_oracle(d, case["beta"], dtype, case["lbeta"])
     bq = oq.quantized(case["beta"], dtype)
@@ -393,12 +393,62 @@ def test_backward_deterministic_many_points_per_cell():
     assert normwise(b.cpu().numpy()[0, ..., :33], rb) < 1e-12
 
 
+@pytest.mark.parametrize("n_orb", [37, 70])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_backward_deterministic_row_tiles(dtype, n_orb):
+    """Under 4 points per cell the deterministic adjoint forms each tile of 4 x 4 x 4 table rows from
+    the points of the cells whose blocks reach it: axes of 4 and 6 cells (the window is the whole axis;
+    6 leaves a last tile of 2 rows) and of 19 (a window of 7 of them; a last tile of 3 rows), clustered
+    points so that some windows hold several batches of 32 points and some tiles receive none, every
+    upstream term with the separate Laplacian table, a non-finite point, and orbital counts that leave
+    waves of a workgroup partly or wholly past the last orbital.  Oracle parity and a bitwise repeat."""
+    rng = np.random.default_rng(113)
+    grid = (4, 6, 19)
+    n = 2 * int(np.prod(grid))                          # 2 points per cell on average: the row-tile form
+    beta = rng.standard_normal(grid + (n_orb,))
+    lbeta = rng.standard_normal(grid + (n_orb,))
+    d = P.spline_desc_init(SKEW, grid, n_orb, dtype, has_lap=True)
+    tab = table_from_oracle(d, beta, dtype, lbeta)
+    bq, lq = oq.quantized(beta, dtype), oq.quantized(lbeta, dtype)
+    centers = np.array([[0.1, 0.2, 0.1], [0.6, 0.7, 0.15], [0.3, 0.4, 0.2]])
+    s = (centers[rng.integers(0, 3, n)] + rng.normal(0, 0.05, size=(n, 3))) % 1.0
+    pos = s @ SKEW
+    pos[5] = np.nan
+    i0, _, ok = oeval.reduced_coordinates(SKEW, grid, pos)
+    # points of each tile's window: cells within -2 .. +4 of the tile's first row along every axis
+    win = []
+    for tx in range(0, grid[0], 4):
+        for ty in range(0, grid[1], 4):
+            for tz in range(0, grid[2], 4):
+                near = np.ones(n, bool)
+                for ax, t0 in enumerate((tx, ty, tz)):
+                    near &= ((i0[:, ax] - (t0 - 2)) % grid[ax]) <= 6 if grid[ax] >= 7 else True
+                win.append(int((near & ok).sum()))
+    assert max(win) > 2 * 32 and min(win) == 0
+    gv, gg, gl = rng.standard_normal((n, n_orb)), rng.standard_normal((n, 3, n_orb)), rng.standard_normal((n, n_orb))
+    od = torch.float64 if dtype == "f64" else torch.float32
+    args = (to_dev(gv, od), to_dev(gg, od), to_dev(gl, od))
+    say("deterministic backward, row tiles", dtype, n_orb)
+    runs = []
+    for _ in range(2):
+        gt, _ = P.spline_eval_vgl_backward(d, tab, to_dev(pos), *args, want_pos=False, flags=P.SPL_DETERMINISTIC)
+        torch.cuda.synchronize()
+        runs.append(gt.clone())
+    assert torch.equal(runs[0], runs[1])
+    rb, rlb, _ = oadj.vgl_backward(bq, SKEW, pos[ok], gv[ok], gg[ok], gl[ok], lap_beta=lq)
+    got = runs[0].double().cpu().numpy()
+    tol = 1e-12 if dtype == "f64" else 2e-5
+    assert normwise(got[0, ..., :n_orb], rb) <= tol
+    assert normwise(got[1, ..., :n_orb], rlb) <= tol
+    assert np.all(got[..., n_orb:] == 0.0)
+
+
 @pytest.mark.parametrize("n_orb", [37, 38])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_backward_deterministic_dense_path(dtype, n_orb):
     """At 4 or more points per cell the deterministic adjoint sums the cell blocks of every brick of
     2 x 2 x 2 cells into a 5 x 5 x 5-row region in the workspace and gathers the regions per table row
-    (no colour classes): oracle parity with the separate Laplacian table and every upstream term, an
+    (not per row tile): oracle parity with the separate Laplacian table and every upstream term, an
     odd or even orbital count, a ragged grid (odd cell counts leave partial bricks; 5 cells wrap a region onto
     itself), repeatable bit for bit.  An even orbital count takes FP32's paired columns."""
     rng = np.random.default_rng(107)

@@ -2,8 +2,8 @@
 // spline_eval_vgl_backward (flag SPL_DETERMINISTIC) and the cell-wise forward evaluation
 // spline_eval_vgl_cells.  Both start from the same sort:
 //
-//  1. every point gets the key (colour class, cell) of the grid cell it falls in; points with
-//     non-finite coordinates get a key past all classes;
+//  1. every point gets the index of the grid cell it falls in as its key; points with non-finite
+//     coordinates get a key past all cells;
 //  2. a stable radix sort orders points by key (then by index), a run-length encoding lists the
 //     occupied cells with the range of their points, and each sorted point gets a record of its
 //     reduced coordinates and index.
@@ -37,18 +37,11 @@
 
 namespace pws {
 
-__host__ __device__ inline int axis_colour(int i, int n) {
-  const int full = n & ~3;
-  return i < full ? (i & 3) : 4 + (i - full);
-}
-__host__ __device__ inline int axis_colours(int n) { return 4 + (n & 3); }
-
 struct SortLayout {
-  size_t keys_in, keys_out, vals_in, vals_out, uniq, counts, offsets, num_runs, class_start, pts, cell_range, blocks,
+  size_t keys_in, keys_out, vals_in, vals_out, uniq, counts, offsets, num_runs, finite_runs, pts, cell_range, blocks,
       partials, temp;
   size_t temp_bytes, total;
-  int n_classes;
-  int dense;           // 1: brick regions in the workspace and a per-row gather instead of colour classes
+  int dense;           // 1: brick regions in the workspace and a per-row gather instead of row tiles
   int64_t n_cells;
   int end_bit;
 };
@@ -75,8 +68,7 @@ constexpr int FIT_SUM_THREADS = 256;
 static int sort_layout(const spl_desc* d, int64_t n_pts, SortLayout* L, bool adjoint_blocks = true,
                        bool fit_partials = false) {
   L->n_cells = (int64_t)d->grid[0] * d->grid[1] * d->grid[2];
-  L->n_classes = axis_colours(d->grid[0]) * axis_colours(d->grid[1]) * axis_colours(d->grid[2]);
-  const uint64_t max_key = (uint64_t)(L->n_classes + 1) * (uint64_t)L->n_cells;
+  const uint64_t max_key = (uint64_t)L->n_cells;     // the non-finite points' key
   int bits = 1;
   while (bits < 63 && ((uint64_t)1 << bits) <= max_key) ++bits;
   L->end_bit = bits;
@@ -103,7 +95,7 @@ static int sort_layout(const spl_desc* d, int64_t n_pts, SortLayout* L, bool adj
   L->counts = off; off = align_up(off + 4 * n);
   L->offsets = off; off = align_up(off + 4 * n);
   L->num_runs = off; off = align_up(off + 4);
-  L->class_start = off; off = align_up(off + 4 * (size_t)(L->n_classes + 2));
+  L->finite_runs = off; off = align_up(off + 4);
   L->pts = off; off = align_up(off + (d->dtype == SPL_F64 ? 32 : 16) * n);
   // dense points (at least 4 per cell on average): the 5 x 5 x 5-row region of every brick of 2 x 2 x 2
   // cells gets its own place, and every cell its sorted point range
@@ -132,26 +124,20 @@ __global__ __launch_bounds__(256) void k_cell_keys(Geom g, const double* pos, in
   double t[3];
   const bool ok = reduce_point(g, pos[3 * (int64_t)p], pos[3 * (int64_t)p + 1], pos[3 * (int64_t)p + 2], i0, t);
   const int64_t cell = ((int64_t)i0[0] * g.n[1] + i0[1]) * g.n[2] + i0[2];
-  const int c1 = axis_colours(g.n[1]), c2 = axis_colours(g.n[2]);
-  const int64_t cls = ((int64_t)axis_colour(i0[0], g.n[0]) * c1 + axis_colour(i0[1], g.n[1])) * c2 +
-                      axis_colour(i0[2], g.n[2]);
-  keys[p] = ok ? cls * n_cells + cell : sentinel;
+  keys[p] = ok ? cell : sentinel;
   vals[p] = p;
 }
 
-// class_start[c] = first run whose key belongs to class c or later (c = 0 .. n_classes)
-__global__ void k_class_starts(const int64_t* uniq, const int32_t* num_runs, int64_t n_cells, int32_t n_classes,
-                               int32_t* class_start) {
-  const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (c > n_classes) return;
-  const int64_t key = (int64_t)c * n_cells;
+// finite_runs = the runs of finite points (occupied cells): the first run whose key is n_cells or more
+__global__ void k_finite_runs(const int64_t* uniq, const int32_t* num_runs, int64_t n_cells, int32_t* finite_runs) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
   int lo = 0, hi = *num_runs;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
-    if (uniq[mid] < key) lo = mid + 1;
+    if (uniq[mid] < n_cells) lo = mid + 1;
     else hi = mid;
   }
-  class_start[c] = lo;
+  *finite_runs = lo;
 }
 
 // A point in sorted order: its reduced coordinates within its cell and its index.
@@ -191,16 +177,10 @@ struct CellArgs {
   int32_t kind[5];         // TERM_* of each term
   int32_t n_terms;
   void* gtable;            // base of the table this pass writes (orbital or Laplacian table)
-  const int64_t* uniq;
-  const int32_t* counts;
-  const int32_t* offsets;
   const void* pts;         // SortedPoint records in sorted order
-  const int32_t* class_start;
   int64_t n_cells;
-  int32_t cls;
   int32_t n_orb;
   int32_t n_groups;        // orbital groups of 16 OT per cell
-  int32_t n_classes;
   int32_t n_pts;           // every index read from the sort is checked against this and n_cells
   int32_t o_pad;
   void* blocks;              // dense: [n_bricks][125][o_pad] gradient regions of the bricks of 2 x 2 x 2 cells
@@ -675,10 +655,10 @@ __global__ __launch_bounds__(256) void k_bwd_brick_gather(Geom g, const A* regio
 //     d beta[row][o] = sum over the window's points and the terms of W_term(point)[row] g_term[point][o],
 // where a point's 1-D weights are moved onto the tile rows they land on (0 on a tile row outside
 // its support), and adds it to the table once.  Every row belongs to one workgroup: no atomics,
-// no colour classes, one launch, and a fixed order of every sum (window cells in order, each
-// cell's points in sorted order).  Each point is multiplied with the whole tile, so the matrix
-// cores do about (7/4)^3 times the useful products; with under 4 points per cell that costs less
-// than reading and writing the table rows once per cell.
+// one launch, and a fixed order of every sum (window cells in order, each cell's points in sorted
+// order).  Each point is multiplied with the whole tile, so the matrix cores do about (7/4)^3 times
+// the useful products; with under 4 points per cell that costs less than a workspace region per
+// brick, which would be read and written for few points.
 //
 // The window's points are taken in batches of CELL_PB across cell boundaries (slot q of the window
 // is found by a binary search over the prefix sums of its cells' counts), with the pipeline of the
@@ -985,9 +965,8 @@ __global__ __launch_bounds__(64 * TILE_WAVES) void k_bwd_tiles(CellArgs a) {
 // Each occupied cell's sorted point range (first point, count) and run index; the runs past the
 // finite points' (the non-finite points' sentinel key) are left out.
 __global__ void k_cell_ranges(const int64_t* uniq, const int32_t* counts, const int32_t* offsets,
-                              const int32_t* class_start, int64_t n_cells, int32_t n_classes, int32_t n_pts,
-                              int32_t* cell_range) {
-  const int n_runs = (int)min((int64_t)min(max(class_start[n_classes], 0), n_pts), n_cells);
+                              const int32_t* finite_runs, int64_t n_cells, int32_t n_pts, int32_t* cell_range) {
+  const int n_runs = (int)min((int64_t)min(max(*finite_runs, 0), n_pts), n_cells);
   const int r = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (r >= n_runs) return;
   const int64_t cell = uniq[r] % n_cells;
@@ -1033,15 +1012,15 @@ static CellKernel pick_tiles(int nt, bool buf) {
   return buf ? k_bwd_tiles<A, OT, 5, true> : k_bwd_tiles<A, OT, 5, false>;
 }
 
-// The points sorted by (colour class, cell): keys, permutation, runs of one cell with their point
-// ranges, the first run of each class, and each sorted point's record.
+// The points sorted by cell: keys, permutation, runs of one cell with their point ranges, the number
+// of runs of finite points, and each sorted point's record.
 struct CellSort {
-  int64_t* keys;         // sorted keys (class n_cells + cell; non-finite points: sentinel, last)
+  int64_t* keys;         // sorted keys (the cell; non-finite points: n_cells, last)
   int32_t* perm;         // sorted position -> point index
   int64_t* uniq;         // key of each run
   int32_t* counts;       // points in each run
   int32_t* offsets;      // first sorted position of each run
-  int32_t* class_start;  // first run of each class (n_classes + 1 entries)
+  int32_t* finite_runs;  // runs of finite points (one value)
   void* pts;             // SortedPoint records in sorted order
   char* base;            // the workspace
 };
@@ -1051,7 +1030,7 @@ static CellSort cell_sort_view(void* work, const SortLayout& L) {
   char* W = static_cast<char*>(work);
   return CellSort{reinterpret_cast<int64_t*>(W + L.keys_out), reinterpret_cast<int32_t*>(W + L.vals_out),
                   reinterpret_cast<int64_t*>(W + L.uniq), reinterpret_cast<int32_t*>(W + L.counts),
-                  reinterpret_cast<int32_t*>(W + L.offsets), reinterpret_cast<int32_t*>(W + L.class_start),
+                  reinterpret_cast<int32_t*>(W + L.offsets), reinterpret_cast<int32_t*>(W + L.finite_runs),
                   W + L.pts, W};
 }
 
@@ -1072,13 +1051,13 @@ static int cell_sort(const spl_desc* d, int64_t n_pts, const double* pos, void* 
   int32_t* counts = reinterpret_cast<int32_t*>(W + L.counts);
   int32_t* offsets = reinterpret_cast<int32_t*>(W + L.offsets);
   int32_t* num_runs = reinterpret_cast<int32_t*>(W + L.num_runs);
-  int32_t* class_start = reinterpret_cast<int32_t*>(W + L.class_start);
+  int32_t* finite_runs = reinterpret_cast<int32_t*>(W + L.finite_runs);
   void* pts = W + L.pts;
   void* temp = W + L.temp;
   const Geom g = make_geom(d);
   const int n = (int)n_pts;
   hipLaunchKernelGGL(k_cell_keys, dim3((n + 255) / 256), dim3(256), 0, stream, g, pos, (int32_t)n, L.n_cells,
-                     (int64_t)L.n_classes * L.n_cells, keys_in, vals_in);
+                     L.n_cells, keys_in, vals_in);
   if ((rc = hip_fail(hipGetLastError(), "cell key launch"))) return rc;
   size_t tb = L.temp_bytes;
   if ((rc = hip_fail(sort_cell_keys(temp, tb, keys_in, keys_out, vals_in, vals_out, n, L.end_bit, stream),
@@ -1090,8 +1069,7 @@ static int cell_sort(const spl_desc* d, int64_t n_pts, const double* pos, void* 
     return rc;
   tb = L.temp_bytes;
   if ((rc = hip_fail(hipcub::DeviceScan::ExclusiveSum(temp, tb, counts, offsets, n, stream), "scan"))) return rc;
-  hipLaunchKernelGGL(k_class_starts, dim3((L.n_classes + 1 + 255) / 256), dim3(256), 0, stream, uniq, num_runs,
-                     L.n_cells, (int32_t)L.n_classes, class_start);
+  hipLaunchKernelGGL(k_finite_runs, dim3(1), dim3(64), 0, stream, uniq, num_runs, L.n_cells, finite_runs);
   if ((rc = hip_fail(hipGetLastError(), "class start launch"))) return rc;
   if (d->dtype == SPL_F64)
     hipLaunchKernelGGL(k_sorted_points<double>, dim3((n + 255) / 256), dim3(256), 0, stream, g, pos, vals_out,
@@ -1129,7 +1107,6 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
   int64_t* uniq = cs.uniq;
   int32_t* counts = cs.counts;
   int32_t* offsets = cs.offsets;
-  int32_t* class_start = cs.class_start;
   void* pts = cs.pts;
   const Geom g = make_geom(d);
 
@@ -1140,15 +1117,10 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
   memset(&a, 0, sizeof(a));
   a.g = g;
   a.pos = pos;
-  a.uniq = uniq;
-  a.counts = counts;
-  a.offsets = offsets;
   a.pts = pts;
-  a.class_start = class_start;
   a.n_cells = L.n_cells;
   a.n_orb = d->n_orb;
   a.n_groups = (tiles + ot - 1) / ot;
-  a.n_classes = L.n_classes;
   a.n_pts = (int32_t)n_pts;
   a.o_pad = d->o_pad;
   {
@@ -1161,7 +1133,7 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
     if ((rc = hip_fail(hipGetLastError(), "cell range clear launch"))) return rc;
     const int max_runs = (int)std::min<int64_t>(n_pts, L.n_cells);
     hipLaunchKernelGGL(k_cell_ranges, dim3((unsigned)((max_runs + 255) / 256)), dim3(256), 0, stream, uniq, counts,
-                       offsets, class_start, L.n_cells, (int32_t)L.n_classes, (int32_t)n_pts, cell_range);
+                       offsets, cs.finite_runs, L.n_cells, (int32_t)n_pts, cell_range);
     if ((rc = hip_fail(hipGetLastError(), "cell range launch"))) return rc;
   }
   const int64_t no = d->n_orb;
@@ -1257,9 +1229,8 @@ struct FwdArgs {
   const int32_t* counts;
   const int32_t* offsets;
   const void* pts;
-  const int32_t* class_start;
+  const int32_t* finite_runs;  // runs of finite points (occupied cells), from the sort
   int64_t n_cells;
-  int32_t n_classes;
   int32_t n_orb;
   int32_t n_groups;
   int32_t n_pts;           // every index read from the sort is checked against this and n_cells
@@ -1325,7 +1296,7 @@ void k_fwd_cells(FwdArgs a) {
   const int grp = lane >> 4;
   const int col = lane & 15;
   // every run before the non-finite points (at most one per occupied cell)
-  const int n_runs = (int)min((int64_t)min(max(a.class_start[a.n_classes], 0), a.n_pts), a.n_cells);
+  const int n_runs = (int)min((int64_t)min(max(*a.finite_runs, 0), a.n_pts), a.n_cells);
   const int64_t n_work = (int64_t)n_runs * a.n_groups;
   const int nt = a.n_terms;
   const SortedPoint<A>* pts = static_cast<const SortedPoint<A>*>(a.pts);
@@ -1899,11 +1870,11 @@ __device__ __forceinline__ double block_tree_sum(double v, double* red) {
   return red[0];
 }
 
-__global__ __launch_bounds__(FIT_SUM_THREADS) void k_fit_blocks(const int32_t* class_start, int32_t n_classes,
-                                                                int32_t n_pts, int64_t n_cells, int32_t n_groups,
+__global__ __launch_bounds__(FIT_SUM_THREADS) void k_fit_blocks(const int32_t* finite_runs, int32_t n_pts,
+                                                                int64_t n_cells, int32_t n_groups,
                                                                 const double* partial, double* block_sum) {
   __shared__ double red[FIT_SUM_THREADS];
-  const int64_t n_runs = min((int64_t)min(max(class_start[n_classes], 0), n_pts), n_cells);
+  const int64_t n_runs = min((int64_t)min(max(*finite_runs, 0), n_pts), n_cells);
   const int64_t n_work = n_runs * n_groups;
   constexpr int64_t S = (int64_t)FIT_SUM_BLOCKS * FIT_SUM_THREADS;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -2028,9 +1999,8 @@ int launch_eval_cells(const spl_desc* d, const void* table, int64_t n_pts, const
   a.counts = cs.counts;
   a.offsets = cs.offsets;
   a.pts = cs.pts;
-  a.class_start = cs.class_start;
+  a.finite_runs = cs.finite_runs;
   a.n_cells = L.n_cells;
-  a.n_classes = L.n_classes;
   a.n_pts = (int32_t)n_pts;
   a.n_orb = d->n_orb;
   const int ot = fwd_tiles(d->dtype, nt, a.use_lap_table != 0);
@@ -2047,19 +2017,19 @@ int launch_eval_cells(const spl_desc* d, const void* table, int64_t n_pts, const
   if (fit) {
     // the block sums follow the work items' partials (at most min(n, cells) runs x 16-orbital tiles)
     double* block_sum = a.partial + std::min<int64_t>(n_pts, L.n_cells) * (int64_t)((d->n_orb + 15) / 16);
-    hipLaunchKernelGGL(k_fit_blocks, dim3(FIT_SUM_BLOCKS), dim3(FIT_SUM_THREADS), 0, stream, cs.class_start,
-                       (int32_t)L.n_classes, a.n_pts, L.n_cells, a.n_groups, a.partial, block_sum);
+    hipLaunchKernelGGL(k_fit_blocks, dim3(FIT_SUM_BLOCKS), dim3(FIT_SUM_THREADS), 0, stream, cs.finite_runs,
+                       a.n_pts, L.n_cells, a.n_groups, a.partial, block_sum);
     if ((rc = hip_fail(hipGetLastError(), "fit block sums launch"))) return rc;
     hipLaunchKernelGGL(k_fit_total, dim3(1), dim3(FIT_SUM_THREADS), 0, stream, block_sum, cs.keys, a.n_pts,
-                       (int64_t)L.n_classes * L.n_cells, fit->loss);
+                       L.n_cells, fit->loss);
     if ((rc = hip_fail(hipGetLastError(), "fit total launch"))) return rc;
   }
   if (d->dtype == SPL_F64)
     hipLaunchKernelGGL(k_fwd_nan<double>, dim3((n + 255) / 256), dim3(256), 0, stream, cs.keys, cs.perm, n,
-                       (int64_t)L.n_classes * L.n_cells, a);
+                       L.n_cells, a);
   else
     hipLaunchKernelGGL(k_fwd_nan<float>, dim3((n + 255) / 256), dim3(256), 0, stream, cs.keys, cs.perm, n,
-                       (int64_t)L.n_classes * L.n_cells, a);
+                       L.n_cells, a);
   return hip_fail(hipGetLastError(), "non-finite point launch");
 }
 
@@ -2099,8 +2069,7 @@ int launch_fit_gradient(const spl_desc* d, const void* table, int64_t n_pts, con
   if ((rc = hip_fail(hipGetLastError(), "cell range clear launch"))) return rc;
   const int max_runs = (int)std::min<int64_t>(n_pts, L.n_cells);
   hipLaunchKernelGGL(k_cell_ranges, dim3((unsigned)((max_runs + 255) / 256)), dim3(256), 0, stream, cs.uniq,
-                     cs.counts, cs.offsets, cs.class_start, L.n_cells, (int32_t)L.n_classes, (int32_t)n_pts,
-                     cell_range);
+                     cs.counts, cs.offsets, cs.finite_runs, L.n_cells, (int32_t)n_pts, cell_range);
   if ((rc = hip_fail(hipGetLastError(), "cell range launch"))) return rc;
   FitArgs a;
   memset(&a, 0, sizeof(a));
@@ -2132,11 +2101,11 @@ int launch_fit_gradient(const spl_desc* d, const void* table, int64_t n_pts, con
   if ((rc = hip_fail(hipGetLastError(), "row gather launch"))) return rc;
   // the loss: the same two fixed-order sums over the same partials as the fit terms
   double* block_sum = a.partial + std::min<int64_t>(n_pts, L.n_cells) * (int64_t)((d->n_orb + 15) / 16);
-  hipLaunchKernelGGL(k_fit_blocks, dim3(FIT_SUM_BLOCKS), dim3(FIT_SUM_THREADS), 0, stream, cs.class_start,
-                     (int32_t)L.n_classes, a.n_pts, L.n_cells, a.n_groups, a.partial, block_sum);
+  hipLaunchKernelGGL(k_fit_blocks, dim3(FIT_SUM_BLOCKS), dim3(FIT_SUM_THREADS), 0, stream, cs.finite_runs,
+                     a.n_pts, L.n_cells, a.n_groups, a.partial, block_sum);
   if ((rc = hip_fail(hipGetLastError(), "fit block sums launch"))) return rc;
   hipLaunchKernelGGL(k_fit_total, dim3(1), dim3(FIT_SUM_THREADS), 0, stream, block_sum, cs.keys, a.n_pts,
-                     (int64_t)L.n_classes * L.n_cells, loss);
+                     L.n_cells, loss);
   return hip_fail(hipGetLastError(), "fit total launch");
 }
 

@@ -357,11 +357,12 @@ int spline_fit_gradient_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* by
  *   gpos             device, FP64 [n_pts][3], OVERWRITTEN; may be NULL to skip
  *   flags            0: the coefficient gradient is summed with hardware float atomics (order
  *                    of summation not reproducible; no workspace); SPL_DETERMINISTIC: points are
- *                    sorted by grid cell and each cell's 64-row block is formed on the matrix
- *                    cores in point order, then either added class by class with ordinary
- *                    stores (cells of one class have disjoint blocks) or, at 4 or more points
- *                    per cell, stored per cell and gathered per table row in a fixed order:
- *                    bitwise reproducible, and the faster of the two at every density measured
+ *                    sorted by grid cell and every sum is formed in a fixed order on the matrix
+ *                    cores: under 4 points per cell, each tile of 4x4x4 table rows sums the
+ *                    points of the cells whose blocks reach it and adds the sum once; at 4 or
+ *                    more, the cells' blocks are summed per brick of 2x2x2 cells and gathered
+ *                    per table row: bitwise reproducible, and the faster of the two at every
+ *                    density measured
  *                    SPL_REUSE_SORT (with SPL_DETERMINISTIC): the workspace already holds the
  *                    cell sort of these points
  *   work, work_bytes device workspace for SPL_DETERMINISTIC, 256-byte aligned, at least
@@ -377,8 +378,9 @@ int spline_eval_vgl_backward(const spl_desc* d, const void* table, int64_t n_pts
                              void* work, int64_t work_bytes, void* stream);
 
 /* Workspace size (bytes) spline_eval_vgl_backward needs for n_pts points and `flags` (0 without
- * SPL_DETERMINISTIC).  With it: the sort's keys, runs and point records, and, when n_pts >=
- * 4 N1 N2 N3 and they fit in 4 GiB, the per-cell blocks (N1 N2 N3 64 o_pad gradient values).
+ * SPL_DETERMINISTIC).  With it: the sort's keys, runs and point records, every cell's point range
+ * (12 bytes per cell), and, when n_pts >= 4 N1 N2 N3 and they fit in 4 GiB, the regions of the
+ * bricks of 2x2x2 cells (ceil(N1/2) ceil(N2/2) ceil(N3/2) 125 o_pad gradient values).
  * Host only; may query the current HIP device. */
 int spline_backward_work_bytes(const spl_desc* d, int64_t n_pts, int32_t flags, int64_t* bytes);
 

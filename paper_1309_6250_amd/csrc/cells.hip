@@ -661,10 +661,13 @@ __global__ __launch_bounds__(256) void k_bwd_brick_gather(Geom g, const A* regio
 // brick, which would be read and written for few points.
 //
 // The window's points are taken in batches of CELL_PB across cell boundaries (slot q of the window
-// is found by a binary search over the prefix sums of its cells' counts), with the pipeline of the
-// brick kernel: the records of later batches load while the current batch is multiplied, their
-// weights and indices are staged in a second LDS buffer, and (with at most two terms) every wave
-// loads the next batch's upstream values before it multiplies the current one.
+// is found by a binary search over the prefix sums of its cells' counts): the records of later
+// batches load while the current batch is multiplied, their weights and indices are staged in a
+// second LDS buffer, and each step's upstream values load while the step before is multiplied.
+// A window holds few batches (about 7 on the Si-like cell, 1 on the MgO-like cell), so what hides
+// its chain of dependent accesses is the number of workgroups in flight: the kernel is held to 3
+// waves per SIMD (measured: loading a whole batch's upstream values ahead, in registers that allow
+// only 2, was 8-27% slower).
 constexpr int TILE_WAVES = 4;
 constexpr int TILE_WIN = 7;                               // window cells per axis (at most)
 constexpr int TILE_WIN3 = TILE_WIN * TILE_WIN * TILE_WIN;
@@ -675,15 +678,12 @@ __device__ __forceinline__ A select4(int l, A a0, A a1, A a2, A a3) {
 }
 
 template <typename A, int OT, int NT, bool BUF>
-__global__ __launch_bounds__(64 * TILE_WAVES) void k_bwd_tiles(CellArgs a) {
+__global__ __launch_bounds__(64 * TILE_WAVES) __attribute__((amdgpu_waves_per_eu(3))) void k_bwd_tiles(CellArgs a) {
   using M = Mfma<A>;
   using Acc = typename M::acc;
   constexpr int BW = 16 * OT;                          // orbitals of a wave
   constexpr int WBW = TILE_WAVES * BW;                 // orbitals of a workgroup
-  constexpr int NQ = CELL_PB / 4;                      // steps of four points in a full batch
   constexpr int NB = NT <= 2 ? NT : 5;                 // upstream values per point and orbital tile
-  constexpr bool AHEAD = NT <= 2;                      // next batch's upstream values loaded ahead
-  constexpr int NQB = AHEAD ? NQ : 1;
   static_assert(2 * 64 * TILE_WAVES >= TILE_WIN3, "two window cells per thread");
   __shared__ int s_start[TILE_WIN3];                   // first sorted point of each window cell
   __shared__ int s_pre[TILE_WIN3 + 1];                 // points of the window cells before each
@@ -841,10 +841,6 @@ __global__ __launch_bounds__(64 * TILE_WAVES) void k_bwd_tiles(CellArgs a) {
         }
       }
     };
-    auto load_upstream = [&](int nb, const int* sp_in, A (&bv)[NQB][NB][OT]) {
-#pragma unroll
-      for (int qi = 0; qi < NQB; ++qi) load_step(nb, sp_in, 4 * qi, bv[qi]);
-    };
     Acc acc[4][OT];
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt)
@@ -875,23 +871,18 @@ __global__ __launch_bounds__(64 * TILE_WAVES) void k_bwd_tiles(CellArgs a) {
         }
       }
     };
-    auto multiply = [&](int nb, const int* sp_in, const A (*sw)[36], const A (&bv)[NQB][NB][OT]) {
-      if constexpr (AHEAD) {
+    // one batch: each step's upstream values load while the step before is multiplied
+    auto multiply = [&](int nb, const int* sp_in, const A (*sw)[36]) {
+      A bcur[NB][OT];
+      load_step(nb, sp_in, 0, bcur);
+      for (int q = 0; q < nb; q += 4) {
+        A bnext[NB][OT];                               // unconditional: past the batch every lane reads 0
+        load_step(nb, sp_in, q + 4, bnext);
+        multiply_step(nb, q, sw, bcur);
 #pragma unroll
-        for (int qi = 0; qi < NQB; ++qi)
-          if (4 * qi < nb) multiply_step(nb, 4 * qi, sw, bv[qi]);
-      } else {
-        A bcur[NB][OT];
-        load_step(nb, sp_in, 0, bcur);
-        for (int q = 0; q < nb; q += 4) {
-          A bnext[NB][OT];                             // unconditional: past the batch every lane reads 0
-          load_step(nb, sp_in, q + 4, bnext);
-          multiply_step(nb, q, sw, bcur);
+        for (int c = 0; c < NB; ++c)
 #pragma unroll
-          for (int c = 0; c < NB; ++c)
-#pragma unroll
-            for (int ot = 0; ot < OT; ++ot) bcur[c][ot] = bnext[c][ot];
-        }
+          for (int ot = 0; ot < OT; ++ot) bcur[c][ot] = bnext[c][ot];
       }
     };
 
@@ -906,33 +897,16 @@ __global__ __launch_bounds__(64 * TILE_WAVES) void k_bwd_tiles(CellArgs a) {
       stage_index(1, sp_next, s_p[1]);
     }
     __syncthreads();
-    A bq[2][NQB][NB][OT];
-    if constexpr (AHEAD) load_upstream(count(0), s_p[0], bq[0]);
-    // batch k: load batch k + 1's upstream values, stage its weights and batch k + 2's indices (over
-    // batch k's: before the multiplication where batch k's upstream values are already loaded, after
-    // it where the multiplication loads them), multiply batch k
-    auto step = [&](int k, int buf, A (&cur)[NQB][NB][OT], A (&nxt)[NQB][NB][OT]) {
-      if constexpr (AHEAD) load_upstream(count(k + 1), s_p[buf ^ 1], nxt);
-      if (tid < 3 * CELL_PB) {
-        stage_weights(k + 1, sp_next, s_w[buf ^ 1]);
-        if constexpr (AHEAD) stage_index(k + 2, sp_after, s_p[buf]);
-      }
-      if constexpr (AHEAD) {
-        sp_next = sp_after;
-        load_points(k + 3, sp_after);
-      }
-      multiply(count(k), s_p[buf], s_w[buf], cur);
+    // batch k: stage batch k + 1's weights, multiply batch k, then (every wave done with batch k's
+    // indices) stage batch k + 2's indices over them
+    for (int k = 0; k < n_bat; ++k) {
+      const int buf = k & 1;
+      if (tid < 3 * CELL_PB) stage_weights(k + 1, sp_next, s_w[buf ^ 1]);
+      multiply(count(k), s_p[buf], s_w[buf]);
       __syncthreads();                                 // every wave is done with batch k's weights and indices
-      if constexpr (!AHEAD) {
-        if (tid < 3 * CELL_PB) stage_index(k + 2, sp_after, s_p[buf]);
-        sp_next = sp_after;
-        load_points(k + 3, sp_after);
-      }
-    };
-    for (int k = 0; k < n_bat; k += 2) {
-      step(k, 0, bq[0], bq[1]);
-      if (k + 1 >= n_bat) break;
-      step(k + 1, 1, bq[1], bq[0]);
+      if (tid < 3 * CELL_PB) stage_index(k + 2, sp_after, s_p[buf]);
+      sp_next = sp_after;
+      load_points(k + 3, sp_after);
     }
     // the tile's rows inside the table: every old value is loaded before the first store
     A old[4][4][OT];

@@ -332,7 +332,7 @@ int spline_fit_terms_cells(const spl_desc* d, const void* table, int64_t n_pts, 
  *   flags        SPL_REUSE_SORT: the workspace holds the cell sort of these points from an earlier
  *                call of this function (the layout differs from spline_cells_work_bytes')
  *   work         device, 256-byte aligned, spline_fit_gradient_work_bytes() bytes
- * Supported: FP32 B-spline tables without a separate Laplacian table, at least 4 points per cell
+ * Supported: FP32 B-spline tables without a separate Laplacian table, at least 2.5 points per cell
  * on average, and the table and each target array under 2 GiB; otherwise SPL_EUNSUPPORTED (use
  * spline_fit_terms_cells and spline_eval_vgl_backward).  A non-finite point contributes nothing to
  * gtable and makes the loss NaN.  Other errors as for spline_fit_terms_cells.  Allocates nothing.
@@ -358,9 +358,9 @@ int spline_fit_gradient_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* by
  *   flags            0: the coefficient gradient is summed with hardware float atomics (order
  *                    of summation not reproducible; no workspace); SPL_DETERMINISTIC: points are
  *                    sorted by grid cell and every sum is formed in a fixed order on the matrix
- *                    cores: under 4 points per cell, each tile of 4x4x4 table rows sums the
- *                    points of the cells whose blocks reach it and adds the sum once; at 4 or
- *                    more, the cells' blocks are summed per brick of 2x2x2 cells and gathered
+ *                    cores: under 2.5 points per cell, each tile of 4x4x4 table rows sums the
+ *                    points of the cells whose blocks reach it and adds the sum once; at 2.5
+ *                    or more, the cells' blocks are summed per brick of 2x2x2 cells and gathered
  *                    per table row: bitwise reproducible, and the faster of the two at every
  *                    density measured
  *                    SPL_REUSE_SORT (with SPL_DETERMINISTIC): the workspace already holds the
@@ -379,7 +379,7 @@ int spline_eval_vgl_backward(const spl_desc* d, const void* table, int64_t n_pts
 
 /* Workspace size (bytes) spline_eval_vgl_backward needs for n_pts points and `flags` (0 without
  * SPL_DETERMINISTIC).  With it: the sort's keys, runs and point records, every cell's point range
- * (12 bytes per cell), and, when n_pts >= 4 N1 N2 N3 and they fit in 4 GiB, the regions of the
+ * (12 bytes per cell), and, when 2 n_pts >= 5 N1 N2 N3 and they fit in 4 GiB, the regions of the
  * bricks of 2x2x2 cells (ceil(N1/2) ceil(N2/2) ceil(N3/2) 125 o_pad gradient values).
  * Host only; may query the current HIP device. */
 int spline_backward_work_bytes(const spl_desc* d, int64_t n_pts, int32_t flags, int64_t* bytes);

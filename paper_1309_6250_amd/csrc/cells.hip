@@ -14,7 +14,7 @@
 // Adjoint.  The gradient of a coefficient is a sum over every point whose 4x4x4 block contains it;
 // float atomics would make its order, and so its rounding, depend on scheduling.  Here every sum
 // is formed in a fixed order, either
-//  - with 4 or more points per cell, cell by cell: each cell's block in point order, summed per
+//  - with 2.5 or more points per cell, cell by cell: each cell's block in point order, summed per
 //    brick of 2 x 2 x 2 cells into the workspace, followed by a gather in which every table row
 //    sums the brick regions that contain it in a fixed order; or
 //  - with fewer, tile by tile: each tile of 4 x 4 x 4 rows sums the points of the cells whose
@@ -102,7 +102,9 @@ static int sort_layout(const spl_desc* d, int64_t n_pts, SortLayout* L, bool adj
   const size_t gsz = d->dtype == SPL_F64 ? 8 : 4;
   const size_t n_bricks = (size_t)((d->grid[0] + 1) / 2) * ((d->grid[1] + 1) / 2) * ((d->grid[2] + 1) / 2);
   const size_t block_bytes = n_bricks * 125 * (size_t)d->o_pad * gsz;
-  L->dense = adjoint_blocks && n_pts >= 4 * L->n_cells && block_bytes <= ((size_t)4 << 30);
+  // (the crossover of the two forms measured on the Si-like cell: 1.7 to 2.7 points per cell, by term set
+  // and precision)
+  L->dense = adjoint_blocks && 2 * n_pts >= 5 * L->n_cells && block_bytes <= ((size_t)4 << 30);
   // every cell's sorted point range: the adjoint's brick and row-tile forms both look cells up
   L->cell_range = off; off = align_up(off + (adjoint_blocks ? 12 * (size_t)L->n_cells : 0));
   L->blocks = off; off = align_up(off + (L->dense ? block_bytes : 0));
@@ -238,7 +240,7 @@ __device__ __forceinline__ void term_factors(int kind, A wy, A dwy, A d2wy, A wz
 // LDS once and shared by the waves of a workgroup, four points per matrix-core step.
 constexpr int CELL_PB = 32;         // most points per batch
 
-// Dense points (4 or more per cell): the cells are taken in bricks of 2 x 2 x 2 (the last brick of
+// Dense points (2.5 or more per cell): the cells are taken in bricks of 2 x 2 x 2 (the last brick of
 // an axis with an odd count holds one cell along it).  The blocks of a brick's cells cover a
 // region of 5 x 5 x 5 table rows (rows 2 b - 1 .. 2 b + 3 along each axis, before the periodic
 // wrap).  One workgroup of BRICK_WAVES waves per (brick, group of BRICK_WAVES x 16 OT orbitals)
@@ -646,7 +648,7 @@ __global__ __launch_bounds__(256) void k_bwd_brick_gather(Geom g, const A* regio
   }
 }
 
-// Sparse points (fewer than 4 per cell on average): the gradient formed row-tile by row-tile.  Along
+// Sparse points (fewer than 2.5 per cell on average): the gradient formed row-tile by row-tile.  Along
 // an axis a point of cell i touches rows i - 1 .. i + 2 (Eq. b-splineapproximation), so row X
 // receives the points of cells X - 2 .. X + 1, and a tile of 4 x 4 x 4 rows those of a window of
 // 7 x 7 x 7 cells (the whole axis when it has fewer than 7 cells; the last tile of an axis holds
@@ -657,7 +659,7 @@ __global__ __launch_bounds__(256) void k_bwd_brick_gather(Geom g, const A* regio
 // its support), and adds it to the table once.  Every row belongs to one workgroup: no atomics,
 // one launch, and a fixed order of every sum (window cells in order, each cell's points in sorted
 // order).  Each point is multiplied with the whole tile, so the matrix cores do about (7/4)^3 times
-// the useful products; with under 4 points per cell that costs less than a workspace region per
+// the useful products; with under 2.5 points per cell that costs less than a workspace region per
 // brick, which would be read and written for few points.
 //
 // The window's points are taken in batches of CELL_PB across cell boundaries (slot q of the window
@@ -2030,7 +2032,7 @@ int launch_fit_gradient(const spl_desc* d, const void* table, int64_t n_pts, con
   int rc = sort_layout(d, n_pts, &L, true, true);
   if (rc) return rc;
   if (!L.dense)
-    return fail(SPL_EUNSUPPORTED, "the one-pass fit gradient needs at least 4 points per cell (%lld points, %lld cells)",
+    return fail(SPL_EUNSUPPORTED, "the one-pass fit gradient needs at least 2.5 points per cell (%lld points, %lld cells)",
                 (long long)n_pts, (long long)L.n_cells);
   if (!work || work_bytes < (int64_t)L.total)
     return fail(SPL_EINVAL, "spline_fit_gradient_cells needs a workspace of %lld bytes", (long long)L.total);

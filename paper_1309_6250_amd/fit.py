@@ -108,7 +108,7 @@ class FitProblem:
         cells = desc.grid[0] * desc.grid[1] * desc.grid[2]
         under = (1 << 31) - 4096
         self.one_pass = (fused and deterministic and use_lap and desc.dtype == SPL_F32 and not desc.has_lap
-                         and n >= 4 * cells and desc.table_bytes < under and 4 * n * o < under)
+                         and 2 * n >= 5 * cells and desc.table_bytes < under and 4 * n * o < under)
         nb = max(spline_cells_work_bytes(desc, n), spline_backward_work_bytes(desc, n, self.flags))
         if self.one_pass:
             nb = max(nb, spline_fit_gradient_work_bytes(desc, n))

@@ -337,8 +337,9 @@ def test_no_writes_past_outputs(dtype, n_orb):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 def test_backward_deterministic_matches_oracle_and_repeats(case, dtype):
-    """SPL_DETERMINISTIC: cell-sorted accumulation (row tiles at these densities) with ragged tails (5,
-    7, 9 cells per axis here), non-finite points; equal to the oracle and bitwise equal across runs."""
+    """SPL_DETERMINISTIC: cell-sorted accumulation (row tiles, or bricks for the 2.9 points per cell of
+    the ragged case) with ragged tails (5, 7, 9 cells per axis there), non-finite points; equal to the
+    oracle and bitwise equal across runs."""
     d = _desc(case, dtype)
     tab = table_from_oracle(d, case["beta"], dtype, case["lbeta"])
     bq = oq.quantized(case["beta"], dtype)
@@ -396,7 +397,7 @@ def test_backward_deterministic_many_points_per_cell():
 @pytest.mark.parametrize("n_orb", [37, 70])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_backward_deterministic_row_tiles(dtype, n_orb):
-    """Under 4 points per cell the deterministic adjoint forms each tile of 4 x 4 x 4 table rows from
+    """Under 2.5 points per cell the deterministic adjoint forms each tile of 4 x 4 x 4 table rows from
     the points of the cells whose blocks reach it: axes of 4 and 6 cells (the window is the whole axis;
     6 leaves a last tile of 2 rows) and of 19 (a window of 7 of them; a last tile of 3 rows), clustered
     points so that some windows hold several batches of 32 points and some tiles receive none, every
@@ -446,7 +447,7 @@ def test_backward_deterministic_row_tiles(dtype, n_orb):
 @pytest.mark.parametrize("n_orb", [37, 38])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_backward_deterministic_dense_path(dtype, n_orb):
-    """At 4 or more points per cell the deterministic adjoint sums the cell blocks of every brick of
+    """At 2.5 or more points per cell the deterministic adjoint sums the cell blocks of every brick of
     2 x 2 x 2 cells into a 5 x 5 x 5-row region in the workspace and gathers the regions per table row
     (not per row tile): oracle parity with the separate Laplacian table and every upstream term, an
     odd or even orbital count, a ragged grid (odd cell counts leave partial bricks; 5 cells wrap a region onto

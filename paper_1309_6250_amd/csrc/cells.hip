@@ -273,9 +273,11 @@ template <> struct BufLoad<double> {
   }
 };
 
-// The term set of the fit (value and Laplacian upstream gradients, in that order) takes its row
-// weights without a choice at run time; any other set reads each term's kind from CellArgs.
-enum { TSET_ANY = 0, TSET_VL = 1 };
+// The term set of the fit (value and Laplacian upstream gradients, in that order), the full set
+// (value, the three gradient components and the Laplacian, in that order) and a value term alone
+// (the separate Laplacian table's pass) take their row weights without a choice at run time; any
+// other set reads each term's kind from CellArgs.
+enum { TSET_ANY = 0, TSET_VL = 1, TSET_ALL = 2, TSET_V = 3 };
 
 // Position in a brick's sequence of batches: cell c (0..7; 8 once the sequence is exhausted) and the
 // batch's first point b0 within that cell.
@@ -679,7 +681,7 @@ __device__ __forceinline__ A select4(int l, A a0, A a1, A a2, A a3) {
   return l == 0 ? a0 : (l == 1 ? a1 : (l == 2 ? a2 : a3));
 }
 
-template <typename A, int OT, int NT, bool BUF>
+template <typename A, int OT, int NT, int TSET, bool BUF>
 __global__ __launch_bounds__(64 * TILE_WAVES) __attribute__((amdgpu_waves_per_eu(3))) void k_bwd_tiles(CellArgs a) {
   using M = Mfma<A>;
   using Acc = typename M::acc;
@@ -687,6 +689,8 @@ __global__ __launch_bounds__(64 * TILE_WAVES) __attribute__((amdgpu_waves_per_eu
   constexpr int WBW = TILE_WAVES * BW;                 // orbitals of a workgroup
   constexpr int NB = NT <= 2 ? NT : 5;                 // upstream values per point and orbital tile
   static_assert(2 * 64 * TILE_WAVES >= TILE_WIN3, "two window cells per thread");
+  static_assert(TSET == TSET_ANY || NT == (TSET == TSET_VL ? 2 : (TSET == TSET_V ? 1 : 5)),
+                "a fixed term set has its own count");
   __shared__ int s_start[TILE_WIN3];                   // first sorted point of each window cell
   __shared__ int s_pre[TILE_WIN3 + 1];                 // points of the window cells before each
   __shared__ int s_wsum[TILE_WAVES];
@@ -704,7 +708,7 @@ __global__ __launch_bounds__(64 * TILE_WAVES) __attribute__((amdgpu_waves_per_eu
   const int64_t n_work = n_tiles * n_wg;
   const int nw[3] = {min(a.g.n[0], TILE_WIN), min(a.g.n[1], TILE_WIN), min(a.g.n[2], TILE_WIN)};
   const int nwin = nw[0] * nw[1] * nw[2];
-  const int nt = a.n_terms;
+  const int nt = TSET == TSET_ANY ? a.n_terms : NT;
   const SortedPoint<A>* pts = static_cast<const SortedPoint<A>*>(a.pts);
   A* gtab = static_cast<A*>(a.gtable);
   A jm[9], mt[6];
@@ -774,7 +778,7 @@ __global__ __launch_bounds__(64 * TILE_WAVES) __attribute__((amdgpu_waves_per_eu
     };
     // every thread loads (slot clamped into the window, so threads past the batch read a real record)
     auto load_points = [&](int k, Staged& sp) {
-      const int q = min(k * CELL_PB + sj, total - 1);
+      const int q = (int)min((int64_t)k * CELL_PB + sj, (int64_t)total - 1);
       int lo = 0, hi = nwin;                           // s_pre[lo] <= q < s_pre[hi]
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -864,10 +868,13 @@ __global__ __launch_bounds__(64 * TILE_WAVES) __attribute__((amdgpu_waves_per_eu
       for (int c = 0; c < NB; ++c) {
         if (c >= nt) break;
         A q0, q1, q2;
-        term_factors<A>(a.kind[c], wy, dwy, d2wy, wz, dwz, d2wz, jm, mt, q0, q1, q2);
+        const int kind = TSET == TSET_ANY ? a.kind[c] : (TSET == TSET_VL ? (c == 0 ? TERM_VAL : TERM_LAP) : c);
+        term_factors<A>(kind, wy, dwy, d2wy, wz, dwz, d2wz, jm, mt, q0, q1, q2);
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
-          const A av = fmaa(q2, d2wx[rt], fmaa(q1, dwx[rt], q0 * wx[rt]));
+          // a fixed set's value term: Q1 = Q2 = 0, and with finite non-negative weights the two
+          // vanishing products change no bit of q0 w_x
+          const A av = (TSET != TSET_ANY && c == 0) ? q0 * wx[rt] : fmaa(q2, d2wx[rt], fmaa(q1, dwx[rt], q0 * wx[rt]));
 #pragma unroll
           for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = M::step(av, bv[c][ot], acc[rt][ot]);
         }
@@ -980,12 +987,18 @@ static int brick_ot() {
   return sizeof(A) == 4 ? 2 : 1;
 }
 
-// row tiles: the orbital tiles of the brick form
-template <typename A>
-static CellKernel pick_tiles(int nt, bool buf) {
+// row tiles: the orbital tiles of the brick form; tset: TSET_V, TSET_VL or TSET_ALL where the terms are that set
+template <typename A, bool BUF>
+static CellKernel pick_tiles_buf(int nt, int tset) {
   constexpr int OT = sizeof(A) == 4 ? 2 : 1;
-  if (nt <= 2) return buf ? k_bwd_tiles<A, OT, 2, true> : k_bwd_tiles<A, OT, 2, false>;
-  return buf ? k_bwd_tiles<A, OT, 5, true> : k_bwd_tiles<A, OT, 5, false>;
+  if (tset == TSET_V) return k_bwd_tiles<A, OT, 1, TSET_V, BUF>;
+  if (tset == TSET_VL) return k_bwd_tiles<A, OT, 2, TSET_VL, BUF>;
+  if (tset == TSET_ALL) return k_bwd_tiles<A, OT, 5, TSET_ALL, BUF>;
+  return nt <= 2 ? k_bwd_tiles<A, OT, 2, TSET_ANY, BUF> : k_bwd_tiles<A, OT, 5, TSET_ANY, BUF>;
+}
+template <typename A>
+static CellKernel pick_tiles(int nt, int tset, bool buf) {
+  return buf ? pick_tiles_buf<A, true>(nt, tset) : pick_tiles_buf<A, false>(nt, tset);
 }
 
 // The points sorted by cell: keys, permutation, runs of one cell with their point ranges, the number
@@ -1171,7 +1184,11 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
       continue;
     }
     // sparse points: every tile of 4 x 4 x 4 rows at once, each from its window of cells
-    const CellKernel kt = d->dtype == SPL_F64 ? pick_tiles<double>(nt, buf) : pick_tiles<float>(nt, buf);
+    bool all = nt == 5;
+    for (int c = 0; c < nt; ++c) all = all && a.kind[c] == TERM_VAL + c;
+    const bool vl = nt == 2 && a.kind[0] == TERM_VAL && a.kind[1] == TERM_LAP;
+    const int tset = vl ? TSET_VL : (all ? TSET_ALL : (nt == 1 && a.kind[0] == TERM_VAL ? TSET_V : TSET_ANY));
+    const CellKernel kt = d->dtype == SPL_F64 ? pick_tiles<double>(nt, tset, buf) : pick_tiles<float>(nt, tset, buf);
     const int64_t n_tiles = (int64_t)((d->grid[0] + 3) / 4) * ((d->grid[1] + 3) / 4) * ((d->grid[2] + 3) / 4);
     const int64_t n_wg = (a.n_groups + TILE_WAVES - 1) / TILE_WAVES;
     const int grid = (int)std::min<int64_t>(n_tiles * n_wg, 1 << 16);

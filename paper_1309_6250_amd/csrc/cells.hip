@@ -300,7 +300,8 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) void k_bwd_bricks(CellArgs a) {
   // batch is staged while the current one is multiplied, with one barrier per batch (an FP64
   // workgroup has no room for the second buffer: two workgroups per CU need under 80 KB each)
   constexpr int NW = (AHEAD && sizeof(A) == 4) ? 2 : 1;
-  static_assert(TSET == TSET_ANY || NT == 2, "the value-and-Laplacian term set has two terms");
+  static_assert(TSET == TSET_ANY || NT == (TSET == TSET_VL ? 2 : (TSET == TSET_V ? 1 : 5)),
+                "a fixed term set has its own count");
   static_assert(!PAIR || (OT == 2 && sizeof(A) == 4), "paired orbital columns: FP32, two tiles");
   __shared__ int s_p[2][CELL_PB];                      // point indices of two consecutive batches
   __shared__ A s_w[NW][CELL_PB][36];                   // per point: x, y, z  x  (w[4], w'[4], w''[4])
@@ -319,7 +320,7 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) void k_bwd_bricks(CellArgs a) {
   const int64_t n_bricks = (int64_t)nbx * nby * nbz;
   const int n_wg = (a.n_groups + BRICK_WAVES - 1) / BRICK_WAVES;   // orbital groups of a workgroup
   const int64_t n_work = n_bricks * n_wg;
-  const int nt = TSET == TSET_VL ? 2 : a.n_terms;     // terms in use (the fit's set: a constant)
+  const int nt = TSET == TSET_ANY ? a.n_terms : NT;  // terms in use (a fixed set: a constant)
   const SortedPoint<A>* pts = static_cast<const SortedPoint<A>*>(a.pts);
   A jm[9], mt[6];
 #pragma unroll
@@ -470,13 +471,13 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) void k_bwd_bricks(CellArgs a) {
       for (int c = 0; c < NB; ++c) {
         if (c >= nt) break;
         A q0, q1, q2;
-        const int kind = TSET == TSET_VL ? (c == 0 ? TERM_VAL : TERM_LAP) : a.kind[c];
+        const int kind = TSET == TSET_ANY ? a.kind[c] : (TSET == TSET_VL ? (c == 0 ? TERM_VAL : TERM_LAP) : c);
         term_factors<A>(kind, wy, dwy, d2wy, wz, dwz, d2wz, jm, mt, q0, q1, q2);
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
-          // the value term of the fit's set: Q1 = Q2 = 0, and with finite non-negative weights the
-          // two vanishing products change no bit of q0 w_x
-          const A av = (TSET == TSET_VL && c == 0) ? q0 * wx[rt] : fmaa(q2, d2wx[rt], fmaa(q1, dwx[rt], q0 * wx[rt]));
+          // a fixed set's value term: Q1 = Q2 = 0, and with finite non-negative weights the two
+          // vanishing products change no bit of q0 w_x
+          const A av = (TSET != TSET_ANY && c == 0) ? q0 * wx[rt] : fmaa(q2, d2wx[rt], fmaa(q1, dwx[rt], q0 * wx[rt]));
 #pragma unroll
           for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = M::step(av, bv[c][ot], acc[rt][ot]);
         }
@@ -969,18 +970,20 @@ typedef void (*CellKernel)(CellArgs);
 
 // brick regions: FP32 two orbital tiles per wave, FP64 one (64 KB of LDS for a workgroup's region either way)
 template <typename A, bool BUF, bool PAIR>
-static CellKernel pick_bricks_buf(int nt, bool vl) {
+static CellKernel pick_bricks_buf(int nt, int tset) {
   constexpr int OT = sizeof(A) == 4 ? 2 : 1;
-  if (vl) return k_bwd_bricks<A, OT, 2, TSET_VL, BUF, PAIR>;
+  if (tset == TSET_V) return k_bwd_bricks<A, OT, 1, TSET_V, BUF, PAIR>;
+  if (tset == TSET_VL) return k_bwd_bricks<A, OT, 2, TSET_VL, BUF, PAIR>;
+  if (tset == TSET_ALL) return k_bwd_bricks<A, OT, 5, TSET_ALL, BUF, PAIR>;
   return nt <= 2 ? k_bwd_bricks<A, OT, 2, TSET_ANY, BUF, PAIR> : k_bwd_bricks<A, OT, 5, TSET_ANY, BUF, PAIR>;
 }
-// pair: FP32 with an even orbital count and 8-byte aligned upstream arrays
+// pair: FP32 with an even orbital count and 8-byte aligned upstream arrays; tset as for the row tiles
 template <typename A>
-static CellKernel pick_bricks(int nt, bool vl, bool buf, bool pair) {
+static CellKernel pick_bricks(int nt, int tset, bool buf, bool pair) {
   if constexpr (sizeof(A) == 4) {
-    if (pair) return buf ? pick_bricks_buf<A, true, true>(nt, vl) : pick_bricks_buf<A, false, true>(nt, vl);
+    if (pair) return buf ? pick_bricks_buf<A, true, true>(nt, tset) : pick_bricks_buf<A, false, true>(nt, tset);
   }
-  return buf ? pick_bricks_buf<A, true, false>(nt, vl) : pick_bricks_buf<A, false, false>(nt, vl);
+  return buf ? pick_bricks_buf<A, true, false>(nt, tset) : pick_bricks_buf<A, false, false>(nt, tset);
 }
 template <typename A>
 static int brick_ot() {
@@ -1163,11 +1166,15 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
       buf = buf && a.src_bytes[c] >= 0;
       pair = pair && a.src_stride[c] % 2 == 0 && reinterpret_cast<uintptr_t>(a.src[c]) % 8 == 0;
     }
+    // a term set the kernels fix at compile time: the value alone, the fit's pair, all five in order
+    bool all = nt == 5;
+    for (int c = 0; c < nt; ++c) all = all && a.kind[c] == TERM_VAL + c;
+    const bool vl = nt == 2 && a.kind[0] == TERM_VAL && a.kind[1] == TERM_LAP;
+    const int tset = vl ? TSET_VL : (all ? TSET_ALL : (nt == 1 && a.kind[0] == TERM_VAL ? TSET_V : TSET_ANY));
     if (L.dense) {
       // every brick at once into its region, then one gather per table row
-      const bool vl = nt == 2 && a.kind[0] == TERM_VAL && a.kind[1] == TERM_LAP;
-      const CellKernel kb = d->dtype == SPL_F64 ? pick_bricks<double>(nt, vl, buf, false)
-                                                : pick_bricks<float>(nt, vl, buf, pair);
+      const CellKernel kb = d->dtype == SPL_F64 ? pick_bricks<double>(nt, tset, buf, false)
+                                                : pick_bricks<float>(nt, tset, buf, pair);
       const int64_t n_bricks = (int64_t)((d->grid[0] + 1) / 2) * ((d->grid[1] + 1) / 2) * ((d->grid[2] + 1) / 2);
       const int64_t n_wg = (a.n_groups + BRICK_WAVES - 1) / BRICK_WAVES;
       const int grid = (int)std::min<int64_t>(n_bricks * n_wg, 1 << 16);
@@ -1184,10 +1191,6 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
       continue;
     }
     // sparse points: every tile of 4 x 4 x 4 rows at once, each from its window of cells
-    bool all = nt == 5;
-    for (int c = 0; c < nt; ++c) all = all && a.kind[c] == TERM_VAL + c;
-    const bool vl = nt == 2 && a.kind[0] == TERM_VAL && a.kind[1] == TERM_LAP;
-    const int tset = vl ? TSET_VL : (all ? TSET_ALL : (nt == 1 && a.kind[0] == TERM_VAL ? TSET_V : TSET_ANY));
     const CellKernel kt = d->dtype == SPL_F64 ? pick_tiles<double>(nt, tset, buf) : pick_tiles<float>(nt, tset, buf);
     const int64_t n_tiles = (int64_t)((d->grid[0] + 3) / 4) * ((d->grid[1] + 3) / 4) * ((d->grid[2] + 3) / 4);
     const int64_t n_wg = (a.n_groups + TILE_WAVES - 1) / TILE_WAVES;

@@ -69,8 +69,10 @@ __global__ __launch_bounds__(MISFIT_THREADS) void k_misfit_total(const double* p
 //     loss  += w sum over axes, grid points and orbitals of (D beta)^2
 //     gbeta += 2 w sum over axes of D (D beta)        (D is symmetric under the periodic wrap;
 //              D D = the five-point stencil 1 -4 6 -4 1)
-// One thread per (grid point, orbital), in FP64 whatever the storage type; the sum over the
-// fixed grid of MISFIT_BLOCKS workgroups is reduced like the misfit's.
+// MISFIT_BLOCKS workgroups of four waves take the table rows (grid points) in a fixed stride, each
+// wave its own rows, one lane per orbital, in FP64 whatever the storage type: a row's index and its
+// periodic neighbours' offsets are worked out once for all of its orbitals.  Each workgroup's sum is
+// reduced in LDS and the MISFIT_BLOCKS partial sums like the misfit's.
 template <typename TS> struct Coef;
 template <> struct Coef<double> {
   __device__ __forceinline__ static double at(const double* p) { return *p; }
@@ -82,39 +84,48 @@ template <> struct Coef<uint16_t> {   // BF16 bits
   __device__ __forceinline__ static double at(const uint16_t* p) { return (double)__uint_as_float((uint32_t)*p << 16); }
 };
 
+constexpr int PENALTY_THREADS = 256;
+
 template <typename TS, typename GO>
-__global__ __launch_bounds__(MISFIT_THREADS) void k_penalty(Geom g, const TS* beta, int32_t n_orb, double w,
-                                                            GO* gbeta, double* partial) {
-  __shared__ double red[MISFIT_THREADS];
-  const int64_t n = (int64_t)g.n[0] * g.n[1] * g.n[2] * n_orb;
-  const int64_t stride = (int64_t)MISFIT_BLOCKS * MISFIT_THREADS;
+__global__ __launch_bounds__(PENALTY_THREADS) void k_penalty(Geom g, const TS* beta, int32_t n_orb, double w,
+                                                             GO* gbeta, double* partial) {
+  __shared__ double red[PENALTY_THREADS];
+  constexpr int WAVES = PENALTY_THREADS / 64;
+  const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+  const int64_t n_rows = (int64_t)g.n[0] * g.n[1] * g.n[2];
   const int64_t step[3] = {g.s0, g.s1, g.o_pad};
   double s = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * MISFIT_THREADS + threadIdx.x; i < n; i += stride) {
-    const int o = (int)(i % n_orb);
-    const int64_t pt = i / n_orb;
-    const int idx[3] = {(int)(pt / ((int64_t)g.n[1] * g.n[2])), (int)((pt / g.n[2]) % g.n[1]), (int)(pt % g.n[2])};
-    const int64_t base = idx[0] * g.s0 + idx[1] * g.s1 + idx[2] * (int64_t)g.o_pad + o;
-    const double b0 = Coef<TS>::at(beta + base);
-    double grad = 0.0;
+  for (int64_t r = blockIdx.x + (int64_t)wave * MISFIT_BLOCKS; r < n_rows; r += (int64_t)WAVES * MISFIT_BLOCKS) {
+    const int idx[3] = {(int)(r / ((int64_t)g.n[1] * g.n[2])), (int)((r / g.n[2]) % g.n[1]), (int)(r % g.n[2])};
+    const int64_t row = idx[0] * g.s0 + idx[1] * g.s1 + idx[2] * (int64_t)g.o_pad;
+    int64_t nb[3][4];                      // offsets of the neighbours at -2, -1, +1, +2 along each axis, periodic
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const int N = g.n[ax];
-      auto at = [&](int k) {               // beta at offset k along this axis, periodic
-        const int j = (idx[ax] + k + 2 * N) % N;
-        return Coef<TS>::at(beta + base + (int64_t)(j - idx[ax]) * step[ax]);
-      };
-      const double m2 = at(-2), m1 = at(-1), p1 = at(1), p2 = at(2);
-      const double d2 = m1 - 2.0 * b0 + p1;
-      s += d2 * d2;
-      grad += (m2 + p2) - 4.0 * (m1 + p1) + 6.0 * b0;
+      const int ks[4] = {-2, -1, 1, 2};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) nb[ax][q] = (int64_t)((idx[ax] + ks[q] + 2 * N) % N - idx[ax]) * step[ax];
     }
-    GO* gp = gbeta + base;
-    *gp = (GO)((double)*gp + 2.0 * w * grad);
+#pragma unroll 2
+    for (int o = lane; o < n_orb; o += 64) {
+      const int64_t base = row + o;
+      const double b0 = Coef<TS>::at(beta + base);
+      double grad = 0.0;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        const double m2 = Coef<TS>::at(beta + base + nb[ax][0]), m1 = Coef<TS>::at(beta + base + nb[ax][1]);
+        const double p1 = Coef<TS>::at(beta + base + nb[ax][2]), p2 = Coef<TS>::at(beta + base + nb[ax][3]);
+        const double d2 = m1 - 2.0 * b0 + p1;
+        s += d2 * d2;
+        grad += (m2 + p2) - 4.0 * (m1 + p1) + 6.0 * b0;
+      }
+      GO* gp = gbeta + base;
+      *gp = (GO)((double)*gp + 2.0 * w * grad);
+    }
   }
   red[threadIdx.x] = s;
   __syncthreads();
-  for (int h = MISFIT_THREADS / 2; h > 0; h >>= 1) {
+  for (int h = PENALTY_THREADS / 2; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
@@ -185,13 +196,13 @@ int spline_smoothness_penalty(const spl_desc* d, const void* table, double w, vo
   double* partial = static_cast<double*>(work);
   const Geom g = make_geom(d);
   if (d->dtype == SPL_F64)
-    hipLaunchKernelGGL((k_penalty<double, double>), dim3(MISFIT_BLOCKS), dim3(MISFIT_THREADS), 0, s, g,
+    hipLaunchKernelGGL((k_penalty<double, double>), dim3(MISFIT_BLOCKS), dim3(PENALTY_THREADS), 0, s, g,
                        static_cast<const double*>(table), d->n_orb, w, static_cast<double*>(gtable), partial);
   else if (d->dtype == SPL_F32)
-    hipLaunchKernelGGL((k_penalty<float, float>), dim3(MISFIT_BLOCKS), dim3(MISFIT_THREADS), 0, s, g,
+    hipLaunchKernelGGL((k_penalty<float, float>), dim3(MISFIT_BLOCKS), dim3(PENALTY_THREADS), 0, s, g,
                        static_cast<const float*>(table), d->n_orb, w, static_cast<float*>(gtable), partial);
   else
-    hipLaunchKernelGGL((k_penalty<uint16_t, float>), dim3(MISFIT_BLOCKS), dim3(MISFIT_THREADS), 0, s, g,
+    hipLaunchKernelGGL((k_penalty<uint16_t, float>), dim3(MISFIT_BLOCKS), dim3(PENALTY_THREADS), 0, s, g,
                        static_cast<const uint16_t*>(table), d->n_orb, w, static_cast<float*>(gtable), partial);
   if ((rc = hip_fail(hipGetLastError(), "penalty launch"))) return rc;
   hipLaunchKernelGGL(k_misfit_total, dim3(1), dim3(MISFIT_THREADS), 0, s, partial, w, loss);

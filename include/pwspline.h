@@ -345,6 +345,7 @@ int spline_fit_gradient_cells(const spl_desc* d, const void* table, int64_t n_pt
  * range, the brick regions and the loss partial sums).  Host only; may query the current HIP device. */
 int spline_fit_gradient_work_bytes(const spl_desc* d, int64_t n_pts, int64_t* bytes);
 
+
 /*
  * Adjoint of spline_eval_vgl: given dL/dv, dL/dgrad, dL/dlap of a scalar loss L,
  *   gtable += dL/dtable   (the transpose of the 64-coefficient gather, periodic wrap)
@@ -422,6 +423,23 @@ int spline_smoothness_penalty(const spl_desc* d, const void* table, double w, vo
 
 /* Workspace bytes of spline_misfit (a fixed number of FP64 partial sums).  Host only. */
 int spline_misfit_work_bytes(const spl_desc* d, int64_t n, int64_t* bytes);
+
+/*
+ * One Adam step (Kingma and Ba, Algorithm 1) on n stored coefficients, element by element:
+ *   m = beta1 m + (1 - beta1) g,   v = beta2 v + (1 - beta2) g^2,
+ *   param -= lr / (1 - beta1^step) m / (sqrt(v) / sqrt(1 - beta2^step) + eps)
+ * in the precision of the moments: FP64 for SPL_F64, FP32 for SPL_F32 and SPL_BF16 (BF16 parameters
+ * are widened and rounded back to nearest even).  The fit's optimizer.
+ *   dtype        SPL_F64, SPL_F32 or SPL_BF16 (the table's)
+ *   param        device, n values of the table's storage type, UPDATED
+ *   grad, m, v   device, n values of the moment type (FP64 for SPL_F64, else FP32); m, v UPDATED
+ *                (zero before step 1)
+ *   lr, beta1, beta2, eps, step   finite lr; 0 <= beta1, beta2 < 1; eps > 0; step >= 1
+ * n = 0 is a no-op.  Errors: unknown dtype -> SPL_EDTYPE; n < 0, arguments out of range, NULL or
+ * misaligned pointers -> SPL_EINVAL.  Allocates nothing.
+ */
+int spline_adam_step(int32_t dtype, int64_t n, void* param, const void* grad, void* m, void* v, double lr,
+                     double beta1, double beta2, double eps, int32_t step, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Batched evaluation: many independent systems (tables of different sizes and

@@ -10,7 +10,7 @@ from ._lib import (SPL_F64, SPL_F32, SPL_BF16, SPL_OK, SPL_EINVAL, SPL_EGRID, SP
 from .api import (spline_desc_init, spline_build, spline_build_tables, spline_eval_v, spline_eval_vgl,
                   spline_eval_vgl_sorted, spline_sorted_work_bytes, spline_eval_vgl_sorted_noalloc, spline_eval_vgl_cells,
                   spline_cells_work_bytes, spline_fit_terms_cells, spline_fit_gradient_cells,
-                  spline_fit_gradient_work_bytes,
+                  spline_fit_gradient_work_bytes, spline_adam_step,
                   spline_eval_vgl_backward,
                   spline_autotune, spline_tile_for, spline_backward_work_bytes, spline_build_smoothing,
                   spline_smoothing_work_bytes, spline_misfit, spline_misfit_work_bytes, spline_smoothness_penalty,
@@ -22,7 +22,7 @@ from .autograd import SplineVGL, spline_vgl
 __all__ = [
     "spline_desc_init", "spline_build", "spline_build_tables", "spline_eval_v", "spline_eval_vgl_sorted",
     "spline_eval_vgl_cells", "spline_cells_work_bytes", "spline_fit_terms_cells", "spline_fit_gradient_cells",
-    "spline_fit_gradient_work_bytes", "spline_eval_vgl_sorted_noalloc",
+    "spline_fit_gradient_work_bytes", "spline_adam_step", "spline_eval_vgl_sorted_noalloc",
     "spline_sorted_work_bytes", "spline_eval_vgl", "spline_eval_vgl_backward",
     "spline_autotune", "spline_tile_for", "spline_backward_work_bytes", "spline_build_smoothing",
     "spline_smoothing_work_bytes", "spline_misfit", "spline_misfit_work_bytes", "spline_smoothness_penalty",

@@ -29,7 +29,7 @@ EXPORTS = (
     "spline_misfit_work_bytes", "spline_smoothness_penalty", "spline_eval_vgl_cells", "spline_cells_work_bytes",
     "spline_fit_terms_cells", "spline_stream_read", "spline_eval_vgl_sorted_noalloc",
     "spline_batch_plan_get_tiles", "spline_batch_plan_set_tiles", "spline_fit_gradient_cells",
-    "spline_fit_gradient_work_bytes",
+    "spline_fit_gradient_work_bytes", "spline_adam_step",
 )
 
 
@@ -113,6 +113,8 @@ def lib():
             "spline_fit_gradient_cells": (ctypes.c_int, [pd, vp, i64, vp, vp, ctypes.c_double, vp, ctypes.c_double,
                                                          vp, vp, i32, vp, i64, vp]),
             "spline_fit_gradient_work_bytes": (ctypes.c_int, [pd, i64, ctypes.POINTER(i64)]),
+            "spline_adam_step": (ctypes.c_int, [i32, i64, vp, vp, vp, vp, ctypes.c_double, ctypes.c_double,
+                                                ctypes.c_double, ctypes.c_double, i32, vp]),
             "spline_build_smoothing": (ctypes.c_int, [pd, i64, vp, vp, vp, vp, vp]),
             "spline_smoothing_work_bytes": (ctypes.c_int, [pd, ctypes.POINTER(i64)]),
             "spline_batch_plan_create": (ctypes.c_int, [ctypes.POINTER(SplItem), i32, i32p, vp,

@@ -373,6 +373,22 @@ def spline_fit_gradient_cells(desc, table, pos, t_v, w_v, t_lap, w_lap, gtable=N
     return gtable, loss
 
 
+def spline_adam_step(param, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    """One Adam step on a table (or any array of its storage type): param, m and v are updated in
+    place.  param FP64, FP32 or BF16; grad, m, v FP64 for an FP64 param, else FP32."""
+    codes = {torch.float64: SPL_F64, torch.float32: SPL_F32, torch.bfloat16: SPL_BF16}
+    if not isinstance(param, torch.Tensor) or param.dtype not in codes:
+        raise TypeError("param must be an FP64, FP32 or BF16 torch tensor")
+    dtype = codes[param.dtype]
+    _need(param, "param", param.dtype, None)
+    for name, t in (("grad", grad), ("m", m), ("v", v)):
+        _need(t, name, OUT_TORCH[dtype], param.numel())
+    check(lib().spline_adam_step(int(dtype), param.numel(), _ptr(param), _ptr(grad), _ptr(m), _ptr(v), float(lr),
+                                 float(beta1), float(beta2), float(eps), int(step), _stream(stream)),
+          "spline_adam_step")
+    return param
+
+
 def spline_eval_vgl_backward(desc, table, pos, gv=None, ggrad=None, glap=None, gtable=None, gpos=None,
                              want_table=True, want_pos=True, flags=0, stream=None, work=None):
     """Returns (gtable, gpos).  gtable is accumulated into (a fresh zero table if not given).

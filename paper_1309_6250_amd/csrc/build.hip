@@ -20,6 +20,7 @@
 #include <math.h>
 
 #include "common.hpp"
+#include "update.hpp"
 
 namespace pws {
 
@@ -36,13 +37,6 @@ struct LineArgs {
 };
 
 enum { OUT_F64_WORK = 0, OUT_TABLE_F64 = 1, OUT_TABLE_F32 = 2, OUT_TABLE_BF16 = 3 };
-
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);   // quiet NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
 
 template <int OUT>
 __global__ __launch_bounds__(256) void k_cyclic_axis(LineArgs a) {

@@ -10,9 +10,11 @@
 // grid-strided elements on every call and reduce them in a fixed tree in LDS; one workgroup
 // then adds the partial sums in a fixed tree and the result to *loss.  So the loss is
 // reproducible bit for bit, like the deterministic adjoint it feeds.
+#include <algorithm>
 #include <cmath>
 
 #include "common.hpp"
+#include "update.hpp"
 
 namespace pws {
 
@@ -132,6 +134,37 @@ __global__ __launch_bounds__(PENALTY_THREADS) void k_penalty(Geom g, const TS* b
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// spline_adam_step: one Adam update of n stored coefficients from their gradient and moments, in
+// the precision of the moments (FP64 for FP64 tables, else FP32; BF16 coefficients are widened and
+// rounded back to nearest even).  Element-wise, so every element's bits are fixed.
+template <typename TS> struct Stored1;
+template <> struct Stored1<double> {
+  __device__ __forceinline__ static double get(const double* p) { return *p; }
+  __device__ __forceinline__ static void put(double* p, double x) { *p = x; }
+};
+template <> struct Stored1<float> {
+  __device__ __forceinline__ static float get(const float* p) { return *p; }
+  __device__ __forceinline__ static void put(float* p, float x) { *p = x; }
+};
+template <> struct Stored1<uint16_t> {
+  __device__ __forceinline__ static float get(const uint16_t* p) { return __uint_as_float((uint32_t)*p << 16); }
+  __device__ __forceinline__ static void put(uint16_t* p, float x) { *p = f32_to_bf16_rne(x); }
+};
+
+template <typename TS>
+__global__ __launch_bounds__(256) void k_adam(int64_t n, TS* param, const typename Acc<TS>::type* grad,
+                                              typename Acc<TS>::type* m, typename Acc<TS>::type* v,
+                                              AdamCoef<typename Acc<TS>::type> k) {
+  using T = typename Acc<TS>::type;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    T p = Stored1<TS>::get(param + i), mi = m[i], vi = v[i];
+    adam_update<T>(k, grad[i], p, mi, vi);
+    Stored1<TS>::put(param + i, p);
+    m[i] = mi;
+    v[i] = vi;
+  }
+}
+
 }  // namespace pws
 
 using namespace pws;
@@ -207,6 +240,36 @@ int spline_smoothness_penalty(const spl_desc* d, const void* table, double w, vo
   if ((rc = hip_fail(hipGetLastError(), "penalty launch"))) return rc;
   hipLaunchKernelGGL(k_misfit_total, dim3(1), dim3(MISFIT_THREADS), 0, s, partial, w, loss);
   return hip_fail(hipGetLastError(), "penalty total launch");
+}
+
+int spline_adam_step(int32_t dtype, int64_t n, void* param, const void* grad, void* m, void* v, double lr,
+                     double beta1, double beta2, double eps, int32_t step, void* stream) {
+  clear_error();
+  if (dtype != SPL_F64 && dtype != SPL_F32 && dtype != SPL_BF16) return fail(SPL_EDTYPE, "dtype %d", dtype);
+  if (n < 0) return fail(SPL_EINVAL, "n = %lld < 0", (long long)n);
+  if (!std::isfinite(lr) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) ||
+      !(eps > 0.0 && std::isfinite(eps)) || step < 1)
+    return fail(SPL_EINVAL, "lr, beta1, beta2, eps or step out of range");
+  if (n == 0) return SPL_OK;
+  const uintptr_t ps = dtype == SPL_F64 ? 8 : (dtype == SPL_F32 ? 4 : 2), ms = dtype == SPL_F64 ? 8 : 4;
+  if (!param || !grad || !m || !v) return fail(SPL_EINVAL, "NULL param, grad, m or v");
+  if ((uintptr_t)param % ps || (uintptr_t)grad % ms || (uintptr_t)m % ms || (uintptr_t)v % ms)
+    return fail(SPL_EINVAL, "param, grad, m or v misaligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+  if (dtype == SPL_F64)
+    hipLaunchKernelGGL(k_adam<double>, dim3(grid), dim3(256), 0, s, n, static_cast<double*>(param),
+                       static_cast<const double*>(grad), static_cast<double*>(m), static_cast<double*>(v),
+                       adam_coef<double>(lr, beta1, beta2, eps, step));
+  else if (dtype == SPL_F32)
+    hipLaunchKernelGGL(k_adam<float>, dim3(grid), dim3(256), 0, s, n, static_cast<float*>(param),
+                       static_cast<const float*>(grad), static_cast<float*>(m), static_cast<float*>(v),
+                       adam_coef<float>(lr, beta1, beta2, eps, step));
+  else
+    hipLaunchKernelGGL(k_adam<uint16_t>, dim3(grid), dim3(256), 0, s, n, static_cast<uint16_t*>(param),
+                       static_cast<const float*>(grad), static_cast<float*>(m), static_cast<float*>(v),
+                       adam_coef<float>(lr, beta1, beta2, eps, step));
+  return hip_fail(hipGetLastError(), "adam launch");
 }
 
 }  // extern "C"

@@ -9,12 +9,12 @@ Minimizes over the coefficient table beta (FP32 or FP64)
 with wV = 1 / mean V_t^2 and wL = 1 / mean lap_t^2 (or 0), periodic second differences,
 by Adam.  Two forms of the same loss:
 
-- FitProblem.loss_and_grad, used by fit_adam: every term runs in the library's kernels
-  (spline_fit_terms_cells, the cell-wise forward of V and lap that forms the upstream gradients
-  2 w (y - t) as it evaluates and sums the squared residuals in FP64 in a fixed order; the
-  adjoint; spline_smoothness_penalty on the table); the Adam update is torch's fused Adam.
-  Buffers are allocated once.  With fused=False the forward writes V and lap and spline_misfit
-  forms the same gradients from them in a second pass.
+- FitProblem.loss_and_grad and FitProblem.adam_step, used by fit_adam: every term runs in the
+  library's kernels (spline_fit_terms_cells, the cell-wise forward of V and lap that forms the
+  upstream gradients 2 w (y - t) as it evaluates and sums the squared residuals in FP64 in a fixed
+  order; the adjoint; spline_smoothness_penalty on the table), and so does the Adam update
+  (spline_adam_step).  Buffers are allocated once.  With fused=False the forward writes V and lap and
+  spline_misfit forms the same gradients from them in a second pass.
 - make_loss, a differentiable function of the table built on SplineVGL, for use inside a
   larger autograd graph.  Its residuals are formed in the kernel's output precision and
   their squares summed in FP64.
@@ -24,8 +24,9 @@ import math
 import torch
 
 from ._lib import SPL_DETERMINISTIC, SPL_F32, SPL_REUSE_SORT
-from .api import (OUT_TORCH, new_gtable, spline_eval_vgl_backward, spline_eval_vgl_cells, spline_fit_terms_cells,
-                  spline_fit_gradient_cells, spline_fit_gradient_work_bytes,
+from .api import (OUT_TORCH, new_gtable, spline_adam_step, spline_eval_vgl_backward, spline_eval_vgl_cells,
+                  spline_fit_terms_cells, spline_fit_gradient_cells,
+                  spline_fit_gradient_work_bytes,
                   spline_misfit, spline_misfit_work_bytes, spline_smoothness_penalty, spline_cells_work_bytes,
                   spline_backward_work_bytes)
 from .autograd import SplineVGL
@@ -151,6 +152,15 @@ class FitProblem:
             spline_smoothness_penalty(d, beta, self.reg_scale, self.loss, gtable=self.gtable, work=self.misfit_work)
         return self.loss, self.gtable
 
+    def adam_step(self, beta, m, v, lr, step, betas=(0.9, 0.999), eps=1e-8):
+        """One Adam step (Kingma and Ba, Algorithm 1; `step` counts from 1) on the loss at `beta`: the
+        table is updated in place by spline_adam_step from the gradient of loss_and_grad, the moments
+        m and v (FP64 for FP64 tables, else FP32) likewise, and the loss at the old `beta` is returned
+        (a one-element FP64 device tensor, reused by the next call)."""
+        loss, g = self.loss_and_grad(beta)
+        spline_adam_step(beta, g, m, v, lr, step, beta1=betas[0], beta2=betas[1], eps=eps)
+        return loss
+
 
 def fit_adam(desc, table, pos, v_t, lap_t, steps=200, lam=1e-3, lr=None, use_lap=True, callback=None,
              deterministic=True, checkpoint=None, checkpoint_every=0, schedule="cosine", lr_min_frac=0.01):
@@ -162,30 +172,31 @@ def fit_adam(desc, table, pos, v_t, lap_t, steps=200, lam=1e-3, lr=None, use_lap
     lr_min + (lr - lr_min)(1 + cos(pi k / steps)) / 2 with lr_min = lr_min_frac lr (a function of k
     alone, so a resumed fit takes the same steps).
     deterministic: bitwise-reproducible coefficient gradients (cell-sorted accumulation).
-    checkpoint: file path.  If it exists, the fit resumes from it (coefficients, Adam moments and
-    step count, loaded with torch.load(weights_only=True)); every `checkpoint_every` steps (and
+    checkpoint: file path.  If it exists, the fit resumes from it (coefficients, Adam moments m and v
+    and step count, loaded with torch.load(weights_only=True)); every `checkpoint_every` steps (and
     after the last step) the state is written there, to a temporary file first and then renamed.
     With the deterministic gradient a resumed fit retraces the uninterrupted one bit for bit."""
     import os
     prob = FitProblem(desc, pos, v_t, lap_t, lam=lam, use_lap=use_lap, deterministic=deterministic)
-    beta = table.detach().clone().requires_grad_(True)
+    beta = table.detach().clone()
+    mom = torch.float64 if beta.dtype == torch.float64 else torch.float32
+    m = torch.zeros(beta.shape, dtype=mom, device=beta.device)
+    v = torch.zeros_like(m)
     if lr is None:
         lr = 0.1 * float(torch.sqrt(torch.mean(table.detach().to(torch.float64) ** 2)))
-    # torch's fused Adam: the whole update of the table in one kernel
-    opt = torch.optim.Adam([beta], lr=lr, betas=(0.9, 0.999), fused=beta.is_cuda)
     start, done = 0, []
     if checkpoint is not None and os.path.exists(checkpoint):
         state = torch.load(checkpoint, map_location=beta.device, weights_only=True)
         if tuple(state["beta"].shape) != tuple(beta.shape) or state["beta"].dtype != beta.dtype:
             raise ValueError(f"{checkpoint} holds a table of another shape or dtype")
-        with torch.no_grad():
-            beta.copy_(state["beta"])
-        opt.load_state_dict(state["adam"])
+        beta.copy_(state["beta"])
+        m.copy_(state["m"])
+        v.copy_(state["v"])
         start, done = int(state["step"]), [float(x) for x in state["losses"]]
 
     def save(step, losses):
         tmp = checkpoint + ".tmp"
-        torch.save({"beta": beta.detach(), "adam": opt.state_dict(), "step": step,
+        torch.save({"beta": beta, "m": m, "v": v, "step": step,
                     "losses": torch.tensor(done + [float(x) for x in torch.cat(losses).cpu()] if losses else done,
                                            dtype=torch.float64)}, tmp)
         os.replace(tmp, checkpoint)
@@ -195,12 +206,10 @@ def fit_adam(desc, table, pos, v_t, lap_t, steps=200, lam=1e-3, lr=None, use_lap
     lr_min = lr_min_frac * lr
     losses = []
     for step in range(start, steps):
+        lr_k = lr
         if schedule == "cosine":
-            for grp in opt.param_groups:
-                grp["lr"] = lr_min + (lr - lr_min) * 0.5 * (1.0 + math.cos(math.pi * step / steps))
-        loss, g = prob.loss_and_grad(beta.detach())
-        beta.grad = g if g.dtype == beta.dtype else g.to(beta.dtype)
-        opt.step()
+            lr_k = lr_min + (lr - lr_min) * 0.5 * (1.0 + math.cos(math.pi * step / steps))
+        loss = prob.adam_step(beta, m, v, lr_k, step + 1)
         losses.append(loss.clone())
         if callback is not None:
             callback(step, float(losses[-1]))

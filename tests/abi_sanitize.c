@@ -174,6 +174,20 @@ int main(void) {
   expect(spline_fit_gradient_cells(&d, fake, 0, fpos, fake, 1.0, fake, 1.0, fake, fake, 0, NULL, 0, NULL), SPL_OK,
          "fit gradient n == 0");
 
+  /* the element-wise Adam step */
+  expect(spline_adam_step(SPL_F32, 0, NULL, NULL, NULL, NULL, 0.1, 0.9, 0.999, 1e-8, 1, NULL), SPL_OK, "adam n == 0");
+  expect(spline_adam_step(7, 10, fake, fake, fake, fake, 0.1, 0.9, 0.999, 1e-8, 1, NULL), SPL_EDTYPE, "adam dtype");
+  expect(spline_adam_step(SPL_F32, -1, fake, fake, fake, fake, 0.1, 0.9, 0.999, 1e-8, 1, NULL), SPL_EINVAL,
+         "adam n < 0");
+  expect(spline_adam_step(SPL_F32, 10, fake, NULL, fake, fake, 0.1, 0.9, 0.999, 1e-8, 1, NULL), SPL_EINVAL,
+         "adam NULL grad");
+  expect(spline_adam_step(SPL_F64, 10, (char*)fake + 4, fake, fake, fake, 0.1, 0.9, 0.999, 1e-8, 1, NULL), SPL_EINVAL,
+         "adam misaligned param");
+  expect(spline_adam_step(SPL_F32, 10, fake, fake, fake, fake, 0.1, -0.1, 0.999, 1e-8, 1, NULL), SPL_EINVAL,
+         "adam negative beta1");
+  expect(spline_adam_step(SPL_F32, 10, fake, fake, fake, fake, 0.1, 0.9, 0.999, 1e-8, 0, NULL), SPL_EINVAL,
+         "adam step 0");
+
   /* build */
   expect(spline_build(&d, fake, fake, fake, fake, NULL), SPL_EINVAL, "build lap values without lap table");
   expect(spline_build(&d32, fake, NULL, fake, fake, NULL), SPL_EINVAL, "build lap table without values");

@@ -380,3 +380,33 @@ def test_fit_gradient_one_pass_nonfinite_and_unsupported():
         with pytest.raises(P.SplineError) as err:
             P.spline_fit_gradient_cells(dd, P.new_table(dd), x[:nn], tt, 1.0, tt, 1.0)
         assert err.value.code == P.SPL_EUNSUPPORTED
+
+
+# ---------------------------------------------------------------- the fit's Adam step
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_adam_step_matches_torch_adam(dtype):
+    """spline_adam_step against torch.optim.Adam in FP64 on the CPU (the same hyperparameters), over
+    three steps whose gradients differ in scale: an FP64 table to 1e-12 of its largest coefficient,
+    FP32 to 2e-6, and BF16 coefficients (rounded back to BF16 every step, moments in FP32) to four
+    units of their last place."""
+    rng = np.random.default_rng(141)
+    shape = (5, 6, 7, 16)
+    p0 = rng.standard_normal(shape)
+    grads = [rng.standard_normal(shape) * 10.0 ** k for k in (0, -2, 1)]
+    lr, b1, b2, eps = 0.05, 0.9, 0.999, 1e-8
+    ref = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([ref], lr=lr, betas=(b1, b2), eps=eps, foreach=False)
+    store = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dtype]
+    mom = torch.float64 if dtype == "f64" else torch.float32
+    p = torch.tensor(p0).to(store).to(DEV)
+    m = torch.zeros(shape, dtype=mom, device=DEV)
+    v = torch.zeros_like(m)
+    say("Adam step", dtype)
+    for k, g in enumerate(grads, 1):
+        ref.grad = torch.tensor(g)
+        opt.step()
+        P.spline_adam_step(p, torch.tensor(g).to(mom).to(DEV), m, v, lr, k, beta1=b1, beta2=b2, eps=eps)
+    torch.cuda.synchronize()
+    got, want = p.double().cpu(), ref.detach()
+    tol = {"f64": 1e-12, "f32": 2e-6, "bf16": 4 * 2.0 ** -8}[dtype]
+    assert float((got - want).abs().max()) <= tol * float(want.abs().max())

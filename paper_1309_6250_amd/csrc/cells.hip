@@ -410,8 +410,9 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) void k_bwd_bricks(CellArgs a) {
       col_flag[ot] = ocol[ot] ? 0u : 0x80000000u;
     }
     auto load_step = [&](int nb, const int* sp_in, int q, A (&bv)[NB][OT]) {
-      const int j = q + grp;
-      const int pj = j < nb ? sp_in[j] : -1;
+      const int j = q + grp;                           // under CELL_PB
+      // -1 past the batch; no select of a loaded value (the compiler makes a branch of one)
+      const int pj = sp_in[j] | -(int)(j >= nb);
       const bool live = pj >= 0;
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
@@ -423,8 +424,10 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) void k_bwd_bricks(CellArgs a) {
         if constexpr (BUF) {
           const __amdgpu_buffer_rsrc_t rs =
               __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(a.src[c]), (short)0, a.src_bytes[c], 0x00020000);
-          const uint32_t row = live ? (uint32_t)pj * (uint32_t)(a.src_stride[c] * sizeof(A)) : 0u;
-          const uint32_t flag = live ? 0u : 0x80000000u;
+          // no select on the offset either (the compiler would branch to two loads): a dead lane's
+          // pj = -1 carries bit 31 into the offset, whatever the product's low bits
+          const uint32_t row = (uint32_t)pj * (uint32_t)(a.src_stride[c] * sizeof(A));
+          const uint32_t flag = (uint32_t)pj & 0x80000000u;
           if constexpr (PAIR) {
             // n_orb is even, so both orbitals of a pair are in range or neither is
             const auto v2 = __builtin_amdgcn_raw_buffer_load_b64(rs, (row + col_off[0]) | flag | col_flag[0], 0, 0);
@@ -613,16 +616,23 @@ __device__ __forceinline__ int brick_parts(int X, int n, int nb, int32_t stride_
 }
 
 // Dense points, second step: table row (X, Y, Z) receives every brick region row that lands on it
-// (at most 3 along each axis), summed in a fixed order and added to the gradient table.  One
-// workgroup per row (so the lookups are uniform), its threads over the orbitals; the offset of a
-// region row is the sum of its three axis shares, and every region row is loaded before the sum,
-// so the loads are in flight together.
+// (at most 3 along each axis), summed in a fixed order and added to the gradient table.  A thread
+// takes 16 bytes of orbitals of one row (4 FP32 or 2 FP64 values; the rows are padded to 16 bytes),
+// so a wave covers whole rows with 16-byte loads; the offset of a region row is the sum of its
+// three axis shares, and every region row is loaded before the sum, so the loads are in flight
+// together.  Each orbital's sum runs over the region rows in the same order whatever the vector
+// width.  Orbitals of the row's padding are read and summed but not written.
 constexpr int GATHER_MAX = 27;
 
 template <typename A>
 __global__ __launch_bounds__(256) void k_bwd_brick_gather(Geom g, const A* regions, int32_t n_orb, int32_t o_pad,
-                                                          A* gtab) {
-  const int64_t row = blockIdx.x;
+                                                          int32_t per_row, int64_t n_rows, A* gtab) {
+  constexpr int V = 16 / (int)sizeof(A);
+  typedef A Vec __attribute__((ext_vector_type(V)));
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t row = idx / per_row;
+  if (row >= n_rows) return;
+  const int o = (int)(idx - row * per_row) * V;        // first orbital of the thread
   const int Z = (int)(row % g.n[2]);
   const int Y = (int)((row / g.n[2]) % g.n[1]);
   const int X = (int)(row / ((int64_t)g.n[2] * g.n[1]));
@@ -633,22 +643,38 @@ __global__ __launch_bounds__(256) void k_bwd_brick_gather(Geom g, const A* regio
   const int kx = brick_parts(X, g.n[0], nbx, sx, 25 * o_pad, px);
   const int ky = brick_parts(Y, g.n[1], nby, sy, 5 * o_pad, py);
   const int kz = brick_parts(Z, g.n[2], nbz, sz, o_pad, pz);
-  for (int o = threadIdx.x; o < n_orb; o += blockDim.x) {
-    A part[GATHER_MAX];
+  Vec part[GATHER_MAX];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j)
+    for (int j = 0; j < 3; ++j)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const bool live = i < kx && j < ky && k < kz;
-          part[9 * i + 3 * j + k] = live ? regions[(int64_t)(px[i] + py[j] + pz[k]) + o] : A(0);
-        }
-    A sum = A(0);
+      for (int k = 0; k < 3; ++k) {
+        const bool live = i < kx && j < ky && k < kz;
+        part[9 * i + 3 * j + k] =
+            live ? *reinterpret_cast<const Vec*>(regions + (int64_t)(px[i] + py[j] + pz[k]) + o) : Vec(0);
+      }
+  Vec sum = Vec(0);
 #pragma unroll
-    for (int c = 0; c < GATHER_MAX; ++c) sum += part[c];
-    gtab[row * o_pad + o] += sum;
-  }
+  for (int c = 0; c < GATHER_MAX; ++c) sum += part[c];
+  Vec* dst = reinterpret_cast<Vec*>(gtab + row * o_pad + o);
+  Vec cur = *dst;
+#pragma unroll
+  for (int v = 0; v < V; ++v)
+    if (o + v < n_orb) cur[v] += sum[v];
+  *dst = cur;
+}
+
+// the gather over every table row: 16 bytes of orbitals per thread
+template <typename A>
+static int launch_brick_gather(const spl_desc* d, const Geom& g, const void* regions, void* gtable, hipStream_t stream) {
+  constexpr int V = 16 / (int)sizeof(A);
+  const int per_row = (d->n_orb + V - 1) / V;          // within the padded row: o_pad is a multiple of V
+  const int64_t n_rows = (int64_t)d->grid[0] * d->grid[1] * d->grid[2];
+  const int64_t blocks = (n_rows * per_row + 255) / 256;
+  hipLaunchKernelGGL(k_bwd_brick_gather<A>, dim3((unsigned)blocks), dim3(256), 0, stream, g,
+                     static_cast<const A*>(regions), d->n_orb, d->o_pad, (int32_t)per_row, n_rows, static_cast<A*>(gtable));
+  return hip_fail(hipGetLastError(), "row gather launch");
 }
 
 // Sparse points (fewer than 2.5 per cell on average): the gradient formed row-tile by row-tile.  Along
@@ -1180,14 +1206,9 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
       const int grid = (int)std::min<int64_t>(n_bricks * n_wg, 1 << 16);
       hipLaunchKernelGGL(kb, dim3(grid), dim3(64 * BRICK_WAVES), 0, stream, a);
       if ((rc = hip_fail(hipGetLastError(), "brick region launch"))) return rc;
-      const int gthreads = d->o_pad >= 256 ? 256 : (d->o_pad + 63) / 64 * 64;
-      if (d->dtype == SPL_F64)
-        hipLaunchKernelGGL(k_bwd_brick_gather<double>, dim3((unsigned)L.n_cells), dim3(gthreads), 0, stream, g,
-                           static_cast<const double*>(a.blocks), d->n_orb, d->o_pad, static_cast<double*>(a.gtable));
-      else
-        hipLaunchKernelGGL(k_bwd_brick_gather<float>, dim3((unsigned)L.n_cells), dim3(gthreads), 0, stream, g,
-                           static_cast<const float*>(a.blocks), d->n_orb, d->o_pad, static_cast<float*>(a.gtable));
-      if ((rc = hip_fail(hipGetLastError(), "row gather launch"))) return rc;
+      rc = d->dtype == SPL_F64 ? launch_brick_gather<double>(d, g, a.blocks, a.gtable, stream)
+                               : launch_brick_gather<float>(d, g, a.blocks, a.gtable, stream);
+      if (rc) return rc;
       continue;
     }
     // sparse points: every tile of 4 x 4 x 4 rows at once, each from its window of cells
@@ -1628,8 +1649,9 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) __attribute__((amdgpu_waves_per_e
       sp.t = rec->t[sax];
       sp.p = rec->p;
     };
+    // a point's target row as a byte offset (under 2^31: each target array is under 2 GiB), -1: none
     auto stage_index = [&](const BrickBatch& b, const Staged& sp, int* sp_out) {
-      if (sax == 0 && sj < count(b)) sp_out[sj] = (unsigned)sp.p < (unsigned)a.n_pts ? sp.p : -1;
+      if (sax == 0 && sj < count(b)) sp_out[sj] = (unsigned)sp.p < (unsigned)a.n_pts ? (int)((uint32_t)sp.p * row_bytes) : -1;
     };
     auto stage_weights = [&](const BrickBatch& b, const Staged& sp, A (*sw)[36]) {
       if (sj < count(b)) {
@@ -1650,13 +1672,18 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) __attribute__((amdgpu_waves_per_e
       wrap4(min(X, a.g.n[0] - 1), a.g.n[0], ix);
       wrap4(min(Y, a.g.n[1] - 1), a.g.n[1], iy);
       wrap4(min(Z, a.g.n[2] - 1), a.g.n[2], iz);
+      // the lane's part of the offset (third axis, orbital) in the vector offset, the part shared by
+      // the wave (first two axes) in the scalar offset; an orbital past n_orb sets bit 31 of the
+      // vector offset, out of range with or without the scalar part
+      uint32_t voff[OT];
+#pragma unroll
+      for (int ot = 0; ot < OT; ++ot) voff[ot] = ((uint32_t)iz[grp] * (uint32_t)a.g.o_pad * 4u + col_off[ot]) | col_flag[ot];
 #pragma unroll
       for (int ks = 0; ks < 16; ++ks) {
-        const uint32_t row = (uint32_t)((int64_t)ix[ks >> 2] * a.g.s0 + (int64_t)iy[ks & 3] * a.g.s1 +
-                                        (int64_t)iz[grp] * a.g.o_pad) * 4u;
+        const int soff = (int)((uint32_t)((int64_t)ix[ks >> 2] * a.g.s0 + (int64_t)iy[ks & 3] * a.g.s1) * 4u);
 #pragma unroll
         for (int ot = 0; ot < OT; ++ot)
-          blk[ks][ot] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs_tab, (row + col_off[ot]) | col_flag[ot], 0, 0));
+          blk[ks][ot] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs_tab, voff[ot], soff, 0));
       }
     };
     // the targets of a batch, in the forward's output layout: tile mt, lane group k, element e is
@@ -1671,7 +1698,7 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) __attribute__((amdgpu_waves_per_e
           const int pj = j < nb ? sp_in[j] : -1;
           const bool live = pj >= 0;
           valid |= live ? 1u << (4 * mt_ + e) : 0u;
-          const uint32_t row = live ? (uint32_t)pj * row_bytes : 0u;
+          const uint32_t row = live ? (uint32_t)pj : 0u;
           const uint32_t flag = live ? 0u : 0x80000000u;
 #pragma unroll
           for (int ot = 0; ot < OT; ++ot) {
@@ -1732,9 +1759,14 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) __attribute__((amdgpu_waves_per_e
         for (int c = 0; c < 2; ++c)
 #pragma unroll
           for (int ot = 0; ot < OT; ++ot) {
+            // an entry not written adds w 0 0 = +-0 (w finite) to a sum that starts at +0 and so is
+            // never -0: the same bits as skipping it, with no branch (the compiler branches on a
+            // select of a loaded value)
+            const bool use = ok && ocol[ot];
             const A res = accf[c][ot][e] - tg[mt_][c][ot][e];
-            if (ok && ocol[ot]) sq = fma(a.w[c] * (double)res, (double)res, sq);
-            gd[c][ot][e] = (ok && ocol[ot]) ? two_w[c] * res : A(0);
+            const double rd = use ? (double)res : 0.0;
+            sq = fma(a.w[c] * rd, rd, sq);
+            gd[c][ot][e] = use ? two_w[c] * res : A(0);
           }
       }
 #pragma unroll
@@ -2091,10 +2123,7 @@ int launch_fit_gradient(const spl_desc* d, const void* table, int64_t n_pts, con
   hipLaunchKernelGGL(k_fit_bricks, dim3((unsigned)std::min<int64_t>(n_bricks * n_wg, 1 << 16)),
                      dim3(64 * BRICK_WAVES), 0, stream, a);
   if ((rc = hip_fail(hipGetLastError(), "fit gradient launch"))) return rc;
-  const int gthreads = d->o_pad >= 256 ? 256 : (d->o_pad + 63) / 64 * 64;
-  hipLaunchKernelGGL(k_bwd_brick_gather<float>, dim3((unsigned)L.n_cells), dim3(gthreads), 0, stream, a.g,
-                     static_cast<const float*>(a.blocks), d->n_orb, d->o_pad, static_cast<float*>(gtable));
-  if ((rc = hip_fail(hipGetLastError(), "row gather launch"))) return rc;
+  if ((rc = launch_brick_gather<float>(d, a.g, a.blocks, gtable, stream))) return rc;
   // the loss: the same two fixed-order sums over the same partials as the fit terms
   double* block_sum = a.partial + std::min<int64_t>(n_pts, L.n_cells) * (int64_t)((d->n_orb + 15) / 16);
   hipLaunchKernelGGL(k_fit_blocks, dim3(FIT_SUM_BLOCKS), dim3(FIT_SUM_THREADS), 0, stream, cs.finite_runs,

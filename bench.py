@@ -589,8 +589,9 @@ def fit_rows(steps, warmup, adam_steps=200, cg_iters=400):
                                      "lambda": 1e-3, "deterministic_gradient": True, "heldout": res,
                                      "note": "per step: spline_fit_gradient_cells (cell-wise forward, misfit of V "
                                              "and lap, and adjoint in one pass) and the smoothness penalty on the "
-                                             "cell sort of the first step; torch's fused Adam on the "
-                                             "16.8 MB table; after 2 untimed steps"}
+                                             "cell sort of the first step; the library's Adam update "
+                                             "(spline_adam_step) of the 16.8 MB table and its moments; after 2 "
+                                             "untimed steps"}
     return out
 
 

@@ -410,9 +410,13 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) void k_bwd_bricks(CellArgs a) {
       col_flag[ot] = ocol[ot] ? 0u : 0x80000000u;
     }
     auto load_step = [&](int nb, const int* sp_in, int q, A (&bv)[NB][OT]) {
-      const int j = q + grp;                           // under CELL_PB
-      // -1 past the batch; no select of a loaded value (the compiler makes a branch of one)
-      const int pj = sp_in[j] | -(int)(j >= nb);
+      const int j = q + grp;
+      // -1 past the batch.  With the batch's values loaded ahead (j under CELL_PB), no select of a
+      // loaded value, of which the compiler would make a branch; otherwise the next step's j can
+      // pass the batch's slots and only the select keeps the read inside them
+      int pj;
+      if constexpr (AHEAD) pj = sp_in[j] | -(int)(j >= nb);
+      else pj = j < nb ? sp_in[j] : -1;
       const bool live = pj >= 0;
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
@@ -424,10 +428,11 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) void k_bwd_bricks(CellArgs a) {
         if constexpr (BUF) {
           const __amdgpu_buffer_rsrc_t rs =
               __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(a.src[c]), (short)0, a.src_bytes[c], 0x00020000);
-          // no select on the offset either (the compiler would branch to two loads): a dead lane's
-          // pj = -1 carries bit 31 into the offset, whatever the product's low bits
-          const uint32_t row = (uint32_t)pj * (uint32_t)(a.src_stride[c] * sizeof(A));
-          const uint32_t flag = (uint32_t)pj & 0x80000000u;
+          // ahead: no select on the offset either (the compiler would branch to two loads): a dead
+          // lane's pj = -1 carries bit 31 into the offset, whatever the product's low bits
+          const uint32_t stride_b = (uint32_t)(a.src_stride[c] * sizeof(A));
+          const uint32_t row = AHEAD ? (uint32_t)pj * stride_b : (live ? (uint32_t)pj * stride_b : 0u);
+          const uint32_t flag = AHEAD ? ((uint32_t)pj & 0x80000000u) : (live ? 0u : 0x80000000u);
           if constexpr (PAIR) {
             // n_orb is even, so both orbitals of a pair are in range or neither is
             const auto v2 = __builtin_amdgcn_raw_buffer_load_b64(rs, (row + col_off[0]) | flag | col_flag[0], 0, 0);

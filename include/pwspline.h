@@ -321,9 +321,10 @@ int spline_fit_terms_cells(const spl_desc* d, const void* table, int64_t n_pts, 
  *   *loss  += w_v sum (y_v - t_v)^2 + w_lap sum (y_lap - t_lap)^2                (ACCUMULATED)
  *   gtable += d/dtable of those two sums                                            (ACCUMULATED)
  * that is, spline_fit_terms_cells followed by spline_eval_vgl_backward (SPL_DETERMINISTIC) of its
- * upstream gradients, with the same results bit for bit, but the upstream gradients are never
- * stored: each batch of a cell's points is evaluated, compared with its targets and multiplied back
- * on the matrix cores in one kernel.  (The fit's regression counterpart of the smoothing spline of
+ * upstream gradients, with the same results bit for bit (for a lattice with orthogonal vectors the
+ * same numbers: the vanishing mixed terms of the Laplacian are skipped, so an exact zero may differ
+ * in sign), but the upstream gradients are never stored: each batch of a cell's points is
+ * evaluated, compared with its targets and multiplied back on the matrix cores in one kernel.  (The fit's regression counterpart of the smoothing spline of
  * App. A; the adjoint is the transpose of Eq. b-splineapproximation.)
  *   t_v, t_lap   device, FP32 [n_pts][n_orb] in the caller's point order (both required)
  *   w_v, w_lap   the terms' weights, finite

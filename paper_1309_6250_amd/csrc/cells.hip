@@ -276,8 +276,20 @@ template <> struct BufLoad<double> {
 // The term set of the fit (value and Laplacian upstream gradients, in that order), the full set
 // (value, the three gradient components and the Laplacian, in that order) and a value term alone
 // (the separate Laplacian table's pass) take their row weights without a choice at run time; any
-// other set reads each term's kind from CellArgs.
-enum { TSET_ANY = 0, TSET_VL = 1, TSET_ALL = 2, TSET_V = 3 };
+// other set reads each term's kind from CellArgs.  TSET_VLD is the fit's pair for a diagonal metric
+// (orthogonal lattice vectors): the Laplacian's mixed terms, exact zeros there, are skipped, which
+// gives the same numbers (an exact zero may differ in sign); the row tiles take it as TSET_VL.
+enum { TSET_ANY = 0, TSET_VL = 1, TSET_ALL = 2, TSET_V = 3, TSET_VLD = 4 };
+
+// The Laplacian's row-weight factors for a diagonal metric (M01 = M02 = M12 = 0): Q1 = 0, and Q0
+// without its 2 M12 w_y' w_z' term; the general form's products of those zeros change no nonzero
+// value.
+template <typename A>
+__device__ __forceinline__ void lap_factors_diag(A wy, A d2wy, A wz, A d2wz, const A (&mt)[6], A& q0, A& q1, A& q2) {
+  q2 = mt[0] * (wy * wz);
+  q1 = A(0);
+  q0 = fmaa(mt[1] * d2wy, wz, (mt[2] * wy) * d2wz);
+}
 
 // Position in a brick's sequence of batches: cell c (0..7; 8 once the sequence is exhausted) and the
 // batch's first point b0 within that cell.
@@ -300,7 +312,7 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) void k_bwd_bricks(CellArgs a) {
   // batch is staged while the current one is multiplied, with one barrier per batch (an FP64
   // workgroup has no room for the second buffer: two workgroups per CU need under 80 KB each)
   constexpr int NW = (AHEAD && sizeof(A) == 4) ? 2 : 1;
-  static_assert(TSET == TSET_ANY || NT == (TSET == TSET_VL ? 2 : (TSET == TSET_V ? 1 : 5)),
+  static_assert(TSET == TSET_ANY || NT == (TSET == TSET_VL || TSET == TSET_VLD ? 2 : (TSET == TSET_V ? 1 : 5)),
                 "a fixed term set has its own count");
   static_assert(!PAIR || (OT == 2 && sizeof(A) == 4), "paired orbital columns: FP32, two tiles");
   __shared__ int s_p[2][CELL_PB];                      // point indices of two consecutive batches
@@ -479,13 +491,17 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) void k_bwd_bricks(CellArgs a) {
       for (int c = 0; c < NB; ++c) {
         if (c >= nt) break;
         A q0, q1, q2;
-        const int kind = TSET == TSET_ANY ? a.kind[c] : (TSET == TSET_VL ? (c == 0 ? TERM_VAL : TERM_LAP) : c);
-        term_factors<A>(kind, wy, dwy, d2wy, wz, dwz, d2wz, jm, mt, q0, q1, q2);
+        constexpr bool DIAG = TSET == TSET_VLD;
+        const int kind = TSET == TSET_ANY ? a.kind[c]
+                                          : (TSET == TSET_VL || DIAG ? (c == 0 ? TERM_VAL : TERM_LAP) : c);
+        if (DIAG && c == 1) lap_factors_diag<A>(wy, d2wy, wz, d2wz, mt, q0, q1, q2);
+        else term_factors<A>(kind, wy, dwy, d2wy, wz, dwz, d2wz, jm, mt, q0, q1, q2);
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
           // a fixed set's value term: Q1 = Q2 = 0, and with finite non-negative weights the two
-          // vanishing products change no bit of q0 w_x
-          const A av = (TSET != TSET_ANY && c == 0) ? q0 * wx[rt] : fmaa(q2, d2wx[rt], fmaa(q1, dwx[rt], q0 * wx[rt]));
+          // vanishing products change no bit of q0 w_x (so too Q1 = 0 of a diagonal metric)
+          const A av = (TSET != TSET_ANY && c == 0) ? q0 * wx[rt]
+                       : (DIAG ? fmaa(q2, d2wx[rt], q0 * wx[rt]) : fmaa(q2, d2wx[rt], fmaa(q1, dwx[rt], q0 * wx[rt])));
 #pragma unroll
           for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = M::step(av, bv[c][ot], acc[rt][ot]);
         }
@@ -1011,6 +1027,7 @@ static CellKernel pick_bricks_buf(int nt, int tset) {
   constexpr int OT = sizeof(A) == 4 ? 2 : 1;
   if (tset == TSET_V) return k_bwd_bricks<A, OT, 1, TSET_V, BUF, PAIR>;
   if (tset == TSET_VL) return k_bwd_bricks<A, OT, 2, TSET_VL, BUF, PAIR>;
+  if (tset == TSET_VLD) return k_bwd_bricks<A, OT, 2, TSET_VLD, BUF, PAIR>;
   if (tset == TSET_ALL) return k_bwd_bricks<A, OT, 5, TSET_ALL, BUF, PAIR>;
   return nt <= 2 ? k_bwd_bricks<A, OT, 2, TSET_ANY, BUF, PAIR> : k_bwd_bricks<A, OT, 5, TSET_ANY, BUF, PAIR>;
 }
@@ -1032,7 +1049,7 @@ template <typename A, bool BUF>
 static CellKernel pick_tiles_buf(int nt, int tset) {
   constexpr int OT = sizeof(A) == 4 ? 2 : 1;
   if (tset == TSET_V) return k_bwd_tiles<A, OT, 1, TSET_V, BUF>;
-  if (tset == TSET_VL) return k_bwd_tiles<A, OT, 2, TSET_VL, BUF>;
+  if (tset == TSET_VL || tset == TSET_VLD) return k_bwd_tiles<A, OT, 2, TSET_VL, BUF>;
   if (tset == TSET_ALL) return k_bwd_tiles<A, OT, 5, TSET_ALL, BUF>;
   return nt <= 2 ? k_bwd_tiles<A, OT, 2, TSET_ANY, BUF> : k_bwd_tiles<A, OT, 5, TSET_ANY, BUF>;
 }
@@ -1207,7 +1224,12 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
     bool all = nt == 5;
     for (int c = 0; c < nt; ++c) all = all && a.kind[c] == TERM_VAL + c;
     const bool vl = nt == 2 && a.kind[0] == TERM_VAL && a.kind[1] == TERM_LAP;
-    const int tset = vl ? TSET_VL : (all ? TSET_ALL : (nt == 1 && a.kind[0] == TERM_VAL ? TSET_V : TSET_ANY));
+    // the metric as the kernels round it (FP64 tables in FP64, else FP32)
+    bool diag = true;
+    for (int i = 3; i < 6; ++i)
+      diag = diag && (d->dtype == SPL_F64 ? d->metric[i] == 0.0 : (float)d->metric[i] == 0.0f);
+    const int tset = vl ? (diag ? TSET_VLD : TSET_VL)
+                        : (all ? TSET_ALL : (nt == 1 && a.kind[0] == TERM_VAL ? TSET_V : TSET_ANY));
     if (L.dense) {
       // every brick at once into its region, then one gather per table row
       const CellKernel kb = d->dtype == SPL_F64 ? pick_bricks<double>(nt, tset, buf, false)
@@ -1753,13 +1775,8 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) __attribute__((amdgpu_waves_per_e
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
             A q0, q1, q2;
-            if (DIAG && c == 1) {
-              q2 = mt[0] * (wy * wz);
-              q1 = A(0);
-              q0 = fmaa(mt[1] * d2wy, wz, (mt[2] * wy) * d2wz);
-            } else {
-              term_factors<A>(c == 0 ? TERM_VAL : TERM_LAP, wy, dwy, d2wy, wz, dwz, d2wz, jm, mt, q0, q1, q2);
-            }
+            if (DIAG && c == 1) lap_factors_diag<A>(wy, d2wy, wz, d2wz, mt, q0, q1, q2);
+            else term_factors<A>(c == 0 ? TERM_VAL : TERM_LAP, wy, dwy, d2wy, wz, dwz, d2wz, jm, mt, q0, q1, q2);
 #pragma unroll
             for (int l = 0; l < 4; ++l) {
               // the value term: the vanishing Q1, Q2 products change no bit of q0 w_x (finite,
@@ -1813,13 +1830,8 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) __attribute__((amdgpu_waves_per_e
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
           A q0, q1, q2;
-          if (DIAG && c == 1) {
-            q2 = mt[0] * (wy * wz);
-            q1 = A(0);
-            q0 = fmaa(mt[1] * d2wy, wz, (mt[2] * wy) * d2wz);
-          } else {
-            term_factors<A>(c == 0 ? TERM_VAL : TERM_LAP, wy, dwy, d2wy, wz, dwz, d2wz, jm, mt, q0, q1, q2);
-          }
+          if (DIAG && c == 1) lap_factors_diag<A>(wy, d2wy, wz, d2wz, mt, q0, q1, q2);
+          else term_factors<A>(c == 0 ? TERM_VAL : TERM_LAP, wy, dwy, d2wy, wz, dwz, d2wz, jm, mt, q0, q1, q2);
 #pragma unroll
           for (int rt = 0; rt < 4; ++rt) {
             const A av = c == 0 ? q0 * wx[rt] : (DIAG ? fmaa(q2, d2wx[rt], q0 * wx[rt]) : fmaa(q2, d2wx[rt], fmaa(q1, dwx[rt], q0 * wx[rt])));

@@ -348,7 +348,8 @@ def spline_fit_gradient_cells(desc, table, pos, t_v, w_v, t_lap, w_lap, gtable=N
                               stream=None):
     """The fit's value and Laplacian misfit and its coefficient gradient in one pass: returns
     (gtable, loss), both accumulated into (fresh zeros if not given); the same bits as
-    spline_fit_terms_cells followed by the deterministic spline_eval_vgl_backward.  FP32 tables,
+    spline_fit_terms_cells followed by the deterministic spline_eval_vgl_backward (for orthogonal
+    lattice vectors the same numbers, an exact zero possibly of the other sign).  FP32 tables,
     dense points (SPL_EUNSUPPORTED otherwise).  flags: SPL_REUSE_SORT when `work` already holds this
     function's cell sort of these same points."""
     n = _check_inputs(desc, table, pos)

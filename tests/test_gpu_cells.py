@@ -382,6 +382,56 @@ def test_fit_gradient_one_pass_nonfinite_and_unsupported():
         assert err.value.code == P.SPL_EUNSUPPORTED
 
 
+
+ORTHO = np.diag([7.0, 6.2, 8.3])    # orthogonal, axis-aligned lattice vectors: the metric is exactly diagonal
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_diagonal_metric_forms_against_oracle(dtype):
+    """An orthorhombic cell (the metric's off-diagonal entries exactly 0) takes the forms that skip the
+    Laplacian's mixed terms: the deterministic adjoint of value and Laplacian upstream values at dense
+    points against the oracle's adjoint, and (FP32) the one-pass fit gradient against the oracle's loss
+    and gradient, and against the fit terms followed by the adjoint (equal values).  A ragged grid and
+    an odd orbital count."""
+    from oracle import adjoint as oadj
+    rng = np.random.default_rng(151)
+    grid, n_orb, n = (6, 5, 7), 37, 2000
+    beta = rng.standard_normal(grid + (n_orb,))
+    d = P.spline_desc_init(ORTHO, grid, n_orb, dtype)
+    assert d.metric[3] == 0.0 and d.metric[4] == 0.0 and d.metric[5] == 0.0
+    tab = table_from_oracle(d, beta, dtype)
+    bq = oq.quantized(beta, dtype)
+    pos = rng.uniform(-3, 3, size=(n, 3)) @ ORTHO / 3.0
+    x = to_dev(pos)
+    od = torch.float64 if dtype == "f64" else torch.float32
+    nd = np.float64 if dtype == "f64" else np.float32
+    gv, gl = rng.standard_normal((n, n_orb)), rng.standard_normal((n, n_orb))
+    say("diagonal metric: deterministic adjoint", dtype)
+    gt, _ = P.spline_eval_vgl_backward(d, tab, x, to_dev(gv, od), None, to_dev(gl, od), want_pos=False,
+                                       flags=P.SPL_DETERMINISTIC)
+    torch.cuda.synchronize()
+    rb, _, _ = oadj.vgl_backward(bq, ORTHO, pos, gv, None, gl)
+    tol = 1e-12 if dtype == "f64" else 2e-5
+    assert normwise(gt.double().cpu().numpy()[0, ..., :n_orb], rb) <= tol
+    if dtype == "f64":
+        return
+    ov, _, ol = oeval.eval_vgl(bq, ORTHO, pos)
+    t_v = (ov + 0.1 * rng.standard_normal(ov.shape)).astype(nd)
+    t_l = (ol + 0.5 * rng.standard_normal(ol.shape)).astype(nd)
+    wv, wl = 0.7, 0.05
+    say("diagonal metric: one-pass fit gradient")
+    tv, tl = to_dev(t_v, od), to_dev(t_l, od)
+    gt1, loss = P.spline_fit_gradient_cells(d, tab, x, tv, wv, tl, wl)
+    rgt, rloss = _fit_gradient_reference(d, tab, x, tv, wv, tl, wl, 0.0, torch.zeros_like(gt1))
+    torch.cuda.synchronize()
+    rv, rl = ov - t_v.astype(np.float64), ol - t_l.astype(np.float64)
+    ref = wv * np.sum(rv ** 2) + wl * np.sum(rl ** 2)
+    assert abs(float(loss) - ref) <= 1e-5 * ref
+    rg, _, _ = oadj.vgl_backward(bq, ORTHO, pos, 2 * wv * rv, None, 2 * wl * rl)
+    assert normwise(gt1.double().cpu().numpy()[0, ..., :n_orb], rg) <= 2e-5
+    assert torch.equal(gt1, rgt)
+    assert float(loss) == float(rloss)
+
 # ---------------------------------------------------------------- the fit's Adam step
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 def test_adam_step_matches_torch_adam(dtype):

@@ -277,9 +277,10 @@ template <> struct BufLoad<double> {
 // (value, the three gradient components and the Laplacian, in that order) and a value term alone
 // (the separate Laplacian table's pass) take their row weights without a choice at run time; any
 // other set reads each term's kind from CellArgs.  TSET_VLD is the fit's pair for a diagonal metric
-// (orthogonal lattice vectors): the Laplacian's mixed terms, exact zeros there, are skipped, which
-// gives the same numbers (an exact zero may differ in sign); the row tiles take it as TSET_VL.
-enum { TSET_ANY = 0, TSET_VL = 1, TSET_ALL = 2, TSET_V = 3, TSET_VLD = 4 };
+// (orthogonal lattice vectors) and TSET_ALLD the full set for a diagonal Jacobian (orthogonal
+// vectors along the Cartesian axes): the products of the zero entries, exact zeros in the general
+// form, are skipped, which gives the same numbers (an exact zero may differ in sign).
+enum { TSET_ANY = 0, TSET_VL = 1, TSET_ALL = 2, TSET_V = 3, TSET_VLD = 4, TSET_ALLD = 5 };
 
 // The Laplacian's row-weight factors for a diagonal metric (M01 = M02 = M12 = 0): Q1 = 0, and Q0
 // without its 2 M12 w_y' w_z' term; the general form's products of those zeros change no nonzero
@@ -289,6 +290,37 @@ __device__ __forceinline__ void lap_factors_diag(A wy, A d2wy, A wz, A d2wz, con
   q2 = mt[0] * (wy * wz);
   q1 = A(0);
   q0 = fmaa(mt[1] * d2wy, wz, (mt[2] * wy) * d2wz);
+}
+
+// The weights of term c (kind `kind`) on a lane's four block rows l = 0..3 along the first axis,
+// at its second- and third-axis offsets with 1-D weights (wy, wy', wy'') and (wz, wz', wz''):
+// Q0 w_x[l] + Q1 w_x'[l] + Q2 w_x''[l].  A fixed set's value term is Q0 w_x (Q1 = Q2 = 0: with
+// finite non-negative weights the two vanishing products change no bit).  With a diagonal Jacobian a
+// gradient term is one product (x: Q1 = J00 w_y w_z; y: Q0 = J11 w_y' w_z; z: Q0 = J22 w_y w_z'), and
+// with a diagonal metric the Laplacian has no Q1 (lap_factors_diag).
+template <typename A, int TSET>
+__device__ __forceinline__ void row_weights(int c, int kind, const A (&wx)[4], const A (&dwx)[4], const A (&d2wx)[4],
+                                            A wy, A dwy, A d2wy, A wz, A dwz, A d2wz, const A (&jm)[9],
+                                            const A (&mt)[6], A (&av)[4]) {
+  if (TSET != TSET_ANY && c == 0) {
+    const A q0 = wy * wz;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) av[l] = q0 * wx[l];
+  } else if (TSET == TSET_ALLD && c >= 1 && c <= 3) {
+    const A q = c == 1 ? jm[0] * (wy * wz) : (c == 2 ? (jm[4] * dwy) * wz : (jm[8] * wy) * dwz);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) av[l] = q * (c == 1 ? dwx[l] : wx[l]);
+  } else if ((TSET == TSET_VLD && c == 1) || (TSET == TSET_ALLD && c == 4)) {
+    A q0, q1, q2;
+    lap_factors_diag<A>(wy, d2wy, wz, d2wz, mt, q0, q1, q2);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) av[l] = fmaa(q2, d2wx[l], q0 * wx[l]);
+  } else {
+    A q0, q1, q2;
+    term_factors<A>(kind, wy, dwy, d2wy, wz, dwz, d2wz, jm, mt, q0, q1, q2);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) av[l] = fmaa(q2, d2wx[l], fmaa(q1, dwx[l], q0 * wx[l]));
+  }
 }
 
 // Position in a brick's sequence of batches: cell c (0..7; 8 once the sequence is exhausted) and the
@@ -490,21 +522,14 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) void k_bwd_bricks(CellArgs a) {
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
         if (c >= nt) break;
-        A q0, q1, q2;
-        constexpr bool DIAG = TSET == TSET_VLD;
         const int kind = TSET == TSET_ANY ? a.kind[c]
-                                          : (TSET == TSET_VL || DIAG ? (c == 0 ? TERM_VAL : TERM_LAP) : c);
-        if (DIAG && c == 1) lap_factors_diag<A>(wy, d2wy, wz, d2wz, mt, q0, q1, q2);
-        else term_factors<A>(kind, wy, dwy, d2wy, wz, dwz, d2wz, jm, mt, q0, q1, q2);
+                                          : (TSET == TSET_VL || TSET == TSET_VLD ? (c == 0 ? TERM_VAL : TERM_LAP) : c);
+        A av[4];
+        row_weights<A, TSET>(c, kind, wx, dwx, d2wx, wy, dwy, d2wy, wz, dwz, d2wz, jm, mt, av);
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-          // a fixed set's value term: Q1 = Q2 = 0, and with finite non-negative weights the two
-          // vanishing products change no bit of q0 w_x (so too Q1 = 0 of a diagonal metric)
-          const A av = (TSET != TSET_ANY && c == 0) ? q0 * wx[rt]
-                       : (DIAG ? fmaa(q2, d2wx[rt], q0 * wx[rt]) : fmaa(q2, d2wx[rt], fmaa(q1, dwx[rt], q0 * wx[rt])));
+        for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-          for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = M::step(av, bv[c][ot], acc[rt][ot]);
-        }
+          for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = M::step(av[rt], bv[c][ot], acc[rt][ot]);
       }
     };
     // one batch: with its upstream values already loaded, or (more than two terms) loading each
@@ -743,7 +768,7 @@ __global__ __launch_bounds__(64 * TILE_WAVES) __attribute__((amdgpu_waves_per_eu
   constexpr int WBW = TILE_WAVES * BW;                 // orbitals of a workgroup
   constexpr int NB = NT <= 2 ? NT : 5;                 // upstream values per point and orbital tile
   static_assert(2 * 64 * TILE_WAVES >= TILE_WIN3, "two window cells per thread");
-  static_assert(TSET == TSET_ANY || NT == (TSET == TSET_VL ? 2 : (TSET == TSET_V ? 1 : 5)),
+  static_assert(TSET == TSET_ANY || NT == (TSET == TSET_VL || TSET == TSET_VLD ? 2 : (TSET == TSET_V ? 1 : 5)),
                 "a fixed term set has its own count");
   __shared__ int s_start[TILE_WIN3];                   // first sorted point of each window cell
   __shared__ int s_pre[TILE_WIN3 + 1];                 // points of the window cells before each
@@ -921,17 +946,14 @@ __global__ __launch_bounds__(64 * TILE_WAVES) __attribute__((amdgpu_waves_per_eu
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
         if (c >= nt) break;
-        A q0, q1, q2;
-        const int kind = TSET == TSET_ANY ? a.kind[c] : (TSET == TSET_VL ? (c == 0 ? TERM_VAL : TERM_LAP) : c);
-        term_factors<A>(kind, wy, dwy, d2wy, wz, dwz, d2wz, jm, mt, q0, q1, q2);
+        const int kind = TSET == TSET_ANY ? a.kind[c]
+                                          : (TSET == TSET_VL || TSET == TSET_VLD ? (c == 0 ? TERM_VAL : TERM_LAP) : c);
+        A av[4];
+        row_weights<A, TSET>(c, kind, wx, dwx, d2wx, wy, dwy, d2wy, wz, dwz, d2wz, jm, mt, av);
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-          // a fixed set's value term: Q1 = Q2 = 0, and with finite non-negative weights the two
-          // vanishing products change no bit of q0 w_x
-          const A av = (TSET != TSET_ANY && c == 0) ? q0 * wx[rt] : fmaa(q2, d2wx[rt], fmaa(q1, dwx[rt], q0 * wx[rt]));
+        for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-          for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = M::step(av, bv[c][ot], acc[rt][ot]);
-        }
+          for (int ot = 0; ot < OT; ++ot) acc[rt][ot] = M::step(av[rt], bv[c][ot], acc[rt][ot]);
       }
     };
     // one batch: each step's upstream values load while the step before is multiplied
@@ -1028,6 +1050,7 @@ static CellKernel pick_bricks_buf(int nt, int tset) {
   if (tset == TSET_V) return k_bwd_bricks<A, OT, 1, TSET_V, BUF, PAIR>;
   if (tset == TSET_VL) return k_bwd_bricks<A, OT, 2, TSET_VL, BUF, PAIR>;
   if (tset == TSET_VLD) return k_bwd_bricks<A, OT, 2, TSET_VLD, BUF, PAIR>;
+  if (tset == TSET_ALLD) return k_bwd_bricks<A, OT, 5, TSET_ALLD, BUF, PAIR>;
   if (tset == TSET_ALL) return k_bwd_bricks<A, OT, 5, TSET_ALL, BUF, PAIR>;
   return nt <= 2 ? k_bwd_bricks<A, OT, 2, TSET_ANY, BUF, PAIR> : k_bwd_bricks<A, OT, 5, TSET_ANY, BUF, PAIR>;
 }
@@ -1044,12 +1067,15 @@ static int brick_ot() {
   return sizeof(A) == 4 ? 2 : 1;
 }
 
-// row tiles: the orbital tiles of the brick form; tset: TSET_V, TSET_VL or TSET_ALL where the terms are that set
+// row tiles: the orbital tiles of the brick form; tset: a fixed term set (TSET_V, TSET_VL, TSET_VLD, TSET_ALL,
+// TSET_ALLD) where the terms are that set
 template <typename A, bool BUF>
 static CellKernel pick_tiles_buf(int nt, int tset) {
   constexpr int OT = sizeof(A) == 4 ? 2 : 1;
   if (tset == TSET_V) return k_bwd_tiles<A, OT, 1, TSET_V, BUF>;
-  if (tset == TSET_VL || tset == TSET_VLD) return k_bwd_tiles<A, OT, 2, TSET_VL, BUF>;
+  if (tset == TSET_VL) return k_bwd_tiles<A, OT, 2, TSET_VL, BUF>;
+  if (tset == TSET_VLD) return k_bwd_tiles<A, OT, 2, TSET_VLD, BUF>;
+  if (tset == TSET_ALLD) return k_bwd_tiles<A, OT, 5, TSET_ALLD, BUF>;
   if (tset == TSET_ALL) return k_bwd_tiles<A, OT, 5, TSET_ALL, BUF>;
   return nt <= 2 ? k_bwd_tiles<A, OT, 2, TSET_ANY, BUF> : k_bwd_tiles<A, OT, 5, TSET_ANY, BUF>;
 }
@@ -1224,12 +1250,14 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
     bool all = nt == 5;
     for (int c = 0; c < nt; ++c) all = all && a.kind[c] == TERM_VAL + c;
     const bool vl = nt == 2 && a.kind[0] == TERM_VAL && a.kind[1] == TERM_LAP;
-    // the metric as the kernels round it (FP64 tables in FP64, else FP32)
-    bool diag = true;
-    for (int i = 3; i < 6; ++i)
-      diag = diag && (d->dtype == SPL_F64 ? d->metric[i] == 0.0 : (float)d->metric[i] == 0.0f);
+    // the metric and the Jacobian as the kernels round them (FP64 tables in FP64, else FP32)
+    auto zero = [&](double x) { return d->dtype == SPL_F64 ? x == 0.0 : (float)x == 0.0f; };
+    const bool diag = zero(d->metric[3]) && zero(d->metric[4]) && zero(d->metric[5]);
+    const bool diagj = zero(d->jac[1]) && zero(d->jac[2]) && zero(d->jac[3]) && zero(d->jac[5]) &&
+                       zero(d->jac[6]) && zero(d->jac[7]);
     const int tset = vl ? (diag ? TSET_VLD : TSET_VL)
-                        : (all ? TSET_ALL : (nt == 1 && a.kind[0] == TERM_VAL ? TSET_V : TSET_ANY));
+                        : (all ? (diagj && diag ? TSET_ALLD : TSET_ALL)
+                               : (nt == 1 && a.kind[0] == TERM_VAL ? TSET_V : TSET_ANY));
     if (L.dense) {
       // every brick at once into its region, then one gather per table row
       const CellKernel kb = d->dtype == SPL_F64 ? pick_bricks<double>(nt, tset, buf, false)

@@ -388,31 +388,36 @@ ORTHO = np.diag([7.0, 6.2, 8.3])    # orthogonal, axis-aligned lattice vectors: 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_diagonal_metric_forms_against_oracle(dtype):
-    """An orthorhombic cell (the metric's off-diagonal entries exactly 0) takes the forms that skip the
-    Laplacian's mixed terms: the deterministic adjoint of value and Laplacian upstream values at dense
-    points against the oracle's adjoint, and (FP32) the one-pass fit gradient against the oracle's loss
-    and gradient, and against the fit terms followed by the adjoint (equal values).  A ragged grid and
-    an odd orbital count."""
+    """An orthorhombic cell along the Cartesian axes (the metric's and the Jacobian's off-diagonal
+    entries exactly 0) takes the forms that skip their products: the deterministic adjoint of value and
+    Laplacian upstream values, and of all five, at dense points (bricks) and at sparse points (row
+    tiles), against the oracle's adjoint; and (FP32) the one-pass fit gradient against the oracle's
+    loss and gradient, and against the fit terms followed by the adjoint (equal values).  A ragged
+    grid and an odd orbital count."""
     from oracle import adjoint as oadj
     rng = np.random.default_rng(151)
     grid, n_orb, n = (6, 5, 7), 37, 2000
     beta = rng.standard_normal(grid + (n_orb,))
     d = P.spline_desc_init(ORTHO, grid, n_orb, dtype)
     assert d.metric[3] == 0.0 and d.metric[4] == 0.0 and d.metric[5] == 0.0
+    assert all(d.jac[i] == 0.0 for i in (1, 2, 3, 5, 6, 7))
     tab = table_from_oracle(d, beta, dtype)
     bq = oq.quantized(beta, dtype)
     pos = rng.uniform(-3, 3, size=(n, 3)) @ ORTHO / 3.0
     x = to_dev(pos)
     od = torch.float64 if dtype == "f64" else torch.float32
     nd = np.float64 if dtype == "f64" else np.float32
-    gv, gl = rng.standard_normal((n, n_orb)), rng.standard_normal((n, n_orb))
-    say("diagonal metric: deterministic adjoint", dtype)
-    gt, _ = P.spline_eval_vgl_backward(d, tab, x, to_dev(gv, od), None, to_dev(gl, od), want_pos=False,
-                                       flags=P.SPL_DETERMINISTIC)
-    torch.cuda.synchronize()
-    rb, _, _ = oadj.vgl_backward(bq, ORTHO, pos, gv, None, gl)
+    gv, gg, gl = rng.standard_normal((n, n_orb)), rng.standard_normal((n, 3, n_orb)), rng.standard_normal((n, n_orb))
     tol = 1e-12 if dtype == "f64" else 2e-5
-    assert normwise(gt.double().cpu().numpy()[0, ..., :n_orb], rb) <= tol
+    for m in (n, 300):                               # 9.5 and 1.4 points per cell: bricks, row tiles
+        for with_grad in (False, True):
+            say("diagonal metric: deterministic adjoint", dtype, m, "points", "all terms" if with_grad else "V and L")
+            gt, _ = P.spline_eval_vgl_backward(d, tab, x[:m], to_dev(gv[:m], od),
+                                               to_dev(gg[:m], od) if with_grad else None, to_dev(gl[:m], od),
+                                               want_pos=False, flags=P.SPL_DETERMINISTIC)
+            torch.cuda.synchronize()
+            rb, _, _ = oadj.vgl_backward(bq, ORTHO, pos[:m], gv[:m], gg[:m] if with_grad else None, gl[:m])
+            assert normwise(gt.double().cpu().numpy()[0, ..., :n_orb], rb) <= tol
     if dtype == "f64":
         return
     ov, _, ol = oeval.eval_vgl(bq, ORTHO, pos)

@@ -1664,13 +1664,14 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) __attribute__((amdgpu_waves_per_e
     const int bx = (int)(brick / ((int64_t)nbz * nby));
     // the lane's orbital in tile ot: ob + 16 ot + col (as the FP32 fit terms); an orbital past
     // n_orb sets bit 31 of its offsets, which reads 0
-    uint32_t col_off[OT], col_flag[OT];
+    uint32_t col_off[OT], col_flag[OT], col_tgt[OT];
     bool ocol[OT];
 #pragma unroll
     for (int ot = 0; ot < OT; ++ot) {
       ocol[ot] = ob + 16 * ot + col < a.n_orb;
       col_off[ot] = ocol[ot] ? (uint32_t)(ob + 16 * ot + col) * 4u : 0u;
       col_flag[ot] = ocol[ot] ? 0u : 0x80000000u;
+      col_tgt[ot] = ocol[ot] ? col_off[ot] : 0x80000000u;
     }
     __syncthreads();                                   // the previous region is written out
     for (int i = tid; i < BRICK_ROWS * WBW; i += 64 * BRICK_WAVES) s_reg[i] = A(0);
@@ -1715,9 +1716,11 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) __attribute__((amdgpu_waves_per_e
       sp.t = rec->t[sax];
       sp.p = rec->p;
     };
-    // a point's target row as a byte offset (under 2^31: each target array is under 2 GiB), -1: none
+    // a point's target row as a byte offset (under 2^31 - 4096: each target array is under that);
+    // none: bit 31 alone
     auto stage_index = [&](const BrickBatch& b, const Staged& sp, int* sp_out) {
-      if (sax == 0 && sj < count(b)) sp_out[sj] = (unsigned)sp.p < (unsigned)a.n_pts ? (int)((uint32_t)sp.p * row_bytes) : -1;
+      if (sax == 0 && sj < count(b))
+        sp_out[sj] = (unsigned)sp.p < (unsigned)a.n_pts ? (int)((uint32_t)sp.p * row_bytes) : (int)0x80000000u;
     };
     auto stage_weights = [&](const BrickBatch& b, const Staged& sp, A (*sw)[36]) {
       if (sj < count(b)) {
@@ -1760,15 +1763,18 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) __attribute__((amdgpu_waves_per_e
       for (int mt_ = 0; mt_ < 2; ++mt_)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int j = mt_ * 16 + M::row(grp, e);
-          const int pj = j < nb ? sp_in[j] : -1;
+          const int j = mt_ * 16 + M::row(grp, e);            // under CELL_PB
+          // past the batch: bit 31 set over a stale entry (no select of a loaded value, which the
+          // compiler would make a branch of)
+          const int pj = sp_in[j] | (int)((uint32_t)(j >= nb) << 31);
           const bool live = pj >= 0;
           valid |= live ? 1u << (4 * mt_ + e) : 0u;
-          const uint32_t row = live ? (uint32_t)pj : 0u;
-          const uint32_t flag = live ? 0u : 0x80000000u;
 #pragma unroll
           for (int ot = 0; ot < OT; ++ot) {
-            const uint32_t off = (row + col_off[ot]) | flag | col_flag[ot];
+            // one add: a live point and orbital give the value's offset; a dead orbital (bit 31 in
+            // col_tgt) on a live row stays past the array and reads 0; a dead point may wrap into the
+            // array, and its value is never used (`valid`)
+            const uint32_t off = (uint32_t)pj + col_tgt[ot];
             tg[mt_][0][ot][e] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs_t0, off, 0, 0));
             tg[mt_][1][ot][e] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs_t1, off, 0, 0));
           }
@@ -1831,7 +1837,7 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) __attribute__((amdgpu_waves_per_e
             // select of a loaded value)
             const bool use = ok && ocol[ot];
             const A res = accf[c][ot][e] - tg[mt_][c][ot][e];
-            const double rd = use ? (double)res : 0.0;
+            const double rd = (double)(use ? res : A(0));
             sq = fma(a.w[c] * rd, rd, sq);
             gd[c][ot][e] = use ? two_w[c] * res : A(0);
           }

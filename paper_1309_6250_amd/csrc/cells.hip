@@ -1350,10 +1350,15 @@ template <> struct StoredPair<uint16_t> {
 // FIT: every term has a target (spline_fit_terms_cells); the targets of a batch are loaded before
 // its products, so their latency hides behind the matrix-core work
 // LT: some term reads the separate Laplacian table (else its operands take no registers)
-template <typename TS, typename A, int OT, int NT, bool FIT, bool LT>
+// TSET: a term set fixed at compile time (the value alone, the value and Laplacian, all five in
+// order, each with its diagonal forms; only without the Laplacian table), else TSET_ANY (each term's
+// kind read at run time)
+template <typename TS, typename A, int OT, int NT, bool FIT, bool LT, int TSET>
 __global__ __launch_bounds__(64)
 __attribute__((amdgpu_waves_per_eu(sizeof(A) == 4 && (FIT || (OT == 2 && NT == 5 && !LT)) ? 3 : 1)))
 void k_fwd_cells(FwdArgs a) {
+  static_assert(TSET == TSET_ANY || (!LT && NT == (TSET == TSET_ALL || TSET == TSET_ALLD ? 5 : 2)),
+                "a fixed term set reads the main table, with its own count");
   using M = Mfma<A>;
   using Acc = typename M::acc;
   constexpr int BW = 16 * OT;
@@ -1499,27 +1504,18 @@ void k_fwd_cells(FwdArgs a) {
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           const A wy = wp[12 + m], dwy = wp[16 + m], d2wy = wp[20 + m];
-          const A yz = wy * wz;
 #pragma unroll
           for (int c = 0; c < NT; ++c) {
             if (c >= nt) break;
-            const int kind = a.kind[c];
-            A q0, q1 = A(0), q2 = A(0);
-            if (kind == TERM_VAL) {
-              q0 = yz;
-            } else if (kind == TERM_LAP) {
-              q2 = mt[0] * yz;
-              q1 = A(2) * fmaa(mt[3] * dwy, wz, mt[4] * wy * dwz);
-              q0 = fmaa(mt[1] * d2wy, wz, fmaa(mt[2] * wy, d2wz, A(2) * mt[5] * dwy * dwz));
-            } else {
-              const int k = kind - TERM_GX;
-              q1 = jm[k] * yz;
-              q0 = fmaa(jm[3 + k] * dwy, wz, jm[6 + k] * wy * dwz);
-            }
+            const int kind = TSET == TSET_ANY ? a.kind[c]
+                             : (TSET == TSET_V ? TERM_VAL
+                                               : (TSET == TSET_VL || TSET == TSET_VLD ? (c == 0 ? TERM_VAL : TERM_LAP) : c));
+            A avs[4];
+            row_weights<A, TSET>(c, kind, wx, dwx, d2wx, wy, dwy, d2wy, wz, dwz, d2wz, jm, mt, avs);
             const bool lt = a.src[c] != 0;
 #pragma unroll
             for (int l = 0; l < 4; ++l) {
-              const A av = fmaa(q2, d2wx[l], fmaa(q1, dwx[l], q0 * wx[l]));
+              const A av = avs[l];
 #pragma unroll
               for (int ot = 0; ot < OT; ++ot)
                 acc[c][ot] = M::step(av, (LT && lt) ? b1[LT ? 4 * l + m : 0][ot] : b0[4 * l + m][ot], acc[c][ot]);
@@ -2017,22 +2013,35 @@ typedef void (*FwdKernel)(FwdArgs);
 
 // FP32 with at most two terms: two orbital tiles per wave; otherwise one (accumulator registers)
 // (the fit terms come in at most two: values and Laplacians)
-template <typename TS, typename A, bool LT>
-static FwdKernel pick_fwd_lt(int nt, bool fit) {
-  if (fit) {
-    if constexpr (sizeof(A) == 4) return k_fwd_cells<TS, A, 2, 2, true, LT>;
-    else return k_fwd_cells<TS, A, 1, 2, true, LT>;
+template <typename TS, typename A, bool LT, int TSET>
+static FwdKernel pick_fwd_set(int nt, bool fit) {
+  constexpr int OT2 = sizeof(A) == 4 ? 2 : 1;   // orbital tiles of the at-most-two-term forms
+  if constexpr (TSET == TSET_ALL || TSET == TSET_ALLD) {
+    return k_fwd_cells<TS, A, OT2, 5, false, LT, TSET>;
+  } else if constexpr (TSET != TSET_ANY) {
+    return fit ? k_fwd_cells<TS, A, OT2, 2, true, LT, TSET> : k_fwd_cells<TS, A, OT2, 2, false, LT, TSET>;
+  } else {
+    if (fit) return k_fwd_cells<TS, A, OT2, 2, true, LT, TSET_ANY>;
+    if constexpr (sizeof(A) == 4) {
+      if (nt <= 2) return k_fwd_cells<TS, A, 2, 2, false, LT, TSET_ANY>;
+      if constexpr (!LT) return k_fwd_cells<TS, A, 2, 5, false, LT, TSET_ANY>;
+    }
+    return nt <= 2 ? k_fwd_cells<TS, A, 1, 2, false, LT, TSET_ANY> : k_fwd_cells<TS, A, 1, 5, false, LT, TSET_ANY>;
   }
-  if constexpr (sizeof(A) == 4) {
-    if (nt <= 2) return k_fwd_cells<TS, A, 2, 2, false, LT>;
-    if constexpr (!LT) return k_fwd_cells<TS, A, 2, 5, false, LT>;
-  }
-  return nt <= 2 ? k_fwd_cells<TS, A, 1, 2, false, LT> : k_fwd_cells<TS, A, 1, 5, false, LT>;
 }
 
+// tset: a fixed term set (only without the Laplacian table), else TSET_ANY
 template <typename TS, typename A>
-static FwdKernel pick_fwd(int nt, bool fit, bool lt) {
-  return lt ? pick_fwd_lt<TS, A, true>(nt, fit) : pick_fwd_lt<TS, A, false>(nt, fit);
+static FwdKernel pick_fwd(int nt, bool fit, bool lt, int tset) {
+  if (lt) return pick_fwd_set<TS, A, true, TSET_ANY>(nt, fit);
+  switch (tset) {
+    case TSET_V: return pick_fwd_set<TS, A, false, TSET_V>(nt, fit);
+    case TSET_VL: return pick_fwd_set<TS, A, false, TSET_VL>(nt, fit);
+    case TSET_VLD: return pick_fwd_set<TS, A, false, TSET_VLD>(nt, fit);
+    case TSET_ALL: return pick_fwd_set<TS, A, false, TSET_ALL>(nt, fit);
+    case TSET_ALLD: return pick_fwd_set<TS, A, false, TSET_ALLD>(nt, fit);
+    default: return pick_fwd_set<TS, A, false, TSET_ANY>(nt, fit);
+  }
 }
 
 static int fwd_tiles(int dtype, int nt, bool lt) { return dtype != SPL_F64 && (nt <= 2 || !lt) ? 2 : 1; }
@@ -2109,9 +2118,21 @@ int launch_eval_cells(const spl_desc* d, const void* table, int64_t n_pts, const
   a.n_groups = (d->n_orb + 16 * ot - 1) / (16 * ot);
   FwdKernel k;
   const bool lt = a.use_lap_table != 0;
-  if (d->dtype == SPL_F64) k = pick_fwd<double, double>(nt, fit != nullptr, lt);
-  else if (d->dtype == SPL_F32) k = pick_fwd<float, float>(nt, fit != nullptr, lt);
-  else k = pick_fwd<uint16_t, float>(nt, fit != nullptr, lt);
+  // a term set the kernel fixes at compile time, with its diagonal forms where the metric and the
+  // Jacobian (as the kernel rounds them) have zero off-diagonal entries
+  auto zero = [&](double x) { return d->dtype == SPL_F64 ? x == 0.0 : (float)x == 0.0f; };
+  const bool diag = zero(d->metric[3]) && zero(d->metric[4]) && zero(d->metric[5]);
+  const bool diagj = diag && zero(d->jac[1]) && zero(d->jac[2]) && zero(d->jac[3]) && zero(d->jac[5]) &&
+                     zero(d->jac[6]) && zero(d->jac[7]);
+  bool all = nt == 5;
+  for (int c = 0; c < nt; ++c) all = all && a.kind[c] == TERM_VAL + c;
+  int tset = TSET_ANY;
+  if (nt == 2 && a.kind[0] == TERM_VAL && a.kind[1] == TERM_LAP) tset = diag ? TSET_VLD : TSET_VL;
+  else if (all && !fit) tset = diagj ? TSET_ALLD : TSET_ALL;
+  else if (nt == 1 && a.kind[0] == TERM_VAL && !fit) tset = TSET_V;
+  if (d->dtype == SPL_F64) k = pick_fwd<double, double>(nt, fit != nullptr, lt, tset);
+  else if (d->dtype == SPL_F32) k = pick_fwd<float, float>(nt, fit != nullptr, lt, tset);
+  else k = pick_fwd<uint16_t, float>(nt, fit != nullptr, lt, tset);
   const int grid = (int)std::min<int64_t>(std::min<int64_t>(n_pts, L.n_cells) * a.n_groups, 1 << 16);
   hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, stream, a);
   if ((rc = hip_fail(hipGetLastError(), "cell forward launch"))) return rc;

@@ -389,11 +389,12 @@ ORTHO = np.diag([7.0, 6.2, 8.3])    # orthogonal, axis-aligned lattice vectors: 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_diagonal_metric_forms_against_oracle(dtype):
     """An orthorhombic cell along the Cartesian axes (the metric's and the Jacobian's off-diagonal
-    entries exactly 0) takes the forms that skip their products: the deterministic adjoint of value and
-    Laplacian upstream values, and of all five, at dense points (bricks) and at sparse points (row
-    tiles), against the oracle's adjoint; and (FP32) the one-pass fit gradient against the oracle's
-    loss and gradient, and against the fit terms followed by the adjoint (equal values).  A ragged
-    grid and an odd orbital count."""
+    entries exactly 0) takes the forms that skip their products: the cell-wise forward of V and lap and
+    of all five outputs against the oracle's values; the deterministic adjoint of value and Laplacian
+    upstream values, and of all five, at dense points (bricks) and at sparse points (row tiles),
+    against the oracle's adjoint; and (FP32) the one-pass fit gradient against the oracle's loss and
+    gradient, and against the fit terms followed by the adjoint (equal values).  A ragged grid and an
+    odd orbital count."""
     from oracle import adjoint as oadj
     rng = np.random.default_rng(151)
     grid, n_orb, n = (6, 5, 7), 37, 2000
@@ -409,6 +410,18 @@ def test_diagonal_metric_forms_against_oracle(dtype):
     nd = np.float64 if dtype == "f64" else np.float32
     gv, gg, gl = rng.standard_normal((n, n_orb)), rng.standard_normal((n, 3, n_orb)), rng.standard_normal((n, n_orb))
     tol = 1e-12 if dtype == "f64" else 2e-5
+    from gpu_helpers import assert_elementwise, coordinate_rounding, U_ACC
+    ov, og, ol = oeval.eval_vgl(bq, ORTHO, pos)
+    bnd = oeval.eval_abs_bound(bq, ORTHO, pos)
+    crd = oeval.coordinate_error_bound(bq, ORTHO, pos, coordinate_rounding(d, ORTHO, pos, dtype))
+    fac = 2 * 64 * U_ACC[dtype] + (0.0 if dtype == "f64" else 2.0**-24)
+    for outputs in ("vl", "vgl"):                    # the cell-wise forward's diagonal forms, element by element
+        say("diagonal metric: cell-wise forward", dtype, outputs)
+        outs = P.spline_eval_vgl_cells(d, tab, x, outputs=outputs)
+        torch.cuda.synchronize()
+        for name, got, r, b, c in zip(("V", "grad", "lap"), outs, (ov, og, ol), bnd, crd):
+            if got is not None:
+                assert_elementwise(got.double().cpu().numpy(), r, b + c / fac, fac, name)
     for m in (n, 300):                               # 9.5 and 1.4 points per cell: bricks, row tiles
         for with_grad in (False, True):
             say("diagonal metric: deterministic adjoint", dtype, m, "points", "all terms" if with_grad else "V and L")
@@ -420,7 +433,6 @@ def test_diagonal_metric_forms_against_oracle(dtype):
             assert normwise(gt.double().cpu().numpy()[0, ..., :n_orb], rb) <= tol
     if dtype == "f64":
         return
-    ov, _, ol = oeval.eval_vgl(bq, ORTHO, pos)
     t_v = (ov + 0.1 * rng.standard_normal(ov.shape)).astype(nd)
     t_l = (ol + 0.5 * rng.standard_normal(ol.shape)).astype(nd)
     wv, wl = 0.7, 0.05

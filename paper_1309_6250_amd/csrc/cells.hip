@@ -292,6 +292,20 @@ __device__ __forceinline__ void lap_factors_diag(A wy, A d2wy, A wz, A d2wz, con
   q0 = fmaa(mt[1] * d2wy, wz, (mt[2] * wy) * d2wz);
 }
 
+// Whether the kernels' diagonal forms apply: the metric's off-diagonal entries (diag), and also the
+// Jacobian's (diag_jac), are zero as the kernels round them (FP64 for FP64 tables, else FP32).
+struct DiagForms {
+  bool diag, diag_jac;
+};
+static DiagForms diag_forms(const spl_desc* d) {
+  auto zero = [&](double x) { return d->dtype == SPL_F64 ? x == 0.0 : (float)x == 0.0f; };
+  DiagForms f;
+  f.diag = zero(d->metric[3]) && zero(d->metric[4]) && zero(d->metric[5]);
+  f.diag_jac = f.diag && zero(d->jac[1]) && zero(d->jac[2]) && zero(d->jac[3]) && zero(d->jac[5]) &&
+               zero(d->jac[6]) && zero(d->jac[7]);
+  return f;
+}
+
 // The weights of term c (kind `kind`) on a lane's four block rows l = 0..3 along the first axis,
 // at its second- and third-axis offsets with 1-D weights (wy, wy', wy'') and (wz, wz', wz''):
 // Q0 w_x[l] + Q1 w_x'[l] + Q2 w_x''[l].  A fixed set's value term is Q0 w_x (Q1 = Q2 = 0: with
@@ -1250,13 +1264,9 @@ int launch_backward_sorted(const spl_desc* d, int64_t n_pts, const double* pos, 
     bool all = nt == 5;
     for (int c = 0; c < nt; ++c) all = all && a.kind[c] == TERM_VAL + c;
     const bool vl = nt == 2 && a.kind[0] == TERM_VAL && a.kind[1] == TERM_LAP;
-    // the metric and the Jacobian as the kernels round them (FP64 tables in FP64, else FP32)
-    auto zero = [&](double x) { return d->dtype == SPL_F64 ? x == 0.0 : (float)x == 0.0f; };
-    const bool diag = zero(d->metric[3]) && zero(d->metric[4]) && zero(d->metric[5]);
-    const bool diagj = zero(d->jac[1]) && zero(d->jac[2]) && zero(d->jac[3]) && zero(d->jac[5]) &&
-                       zero(d->jac[6]) && zero(d->jac[7]);
-    const int tset = vl ? (diag ? TSET_VLD : TSET_VL)
-                        : (all ? (diagj && diag ? TSET_ALLD : TSET_ALL)
+    const DiagForms df = diag_forms(d);
+    const int tset = vl ? (df.diag ? TSET_VLD : TSET_VL)
+                        : (all ? (df.diag_jac ? TSET_ALLD : TSET_ALL)
                                : (nt == 1 && a.kind[0] == TERM_VAL ? TSET_V : TSET_ANY));
     if (L.dense) {
       // every brick at once into its region, then one gather per table row
@@ -2118,17 +2128,13 @@ int launch_eval_cells(const spl_desc* d, const void* table, int64_t n_pts, const
   a.n_groups = (d->n_orb + 16 * ot - 1) / (16 * ot);
   FwdKernel k;
   const bool lt = a.use_lap_table != 0;
-  // a term set the kernel fixes at compile time, with its diagonal forms where the metric and the
-  // Jacobian (as the kernel rounds them) have zero off-diagonal entries
-  auto zero = [&](double x) { return d->dtype == SPL_F64 ? x == 0.0 : (float)x == 0.0f; };
-  const bool diag = zero(d->metric[3]) && zero(d->metric[4]) && zero(d->metric[5]);
-  const bool diagj = diag && zero(d->jac[1]) && zero(d->jac[2]) && zero(d->jac[3]) && zero(d->jac[5]) &&
-                     zero(d->jac[6]) && zero(d->jac[7]);
+  // a term set the kernel fixes at compile time, with its diagonal forms where they apply
+  const DiagForms df = diag_forms(d);
   bool all = nt == 5;
   for (int c = 0; c < nt; ++c) all = all && a.kind[c] == TERM_VAL + c;
   int tset = TSET_ANY;
-  if (nt == 2 && a.kind[0] == TERM_VAL && a.kind[1] == TERM_LAP) tset = diag ? TSET_VLD : TSET_VL;
-  else if (all && !fit) tset = diagj ? TSET_ALLD : TSET_ALL;
+  if (nt == 2 && a.kind[0] == TERM_VAL && a.kind[1] == TERM_LAP) tset = df.diag ? TSET_VLD : TSET_VL;
+  else if (all && !fit) tset = df.diag_jac ? TSET_ALLD : TSET_ALL;
   else if (nt == 1 && a.kind[0] == TERM_VAL && !fit) tset = TSET_V;
   if (d->dtype == SPL_F64) k = pick_fwd<double, double>(nt, fit != nullptr, lt, tset);
   else if (d->dtype == SPL_F32) k = pick_fwd<float, float>(nt, fit != nullptr, lt, tset);
@@ -2215,9 +2221,7 @@ int launch_fit_gradient(const spl_desc* d, const void* table, int64_t n_pts, con
   a.n_runs = max_runs;
   const int64_t n_bricks = (int64_t)((d->grid[0] + 1) / 2) * ((d->grid[1] + 1) / 2) * ((d->grid[2] + 1) / 2);
   const int64_t n_wg = (a.n_groups + BRICK_WAVES - 1) / BRICK_WAVES;
-  // the metric as the kernel rounds it (FP32)
-  const bool diag = (float)d->metric[3] == 0.0f && (float)d->metric[4] == 0.0f && (float)d->metric[5] == 0.0f;
-  hipLaunchKernelGGL(diag ? k_fit_bricks<true> : k_fit_bricks<false>, dim3((unsigned)std::min<int64_t>(n_bricks * n_wg, 1 << 16)),
+  hipLaunchKernelGGL(diag_forms(d).diag ? k_fit_bricks<true> : k_fit_bricks<false>, dim3((unsigned)std::min<int64_t>(n_bricks * n_wg, 1 << 16)),
                      dim3(64 * BRICK_WAVES), 0, stream, a);
   if ((rc = hip_fail(hipGetLastError(), "fit gradient launch"))) return rc;
   if ((rc = launch_brick_gather<float>(d, a.g, a.blocks, gtable, stream))) return rc;

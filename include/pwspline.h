@@ -330,8 +330,9 @@ int spline_fit_terms_cells(const spl_desc* d, const void* table, int64_t n_pts, 
  *   w_v, w_lap   the terms' weights, finite
  *   gtable       device, d->gtable_bytes, FP32 [N1][N2][N3][o_pad]; padding columns are never written
  *   loss         device, one FP64
- *   flags        SPL_REUSE_SORT: the workspace holds the cell sort of these points from an earlier
- *                call of this function (the layout differs from spline_cells_work_bytes')
+ *   flags        SPL_REUSE_SORT: the workspace holds the cell sort of these points, with its cells'
+ *                point ranges, from an earlier call of this function (the layout differs from
+ *                spline_cells_work_bytes')
  *   work         device, 256-byte aligned, spline_fit_gradient_work_bytes() bytes
  * Supported: FP32 B-spline tables without a separate Laplacian table, at least 2.5 points per cell
  * on average, and the table and each target array under 2 GiB; otherwise SPL_EUNSUPPORTED (use

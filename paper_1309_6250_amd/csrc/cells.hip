@@ -2193,13 +2193,17 @@ int launch_fit_gradient(const spl_desc* d, const void* table, int64_t n_pts, con
   if ((rc = cell_sort(d, n_pts, pos, work, L, reuse, stream, &cs))) return rc;
   char* W = cs.base;
   int32_t* cell_range = reinterpret_cast<int32_t*>(W + L.cell_range);
-  hipLaunchKernelGGL(k_bwd_fill_i32, dim3((unsigned)((3 * L.n_cells + 255) / 256)), dim3(256), 0, stream, cell_range,
-                     3 * L.n_cells, 0);
-  if ((rc = hip_fail(hipGetLastError(), "cell range clear launch"))) return rc;
   const int max_runs = (int)std::min<int64_t>(n_pts, L.n_cells);
-  hipLaunchKernelGGL(k_cell_ranges, dim3((unsigned)((max_runs + 255) / 256)), dim3(256), 0, stream, cs.uniq,
-                     cs.counts, cs.offsets, cs.finite_runs, L.n_cells, (int32_t)n_pts, cell_range);
-  if ((rc = hip_fail(hipGetLastError(), "cell range launch"))) return rc;
+  if (!reuse) {
+    // the cells' point ranges, part of this function's sort: a reused sort comes from an earlier
+    // call of this function, which left them in the workspace
+    hipLaunchKernelGGL(k_bwd_fill_i32, dim3((unsigned)((3 * L.n_cells + 255) / 256)), dim3(256), 0, stream,
+                       cell_range, 3 * L.n_cells, 0);
+    if ((rc = hip_fail(hipGetLastError(), "cell range clear launch"))) return rc;
+    hipLaunchKernelGGL(k_cell_ranges, dim3((unsigned)((max_runs + 255) / 256)), dim3(256), 0, stream, cs.uniq,
+                       cs.counts, cs.offsets, cs.finite_runs, L.n_cells, (int32_t)n_pts, cell_range);
+    if ((rc = hip_fail(hipGetLastError(), "cell range launch"))) return rc;
+  }
   FitArgs a;
   memset(&a, 0, sizeof(a));
   a.g = make_geom(d);

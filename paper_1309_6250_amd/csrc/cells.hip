@@ -605,7 +605,11 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) void k_bwd_bricks(CellArgs a) {
     }
     __syncthreads();
     A bq[NBUF][NQB][NB][OT];
-    if constexpr (AHEAD) load_upstream(count(b0), s_p[0], bq[0]);
+    if constexpr (AHEAD) {
+      load_upstream(count(b0), s_p[0], bq[0]);
+      // every wave has read b0's indices before the first step stages b2's over them
+      if constexpr (NW == 2) __syncthreads();
+    }
     // one batch: multiply b0, add the block if b0 ends its cell, stage b1's weights and b2's indices,
     // and shift the sequence; `cur` holds b0's upstream values, `nxt` receives b1's
     auto step = [&](int buf, A (&cur)[NQB][NB][OT], A (&nxt)[NQB][NB][OT]) {
@@ -1916,6 +1920,8 @@ __global__ __launch_bounds__(64 * BRICK_WAVES) __attribute__((amdgpu_waves_per_e
     A tgq[2][2][2][OT][4];
     uint32_t vq[2];
     load_targets(count(b0), s_p[0], tgq[0], vq[0]);
+    __syncthreads();                                   // every wave has read b0's indices before the first
+                                                       // step stages b2's over them
     auto step = [&](int buf, A (&tg_cur)[2][2][OT][4], uint32_t& v_cur, A (&tg_nxt)[2][2][OT][4], uint32_t& v_nxt) {
       const int nb = count(b0);
       load_targets(count(b1), s_p[buf ^ 1], tg_nxt, v_nxt);

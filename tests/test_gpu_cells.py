@@ -335,7 +335,7 @@ def test_fit_gradient_one_pass_equals_terms_then_adjoint(n_orb):
 @pytest.mark.timeout(600)
 def test_fit_gradient_one_pass_at_fit_size():
     """The 64-atom fit workload (10^6 points, 128 orbitals, 32^3 FP32 table): one pass equals fit terms
-    then adjoint bit for bit, gradient and loss."""
+    then adjoint bit for bit, gradient and loss, over four calls (fresh and reused sort)."""
     w = config(4)
     s = w.system
     x = to_dev(w.positions())
@@ -348,10 +348,12 @@ def test_fit_gradient_one_pass_at_fit_size():
     g0 = torch.zeros(P.table_shape(d), dtype=torch.float32, device=DEV)
     say("one-pass fit gradient at fit size")
     rgt, rloss = _fit_gradient_reference(d, tab, x, tv, 1.0, tl, 1e-3, 0.0, g0)
-    gt, loss = P.spline_fit_gradient_cells(d, tab, x, tv, 1.0, tl, 1e-3)
-    torch.cuda.synchronize()
-    assert torch.equal(gt, rgt)
-    assert float(loss) == float(rloss)
+    work = torch.empty(P.spline_fit_gradient_work_bytes(d, n), dtype=torch.uint8, device=DEV)
+    for flags in (0, P.SPL_REUSE_SORT, P.SPL_REUSE_SORT, 0):    # repeated, on a fresh and a reused sort
+        gt, loss = P.spline_fit_gradient_cells(d, tab, x, tv, 1.0, tl, 1e-3, work=work, flags=flags)
+        torch.cuda.synchronize()
+        assert torch.equal(gt, rgt)
+        assert float(loss) == float(rloss)
 
 
 def test_fit_gradient_one_pass_nonfinite_and_unsupported():
